@@ -1,0 +1,807 @@
+/*
+ * polrad_oracle.c -- FP64 CPU oracle for polarized Monte Carlo radiative
+ * transfer with two-step imaging, after Yang & Wang, "Kratos-polrad: Novel GPU
+ * system for Monte-Carlo simulations with consistent polarization
+ * calculations" (arXiv:2512.01283).
+ *
+ * TEST INFRASTRUCTURE ONLY: a plain, slow, step-by-step statement of what the
+ * method computes.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it; the product path never does.  It shares
+ * no code with the HIP library.
+ *
+ * Every routine names the passage of the paper it follows.  Where the paper is
+ * silent or its printed formula is inconsistent, the reading taken is stated
+ * at the routine (the same readings are listed in the design notes):
+ *  R1 extinction matrix signs (Appendix A): the printed solution is the
+ *     reference; it fixes K = [[a1,a2,0,0],[a2,a1,0,0],[0,0,a1,a3],[0,0,-a3,a1]].
+ *  R2 sign of eta (Sec. 2.1, rotation-angle equation): signed,
+ *     sin(eta) = n_GF . (phi_GF x phi'), cos(eta) = phi_GF . phi'.
+ *  R3 optical depth sampled (Sec. 2.2): exponential in the scattering optical
+ *     depth with rate kbar = rho*kappa_sca; the rest of the extinction acts on
+ *     the Stokes vector continuously as exp(-(K - kbar) l).
+ *  R4 grain optics (Sec. 3 intro, dipole approximation): polarizability
+ *     diag(a_perp, a_perp, a_par) in the grain frame; extinction from Im
+ *     (optical theorem), normalised by the orientation average.
+ *  R5 segment contribution to S (Sec. 2.3): the exact integral of the Stokes
+ *     vector over the segment, times rho*kappa_sca / V_cell, through the
+ *     Mueller matrix normalised to unit solid-angle integral.
+ *  R6 rejection sampling (Sec. 3 intro): proposals uniform on the sphere in
+ *     the grain frame, bound 3/(8 pi N_P) max(|a_perp|^2,|a_par|^2) I.
+ *  R7 weight after scattering: I' = tr(alpha C alpha^dagger)/N_P.
+ *  R8 termination: open boundaries, Russian roulette, event cap.
+ *  R9 orthographic camera, image x along phi_hat, y along -theta_hat.
+ */
+#include "polrad_oracle.h"
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define PI_ 3.14159265358979323846264338327950288
+#define POLE_EPS2 8.673617379884035e-19 /* 2^-60 */
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two     */
+/* 64x64->128 multiplies with a Weyl-sequence key schedule.                  */
+/* ------------------------------------------------------------------------ */
+void kpo_philox(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+  uint64_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint64_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    unsigned __int128 p0 = (unsigned __int128)M0 * x0;
+    unsigned __int128 p1 = (unsigned __int128)M1 * x2;
+    uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+    uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+    x0 = hi1 ^ x1 ^ k0;
+    x1 = lo1;
+    x2 = hi0 ^ x3 ^ k1;
+    x3 = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+  out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+typedef struct {
+  uint64_t key[2];
+  uint64_t packet;
+  uint64_t next;     /* next draw index */
+  uint64_t block;    /* block held in buf */
+  int have;
+  uint64_t buf[4];
+} rng_t;
+
+static double word_to_uniform(uint64_t w) {
+  /* 23 high bits, centred: (k + 1/2) 2^-23, strictly inside (0,1) and exact in
+   * both float32 and float64 */
+  return ((double)(w >> 41) + 0.5) * (1.0 / 8388608.0);
+}
+
+static double draw(rng_t *r) {
+  uint64_t d = r->next++;
+  uint64_t b = d >> 2;
+  if (!r->have || r->block != b) {
+    uint64_t c[4] = {r->packet, b, 0, 0};
+    kpo_philox(c, r->key, r->buf);
+    r->block = b;
+    r->have = 1;
+  }
+  return word_to_uniform(r->buf[d & 3]);
+}
+
+double kpo_uniform(uint64_t seed, uint64_t lam, uint64_t packet, uint64_t drawi) {
+  rng_t r = {{seed, lam}, packet, drawi, 0, 0, {0, 0, 0, 0}};
+  return draw(&r);
+}
+
+/* ------------------------------------------------------------------------ */
+/* small vector helpers                                                      */
+/* ------------------------------------------------------------------------ */
+static double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+static void cross3(const double a[3], const double b[3], double o[3]) {
+  double t0 = a[1] * b[2] - a[2] * b[1];
+  double t1 = a[2] * b[0] - a[0] * b[2];
+  double t2 = a[0] * b[1] - a[1] * b[0];
+  o[0] = t0; o[1] = t1; o[2] = t2;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Quaternions (Sec. 2.1).  q = (q0, q1, q2, q3) = q0 + q1 i + q2 j + q3 k.  */
+/* ------------------------------------------------------------------------ */
+static void qmul(const double a[4], const double b[4], double o[4]) {
+  double w = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+  double x = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+  double y = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+  double z = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+  o[0] = w; o[1] = x; o[2] = y; o[3] = z;
+}
+
+/* Grain-frame quaternion from the alignment direction (theta_B, phi_B),
+ * grain-quaternion equation of Sec. 2.1. */
+void kpo_quat_from_b(const double b_in[3], double q[4]) {
+  double nb = sqrt(dot3(b_in, b_in));
+  double b[3] = {b_in[0] / nb, b_in[1] / nb, b_in[2] / nb};
+  double rxy2 = b[0] * b[0] + b[1] * b[1];
+  double thB = atan2(sqrt(rxy2), b[2]);
+  double phB = rxy2 <= POLE_EPS2 ? 0.0 : atan2(b[1], b[0]);
+  q[0] = cos(0.5 * phB) * cos(0.5 * thB);
+  q[1] = -sin(0.5 * phB) * sin(0.5 * thB);
+  q[2] = cos(0.5 * phB) * sin(0.5 * thB);
+  q[3] = sin(0.5 * phB) * cos(0.5 * thB);
+}
+
+/* (0, v_GF) = q^* (0, v) q   (vector-transform equation, Sec. 2.1) */
+void kpo_to_grain(const double q[4], const double v[3], double out[3]) {
+  double qc[4] = {q[0], -q[1], -q[2], -q[3]};
+  double pv[4] = {0.0, v[0], v[1], v[2]};
+  double t[4], r[4];
+  qmul(qc, pv, t);
+  qmul(t, q, r);
+  out[0] = r[1]; out[1] = r[2]; out[2] = r[3];
+}
+
+/* inverse map: (0, v) = q (0, v_GF) q^* */
+void kpo_from_grain(const double q[4], const double v[3], double out[3]) {
+  double qc[4] = {q[0], -q[1], -q[2], -q[3]};
+  double pv[4] = {0.0, v[0], v[1], v[2]};
+  double t[4], r[4];
+  qmul(q, pv, t);
+  qmul(t, qc, r);
+  out[0] = r[1]; out[1] = r[2]; out[2] = r[3];
+}
+
+/* Stokes reference basis of a direction (Sec. 2.1).  At the poles
+ * (nx^2+ny^2 <= 2^-60) phi is taken as 0. */
+void kpo_basis(const double n[3], double th[3], double ph[3]) {
+  double rxy2 = n[0] * n[0] + n[1] * n[1];
+  double t = atan2(sqrt(rxy2), n[2]);
+  double p = rxy2 <= POLE_EPS2 ? 0.0 : atan2(n[1], n[0]);
+  th[0] = cos(t) * cos(p);
+  th[1] = cos(t) * sin(p);
+  th[2] = -sin(t);
+  ph[0] = -sin(p);
+  ph[1] = cos(p);
+  ph[2] = 0.0;
+}
+
+/* Signed angle between the lab phi_hat carried into the grain frame and the
+ * natural phi_hat' of the grain-frame direction (rotation-angle equation,
+ * reading R2).  v is the lab direction, vg its grain-frame image. */
+static double eta_pair(const double q[4], const double v[3], const double vg[3]) {
+  double th[3], ph[3], thg[3], phg[3], ph_in_g[3], cr[3];
+  kpo_basis(v, th, ph);
+  kpo_to_grain(q, ph, ph_in_g);
+  kpo_basis(vg, thg, phg);
+  cross3(ph_in_g, phg, cr);
+  double s = dot3(vg, cr);
+  double c = dot3(ph_in_g, phg);
+  return atan2(s, c);
+}
+
+double kpo_eta(const double q[4], const double n[3]) {
+  double ng[3];
+  kpo_to_grain(q, n, ng);
+  return eta_pair(q, n, ng);
+}
+
+/* Stokes rotation (stokes-rotation equation, Sec. 2.1): I and V invariant. */
+void kpo_rotate_stokes(double eta, const double s[4], double out[4]) {
+  double c2 = cos(2.0 * eta), s2 = sin(2.0 * eta);
+  double Q = c2 * s[1] + s2 * s[2];
+  double U = -s2 * s[1] + c2 * s[2];
+  out[0] = s[0]; out[1] = Q; out[2] = U; out[3] = s[3];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dipole grain optics (reading R4).                                         */
+/* ------------------------------------------------------------------------ */
+static int is_sphere(const kpo_dust *d) {
+  return d->a_perp_re == d->a_par_re && d->a_perp_im == d->a_par_im;
+}
+
+/* Dimensionless extinction coefficients alpha_1..3 of the transfer equation
+ * (Sec. 2.2, Appendix A) for a direction at polar angle t' from the grain
+ * axis.  C_theta/C_phi are the cross sections for E along theta'/phi'. */
+void kpo_alphas(const kpo_dust *d, double cos_t, double a[3]) {
+  if (is_sphere(d)) { a[0] = 1.0; a[1] = 0.0; a[2] = 0.0; return; }
+  double sin2 = 1.0 - cos_t * cos_t;
+  double c_th = d->a_perp_im * cos_t * cos_t + d->a_par_im * sin2;
+  double c_ph = d->a_perp_im;
+  double c_avg = (2.0 * d->a_perp_im + d->a_par_im) / 3.0;
+  a[0] = (c_th + c_ph) / (2.0 * c_avg);
+  a[1] = (c_th - c_ph) / (2.0 * c_avg);
+  a[2] = d->alpha3_scale * a[1];
+}
+
+static double norm_p(const kpo_dust *d) {
+  double ap2 = d->a_perp_re * d->a_perp_re + d->a_perp_im * d->a_perp_im;
+  double aa2 = d->a_par_re * d->a_par_re + d->a_par_im * d->a_par_im;
+  return (2.0 * ap2 + aa2) / 3.0;
+}
+
+/* Scattering Mueller matrix applied in the grain frame (Sec. 2.2, dipole
+ * approximation of Sec. 3): Jones J_ij = f_i . alpha . e_j between the
+ * natural bases of the incident (ng) and scattered (mg) grain-frame
+ * directions; rho_out = J rho_in J^dagger; normalised so the solid-angle
+ * integral of the scattered I is 1 for unpolarised light on
+ * orientation-averaged grains (reading R5). */
+static void mueller_grain(const kpo_dust *d, const double mg[3], const double ng[3],
+                          const double s[4], double out[4]) {
+  double e[2][3], f[2][3];
+  kpo_basis(ng, e[0], e[1]);
+  kpo_basis(mg, f[0], f[1]);
+  double complex a[3] = {d->a_perp_re + I * d->a_perp_im, d->a_perp_re + I * d->a_perp_im,
+                         d->a_par_re + I * d->a_par_im};
+  double complex J[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      J[i][j] = 0.0;
+      for (int k = 0; k < 3; ++k) J[i][j] += f[i][k] * a[k] * e[j][k];
+    }
+  double complex rho[2][2] = {{0.5 * (s[0] + s[1]), 0.5 * (s[2] - I * s[3])},
+                              {0.5 * (s[2] + I * s[3]), 0.5 * (s[0] - s[1])}};
+  double complex t[2][2], ro[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) t[i][j] = J[i][0] * rho[0][j] + J[i][1] * rho[1][j];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) ro[i][j] = t[i][0] * conj(J[j][0]) + t[i][1] * conj(J[j][1]);
+  double k = 3.0 / (8.0 * PI_ * norm_p(d));
+  out[0] = k * creal(ro[0][0] + ro[1][1]);
+  out[1] = k * creal(ro[0][0] - ro[1][1]);
+  out[2] = k * 2.0 * creal(ro[0][1]);
+  out[3] = -k * 2.0 * cimag(ro[0][1]);
+}
+
+/* P(m; n) s with both Stokes vectors in lab bases: into the grain frame by
+ * quaternion + eta rotation, Mueller there, and back (Sec. 2.1-2.2). */
+void kpo_mueller_lab(const kpo_dust *d, const double q[4], const double m[3],
+                     const double n[3], const double s[4], double out[4]) {
+  double ng[3], mg[3], sg[4], og[4];
+  kpo_to_grain(q, n, ng);
+  kpo_to_grain(q, m, mg);
+  kpo_rotate_stokes(eta_pair(q, n, ng), s, sg);
+  mueller_grain(d, mg, ng, sg, og);
+  kpo_rotate_stokes(-eta_pair(q, m, mg), og, out);
+}
+
+/* tr(alpha C alpha^dagger)/N_P, C = sum_ab rho_ab e_a e_b^T the incident 3x3
+ * coherency (reading R7), Stokes s in the grain-frame natural basis of ng. */
+static double scatter_weight_grain(const kpo_dust *d, const double ng[3], const double s[4]) {
+  double e[2][3];
+  kpo_basis(ng, e[0], e[1]);
+  double complex rho[2][2] = {{0.5 * (s[0] + s[1]), 0.5 * (s[2] - I * s[3])},
+                              {0.5 * (s[2] + I * s[3]), 0.5 * (s[0] - s[1])}};
+  double complex C[3][3];
+  for (int k = 0; k < 3; ++k)
+    for (int l = 0; l < 3; ++l) {
+      C[k][l] = 0.0;
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) C[k][l] += rho[a][b] * e[a][k] * e[b][l];
+    }
+  double complex al[3] = {d->a_perp_re + I * d->a_perp_im, d->a_perp_re + I * d->a_perp_im,
+                          d->a_par_re + I * d->a_par_im};
+  double tr = 0.0;
+  for (int k = 0; k < 3; ++k) tr += creal(al[k] * C[k][k] * conj(al[k]));
+  return tr / norm_p(d);
+}
+
+double kpo_scatter_weight(const kpo_dust *d, const double q[4], const double n[3],
+                          const double s[4]) {
+  double ng[3], sg[4];
+  kpo_to_grain(q, n, ng);
+  kpo_rotate_stokes(eta_pair(q, n, ng), s, sg);
+  return scatter_weight_grain(d, ng, sg);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Appendix A: analytic solution of the polarised transfer equation across  */
+/* one cell with constant coefficients and source (reading R1 for signs).    */
+/* The printed I, Q, U, V expressions are evaluated term by term; only the   */
+/* exponential factors are formed stably:                                    */
+/*   exp(-a1 x) cosh(a2 x) = (exp(-(a1-a2)x) + exp(-(a1+a2)x))/2 (no overflow)*/
+/*   1 - that             = -(expm1(-(a1-a2)x) + expm1(-(a1+a2)x))/2         */
+/*   exp(-a1 x) sinh(a2 x) = -exp(-(a1-a2)x) expm1(-2 a2 x)/2  (a2 >= 0)       */
+/* ------------------------------------------------------------------------ */
+void kpo_appA(double a1, double a2, double a3, double dtau,
+              const double src[4], const double in[4], double out[4]) {
+  double xm = (a1 - a2) * dtau, xp = (a1 + a2) * dtau;
+  double x1 = a1 * dtau, x3 = a3 * dtau;
+  double em1m = expm1(-xm), em1p = expm1(-xp);
+  double Ec = 0.5 * (exp(-xm) + exp(-xp));         /* e^{-a1 x} cosh(a2 x) */
+  /* e^{-a1 x} sinh(a2 x), factored so that neither a difference of two tiny
+   * exponentials nor an overflowing one is formed */
+  double Es = a2 >= 0.0 ? -0.5 * exp(-xm) * expm1(-2.0 * a2 * dtau)
+                        : 0.5 * exp(-xp) * expm1(2.0 * a2 * dtau);
+  double one_m_Ec = -0.5 * (em1m + em1p);
+  double e1 = exp(-x1);
+  double Fc = e1 * cos(x3), Fs = e1 * sin(x3);
+  double sh = sin(0.5 * x3);
+  double one_m_Fc = -expm1(-x1) + e1 * 2.0 * sh * sh;
+  double Is = 0.0, Qs = 0.0, Us = 0.0, Vs = 0.0;
+  if (src && (src[0] != 0.0 || src[1] != 0.0 || src[2] != 0.0 || src[3] != 0.0)) {
+    double D = a1 * a1 - a2 * a2, G = a1 * a1 + a3 * a3;
+    Is = (a1 * src[0] - a2 * src[1]) / D;
+    Qs = (a1 * src[1] - a2 * src[0]) / D;
+    Us = (a1 * src[2] - a3 * src[3]) / G;
+    Vs = (a1 * src[3] + a3 * src[2]) / G;
+  }
+  double I0 = in[0], Q0 = in[1], U0 = in[2], V0 = in[3];
+  out[0] = I0 * Ec - Q0 * Es + Is * one_m_Ec + Qs * Es;
+  out[1] = -I0 * Es + Q0 * Ec + Qs * one_m_Ec + Is * Es;
+  out[2] = U0 * Fc - V0 * Fs + Us * one_m_Fc + Vs * Fs;
+  out[3] = U0 * Fs + V0 * Fc + Vs * one_m_Fc - Us * Fs;
+}
+
+/* integral_0^len exp(-m s) ds = len * expm1(-m len)/(-m len) */
+static double seg_real(double m, double len) {
+  double x = -m * len;
+  return x == 0.0 ? len : len * expm1(x) / x;
+}
+
+/* integral_0^len exp((-m1 + i m3) s) ds */
+static double complex seg_cplx(double m1, double m3, double len) {
+  double a = -m1 * len, b = m3 * len;
+  if (a == 0.0 && b == 0.0) return len;
+  double sh = sin(0.5 * b);
+  double complex em1 = (expm1(a) * cos(b) - 2.0 * sh * sh) + I * (exp(a) * sin(b));
+  return len * em1 / (a + I * b);
+}
+
+/* Stokes vector over one straight segment with the scalar split of reading
+ * R3: d/ds I = -M I, M = [[m1,m2,0,0],[m2,m1,0,0],[0,0,m1,m3],[0,0,-m3,m1]]
+ * (per unit length).  integral = int_0^len exp(-M s) ds in (reading R5),
+ * out = exp(-M len) in (Appendix A with zero source). */
+void kpo_segment(double m1, double m2, double m3, double len,
+                 const double in[4], double integral[4], double out[4]) {
+  double gm = seg_real(m1 - m2, len), gp = seg_real(m1 + m2, len);
+  double Gc = 0.5 * (gm + gp);   /* int e^{-m1 s} cosh(m2 s) */
+  double Gs = 0.5 * (gm - gp);   /* int e^{-m1 s} sinh(m2 s) */
+  double complex H = seg_cplx(m1, m3, len);
+  double Hc = creal(H), Hs = cimag(H);
+  integral[0] = Gc * in[0] - Gs * in[1];
+  integral[1] = -Gs * in[0] + Gc * in[1];
+  integral[2] = Hc * in[2] - Hs * in[3];
+  integral[3] = Hs * in[2] + Hc * in[3];
+  kpo_appA(m1, m2, m3, len, NULL, in, out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Grid walking: integer cell + offset inside the cell in cell units.        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int64_t i[3];
+  double f[3];
+} gpos_t;
+
+static int inside(const kpo_grid *g, const gpos_t *p) {
+  return p->i[0] >= 0 && p->i[0] < g->nx && p->i[1] >= 0 && p->i[1] < g->ny &&
+         p->i[2] >= 0 && p->i[2] < g->nz;
+}
+static int64_t flat(const kpo_grid *g, const gpos_t *p) {
+  return p->i[0] + (int64_t)g->nx * (p->i[1] + (int64_t)g->ny * p->i[2]);
+}
+
+/* Cell holding a point; a coordinate exactly on a face belongs to the cell the
+ * direction points into. */
+static void locate(const kpo_grid *g, const double x[3], const double n[3], gpos_t *p) {
+  double o[3] = {g->x0, g->y0, g->z0};
+  for (int a = 0; a < 3; ++a) {
+    double t = (x[a] - o[a]) / g->dx;
+    double fl = floor(t);
+    p->i[a] = (int64_t)fl;
+    p->f[a] = t - fl;
+    if (p->f[a] == 0.0 && n[a] < 0.0) { p->i[a] -= 1; p->f[a] = 1.0; }
+  }
+}
+
+/* distance (cell units) to the exit face; ties go to the lowest axis */
+static double face_dist(const gpos_t *p, const double n[3], int *axis) {
+  double best = INFINITY;
+  *axis = -1;
+  for (int a = 0; a < 3; ++a) {
+    double t;
+    if (n[a] > 0.0) t = (1.0 - p->f[a]) / n[a];
+    else if (n[a] < 0.0) t = -p->f[a] / n[a];
+    else continue;
+    if (t < best) { best = t; *axis = a; }
+  }
+  return best;
+}
+
+static double clamp01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); }
+
+static void move_inside(gpos_t *p, const double n[3], double t) {
+  for (int a = 0; a < 3; ++a) p->f[a] = clamp01(p->f[a] + t * n[a]);
+}
+
+static void cross_face(gpos_t *p, const double n[3], double t, int axis) {
+  for (int a = 0; a < 3; ++a)
+    if (a != axis) p->f[a] = clamp01(p->f[a] + t * n[a]);
+  if (n[axis] > 0.0) { p->i[axis] += 1; p->f[axis] = 0.0; }
+  else { p->i[axis] -= 1; p->f[axis] = 1.0; }
+}
+
+static void cell_quat(const float *bhat, int64_t ncell, int64_t c, double q[4]) {
+  if (!bhat) { q[0] = 1.0; q[1] = q[2] = q[3] = 0.0; return; }
+  double b[3] = {bhat[c], bhat[ncell + c], bhat[2 * ncell + c]};
+  kpo_quat_from_b(b, q);
+}
+
+static uint64_t fnv_u32(uint64_t h, uint32_t v) {
+  for (int k = 0; k < 4; ++k) {
+    h ^= (v >> (8 * k)) & 0xffu;
+    h *= 1099511628211ULL;
+  }
+  return h;
+}
+static uint64_t hash_event(uint64_t h, uint32_t kind, int64_t cell) {
+  return fnv_u32(fnv_u32(h, kind), (uint32_t)cell);
+}
+
+static void dir_from(double mu, double phi, double n[3]) {
+  double s = sqrt(fmax(0.0, 1.0 - mu * mu));
+  n[0] = s * cos(phi);
+  n[1] = s * sin(phi);
+  n[2] = mu;
+}
+
+/* Scattering event (Sec. 2.2 and the rejection sampling named in Sec. 3):
+ * into the grain frame by quaternion and eta rotation, proposals uniform on
+ * the sphere (cos, azimuth, acceptance uniform -- three draws per trial),
+ * accept if u * bound <= [P s]_I (reading R6), rescale to the scattered power
+ * (reading R7), back to the lab frame.  Returns 0, or -1 if the bound is
+ * exceeded or no proposal is accepted within 100000 trials. */
+static int scatter_event(const kpo_dust *d, const double q[4], const double n[3],
+                         const double s[4], rng_t *rng, int64_t *trials,
+                         double m_out[3], double s_out[4]) {
+  double ng[3], sg[4];
+  kpo_to_grain(q, n, ng);
+  kpo_rotate_stokes(eta_pair(q, n, ng), s, sg);
+  double ap2 = d->a_perp_re * d->a_perp_re + d->a_perp_im * d->a_perp_im;
+  double aa2 = d->a_par_re * d->a_par_re + d->a_par_im * d->a_par_im;
+  double bound = 3.0 / (8.0 * PI_ * norm_p(d)) * fmax(ap2, aa2) * sg[0];
+  double mg[3], og[4];
+  int accepted = 0;
+  for (int trial = 0; trial < 100000 && !accepted; ++trial) {
+    double mu = 2.0 * draw(rng) - 1.0;
+    double ph = 2.0 * PI_ * draw(rng);
+    double ua = draw(rng);
+    ++*trials;
+    dir_from(mu, ph, mg);
+    mueller_grain(d, mg, ng, sg, og);
+    if (og[0] > bound * (1.0 + 1e-12)) return -1;
+    if (ua * bound <= og[0]) accepted = 1;
+  }
+  if (!accepted) return -1;
+  double scale = scatter_weight_grain(d, ng, sg) / og[0];
+  for (int k = 0; k < 4; ++k) og[k] *= scale;
+  double m[3];
+  kpo_from_grain(q, mg, m);
+  kpo_rotate_stokes(-eta_pair(q, m, mg), og, s_out);
+  m_out[0] = m[0]; m_out[1] = m[1]; m_out[2] = m[2];
+  return 0;
+}
+
+int kpo_scatter_sample(const kpo_dust *d, const double q[4], const double n[3],
+                       const double s[4], uint64_t seed, uint64_t lam, uint64_t packet,
+                       uint64_t first_draw, double m_out[3], double s_out[4],
+                       int64_t *trials) {
+  rng_t r = {{seed, lam}, packet, first_draw, 0, 0, {0, 0, 0, 0}};
+  *trials = 0;
+  return scatter_event(d, q, n, s, &r, trials, m_out, s_out);
+}
+
+typedef struct {
+  const kpo_grid *g;
+  const float *rho, *bhat;
+  const kpo_dust *d;
+  const kpo_source *src;
+  const kpo_opts *o;
+  int32_t lam;
+  uint64_t n_total;
+  int32_t n_views;
+  const kpo_view *views;
+  double (*vdir)[3];     /* camera directions */
+  double *S;             /* [cell][view][4] or NULL */
+} run_t;
+
+static void atomic_add(double *p, double v) {
+#pragma omp atomic
+  *p += v;
+}
+
+/* One packet from emission to termination (Sec. 2.2-2.3). */
+static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *st) {
+  const kpo_grid *g = R->g;
+  const kpo_dust *d = R->d;
+  int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
+  double kext = d->kappa_sca + d->kappa_abs;
+  double vol = g->dx * g->dx * g->dx;
+  rng_t rng = {{R->o->seed, (uint64_t)R->lam}, pid, 0, 0, 0, {0, 0, 0, 0}};
+
+  /* emission: isotropic direction, unpolarised, exponential scattering depth */
+  double n[3];
+  double u0 = draw(&rng), u1 = draw(&rng);
+  if (R->src->kind == 1) {
+    double nn = sqrt(dot3(R->src->dir, R->src->dir));
+    for (int a = 0; a < 3; ++a) n[a] = R->src->dir[a] / nn;
+  } else {
+    dir_from(2.0 * u0 - 1.0, 2.0 * PI_ * u1, n);
+  }
+  double tau = -log(draw(&rng));
+  double w0 = R->src->lum / (double)R->n_total;
+  double s[4] = {w0, 0.0, 0.0, 0.0};
+  st->e_emitted += w0;
+
+  gpos_t p;
+  locate(g, R->src->pos, n, &p);
+  int32_t events = 0, end = KPO_END_NONE;
+  int64_t steps = 0, last = -1;
+  uint64_t h = 14695981039346656037ULL;
+  if (!inside(g, &p)) {
+    end = KPO_END_ESCAPE;
+    st->escaped++;
+    st->e_escaped += s[0];
+  }
+  while (end == KPO_END_NONE) {
+    int64_t c = flat(g, &p);
+    last = c;
+    if (events >= R->o->max_events) {
+      h = hash_event(h, KPO_END_BUDGET, c);
+      end = KPO_END_BUDGET;
+      st->budget++;
+      st->e_budget += s[0];
+      break;
+    }
+    int axis;
+    double tf = face_dist(&p, n, &axis);
+    if (axis < 0 || !isfinite(tf)) { end = KPO_END_NUMERIC; st->numeric++; break; }
+    double rho = (double)R->rho[c];
+    double kbar = rho * d->kappa_sca, ke = rho * kext;
+    double lface = tf * g->dx, len;
+    int scat;
+    if (kbar > 0.0 && tau < kbar * lface) { len = tau / kbar; scat = 1; }
+    else { len = lface; tau -= kbar * lface; scat = 0; }
+    steps++;
+    st->cell_steps++;
+
+    double q[4];
+    cell_quat(R->bhat, ncell, c, q);
+    if (rho > 0.0 && len > 0.0) {
+      /* extinction across the segment in the grain frame (Sec. 2.2, App. A) */
+      double ng[3], al[3], sg[4], jg[4], og[4], jl[4];
+      kpo_to_grain(q, n, ng);
+      kpo_alphas(d, ng[2], al);
+      double eta = eta_pair(q, n, ng);
+      kpo_rotate_stokes(eta, s, sg);
+      kpo_segment(ke * al[0] - kbar, ke * al[1], ke * al[2], len, sg, jg, og);
+      kpo_rotate_stokes(-eta, jg, jl);
+      double I_before = s[0];
+      kpo_rotate_stokes(-eta, og, s);
+      st->e_absorbed += I_before - s[0];
+      /* scattering source tally, every segment (Sec. 2.3, reading R5) */
+      if (R->S && kbar > 0.0) {
+        for (int v = 0; v < R->n_views; ++v) {
+          double pv[4];
+          kpo_mueller_lab(d, q, R->vdir[v], n, jl, pv);
+          double *dst = R->S + (c * R->n_views + v) * 4;
+          for (int k = 0; k < 4; ++k) atomic_add(dst + k, kbar / vol * pv[k]);
+        }
+      }
+    }
+
+    if (scat) {
+      move_inside(&p, n, len / g->dx);
+      double m[3], i_in = s[0];
+      if (scatter_event(d, q, n, s, &rng, &st->trials, m, s) != 0) {
+        end = KPO_END_NUMERIC;
+        st->numeric++;
+        break;
+      }
+      n[0] = m[0]; n[1] = m[1]; n[2] = m[2];
+      st->e_scat_delta += s[0] - i_in;
+      events++;
+      st->scatterings++;
+      h = hash_event(h, KPO_EV_SCATTER, c);
+      tau = -log(draw(&rng));
+    } else {
+      cross_face(&p, n, tf, axis);
+      if (!inside(g, &p)) {
+        h = hash_event(h, KPO_END_ESCAPE, c);
+        end = KPO_END_ESCAPE;
+        st->escaped++;
+        st->e_escaped += s[0];
+        break;
+      }
+    }
+    if (!isfinite(s[0])) { end = KPO_END_NUMERIC; st->numeric++; break; }
+    /* Russian roulette (reading R8) */
+    if (R->o->rr_wmin > 0.0 && s[0] < R->o->rr_wmin * w0) {
+      double u = draw(&rng);
+      if (u < R->o->rr_psurv) {
+        double before = s[0];
+        for (int k = 0; k < 4; ++k) s[k] /= R->o->rr_psurv;
+        st->rr_survivals++;
+        st->e_rr_gained += s[0] - before;
+        h = hash_event(h, KPO_EV_RR_SURVIVE, flat(g, &p));
+      } else {
+        st->rr_kills++;
+        st->e_rr_killed += s[0];
+        h = hash_event(h, KPO_END_RR_KILL, flat(g, &p));
+        end = KPO_END_RR_KILL;
+        break;
+      }
+    }
+  }
+  if (tr) {
+    tr->packet = pid;
+    tr->end_kind = end;
+    tr->events = events;
+    tr->steps = steps;
+    tr->last_cell = last;
+    for (int a = 0; a < 3; ++a) tr->n[a] = n[a];
+    for (int k = 0; k < 4; ++k) tr->stokes[k] = s[k];
+    tr->hash = h;
+  }
+}
+
+static void view_dir(const kpo_view *v, double out[3]) {
+  out[0] = sin(v->theta) * cos(v->phi);
+  out[1] = sin(v->theta) * sin(v->phi);
+  out[2] = cos(v->theta);
+}
+
+static void stats_add(kpo_stats *a, const kpo_stats *b) {
+  a->cell_steps += b->cell_steps; a->scatterings += b->scatterings; a->trials += b->trials;
+  a->rr_kills += b->rr_kills; a->rr_survivals += b->rr_survivals; a->escaped += b->escaped;
+  a->budget += b->budget; a->numeric += b->numeric;
+  a->e_emitted += b->e_emitted; a->e_escaped += b->e_escaped; a->e_absorbed += b->e_absorbed;
+  a->e_rr_killed += b->e_rr_killed; a->e_rr_gained += b->e_rr_gained; a->e_budget += b->e_budget;
+  a->e_scat_delta += b->e_scat_delta;
+}
+
+static int check_inputs(const kpo_grid *g, const kpo_dust *d, const kpo_source *src) {
+  if (!g || !d || !src) return -1;
+  if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0 || !(g->dx > 0.0)) return -1;
+  if (!(d->kappa_sca >= 0.0) || !(d->kappa_abs >= 0.0)) return -1;
+  if (!is_sphere(d) && !(2.0 * d->a_perp_im + d->a_par_im > 0.0)) return -1;
+  if (src->kind != 0 && src->kind != 1) return -1;
+  return 0;
+}
+
+int kpo_transport(const kpo_grid *g, const float *rho, const float *bhat,
+                  const kpo_dust *d, int32_t lam, const kpo_source *src,
+                  int32_t n_views, const kpo_view *views,
+                  uint64_t p_begin, uint64_t p_end, uint64_t n_total,
+                  const kpo_opts *o, double *S, kpo_trace *traces,
+                  kpo_stats *stats) {
+  if (check_inputs(g, d, src) || !o || n_total == 0 || p_end < p_begin) return -1;
+  if (S && (n_views <= 0 || !views)) return -1;
+  double (*vdir)[3] = NULL;
+  if (n_views > 0) {
+    vdir = malloc(sizeof(double[3]) * (size_t)n_views);
+    for (int v = 0; v < n_views; ++v) view_dir(&views[v], vdir[v]);
+  }
+  run_t R = {g, rho, bhat, d, src, o, lam, n_total, n_views, views, vdir, S};
+  kpo_stats total;
+  memset(&total, 0, sizeof total);
+  int nth = o->nthreads;
+#pragma omp parallel num_threads(nth > 0 ? nth : omp_get_max_threads())
+  {
+    kpo_stats local;
+    memset(&local, 0, sizeof local);
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t k = 0; k < (int64_t)(p_end - p_begin); ++k)
+      run_packet(&R, p_begin + (uint64_t)k, traces ? &traces[k] : NULL, &local);
+#pragma omp critical
+    stats_add(&total, &local);
+  }
+  if (stats) stats_add(stats, &total);
+  free(vdir);
+  return 0;
+}
+
+int kpo_trace_packets(const kpo_grid *g, const float *rho, const float *bhat,
+                      const kpo_dust *d, int32_t lam, const kpo_source *src,
+                      const uint64_t *ids, uint64_t n_ids, uint64_t n_total,
+                      const kpo_opts *o, kpo_trace *traces) {
+  if (check_inputs(g, d, src) || !o || !ids || !traces || n_total == 0) return -1;
+  run_t R = {g, rho, bhat, d, src, o, lam, n_total, 0, NULL, NULL, NULL};
+  int nth = o->nthreads;
+#pragma omp parallel num_threads(nth > 0 ? nth : omp_get_max_threads())
+  {
+    kpo_stats local;
+    memset(&local, 0, sizeof local);
+#pragma omp for schedule(dynamic, 4)
+    for (int64_t k = 0; k < (int64_t)n_ids; ++k) run_packet(&R, ids[k], &traces[k], &local);
+  }
+  return 0;
+}
+
+/* Step 2 of two-step imaging (Sec. 2.3): march each pixel ray across the
+ * grid toward the camera, solving Appendix A cell by cell with the source
+ * S/(rho kappa_ext) per unit optical depth (reading R9 for the camera). */
+int kpo_image(const kpo_grid *g, const float *rho, const float *bhat,
+              const kpo_dust *d, int32_t n_views, const kpo_view *views,
+              const double *S, double *images) {
+  kpo_source dummy = {0, {0, 0, 0}, {0, 0, 1}, 1.0};
+  if (check_inputs(g, d, &dummy) || n_views <= 0 || !views || !S || !images) return -1;
+  int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
+  double kext = d->kappa_sca + d->kappa_abs;
+  double lo[3] = {g->x0, g->y0, g->z0};
+  double hi[3] = {g->x0 + g->nx * g->dx, g->y0 + g->ny * g->dx, g->z0 + g->nz * g->dx};
+  int32_t npx = views[0].npx, npy = views[0].npy;
+  for (int v = 0; v < n_views; ++v)
+    if (views[v].npx != npx || views[v].npy != npy || npx <= 0 || npy <= 0) return -1;
+  for (int v = 0; v < n_views; ++v) {
+    double om[3], th[3], ph[3];
+    view_dir(&views[v], om);
+    kpo_basis(om, th, ph);
+    double W = views[v].half_width;
+#pragma omp parallel for schedule(dynamic, 8) collapse(2)
+    for (int iy = 0; iy < npy; ++iy)
+      for (int ix = 0; ix < npx; ++ix) {
+        double xp = -W + (ix + 0.5) * (2.0 * W / npx);
+        double yp = -W + (iy + 0.5) * (2.0 * W / npy);
+        double P0[3];
+        for (int a = 0; a < 3; ++a) P0[a] = xp * ph[a] - yp * th[a];
+        double sn = -INFINITY, sf = INFINITY;
+        int miss = 0;
+        for (int a = 0; a < 3; ++a) {
+          if (om[a] != 0.0) {
+            double s1 = (lo[a] - P0[a]) / om[a], s2 = (hi[a] - P0[a]) / om[a];
+            sn = fmax(sn, fmin(s1, s2));
+            sf = fmin(sf, fmax(s1, s2));
+          } else if (P0[a] < lo[a] || P0[a] >= hi[a]) {
+            miss = 1;
+          }
+        }
+        double st[4] = {0, 0, 0, 0};
+        if (!miss && sn < sf) {
+          gpos_t p;
+          int64_t nn[3] = {g->nx, g->ny, g->nz};
+          for (int a = 0; a < 3; ++a) {
+            double t = (P0[a] + sn * om[a] - lo[a]) / g->dx;
+            double fl = floor(t);
+            int64_t i = (int64_t)fl;
+            if (i < 0) i = 0;
+            if (i > nn[a] - 1) i = nn[a] - 1;
+            p.i[a] = i;
+            p.f[a] = clamp01(t - (double)i);
+          }
+          while (inside(g, &p)) {
+            int axis;
+            double tf = face_dist(&p, om, &axis);
+            if (axis < 0) break;
+            int64_t c = flat(g, &p);
+            double r = (double)rho[c];
+            if (r > 0.0) {
+              double ke = r * kext, q[4], og[3], al[3], sg[4], srcg[4], src[4];
+              cell_quat(bhat, ncell, c, q);
+              kpo_to_grain(q, om, og);
+              kpo_alphas(d, og[2], al);
+              double eta = eta_pair(q, om, og);
+              const double *Sc = S + (c * n_views + v) * 4;
+              for (int k = 0; k < 4; ++k) src[k] = Sc[k] / ke;
+              kpo_rotate_stokes(eta, st, sg);
+              kpo_rotate_stokes(eta, src, srcg);
+              double out[4];
+              kpo_appA(al[0], al[1], al[2], ke * tf * g->dx, srcg, sg, out);
+              kpo_rotate_stokes(-eta, out, st);
+            }
+            cross_face(&p, om, tf, axis);
+          }
+        }
+        for (int k = 0; k < 4; ++k)
+          images[(((int64_t)v * 4 + k) * npy + iy) * npx + ix] = st[k];
+      }
+  }
+  return 0;
+}

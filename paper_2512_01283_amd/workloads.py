@@ -1,0 +1,240 @@
+"""Seeded synthetic inputs for the transport and imaging path.
+
+This module only builds input arrays and parameter records (density grids,
+alignment fields, grain polarizabilities, sources, cameras, packet counts).
+It holds none of the transport or imaging arithmetic, and it is the only
+module that both the HIP path and the CPU oracle consume.
+
+A workload is a plain dict:
+  grid    {nx, ny, nz, x0, y0, z0, dx}  cubic cells, lower corner (x0, y0, z0)
+  rho     float32[nz*ny*nx]             density, x fastest
+  bhat    float32[3, ncell] or None     unit grain-alignment direction per cell
+  dust    list (one per wavelength) of {kappa_sca, kappa_abs, a_perp, a_par,
+          alpha3_scale}; kappas per unit density per unit length
+  source  {kind (0 isotropic point, 1 pencil), pos, dir, lum}
+  views   list of {theta, phi, npx, npy, half_width}
+  packets list (one per wavelength) of packet counts
+  opts    {seed, rr_wmin, rr_psurv, max_events}
+  precision "f64" | "f32"  (arithmetic of the Monte Carlo step)
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+DEG = math.pi / 180.0
+
+
+# --------------------------------------------------------------------------
+# grain polarizabilities (input parameters, not part of the transport)
+# --------------------------------------------------------------------------
+def oblate_depolarization(aspect: float) -> tuple[float, float]:
+    """Depolarization factors (L_long, L_short) of an oblate spheroid with
+    axis ratio `aspect` = long/short (Bohren & Huffman 1983, Sec. 5.3).
+    The two long axes share L_long; L_long*2 + L_short = 1."""
+    e2 = 1.0 - 1.0 / aspect ** 2
+    g = math.sqrt((1.0 - e2) / e2)
+    l_long = g / (2.0 * e2) * (math.pi / 2.0 - math.atan(g)) - g * g / 2.0
+    return l_long, 1.0 - 2.0 * l_long
+
+
+def dipole_polarizabilities(m: complex, aspect: float) -> tuple[complex, complex]:
+    """(a_perp, a_par) of a perfectly aligned oblate spheroid in the dipole
+    approximation, a_j = (eps-1)/(1+L_j(eps-1)) (common volume factor dropped:
+    only ratios enter).  a_perp is across the symmetry (short) axis, which is
+    the alignment direction; a_par is along it."""
+    eps = m * m
+    l_long, l_short = oblate_depolarization(aspect)
+    return (eps - 1) / (1 + l_long * (eps - 1)), (eps - 1) / (1 + l_short * (eps - 1))
+
+
+def sphere_dust(kappa_ext: float, albedo: float) -> dict:
+    return dict(kappa_sca=albedo * kappa_ext, kappa_abs=(1.0 - albedo) * kappa_ext,
+                a_perp=1.0 + 0j, a_par=1.0 + 0j, alpha3_scale=0.0)
+
+
+def oblate_dust(kappa_ext: float, albedo: float, m=2.30 + 0.0228j, aspect=2.0,
+                alpha3_scale=0.0) -> dict:
+    ap, aa = dipole_polarizabilities(m, aspect)
+    return dict(kappa_sca=albedo * kappa_ext, kappa_abs=(1.0 - albedo) * kappa_ext,
+                a_perp=complex(ap), a_par=complex(aa), alpha3_scale=alpha3_scale)
+
+
+def default_opts(seed: int) -> dict:
+    return dict(seed=int(seed), rr_wmin=1e-3, rr_psurv=0.1, max_events=10000)
+
+
+def _centres(n: int, x0: float, dx: float) -> np.ndarray:
+    return x0 + (np.arange(n) + 0.5) * dx
+
+
+def _cube(n: int):
+    dx = 2.0 / n
+    return dict(nx=n, ny=n, nz=n, x0=-1.0, y0=-1.0, z0=-1.0, dx=dx)
+
+
+def _mesh(grid):
+    x = _centres(grid["nx"], grid["x0"], grid["dx"])
+    y = _centres(grid["ny"], grid["y0"], grid["dx"])
+    z = _centres(grid["nz"], grid["z0"], grid["dx"])
+    return np.meshgrid(x, y, z, indexing="ij")  # arrays indexed [i, j, k]
+
+
+def _flat(a_ijk: np.ndarray) -> np.ndarray:
+    """[i, j, k] -> flat x-fastest float32."""
+    return np.ascontiguousarray(np.transpose(a_ijk, (2, 1, 0)), dtype=np.float32).reshape(-1)
+
+
+def view(theta_deg, phi_deg, npix, half_width=1.0):
+    return dict(theta=theta_deg * DEG, phi=phi_deg * DEG, npx=npix, npy=npix,
+                half_width=half_width)
+
+
+# --------------------------------------------------------------------------
+# the five headline workloads
+# --------------------------------------------------------------------------
+def uniform_sphere(n=32, packets=100_000, albedo=1.0, tau_radius=1.0, seed=0,
+                   views=None, npix=64) -> dict:
+    """Uniform sphere of radius 1 on an n^3 grid over [-1,1]^3 (density 1 where
+    the cell centre lies inside), radial optical depth `tau_radius`, Rayleigh
+    spheres, isotropic unpolarised star at the centre (a grid vertex)."""
+    grid = _cube(n)
+    X, Y, Z = _mesh(grid)
+    rho = (X * X + Y * Y + Z * Z < 1.0).astype(np.float64)
+    return dict(name=f"sphere{n}", grid=grid, rho=_flat(rho), bhat=None,
+                dust=[sphere_dust(tau_radius, albedo)],
+                source=dict(kind=0, pos=(0.0, 0.0, 0.0), dir=(0.0, 0.0, 1.0), lum=1.0),
+                views=views if views is not None else [view(90.0, 0.0, npix)],
+                packets=[int(packets)], opts=default_opts(seed), precision="f64")
+
+
+def slab_clump(n=128, packets=10_000_000, seed=1, npix=None) -> dict:
+    """Slab |z| <= 0.25 of log-normal density (sigma_ln = 1; a Gaussian random
+    field from white noise smoothed over 2 cells and re-standardised; median
+    cell optical depth 0.02) plus a Gaussian clump at (0.4, 0, 0) of radius
+    0.05 with peak cell optical depth 100; cell optical depths clipped to
+    [1e-3, 100] inside the slab.  Oblate 2:1 grains (m = 2.30 + 0.0228i)
+    aligned with a uniform field tilted 45 deg from z toward x; albedo 0.5."""
+    from scipy.ndimage import gaussian_filter
+
+    grid = _cube(n)
+    dx = grid["dx"]
+    X, Y, Z = _mesh(grid)
+    rng = np.random.Generator(np.random.Philox(seed))
+    g = gaussian_filter(rng.standard_normal((n, n, n)), sigma=2.0, mode="wrap")
+    g = (g - g.mean()) / g.std()
+    kext = 1.0
+    tau_med = 0.02
+    tau_grf = tau_med * np.exp(g)                  # median tau_med, sigma_ln 1
+    r2c = (X - 0.4) ** 2 + Y ** 2 + Z ** 2
+    tau_clump = 100.0 * np.exp(-r2c / (2 * 0.05 ** 2))
+    tau = np.clip(tau_grf + tau_clump, 1e-3, 100.0)
+    rho = np.where(np.abs(Z) <= 0.25, tau / (kext * dx), 0.0)
+    b = np.array([math.sin(45 * DEG), 0.0, math.cos(45 * DEG)])
+    ncell = n ** 3
+    bhat = np.repeat(b[:, None], ncell, axis=1).astype(np.float32)
+    npix = npix or n
+    return dict(name=f"slab_clump{n}", grid=grid, rho=_flat(rho), bhat=bhat,
+                dust=[oblate_dust(kext, 0.5)],
+                source=dict(kind=0, pos=(0.0, 0.0, 0.0), dir=(0.0, 0.0, 1.0), lum=1.0),
+                views=[view(t, 0.0, npix) for t in (0.0, 30.0, 60.0, 90.0)],
+                packets=[int(packets)], opts=default_opts(seed), precision="f32")
+
+
+def disk_density(grid, h0=0.1, r_in=0.05, r_out=1.0, tau_mid=1.0e4):
+    """Flared disk rho ~ r^-1 exp(-z^2/2h^2), h/r = h0 (r/r_out)^0.25,
+    zero outside r_in <= r <= r_out (cylindrical r at cell centres).
+    Returns (rho, kappa_ext) with kappa_ext set so that the midplane optical
+    depth summed over the cells just above the +x axis is tau_mid."""
+    X, Y, Z = _mesh(grid)
+    r = np.sqrt(X * X + Y * Y)
+    h = h0 * r * (r / r_out) ** 0.25
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rho = np.where((r >= r_in) & (r <= r_out), np.exp(-Z * Z / (2 * h * h)) / r, 0.0)
+    rho32 = rho.astype(np.float32)
+    j0, k0 = grid["ny"] // 2, grid["nz"] // 2
+    column = rho32[grid["nx"] // 2:, j0, k0].astype(np.float64).sum() * grid["dx"]
+    return rho32, tau_mid / column
+
+
+def flared_disk(n=256, packets=100_000_000, seed=2, n_views=8, npix=None, albedo=0.5,
+                h0=0.1, tau_mid=1.0e4) -> dict:
+    """Flared protoplanetary disk on n^3 over [-1,1]^3, Rayleigh spheres,
+    central star, two-step imaging at n_views inclinations from 0 to 90 deg."""
+    grid = _cube(n)
+    rho, kext = disk_density(grid, h0=h0, tau_mid=tau_mid)
+    npix = npix or n
+    views = [view(k * 90.0 / max(n_views - 1, 1), 0.0, npix) for k in range(n_views)]
+    return dict(name=f"disk{n}", grid=grid, rho=_flat(rho), bhat=None,
+                dust=[sphere_dust(kext, albedo)],
+                source=dict(kind=0, pos=(0.0, 0.0, 0.0), dir=(0.0, 0.0, 1.0), lum=1.0),
+                views=views, packets=[int(packets)], opts=default_opts(seed),
+                precision="f32")
+
+
+def bitrev5(k: int) -> int:
+    return int(f"{k:05b}"[::-1], 2)
+
+
+def batched_lambda_counts(n_lambda=32, n_min=1.0e6, ratio=30.0):
+    return [int(round(n_min * ratio ** (bitrev5(k) / 31.0))) for k in range(n_lambda)]
+
+
+def helical_field(grid, pitch_deg=30.0) -> np.ndarray:
+    """B = cos(pitch) phi_hat_cyl + sin(pitch) z_hat at cell centres."""
+    X, Y, Z = _mesh(grid)
+    r = np.sqrt(X * X + Y * Y)
+    c, s = math.cos(pitch_deg * DEG), math.sin(pitch_deg * DEG)
+    bx, by, bz = -c * Y / r, c * X / r, np.full_like(r, s)
+    return np.stack([_flat(bx), _flat(by), _flat(bz)]).astype(np.float32)
+
+
+def batched_disk(n=256, n_lambda=32, seed=3, npix=None, counts=None) -> dict:
+    """Disk density with a helical field (pitch 30 deg) and aligned oblate
+    grains at n_lambda wavelengths, lambda_k = lambda_0 10^(k/31), opacities
+    kappa(lambda) = kappa(lambda_0) (lambda/lambda_0)^-1.5, uneven packet
+    counts 1e6 * 30^(bitrev5(k)/31); 16 views."""
+    grid = _cube(n)
+    rho, kext0 = disk_density(grid)
+    npix = npix or n
+    dust = [oblate_dust(kext0 * 10.0 ** (-1.5 * k / 31.0), 0.5) for k in range(n_lambda)]
+    views = [view(t, p, npix) for t in (15.0, 40.0, 65.0, 90.0) for p in (0.0, 90.0, 180.0, 270.0)]
+    return dict(name=f"batched_disk{n}x{n_lambda}", grid=grid, rho=_flat(rho),
+                bhat=helical_field(grid), dust=dust,
+                source=dict(kind=0, pos=(0.0, 0.0, 0.0), dir=(0.0, 0.0, 1.0), lum=1.0),
+                views=views,
+                packets=counts if counts is not None else batched_lambda_counts(n_lambda),
+                opts=default_opts(seed), precision="f32")
+
+
+# --------------------------------------------------------------------------
+# small verification workloads (pins and parity cases)
+# --------------------------------------------------------------------------
+def pencil_slab(n_z=256, tau_total=1.0, p0=0.01, alpha3_scale=0.0, twist=True,
+                start_tau=1.0, nxy=2) -> dict:
+    """Plane slab of optical depth tau_total along z with dichroic grains whose
+    alignment lies in the xy plane; twist=True rotates it as
+    (cos 2 pi tau, sin 2 pi tau, 0) with depth tau (Sec. 3.2), else it is
+    fixed along x.  A pencil beam starts at depth start_tau and travels -z.
+    Grains are given a_perp, a_par with Im ratio chosen so that the
+    polarization efficiency across the axis is p0."""
+    dz = tau_total / n_z
+    grid = dict(nx=nxy, ny=nxy, nz=n_z, x0=-nxy * dz / 2, y0=-nxy * dz / 2, z0=0.0, dx=dz)
+    zc = (np.arange(n_z) + 0.5) * dz
+    ang = 2 * math.pi * zc if twist else np.zeros(n_z)
+    b = np.stack([np.cos(ang), np.sin(ang), np.zeros(n_z)])
+    bhat = np.repeat(b[:, :, None], nxy * nxy, axis=2).reshape(3, -1).astype(np.float32)
+    rho = np.ones(nxy * nxy * n_z, dtype=np.float32)
+    # across the axis: alpha2/alpha1 = (Im a_par - Im a_perp)/(Im a_par + Im a_perp) = -p0
+    im_perp, im_par = 1.0 + p0, 1.0 - p0
+    dust = dict(kappa_sca=0.0, kappa_abs=1.0, a_perp=complex(1.0, im_perp),
+                a_par=complex(1.0, im_par), alpha3_scale=alpha3_scale)
+    # kappa_ext per unit length so that alpha1 (across the axis) = 1 in units of tau
+    c_avg = (2 * im_perp + im_par) / 3.0
+    a1 = (im_par + im_perp) / (2 * c_avg)
+    dust["kappa_abs"] = 1.0 / a1
+    return dict(name="pencil_slab", grid=grid, rho=rho, bhat=bhat, dust=[dust],
+                source=dict(kind=1, pos=(0.0, 0.0, start_tau), dir=(0.0, 0.0, -1.0), lum=1.0),
+                views=[view(0.0, 0.0, 4)], packets=[1],
+                opts=dict(default_opts(0), rr_wmin=0.0), precision="f64")
