@@ -1,0 +1,202 @@
+/*
+ * polrad.h -- C ABI of the MI355X (gfx950) polarized Monte Carlo radiative
+ * transfer library (libpolrad.so).
+ *
+ * The library implements the method of Yang & Wang, "Kratos-polrad: Novel GPU
+ * system for Monte-Carlo simulations with consistent polarization
+ * calculations" (arXiv:2512.01283): photon packets carrying the full Stokes
+ * vector (I,Q,U,V) through a uniform Cartesian density grid (Sec. 2.2), with
+ * per-cell analytic dichroic extinction (Appendix A), dipole Mueller-matrix
+ * scattering in the grain frame reached by quaternions (Sec. 2.1), and
+ * two-step imaging (Sec. 2.3): step 1 tallies the scattering source on the
+ * grid from every path segment, step 2 ray-marches it to each camera.
+ *
+ * General rules
+ *  - Every entry point returns kp_status; none throws or aborts.  On failure
+ *    kp_last_error() gives a message.  Arguments are validated before any
+ *    launch; an invalid argument leaves the context unchanged.
+ *  - A context is bound to one HIP device and is not thread-safe; separate
+ *    contexts are independent.
+ *  - "host" pointers are ordinary CPU memory.  "device" pointers are HIP
+ *    device allocations owned by the caller (borrowed: the caller keeps them
+ *    alive and unchanged until the stream of the call that uses them has
+ *    completed; the library never frees them).
+ *  - hip_stream is a hipStream_t passed as void* (NULL = default stream).
+ *  - Arrays over cells use the flat index c = i + nx*(j + ny*k), x fastest.
+ *
+ * Conventions (Sec. 2.1): a direction (theta, phi) has the Stokes basis
+ * theta_hat = (cos t cos p, cos t sin p, -sin t), phi_hat = (-sin p, cos p, 0);
+ * Q > 0 is polarisation along theta_hat, U > 0 at +45 degrees from theta_hat
+ * toward phi_hat, V > 0 where the coherency is 1/2 [[I+Q, U-iV],[U+iV, I-Q]].
+ */
+#ifndef POLRAD_H
+#define POLRAD_H
+#include <stddef.h>
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KP_OK = 0,
+  KP_ERR_ARG = 1,     /* invalid argument (nothing was launched) */
+  KP_ERR_OOM = 2,     /* device memory exhausted or estimate exceeds free memory */
+  KP_ERR_DEVICE = 3,  /* HIP runtime error */
+  KP_ERR_STATE = 4,   /* call out of order (e.g. kp_run before kp_set_grid) */
+  KP_ERR_NUMERIC = 5, /* a packet produced a non-finite state; results suspect */
+  KP_ERR_BUDGET = 6   /* strict mode: a packet reached the scattering-event cap */
+} kp_status;
+
+typedef struct kp_ctx kp_ctx;
+
+/* Uniform grid of cubic cells [x0 + i dx, x0 + (i+1) dx) x ... ; boundary:
+ * 0 = open (packets leaving the box escape).  Other values are rejected. */
+typedef struct {
+  int32_t nx, ny, nz;
+  double x0, y0, z0, dx;
+  int32_t boundary;
+} kp_grid;
+
+/* One dust species at one wavelength (Sec. 2.2, mfp-matrices equation):
+ * kappa_sca, kappa_abs are orientation-averaged opacities per unit density per
+ * unit length (lambda^-1 = rho * kappa).  The grain optics are a dipole
+ * (Sec. 3): complex polarizabilities (re, im) across (a_perp) and along
+ * (a_par) the grain symmetry axis, which is the local alignment direction;
+ * only their ratios matter.  a_perp == a_par means spheres (Rayleigh).
+ * alpha3_scale sets the artificial U-V extinction term alpha3 =
+ * alpha3_scale * alpha2 used by the twisted-field verification (Sec. 3.2);
+ * physical grains have 0. */
+typedef struct {
+  double kappa_sca, kappa_abs;
+  double a_perp[2], a_par[2];
+  double alpha3_scale;
+} kp_dust;
+
+/* kind 0: isotropic unpolarised point source at pos; kind 1: pencil beam from
+ * pos along dir (tests).  lum is the luminosity per wavelength; each packet
+ * of a wavelength with N packets starts with I = lum / N.  pos must lie in
+ * the closed grid box. */
+typedef struct {
+  int32_t kind;
+  double pos[3], dir[3];
+  double lum;
+} kp_source;
+
+/* Camera (Sec. 2.3): direction (theta, phi) from the grid toward the
+ * observer; orthographic, npx x npy pixels spanning [-half_width, half_width]^2
+ * in the sky plane through the origin, image x along phi_hat, image y along
+ * -theta_hat; Stokes in the (theta_hat, phi_hat) basis of the camera
+ * direction.  All views of a context share npx and npy. */
+typedef struct {
+  double theta, phi;
+  int32_t npx, npy;
+  double half_width;
+} kp_view;
+
+/* Run options.
+ *  seed            Philox4x64-10 key word 0 (key word 1 = wavelength index).
+ *  transport_fp64  1: step 1 in FP64 (parity runs); 0: FP32 with FP64 tallies.
+ *  tally_mode      0 (only value): per-cell incident coherency tally.
+ *  rr_wmin, rr_psurv  Russian roulette when I < rr_wmin * I0 (0 disables).
+ *  max_events      scattering-event cap per packet (>= 1).
+ *  trace_packets   number of packets per wavelength whose final state is
+ *                  recorded (ids 0, trace_stride, 2 trace_stride, ...).
+ *  trace_stride    >= 1.
+ *  block_size      threads per block of the transport kernel (64..1024, a
+ *                  multiple of 64; 0 = default 256).
+ *  blocks_per_cu   resident blocks per compute unit (0 = default).
+ *  strict          1: kp_run returns KP_ERR_BUDGET if any packet hit the cap. */
+typedef struct {
+  uint64_t seed;
+  int32_t transport_fp64;
+  int32_t tally_mode;
+  double rr_wmin, rr_psurv;
+  int64_t max_events;
+  uint32_t trace_packets;
+  uint32_t trace_stride;
+  int32_t block_size;
+  int32_t blocks_per_cu;
+  int32_t strict;
+} kp_opts;
+
+/* Counters of the last kp_run/kp_transport (energies in units of lum). */
+typedef struct {
+  int64_t cell_steps, scatterings, trials, rr_kills, rr_survivals,
+          escaped, budget, numeric;
+  double e_emitted, e_escaped, e_absorbed, e_rr_killed, e_rr_gained, e_budget,
+         e_scat_delta;
+  double ms_transport; /* transport kernel time (HIP events on the run's stream) */
+  double ms_image;     /* imaging kernel time */
+  int64_t packets;
+} kp_stats;
+
+/* Final state of a traced packet. end_kind: 2 escaped, 4 roulette kill,
+ * 5 event cap, 6 non-finite state.  hash: FNV-1a-64 over the 4-byte
+ * little-endian (kind, cell) pairs of its events (1 scatter, 2 escape,
+ * 3 roulette survival, 4 roulette kill, 5 cap). */
+typedef struct {
+  uint64_t packet;
+  int32_t end_kind;
+  int32_t events;
+  int64_t steps;
+  int64_t last_cell;
+  double n[3];
+  double stokes[4];
+  uint64_t hash;
+} kp_packet_trace;
+
+/* Create a context on HIP device `device`.  *out receives an owned handle
+ * (release with kp_destroy). */
+kp_status kp_create(int device, kp_ctx **out);
+void kp_destroy(kp_ctx *ctx);
+const char *kp_last_error(const kp_ctx *ctx);
+
+/* Density rho[ncell] (float32, finite, >= 0) and optional unit alignment
+ * field bhat[3][ncell] (float32 SoA, |b| = 1 within 1e-5; NULL = no
+ * alignment: the grain frame coincides with the lab frame).
+ * kp_set_grid copies host arrays into library-owned device memory;
+ * kp_set_grid_device borrows device arrays (validated by a device pass).
+ * Either resets the tally. */
+kp_status kp_set_grid(kp_ctx *ctx, const kp_grid *grid, const float *rho, const float *bhat);
+kp_status kp_set_grid_device(kp_ctx *ctx, const kp_grid *grid, const float *d_rho,
+                             const float *d_bhat);
+
+/* n_lambda (1..1024) dust records, one per wavelength (copied). */
+kp_status kp_set_dust(kp_ctx *ctx, int32_t n_lambda, const kp_dust *dust);
+kp_status kp_set_source(kp_ctx *ctx, const kp_source *src);
+/* n_views (1..4096) cameras (copied). */
+kp_status kp_set_views(kp_ctx *ctx, int32_t n_views, const kp_view *views);
+
+/* Step 1 + step 2 for all wavelengths in one persistent launch each:
+ * packets_per_lambda[n_lambda] (host, >= 0, total >= 1).  Images stay on the
+ * device; the call synchronises hip_stream before returning (it reads the
+ * counters back).  Returns KP_ERR_NUMERIC / KP_ERR_BUDGET (strict) after a
+ * completed run whose counters show them. */
+kp_status kp_run(kp_ctx *ctx, const uint64_t *packets_per_lambda, const kp_opts *opts,
+                 void *hip_stream);
+/* Step 1 only (Sec. 2.3 first step): tallies the scattering source. */
+kp_status kp_transport(kp_ctx *ctx, const uint64_t *packets_per_lambda, const kp_opts *opts,
+                       void *hip_stream);
+/* Step 2 only, from the tally of the last kp_transport. */
+kp_status kp_image(kp_ctx *ctx, void *hip_stream);
+/* Step 2 alone on a caller-supplied per-view source (wavelength 0):
+ * d_S device [ncell][n_views][4] FP64, emissivity per unit length per unit
+ * solid angle in each camera basis; d_out device [n_views][4][npy][npx]. */
+kp_status kp_image_source(kp_ctx *ctx, const double *d_S, double *d_out, void *hip_stream);
+
+/* Images [n_lambda][n_views][4][npy][npx] FP64 of the last step 2; n is the
+ * element count of the destination and must equal that size. */
+kp_status kp_get_images(kp_ctx *ctx, double *host_out, size_t n);
+kp_status kp_get_images_device(kp_ctx *ctx, double *d_out, size_t n, void *hip_stream);
+/* Incident-coherency tally [n_lambda][ncell][9] FP64 of the last step 1
+ * (components xx yy zz xy xz yz and the imaginary yz zx xy parts), per unit
+ * cell volume times dx^3; n must equal that size. */
+kp_status kp_get_tally(kp_ctx *ctx, double *host_out, size_t n);
+kp_status kp_get_stats(kp_ctx *ctx, kp_stats *out);
+/* Traces of the last step 1: n must equal n_lambda * trace_packets. */
+kp_status kp_get_trace(kp_ctx *ctx, kp_packet_trace *out, size_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,597 @@
+// kp_api.cpp -- host side of the C ABI declared in include/polrad.h:
+// argument validation, device buffers owned by a context, kernel launches,
+// timing with HIP events recorded on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/polrad.h"
+#include "kp_internal.hpp"
+
+using namespace kp;
+
+struct kp_ctx {
+  int device = 0;
+  int cu_count = 0;
+  std::string err;
+  // grid
+  bool have_grid = false;
+  kp_grid grid{};
+  uint64_t ncell = 0;
+  float* d_rho = nullptr;   // active pointers (owned or borrowed)
+  float* d_bhat = nullptr;  // [3][ncell] or null
+  float* own_rho = nullptr;
+  float* own_bhat = nullptr;
+  // dust, source, views
+  std::vector<kp_dust> dust;
+  bool have_source = false;
+  kp_source src{};
+  std::vector<kp_view> views;
+  std::vector<ViewDev> hviews;
+  ViewDev* d_views = nullptr;
+  size_t d_views_n = 0;
+  std::vector<DustDev> hdust;
+  DustDev* d_dust = nullptr;
+  size_t d_dust_n = 0;
+  // results
+  double* d_tally = nullptr;
+  size_t tally_n = 0;      // doubles allocated
+  int tally_lambda = 0;    // wavelengths of the last step 1
+  bool have_tally = false;
+  double* d_images = nullptr;
+  size_t images_n = 0;
+  bool have_images = false;
+  size_t images_valid_n = 0;
+  StatsDev* d_stats = nullptr;
+  unsigned long long* d_counter = nullptr;
+  unsigned long long* d_bad = nullptr;
+  TraceDev* d_traces = nullptr;
+  size_t traces_n = 0;
+  size_t traces_valid = 0;
+  kp_stats stats{};
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+kp_status fail(kp_ctx* c, kp_status st, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+kp_status fail(kp_ctx* c, kp_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+kp_status hip_fail(kp_ctx* c, hipError_t e, const char* what) {
+  return fail(c, e == hipErrorOutOfMemory ? KP_ERR_OOM : KP_ERR_DEVICE, "%s: %s", what,
+              hipGetErrorString(e));
+}
+
+#define KP_HIP(call, what)                        \
+  do {                                            \
+    hipError_t e_ = (call);                       \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+  } while (0)
+
+bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+bool is_sphere(const kp_dust& d) {
+  return d.a_perp[0] == d.a_par[0] && d.a_perp[1] == d.a_par[1];
+}
+
+template <typename T>
+kp_status ensure(kp_ctx* ctx, T** p, size_t* have, size_t need, const char* what) {
+  if (*have >= need && *p) return KP_OK;
+  if (*p) { (void)hipFree(*p); *p = nullptr; *have = 0; }
+  if (need == 0) return KP_OK;
+  hipError_t e = hipMalloc((void**)p, need * sizeof(T));
+  if (e != hipSuccess) { *p = nullptr; return hip_fail(ctx, e, what); }
+  *have = need;
+  return KP_OK;
+}
+
+void release_grid(kp_ctx* ctx) {
+  if (ctx->own_rho) (void)hipFree(ctx->own_rho);
+  if (ctx->own_bhat) (void)hipFree(ctx->own_bhat);
+  ctx->own_rho = ctx->own_bhat = nullptr;
+  ctx->d_rho = ctx->d_bhat = nullptr;
+  ctx->have_grid = false;
+  ctx->have_tally = false;
+  ctx->have_images = false;
+}
+
+kp_status check_grid(kp_ctx* ctx, const kp_grid* g) {
+  if (!g) return fail(ctx, KP_ERR_ARG, "grid is NULL");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(ctx, KP_ERR_ARG, "grid dimensions must be >= 1");
+  if (!(g->dx > 0.0) || !std::isfinite(g->dx)) return fail(ctx, KP_ERR_ARG, "dx must be finite and > 0");
+  if (!std::isfinite(g->x0) || !std::isfinite(g->y0) || !std::isfinite(g->z0))
+    return fail(ctx, KP_ERR_ARG, "grid origin must be finite");
+  if (g->boundary != 0) return fail(ctx, KP_ERR_ARG, "only open boundaries (0) are supported");
+  const double n = (double)g->nx * g->ny * g->nz;
+  if (n > 4.0e9) return fail(ctx, KP_ERR_ARG, "grid has more than 4e9 cells");
+  return KP_OK;
+}
+
+void fill_view(const kp_view& v, ViewDev& o) {
+  o.ox = std::sin(v.theta) * std::cos(v.phi);
+  o.oy = std::sin(v.theta) * std::sin(v.phi);
+  o.oz = std::cos(v.theta);
+  const double r2 = o.ox * o.ox + o.oy * o.oy, st = std::sqrt(r2);
+  double cp = 1.0, sp = 0.0;
+  if (r2 > 8.673617379884035e-19) { cp = o.ox / st; sp = o.oy / st; }
+  o.tx = o.oz * cp; o.ty = o.oz * sp; o.tz = -st;
+  o.px = -sp; o.py = cp; o.pz = 0.0;
+  o.half_width = v.half_width;
+}
+
+// per-wavelength constants in cell units
+void fill_dust(const kp_ctx* ctx, const uint64_t* counts, std::vector<DustDev>& out) {
+  const double dx = ctx->grid.dx;
+  const double lum = ctx->src.lum;
+  out.resize(ctx->dust.size());
+  uint64_t first = 0;
+  for (size_t l = 0; l < ctx->dust.size(); ++l) {
+    const kp_dust& d = ctx->dust[l];
+    DustDev& o = out[l];
+    std::memset(&o, 0, sizeof o);
+    o.ks_cell = d.kappa_sca * dx;
+    o.ka_cell = d.kappa_abs * dx;
+    o.ke_cell = (d.kappa_sca + d.kappa_abs) * dx;
+    o.kext = d.kappa_sca + d.kappa_abs;
+    o.sphere = is_sphere(d) ? 1 : 0;
+    if (o.sphere) {
+      o.ap_re = o.aa_re = 1.0;
+      o.ap_im = o.aa_im = 0.0;
+    } else {
+      o.ap_re = d.a_perp[0]; o.ap_im = d.a_perp[1];
+      o.aa_re = d.a_par[0]; o.aa_im = d.a_par[1];
+    }
+    const double cavg = (2.0 * o.ap_im + o.aa_im) / 3.0;
+    o.inv2cavg = o.sphere ? 0.0 : 1.0 / (2.0 * cavg);
+    o.alpha3_scale = d.alpha3_scale;
+    const double ap2 = o.ap_re * o.ap_re + o.ap_im * o.ap_im;
+    const double aa2 = o.aa_re * o.aa_re + o.aa_im * o.aa_im;
+    const double np = (2.0 * ap2 + aa2) / 3.0;
+    o.pfac = 3.0 / (8.0 * M_PI * np);
+    o.bound_fac = o.pfac * (ap2 > aa2 ? ap2 : aa2);
+    o.ap2_np = ap2 / np;
+    o.aa2_np = aa2 / np;
+    o.count = counts ? counts[l] : 0;
+    o.first = first;
+    o.w0 = o.count ? lum / (double)o.count : 0.0;
+    first += o.count;
+  }
+}
+
+kp_status upload_small(kp_ctx* ctx, hipStream_t s) {
+  kp_status st = ensure(ctx, &ctx->d_dust, &ctx->d_dust_n, ctx->hdust.size(), "dust table");
+  if (st) return st;
+  st = ensure(ctx, &ctx->d_views, &ctx->d_views_n, ctx->hviews.size(), "view table");
+  if (st) return st;
+  KP_HIP(hipMemcpyAsync(ctx->d_dust, ctx->hdust.data(), ctx->hdust.size() * sizeof(DustDev),
+                        hipMemcpyHostToDevice, s), "dust upload");
+  KP_HIP(hipMemcpyAsync(ctx->d_views, ctx->hviews.data(), ctx->hviews.size() * sizeof(ViewDev),
+                        hipMemcpyHostToDevice, s), "view upload");
+  return KP_OK;
+}
+
+kp_status check_ready(kp_ctx* ctx) {
+  if (!ctx->have_grid) return fail(ctx, KP_ERR_STATE, "kp_set_grid has not been called");
+  if (ctx->dust.empty()) return fail(ctx, KP_ERR_STATE, "kp_set_dust has not been called");
+  if (!ctx->have_source) return fail(ctx, KP_ERR_STATE, "kp_set_source has not been called");
+  if (ctx->views.empty()) return fail(ctx, KP_ERR_STATE, "kp_set_views has not been called");
+  const kp_grid& g = ctx->grid;
+  const double lo[3] = {g.x0, g.y0, g.z0};
+  const int n[3] = {g.nx, g.ny, g.nz};
+  for (int k = 0; k < 3; ++k)
+    if (!(ctx->src.pos[k] >= lo[k] && ctx->src.pos[k] <= lo[k] + n[k] * g.dx))
+      return fail(ctx, KP_ERR_ARG, "source position lies outside the grid box");
+  return KP_OK;
+}
+
+kp_status image_launch(kp_ctx* ctx, bool user_source, const double* d_S, double* d_out,
+                       int n_lambda, hipStream_t s) {
+  ImageArgs a{};
+  a.rho = ctx->d_rho;
+  if (ctx->d_bhat) {
+    a.bx = ctx->d_bhat;
+    a.by = ctx->d_bhat + ctx->ncell;
+    a.bz = ctx->d_bhat + 2 * ctx->ncell;
+  }
+  a.nx = ctx->grid.nx; a.ny = ctx->grid.ny; a.nz = ctx->grid.nz;
+  a.x0 = ctx->grid.x0; a.y0 = ctx->grid.y0; a.z0 = ctx->grid.z0; a.dx = ctx->grid.dx;
+  a.dust = ctx->d_dust;
+  a.views = ctx->d_views;
+  a.n_views = (int)ctx->views.size();
+  a.n_lambda = n_lambda;
+  a.npx = ctx->views[0].npx;
+  a.npy = ctx->views[0].npy;
+  a.tally = ctx->d_tally;
+  a.user_S = d_S;
+  a.images = d_out;
+  a.ncell = ctx->ncell;
+  // every wavelength shares the grain model kind of wavelength 0 for the
+  // kernel choice; mixed sphere / non-sphere tables use the general kernel
+  bool sphere = true;
+  for (int l = 0; l < n_lambda; ++l) sphere = sphere && ctx->hdust[l].sphere;
+  KP_HIP(hipEventRecord(ctx->ev[2], s), "event record");
+  KP_HIP(launch_image(a, ctx->d_bhat != nullptr, sphere, user_source, s), "imaging kernel launch");
+  KP_HIP(hipEventRecord(ctx->ev[3], s), "event record");
+  return KP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kp_status kp_create(int device, kp_ctx** out) {
+  if (!out) return KP_ERR_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return KP_ERR_DEVICE;
+  if (device < 0 || device >= n) return KP_ERR_ARG;
+  kp_ctx* ctx = new (std::nothrow) kp_ctx();
+  if (!ctx) return KP_ERR_OOM;
+  ctx->device = device;
+  if (hipSetDevice(device) != hipSuccess) { delete ctx; return KP_ERR_DEVICE; }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete ctx; return KP_ERR_DEVICE; }
+  ctx->cu_count = prop.multiProcessorCount;
+  for (auto& e : ctx->ev)
+    if (hipEventCreate(&e) != hipSuccess) { kp_destroy(ctx); return KP_ERR_DEVICE; }
+  if (hipMalloc(&ctx->d_stats, sizeof(StatsDev)) != hipSuccess ||
+      hipMalloc(&ctx->d_counter, sizeof(unsigned long long)) != hipSuccess ||
+      hipMalloc(&ctx->d_bad, sizeof(unsigned long long)) != hipSuccess) {
+    kp_destroy(ctx);
+    return KP_ERR_OOM;
+  }
+  *out = ctx;
+  return KP_OK;
+}
+
+void kp_destroy(kp_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  release_grid(ctx);
+  for (void* p : {(void*)ctx->d_views, (void*)ctx->d_dust, (void*)ctx->d_tally,
+                  (void*)ctx->d_images, (void*)ctx->d_stats, (void*)ctx->d_counter,
+                  (void*)ctx->d_bad, (void*)ctx->d_traces})
+    if (p) (void)hipFree(p);
+  for (auto& e : ctx->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+const char* kp_last_error(const kp_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+kp_status kp_set_grid(kp_ctx* ctx, const kp_grid* g, const float* rho, const float* bhat) {
+  if (!ctx) return KP_ERR_ARG;
+  kp_status st = check_grid(ctx, g);
+  if (st) return st;
+  if (!rho) return fail(ctx, KP_ERR_ARG, "rho is NULL");
+  const uint64_t n = (uint64_t)g->nx * g->ny * g->nz;
+  for (uint64_t i = 0; i < n; ++i)
+    if (!(rho[i] >= 0.0f) || !std::isfinite(rho[i]))
+      return fail(ctx, KP_ERR_ARG, "rho[%llu] is negative or not finite", (unsigned long long)i);
+  if (bhat)
+    for (uint64_t i = 0; i < n; ++i) {
+      const double b = std::sqrt((double)bhat[i] * bhat[i] + (double)bhat[n + i] * bhat[n + i] +
+                                 (double)bhat[2 * n + i] * bhat[2 * n + i]);
+      if (!(std::fabs(b - 1.0) <= 1e-5))
+        return fail(ctx, KP_ERR_ARG, "bhat[:, %llu] is not a unit vector", (unsigned long long)i);
+    }
+  KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  release_grid(ctx);
+  KP_HIP(hipMalloc(&ctx->own_rho, n * sizeof(float)), "rho allocation");
+  KP_HIP(hipMemcpy(ctx->own_rho, rho, n * sizeof(float), hipMemcpyHostToDevice), "rho upload");
+  if (bhat) {
+    KP_HIP(hipMalloc(&ctx->own_bhat, 3 * n * sizeof(float)), "bhat allocation");
+    KP_HIP(hipMemcpy(ctx->own_bhat, bhat, 3 * n * sizeof(float), hipMemcpyHostToDevice), "bhat upload");
+  }
+  ctx->d_rho = ctx->own_rho;
+  ctx->d_bhat = ctx->own_bhat;
+  ctx->grid = *g;
+  ctx->ncell = n;
+  ctx->have_grid = true;
+  return KP_OK;
+}
+
+kp_status kp_set_grid_device(kp_ctx* ctx, const kp_grid* g, const float* d_rho, const float* d_bhat) {
+  if (!ctx) return KP_ERR_ARG;
+  kp_status st = check_grid(ctx, g);
+  if (st) return st;
+  if (!d_rho) return fail(ctx, KP_ERR_ARG, "rho is NULL");
+  const uint64_t n = (uint64_t)g->nx * g->ny * g->nz;
+  KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  KP_HIP(hipMemset(ctx->d_bad, 0, sizeof(unsigned long long)), "validation reset");
+  KP_HIP(launch_validate(d_rho, d_bhat, d_bhat ? d_bhat + n : nullptr,
+                         d_bhat ? d_bhat + 2 * n : nullptr, n, ctx->d_bad, 0), "validation launch");
+  unsigned long long bad = 0;
+  KP_HIP(hipMemcpy(&bad, ctx->d_bad, sizeof bad, hipMemcpyDeviceToHost), "validation readback");
+  if (bad) return fail(ctx, KP_ERR_ARG, "%llu grid values are invalid (negative/non-finite rho or non-unit bhat)", bad);
+  release_grid(ctx);
+  ctx->d_rho = const_cast<float*>(d_rho);
+  ctx->d_bhat = const_cast<float*>(d_bhat);
+  ctx->grid = *g;
+  ctx->ncell = n;
+  ctx->have_grid = true;
+  return KP_OK;
+}
+
+kp_status kp_set_dust(kp_ctx* ctx, int32_t n_lambda, const kp_dust* d) {
+  if (!ctx) return KP_ERR_ARG;
+  if (n_lambda < 1 || n_lambda > 1024 || !d) return fail(ctx, KP_ERR_ARG, "n_lambda must be in 1..1024");
+  for (int l = 0; l < n_lambda; ++l) {
+    const kp_dust& x = d[l];
+    if (!(x.kappa_sca >= 0.0) || !(x.kappa_abs >= 0.0) || !std::isfinite(x.kappa_sca) ||
+        !std::isfinite(x.kappa_abs) || !(x.kappa_sca + x.kappa_abs > 0.0))
+      return fail(ctx, KP_ERR_ARG, "dust %d: opacities must be finite, >= 0, with a positive sum", l);
+    const double v[5] = {x.a_perp[0], x.a_perp[1], x.a_par[0], x.a_par[1], x.alpha3_scale};
+    for (double t : v)
+      if (!std::isfinite(t)) return fail(ctx, KP_ERR_ARG, "dust %d: non-finite polarizability", l);
+    if (!is_sphere(x)) {
+      if (!(2.0 * x.a_perp[1] + x.a_par[1] > 0.0) || x.a_perp[1] < 0.0 || x.a_par[1] < 0.0)
+        return fail(ctx, KP_ERR_ARG, "dust %d: aligned grains need Im(a) >= 0 with a positive average", l);
+    } else if (x.a_perp[0] == 0.0 && x.a_perp[1] == 0.0) {
+      return fail(ctx, KP_ERR_ARG, "dust %d: zero polarizability", l);
+    }
+  }
+  ctx->dust.assign(d, d + n_lambda);
+  ctx->have_tally = false;
+  ctx->have_images = false;
+  return KP_OK;
+}
+
+kp_status kp_set_source(kp_ctx* ctx, const kp_source* s) {
+  if (!ctx) return KP_ERR_ARG;
+  if (!s) return fail(ctx, KP_ERR_ARG, "source is NULL");
+  if (s->kind != 0 && s->kind != 1) return fail(ctx, KP_ERR_ARG, "source kind must be 0 or 1");
+  if (!finite3(s->pos) || !std::isfinite(s->lum) || !(s->lum > 0.0))
+    return fail(ctx, KP_ERR_ARG, "source position/luminosity invalid");
+  kp_source c = *s;
+  if (s->kind == 1) {
+    if (!finite3(s->dir)) return fail(ctx, KP_ERR_ARG, "pencil direction not finite");
+    const double n = std::sqrt(s->dir[0] * s->dir[0] + s->dir[1] * s->dir[1] + s->dir[2] * s->dir[2]);
+    if (!(n > 0.0)) return fail(ctx, KP_ERR_ARG, "pencil direction is zero");
+    for (int k = 0; k < 3; ++k) c.dir[k] = s->dir[k] / n;
+  }
+  ctx->src = c;
+  ctx->have_source = true;
+  return KP_OK;
+}
+
+kp_status kp_set_views(kp_ctx* ctx, int32_t n_views, const kp_view* v) {
+  if (!ctx) return KP_ERR_ARG;
+  if (n_views < 1 || n_views > 4096 || !v) return fail(ctx, KP_ERR_ARG, "n_views must be in 1..4096");
+  for (int k = 0; k < n_views; ++k) {
+    if (!std::isfinite(v[k].theta) || !std::isfinite(v[k].phi) || !(v[k].half_width > 0.0) ||
+        !std::isfinite(v[k].half_width))
+      return fail(ctx, KP_ERR_ARG, "view %d: invalid direction or half width", k);
+    if (v[k].npx < 1 || v[k].npy < 1 || v[k].npx > 16384 || v[k].npy > 16384)
+      return fail(ctx, KP_ERR_ARG, "view %d: npx, npy must be in 1..16384", k);
+    if (v[k].npx != v[0].npx || v[k].npy != v[0].npy)
+      return fail(ctx, KP_ERR_ARG, "all views must share npx and npy");
+  }
+  ctx->views.assign(v, v + n_views);
+  ctx->hviews.resize(n_views);
+  for (int k = 0; k < n_views; ++k) fill_view(v[k], ctx->hviews[k]);
+  ctx->have_images = false;
+  return KP_OK;
+}
+
+kp_status kp_transport(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, void* stream) {
+  if (!ctx) return KP_ERR_ARG;
+  kp_status st = check_ready(ctx);
+  if (st) return st;
+  if (!counts || !o) return fail(ctx, KP_ERR_ARG, "packets or options are NULL");
+  const int nl = (int)ctx->dust.size();
+  uint64_t total = 0;
+  for (int l = 0; l < nl; ++l) {
+    if (counts[l] > (1ull << 40)) return fail(ctx, KP_ERR_ARG, "packet count of wavelength %d too large", l);
+    total += counts[l];
+  }
+  if (total == 0) return fail(ctx, KP_ERR_ARG, "no packets");
+  if (o->tally_mode != 0) return fail(ctx, KP_ERR_ARG, "tally_mode must be 0");
+  if (o->max_events < 1 || o->max_events > (1 << 30)) return fail(ctx, KP_ERR_ARG, "max_events out of range");
+  if (!(o->rr_wmin >= 0.0) || !std::isfinite(o->rr_wmin) ||
+      (o->rr_wmin > 0.0 && !(o->rr_psurv > 0.0 && o->rr_psurv <= 1.0)))
+    return fail(ctx, KP_ERR_ARG, "roulette parameters out of range");
+  if (o->trace_packets > 0 && o->trace_stride < 1) return fail(ctx, KP_ERR_ARG, "trace_stride must be >= 1");
+  const int bs = o->block_size ? o->block_size : 256;
+  if (bs < 64 || bs > 256 || bs % 64) return fail(ctx, KP_ERR_ARG, "block_size must be 64, 128, 192 or 256");
+  if (o->blocks_per_cu < 0 || o->blocks_per_cu > 64) return fail(ctx, KP_ERR_ARG, "blocks_per_cu out of range");
+  if (o->transport_fp64 != 0 && o->transport_fp64 != 1) return fail(ctx, KP_ERR_ARG, "transport_fp64 must be 0 or 1");
+
+  KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t tally_need = (size_t)nl * ctx->ncell * 9;
+  const size_t trace_need = (size_t)nl * o->trace_packets;
+  size_t free_b = 0, total_b = 0;
+  KP_HIP(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+  size_t extra = (tally_need > ctx->tally_n ? tally_need * 8 : 0) +
+                 (trace_need > ctx->traces_n ? trace_need * sizeof(TraceDev) : 0);
+  if (extra > free_b) return fail(ctx, KP_ERR_OOM, "tally needs %zu bytes, %zu free", extra, free_b);
+  if ((st = ensure(ctx, &ctx->d_tally, &ctx->tally_n, tally_need, "tally allocation"))) return st;
+  if ((st = ensure(ctx, &ctx->d_traces, &ctx->traces_n, trace_need, "trace allocation"))) return st;
+
+  fill_dust(ctx, counts, ctx->hdust);
+  if ((st = upload_small(ctx, s))) return st;
+  KP_HIP(launch_fill_zero(ctx->d_tally, tally_need * sizeof(double), s), "tally clear");
+  KP_HIP(launch_fill_zero(ctx->d_stats, sizeof(StatsDev), s), "stats clear");
+  KP_HIP(launch_fill_zero(ctx->d_counter, sizeof(unsigned long long), s), "counter clear");
+  if (trace_need) KP_HIP(launch_fill_zero(ctx->d_traces, trace_need * sizeof(TraceDev), s), "trace clear");
+
+  TransportArgs a{};
+  a.rho = ctx->d_rho;
+  if (ctx->d_bhat) {
+    a.bx = ctx->d_bhat;
+    a.by = ctx->d_bhat + ctx->ncell;
+    a.bz = ctx->d_bhat + 2 * ctx->ncell;
+  }
+  a.nx = ctx->grid.nx; a.ny = ctx->grid.ny; a.nz = ctx->grid.nz;
+  a.x0 = ctx->grid.x0; a.y0 = ctx->grid.y0; a.z0 = ctx->grid.z0; a.dx = ctx->grid.dx;
+  a.dust = ctx->d_dust;
+  a.n_lambda = nl;
+  a.total = total;
+  a.src_kind = ctx->src.kind;
+  a.sx = ctx->src.pos[0]; a.sy = ctx->src.pos[1]; a.sz = ctx->src.pos[2];
+  a.dx_ = ctx->src.dir[0]; a.dy_ = ctx->src.dir[1]; a.dz_ = ctx->src.dir[2];
+  a.seed = o->seed;
+  a.rr_wmin = o->rr_wmin;
+  a.rr_psurv = o->rr_psurv;
+  a.max_events = (int)o->max_events;
+  a.tally = ctx->d_tally;
+  a.ncell = ctx->ncell;
+  a.counter = ctx->d_counter;
+  a.stats = ctx->d_stats;
+  a.traces = ctx->d_traces;
+  a.trace_count = o->trace_packets;
+  a.trace_stride = o->trace_stride ? o->trace_stride : 1;
+
+  bool sphere = true;
+  for (int l = 0; l < nl; ++l) sphere = sphere && ctx->hdust[l].sphere;
+  const bool aligned = ctx->d_bhat != nullptr;
+  const bool fp64 = o->transport_fp64 == 1;
+  int bpc = o->blocks_per_cu;
+  if (bpc == 0) {
+    bpc = transport_max_blocks_per_cu(fp64, aligned, sphere, bs);
+    if (bpc < 1) bpc = 1;
+    if (bpc > 8) bpc = 8;
+  }
+  uint64_t blocks = (uint64_t)ctx->cu_count * bpc;
+  const uint64_t need_blocks = (total + bs - 1) / bs;
+  if (blocks > need_blocks) blocks = need_blocks;
+  KP_HIP(hipEventRecord(ctx->ev[0], s), "event record");
+  KP_HIP(launch_transport(a, fp64, aligned, sphere, (int)blocks, bs, s), "transport kernel launch");
+  KP_HIP(hipEventRecord(ctx->ev[1], s), "event record");
+  KP_HIP(hipStreamSynchronize(s), "transport kernel");
+
+  StatsDev h{};
+  KP_HIP(hipMemcpy(&h, ctx->d_stats, sizeof h, hipMemcpyDeviceToHost), "stats readback");
+  kp_stats& r = ctx->stats;
+  std::memset(&r, 0, sizeof r);
+  r.cell_steps = (int64_t)h.cell_steps; r.scatterings = (int64_t)h.scatterings;
+  r.trials = (int64_t)h.trials; r.rr_kills = (int64_t)h.rr_kills;
+  r.rr_survivals = (int64_t)h.rr_survivals; r.escaped = (int64_t)h.escaped;
+  r.budget = (int64_t)h.budget; r.numeric = (int64_t)h.numeric; r.packets = (int64_t)h.packets;
+  r.e_emitted = h.e_emitted; r.e_escaped = h.e_escaped; r.e_absorbed = h.e_absorbed;
+  r.e_rr_killed = h.e_rr_killed; r.e_rr_gained = h.e_rr_gained; r.e_budget = h.e_budget;
+  r.e_scat_delta = h.e_scat_delta;
+  float ms = 0.0f;
+  KP_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]), "event timing");
+  r.ms_transport = ms;
+  ctx->tally_lambda = nl;
+  ctx->have_tally = true;
+  ctx->have_images = false;
+  ctx->traces_valid = trace_need;
+  if (r.packets != (int64_t)total)
+    return fail(ctx, KP_ERR_DEVICE, "transport finished %lld of %llu packets", (long long)r.packets,
+                (unsigned long long)total);
+  if (r.numeric) return fail(ctx, KP_ERR_NUMERIC, "%lld packets reached a non-finite state", (long long)r.numeric);
+  if (o->strict && r.budget) return fail(ctx, KP_ERR_BUDGET, "%lld packets hit the event cap", (long long)r.budget);
+  return KP_OK;
+}
+
+kp_status kp_image(kp_ctx* ctx, void* stream) {
+  if (!ctx) return KP_ERR_ARG;
+  if (!ctx->have_tally) return fail(ctx, KP_ERR_STATE, "no step-1 tally: call kp_transport first");
+  kp_status st = check_ready(ctx);
+  if (st) return st;
+  KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const int nl = ctx->tally_lambda;
+  const size_t need = (size_t)nl * ctx->views.size() * 4 * ctx->views[0].npx * ctx->views[0].npy;
+  if ((st = ensure(ctx, &ctx->d_images, &ctx->images_n, need, "image allocation"))) return st;
+  if ((st = upload_small(ctx, s))) return st;
+  if ((st = image_launch(ctx, false, nullptr, ctx->d_images, nl, s))) return st;
+  KP_HIP(hipStreamSynchronize(s), "imaging kernel");
+  float ms = 0.0f;
+  KP_HIP(hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]), "event timing");
+  ctx->stats.ms_image = ms;
+  ctx->have_images = true;
+  ctx->images_valid_n = need;
+  return KP_OK;
+}
+
+kp_status kp_run(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, void* stream) {
+  kp_status st = kp_transport(ctx, counts, o, stream);
+  if (st != KP_OK && st != KP_ERR_NUMERIC && st != KP_ERR_BUDGET) return st;
+  kp_status st2 = kp_image(ctx, stream);
+  return st2 != KP_OK ? st2 : st;
+}
+
+kp_status kp_image_source(kp_ctx* ctx, const double* d_S, double* d_out, void* stream) {
+  if (!ctx) return KP_ERR_ARG;
+  kp_status st = check_ready(ctx);
+  if (st) return st;
+  if (!d_S || !d_out) return fail(ctx, KP_ERR_ARG, "source or output is NULL");
+  KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<uint64_t> ones(ctx->dust.size(), 1);
+  fill_dust(ctx, ones.data(), ctx->hdust);
+  if ((st = upload_small(ctx, s))) return st;
+  if ((st = image_launch(ctx, true, d_S, d_out, 1, s))) return st;
+  KP_HIP(hipStreamSynchronize(s), "imaging kernel");
+  float ms = 0.0f;
+  KP_HIP(hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]), "event timing");
+  ctx->stats.ms_image = ms;
+  return KP_OK;
+}
+
+kp_status kp_get_images(kp_ctx* ctx, double* out, size_t n) {
+  if (!ctx) return KP_ERR_ARG;
+  if (!ctx->have_images) return fail(ctx, KP_ERR_STATE, "no images: call kp_run or kp_image first");
+  if (!out || n != ctx->images_valid_n) return fail(ctx, KP_ERR_ARG, "destination must hold %zu doubles", ctx->images_valid_n);
+  KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  KP_HIP(hipMemcpy(out, ctx->d_images, n * sizeof(double), hipMemcpyDeviceToHost), "image copy");
+  return KP_OK;
+}
+
+kp_status kp_get_images_device(kp_ctx* ctx, double* d_out, size_t n, void* stream) {
+  if (!ctx) return KP_ERR_ARG;
+  if (!ctx->have_images) return fail(ctx, KP_ERR_STATE, "no images: call kp_run or kp_image first");
+  if (!d_out || n != ctx->images_valid_n) return fail(ctx, KP_ERR_ARG, "destination must hold %zu doubles", ctx->images_valid_n);
+  KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  KP_HIP(hipMemcpyAsync(d_out, ctx->d_images, n * sizeof(double), hipMemcpyDeviceToDevice,
+                        (hipStream_t)stream), "image copy");
+  return KP_OK;
+}
+
+kp_status kp_get_tally(kp_ctx* ctx, double* out, size_t n) {
+  if (!ctx) return KP_ERR_ARG;
+  if (!ctx->have_tally) return fail(ctx, KP_ERR_STATE, "no tally: call kp_transport first");
+  const size_t need = (size_t)ctx->tally_lambda * ctx->ncell * 9;
+  if (!out || n != need) return fail(ctx, KP_ERR_ARG, "destination must hold %zu doubles", need);
+  KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  KP_HIP(hipMemcpy(out, ctx->d_tally, n * sizeof(double), hipMemcpyDeviceToHost), "tally copy");
+  return KP_OK;
+}
+
+kp_status kp_get_stats(kp_ctx* ctx, kp_stats* out) {
+  if (!ctx) return KP_ERR_ARG;
+  if (!out) return fail(ctx, KP_ERR_ARG, "output is NULL");
+  *out = ctx->stats;
+  return KP_OK;
+}
+
+kp_status kp_get_trace(kp_ctx* ctx, kp_packet_trace* out, size_t n) {
+  if (!ctx) return KP_ERR_ARG;
+  if (!out || n != ctx->traces_valid) return fail(ctx, KP_ERR_ARG, "destination must hold %zu traces", ctx->traces_valid);
+  if (n == 0) return KP_OK;
+  static_assert(sizeof(kp_packet_trace) == sizeof(TraceDev), "trace layout");
+  KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  KP_HIP(hipMemcpy(out, ctx->d_traces, n * sizeof(TraceDev), hipMemcpyDeviceToHost), "trace copy");
+  return KP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// kp_internal.hpp -- records shared by the host API and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace kp {
+
+// Per-wavelength constants, prepared on the host from kp_dust.
+struct DustDev {
+  double ks_cell;    // kappa_sca * dx   (per unit density, per cell length)
+  double ka_cell;    // kappa_abs * dx
+  double ke_cell;    // (kappa_sca + kappa_abs) * dx
+  double kext;       // kappa_sca + kappa_abs (per unit length)
+  double ap_re, ap_im, aa_re, aa_im;
+  double inv2cavg;   // 1 / (2 C_avg), C_avg = (2 Im a_perp + Im a_par)/3
+  double alpha3_scale;
+  double pfac;       // 3 / (8 pi N_P),  N_P = (2|a_perp|^2 + |a_par|^2)/3
+  double bound_fac;  // pfac * max(|a_perp|^2, |a_par|^2)
+  double ap2_np, aa2_np;  // |a_perp|^2 / N_P, |a_par|^2 / N_P
+  double w0;         // lum / N_lambda
+  uint64_t first;    // first global work index of this wavelength
+  uint64_t count;    // packets of this wavelength
+  int32_t sphere;
+  int32_t pad;
+};
+
+struct ViewDev {
+  double ox, oy, oz;     // camera direction
+  double tx, ty, tz;     // theta_hat
+  double px, py, pz;     // phi_hat
+  double half_width;
+};
+
+struct StatsDev {
+  unsigned long long cell_steps, scatterings, trials, rr_kills, rr_survivals, escaped,
+      budget, numeric, packets;
+  double e_emitted, e_escaped, e_absorbed, e_rr_killed, e_rr_gained, e_budget, e_scat_delta;
+};
+
+struct TraceDev {
+  uint64_t packet;
+  int32_t end_kind;
+  int32_t events;
+  int64_t steps;
+  int64_t last_cell;
+  double n[3];
+  double stokes[4];
+  uint64_t hash;
+};
+
+struct TransportArgs {
+  const float* rho;
+  const float* bx;
+  const float* by;
+  const float* bz;
+  int nx, ny, nz;
+  double x0, y0, z0, dx;
+  const DustDev* dust;
+  int n_lambda;
+  uint64_t total;
+  int src_kind;
+  double sx, sy, sz;
+  double dx_, dy_, dz_;  // pencil direction (unit)
+  uint64_t seed;
+  double rr_wmin, rr_psurv;
+  int max_events;
+  double* tally;  // [lambda][ncell][9]
+  uint64_t ncell;
+  unsigned long long* counter;
+  StatsDev* stats;
+  TraceDev* traces;
+  uint32_t trace_count, trace_stride;
+};
+
+struct ImageArgs {
+  const float* rho;
+  const float* bx;
+  const float* by;
+  const float* bz;
+  int nx, ny, nz;
+  double x0, y0, z0, dx;
+  const DustDev* dust;
+  const ViewDev* views;
+  int n_views, n_lambda, npx, npy;
+  const double* tally;  // [lambda][ncell][9]   (coherency source)
+  const double* user_S; // [ncell][view][4]     (per-view source, wavelength 0)
+  double* images;       // [lambda][view][4][npy][npx]
+  uint64_t ncell;
+};
+
+// launchers (kp_kernels.hip)
+hipError_t launch_transport(const TransportArgs& a, bool fp64, bool aligned, bool sphere,
+                            int blocks, int block_size, hipStream_t s);
+hipError_t launch_image(const ImageArgs& a, bool aligned, bool sphere, bool user_source,
+                        hipStream_t s);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_validate(const float* rho, const float* bx, const float* by, const float* bz,
+                           uint64_t n, unsigned long long* bad, hipStream_t s);
+int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, int block_size);
+
+}  // namespace kp

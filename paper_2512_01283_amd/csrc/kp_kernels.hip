@@ -1,0 +1,815 @@
+// kp_kernels.hip -- gfx950 kernels of the polarized Monte Carlo transport
+// (step 1) and the deterministic imaging ray-march (step 2) of Yang & Wang,
+// arXiv:2512.01283, Sec. 2.2-2.3 and Appendix A.
+//
+// Step 1 is a persistent packet-per-lane loop: every lane of a 64-wide
+// wavefront carries one photon packet and advances it by one cell segment per
+// iteration (plus the scattering event that may end the segment); lanes whose
+// packet ended are refilled from a global work counter once per iteration
+// (one atomic per wavefront, ids handed out by lane rank), so long and short
+// paths do not idle a wavefront.  Packets are independent: each draws from its
+// own Philox stream (key (seed, wavelength), counter (packet, block, 0, 0)),
+// so the schedule never changes a packet's path.
+//
+// The scattering-source tally of step 1 is kept as the incident coherency of
+// each cell (3x3 Hermitian, 9 reals): because every scatterer here is a
+// dipole, the source toward any camera is a fixed linear map of it (formed in
+// step 2), so one tally serves all views and wavelengths' views at 9 FP64
+// atomics per segment instead of 4 per view.  A lane keeps the running sum
+// for its current cell in registers and flushes it with FP64 atomics only
+// when it moves to another cell (multiple scattering inside a thick cell, and
+// consecutive packets of a lane leaving the source cell, cost no atomics).
+#include "kp_device.hpp"
+#include "kp_internal.hpp"
+
+namespace kp {
+
+enum : uint32_t {
+  EV_SCATTER = 1, END_ESCAPE = 2, EV_RR_SURVIVE = 3, END_RR_KILL = 4, END_BUDGET = 5,
+  END_NUMERIC = 6
+};
+
+__device__ __forceinline__ uint64_t fnv_u32(uint64_t h, uint32_t v) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    h ^= (v >> (8 * k)) & 0xffu;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+__device__ __forceinline__ uint64_t hash_event(uint64_t h, uint32_t kind, uint64_t cell) {
+  return fnv_u32(fnv_u32(h, kind), (uint32_t)cell);
+}
+
+template <typename R> struct Cx { R re, im; };
+template <typename R> __device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename R> __device__ __forceinline__ Cx<R> cmulc(Cx<R> a, Cx<R> b) {  // a * conj(b)
+  return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+template <typename R> __device__ __forceinline__ Cx<R> cadd(Cx<R> a, Cx<R> b) {
+  return {a.re + b.re, a.im + b.im};
+}
+template <typename R> __device__ __forceinline__ R cabs2(Cx<R> a) { return a.re * a.re + a.im * a.im; }
+template <typename R> __device__ __forceinline__ Cx<R> cscale(Cx<R> a, R s) { return {a.re * s, a.im * s}; }
+
+template <typename R>
+struct Packet {
+  R fx, fy, fz;       // position inside the cell, cell units [0,1]
+  R nx, ny, nz;       // direction
+  R I, Q, U, V;       // Stokes vector in the lab basis of n
+  R tau;              // remaining scattering optical depth
+  R w0;               // initial weight
+  R u0, u1, u2, u3;   // uniforms of the Philox block `blk`
+  double e_abs, e_scat, e_gain;
+  uint64_t pid, hash;
+  int64_t last;
+  int ci, cj, ck;
+  uint32_t draw, blk;
+  int events, steps, trials, lam, rr;
+};
+
+template <typename R>
+__device__ __forceinline__ R next_uniform(Packet<R>& p, uint64_t seed) {
+  uint32_t d = p.draw++;
+  uint32_t b = d >> 2;
+  if (b != p.blk) {
+    uint64_t w[4];
+    philox4x64_10(p.pid, (uint64_t)b, 0ull, 0ull, seed, (uint64_t)p.lam, w);
+    p.u0 = word_uniform<R>(w[0]);
+    p.u1 = word_uniform<R>(w[1]);
+    p.u2 = word_uniform<R>(w[2]);
+    p.u3 = word_uniform<R>(w[3]);
+    p.blk = b;
+  }
+  uint32_t k = d & 3u;
+  return k == 0 ? p.u0 : (k == 1 ? p.u1 : (k == 2 ? p.u2 : p.u3));
+}
+
+// Emission (Sec. 2.2): isotropic direction (or the pencil direction), an
+// unpolarised Stokes vector of weight lum/N, an exponential scattering depth,
+// and the cell holding the source (a coordinate on a face belongs to the cell
+// the direction points into).  Returns false if the start lies outside.
+template <typename R>
+__device__ bool init_packet(Packet<R>& p, uint64_t g, const TransportArgs& a) {
+  int lo = 0, hi = a.n_lambda - 1;
+  while (lo < hi) {  // last wavelength whose first index <= g
+    int mid = (lo + hi + 1) >> 1;
+    if (a.dust[mid].first <= g) lo = mid; else hi = mid - 1;
+  }
+  p.lam = lo;
+  p.pid = g - a.dust[lo].first;
+  p.draw = 0;
+  p.blk = 0xffffffffu;
+  R u0 = next_uniform(p, a.seed), u1 = next_uniform(p, a.seed);
+  if (a.src_kind == 1) {
+    p.nx = (R)a.dx_; p.ny = (R)a.dy_; p.nz = (R)a.dz_;
+  } else {
+    R mu = (R)2 * u0 - (R)1;
+    R s = k_sqrt(fmax((R)0, (R)1 - mu * mu));
+    R sp, cp;
+    k_sincospi((R)2 * u1, &sp, &cp);
+    p.nx = s * cp; p.ny = s * sp; p.nz = mu;
+  }
+  p.tau = -k_log(next_uniform(p, a.seed));
+  p.w0 = (R)a.dust[lo].w0;
+  p.I = p.w0; p.Q = (R)0; p.U = (R)0; p.V = (R)0;
+  p.e_abs = 0.0; p.e_scat = 0.0; p.e_gain = 0.0;
+  p.events = 0; p.steps = 0; p.trials = 0; p.rr = 0;
+  p.hash = 14695981039346656037ull;
+  p.last = -1;
+  const double pos[3] = {a.sx, a.sy, a.sz}, org[3] = {a.x0, a.y0, a.z0};
+  const R dir[3] = {p.nx, p.ny, p.nz};
+  int ci[3];
+  R fr[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double t = (pos[k] - org[k]) / a.dx;
+    double fl = floor(t);
+    double f = t - fl;
+    int i = (int)fl;
+    if (f == 0.0 && dir[k] < (R)0) { i -= 1; f = 1.0; }
+    ci[k] = i;
+    fr[k] = (R)f;
+  }
+  p.ci = ci[0]; p.cj = ci[1]; p.ck = ci[2];
+  p.fx = fr[0]; p.fy = fr[1]; p.fz = fr[2];
+  return p.ci >= 0 && p.ci < a.nx && p.cj >= 0 && p.cj < a.ny && p.ck >= 0 && p.ck < a.nz;
+}
+
+// Coherency contribution of a segment-integrated Stokes vector J (lab basis of
+// n): sum_ab rho_ab e_a e_b^T with rho = 1/2 [[I+Q, U-iV],[U+iV, I-Q]],
+// e1 = theta_hat(n), e2 = phi_hat(n), times the weight w.  Output order: real
+// xx yy zz xy xz yz, imaginary yz zx xy (the antisymmetric part equals
+// -V/2 [n]_x in this basis).
+template <typename R>
+__device__ __forceinline__ void coherency(const V3<R>& n, R JI, R JQ, R JU, R JV, R w,
+                                          R out[9]) {
+  V3<R> e1, e2;
+  basis(n, e1, e2);
+  R a = (R)0.5 * (JI + JQ) * w, b = (R)0.5 * (JI - JQ) * w, u = (R)0.5 * JU * w;
+  R v = (R)-0.5 * JV * w;
+  out[0] = a * e1.x * e1.x + b * e2.x * e2.x + (R)2 * u * e1.x * e2.x;
+  out[1] = a * e1.y * e1.y + b * e2.y * e2.y + (R)2 * u * e1.y * e2.y;
+  out[2] = a * e1.z * e1.z;
+  out[3] = a * e1.x * e1.y + b * e2.x * e2.y + u * (e1.x * e2.y + e2.x * e1.y);
+  out[4] = a * e1.x * e1.z + u * (e2.x * e1.z);
+  out[5] = a * e1.y * e1.z + u * (e2.y * e1.z);
+  out[6] = v * n.x;
+  out[7] = v * n.y;
+  out[8] = v * n.z;
+}
+
+__device__ __forceinline__ void flush_acc(double* tally, int64_t key, const double acc[9]) {
+  if (key < 0) return;
+  double* dst = tally + (uint64_t)key * 9u;
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+    if (acc[k] != 0.0) unsafeAtomicAdd(dst + k, acc[k]);
+}
+
+// Dimensionless extinction coefficients for a direction with cos(theta') =
+// ct to the grain axis (dipole: cross sections from Im of the
+// polarizability, normalised by the orientation average).
+template <typename R, bool SPHERE>
+__device__ __forceinline__ void alphas(const DustDev& D, R ct, R& a1, R& a2, R& a3) {
+  if (SPHERE) { a1 = (R)1; a2 = (R)0; a3 = (R)0; return; }
+  R cth = (R)D.ap_im * ct * ct + (R)D.aa_im * ((R)1 - ct * ct);
+  R cph = (R)D.ap_im;
+  a1 = (cth + cph) * (R)D.inv2cavg;
+  a2 = (cth - cph) * (R)D.inv2cavg;
+  a3 = (R)D.alpha3_scale * a2;
+}
+
+// Scattering event (Sec. 2.2; rejection sampling of Sec. 3): incident state
+// carried into the grain frame, proposals uniform on the sphere there
+// (cos, azimuth, acceptance: three uniforms per trial), accepted when
+// u * bound <= [P s]_I, output rescaled to the scattered power, then carried
+// back to the lab frame.  Returns false on a numerical failure.
+template <typename R, bool ALIGNED, bool SPHERE>
+__device__ bool scatter(Packet<R>& p, const Quat<R>& q, const DustDev& D, uint64_t seed) {
+  const V3<R> n{p.nx, p.ny, p.nz};
+  V3<R> ng = n;
+  R c2 = (R)1, s2 = (R)0;
+  if (ALIGNED) {
+    ng = to_grain(q, n);
+    eta2(q, n, ng, c2, s2);
+  }
+  const R I = p.I, Qg = c2 * p.Q + s2 * p.U, Ug = -s2 * p.Q + c2 * p.U, V = p.V;
+  V3<R> e1, e2;
+  R cpn, spn, stn;
+  azimuth(ng, cpn, spn, stn);
+  e1 = {ng.z * cpn, ng.z * spn, -stn};
+  e2 = {-spn, cpn, (R)0};
+  const R r11 = (R)0.5 * (I + Qg), r22 = (R)0.5 * (I - Qg);
+  const Cx<R> r12{(R)0.5 * Ug, (R)-0.5 * V};
+  const R pf = (R)D.pfac;
+  const R bound = (R)D.bound_fac * I;
+  const R tol = sizeof(R) == 4 ? (R)1e-4 : (R)1e-12;
+  const Cx<R> ap{(R)D.ap_re, (R)D.ap_im};
+  const Cx<R> dd{(R)(D.aa_re - D.ap_re), (R)(D.aa_im - D.ap_im)};
+  Cx<R> J11, J12, J21, J22;
+  R mu = 0, smu = 0, cph = 1, sph = 0, Iout = 0;
+  bool ok = false;
+  for (int trial = 0; trial < 100000; ++trial) {
+    mu = (R)2 * next_uniform(p, seed) - (R)1;
+    R uph = next_uniform(p, seed);
+    R ua = next_uniform(p, seed);
+    p.trials++;
+    smu = k_sqrt(fmax((R)0, (R)1 - mu * mu));
+    k_sincospi((R)2 * uph, &sph, &cph);
+    if (smu * smu <= (R)KP_POLE2) { cph = (R)1; sph = (R)0; }
+    const V3<R> f1{mu * cph, mu * sph, -smu}, f2{-sph, cph, (R)0};
+    const R D11 = dot(f1, e1), D12 = dot(f1, e2), D21 = dot(f2, e1), D22 = dot(f2, e2);
+    if (SPHERE) {
+      J11 = {D11, 0}; J12 = {D12, 0}; J21 = {D21, 0}; J22 = {D22, 0};
+      Iout = pf * ((D11 * D11 + D21 * D21) * r11 + (D12 * D12 + D22 * D22) * r22 +
+                   (R)2 * (D11 * D12 + D21 * D22) * r12.re);
+    } else {
+      J11 = cadd(cscale(ap, D11), cscale(dd, smu * stn));
+      J12 = cscale(ap, D12);
+      J21 = cscale(ap, D21);
+      J22 = cscale(ap, D22);
+      Iout = pf * (cabs2(J11) * r11 + cabs2(J12) * r22 + (R)2 * cmulc(cmul(J11, r12), J12).re +
+                   cabs2(J21) * r11 + cabs2(J22) * r22 + (R)2 * cmulc(cmul(J21, r12), J22).re);
+    }
+    if (!(Iout <= bound * ((R)1 + tol))) return false;
+    if (ua * bound <= Iout) { ok = true; break; }
+  }
+  if (!ok) return false;
+  // full scattered state rho' = J rho J^dagger in the natural basis of mg
+  const Cx<R> r21{r12.re, -r12.im};
+  const Cx<R> T11 = cadd(cscale(J11, r11), cmul(J12, r21));
+  const Cx<R> T12 = cadd(cmul(J11, r12), cscale(J12, r22));
+  const Cx<R> T21 = cadd(cscale(J21, r11), cmul(J22, r21));
+  const Cx<R> T22 = cadd(cmul(J21, r12), cscale(J22, r22));
+  const R p11 = cmulc(T11, J11).re + cmulc(T12, J12).re;
+  const R p22 = cmulc(T21, J21).re + cmulc(T22, J22).re;
+  const Cx<R> p12 = cadd(cmulc(T11, J21), cmulc(T12, J22));
+  R So = pf * (p11 + p22), Qo = pf * (p11 - p22), Uo = pf * (R)2 * p12.re,
+    Vo = pf * (R)-2 * p12.im;
+  // scattered power: sum_k |a_k|^2 C_kk / N_P with C_zz = r11 sin^2(theta'_n)
+  R sig = I;
+  if (!SPHERE) {
+    R czz = r11 * stn * stn;
+    sig = (R)D.ap2_np * (I - czz) + (R)D.aa2_np * czz;
+  }
+  R scale = sig / So;
+  So = sig; Qo *= scale; Uo *= scale; Vo *= scale;
+  V3<R> mg{smu * cph, smu * sph, mu};
+  V3<R> m = mg;
+  R cm = (R)1, sm = (R)0;
+  if (ALIGNED) {
+    m = from_grain(q, mg);
+    eta2(q, m, mg, cm, sm);
+  }
+  p.nx = m.x; p.ny = m.y; p.nz = m.z;
+  p.e_scat += (double)(sig - I);
+  p.I = So;
+  p.Q = cm * Qo - sm * Uo;
+  p.U = sm * Qo + cm * Uo;
+  p.V = Vo;
+  return true;
+}
+
+// One loop iteration: one cell segment (Sec. 2.2: cell-to-cell traversal,
+// exponential scattering depth, continuous extinction across the segment by
+// the analytic cell solution of Appendix A, tally of the segment into the
+// scattering source of Sec. 2.3), then a scattering event or the crossing
+// into the next cell, then Russian roulette.  Returns 0 or an end kind.
+template <typename R, bool ALIGNED, bool SPHERE>
+__device__ uint32_t step(Packet<R>& p, const TransportArgs& a, int64_t& acc_key, double acc[9]) {
+  const uint64_t c = (uint64_t)p.ci + (uint64_t)a.nx * ((uint64_t)p.cj + (uint64_t)a.ny * p.ck);
+  p.last = (int64_t)c;
+  if (p.events >= a.max_events) {
+    p.hash = hash_event(p.hash, END_BUDGET, c);
+    return END_BUDGET;
+  }
+  const R inf = k_inf<R>();
+  R tx = p.nx > (R)0 ? ((R)1 - p.fx) / p.nx : (p.nx < (R)0 ? -p.fx / p.nx : inf);
+  R ty = p.ny > (R)0 ? ((R)1 - p.fy) / p.ny : (p.ny < (R)0 ? -p.fy / p.ny : inf);
+  R tz = p.nz > (R)0 ? ((R)1 - p.fz) / p.nz : (p.nz < (R)0 ? -p.fz / p.nz : inf);
+  R t = tx;
+  int axis = 0;
+  if (ty < t) { t = ty; axis = 1; }
+  if (tz < t) { t = tz; axis = 2; }
+  if (!(t < inf)) return END_NUMERIC;
+  const DustDev& D = a.dust[p.lam];
+  const R rho = (R)a.rho[c];
+  const R kb = rho * (R)D.ks_cell;
+  R tl;
+  bool scat;
+  if (kb > (R)0 && p.tau < kb * t) { tl = p.tau / kb; scat = true; }
+  else { tl = t; p.tau -= kb * t; scat = false; }
+  p.steps++;
+  Quat<R> q{(R)1, (R)0, (R)0, (R)0};
+  if (ALIGNED && rho > (R)0) q = grain_quat(V3<R>{(R)a.bx[c], (R)a.by[c], (R)a.bz[c]});
+  if (rho > (R)0 && tl > (R)0) {
+    const V3<R> n{p.nx, p.ny, p.nz};
+    const R Ib = p.I;
+    R JI, JQ, JU, JV;
+    if (SPHERE && !ALIGNED) {
+      // spheres: extinction is the scalar absorption e^{-rho kappa_abs l}
+      const R m1 = rho * (R)D.ka_cell;
+      const R E = k_exp(-m1 * tl), G = tl * phi1(m1 * tl);
+      JI = p.I * G; JQ = p.Q * G; JU = p.U * G; JV = p.V * G;
+      p.I *= E; p.Q *= E; p.U *= E; p.V *= E;
+    } else {
+      V3<R> ng = n;
+      R c2 = (R)1, s2 = (R)0;
+      if (ALIGNED) {
+        ng = to_grain(q, n);
+        eta2(q, n, ng, c2, s2);
+      }
+      R a1, a2, a3;
+      alphas<R, SPHERE>(D, ng.z, a1, a2, a3);
+      const R ke = rho * (R)D.ke_cell;
+      const R mA = ke * (a1 + a2) - kb, mB = ke * (a1 - a2) - kb, mU = ke * a1 - kb;
+      const R w = ke * a3;
+      const R Qg = c2 * p.Q + s2 * p.U, Ug = -s2 * p.Q + c2 * p.U;
+      const R A = p.I + Qg, B = p.I - Qg;
+      const R gA = tl * phi1(mA * tl), gB = tl * phi1(mB * tl);
+      const R eA = k_exp(-mA * tl), eB = k_exp(-mB * tl);
+      R JUg, JVg, Un, Vn;
+      if (w == (R)0) {
+        const R gU = tl * phi1(mU * tl), eU = k_exp(-mU * tl);
+        JUg = Ug * gU; JVg = p.V * gU;
+        Un = Ug * eU; Vn = p.V * eU;
+      } else {
+        // U + iV evolves as exp((-mU + i w) s)
+        const R x = -mU * tl, y = w * tl;
+        const R ex = k_exp(x), cy = k_cos(y), sy = k_sin(y), sh = k_sin((R)0.5 * y);
+        const Cx<R> ez{ex * cy, ex * sy};
+        const Cx<R> em1{k_expm1(x) * cy - (R)2 * sh * sh, ex * sy};
+        const R den = x * x + y * y;
+        const Cx<R> phic{(em1.re * x + em1.im * y) / den, (em1.im * x - em1.re * y) / den};
+        const Cx<R> Z{Ug, p.V};
+        const Cx<R> JZ = cscale(cmul(Z, phic), tl), Zn = cmul(Z, ez);
+        JUg = JZ.re; JVg = JZ.im; Un = Zn.re; Vn = Zn.im;
+      }
+      const R JA = A * gA, JB = B * gB, An = A * eA, Bn = B * eB;
+      const R JQg = (R)0.5 * (JA - JB), Qn = (R)0.5 * (An - Bn);
+      JI = (R)0.5 * (JA + JB);
+      JQ = c2 * JQg - s2 * JUg;
+      JU = s2 * JQg + c2 * JUg;
+      JV = JVg;
+      p.I = (R)0.5 * (An + Bn);
+      p.Q = c2 * Qn - s2 * Un;
+      p.U = s2 * Qn + c2 * Un;
+      p.V = Vn;
+    }
+    p.e_abs += (double)(Ib - p.I);
+    if (kb > (R)0) {
+      R cc[9];
+      coherency(n, JI, JQ, JU, JV, kb, cc);
+      const int64_t key = (int64_t)((uint64_t)p.lam * a.ncell + c);
+      if (key != acc_key) {
+        flush_acc(a.tally, acc_key, acc);
+        acc_key = key;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[k] = (double)cc[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) acc[k] += (double)cc[k];
+      }
+    }
+  }
+  if (!(p.I > (R)0)) {
+    // the weight underflowed in a very thick absorbing segment: the packet is
+    // absorbed (a non-finite weight is reported as a numerical failure)
+    if (!isfinite(p.I)) return END_NUMERIC;
+    p.hash = hash_event(p.hash, END_RR_KILL, c);
+    return END_RR_KILL;
+  }
+  if (scat) {
+    p.fx = fmin((R)1, fmax((R)0, p.fx + tl * p.nx));
+    p.fy = fmin((R)1, fmax((R)0, p.fy + tl * p.ny));
+    p.fz = fmin((R)1, fmax((R)0, p.fz + tl * p.nz));
+    if (!scatter<R, ALIGNED, SPHERE>(p, q, D, a.seed)) return END_NUMERIC;
+    p.events++;
+    p.hash = hash_event(p.hash, EV_SCATTER, c);
+    p.tau = -k_log(next_uniform(p, a.seed));
+  } else {
+    if (axis != 0) p.fx = fmin((R)1, fmax((R)0, p.fx + t * p.nx));
+    if (axis != 1) p.fy = fmin((R)1, fmax((R)0, p.fy + t * p.ny));
+    if (axis != 2) p.fz = fmin((R)1, fmax((R)0, p.fz + t * p.nz));
+    bool out;
+    if (axis == 0) {
+      if (p.nx > (R)0) { p.ci++; p.fx = (R)0; } else { p.ci--; p.fx = (R)1; }
+      out = p.ci < 0 || p.ci >= a.nx;
+    } else if (axis == 1) {
+      if (p.ny > (R)0) { p.cj++; p.fy = (R)0; } else { p.cj--; p.fy = (R)1; }
+      out = p.cj < 0 || p.cj >= a.ny;
+    } else {
+      if (p.nz > (R)0) { p.ck++; p.fz = (R)0; } else { p.ck--; p.fz = (R)1; }
+      out = p.ck < 0 || p.ck >= a.nz;
+    }
+    if (out) {
+      p.hash = hash_event(p.hash, END_ESCAPE, c);
+      return END_ESCAPE;
+    }
+  }
+  if (!isfinite(p.I)) return END_NUMERIC;
+  if (a.rr_wmin > 0.0 && p.I < (R)a.rr_wmin * p.w0) {
+    const uint64_t cn =
+        (uint64_t)p.ci + (uint64_t)a.nx * ((uint64_t)p.cj + (uint64_t)a.ny * p.ck);
+    R u = next_uniform(p, a.seed);
+    if (u < (R)a.rr_psurv) {
+      const R before = p.I, inv = (R)1 / (R)a.rr_psurv;
+      p.I *= inv; p.Q *= inv; p.U *= inv; p.V *= inv;
+      p.e_gain += (double)(p.I - before);
+      p.rr++;
+      p.hash = hash_event(p.hash, EV_RR_SURVIVE, cn);
+    } else {
+      p.hash = hash_event(p.hash, END_RR_KILL, cn);
+      return END_RR_KILL;
+    }
+  }
+  return 0;
+}
+
+// stats slots in LDS
+enum { SC_STEPS, SC_SCAT, SC_TRIALS, SC_KILL, SC_SURV, SC_ESC, SC_BUDGET, SC_NUM, SC_PACK, SC_N };
+enum { SE_EMIT, SE_ESC, SE_ABS, SE_KILL, SE_GAIN, SE_BUDGET, SE_SCAT, SE_N };
+
+template <typename R>
+__device__ void finish(const Packet<R>& p, uint32_t end, const TransportArgs& a,
+                       unsigned long long* sc, double* se) {
+  atomicAdd(&sc[SC_STEPS], (unsigned long long)p.steps);
+  atomicAdd(&sc[SC_SCAT], (unsigned long long)p.events);
+  atomicAdd(&sc[SC_TRIALS], (unsigned long long)p.trials);
+  atomicAdd(&sc[SC_PACK], 1ull);
+  if (p.rr) atomicAdd(&sc[SC_SURV], (unsigned long long)p.rr);
+  atomicAdd(&se[SE_EMIT], (double)p.w0);
+  if (end != END_NUMERIC) {
+    atomicAdd(&se[SE_ABS], p.e_abs);
+    atomicAdd(&se[SE_SCAT], p.e_scat);
+    if (p.e_gain != 0.0) atomicAdd(&se[SE_GAIN], p.e_gain);
+  }
+  switch (end) {
+    case END_ESCAPE: atomicAdd(&sc[SC_ESC], 1ull); atomicAdd(&se[SE_ESC], (double)p.I); break;
+    case END_RR_KILL: atomicAdd(&sc[SC_KILL], 1ull); atomicAdd(&se[SE_KILL], (double)p.I); break;
+    case END_BUDGET: atomicAdd(&sc[SC_BUDGET], 1ull); atomicAdd(&se[SE_BUDGET], (double)p.I); break;
+    default: atomicAdd(&sc[SC_NUM], 1ull); break;
+  }
+  if (a.trace_count && (p.pid % a.trace_stride) == 0 && p.pid / a.trace_stride < a.trace_count) {
+    TraceDev& t = a.traces[(uint64_t)p.lam * a.trace_count + p.pid / a.trace_stride];
+    t.packet = p.pid;
+    t.end_kind = (int32_t)end;
+    t.events = p.events;
+    t.steps = p.steps;
+    t.last_cell = p.last;
+    t.n[0] = (double)p.nx; t.n[1] = (double)p.ny; t.n[2] = (double)p.nz;
+    t.stokes[0] = (double)p.I; t.stokes[1] = (double)p.Q;
+    t.stokes[2] = (double)p.U; t.stokes[3] = (double)p.V;
+    t.hash = p.hash;
+  }
+}
+
+template <typename R, bool ALIGNED, bool SPHERE>
+__global__ void __launch_bounds__(256) k_transport(TransportArgs a) {
+  __shared__ unsigned long long sc[SC_N];
+  __shared__ double se[SE_N];
+  if (threadIdx.x < SC_N) sc[threadIdx.x] = 0ull;
+  if (threadIdx.x < SE_N) se[threadIdx.x] = 0.0;
+  __syncthreads();
+
+  Packet<R> p;
+  bool active = false, exhausted = false;
+  int64_t acc_key = -1;
+  double acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+  const int lane = (int)__lane_id();
+
+  while (true) {
+    if (!exhausted) {
+      const unsigned long long idle = __ballot(!active);
+      if (idle) {
+        const int nidle = __popcll(idle);
+        const int leader = __ffsll((unsigned long long)idle) - 1;
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(a.counter, (unsigned long long)nidle);
+        base = __shfl(base, leader);
+        if (!active) {
+          const unsigned long long below = lane ? (idle & ((1ull << lane) - 1ull)) : 0ull;
+          const unsigned long long g = base + (unsigned long long)__popcll(below);
+          if (g < a.total) {
+            if (init_packet(p, g, a)) active = true;
+            else finish(p, END_ESCAPE, a, sc, se);
+          }
+        }
+        if (base + (unsigned long long)nidle >= a.total) exhausted = true;
+      }
+    }
+    if (!__any(active)) break;
+    if (active) {
+      const uint32_t end = step<R, ALIGNED, SPHERE>(p, a, acc_key, acc);
+      if (end) {
+        finish(p, end, a, sc, se);
+        active = false;
+      }
+    }
+  }
+  flush_acc(a.tally, acc_key, acc);
+  __syncthreads();
+  if (threadIdx.x < SC_N) atomicAdd(&(&a.stats->cell_steps)[threadIdx.x], sc[threadIdx.x]);
+  if (threadIdx.x < SE_N) unsafeAtomicAdd(&(&a.stats->e_emitted)[threadIdx.x], se[threadIdx.x]);
+}
+
+// ---------------------------------------------------------------------------
+// Step 2 (Sec. 2.3): one lane per (wavelength, view, pixel).  The ray enters
+// the grid box from the far side and is marched cell by cell toward the
+// camera; each cell applies the Appendix A solution with the cell's
+// extinction for the camera direction and the scattering source formed from
+// the coherency tally (or a caller-given per-view source).  FP64 throughout.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void appA_eigen(double a1, double a2, double a3, double dtau,
+                                           const double src[4], double s[4]) {
+  const double a = a1 + a2, b = a1 - a2;
+  const double A = s[0] + s[1], B = s[0] - s[1];
+  const double SA = src[0] + src[1], SB = src[0] - src[1];
+  const double An = A * exp(-a * dtau) + SA * dtau * phi1(a * dtau);
+  const double Bn = B * exp(-b * dtau) + SB * dtau * phi1(b * dtau);
+  double Un, Vn;
+  if (a3 == 0.0) {
+    const double e = exp(-a1 * dtau), g = dtau * phi1(a1 * dtau);
+    Un = s[2] * e + src[2] * g;
+    Vn = s[3] * e + src[3] * g;
+  } else {
+    // U + iV relaxes as exp(-(a1 - i a3) tau) toward the stationary state
+    const double x = -a1 * dtau, y = a3 * dtau;
+    const double ex = exp(x), cy = cos(y), sy = sin(y), sh = sin(0.5 * y);
+    const Cx<double> ez{ex * cy, ex * sy};
+    const Cx<double> em1{expm1(x) * cy - 2.0 * sh * sh, ex * sy};
+    const double den = x * x + y * y;
+    const Cx<double> phic{(em1.re * x + em1.im * y) / den, (em1.im * x - em1.re * y) / den};
+    const Cx<double> Z{s[2], s[3]}, SZ{src[2], src[3]};
+    const Cx<double> Zn = cadd(cmul(Z, ez), cscale(cmul(SZ, phic), dtau));
+    Un = Zn.re; Vn = Zn.im;
+  }
+  s[0] = 0.5 * (An + Bn);
+  s[1] = 0.5 * (An - Bn);
+  s[2] = Un;
+  s[3] = Vn;
+}
+
+template <bool ALIGNED, bool SPHERE, bool USER_S>
+__global__ void __launch_bounds__(256) k_image(ImageArgs a) {
+  const uint64_t npix = (uint64_t)a.npx * a.npy;
+  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t total = npix * a.n_views * a.n_lambda;
+  if (idx >= total) return;
+  const int ix = (int)(idx % a.npx);
+  const int iy = (int)((idx / a.npx) % a.npy);
+  const int v = (int)((idx / npix) % a.n_views);
+  const int lam = (int)(idx / (npix * a.n_views));
+  const ViewDev vw = a.views[v];
+  const DustDev& D = a.dust[lam];
+  const double W = vw.half_width;
+  const double xp = -W + (ix + 0.5) * (2.0 * W / a.npx);
+  const double yp = -W + (iy + 0.5) * (2.0 * W / a.npy);
+  const double P0[3] = {xp * vw.px - yp * vw.tx, xp * vw.py - yp * vw.ty, xp * vw.pz - yp * vw.tz};
+  const double om[3] = {vw.ox, vw.oy, vw.oz};
+  const double lo[3] = {a.x0, a.y0, a.z0};
+  const int nn[3] = {a.nx, a.ny, a.nz};
+  double sn = -__builtin_huge_val(), sf = __builtin_huge_val();
+  bool miss = false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double hi = lo[k] + nn[k] * a.dx;
+    if (om[k] != 0.0) {
+      const double s1 = (lo[k] - P0[k]) / om[k], s2 = (hi - P0[k]) / om[k];
+      sn = fmax(sn, fmin(s1, s2));
+      sf = fmin(sf, fmax(s1, s2));
+    } else if (P0[k] < lo[k] || P0[k] >= hi) {
+      miss = true;
+    }
+  }
+  double st[4] = {0.0, 0.0, 0.0, 0.0};
+  if (!miss && sn < sf) {
+    int ci[3];
+    double f[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double t = (P0[k] + sn * om[k] - lo[k]) / a.dx;
+      int i = (int)floor(t);
+      i = i < 0 ? 0 : (i > nn[k] - 1 ? nn[k] - 1 : i);
+      ci[k] = i;
+      f[k] = fmin(1.0, fmax(0.0, t - (double)i));
+    }
+    const V3<double> Om{om[0], om[1], om[2]};
+    const V3<double> e1{vw.tx, vw.ty, vw.tz}, e2{vw.px, vw.py, vw.pz};
+    const double kext = D.kext;
+    const double inv_vol = 1.0 / (a.dx * a.dx * a.dx);
+    while (true) {
+      double tb = __builtin_huge_val();
+      int axis = -1;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        double t;
+        if (om[k] > 0.0) t = (1.0 - f[k]) / om[k];
+        else if (om[k] < 0.0) t = -f[k] / om[k];
+        else continue;
+        if (t < tb) { tb = t; axis = k; }
+      }
+      if (axis < 0) break;
+      const uint64_t c = (uint64_t)ci[0] + (uint64_t)a.nx * ((uint64_t)ci[1] + (uint64_t)a.ny * ci[2]);
+      const double rho = (double)a.rho[c];
+      if (rho > 0.0) {
+        const double ke = rho * kext;
+        const double dtau = ke * tb * a.dx;
+        double S[4];
+        Quat<double> q{1.0, 0.0, 0.0, 0.0};
+        if (ALIGNED) q = grain_quat(V3<double>{(double)a.bx[c], (double)a.by[c], (double)a.bz[c]});
+        if (USER_S) {
+          const double* Sv = a.user_S + (c * a.n_views + v) * 4;
+          S[0] = Sv[0]; S[1] = Sv[1]; S[2] = Sv[2]; S[3] = Sv[3];
+        } else {
+          // source toward the camera from the incident coherency C of the
+          // cell: rho'_ij = h_i^T C conj(h_j), h_i = alpha e_i with the lab
+          // polarizability alpha = a_perp 1 + (a_par - a_perp) b b^T.
+          const double* T = a.tally + ((uint64_t)lam * a.ncell + c) * 9;
+          const double Cr[3][3] = {{T[0], T[3], T[4]}, {T[3], T[1], T[5]}, {T[4], T[5], T[2]}};
+          const double Ci[3][3] = {{0.0, T[8], -T[7]}, {-T[8], 0.0, T[6]}, {T[7], -T[6], 0.0}};
+          Cx<double> h1[3], h2[3];
+          const double ev1[3] = {e1.x, e1.y, e1.z}, ev2[3] = {e2.x, e2.y, e2.z};
+          if (SPHERE) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) { h1[k] = {ev1[k], 0.0}; h2[k] = {ev2[k], 0.0}; }
+          } else {
+            const V3<double> b = from_grain(q, V3<double>{0.0, 0.0, 1.0});
+            const double bv[3] = {b.x, b.y, b.z};
+            const double b1 = dot(b, e1), b2 = dot(b, e2);
+            const Cx<double> ap{D.ap_re, D.ap_im}, dd{D.aa_re - D.ap_re, D.aa_im - D.ap_im};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              h1[k] = cadd(cscale(ap, ev1[k]), cscale(dd, b1 * bv[k]));
+              h2[k] = cadd(cscale(ap, ev2[k]), cscale(dd, b2 * bv[k]));
+            }
+          }
+          // g_j = C conj(h_j)
+          Cx<double> g1[3], g2[3];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            g1[k] = {0.0, 0.0};
+            g2[k] = {0.0, 0.0};
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+              const Cx<double> C{Cr[k][l], Ci[k][l]};
+              g1[k] = cadd(g1[k], cmulc(C, h1[l]));
+              g2[k] = cadd(g2[k], cmulc(C, h2[l]));
+            }
+          }
+          double r11 = 0.0, r22 = 0.0;
+          Cx<double> r12{0.0, 0.0};
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            r11 += cmul(h1[k], g1[k]).re;
+            r22 += cmul(h2[k], g2[k]).re;
+            r12 = cadd(r12, cmul(h1[k], g2[k]));
+          }
+          const double pf = D.pfac * inv_vol;
+          S[0] = pf * (r11 + r22);
+          S[1] = pf * (r11 - r22);
+          S[2] = pf * 2.0 * r12.re;
+          S[3] = -pf * 2.0 * r12.im;
+        }
+        const double ik = 1.0 / ke;
+        double src[4] = {S[0] * ik, S[1] * ik, S[2] * ik, S[3] * ik};
+        if (SPHERE && !ALIGNED) {
+          const double E = exp(-dtau), G = dtau * phi1(dtau);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) st[k] = st[k] * E + src[k] * G;
+        } else {
+          V3<double> og = Om;
+          double c2 = 1.0, s2 = 0.0;
+          if (ALIGNED) {
+            og = to_grain(q, Om);
+            eta2(q, Om, og, c2, s2);
+          }
+          double a1, a2, a3;
+          alphas<double, SPHERE>(D, og.z, a1, a2, a3);
+          double sg[4] = {st[0], c2 * st[1] + s2 * st[2], -s2 * st[1] + c2 * st[2], st[3]};
+          const double srcg[4] = {src[0], c2 * src[1] + s2 * src[2], -s2 * src[1] + c2 * src[2],
+                                  src[3]};
+          appA_eigen(a1, a2, a3, dtau, srcg, sg);
+          st[0] = sg[0];
+          st[1] = c2 * sg[1] - s2 * sg[2];
+          st[2] = s2 * sg[1] + c2 * sg[2];
+          st[3] = sg[3];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (k != axis) f[k] = fmin(1.0, fmax(0.0, f[k] + tb * om[k]));
+      if (om[axis] > 0.0) { ci[axis]++; f[axis] = 0.0; } else { ci[axis]--; f[axis] = 1.0; }
+      if (ci[axis] < 0 || ci[axis] >= nn[axis]) break;
+    }
+  }
+  double* out = a.images + (((uint64_t)lam * a.n_views + v) * 4) * npix + (uint64_t)iy * a.npx + ix;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) out[(uint64_t)k * npix] = st[k];
+}
+
+// ---------------------------------------------------------------------------
+// utility kernels
+// ---------------------------------------------------------------------------
+__global__ void k_fill_zero(uint64_t* p, uint64_t nwords, unsigned char* tail, int ntail) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride)
+    p[i] = 0ull;
+  if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+__global__ void k_validate(const float* rho, const float* bx, const float* by, const float* bz,
+                           uint64_t n, unsigned long long* bad) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  unsigned long long nbad = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float r = rho[i];
+    if (!(r >= 0.0f) || !isfinite(r)) nbad++;
+    if (bx) {
+      const double b2 = (double)bx[i] * bx[i] + (double)by[i] * by[i] + (double)bz[i] * bz[i];
+      if (!(fabs(sqrt(b2) - 1.0) <= 1e-5)) nbad++;
+    }
+  }
+  if (nbad) atomicAdd(bad, nbad);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename R>
+static hipError_t launch_t(const TransportArgs& a, bool aligned, bool sphere, int blocks, int bs,
+                           hipStream_t s) {
+  if (aligned && sphere) hipLaunchKernelGGL((k_transport<R, true, true>), dim3(blocks), dim3(bs), 0, s, a);
+  else if (aligned) hipLaunchKernelGGL((k_transport<R, true, false>), dim3(blocks), dim3(bs), 0, s, a);
+  else if (sphere) hipLaunchKernelGGL((k_transport<R, false, true>), dim3(blocks), dim3(bs), 0, s, a);
+  else hipLaunchKernelGGL((k_transport<R, false, false>), dim3(blocks), dim3(bs), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_transport(const TransportArgs& a, bool fp64, bool aligned, bool sphere,
+                            int blocks, int block_size, hipStream_t s) {
+  return fp64 ? launch_t<double>(a, aligned, sphere, blocks, block_size, s)
+              : launch_t<float>(a, aligned, sphere, blocks, block_size, s);
+}
+
+template <typename R>
+static int occ_t(bool aligned, bool sphere, int bs) {
+  int n = 0;
+  hipError_t e;
+  if (aligned && sphere) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport<R, true, true>, bs, 0);
+  else if (aligned) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport<R, true, false>, bs, 0);
+  else if (sphere) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport<R, false, true>, bs, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport<R, false, false>, bs, 0);
+  return e == hipSuccess ? n : 0;
+}
+
+int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, int block_size) {
+  return fp64 ? occ_t<double>(aligned, sphere, block_size) : occ_t<float>(aligned, sphere, block_size);
+}
+
+hipError_t launch_image(const ImageArgs& a, bool aligned, bool sphere, bool user_source,
+                        hipStream_t s) {
+  const uint64_t total = (uint64_t)a.npx * a.npy * a.n_views * a.n_lambda;
+  const int bs = 128;
+  const dim3 grid((unsigned)((total + bs - 1) / bs));
+  if (user_source) {
+    if (aligned && sphere) hipLaunchKernelGGL((k_image<true, true, true>), grid, dim3(bs), 0, s, a);
+    else if (aligned) hipLaunchKernelGGL((k_image<true, false, true>), grid, dim3(bs), 0, s, a);
+    else if (sphere) hipLaunchKernelGGL((k_image<false, true, true>), grid, dim3(bs), 0, s, a);
+    else hipLaunchKernelGGL((k_image<false, false, true>), grid, dim3(bs), 0, s, a);
+  } else {
+    if (aligned && sphere) hipLaunchKernelGGL((k_image<true, true, false>), grid, dim3(bs), 0, s, a);
+    else if (aligned) hipLaunchKernelGGL((k_image<true, false, false>), grid, dim3(bs), 0, s, a);
+    else if (sphere) hipLaunchKernelGGL((k_image<false, true, false>), grid, dim3(bs), 0, s, a);
+    else hipLaunchKernelGGL((k_image<false, false, false>), grid, dim3(bs), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  const uint64_t nwords = bytes / 8;
+  const int ntail = (int)(bytes % 8);
+  uint64_t blocks = (nwords + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, (uint64_t*)p, nwords,
+                     (unsigned char*)p + nwords * 8, ntail);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const float* rho, const float* bx, const float* by, const float* bz,
+                           uint64_t n, unsigned long long* bad, hipStream_t s) {
+  uint64_t blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_validate, dim3((unsigned)blocks), dim3(256), 0, s, rho, bx, by, bz, n, bad);
+  return hipGetLastError();
+}
+
+}  // namespace kp

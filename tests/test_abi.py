@@ -1,0 +1,64 @@
+"""The C-ABI library loads and exports every entry point include/polrad.h
+declares; the binding has no CPU fallback.  No compute calls (no GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    txt = open(os.path.join(ROOT, "include", "polrad.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:kp_status|void|const char \*)\s*(kp_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ("kp_create", "kp_destroy", "kp_set_grid", "kp_set_grid_device", "kp_set_dust",
+                 "kp_set_source", "kp_set_views", "kp_run", "kp_transport", "kp_image",
+                 "kp_image_source", "kp_get_images", "kp_get_images_device", "kp_get_stats",
+                 "kp_get_trace", "kp_get_tally", "kp_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2512_01283_amd import polrad as P
+    lib = ctypes.CDLL(P.LIB_PATH)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(P.header_symbols()) == declared()
+
+
+def test_struct_layouts_match_header():
+    from paper_2512_01283_amd import polrad as P
+    # sizes implied by the C declarations (x86-64 SysV alignment)
+    assert ctypes.sizeof(P.kp_grid) == 3 * 4 + 4 + 4 * 8 + 4 + 4
+    assert ctypes.sizeof(P.kp_dust) == 7 * 8
+    assert ctypes.sizeof(P.kp_source) == 8 + 7 * 8
+    assert ctypes.sizeof(P.kp_view) == 2 * 8 + 2 * 4 + 8
+    assert ctypes.sizeof(P.kp_opts) == 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4 + 4 + 4 + 4 + 4
+    assert P.TRACE_DTYPE.itemsize == 8 + 4 + 4 + 8 + 8 + 24 + 32 + 8
+
+
+def test_no_device_is_reported_cleanly():
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present")
+    from paper_2512_01283_amd import polrad as P
+    h = ctypes.c_void_p()
+    assert P._lib.kp_create(0, ctypes.byref(h)) == P.KP_ERR_DEVICE
+    assert P._lib.kp_set_grid(None, None, None, None) == P.KP_ERR_ARG
+    assert P._lib.kp_run(None, None, None, None) == P.KP_ERR_ARG
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    import importlib.util
+    src = os.path.join(ROOT, "paper_2512_01283_amd", "polrad.py")
+    dst = tmp_path / "polrad.py"
+    dst.write_text(open(src).read())
+    spec = importlib.util.spec_from_file_location("polrad_copy", str(dst))
+    mod = importlib.util.module_from_spec(spec)
+    with pytest.raises(ImportError):
+        spec.loader.exec_module(mod)

@@ -1,0 +1,260 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the same
+seeded inputs and the same Philox packet streams.
+
+Bars: FP64 transport -- identical event sequences and 1e-12 (Stokes relative
+to the packet weight, directions absolute); FP32 transport -- 1e-5 on the
+packets whose event sequence matches the oracle's (an FP32 rounding can flip
+a scatter/cross or accept/reject decision, which the event hash detects);
+images -- 1e-10 of the image maximum where the step-1 arithmetic is FP64 and
+the packets identical, else per-pixel agreement within 3 Monte Carlo sigma.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2512_01283_amd import workloads as W
+from parity_util import compare_images_stat, compare_traces, gpu_run, oracle_batches, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle as o
+    o.lib()
+    return o
+
+
+def stokes_bound(img, rel=1e-9):
+    I = img[..., 0, :, :]
+    P = np.sqrt(img[..., 1, :, :] ** 2 + img[..., 2, :, :] ** 2 + img[..., 3, :, :] ** 2)
+    return (I * (1 + rel) + 1e-300 >= P).all()
+
+
+def test_config0_fp64_path_by_path(O):
+    """Uniform sphere 32^3, tau = 1, Rayleigh, 1e5 packets, FP64: every traced
+    packet follows the oracle's path; images agree to 1e-10."""
+    say("case: sphere32 fp64 1e5 packets")
+    cfg = W.uniform_sphere()
+    ctx = gpu_run(cfg, trace_packets=1000, transport_fp64=1)
+    img_g = ctx.images()[0]
+    tr_g = ctx.traces()
+    st = ctx.stats()
+    img_o, S, tr_o, st_o = O.run(cfg, traces=True)
+    compare_traces(tr_g, tr_o[:1000], 1e-12, 1.0, "sphere32 fp64")
+    for k in ("cell_steps", "scatterings", "trials", "escaped", "rr_kills", "packets"):
+        if k in st_o:
+            assert st[k] == st_o[k], k
+    assert st["packets"] == 100_000
+    assert abs(st["e_escaped"] - st_o["e_escaped"]) < 1e-12
+    scale = np.abs(img_o[:, 0]).max()
+    d = np.abs(img_g - img_o).max() / scale
+    say(f"sphere32 fp64 image max |d|/I_max = {d:.3e}")
+    assert d < 1e-10
+    assert stokes_bound(img_g)
+
+
+def test_config0_fp32(O):
+    say("case: sphere32 fp32 2e4 packets")
+    cfg = W.uniform_sphere(packets=20000)
+    ctx = gpu_run(cfg, trace_packets=2000, transport_fp64=0)
+    img_o, batches = oracle_batches(cfg)
+    _, tr_o, _ = O.transport(cfg, p_end=2000, tally=False, traces=True)
+    compare_traces(ctx.traces(), tr_o, 1e-5, 0.99, "sphere32 fp32")
+    compare_images_stat(ctx.images()[0], img_o, batches, label="sphere32 fp32")
+
+
+def test_schedule_independence():
+    """Block shape and residency change nothing: same traces, images equal up
+    to the order of FP64 atomic additions."""
+    say("case: sphere32 fp64 schedules")
+    cfg = W.uniform_sphere(packets=30000, albedo=0.5, tau_radius=3.0)
+    a = gpu_run(cfg, trace_packets=3000, transport_fp64=1)
+    b = gpu_run(cfg, trace_packets=3000, transport_fp64=1, block_size=64, blocks_per_cu=1)
+    ta, tb = a.traces(), b.traces()
+    assert np.array_equal(ta, tb)
+    ia, ib = a.images(), b.images()
+    assert np.abs(ia - ib).max() <= 1e-12 * np.abs(ia[:, :, 0]).max()
+
+
+def test_aligned_slab_clump(O):
+    """128^3 log-normal slab + clump with aligned oblate grains (dichroic
+    extinction, thick cells up to tau = 100), FP32 transport, 4 views."""
+    say("case: slab_clump128 fp32 3e4 packets")
+    cfg = W.slab_clump(packets=30000)
+    ctx = gpu_run(cfg, trace_packets=3000)
+    _, tr_o, st_o = O.transport(cfg, p_end=3000, tally=False, traces=True)
+    tr_g = ctx.traces()
+    compare_traces(tr_g, tr_o, 1e-5, 0.98, "slab_clump fp32")
+    s = tr_g["stokes"]
+    assert (s[:, 0] * (1 + 1e-5) >= np.sqrt((s[:, 1:] ** 2).sum(1))).all()
+    img_o, batches = oracle_batches(cfg)
+    img_g = ctx.images()[0]
+    compare_images_stat(img_g, img_o, batches, label="slab_clump fp32")
+    assert stokes_bound(img_g, 1e-5)
+    st = ctx.stats()
+    bal = st["e_escaped"] + st["e_absorbed"] + st["e_rr_killed"] - st["e_rr_gained"] + st["e_budget"]
+    assert abs(bal - st["e_emitted"] - st["e_scat_delta"]) < 1e-4 * st["e_emitted"]
+
+
+def test_disk_small_images(O):
+    """Flared disk on 64^3 (midplane tau 1e4, roulette), 8 inclinations."""
+    say("case: disk64 fp32 4e4 packets")
+    cfg = W.flared_disk(n=64, packets=40000, npix=64)
+    ctx = gpu_run(cfg, trace_packets=4000)
+    _, tr_o, _ = O.transport(cfg, p_end=4000, tally=False, traces=True)
+    compare_traces(ctx.traces(), tr_o, 1e-5, 0.98, "disk64 fp32")
+    img_o, batches = oracle_batches(cfg)
+    compare_images_stat(ctx.images()[0], img_o, batches, label="disk64 fp32")
+
+
+def test_disk_full_size_sampled(O):
+    """The 256^3 disk at 1e8 packets in the benchmark's launch configuration:
+    1000 packets sampled across the run (every 1e5-th id) follow the oracle's
+    paths; the full images satisfy I >= |P| and the energy budget closes."""
+    say("case: disk256 fp32 1e8 packets, sampled traces")
+    cfg = W.flared_disk()
+    ctx = gpu_run(cfg, trace_packets=1000, trace_stride=100_000)
+    st = ctx.stats()
+    say(f"disk256: {st['packets']} packets, {st['cell_steps']} cell steps, "
+        f"{st['ms_transport']:.1f} ms transport, {st['ms_image']:.1f} ms imaging")
+    tr_g = ctx.traces()
+    ids = np.arange(0, 100_000_000, 100_000, dtype=np.uint64)
+    tr_o = O.trace_packets(cfg, ids)
+    compare_traces(tr_g, tr_o, 1e-5, 0.98, "disk256 sampled")
+    img = ctx.images()[0]
+    assert np.isfinite(img).all()
+    assert stokes_bound(img, 1e-6)
+    bal = st["e_escaped"] + st["e_absorbed"] + st["e_rr_killed"] - st["e_rr_gained"] + st["e_budget"]
+    assert abs(bal - st["e_emitted"]) < 1e-5 * st["e_emitted"]
+    assert st["packets"] == 100_000_000 and st["numeric"] == 0
+
+
+@pytest.mark.parametrize("fp64", [1, 0])
+@pytest.mark.parametrize("a3s", [0.0, -1.0])
+def test_twisted_slab(O, fp64, a3s):
+    """Pencil beam through the twisted-field slab (Sec. 3.2) -- quaternion
+    grain frames, signed eta rotations, dichroic extinction and the U-V term."""
+    for start in (0.3, 1.0):
+        cfg = W.pencil_slab(n_z=64, p0=0.05, alpha3_scale=a3s, start_tau=start)
+        cfg["packets"] = [3]
+        ctx = gpu_run(cfg, trace_packets=3, transport_fp64=fp64)
+        tr_o = O.trace_packets(cfg, np.arange(3, dtype=np.uint64))
+        compare_traces(ctx.traces(), tr_o, 1e-12 if fp64 else 2e-6, 1.0, f"twisted fp64={fp64}")
+
+
+@pytest.mark.parametrize("tau", [1e-3, 1.0, 10.0, 40.0])
+def test_image_source_dichroic_emission(O, tau):
+    """Step 2 alone on a caller-given source: eq. ptau in every pixel, and the
+    oracle's step 2 on the same source to 1e-12."""
+    import torch
+    from paper_2512_01283_amd import polrad as P
+    p0 = 0.3
+    cfg = W.pencil_slab(n_z=16, p0=p0, twist=False, tau_total=tau, start_tau=tau, nxy=4)
+    g = cfg["grid"]
+    cfg["views"] = [dict(theta=0.0, phi=0.0, npx=4, npy=4, half_width=g["dx"])]
+    ncell = g["nx"] * g["ny"] * g["nz"]
+    S = np.zeros((ncell, 1, 4))
+    S[:, 0, 0], S[:, 0, 1] = 2.0, -p0 * 2.0
+    ctx = P.Context(0).load(cfg)
+    dS = torch.from_numpy(S).cuda()
+    out = torch.zeros((1, 4, 4, 4), dtype=torch.float64, device="cuda")
+    P.kp_image_source(ctx.h, dS, out)
+    torch.cuda.synchronize()
+    img = out.cpu().numpy()
+    ref = O.image(cfg, S)
+    assert np.allclose(img, ref, rtol=1e-12, atol=1e-15)
+    Pt = math.exp(-tau) * math.sinh(p0 * tau) / (1 - math.exp(-tau) * math.cosh(p0 * tau))
+    assert np.allclose(-img[0, 1] / img[0, 0], Pt, rtol=1e-10)
+
+
+def test_batched_wavelengths(O):
+    """Several wavelengths with uneven (and one empty) packet counts in one
+    persistent launch: each wavelength follows its own streams exactly as a
+    single-wavelength oracle run does."""
+    say("case: batched disk48 x4 wavelengths")
+    counts = [3000, 0, 1700, 2500]
+    cfg = W.batched_disk(n=48, n_lambda=4, npix=32, counts=counts)
+    ctx = gpu_run(cfg, trace_packets=500)
+    tr = ctx.traces().reshape(4, 500)
+    img_g = ctx.images()
+    for lam, n in enumerate(counts):
+        if n == 0:
+            assert np.all(img_g[lam] == 0)
+            continue
+        _, tr_o, _ = O.transport(cfg, lam=lam, p_end=min(n, 500), tally=False, traces=True)
+        compare_traces(tr[lam][: min(n, 500)], tr_o, 1e-5, 0.98, f"batched lam={lam}")
+        img_o, batches = oracle_batches(cfg, nb=6, lam=lam)
+        compare_images_stat(img_g[lam], img_o, batches, label=f"batched lam={lam}")
+
+
+def test_edge_cases(O):
+    from paper_2512_01283_amd import polrad as P
+    # one packet, and a ragged 65-packet run (one full wavefront + 1 lane)
+    for n in (1, 65):
+        cfg = W.uniform_sphere(packets=n)
+        ctx = gpu_run(cfg, trace_packets=n, transport_fp64=1)
+        _, tr_o, _ = O.transport(cfg, traces=True, tally=False)
+        compare_traces(ctx.traces(), tr_o, 1e-12, 1.0, f"n={n}")
+    # empty grid: packets stream straight out, nothing is tallied or imaged
+    cfg = W.uniform_sphere(packets=500)
+    cfg["rho"] = np.zeros_like(cfg["rho"])
+    ctx = gpu_run(cfg, trace_packets=10, transport_fp64=1)
+    st = ctx.stats()
+    assert st["escaped"] == 500 and st["scatterings"] == 0
+    assert np.all(ctx.images() == 0) and np.all(ctx.tally() == 0)
+    # pencil starting on the outer face, pointing out: escapes before any step
+    cfg = W.pencil_slab(n_z=4, start_tau=1.0)
+    cfg["source"]["dir"] = (0.0, 0.0, 1.0)
+    ctx = gpu_run(cfg, trace_packets=1)
+    t = ctx.traces()[0]
+    assert t["end_kind"] == 2 and t["steps"] == 0 and t["last_cell"] == -1
+
+
+def test_argument_errors():
+    import torch
+    from paper_2512_01283_amd import polrad as P
+    cfg = W.uniform_sphere(packets=10)
+    ctx = P.Context(0)
+    with pytest.raises(P.KpError) as e:
+        ctx_opts = P.make_opts(cfg["opts"])
+        P.kp_run(ctx.h, [10], ctx_opts)
+    assert e.value.status == P.KP_ERR_STATE
+    bad = cfg["rho"].copy()
+    bad[5] = np.nan
+    with pytest.raises(P.KpError) as e:
+        P.kp_set_grid(ctx.h, cfg["grid"], bad, None)
+    assert e.value.status == P.KP_ERR_ARG
+    neg = torch.from_numpy(-np.ones_like(cfg["rho"])).cuda()
+    with pytest.raises(P.KpError) as e:
+        P.kp_set_grid_device(ctx.h, cfg["grid"], neg, None)
+    assert e.value.status == P.KP_ERR_ARG
+    nb = np.zeros((3, cfg["rho"].size), np.float32)
+    nb[0] = 0.5
+    with pytest.raises(P.KpError) as e:
+        P.kp_set_grid(ctx.h, cfg["grid"], cfg["rho"], nb)
+    assert e.value.status == P.KP_ERR_ARG
+    ctx.load(cfg)
+    for kw in (dict(block_size=100), dict(max_events=0), dict(rr_psurv=0.0), dict(tally_mode=3)):
+        with pytest.raises(P.KpError) as e:
+            P.kp_run(ctx.h, [10], ctx.opts(**kw))
+        assert e.value.status == P.KP_ERR_ARG, kw
+    with pytest.raises(P.KpError) as e:
+        P.kp_run(ctx.h, [0], ctx.opts())
+    assert e.value.status == P.KP_ERR_ARG
+    v = [dict(cfg["views"][0]), dict(cfg["views"][0], npx=8)]
+    with pytest.raises(P.KpError) as e:
+        P.kp_set_views(ctx.h, v)
+    assert e.value.status == P.KP_ERR_ARG
+    with pytest.raises(P.KpError) as e:
+        P.kp_set_dust(ctx.h, [dict(cfg["dust"][0], kappa_sca=-1.0)])
+    assert e.value.status == P.KP_ERR_ARG
+    with pytest.raises(P.KpError) as e:
+        P.kp_set_source(ctx.h, dict(cfg["source"], pos=(5.0, 0.0, 0.0)))
+        P.kp_run(ctx.h, [10], ctx.opts())
+    assert e.value.status == P.KP_ERR_ARG
+    # the context still works after the rejected calls
+    P.kp_set_source(ctx.h, cfg["source"])
+    P.kp_run(ctx.h, [10], ctx.opts())
+    ctx.close()
