@@ -23,6 +23,12 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is missing: build it with `python -m paper_2512_01283_amd.build` "
         "(hipcc, gfx950); the transport has no CPU fallback")
 
+# PyTorch ships its own HIP runtime under the same soname (libamdhip64.so.7).
+# Loading torch first makes the dynamic loader bind libpolrad.so to that one
+# runtime, so device pointers and streams from torch are valid in the library
+# (two HIP runtimes in one process do not share devices).
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 KP_OK, KP_ERR_ARG, KP_ERR_OOM, KP_ERR_DEVICE, KP_ERR_STATE, KP_ERR_NUMERIC, KP_ERR_BUDGET = range(7)
