@@ -130,10 +130,12 @@ typedef struct {
   int64_t packets;
 } kp_stats;
 
-/* Final state of a traced packet. end_kind: 2 escaped, 4 roulette kill,
- * 5 event cap, 6 non-finite state.  hash: FNV-1a-64 over the 4-byte
- * little-endian (kind, cell) pairs of its events (1 scatter, 2 escape,
- * 3 roulette survival, 4 roulette kill, 5 cap). */
+/* Final state of a traced packet. end_kind: 2 escaped, 4 roulette kill or
+ * absorbed, 5 event cap, 6 non-finite state.  hash: FNV-1a-64 over the
+ * 4-byte little-endian (kind, cell) pairs of its events (1 scatter,
+ * 2 escape, 3 roulette survival, 4 roulette kill, 5 cap).  tau_path: sum
+ * over its segments of the magnitude of the continuous-extinction exponent
+ * (rho kappa_ext alpha1 - rho kappa_sca) * length. */
 typedef struct {
   uint64_t packet;
   int32_t end_kind;
@@ -143,6 +145,7 @@ typedef struct {
   double n[3];
   double stokes[4];
   uint64_t hash;
+  double tau_path;
 } kp_packet_trace;
 
 /* Create a context on HIP device `device`.  *out receives an owned handle

@@ -64,7 +64,8 @@ class Trace(C.Structure):
     _fields_ = [("packet", C.c_uint64), ("end_kind", C.c_int32),
                 ("events", C.c_int32), ("steps", C.c_int64),
                 ("last_cell", C.c_int64), ("n", C.c_double * 3),
-                ("stokes", C.c_double * 4), ("hash", C.c_uint64)]
+                ("stokes", C.c_double * 4), ("hash", C.c_uint64),
+                ("tau_path", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -78,7 +79,7 @@ class Stats(C.Structure):
 
 TRACE_DTYPE = np.dtype([("packet", "<u8"), ("end_kind", "<i4"), ("events", "<i4"),
                         ("steps", "<i8"), ("last_cell", "<i8"), ("n", "<f8", 3),
-                        ("stokes", "<f8", 4), ("hash", "<u8")])
+                        ("stokes", "<f8", 4), ("hash", "<u8"), ("tau_path", "<f8")])
 assert TRACE_DTYPE.itemsize == C.sizeof(Trace)
 
 END_ESCAPE, END_RR_KILL, END_BUDGET, END_NUMERIC = 2, 4, 5, 6

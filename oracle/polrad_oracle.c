@@ -544,6 +544,7 @@ static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *s
   locate(g, R->src->pos, n, &p);
   int32_t events = 0, end = KPO_END_NONE;
   int64_t steps = 0, last = -1;
+  double tau_path = 0.0;
   uint64_t h = 14695981039346656037ULL;
   if (!inside(g, &p)) {
     end = KPO_END_ESCAPE;
@@ -582,6 +583,7 @@ static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *s
       double eta = eta_pair(q, n, ng);
       kpo_rotate_stokes(eta, s, sg);
       kpo_segment(ke * al[0] - kbar, ke * al[1], ke * al[2], len, sg, jg, og);
+      tau_path += fabs(ke * al[0] - kbar) * len;
       kpo_rotate_stokes(-eta, jg, jl);
       double I_before = s[0];
       kpo_rotate_stokes(-eta, og, s);
@@ -649,6 +651,7 @@ static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *s
     for (int a = 0; a < 3; ++a) tr->n[a] = n[a];
     for (int k = 0; k < 4; ++k) tr->stokes[k] = s[k];
     tr->hash = h;
+    tr->tau_path = tau_path;
   }
 }
 

@@ -71,6 +71,7 @@ typedef struct {
   double n[3];
   double stokes[4];
   uint64_t hash;                /* FNV-1a over (event kind, cell) of every event */
+  double tau_path;              /* sum of |continuous extinction exponent| over segments */
 } kpo_trace;
 
 typedef struct {

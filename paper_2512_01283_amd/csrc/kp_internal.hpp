@@ -46,6 +46,7 @@ struct TraceDev {
   double n[3];
   double stokes[4];
   uint64_t hash;
+  double tau_path;
 };
 
 struct TransportArgs {

@@ -61,6 +61,7 @@ struct Packet {
   R I, Q, U, V;       // Stokes vector in the lab basis of n
   R tau;              // remaining scattering optical depth
   R w0;               // initial weight
+  R tau_path;         // sum of |continuous extinction exponent| along the path
   R u0, u1, u2, u3;   // uniforms of the Philox block `blk`
   double e_abs, e_scat, e_gain;
   uint64_t pid, hash;
@@ -116,6 +117,7 @@ __device__ bool init_packet(Packet<R>& p, uint64_t g, const TransportArgs& a) {
   p.w0 = (R)a.dust[lo].w0;
   p.I = p.w0; p.Q = (R)0; p.U = (R)0; p.V = (R)0;
   p.e_abs = 0.0; p.e_scat = 0.0; p.e_gain = 0.0;
+  p.tau_path = (R)0;
   p.events = 0; p.steps = 0; p.trials = 0; p.rr = 0;
   p.hash = 14695981039346656037ull;
   p.last = -1;
@@ -313,6 +315,7 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, int64_t& acc_key,
       // spheres: extinction is the scalar absorption e^{-rho kappa_abs l}
       const R m1 = rho * (R)D.ka_cell;
       const R E = k_exp(-m1 * tl), G = tl * phi1(m1 * tl);
+      p.tau_path += m1 * tl;
       JI = p.I * G; JQ = p.Q * G; JU = p.U * G; JV = p.V * G;
       p.I *= E; p.Q *= E; p.U *= E; p.V *= E;
     } else {
@@ -327,6 +330,7 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, int64_t& acc_key,
       const R ke = rho * (R)D.ke_cell;
       const R mA = ke * (a1 + a2) - kb, mB = ke * (a1 - a2) - kb, mU = ke * a1 - kb;
       const R w = ke * a3;
+      p.tau_path += fabs(mU * tl);
       const R Qg = c2 * p.Q + s2 * p.U, Ug = -s2 * p.Q + c2 * p.U;
       const R A = p.I + Qg, B = p.I - Qg;
       const R gA = tl * phi1(mA * tl), gB = tl * phi1(mB * tl);
@@ -464,6 +468,7 @@ __device__ void finish(const Packet<R>& p, uint32_t end, const TransportArgs& a,
     t.stokes[0] = (double)p.I; t.stokes[1] = (double)p.Q;
     t.stokes[2] = (double)p.U; t.stokes[3] = (double)p.V;
     t.hash = p.hash;
+    t.tau_path = (double)p.tau_path;
   }
 }
 

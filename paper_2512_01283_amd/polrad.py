@@ -85,7 +85,7 @@ class kp_stats(C.Structure):
 
 TRACE_DTYPE = np.dtype([("packet", "<u8"), ("end_kind", "<i4"), ("events", "<i4"),
                         ("steps", "<i8"), ("last_cell", "<i8"), ("n", "<f8", 3),
-                        ("stokes", "<f8", 4), ("hash", "<u8")])
+                        ("stokes", "<f8", 4), ("hash", "<u8"), ("tau_path", "<f8")])
 
 _P = C.c_void_p
 _dp = C.POINTER(C.c_double)

@@ -17,11 +17,15 @@ def gpu_run(cfg, counts=None, device_arrays=True, **opts):
     return ctx
 
 
-def compare_traces(g, o, tol, min_match=1.0, label=""):
+def compare_traces(g, o, tol, min_match=1.0, label="", tau_coef=0.0):
     """Per-packet parity: identical event sequences (hash, end kind, counts,
-    last cell); on matched packets the final direction and Stokes vector agree
-    to `tol` relative to the packet's initial weight (Stokes) or absolutely
-    (direction).  Returns the matched fraction."""
+    last cell); on matched packets the final direction agrees to `tol`
+    absolutely and the Stokes vector to tol + tau_coef * tau_path relative to
+    the packet's I (tau_path: optical depth of the continuous extinction the
+    packet went through -- in FP32 the segment lengths carry an absolute
+    rounding of order 1e-7 cell, so the weight's relative error grows by about
+    that times the optical depth per cell crossed).  Returns the matched
+    fraction."""
     assert len(g) == len(o)
     assert np.array_equal(g["packet"], o["packet"]), "traced packet ids differ"
     same = ((g["hash"] == o["hash"]) & (g["end_kind"] == o["end_kind"]) &
@@ -32,11 +36,18 @@ def compare_traces(g, o, tol, min_match=1.0, label=""):
     assert frac >= min_match, f"only {frac:.4f} of packets follow the oracle's event sequence"
     gs, os_ = g["stokes"][same], o["stokes"][same]
     scale = np.maximum(np.abs(os_[:, :1]), 1e-300)
-    ds = np.abs(gs - os_) / scale
+    allow = tol + tau_coef * o["tau_path"][same][:, None]
+    ds = np.abs(gs - os_) / scale / allow
     dn = np.abs(g["n"][same] - o["n"][same])
-    say(f"[{label}] max |dS|/I = {ds.max() if ds.size else 0:.3e}, max |dn| = "
-        f"{dn.max() if dn.size else 0:.3e}")
-    assert (ds <= tol).all(), f"Stokes mismatch {ds.max():.3e} > {tol}"
+    raw = np.abs(gs - os_) / scale
+    if raw.size:
+        k = int(np.argmax(raw.max(1)))
+        say(f"[{label}] max |dS|/I = {raw.max():.3e} (tau_path {o['tau_path'][same][k]:.3g}), "
+            f"max over allowance = {ds.max():.3e}, max |dn| = {dn.max():.3e}")
+        tp = o["tau_path"][same]
+        if "tau_path" in g.dtype.names:
+            assert np.allclose(g["tau_path"][same], tp, rtol=10 * max(tol, 1e-6), atol=1e-6)
+    assert (ds <= 1.0).all(), f"Stokes mismatch beyond allowance ({ds.max():.3e})"
     assert (dn <= tol).all(), f"direction mismatch {dn.max():.3e} > {tol}"
     return frac
 

@@ -61,7 +61,7 @@ def test_config0_fp32(O):
     ctx = gpu_run(cfg, trace_packets=2000, transport_fp64=0)
     img_o, batches = oracle_batches(cfg)
     _, tr_o, _ = O.transport(cfg, p_end=2000, tally=False, traces=True)
-    compare_traces(ctx.traces(), tr_o, 1e-5, 0.99, "sphere32 fp32")
+    compare_traces(ctx.traces(), tr_o, 1e-5, 0.99, "sphere32 fp32", tau_coef=1e-6)
     compare_images_stat(ctx.images()[0], img_o, batches, label="sphere32 fp32")
 
 
@@ -86,7 +86,7 @@ def test_aligned_slab_clump(O):
     ctx = gpu_run(cfg, trace_packets=3000)
     _, tr_o, st_o = O.transport(cfg, p_end=3000, tally=False, traces=True)
     tr_g = ctx.traces()
-    compare_traces(tr_g, tr_o, 1e-5, 0.98, "slab_clump fp32")
+    compare_traces(tr_g, tr_o, 1e-5, 0.98, "slab_clump fp32", tau_coef=1e-6)
     s = tr_g["stokes"]
     assert (s[:, 0] * (1 + 1e-5) >= np.sqrt((s[:, 1:] ** 2).sum(1))).all()
     img_o, batches = oracle_batches(cfg)
@@ -104,7 +104,7 @@ def test_disk_small_images(O):
     cfg = W.flared_disk(n=64, packets=40000, npix=64)
     ctx = gpu_run(cfg, trace_packets=4000)
     _, tr_o, _ = O.transport(cfg, p_end=4000, tally=False, traces=True)
-    compare_traces(ctx.traces(), tr_o, 1e-5, 0.98, "disk64 fp32")
+    compare_traces(ctx.traces(), tr_o, 1e-5, 0.98, "disk64 fp32", tau_coef=1e-6)
     img_o, batches = oracle_batches(cfg)
     compare_images_stat(ctx.images()[0], img_o, batches, label="disk64 fp32")
 
@@ -122,7 +122,7 @@ def test_disk_full_size_sampled(O):
     tr_g = ctx.traces()
     ids = np.arange(0, 100_000_000, 100_000, dtype=np.uint64)
     tr_o = O.trace_packets(cfg, ids)
-    compare_traces(tr_g, tr_o, 1e-5, 0.98, "disk256 sampled")
+    compare_traces(tr_g, tr_o, 1e-5, 0.98, "disk256 sampled", tau_coef=1e-6)
     img = ctx.images()[0]
     assert np.isfinite(img).all()
     assert stokes_bound(img, 1e-6)
@@ -184,7 +184,7 @@ def test_batched_wavelengths(O):
             assert np.all(img_g[lam] == 0)
             continue
         _, tr_o, _ = O.transport(cfg, lam=lam, p_end=min(n, 500), tally=False, traces=True)
-        compare_traces(tr[lam][: min(n, 500)], tr_o, 1e-5, 0.98, f"batched lam={lam}")
+        compare_traces(tr[lam][: min(n, 500)], tr_o, 1e-5, 0.98, f"batched lam={lam}", tau_coef=1e-6)
         img_o, batches = oracle_batches(cfg, nb=6, lam=lam)
         compare_images_stat(img_g[lam], img_o, batches, label=f"batched lam={lam}")
 
