@@ -1,0 +1,167 @@
+"""Benchmark: Stokes packets/s of two-step polarized Monte Carlo imaging on the
+256^3 flared protoplanetary disk (1e8 packets per step, 8 inclinations,
+256x256 I/Q/U/V maps), on one MI355X.
+
+One step = one whole pass of the path over the workload: the persistent
+transport kernel (emission, cell marching, analytic dichroic extinction,
+coherency tally, scattering, roulette) for all packets, then the imaging
+ray-march for all views.  Inputs (density grid) are resident in HBM before
+the timed region; images stay on the device.
+
+Prints one JSON line (see the "metric" fields below) with a "roofline"
+object for the dominant kernel (transport) and a "cpu_baseline" object (the
+FP64 oracle timed on a bounded sample of the same workload on the host).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Stokes packets/s at 256^3 disk; packets to fixed Q/U error, plain vs denoised"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per cell step of the transport kernel: the density gather
+# (4 B) and the read-modify-write of the cell's 9 FP64 coherency components
+# (9 x 8 B read + 9 x 8 B written)
+BYTES_PER_STEP_SPHERE = 4 + 2 * 9 * 8
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--packets", type=int, default=100_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=100000,
+                    help="packets of the oracle's timed sample")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a device-to-device copy of this size (counter calibration)")
+    ap.add_argument("--block-size", type=int, default=0)
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    return ap.parse_args()
+
+
+def copy_calibration(mib: int) -> None:
+    """A plain device-to-device copy of known size, so that rocprofv3's
+    FETCH_SIZE / WRITE_SIZE can be converted to bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 4, "launches": 3}))
+
+
+def cpu_baseline(cfg, sample: int):
+    """The oracle as it stands, on the host cores: step 1 for the first
+    `sample` packets of the same run (same weights and streams), step 2 once
+    for all views; scaled to the whole job's packet count."""
+    from oracle import oracle as O
+    nth = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    N = int(cfg["packets"][0])
+    t0 = time.perf_counter()
+    S, _, st = O.transport(cfg, p_end=sample, n_total=N, nthreads=nth)
+    t1 = time.perf_counter()
+    O.image(cfg, S)
+    t2 = time.perf_counter()
+    del S
+    step1, step2 = t1 - t0, t2 - t1
+    job_s = step1 * (N / sample) + step2
+    return {"value": N / job_s, "unit": "packets/s", "cores": nth, "kind": "oracle",
+            "sample": f"first {sample} packets of the {N}-packet run (step 1, {step1:.1f} s, "
+                      f"scaled by {N // sample}) + step 2 for all {len(cfg['views'])} views "
+                      f"({step2:.1f} s), FP64, {nth} OpenMP threads"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the path shards by "
+              "packet ranges across GPUs but this build runs on one device", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration_mib:
+        copy_calibration(args.copy_calibration_mib)
+        return
+
+    import numpy as np
+    import torch
+
+    from paper_2512_01283_amd import polrad as P
+    from paper_2512_01283_amd import workloads as W
+
+    cfg = W.flared_disk(packets=args.packets)
+    ctx = P.Context(0).load(cfg)
+    stream = torch.cuda.current_stream()
+    opts = dict(block_size=args.block_size, blocks_per_cu=args.blocks_per_cu)
+
+    for w in range(args.warmup):
+        ctx.run(stream=stream, **opts)
+        print(f"warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    ms_t, ms_i, steps = [], [], []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ctx.run(stream=stream, **opts)
+        st = ctx.stats()
+        ms_t.append(st["ms_transport"])
+        ms_i.append(st["ms_image"])
+        steps.append(st["cell_steps"])
+        print(f"step {k + 1}/{args.steps}: transport {st['ms_transport']:.1f} ms, imaging "
+              f"{st['ms_image']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    ms_per_step = 1000.0 * elapsed / args.steps
+    packets = args.packets
+    value = packets * args.steps / elapsed
+    img = ctx.images()
+    assert np.isfinite(img).all()
+    avg_t = float(np.mean(ms_t))
+    bytes_launch = float(np.mean(steps)) * BYTES_PER_STEP_SPHERE
+    achieved = bytes_launch / (avg_t * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "packets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "flared disk 256^3, 1e8 packets, 8 inclinations, 256x256 IQUV maps",
+                   "grid": 256, "packets": packets, "views": 8, "npix": 256,
+                   "midplane_tau": 1.0e4, "albedo": 0.5, "grains": "Rayleigh spheres",
+                   "transport": "fp32, fp64 coherency tally", "seed": cfg["opts"]["seed"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "detail": {"kernel": "k_transport<float,false,true>",
+                   "transport_ms": avg_t, "imaging_ms": float(np.mean(ms_i)),
+                   "cell_steps_per_launch": float(np.mean(steps)),
+                   "cell_steps_per_s": float(np.mean(steps)) / (avg_t * 1e-3),
+                   "algorithmic_bytes_per_cell_step": BYTES_PER_STEP_SPHERE,
+                   "scatterings": st["scatterings"], "rr_kills": st["rr_kills"]},
+    }
+    if not args.no_cpu_baseline:
+        print("timing the oracle on a bounded sample ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample)
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
