@@ -27,10 +27,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Stokes packets/s at 256^3 disk; packets to fixed Q/U error, plain vs denoised"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per cell step of the transport kernel: the density gather
-# (4 B) and the read-modify-write of the cell's 9 FP64 coherency components
-# (9 x 8 B read + 9 x 8 B written)
-BYTES_PER_STEP_SPHERE = 4 + 2 * 9 * 8
+# algorithmic bytes per cell step of the transport kernel on Rayleigh spheres:
+# the density gather (4 B) and the read-modify-write of the cell's 6 FP64
+# coherency components (6 x 8 B read + 6 x 8 B written; spheres never create
+# circular polarisation, so the 3 imaginary components are identically zero)
+BYTES_PER_STEP_SPHERE = 4 + 2 * 6 * 8
 
 
 def parse():

@@ -43,6 +43,8 @@ struct kp_ctx {
   double* d_tally = nullptr;
   size_t tally_n = 0;      // doubles allocated
   int tally_lambda = 0;    // wavelengths of the last step 1
+  int tally_ts = 16;       // per-cell stride (doubles) of the last step 1
+  int tally_nc = 9;        // components kept per cell
   bool have_tally = false;
   double* d_images = nullptr;
   size_t images_n = 0;
@@ -414,7 +416,10 @@ kp_status kp_transport(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, vo
 
   KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
-  const size_t tally_need = (size_t)nl * ctx->ncell * 9;
+  bool all_sphere = true;
+  for (int l = 0; l < nl; ++l) all_sphere = all_sphere && is_sphere(ctx->dust[l]);
+  const int ts = tally_stride(all_sphere);
+  const size_t tally_need = (size_t)nl * ctx->ncell * ts;
   const size_t trace_need = (size_t)nl * o->trace_packets;
   size_t free_b = 0, total_b = 0;
   KP_HIP(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
@@ -491,6 +496,8 @@ kp_status kp_transport(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, vo
   KP_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]), "event timing");
   r.ms_transport = ms;
   ctx->tally_lambda = nl;
+  ctx->tally_ts = ts;
+  ctx->tally_nc = tally_components(all_sphere);
   ctx->have_tally = true;
   ctx->have_images = false;
   ctx->traces_valid = trace_need;
@@ -570,10 +577,15 @@ kp_status kp_get_images_device(kp_ctx* ctx, double* d_out, size_t n, void* strea
 kp_status kp_get_tally(kp_ctx* ctx, double* out, size_t n) {
   if (!ctx) return KP_ERR_ARG;
   if (!ctx->have_tally) return fail(ctx, KP_ERR_STATE, "no tally: call kp_transport first");
-  const size_t need = (size_t)ctx->tally_lambda * ctx->ncell * 9;
+  const size_t rows = (size_t)ctx->tally_lambda * ctx->ncell;
+  const size_t need = rows * 9;
   if (!out || n != need) return fail(ctx, KP_ERR_ARG, "destination must hold %zu doubles", need);
   KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-  KP_HIP(hipMemcpy(out, ctx->d_tally, n * sizeof(double), hipMemcpyDeviceToHost), "tally copy");
+  KP_HIP(hipMemcpy2D(out, 9 * sizeof(double), ctx->d_tally, ctx->tally_ts * sizeof(double),
+                     ctx->tally_nc * sizeof(double), rows, hipMemcpyDeviceToHost), "tally copy");
+  if (ctx->tally_nc < 9)
+    for (size_t r = 0; r < rows; ++r)
+      for (int k = ctx->tally_nc; k < 9; ++k) out[r * 9 + k] = 0.0;
   return KP_OK;
 }
 

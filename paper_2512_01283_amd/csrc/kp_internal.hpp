@@ -89,6 +89,11 @@ struct ImageArgs {
   uint64_t ncell;
 };
 
+// Tally layout [lambda][cell][stride] FP64: 6 reals (stride 8, one 64-B block
+// per cell) when every wavelength has spherical grains, else 9 (stride 16).
+inline int tally_components(bool sphere) { return sphere ? 6 : 9; }
+inline int tally_stride(bool sphere) { return sphere ? 8 : 16; }
+
 // launchers (kp_kernels.hip)
 hipError_t launch_transport(const TransportArgs& a, bool fp64, bool aligned, bool sphere,
                             int blocks, int block_size, hipStream_t s);

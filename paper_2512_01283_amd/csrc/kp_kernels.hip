@@ -15,10 +15,15 @@
 // each cell (3x3 Hermitian, 9 reals): because every scatterer here is a
 // dipole, the source toward any camera is a fixed linear map of it (formed in
 // step 2), so one tally serves all views and wavelengths' views at 9 FP64
-// atomics per segment instead of 4 per view.  A lane keeps the running sum
-// for its current cell in registers and flushes it with FP64 atomics only
-// when it moves to another cell (multiple scattering inside a thick cell, and
-// consecutive packets of a lane leaving the source cell, cost no atomics).
+// atomics per segment instead of 4 per view (6 when no circular polarisation
+// can arise, i.e. for spheres).  A lane keeps the running sum for its current
+// cell in registers and hands it over only when it moves to another cell
+// (multiple scattering inside a thick cell costs no atomics).  Hand-overs are
+// flushed cooperatively by the whole wavefront: the pending sums are staged in
+// LDS and re-issued so that one atomic instruction carries the contiguous
+// components of ~7-10 cells, each cell's block aligned to one cache line
+// (64 B for 6 reals, 128 B for 9) -- memory-side FP64 atomics are charged per
+// line request, so this is ~5x cheaper than one cell per lane.
 #include "kp_device.hpp"
 #include "kp_internal.hpp"
 
@@ -56,7 +61,9 @@ template <typename R> __device__ __forceinline__ Cx<R> cscale(Cx<R> a, R s) { re
 
 template <typename R>
 struct Packet {
-  R fx, fy, fz;       // position inside the cell, cell units [0,1]
+  double fx, fy, fz;  // position inside the cell, cell units [0,1] (always FP64:
+                      // an absolute rounding of 1e-7 cell would cost 1e-7 of
+                      // the cell's optical depth, up to 1e-4 in thick cells)
   R nx, ny, nz;       // direction
   R I, Q, U, V;       // Stokes vector in the lab basis of n
   R tau;              // remaining scattering optical depth
@@ -124,7 +131,7 @@ __device__ bool init_packet(Packet<R>& p, uint64_t g, const TransportArgs& a) {
   const double pos[3] = {a.sx, a.sy, a.sz}, org[3] = {a.x0, a.y0, a.z0};
   const R dir[3] = {p.nx, p.ny, p.nz};
   int ci[3];
-  R fr[3];
+  double fr[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     double t = (pos[k] - org[k]) / a.dx;
@@ -133,7 +140,7 @@ __device__ bool init_packet(Packet<R>& p, uint64_t g, const TransportArgs& a) {
     int i = (int)fl;
     if (f == 0.0 && dir[k] < (R)0) { i -= 1; f = 1.0; }
     ci[k] = i;
-    fr[k] = (R)f;
+    fr[k] = f;
   }
   p.ci = ci[0]; p.cj = ci[1]; p.ck = ci[2];
   p.fx = fr[0]; p.fy = fr[1]; p.fz = fr[2];
@@ -145,9 +152,9 @@ __device__ bool init_packet(Packet<R>& p, uint64_t g, const TransportArgs& a) {
 // e1 = theta_hat(n), e2 = phi_hat(n), times the weight w.  Output order: real
 // xx yy zz xy xz yz, imaginary yz zx xy (the antisymmetric part equals
 // -V/2 [n]_x in this basis).
-template <typename R>
+template <typename R, int NC>
 __device__ __forceinline__ void coherency(const V3<R>& n, R JI, R JQ, R JU, R JV, R w,
-                                          R out[9]) {
+                                          R out[NC]) {
   V3<R> e1, e2;
   basis(n, e1, e2);
   R a = (R)0.5 * (JI + JQ) * w, b = (R)0.5 * (JI - JQ) * w, u = (R)0.5 * JU * w;
@@ -158,17 +165,54 @@ __device__ __forceinline__ void coherency(const V3<R>& n, R JI, R JQ, R JU, R JV
   out[3] = a * e1.x * e1.y + b * e2.x * e2.y + u * (e1.x * e2.y + e2.x * e1.y);
   out[4] = a * e1.x * e1.z + u * (e2.x * e1.z);
   out[5] = a * e1.y * e1.z + u * (e2.y * e1.z);
-  out[6] = v * n.x;
-  out[7] = v * n.y;
-  out[8] = v * n.z;
+  if (NC > 6) {
+    out[NC > 6 ? 6 : 0] = v * n.x;
+    out[NC > 7 ? 7 : 0] = v * n.y;
+    out[NC > 8 ? 8 : 0] = v * n.z;
+  }
 }
 
-__device__ __forceinline__ void flush_acc(double* tally, int64_t key, const double acc[9]) {
-  if (key < 0) return;
-  double* dst = tally + (uint64_t)key * 9u;
+// Components of the tally kept per cell and the per-cell stride in doubles:
+// spheres never create circular polarisation from unpolarised light, so the
+// antisymmetric (V) part of the coherency is identically zero.
+template <bool SPHERE> struct TallyShape {
+  static constexpr int NC = SPHERE ? 6 : 9;
+  static constexpr int TS = SPHERE ? 8 : 16;
+};
+
+// Wave-cooperative flush of the lanes whose `need` is set: every such lane
+// stages (key, NC values) in this wavefront's LDS area; then lane L adds
+// component L % NC of staged entry L / NC, so one atomic instruction covers
+// 64 / NC whole cells.  Must be reached by all lanes of the wavefront.
+template <int NC, int TS>
+__device__ __forceinline__ void wave_flush(bool need, int64_t key, const double acc[NC],
+                                           double* tally, double* sv, long long* sk, int lane) {
+  const unsigned long long mask = __ballot(need);
+  if (mask == 0ull) return;
+  const int n = __popcll(mask);
+  if (need) {
+    const int r = __popcll(mask & ((1ull << lane) - 1ull));
 #pragma unroll
-  for (int k = 0; k < 9; ++k)
-    if (acc[k] != 0.0) unsafeAtomicAdd(dst + k, acc[k]);
+    for (int k = 0; k < NC; ++k) sv[r * NC + k] = acc[k];
+    sk[r] = key;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  constexpr int G = 64 / NC;
+  const int slot = lane / NC, k = lane - slot * NC;
+  if (slot < G) {
+    for (int base = 0; base < n; base += G) {
+      const int e = base + slot;
+      if (e < n) {
+        const double v = sv[e * NC + k];
+        if (v != 0.0) unsafeAtomicAdd(tally + (uint64_t)sk[e] * TS + k, v);
+      }
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Dimensionless extinction coefficients for a direction with cos(theta') =
@@ -281,22 +325,26 @@ __device__ bool scatter(Packet<R>& p, const Quat<R>& q, const DustDev& D, uint64
 // scattering source of Sec. 2.3), then a scattering event or the crossing
 // into the next cell, then Russian roulette.  Returns 0 or an end kind.
 template <typename R, bool ALIGNED, bool SPHERE>
-__device__ uint32_t step(Packet<R>& p, const TransportArgs& a, int64_t& acc_key, double acc[9]) {
+__device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_t& key,
+                         R cc[TallyShape<SPHERE>::NC]) {
+  constexpr int NC = TallyShape<SPHERE>::NC;
   const uint64_t c = (uint64_t)p.ci + (uint64_t)a.nx * ((uint64_t)p.cj + (uint64_t)a.ny * p.ck);
   p.last = (int64_t)c;
   if (p.events >= a.max_events) {
     p.hash = hash_event(p.hash, END_BUDGET, c);
     return END_BUDGET;
   }
-  const R inf = k_inf<R>();
-  R tx = p.nx > (R)0 ? ((R)1 - p.fx) / p.nx : (p.nx < (R)0 ? -p.fx / p.nx : inf);
-  R ty = p.ny > (R)0 ? ((R)1 - p.fy) / p.ny : (p.ny < (R)0 ? -p.fy / p.ny : inf);
-  R tz = p.nz > (R)0 ? ((R)1 - p.fz) / p.nz : (p.nz < (R)0 ? -p.fz / p.nz : inf);
-  R t = tx;
+  const double inf = __builtin_huge_val();
+  const double dnx = (double)p.nx, dny = (double)p.ny, dnz = (double)p.nz;
+  double tx = dnx > 0.0 ? (1.0 - p.fx) / dnx : (dnx < 0.0 ? -p.fx / dnx : inf);
+  double ty = dny > 0.0 ? (1.0 - p.fy) / dny : (dny < 0.0 ? -p.fy / dny : inf);
+  double tz = dnz > 0.0 ? (1.0 - p.fz) / dnz : (dnz < 0.0 ? -p.fz / dnz : inf);
+  double td = tx;
   int axis = 0;
-  if (ty < t) { t = ty; axis = 1; }
-  if (tz < t) { t = tz; axis = 2; }
-  if (!(t < inf)) return END_NUMERIC;
+  if (ty < td) { td = ty; axis = 1; }
+  if (tz < td) { td = tz; axis = 2; }
+  if (!(td < inf)) return END_NUMERIC;
+  const R t = (R)td;
   const DustDev& D = a.dust[p.lam];
   const R rho = (R)a.rho[c];
   const R kb = rho * (R)D.ks_cell;
@@ -365,18 +413,9 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, int64_t& acc_key,
     }
     p.e_abs += (double)(Ib - p.I);
     if (kb > (R)0) {
-      R cc[9];
-      coherency(n, JI, JQ, JU, JV, kb, cc);
-      const int64_t key = (int64_t)((uint64_t)p.lam * a.ncell + c);
-      if (key != acc_key) {
-        flush_acc(a.tally, acc_key, acc);
-        acc_key = key;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) acc[k] = (double)cc[k];
-      } else {
-#pragma unroll
-        for (int k = 0; k < 9; ++k) acc[k] += (double)cc[k];
-      }
+      coherency<R, NC>(n, JI, JQ, JU, JV, kb, cc);
+      key = (int64_t)((uint64_t)p.lam * a.ncell + c);
+      has = true;
     }
   }
   if (!(p.I > (R)0)) {
@@ -387,26 +426,27 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, int64_t& acc_key,
     return END_RR_KILL;
   }
   if (scat) {
-    p.fx = fmin((R)1, fmax((R)0, p.fx + tl * p.nx));
-    p.fy = fmin((R)1, fmax((R)0, p.fy + tl * p.ny));
-    p.fz = fmin((R)1, fmax((R)0, p.fz + tl * p.nz));
+    const double dl = (double)tl;
+    p.fx = fmin(1.0, fmax(0.0, p.fx + dl * dnx));
+    p.fy = fmin(1.0, fmax(0.0, p.fy + dl * dny));
+    p.fz = fmin(1.0, fmax(0.0, p.fz + dl * dnz));
     if (!scatter<R, ALIGNED, SPHERE>(p, q, D, a.seed)) return END_NUMERIC;
     p.events++;
     p.hash = hash_event(p.hash, EV_SCATTER, c);
     p.tau = -k_log(next_uniform(p, a.seed));
   } else {
-    if (axis != 0) p.fx = fmin((R)1, fmax((R)0, p.fx + t * p.nx));
-    if (axis != 1) p.fy = fmin((R)1, fmax((R)0, p.fy + t * p.ny));
-    if (axis != 2) p.fz = fmin((R)1, fmax((R)0, p.fz + t * p.nz));
+    if (axis != 0) p.fx = fmin(1.0, fmax(0.0, p.fx + td * dnx));
+    if (axis != 1) p.fy = fmin(1.0, fmax(0.0, p.fy + td * dny));
+    if (axis != 2) p.fz = fmin(1.0, fmax(0.0, p.fz + td * dnz));
     bool out;
     if (axis == 0) {
-      if (p.nx > (R)0) { p.ci++; p.fx = (R)0; } else { p.ci--; p.fx = (R)1; }
+      if (dnx > 0.0) { p.ci++; p.fx = 0.0; } else { p.ci--; p.fx = 1.0; }
       out = p.ci < 0 || p.ci >= a.nx;
     } else if (axis == 1) {
-      if (p.ny > (R)0) { p.cj++; p.fy = (R)0; } else { p.cj--; p.fy = (R)1; }
+      if (dny > 0.0) { p.cj++; p.fy = 0.0; } else { p.cj--; p.fy = 1.0; }
       out = p.cj < 0 || p.cj >= a.ny;
     } else {
-      if (p.nz > (R)0) { p.ck++; p.fz = (R)0; } else { p.ck--; p.fz = (R)1; }
+      if (dnz > 0.0) { p.ck++; p.fz = 0.0; } else { p.ck--; p.fz = 1.0; }
       out = p.ck < 0 || p.ck >= a.nz;
     }
     if (out) {
@@ -474,19 +514,25 @@ __device__ void finish(const Packet<R>& p, uint32_t end, const TransportArgs& a,
 
 template <typename R, bool ALIGNED, bool SPHERE>
 __global__ void __launch_bounds__(256) k_transport(TransportArgs a) {
+  constexpr int NC = TallyShape<SPHERE>::NC, TS = TallyShape<SPHERE>::TS;
   __shared__ unsigned long long sc[SC_N];
   __shared__ double se[SE_N];
+  __shared__ double s_val[4 * 64 * NC];   // flush staging, one area per wavefront
+  __shared__ long long s_key[4 * 64];
   if (threadIdx.x < SC_N) sc[threadIdx.x] = 0ull;
   if (threadIdx.x < SE_N) se[threadIdx.x] = 0.0;
   __syncthreads();
 
+  const int lane = (int)__lane_id();
+  const int wv = (int)(threadIdx.x >> 6);
+  double* sv = s_val + wv * 64 * NC;
+  long long* sk = s_key + wv * 64;
   Packet<R> p;
   bool active = false, exhausted = false;
   int64_t acc_key = -1;
-  double acc[9];
+  double acc[NC];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) acc[k] = 0.0;
-  const int lane = (int)__lane_id();
+  for (int k = 0; k < NC; ++k) acc[k] = 0.0;
 
   while (true) {
     if (!exhausted) {
@@ -498,7 +544,7 @@ __global__ void __launch_bounds__(256) k_transport(TransportArgs a) {
         if (lane == leader) base = atomicAdd(a.counter, (unsigned long long)nidle);
         base = __shfl(base, leader);
         if (!active) {
-          const unsigned long long below = lane ? (idle & ((1ull << lane) - 1ull)) : 0ull;
+          const unsigned long long below = idle & ((1ull << lane) - 1ull);
           const unsigned long long g = base + (unsigned long long)__popcll(below);
           if (g < a.total) {
             if (init_packet(p, g, a)) active = true;
@@ -509,15 +555,30 @@ __global__ void __launch_bounds__(256) k_transport(TransportArgs a) {
       }
     }
     if (!__any(active)) break;
+    bool has = false;
+    int64_t key = -1;
+    R cc[NC];
     if (active) {
-      const uint32_t end = step<R, ALIGNED, SPHERE>(p, a, acc_key, acc);
+      const uint32_t end = step<R, ALIGNED, SPHERE>(p, a, has, key, cc);
       if (end) {
         finish(p, end, a, sc, se);
         active = false;
       }
     }
+    // a lane entering another (wavelength, cell) hands its running sum over
+    wave_flush<NC, TS>(has && key != acc_key && acc_key >= 0, acc_key, acc, a.tally, sv, sk, lane);
+    if (has) {
+      if (key == acc_key) {
+#pragma unroll
+        for (int k = 0; k < NC; ++k) acc[k] += (double)cc[k];
+      } else {
+        acc_key = key;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) acc[k] = (double)cc[k];
+      }
+    }
   }
-  flush_acc(a.tally, acc_key, acc);
+  wave_flush<NC, TS>(acc_key >= 0, acc_key, acc, a.tally, sv, sk, lane);
   __syncthreads();
   if (threadIdx.x < SC_N) atomicAdd(&(&a.stats->cell_steps)[threadIdx.x], sc[threadIdx.x]);
   if (threadIdx.x < SE_N) unsafeAtomicAdd(&(&a.stats->e_emitted)[threadIdx.x], se[threadIdx.x]);
@@ -635,9 +696,12 @@ __global__ void __launch_bounds__(256) k_image(ImageArgs a) {
           // source toward the camera from the incident coherency C of the
           // cell: rho'_ij = h_i^T C conj(h_j), h_i = alpha e_i with the lab
           // polarizability alpha = a_perp 1 + (a_par - a_perp) b b^T.
-          const double* T = a.tally + ((uint64_t)lam * a.ncell + c) * 9;
+          constexpr int TS = TallyShape<SPHERE>::TS;
+          const double* T = a.tally + ((uint64_t)lam * a.ncell + c) * TS;
           const double Cr[3][3] = {{T[0], T[3], T[4]}, {T[3], T[1], T[5]}, {T[4], T[5], T[2]}};
-          const double Ci[3][3] = {{0.0, T[8], -T[7]}, {-T[8], 0.0, T[6]}, {T[7], -T[6], 0.0}};
+          double i6 = 0.0, i7 = 0.0, i8 = 0.0;
+          if (TallyShape<SPHERE>::NC == 9) { i6 = T[6]; i7 = T[7]; i8 = T[8]; }
+          const double Ci[3][3] = {{0.0, i8, -i7}, {-i8, 0.0, i6}, {i7, -i6, 0.0}};
           Cx<double> h1[3], h2[3];
           const double ev1[3] = {e1.x, e1.y, e1.z}, ev2[3] = {e2.x, e2.y, e2.z};
           if (SPHERE) {
