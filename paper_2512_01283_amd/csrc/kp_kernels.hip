@@ -61,12 +61,16 @@ template <typename R> __device__ __forceinline__ Cx<R> cscale(Cx<R> a, R s) { re
 
 template <typename R>
 struct Packet {
-  double fx, fy, fz;  // position inside the cell, cell units [0,1] (always FP64:
-                      // an absolute rounding of 1e-7 cell would cost 1e-7 of
-                      // the cell's optical depth, up to 1e-4 in thick cells)
-  R nx, ny, nz;       // direction
+  // Geometry is FP64 in every variant: position inside the cell (cell units),
+  // direction and remaining scattering depth.  A packet's path is sensitive
+  // to them well beyond their own size -- a scattering depth off by 3e-7
+  // moves a scattering point inside a tenuous cell (rho kappa dx ~ 1e-3) by
+  // 3e-4 cell, which a later cell of optical depth 1e3 turns into a 0.3 %
+  // weight error -- so only the polarisation arithmetic runs in R.
+  double fx, fy, fz;
+  double nx, ny, nz;
+  double tau;
   R I, Q, U, V;       // Stokes vector in the lab basis of n
-  R tau;              // remaining scattering optical depth
   R w0;               // initial weight
   R tau_path;         // sum of |continuous extinction exponent| along the path
   R u0, u1, u2, u3;   // uniforms of the Philox block `blk`
@@ -110,17 +114,17 @@ __device__ bool init_packet(Packet<R>& p, uint64_t g, const TransportArgs& a) {
   p.pid = g - a.dust[lo].first;
   p.draw = 0;
   p.blk = 0xffffffffu;
-  R u0 = next_uniform(p, a.seed), u1 = next_uniform(p, a.seed);
+  const double u0 = (double)next_uniform(p, a.seed), u1 = (double)next_uniform(p, a.seed);
   if (a.src_kind == 1) {
-    p.nx = (R)a.dx_; p.ny = (R)a.dy_; p.nz = (R)a.dz_;
+    p.nx = a.dx_; p.ny = a.dy_; p.nz = a.dz_;
   } else {
-    R mu = (R)2 * u0 - (R)1;
-    R s = k_sqrt(fmax((R)0, (R)1 - mu * mu));
-    R sp, cp;
-    k_sincospi((R)2 * u1, &sp, &cp);
+    const double mu = 2.0 * u0 - 1.0;
+    const double s = sqrt(fmax(0.0, 1.0 - mu * mu));
+    double sp, cp;
+    sincospi(2.0 * u1, &sp, &cp);
     p.nx = s * cp; p.ny = s * sp; p.nz = mu;
   }
-  p.tau = -k_log(next_uniform(p, a.seed));
+  p.tau = -log((double)next_uniform(p, a.seed));
   p.w0 = (R)a.dust[lo].w0;
   p.I = p.w0; p.Q = (R)0; p.U = (R)0; p.V = (R)0;
   p.e_abs = 0.0; p.e_scat = 0.0; p.e_gain = 0.0;
@@ -129,7 +133,7 @@ __device__ bool init_packet(Packet<R>& p, uint64_t g, const TransportArgs& a) {
   p.hash = 14695981039346656037ull;
   p.last = -1;
   const double pos[3] = {a.sx, a.sy, a.sz}, org[3] = {a.x0, a.y0, a.z0};
-  const R dir[3] = {p.nx, p.ny, p.nz};
+  const double dir[3] = {p.nx, p.ny, p.nz};
   int ci[3];
   double fr[3];
 #pragma unroll
@@ -138,7 +142,7 @@ __device__ bool init_packet(Packet<R>& p, uint64_t g, const TransportArgs& a) {
     double fl = floor(t);
     double f = t - fl;
     int i = (int)fl;
-    if (f == 0.0 && dir[k] < (R)0) { i -= 1; f = 1.0; }
+    if (f == 0.0 && dir[k] < 0.0) { i -= 1; f = 1.0; }
     ci[k] = i;
     fr[k] = f;
   }
@@ -234,8 +238,9 @@ __device__ __forceinline__ void alphas(const DustDev& D, R ct, R& a1, R& a2, R& 
 // u * bound <= [P s]_I, output rescaled to the scattered power, then carried
 // back to the lab frame.  Returns false on a numerical failure.
 template <typename R, bool ALIGNED, bool SPHERE>
-__device__ bool scatter(Packet<R>& p, const Quat<R>& q, const DustDev& D, uint64_t seed) {
-  const V3<R> n{p.nx, p.ny, p.nz};
+__device__ bool scatter(Packet<R>& p, const Quat<R>& q, const V3<double>& bdir,
+                        const DustDev& D, uint64_t seed) {
+  const V3<R> n{(R)p.nx, (R)p.ny, (R)p.nz};
   V3<R> ng = n;
   R c2 = (R)1, s2 = (R)0;
   if (ALIGNED) {
@@ -256,11 +261,12 @@ __device__ bool scatter(Packet<R>& p, const Quat<R>& q, const DustDev& D, uint64
   const Cx<R> ap{(R)D.ap_re, (R)D.ap_im};
   const Cx<R> dd{(R)(D.aa_re - D.ap_re), (R)(D.aa_im - D.ap_im)};
   Cx<R> J11, J12, J21, J22;
-  R mu = 0, smu = 0, cph = 1, sph = 0, Iout = 0;
+  R mu = 0, smu = 0, cph = 1, sph = 0, Iout = 0, umu = 0, uph = 0;
   bool ok = false;
   for (int trial = 0; trial < 100000; ++trial) {
-    mu = (R)2 * next_uniform(p, seed) - (R)1;
-    R uph = next_uniform(p, seed);
+    umu = next_uniform(p, seed);
+    mu = (R)2 * umu - (R)1;
+    uph = next_uniform(p, seed);
     R ua = next_uniform(p, seed);
     p.trials++;
     smu = k_sqrt(fmax((R)0, (R)1 - mu * mu));
@@ -303,14 +309,20 @@ __device__ bool scatter(Packet<R>& p, const Quat<R>& q, const DustDev& D, uint64
   }
   R scale = sig / So;
   So = sig; Qo *= scale; Uo *= scale; Vo *= scale;
-  V3<R> mg{smu * cph, smu * sph, mu};
-  V3<R> m = mg;
+  // the accepted direction itself is formed in FP64 from the same uniforms
+  const double mud = 2.0 * (double)umu - 1.0;
+  const double smud = sqrt(fmax(0.0, 1.0 - mud * mud));
+  double sphd, cphd;
+  sincospi(2.0 * (double)uph, &sphd, &cphd);
+  if (smud * smud <= KP_POLE2) { cphd = 1.0; sphd = 0.0; }
+  const V3<double> mgd{smud * cphd, smud * sphd, mud};
+  V3<double> md = mgd;
   R cm = (R)1, sm = (R)0;
   if (ALIGNED) {
-    m = from_grain(q, mg);
-    eta2(q, m, mg, cm, sm);
+    md = from_grain(grain_quat(bdir), mgd);
+    eta2(q, V3<R>{(R)md.x, (R)md.y, (R)md.z}, V3<R>{(R)mgd.x, (R)mgd.y, (R)mgd.z}, cm, sm);
   }
-  p.nx = m.x; p.ny = m.y; p.nz = m.z;
+  p.nx = md.x; p.ny = md.y; p.nz = md.z;
   p.e_scat += (double)(sig - I);
   p.I = So;
   p.Q = cm * Qo - sm * Uo;
@@ -335,7 +347,7 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
     return END_BUDGET;
   }
   const double inf = __builtin_huge_val();
-  const double dnx = (double)p.nx, dny = (double)p.ny, dnz = (double)p.nz;
+  const double dnx = p.nx, dny = p.ny, dnz = p.nz;
   double tx = dnx > 0.0 ? (1.0 - p.fx) / dnx : (dnx < 0.0 ? -p.fx / dnx : inf);
   double ty = dny > 0.0 ? (1.0 - p.fy) / dny : (dny < 0.0 ? -p.fy / dny : inf);
   double tz = dnz > 0.0 ? (1.0 - p.fz) / dnz : (dnz < 0.0 ? -p.fz / dnz : inf);
@@ -344,19 +356,23 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
   if (ty < td) { td = ty; axis = 1; }
   if (tz < td) { td = tz; axis = 2; }
   if (!(td < inf)) return END_NUMERIC;
-  const R t = (R)td;
   const DustDev& D = a.dust[p.lam];
-  const R rho = (R)a.rho[c];
-  const R kb = rho * (R)D.ks_cell;
-  R tl;
+  const double rhod = (double)a.rho[c];
+  const double kbd = rhod * D.ks_cell;
+  double tld;
   bool scat;
-  if (kb > (R)0 && p.tau < kb * t) { tl = p.tau / kb; scat = true; }
-  else { tl = t; p.tau -= kb * t; scat = false; }
+  if (kbd > 0.0 && p.tau < kbd * td) { tld = p.tau / kbd; scat = true; }
+  else { tld = td; p.tau -= kbd * td; scat = false; }
+  const R rho = (R)rhod, kb = (R)kbd, tl = (R)tld;
   p.steps++;
   Quat<R> q{(R)1, (R)0, (R)0, (R)0};
-  if (ALIGNED && rho > (R)0) q = grain_quat(V3<R>{(R)a.bx[c], (R)a.by[c], (R)a.bz[c]});
+  V3<double> bdir{0.0, 0.0, 1.0};
+  if (ALIGNED && rho > (R)0) {
+    bdir = V3<double>{(double)a.bx[c], (double)a.by[c], (double)a.bz[c]};
+    q = grain_quat(V3<R>{(R)bdir.x, (R)bdir.y, (R)bdir.z});
+  }
   if (rho > (R)0 && tl > (R)0) {
-    const V3<R> n{p.nx, p.ny, p.nz};
+    const V3<R> n{(R)p.nx, (R)p.ny, (R)p.nz};
     const R Ib = p.I;
     R JI, JQ, JU, JV;
     if (SPHERE && !ALIGNED) {
@@ -426,14 +442,13 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
     return END_RR_KILL;
   }
   if (scat) {
-    const double dl = (double)tl;
-    p.fx = fmin(1.0, fmax(0.0, p.fx + dl * dnx));
-    p.fy = fmin(1.0, fmax(0.0, p.fy + dl * dny));
-    p.fz = fmin(1.0, fmax(0.0, p.fz + dl * dnz));
-    if (!scatter<R, ALIGNED, SPHERE>(p, q, D, a.seed)) return END_NUMERIC;
+    p.fx = fmin(1.0, fmax(0.0, p.fx + tld * dnx));
+    p.fy = fmin(1.0, fmax(0.0, p.fy + tld * dny));
+    p.fz = fmin(1.0, fmax(0.0, p.fz + tld * dnz));
+    if (!scatter<R, ALIGNED, SPHERE>(p, q, bdir, D, a.seed)) return END_NUMERIC;
     p.events++;
     p.hash = hash_event(p.hash, EV_SCATTER, c);
-    p.tau = -k_log(next_uniform(p, a.seed));
+    p.tau = -log((double)next_uniform(p, a.seed));
   } else {
     if (axis != 0) p.fx = fmin(1.0, fmax(0.0, p.fx + td * dnx));
     if (axis != 1) p.fy = fmin(1.0, fmax(0.0, p.fy + td * dny));
