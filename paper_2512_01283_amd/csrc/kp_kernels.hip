@@ -383,30 +383,34 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
       JI = p.I * G; JQ = p.Q * G; JU = p.U * G; JV = p.V * G;
       p.I *= E; p.Q *= E; p.U *= E; p.V *= E;
     } else {
-      V3<R> ng = n;
+      // The exponents are differences of two cell-scale optical depths
+      // (rho kappa_ext alpha vs rho kappa_sca, each up to ~1e3 per cell), so
+      // the grain-frame direction, the alphas and the exponents are formed in
+      // FP64; the exponentials and the Stokes arithmetic run in R.
+      const V3<double> nd{p.nx, p.ny, p.nz};
+      V3<double> ngd = nd;
+      if (ALIGNED) ngd = to_grain(grain_quat(bdir), nd);
       R c2 = (R)1, s2 = (R)0;
-      if (ALIGNED) {
-        ng = to_grain(q, n);
-        eta2(q, n, ng, c2, s2);
-      }
-      R a1, a2, a3;
-      alphas<R, SPHERE>(D, ng.z, a1, a2, a3);
-      const R ke = rho * (R)D.ke_cell;
-      const R mA = ke * (a1 + a2) - kb, mB = ke * (a1 - a2) - kb, mU = ke * a1 - kb;
-      const R w = ke * a3;
-      p.tau_path += fabs(mU * tl);
+      if (ALIGNED) eta2(q, n, V3<R>{(R)ngd.x, (R)ngd.y, (R)ngd.z}, c2, s2);
+      double a1, a2, a3;
+      alphas<double, SPHERE>(D, ngd.z, a1, a2, a3);
+      const double ked = rhod * D.ke_cell;
+      const double xAd = (ked * (a1 + a2) - kbd) * tld, xBd = (ked * (a1 - a2) - kbd) * tld;
+      const double xUd = (ked * a1 - kbd) * tld, yd = ked * a3 * tld;
+      const R xA = (R)xAd, xB = (R)xBd, xU = (R)xUd;
+      p.tau_path += (R)fabs(xUd);
       const R Qg = c2 * p.Q + s2 * p.U, Ug = -s2 * p.Q + c2 * p.U;
       const R A = p.I + Qg, B = p.I - Qg;
-      const R gA = tl * phi1(mA * tl), gB = tl * phi1(mB * tl);
-      const R eA = k_exp(-mA * tl), eB = k_exp(-mB * tl);
+      const R gA = tl * phi1(xA), gB = tl * phi1(xB);
+      const R eA = k_exp(-xA), eB = k_exp(-xB);
       R JUg, JVg, Un, Vn;
-      if (w == (R)0) {
-        const R gU = tl * phi1(mU * tl), eU = k_exp(-mU * tl);
+      if (yd == 0.0) {
+        const R gU = tl * phi1(xU), eU = k_exp(-xU);
         JUg = Ug * gU; JVg = p.V * gU;
         Un = Ug * eU; Vn = p.V * eU;
       } else {
         // U + iV evolves as exp((-mU + i w) s)
-        const R x = -mU * tl, y = w * tl;
+        const R x = -xU, y = (R)yd;
         const R ex = k_exp(x), cy = k_cos(y), sy = k_sin(y), sh = k_sin((R)0.5 * y);
         const Cx<R> ez{ex * cy, ex * sy};
         const Cx<R> em1{k_expm1(x) * cy - (R)2 * sh * sh, ex * sy};

@@ -26,10 +26,16 @@ def O():
     return o
 
 
-def stokes_bound(img, rel=1e-9):
+def stokes_bound(img, rel=1e-9, floor=0.0):
+    """I >= |P| per pixel, up to `rel` of the pixel's I plus `floor` of the
+    view's largest I (FP32 tally contributions of fully polarised light seen
+    along its polarisation direction have I ~ 0 up to a rounding of order
+    1e-7 of the incident intensity)."""
     I = img[..., 0, :, :]
     P = np.sqrt(img[..., 1, :, :] ** 2 + img[..., 2, :, :] ** 2 + img[..., 3, :, :] ** 2)
-    return (I * (1 + rel) + 1e-300 >= P).all()
+    imax = np.abs(I).max(axis=(-1, -2), keepdims=True)
+    excess = P - I * (1 + rel) - floor * imax
+    return (excess <= 1e-300).all()
 
 
 def test_config0_fp64_path_by_path(O):
@@ -92,7 +98,7 @@ def test_aligned_slab_clump(O):
     img_o, batches = oracle_batches(cfg)
     img_g = ctx.images()[0]
     compare_images_stat(img_g, img_o, batches, label="slab_clump fp32")
-    assert stokes_bound(img_g, 1e-5)
+    assert stokes_bound(img_g, 1e-6, 1e-6)
     st = ctx.stats()
     bal = st["e_escaped"] + st["e_absorbed"] + st["e_rr_killed"] - st["e_rr_gained"] + st["e_budget"]
     assert abs(bal - st["e_emitted"] - st["e_scat_delta"]) < 1e-4 * st["e_emitted"]
@@ -125,7 +131,7 @@ def test_disk_full_size_sampled(O):
     compare_traces(tr_g, tr_o, 1e-5, 0.98, "disk256 sampled", tau_coef=1e-6)
     img = ctx.images()[0]
     assert np.isfinite(img).all()
-    assert stokes_bound(img, 1e-6)
+    assert stokes_bound(img, 1e-6, 1e-6)
     bal = st["e_escaped"] + st["e_absorbed"] + st["e_rr_killed"] - st["e_rr_gained"] + st["e_budget"]
     assert abs(bal - st["e_emitted"]) < 1e-5 * st["e_emitted"]
     assert st["packets"] == 100_000_000 and st["numeric"] == 0
