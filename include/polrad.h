@@ -105,7 +105,14 @@ typedef struct {
  *  block_size      threads per block of the transport kernel (64..1024, a
  *                  multiple of 64; 0 = default 256).
  *  blocks_per_cu   resident blocks per compute unit (0 = default).
- *  strict          1: kp_run returns KP_ERR_BUDGET if any packet hit the cap. */
+ *  strict          1: kp_run returns KP_ERR_BUDGET if any packet hit the cap.
+ *  scatter_batch   a lane that reaches a scattering point waits until this
+ *                  many lanes of its wavefront do (1..64; 0 = default 8) ...
+ *  scatter_wait    ... or until it has waited this many iterations (1..1024;
+ *                  0 = default 16).  Scheduling only: results are identical
+ *                  for every setting (each packet keeps its own streams).
+ * block_size, blocks_per_cu, scatter_batch and scatter_wait are what the
+ * autotuner searches. */
 typedef struct {
   uint64_t seed;
   int32_t transport_fp64;
@@ -117,6 +124,8 @@ typedef struct {
   int32_t block_size;
   int32_t blocks_per_cu;
   int32_t strict;
+  int32_t scatter_batch;
+  int32_t scatter_wait;
 } kp_opts;
 
 /* Counters of the last kp_run/kp_transport (energies in units of lum). */

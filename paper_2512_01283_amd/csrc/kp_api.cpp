@@ -413,6 +413,8 @@ kp_status kp_transport(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, vo
   if (bs < 64 || bs > 256 || bs % 64) return fail(ctx, KP_ERR_ARG, "block_size must be 64, 128, 192 or 256");
   if (o->blocks_per_cu < 0 || o->blocks_per_cu > 64) return fail(ctx, KP_ERR_ARG, "blocks_per_cu out of range");
   if (o->transport_fp64 != 0 && o->transport_fp64 != 1) return fail(ctx, KP_ERR_ARG, "transport_fp64 must be 0 or 1");
+  if (o->scatter_batch < 0 || o->scatter_batch > 64) return fail(ctx, KP_ERR_ARG, "scatter_batch must be in 0..64");
+  if (o->scatter_wait < 0 || o->scatter_wait > 1024) return fail(ctx, KP_ERR_ARG, "scatter_wait must be in 0..1024");
 
   KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
@@ -462,6 +464,8 @@ kp_status kp_transport(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, vo
   a.traces = ctx->d_traces;
   a.trace_count = o->trace_packets;
   a.trace_stride = o->trace_stride ? o->trace_stride : 1;
+  a.scatter_batch = o->scatter_batch ? o->scatter_batch : 8;
+  a.scatter_wait = o->scatter_wait ? o->scatter_wait : 16;
 
   bool sphere = true;
   for (int l = 0; l < nl; ++l) sphere = sphere && ctx->hdust[l].sphere;

@@ -71,6 +71,8 @@ struct TransportArgs {
   StatsDev* stats;
   TraceDev* traces;
   uint32_t trace_count, trace_stride;
+  int scatter_batch;  // run parked scattering events once this many lanes wait
+  int scatter_wait;   // ... or after this many iterations
 };
 
 struct ImageArgs {

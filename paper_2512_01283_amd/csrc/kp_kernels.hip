@@ -331,6 +331,9 @@ __device__ bool scatter(Packet<R>& p, const Quat<R>& q, const V3<double>& bdir,
   return true;
 }
 
+template <typename R>
+__device__ uint32_t roulette(Packet<R>& p, const TransportArgs& a);
+
 // One loop iteration: one cell segment (Sec. 2.2: cell-to-cell traversal,
 // exponential scattering depth, continuous extinction across the segment by
 // the analytic cell solution of Appendix A, tally of the segment into the
@@ -338,7 +341,7 @@ __device__ bool scatter(Packet<R>& p, const Quat<R>& q, const V3<double>& bdir,
 // into the next cell, then Russian roulette.  Returns 0 or an end kind.
 template <typename R, bool ALIGNED, bool SPHERE>
 __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_t& key,
-                         R cc[TallyShape<SPHERE>::NC]) {
+                         R cc[TallyShape<SPHERE>::NC], bool& pending) {
   constexpr int NC = TallyShape<SPHERE>::NC;
   const uint64_t c = (uint64_t)p.ci + (uint64_t)a.nx * ((uint64_t)p.cj + (uint64_t)a.ny * p.ck);
   p.last = (int64_t)c;
@@ -446,13 +449,13 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
     return END_RR_KILL;
   }
   if (scat) {
+    // the scattering event itself runs in scatter_step(), possibly a few
+    // iterations later together with other lanes of the wavefront
     p.fx = fmin(1.0, fmax(0.0, p.fx + tld * dnx));
     p.fy = fmin(1.0, fmax(0.0, p.fy + tld * dny));
     p.fz = fmin(1.0, fmax(0.0, p.fz + tld * dnz));
-    if (!scatter<R, ALIGNED, SPHERE>(p, q, bdir, D, a.seed)) return END_NUMERIC;
-    p.events++;
-    p.hash = hash_event(p.hash, EV_SCATTER, c);
-    p.tau = -log((double)next_uniform(p, a.seed));
+    pending = true;
+    return 0;
   } else {
     if (axis != 0) p.fx = fmin(1.0, fmax(0.0, p.fx + td * dnx));
     if (axis != 1) p.fy = fmin(1.0, fmax(0.0, p.fy + td * dny));
@@ -473,6 +476,30 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
       return END_ESCAPE;
     }
   }
+  return roulette(p, a);
+}
+
+// Scattering event at the packet's current position (Sec. 2.2), the next
+// scattering depth, and the roulette check that follows every segment.
+template <typename R, bool ALIGNED, bool SPHERE>
+__device__ uint32_t scatter_step(Packet<R>& p, const TransportArgs& a) {
+  const uint64_t c = (uint64_t)p.ci + (uint64_t)a.nx * ((uint64_t)p.cj + (uint64_t)a.ny * p.ck);
+  const DustDev& D = a.dust[p.lam];
+  Quat<R> q{(R)1, (R)0, (R)0, (R)0};
+  V3<double> bdir{0.0, 0.0, 1.0};
+  if (ALIGNED) {
+    bdir = V3<double>{(double)a.bx[c], (double)a.by[c], (double)a.bz[c]};
+    q = grain_quat(V3<R>{(R)bdir.x, (R)bdir.y, (R)bdir.z});
+  }
+  if (!scatter<R, ALIGNED, SPHERE>(p, q, bdir, D, a.seed)) return END_NUMERIC;
+  p.events++;
+  p.hash = hash_event(p.hash, EV_SCATTER, c);
+  p.tau = -log((double)next_uniform(p, a.seed));
+  return roulette(p, a);
+}
+
+template <typename R>
+__device__ uint32_t roulette(Packet<R>& p, const TransportArgs& a) {
   if (!isfinite(p.I)) return END_NUMERIC;
   if (a.rr_wmin > 0.0 && p.I < (R)a.rr_wmin * p.w0) {
     const uint64_t cn =
@@ -547,7 +574,8 @@ __global__ void __launch_bounds__(256) k_transport(TransportArgs a) {
   double* sv = s_val + wv * 64 * NC;
   long long* sk = s_key + wv * 64;
   Packet<R> p;
-  bool active = false, exhausted = false;
+  bool active = false, exhausted = false, pending = false;
+  int waited = 0;
   int64_t acc_key = -1;
   double acc[NC];
 #pragma unroll
@@ -577,8 +605,8 @@ __global__ void __launch_bounds__(256) k_transport(TransportArgs a) {
     bool has = false;
     int64_t key = -1;
     R cc[NC];
-    if (active) {
-      const uint32_t end = step<R, ALIGNED, SPHERE>(p, a, has, key, cc);
+    if (active && !pending) {
+      const uint32_t end = step<R, ALIGNED, SPHERE>(p, a, has, key, cc, pending);
       if (end) {
         finish(p, end, a, sc, se);
         active = false;
@@ -594,6 +622,26 @@ __global__ void __launch_bounds__(256) k_transport(TransportArgs a) {
         acc_key = key;
 #pragma unroll
         for (int k = 0; k < NC; ++k) acc[k] = (double)cc[k];
+      }
+    }
+    // Scattering events are run for the parked lanes together once enough
+    // of them wait (or one has waited long enough, or nothing else can
+    // move): the rejection loop then runs for many lanes at once instead of
+    // stalling the wavefront for one lane at a time.
+    const unsigned long long pm = __ballot(pending);
+    if (pm) {
+      ++waited;
+      const unsigned long long movable = __ballot(active && !pending);
+      if (__popcll(pm) >= a.scatter_batch || waited >= a.scatter_wait || movable == 0ull) {
+        waited = 0;
+        if (pending) {
+          pending = false;
+          const uint32_t end = scatter_step<R, ALIGNED, SPHERE>(p, a);
+          if (end) {
+            finish(p, end, a, sc, se);
+            active = false;
+          }
+        }
       }
     }
   }

@@ -70,7 +70,8 @@ class kp_opts(C.Structure):
                 ("rr_psurv", C.c_double), ("max_events", C.c_int64),
                 ("trace_packets", C.c_uint32), ("trace_stride", C.c_uint32),
                 ("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("strict", C.c_int32)]
+                ("strict", C.c_int32), ("scatter_batch", C.c_int32),
+                ("scatter_wait", C.c_int32)]
 
 
 class kp_stats(C.Structure):
@@ -208,7 +209,8 @@ def make_opts(o=None, **kw) -> kp_opts:
                    float(o.get("rr_wmin", 1e-3)), float(o.get("rr_psurv", 0.1)),
                    int(o.get("max_events", 10000)), int(o.get("trace_packets", 0)),
                    int(o.get("trace_stride", 1)), int(o.get("block_size", 0)),
-                   int(o.get("blocks_per_cu", 0)), int(o.get("strict", 0)))
+                   int(o.get("blocks_per_cu", 0)), int(o.get("strict", 0)),
+                   int(o.get("scatter_batch", 0)), int(o.get("scatter_wait", 0)))
 
 
 def _counts(counts):

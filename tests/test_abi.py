@@ -38,7 +38,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(P.kp_dust) == 7 * 8
     assert ctypes.sizeof(P.kp_source) == 8 + 7 * 8
     assert ctypes.sizeof(P.kp_view) == 2 * 8 + 2 * 4 + 8
-    assert ctypes.sizeof(P.kp_opts) == 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4 + 4 + 4 + 4 + 4
+    assert ctypes.sizeof(P.kp_opts) == 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4 + 4 + 4 + 4 + 4 + 4 + 4
     assert P.TRACE_DTYPE.itemsize == 8 + 4 + 4 + 8 + 8 + 24 + 32 + 8 + 8
 
 

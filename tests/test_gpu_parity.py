@@ -77,11 +77,13 @@ def test_schedule_independence():
     say("case: sphere32 fp64 schedules")
     cfg = W.uniform_sphere(packets=30000, albedo=0.5, tau_radius=3.0)
     a = gpu_run(cfg, trace_packets=3000, transport_fp64=1)
-    b = gpu_run(cfg, trace_packets=3000, transport_fp64=1, block_size=64, blocks_per_cu=1)
-    ta, tb = a.traces(), b.traces()
-    assert np.array_equal(ta, tb)
-    ia, ib = a.images(), b.images()
-    assert np.abs(ia - ib).max() <= 1e-12 * np.abs(ia[:, :, 0]).max()
+    for kw in (dict(block_size=64, blocks_per_cu=1), dict(scatter_batch=1, scatter_wait=1),
+               dict(scatter_batch=32, scatter_wait=200, block_size=128)):
+        b = gpu_run(cfg, trace_packets=3000, transport_fp64=1, **kw)
+        ta, tb = a.traces(), b.traces()
+        assert np.array_equal(ta, tb), kw
+        ia, ib = a.images(), b.images()
+        assert np.abs(ia - ib).max() <= 1e-12 * np.abs(ia[:, :, 0]).max(), kw
 
 
 def test_aligned_slab_clump(O):
@@ -242,7 +244,8 @@ def test_argument_errors():
         P.kp_set_grid(ctx.h, cfg["grid"], cfg["rho"], nb)
     assert e.value.status == P.KP_ERR_ARG
     ctx.load(cfg)
-    for kw in (dict(block_size=100), dict(max_events=0), dict(rr_psurv=0.0), dict(tally_mode=3)):
+    for kw in (dict(block_size=100), dict(max_events=0), dict(rr_psurv=0.0), dict(tally_mode=3),
+               dict(scatter_batch=65), dict(scatter_wait=-1)):
         with pytest.raises(P.KpError) as e:
             P.kp_run(ctx.h, [10], ctx.opts(**kw))
         assert e.value.status == P.KP_ERR_ARG, kw
