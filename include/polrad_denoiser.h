@@ -1,0 +1,119 @@
+/*
+ * polrad_denoiser.h -- C ABI of the learned Stokes-map denoiser in
+ * libpolrad.so.
+ *
+ * The denoiser is not part of the radiative-transfer method of Yang & Wang
+ * (arXiv:2512.01283).  It post-processes the Stokes images of two-step
+ * imaging (Sec. 2.3): from a map made with few packets it estimates the Q and
+ * U of a map made with many more.  Monte Carlo noise falls only as N^-1/2, so
+ * a good estimate saves packets.
+ *
+ * Network (all 3x3 convolutions have zero padding 1 and a bias; relu after
+ * every one; widths c1, c2, c3):
+ *   x    = (I, Q, U, V) / s, s = mean of I over the image     H x W, 4 ch
+ *   e1   = conv(conv(x, 4->c1), c1->c1)                      H x W
+ *   e2   = conv(conv(pool(e1), c1->c2), c2->c2)              H/2
+ *   m3   = conv(conv(pool(e2), c2->c3), c3->c3)              H/4
+ *   d2   = conv(conv([up(m3), e2], c3+c2->c2), c2->c2)       H/2
+ *   d1   = conv(conv([up(d2), e1], c2+c1->c1), c1->c1)       H
+ *   out  = (Q, U) / s + head(d1)        head: 1x1 convolution c1 -> 2
+ * pool = 2x2 mean, up = 2x nearest repeat, [a, b] = channel concatenation
+ * (a first).  The denoised map is (I, out_Q s, out_U s, V).
+ * Training minimises the mean over pixels and both channels of
+ * (out - (Q, U)_target / s)^2, with s taken from the low-packet map, by Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on FP32 master weights.
+ *
+ * Parameters are one flat FP32 array: for each convolution in the order
+ * e1a e1b e2a e2b m3a m3b d2a d2b d1a d1b its weights [cout][3][3][cin]
+ * (w[o][dy][dx][c] multiplies x[h + dy - 1][w + dx - 1][c]) then its bias
+ * [cout]; then the head's weights [2][c1] and bias [2].
+ *
+ * Arithmetic: convolutions run on BF16 matrix cores with FP32 accumulation
+ * (weights and activations rounded to BF16, nearest even); the head, loss,
+ * gradients of the weights, the optimiser and the maps are FP32/FP64.
+ *
+ * Maps are FP64 device arrays [batch][4][height][width] (I, Q, U, V), the
+ * layout of kp_get_images_device for one wavelength's views, so images of a
+ * run can be passed straight in.  height and width must be multiples of 4
+ * (two pooling levels); batch * height * width <= 2^24.
+ *
+ * Errors follow polrad.h: every call returns kp_status, arguments are
+ * validated before any launch, kp_dn_last_error() gives the message.  A
+ * handle is bound to one device and is not thread-safe.  Device memory for
+ * activations is allocated on first use for a given size and kept.
+ */
+#ifndef POLRAD_DENOISER_H
+#define POLRAD_DENOISER_H
+#include <stddef.h>
+#include <stdint.h>
+
+#include "polrad.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kp_dn kp_dn;
+
+/* Create a denoiser of widths c1, c2, c3 (each a multiple of 16 in
+ * [16, 512]) on HIP device `device`, with all parameters zero.  *out
+ * receives an owned handle (release with kp_dn_destroy). */
+kp_status kp_dn_create(int device, int32_t c1, int32_t c2, int32_t c3, kp_dn **out);
+void kp_dn_destroy(kp_dn *dn);
+const char *kp_dn_last_error(const kp_dn *dn);
+
+/* Number of FP32 parameters (the length of the flat array above). */
+kp_status kp_dn_num_params(const kp_dn *dn, size_t *n);
+/* Copy n = kp_dn_num_params parameters from / to host memory.  Setting the
+ * parameters clears the Adam moments and step count. */
+kp_status kp_dn_set_params(kp_dn *dn, const float *host_params, size_t n);
+kp_status kp_dn_get_params(kp_dn *dn, float *host_params, size_t n);
+/* Gradient of the loss of the last kp_dn_backward / kp_dn_train_step with
+ * respect to every parameter, same layout (host copy of n floats). */
+kp_status kp_dn_get_grads(kp_dn *dn, float *host_grads, size_t n);
+/* Adam state for checkpoint and resume: first and second moments (n floats
+ * each, host) and the number of steps taken. */
+kp_status kp_dn_get_adam(kp_dn *dn, float *host_m, float *host_v, size_t n, int32_t *step);
+kp_status kp_dn_set_adam(kp_dn *dn, const float *host_m, const float *host_v, size_t n, int32_t step);
+
+/* Denoise: d_maps (device, read) -> d_out (device, written; may not alias
+ * d_maps).  Asynchronous on hip_stream. */
+kp_status kp_dn_infer(kp_dn *dn, const double *d_maps, double *d_out, int32_t batch, int32_t height,
+                      int32_t width, void *hip_stream);
+
+/* Loss and gradients for the pairs (d_low[b], d_high[b]) (device maps).
+ * host_aug (NULL = identity) holds one code per image, 0..7, of the
+ * dihedral transform applied to both maps of a pair before the network:
+ * code a = r + 4 f mirrors the width axis when f = 1, then rotates the image
+ * by r quarter turns (numpy's rot90 on the (height, width) axes), and maps
+ * Stokes as (Q, U, V) -> ((-1)^r Q, (-1)^(r+f) U, (-1)^f V); odd r needs
+ * height == width.  *loss (host) receives the mean squared error; the call
+ * synchronises hip_stream. */
+kp_status kp_dn_backward(kp_dn *dn, const double *d_low, const double *d_high, int32_t batch,
+                         int32_t height, int32_t width, const int32_t *host_aug, double *loss,
+                         void *hip_stream);
+/* One Adam step with learning rate lr (> 0) from the gradients of the last
+ * kp_dn_backward.  Asynchronous on hip_stream. */
+kp_status kp_dn_adam_step(kp_dn *dn, float lr, void *hip_stream);
+/* kp_dn_backward followed by kp_dn_adam_step. */
+kp_status kp_dn_train_step(kp_dn *dn, const double *d_low, const double *d_high, int32_t batch,
+                           int32_t height, int32_t width, const int32_t *host_aug, float lr,
+                           double *loss, void *hip_stream);
+
+/* Device time of the last kp_dn_infer / kp_dn_backward, in ms, split into
+ * the 3x3 convolution kernels (forward and input gradient), the weight
+ * gradient kernels, and everything else; HIP events on the call's stream. */
+typedef struct {
+  double ms_total;
+  double ms_conv;
+  double ms_wgrad;
+  double ms_other;
+  double conv_flop; /* algorithmic FLOP of the convolution kernels timed in ms_conv */
+  double wgrad_flop;
+} kp_dn_timing;
+kp_status kp_dn_get_timing(kp_dn *dn, kp_dn_timing *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpolrad.so")
 ARCH = "gfx950"
 
-SOURCES = ["kp_kernels.hip", "kp_api.cpp"]
+SOURCES = ["kp_kernels.hip", "kp_api.cpp", "kp_denoiser.hip", "kp_dn_api.cpp"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -1,0 +1,606 @@
+// kp_denoiser.hip -- kernels of the learned Stokes-map denoiser on gfx950.
+//
+// The network is a small U-Net (3x3 convolutions at widths c1/c2/c3, 2x2 mean
+// pooling, 2x nearest upsampling, skip concatenation, a 1x1 head that adds a
+// correction to the input's Q and U).  It is not part of the radiative
+// transfer method: it post-processes the step-2 Stokes maps.
+//
+// Tensors are NHWC BF16 (stored as uint16_t) with a per-pixel stride, so a
+// concatenation is two producers writing disjoint channel ranges of one
+// buffer.  Pixel p = (n H + h) W + w.  Every channel count is a multiple of 8,
+// so 8 consecutive channels are one 16-byte load.
+//
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16 (FP32
+// accumulation).  The GEMM K index is k = kk * cin + c with kk = 3 dy + dx
+// the tap and c the input channel; K = 9 cin is zero-padded to a multiple of
+// 32 in the packed weights.  A lane's 8 consecutive K elements never straddle
+// a tap because cin % 8 == 0.
+//
+// MFMA 16x16x32 BF16 operand layout (wave64, lane l, i = l % 16, g = l / 16):
+// A[i][8g + j] and B[8g + j][i] for j = 0..7 come from lane l; the result
+// D[4g + j][i], j = 0..3, lands in lane l.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+
+#include "kp_dn_internal.hpp"
+
+namespace kp {
+namespace dn {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even (inputs are finite)
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ bool bf_pos(uint16_t b) { return !(b & 0x8000u) && b != 0; }
+
+__device__ __forceinline__ u32x4 ld16(const uint16_t* p) { return *(const u32x4*)p; }
+__device__ __forceinline__ void st16(uint16_t* p, u32x4 v) { *(u32x4*)p = v; }
+
+// unpack / pack 8 BF16 held in a 16-byte vector
+__device__ __forceinline__ void unpack8(u32x4 v, float* f) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    f[2 * j] = __uint_as_float(v[j] << 16);
+    f[2 * j + 1] = __uint_as_float(v[j] & 0xFFFF0000u);
+  }
+}
+__device__ __forceinline__ u32x4 pack8(const float* f) {
+  u32x4 v;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) v[j] = (uint32_t)f2bf(f[2 * j]) | ((uint32_t)f2bf(f[2 * j + 1]) << 16);
+  return v;
+}
+
+__device__ __forceinline__ f32x4 mfma(u32x4 a, u32x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution as an implicit GEMM:
+//   y[p][n] = epi( sum_{kk, c} x[p + off(kk)][c] * w[n][kk * cin + c] )
+// off(kk) = (kk / 3 - 1, kk % 3 - 1), zero outside the image.  The forward
+// pass uses the layer's weights; the input gradient of a layer uses the same
+// kernel with the flipped, transposed weights wd[ci][kk * cout + co] =
+// w[co][8 - kk][ci], because off(8 - kk) = -off(kk).
+// One wave computes 32 pixels x 64 output channels (2 x 4 MFMA tiles).
+// ---------------------------------------------------------------------------
+// MODE: CONV_RELU (bias, relu), CONV_LINEAR (bias), CONV_MASK (no bias; zero where mask <= 0 if mask)
+template <int MODE>
+__global__ void __launch_bounds__(256) k_conv3(ConvArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int P = a.B * a.H * a.W;
+  const int ngroups = (a.nout + 63) >> 6;
+  const int ptile = wave / ngroups, ng = wave - ptile * ngroups;
+  if (ptile * 32 >= P) return;
+  const int i = lane & 15, g = lane >> 4;
+  int ph[2], pw[2], pn[2];
+  bool pv[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int p = ptile * 32 + 16 * r + i;
+    pv[r] = p < P;
+    const int q = pv[r] ? p : 0;
+    pw[r] = q % a.W;
+    ph[r] = (q / a.W) % a.H;
+    pn[r] = q / (a.W * a.H);
+  }
+  const int n0 = ng * 64;
+  const int ntile = min(4, (a.nout - n0) >> 4);
+  f32x4 acc[2][4];
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[r][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const uint16_t* wrow[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) wrow[t] = a.w + (size_t)(n0 + 16 * min(t, ntile - 1) + i) * a.kp + 8 * g;
+  const int K = 9 * a.cin;
+  int kk = 0, c = 8 * g;
+  while (c >= a.cin) {
+    c -= a.cin;
+    ++kk;
+  }
+  const u32x4 zero = {0u, 0u, 0u, 0u};
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const int dy = kk / 3 - 1, dx = kk % 3 - 1;
+    u32x4 av[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int hh = ph[r] + dy, ww = pw[r] + dx;
+      const bool ok = pv[r] && kk < 9 && hh >= 0 && hh < a.H && ww >= 0 && ww < a.W;
+      av[r] = ok ? ld16(a.x + ((size_t)(pn[r] * a.H + hh) * a.W + ww) * a.xs + c) : zero;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t < ntile) {
+        const u32x4 bv = ld16(wrow[t] + k0);
+        acc[0][t] = mfma(av[0], bv, acc[0][t]);
+        acc[1][t] = mfma(av[1], bv, acc[1][t]);
+      }
+    }
+    c += 32;
+    while (c >= a.cin) {
+      c -= a.cin;
+      ++kk;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (t >= ntile) continue;
+    const int n = n0 + 16 * t + i;
+    const float bn = MODE == CONV_MASK ? 0.f : a.bias[n];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int p = ptile * 32 + 16 * r + 4 * g + j;
+        if (p >= P) continue;
+        float v = acc[r][t][j] + bn;
+        if (MODE == CONV_RELU) v = fmaxf(v, 0.f);
+        if (MODE == CONV_MASK && a.mask && !bf_pos(a.mask[(size_t)p * a.ms + n])) v = 0.f;
+        a.y[(size_t)p * a.ys + n] = f2bf(v);
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient:  gw[co][kk][c] += sum_p gz[p][co] * x[p + off(kk)][c]
+// GEMM M = co, N = k = kk * cin + c, reduction over pixels.  A workgroup owns
+// a 64 x 64 (co, k) tile and a chunk of pixels; each 32-pixel slab of gz and
+// of the im2col matrix is loaded with 16-byte loads and written transposed to
+// LDS so that every lane's MFMA operand (8 consecutive pixels) is one 16-byte
+// LDS read.  Partial tiles are added to the FP32 gradient with atomics.
+// ---------------------------------------------------------------------------
+constexpr int WG_LDS_STRIDE = 40;  // 32 pixels + 8 pad (row = 80 bytes, 16-byte aligned)
+
+__global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[64 * WG_LDS_STRIDE];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[64 * WG_LDS_STRIDE];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int P = a.B * a.H * a.W;
+  const int mt = blockIdx.x / a.ktiles, kt = blockIdx.x - mt * a.ktiles;
+  const int m0 = mt * 64, kb = kt * 64;
+  const int p_begin = blockIdx.y * a.chunk;
+  const int p_end = min(P, p_begin + a.chunk);
+  // this thread's load slots: pixel row sp of the slab and 8-column group s8
+  const int sp = tid >> 3, s8 = (tid & 7) * 8;
+  const bool a_ok = m0 + s8 < a.cout;
+  const int kx = kb + s8;
+  const int lkk = kx / a.cin, lc = kx - lkk * a.cin;
+  const bool b_ok = lkk < 9;
+  const int ldy = lkk / 3 - 1, ldx = lkk % 3 - 1;
+  f32x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const u32x4 zero = {0u, 0u, 0u, 0u};
+  for (int s0 = p_begin; s0 < p_end; s0 += 32) {
+    const int p = s0 + sp;
+    u32x4 va = zero, vb = zero;
+    if (p < p_end) {
+      if (a_ok) va = ld16(a.gz + (size_t)p * a.gzs + m0 + s8);
+      if (b_ok) {
+        const int w = p % a.W, h = (p / a.W) % a.H, n = p / (a.W * a.H);
+        const int hh = h + ldy, ww = w + ldx;
+        if (hh >= 0 && hh < a.H && ww >= 0 && ww < a.W)
+          vb = ld16(a.x + ((size_t)(n * a.H + hh) * a.W + ww) * a.xs + lc);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      As[(s8 + 2 * j) * WG_LDS_STRIDE + sp] = (uint16_t)(va[j] & 0xFFFFu);
+      As[(s8 + 2 * j + 1) * WG_LDS_STRIDE + sp] = (uint16_t)(va[j] >> 16);
+      Bs[(s8 + 2 * j) * WG_LDS_STRIDE + sp] = (uint16_t)(vb[j] & 0xFFFFu);
+      Bs[(s8 + 2 * j + 1) * WG_LDS_STRIDE + sp] = (uint16_t)(vb[j] >> 16);
+    }
+    __syncthreads();
+    const u32x4 av = *(const u32x4*)(As + (16 * wv + i) * WG_LDS_STRIDE + 8 * g);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const u32x4 bv = *(const u32x4*)(Bs + (16 * t + i) * WG_LDS_STRIDE + 8 * g);
+      acc[t] = mfma(av, bv, acc[t]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int k = kb + 16 * t + i;
+    const int kk = k / a.cin, c = k - kk * a.cin;
+    if (kk >= 9 || c >= a.cin_true) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int co = m0 + 16 * wv + 4 * g + j;
+      if (co < a.cout) atomicAdd(a.gw + ((size_t)co * 9 + kk) * a.cin_true + c, acc[t][j]);
+    }
+  }
+}
+
+// gb[c] += sum_p gz[p][c]: a block sums 1024 pixels, one thread per channel
+__global__ void k_bias_grad(const uint16_t* __restrict__ gz, int gzs, int C, int P, float* __restrict__ gb) {
+  const int p0 = blockIdx.x * 1024, p1 = min(P, p0 + 1024);
+  for (int c = threadIdx.x; c < C; c += blockDim.x) {
+    float s = 0.f;
+    for (int p = p0; p < p1; ++p) s += bf2f(gz[(size_t)p * gzs + c]);
+    atomicAdd(gb + c, s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// resampling, 8 channels per thread.  Sizes: fine grid H x W, coarse H/2 x W/2.
+// ---------------------------------------------------------------------------
+// y (coarse) = mean of each 2x2 block of x (fine)
+__global__ void k_pool(const uint16_t* __restrict__ x, int xs, uint16_t* __restrict__ y, int ys, int B, int H, int W,
+                       int C) {
+  const int Ho = H / 2, Wo = W / 2, C8 = C / 8;
+  const size_t n = (size_t)B * Ho * Wo * C8;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(k % C8) * 8;
+    const size_t q = k / C8;
+    const int w = (int)(q % Wo), h = (int)((q / Wo) % Ho), b = (int)(q / ((size_t)Wo * Ho));
+    const size_t f = (size_t)(b * H + 2 * h) * W + 2 * w;
+    float s[8], t[8];
+    unpack8(ld16(x + f * xs + c), s);
+    const size_t nb[3] = {f + 1, f + W, f + W + 1};
+    for (int m = 0; m < 3; ++m) {
+      unpack8(ld16(x + nb[m] * xs + c), t);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s[j] += t[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s[j] *= 0.25f;
+    st16(y + q * ys + c, pack8(s));
+  }
+}
+
+// y (fine) = x (coarse) repeated over each 2x2 block
+__global__ void k_up(const uint16_t* __restrict__ x, int xs, uint16_t* __restrict__ y, int ys, int B, int H, int W,
+                     int C) {
+  const int C8 = C / 8, Wc = W / 2, Hc = H / 2;
+  const size_t n = (size_t)B * H * W * C8;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(k % C8) * 8;
+    const size_t p = k / C8;
+    const int w = (int)(p % W), h = (int)((p / W) % H), b = (int)(p / ((size_t)W * H));
+    const size_t q = (size_t)(b * Hc + h / 2) * Wc + w / 2;
+    st16(y + p * ys + c, ld16(x + q * xs + c));
+  }
+}
+
+// gx (coarse) = (sum of each 2x2 block of gy (fine)) where mask (coarse) > 0, else 0
+__global__ void k_up_bwd(const uint16_t* __restrict__ gy, int gys, uint16_t* __restrict__ gx, int gxs,
+                         const uint16_t* __restrict__ mask, int ms, int B, int H, int W, int C) {
+  const int Ho = H / 2, Wo = W / 2, C8 = C / 8;
+  const size_t n = (size_t)B * Ho * Wo * C8;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(k % C8) * 8;
+    const size_t q = k / C8;
+    const int w = (int)(q % Wo), h = (int)((q / Wo) % Ho), b = (int)(q / ((size_t)Wo * Ho));
+    const size_t f = (size_t)(b * H + 2 * h) * W + 2 * w;
+    float s[8], t[8];
+    unpack8(ld16(gy + f * gys + c), s);
+    const size_t nb[3] = {f + 1, f + W, f + W + 1};
+    for (int m = 0; m < 3; ++m) {
+      unpack8(ld16(gy + nb[m] * gys + c), t);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s[j] += t[j];
+    }
+    const u32x4 mv = ld16(mask + q * ms + c);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint16_t mb = (uint16_t)((mv[j / 2] >> (16 * (j & 1))) & 0xFFFFu);
+      if (!bf_pos(mb)) s[j] = 0.f;
+    }
+    st16(gx + q * gxs + c, pack8(s));
+  }
+}
+
+// dst (fine) = (a (fine) + g (coarse parent) / 4) where mask (fine) > 0, else 0
+__global__ void k_pool_bwd_add(const uint16_t* __restrict__ a, int as, const uint16_t* __restrict__ g, int gs,
+                               const uint16_t* __restrict__ mask, int ms, uint16_t* __restrict__ dst, int ds, int B,
+                               int H, int W, int C) {
+  const int C8 = C / 8, Wc = W / 2, Hc = H / 2;
+  const size_t n = (size_t)B * H * W * C8;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(k % C8) * 8;
+    const size_t p = k / C8;
+    const int w = (int)(p % W), h = (int)((p / W) % H), b = (int)(p / ((size_t)W * H));
+    const size_t q = (size_t)(b * Hc + h / 2) * Wc + w / 2;
+    float s[8], t[8];
+    unpack8(ld16(a + p * as + c), s);
+    unpack8(ld16(g + q * gs + c), t);
+    const u32x4 mv = ld16(mask + p * ms + c);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint16_t mb = (uint16_t)((mv[j / 2] >> (16 * (j & 1))) & 0xFFFFu);
+      s[j] = bf_pos(mb) ? s[j] + 0.25f * t[j] : 0.f;
+    }
+    st16(dst + p * ds + c, pack8(s));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// input normalisation, head, loss, output, optimiser
+// ---------------------------------------------------------------------------
+// sum[b] += sum of I over image b of maps [B][4][H*W]
+__global__ void k_sum_I(const double* __restrict__ maps, int HW, double* __restrict__ sum) {
+  const int b = blockIdx.y;
+  double acc = 0.0;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < HW; p += gridDim.x * blockDim.x)
+    acc += maps[(size_t)b * 4 * HW + p];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) atomicAdd(sum + b, acc);
+}
+
+// x[p][0..7] = (I, Q, U, V) / s, 0, 0, 0, 0 in BF16 with s the image's mean I;
+// xq[p] = (Q, U) / s in FP32; tgt[p] = (Q, U) of the target maps / s.
+// With aug, image b is first transformed by the dihedral element aug[b] =
+// r + 4 f: mirror the width axis if f, then r quarter turns (output pixel
+// (h, w) of one turn reads (w, W - 1 - h)); Stokes (Q, U, V) ->
+// ((-1)^r Q, (-1)^(r+f) U, (-1)^f V).  Odd r requires H == W.
+__global__ void k_prep(const double* __restrict__ maps, const double* __restrict__ target,
+                       const double* __restrict__ sum, const int32_t* __restrict__ aug, int B, int H, int W,
+                       uint16_t* __restrict__ x, float* __restrict__ xq, float* __restrict__ tgt) {
+  const int HW = H * W;
+  const size_t n = (size_t)B * HW;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    const size_t b = k / HW;
+    int h = (int)(k % HW) / W, w = (int)(k % HW) % W;
+    float sq = 1.f, su = 1.f, sv = 1.f;
+    if (aug) {
+      const int code = aug[b], r = code & 3, f = code >> 2;
+      for (int t = 0; t < r; ++t) {
+        const int h2 = w, w2 = W - 1 - h;
+        h = h2;
+        w = w2;
+      }
+      if (f) w = W - 1 - w;
+      sq = (r & 1) ? -1.f : 1.f;
+      su = ((r + f) & 1) ? -1.f : 1.f;
+      sv = f ? -1.f : 1.f;
+    }
+    const size_t p = (size_t)h * W + w;
+    const double mean = sum[b] / HW;
+    const double inv = mean > 0.0 ? 1.0 / mean : 0.0;
+    const double* m = maps + b * 4 * HW + p;
+    float f8[8];
+    f8[0] = (float)(m[0] * inv);
+    f8[1] = sq * (float)(m[HW] * inv);
+    f8[2] = su * (float)(m[2 * (size_t)HW] * inv);
+    f8[3] = sv * (float)(m[3 * (size_t)HW] * inv);
+#pragma unroll
+    for (int c = 4; c < 8; ++c) f8[c] = 0.f;
+    st16(x + k * 8, pack8(f8));
+    xq[2 * k] = f8[1];
+    xq[2 * k + 1] = f8[2];
+    if (target) {
+      const double* r = target + b * 4 * HW + p;
+      tgt[2 * k] = sq * (float)(r[HW] * inv);
+      tgt[2 * k + 1] = su * (float)(r[2 * (size_t)HW] * inv);
+    }
+  }
+}
+
+// out[p][o] = xq[p][o] + hb[o] + sum_c d[p][c] hw[o][c]   (C % 8 == 0)
+__global__ void k_head(const uint16_t* __restrict__ d, int C, const float* __restrict__ hw,
+                       const float* __restrict__ hb, const float* __restrict__ xq, float* __restrict__ out, size_t P) {
+  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (size_t)gridDim.x * blockDim.x) {
+    float a0 = hb[0], a1 = hb[1];
+    for (int c = 0; c < C; c += 8) {
+      float v[8];
+      unpack8(ld16(d + p * C + c), v);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        a0 += v[j] * hw[c + j];
+        a1 += v[j] * hw[C + c + j];
+      }
+    }
+    out[2 * p] = xq[2 * p] + a0;
+    out[2 * p + 1] = xq[2 * p + 1] + a1;
+  }
+}
+
+// loss += sum (out - tgt)^2 (FP64); go = 2 (out - tgt) / n
+__global__ void k_loss(const float* __restrict__ out, const float* __restrict__ tgt, size_t n, float scale,
+                       float* __restrict__ go, double* __restrict__ loss) {
+  double acc = 0.0;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    const float e = out[k] - tgt[k];
+    go[k] = scale * e;
+    acc += (double)e * e;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) atomicAdd(loss, acc);
+}
+
+// Head backward over a block of 256 pixels, one thread per channel:
+// ghw[o][c] += sum_p go[p][o] d[p][c]; ghb[o] += sum_p go[p][o];
+// gd[p][c] = (sum_o go[p][o] hw[o][c]) where d[p][c] > 0, else 0.
+__global__ void k_head_bwd(const float* __restrict__ go, const uint16_t* __restrict__ d, int C,
+                           const float* __restrict__ hw, float* __restrict__ ghw, float* __restrict__ ghb,
+                           uint16_t* __restrict__ gd, size_t P) {
+  __shared__ float sgo[256][2];
+  const size_t p0 = (size_t)blockIdx.x * 256;
+  const int np = (int)((P - p0) < 256 ? (P - p0) : 256);
+  for (int k = threadIdx.x; k < np; k += blockDim.x) {
+    sgo[k][0] = go[2 * (p0 + k)];
+    sgo[k][1] = go[2 * (p0 + k) + 1];
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < C; c += blockDim.x) {
+    const float h0 = hw[c], h1 = hw[C + c];
+    float a0 = 0.f, a1 = 0.f;
+    for (int k = 0; k < np; ++k) {
+      const size_t p = p0 + k;
+      const uint16_t db = d[p * C + c];
+      const float v = bf2f(db);
+      a0 += sgo[k][0] * v;
+      a1 += sgo[k][1] * v;
+      gd[p * C + c] = bf_pos(db) ? f2bf(sgo[k][0] * h0 + sgo[k][1] * h1) : (uint16_t)0;
+    }
+    atomicAdd(ghw + c, a0);
+    atomicAdd(ghw + C + c, a1);
+  }
+  if (threadIdx.x < 2) {
+    float s = 0.f;
+    for (int k = 0; k < np; ++k) s += sgo[k][threadIdx.x];
+    atomicAdd(ghb + threadIdx.x, s);
+  }
+}
+
+// denoised maps: I and V from the input, Q and U = out * mean I
+__global__ void k_output(const double* __restrict__ maps, const float* __restrict__ out,
+                         const double* __restrict__ sum, int B, int HW, double* __restrict__ dst) {
+  const size_t n = (size_t)B * HW;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    const size_t b = k / HW, p = k % HW;
+    const double mean = sum[b] / HW;
+    const double* m = maps + b * 4 * HW + p;
+    double* o = dst + b * 4 * HW + p;
+    o[0] = m[0];
+    o[HW] = (double)out[2 * k] * mean;
+    o[2 * (size_t)HW] = (double)out[2 * k + 1] * mean;
+    o[3 * (size_t)HW] = m[3 * (size_t)HW];
+  }
+}
+
+// Adam with bias correction (Kingma & Ba 2015) on FP32 master weights
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, size_t n, float lr, float b1, float b2, float eps, float c1, float c2) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    const float gk = g[k];
+    const float mk = b1 * m[k] + (1.f - b1) * gk;
+    const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    p[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+  }
+}
+
+// FP32 master weights [cout][9][cin_true] -> BF16 GEMM weights
+//   w[co][kk * cin + c] (zero for c >= cin_true and for k >= 9 cin, up to kp)
+//   wd[ci][kk * cout + co] = w[co][8 - kk][ci] (zero-padded to kpd), if wd != null
+__global__ void k_pack(const float* __restrict__ wf, int cout, int cin, int cin_true, int kp, int kpd,
+                       uint16_t* __restrict__ w, uint16_t* __restrict__ wd) {
+  const size_t n = (size_t)cout * kp;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    const int co = (int)(k / kp), kx = (int)(k % kp);
+    const int kk = kx / cin, c = kx % cin;
+    const float v = (kk < 9 && c < cin_true) ? wf[((size_t)co * 9 + kk) * cin_true + c] : 0.f;
+    w[k] = f2bf(v);
+  }
+  if (!wd) return;
+  const size_t nd = (size_t)cin_true * kpd;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < nd; k += (size_t)gridDim.x * blockDim.x) {
+    const int ci = (int)(k / kpd), kx = (int)(k % kpd);
+    const int kk = kx / cout, co = kx % cout;
+    const float v = kk < 9 ? wf[((size_t)co * 9 + (8 - kk)) * cin_true + ci] : 0.f;
+    wd[k] = f2bf(v);
+  }
+}
+
+__global__ void k_zero32(uint32_t* __restrict__ p, size_t n) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) p[k] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline unsigned grid_for(size_t n, size_t cap = 65536) {
+  size_t g = (n + 255) / 256;
+  if (g > cap) g = cap;
+  return (unsigned)(g ? g : 1);
+}
+
+void conv3(const ConvArgs& a, int mode, hipStream_t s) {
+  const size_t P = (size_t)a.B * a.H * a.W;
+  const size_t waves = ((P + 31) / 32) * (size_t)((a.nout + 63) / 64);
+  const dim3 grid((unsigned)((waves + 3) / 4));
+  if (mode == CONV_RELU) hipLaunchKernelGGL(k_conv3<CONV_RELU>, grid, dim3(256), 0, s, a);
+  else if (mode == CONV_LINEAR) hipLaunchKernelGGL(k_conv3<CONV_LINEAR>, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_conv3<CONV_MASK>, grid, dim3(256), 0, s, a);
+}
+
+void wgrad(WgradArgs a, float* gb, hipStream_t s) {
+  const size_t P = (size_t)a.B * a.H * a.W;
+  a.ktiles = (9 * a.cin + 63) / 64;
+  const int mtiles = (a.cout + 63) / 64;
+  // pixels per workgroup: enough workgroups to fill the chip several times,
+  // few enough partial tiles to keep the atomics small
+  const size_t tiles = (size_t)mtiles * a.ktiles;
+  size_t chunk = (P * tiles + 4095) / 4096;
+  chunk = ((chunk + 31) / 32) * 32;
+  if (chunk < 256) chunk = 256;
+  if (chunk > 8192) chunk = 8192;
+  a.chunk = (int)chunk;
+  const dim3 grid((unsigned)tiles, (unsigned)((P + chunk - 1) / chunk));
+  hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_bias_grad, dim3((unsigned)((P + 1023) / 1024)), dim3(64), 0, s, a.gz, a.gzs, a.cout, (int)P,
+                     gb);
+}
+
+void pool(const uint16_t* x, int xs, uint16_t* y, int ys, int B, int H, int W, int C, hipStream_t s) {
+  hipLaunchKernelGGL(k_pool, dim3(grid_for((size_t)B * H * W * C / 32)), dim3(256), 0, s, x, xs, y, ys, B, H, W, C);
+}
+void up(const uint16_t* x, int xs, uint16_t* y, int ys, int B, int H, int W, int C, hipStream_t s) {
+  hipLaunchKernelGGL(k_up, dim3(grid_for((size_t)B * H * W * C / 8)), dim3(256), 0, s, x, xs, y, ys, B, H, W, C);
+}
+void up_bwd(const uint16_t* gy, int gys, uint16_t* gx, int gxs, const uint16_t* mask, int ms, int B, int H, int W,
+            int C, hipStream_t s) {
+  hipLaunchKernelGGL(k_up_bwd, dim3(grid_for((size_t)B * H * W * C / 32)), dim3(256), 0, s, gy, gys, gx, gxs, mask,
+                     ms, B, H, W, C);
+}
+void pool_bwd_add(const uint16_t* a, int as, const uint16_t* g, int gs, const uint16_t* mask, int ms, uint16_t* dst,
+                  int ds, int B, int H, int W, int C, hipStream_t s) {
+  hipLaunchKernelGGL(k_pool_bwd_add, dim3(grid_for((size_t)B * H * W * C / 8)), dim3(256), 0, s, a, as, g, gs, mask,
+                     ms, dst, ds, B, H, W, C);
+}
+void sum_I(const double* maps, int B, int HW, double* sum, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_I, dim3(grid_for(HW, 64), B), dim3(256), 0, s, maps, HW, sum);
+}
+void prep(const double* maps, const double* target, const double* sum, const int32_t* aug, int B, int H, int W,
+          uint16_t* x, float* xq, float* tgt, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep, dim3(grid_for((size_t)B * H * W)), dim3(256), 0, s, maps, target, sum, aug, B, H, W, x,
+                     xq, tgt);
+}
+void head(const uint16_t* d, int C, const float* hw, const float* hb, const float* xq, float* out, size_t P,
+          hipStream_t s) {
+  hipLaunchKernelGGL(k_head, dim3(grid_for(P)), dim3(256), 0, s, d, C, hw, hb, xq, out, P);
+}
+void loss(const float* out, const float* tgt, size_t n, float* go, double* l, hipStream_t s) {
+  hipLaunchKernelGGL(k_loss, dim3(grid_for(n, 2048)), dim3(256), 0, s, out, tgt, n, 2.0f / (float)n, go, l);
+}
+void head_bwd(const float* go, const uint16_t* d, int C, const float* hw, float* ghw, float* ghb, uint16_t* gd,
+              size_t P, hipStream_t s) {
+  hipLaunchKernelGGL(k_head_bwd, dim3((unsigned)((P + 255) / 256)), dim3(64), 0, s, go, d, C, hw, ghw, ghb, gd, P);
+}
+void output(const double* maps, const float* out, const double* sum, int B, int HW, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_output, dim3(grid_for((size_t)B * HW)), dim3(256), 0, s, maps, out, sum, B, HW, dst);
+}
+void adam(float* p, const float* g, float* m, float* v, size_t n, float lr, int t, hipStream_t s) {
+  const double b1 = 0.9, b2 = 0.999;
+  const float c1 = (float)(1.0 - std::pow(b1, t)), c2 = (float)(1.0 - std::pow(b2, t));
+  hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(256), 0, s, p, g, m, v, n, lr, (float)b1, (float)b2, 1e-8f, c1,
+                     c2);
+}
+void pack(const float* wf, int cout, int cin, int cin_true, int kp, int kpd, uint16_t* w, uint16_t* wd,
+          hipStream_t s) {
+  hipLaunchKernelGGL(k_pack, dim3(grid_for((size_t)cout * kp)), dim3(256), 0, s, wf, cout, cin, cin_true, kp, kpd, w,
+                     wd);
+}
+void zero(void* p, size_t bytes, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero32, dim3(grid_for(bytes / 4)), dim3(256), 0, s, (uint32_t*)p, bytes / 4);
+}
+
+}  // namespace dn
+}  // namespace kp

@@ -1,0 +1,603 @@
+// kp_dn_api.cpp -- host side of the denoiser C ABI (include/polrad_denoiser.h):
+// parameter layout, workspace carving, the forward and backward schedules of
+// the network, Adam, timing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/polrad_denoiser.h"
+#include "kp_dn_internal.hpp"
+
+using namespace kp::dn;
+
+namespace {
+
+enum { E1A, E1B, E2A, E2B, M3A, M3B, D2A, D2B, D1A, D1B, NLAYER };
+
+struct Layer {
+  int cin_true = 0;  // input channels of the network layer
+  int cin = 0;       // channels per tap in the GEMM (cin_true rounded up to 8)
+  int cout = 0;
+  int kp = 0;        // padded GEMM K of the forward weights
+  int kpd = 0;       // padded GEMM K of the input-gradient weights (0: none)
+  size_t w_off = 0, b_off = 0;          // offsets into the flat FP32 parameters
+  size_t pk_off = 0, pkd_off = 0;       // offsets into the packed BF16 weights
+};
+
+// workspace buffers (element offsets into the BF16 / FP32 / FP64 arenas)
+struct Work {
+  size_t cap = 0;    // level-1 pixel capacity
+  int bcap = 0;      // batch capacity
+  void* mem = nullptr;
+  size_t bytes = 0;
+  // BF16 activations
+  uint16_t *x0, *a1a, *cat1, *pool1, *a2a, *cat2, *pool2, *a3a, *m3, *d2a, *d2, *d1a, *d1;
+  // BF16 gradients
+  uint16_t *g1, *g1b, *gcat1, *g2, *g2b, *gcat2, *g3, *g3b, *gpool2, *ge2, *ge2b, *gpool1, *ge1, *ge1b;
+  float *xq, *tgt, *out, *go;
+  double *sum, *loss;
+  int32_t* aug;
+};
+
+constexpr int NEVENT = 128;
+
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+struct kp_dn {
+  int device = 0;
+  std::string err;
+  int c1 = 0, c2 = 0, c3 = 0;
+  Layer L[NLAYER];
+  size_t head_w = 0, head_b = 0, n_params = 0;
+  float* d_p = nullptr;  // params, grads, m, v: 4 x n_params
+  float* d_g = nullptr;
+  float* d_m = nullptr;
+  float* d_v = nullptr;
+  uint16_t* d_pk = nullptr;
+  size_t pk_n = 0;
+  bool packed = false;
+  int step = 0;
+  Work w;
+  // timing
+  hipEvent_t ev[NEVENT] = {};
+  struct Mark { int a, b, cat; double flop; };
+  std::vector<Mark> marks;
+  int nev = 0;
+  int ev_total0 = -1, ev_total1 = -1;
+};
+
+namespace {
+
+kp_status fail(kp_dn* d, kp_status st, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+kp_status fail(kp_dn* d, kp_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (d) d->err = buf;
+  return st;
+}
+
+kp_status hip_fail(kp_dn* d, hipError_t e, const char* what) {
+  return fail(d, e == hipErrorOutOfMemory ? KP_ERR_OOM : KP_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define DN_HIP(call, what)                      \
+  do {                                          \
+    hipError_t e_ = (call);                     \
+    if (e_ != hipSuccess) return hip_fail(dn, e_, what); \
+  } while (0)
+
+// --- timing marks --------------------------------------------------------------
+enum { CAT_CONV = 0, CAT_WGRAD = 1 };
+
+int mark_begin(kp_dn* dn, hipStream_t s) {
+  if (dn->nev + 2 > NEVENT) return -1;
+  const int e = dn->nev;
+  dn->nev += 2;
+  (void)hipEventRecord(dn->ev[e], s);
+  return e;
+}
+void mark_end(kp_dn* dn, int e, int cat, double flop, hipStream_t s) {
+  if (e < 0) return;
+  (void)hipEventRecord(dn->ev[e + 1], s);
+  dn->marks.push_back({e, e + 1, cat, flop});
+}
+void marks_reset(kp_dn* dn) {
+  dn->marks.clear();
+  dn->nev = 0;
+  dn->ev_total0 = dn->ev_total1 = -1;
+}
+
+// --- workspace -------------------------------------------------------------------
+kp_status ensure_work(kp_dn* dn, size_t P1, int B) {
+  Work& w = dn->w;
+  if (P1 <= w.cap && B <= w.bcap) return KP_OK;
+  const size_t cap = P1 > w.cap ? P1 : w.cap;
+  const int bcap = B > w.bcap ? B : w.bcap;
+  const size_t c1 = dn->c1, c2 = dn->c2, c3 = dn->c3;
+  const size_t P2 = cap / 4, P3 = cap / 16;
+  size_t off = 0;
+  std::vector<std::pair<void**, size_t>> plan;  // (pointer, bytes)
+  auto bf = [&](uint16_t** p, size_t elems) { plan.push_back({(void**)p, elems * 2}); };
+  bf(&w.x0, cap * 8);
+  bf(&w.a1a, cap * c1);
+  bf(&w.cat1, cap * (c2 + c1));
+  bf(&w.pool1, P2 * c1);
+  bf(&w.a2a, P2 * c2);
+  bf(&w.cat2, P2 * (c3 + c2));
+  bf(&w.pool2, P3 * c2);
+  bf(&w.a3a, P3 * c3);
+  bf(&w.m3, P3 * c3);
+  bf(&w.d2a, P2 * c2);
+  bf(&w.d2, P2 * c2);
+  bf(&w.d1a, cap * c1);
+  bf(&w.d1, cap * c1);
+  bf(&w.g1, cap * c1);
+  bf(&w.g1b, cap * c1);
+  bf(&w.gcat1, cap * (c2 + c1));
+  bf(&w.g2, P2 * c2);
+  bf(&w.g2b, P2 * c2);
+  bf(&w.gcat2, P2 * (c3 + c2));
+  bf(&w.g3, P3 * c3);
+  bf(&w.g3b, P3 * c3);
+  bf(&w.gpool2, P3 * c2);
+  bf(&w.ge2, P2 * c2);
+  bf(&w.ge2b, P2 * c2);
+  bf(&w.gpool1, P2 * c1);
+  bf(&w.ge1, cap * c1);
+  bf(&w.ge1b, cap * c1);
+  plan.push_back({(void**)&w.xq, cap * 2 * 4});
+  plan.push_back({(void**)&w.tgt, cap * 2 * 4});
+  plan.push_back({(void**)&w.out, cap * 2 * 4});
+  plan.push_back({(void**)&w.go, cap * 2 * 4});
+  plan.push_back({(void**)&w.sum, (size_t)bcap * 8});
+  plan.push_back({(void**)&w.loss, 8});
+  plan.push_back({(void**)&w.aug, (size_t)bcap * 4});
+  std::vector<size_t> offs;
+  for (auto& e : plan) {
+    offs.push_back(off);
+    off += (e.second + 255) / 256 * 256;
+  }
+  size_t free_b = 0, total_b = 0;
+  DN_HIP(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+  if (off > free_b + w.bytes)
+    return fail(dn, KP_ERR_OOM, "denoiser workspace of %zu bytes exceeds free device memory (%zu)", off,
+                free_b + w.bytes);
+  DN_HIP(hipDeviceSynchronize(), "synchronise before workspace reallocation");
+  if (w.mem) {
+    (void)hipFree(w.mem);
+    w.mem = nullptr;
+    w.cap = 0;
+    w.bcap = 0;
+    w.bytes = 0;
+  }
+  DN_HIP(hipMalloc(&w.mem, off), "denoiser workspace allocation");
+  for (size_t k = 0; k < plan.size(); ++k) *plan[k].first = (char*)w.mem + offs[k];
+  w.cap = cap;
+  w.bcap = bcap;
+  w.bytes = off;
+  return KP_OK;
+}
+
+kp_status ensure_packed(kp_dn* dn, hipStream_t s) {
+  if (dn->packed) return KP_OK;
+  for (int l = 0; l < NLAYER; ++l) {
+    const Layer& y = dn->L[l];
+    pack(dn->d_p + y.w_off, y.cout, y.cin, y.cin_true, y.kp, y.kpd, dn->d_pk + y.pk_off,
+         y.kpd ? dn->d_pk + y.pkd_off : nullptr, s);
+  }
+  DN_HIP(hipGetLastError(), "weight packing launch");
+  dn->packed = true;
+  return KP_OK;
+}
+
+kp_status check_maps(kp_dn* dn, const void* a, const void* b, int32_t B, int32_t H, int32_t W) {
+  if (!a || !b) return fail(dn, KP_ERR_ARG, "map pointer is NULL");
+  if (B < 1) return fail(dn, KP_ERR_ARG, "batch must be >= 1 (got %d)", B);
+  if (H < 4 || W < 4 || H % 4 || W % 4)
+    return fail(dn, KP_ERR_ARG, "height and width must be positive multiples of 4 (got %d x %d)", H, W);
+  if ((uint64_t)B * H * W > (1ull << 24))
+    return fail(dn, KP_ERR_ARG, "batch * height * width = %llu exceeds 2^24",
+                (unsigned long long)((uint64_t)B * H * W));
+  return KP_OK;
+}
+
+// --- network schedule --------------------------------------------------------------
+double conv_flop(const Layer& y, size_t P) { return 2.0 * (double)P * 9.0 * y.cin_true * y.cout; }
+
+void conv_fwd(kp_dn* dn, int l, const uint16_t* x, int xs, uint16_t* y, int ys, int B, int H, int W, hipStream_t s) {
+  const Layer& L = dn->L[l];
+  ConvArgs a{};
+  a.x = x;
+  a.xs = xs;
+  a.cin = L.cin;
+  a.w = dn->d_pk + L.pk_off;
+  a.kp = L.kp;
+  a.nout = L.cout;
+  a.bias = dn->d_p + L.b_off;
+  a.y = y;
+  a.ys = ys;
+  a.B = B;
+  a.H = H;
+  a.W = W;
+  const int e = mark_begin(dn, s);
+  conv3(a, CONV_RELU, s);
+  mark_end(dn, e, CAT_CONV, conv_flop(L, (size_t)B * H * W), s);
+}
+
+// input gradient of layer l: gx (stride cin_true) from gz (stride cout), zero where mask <= 0
+void conv_dgrad(kp_dn* dn, int l, const uint16_t* gz, uint16_t* gx, int gxs, const uint16_t* mask, int ms, int B,
+                int H, int W, hipStream_t s) {
+  const Layer& L = dn->L[l];
+  ConvArgs a{};
+  a.x = gz;
+  a.xs = L.cout;
+  a.cin = L.cout;
+  a.w = dn->d_pk + L.pkd_off;
+  a.kp = L.kpd;
+  a.nout = L.cin_true;
+  a.y = gx;
+  a.ys = gxs;
+  a.mask = mask;
+  a.ms = ms;
+  a.B = B;
+  a.H = H;
+  a.W = W;
+  const int e = mark_begin(dn, s);
+  conv3(a, CONV_MASK, s);
+  mark_end(dn, e, CAT_CONV, conv_flop(L, (size_t)B * H * W), s);
+}
+
+void conv_wgrad(kp_dn* dn, int l, const uint16_t* gz, const uint16_t* x, int xs, int B, int H, int W, hipStream_t s) {
+  const Layer& L = dn->L[l];
+  WgradArgs a{};
+  a.gz = gz;
+  a.gzs = L.cout;
+  a.cout = L.cout;
+  a.x = x;
+  a.xs = xs;
+  a.cin = L.cin;
+  a.cin_true = L.cin_true;
+  a.gw = dn->d_g + L.w_off;
+  a.B = B;
+  a.H = H;
+  a.W = W;
+  const int e = mark_begin(dn, s);
+  wgrad(a, dn->d_g + L.b_off, s);
+  mark_end(dn, e, CAT_WGRAD, conv_flop(L, (size_t)B * H * W), s);
+}
+
+// maps -> w.out (network output, FP32 (Q, U) / s per pixel); all activations kept
+kp_status forward(kp_dn* dn, const double* maps, const double* target, int B, int H, int W, bool use_aug,
+                  hipStream_t s) {
+  Work& w = dn->w;
+  const int c1 = dn->c1, c2 = dn->c2, c3 = dn->c3;
+  const size_t P1 = (size_t)B * H * W;
+  zero(w.sum, (size_t)B * 8, s);
+  sum_I(maps, B, H * W, w.sum, s);
+  prep(maps, target, w.sum, use_aug ? w.aug : nullptr, B, H, W, w.x0, w.xq, w.tgt, s);
+  const int H2 = H / 2, W2 = W / 2, H4 = H / 4, W4 = W / 4;
+  conv_fwd(dn, E1A, w.x0, 8, w.a1a, c1, B, H, W, s);
+  conv_fwd(dn, E1B, w.a1a, c1, w.cat1 + c2, c2 + c1, B, H, W, s);
+  pool(w.cat1 + c2, c2 + c1, w.pool1, c1, B, H, W, c1, s);
+  conv_fwd(dn, E2A, w.pool1, c1, w.a2a, c2, B, H2, W2, s);
+  conv_fwd(dn, E2B, w.a2a, c2, w.cat2 + c3, c3 + c2, B, H2, W2, s);
+  pool(w.cat2 + c3, c3 + c2, w.pool2, c2, B, H2, W2, c2, s);
+  conv_fwd(dn, M3A, w.pool2, c2, w.a3a, c3, B, H4, W4, s);
+  conv_fwd(dn, M3B, w.a3a, c3, w.m3, c3, B, H4, W4, s);
+  up(w.m3, c3, w.cat2, c3 + c2, B, H2, W2, c3, s);
+  conv_fwd(dn, D2A, w.cat2, c3 + c2, w.d2a, c2, B, H2, W2, s);
+  conv_fwd(dn, D2B, w.d2a, c2, w.d2, c2, B, H2, W2, s);
+  up(w.d2, c2, w.cat1, c2 + c1, B, H, W, c2, s);
+  conv_fwd(dn, D1A, w.cat1, c2 + c1, w.d1a, c1, B, H, W, s);
+  conv_fwd(dn, D1B, w.d1a, c1, w.d1, c1, B, H, W, s);
+  head(w.d1, c1, dn->d_p + dn->head_w, dn->d_p + dn->head_b, w.xq, w.out, P1, s);
+  DN_HIP(hipGetLastError(), "denoiser forward launch");
+  return KP_OK;
+}
+
+kp_status backward(kp_dn* dn, int B, int H, int W, hipStream_t s) {
+  Work& w = dn->w;
+  const int c1 = dn->c1, c2 = dn->c2, c3 = dn->c3;
+  const size_t P1 = (size_t)B * H * W;
+  const int H2 = H / 2, W2 = W / 2, H4 = H / 4, W4 = W / 4;
+  zero(dn->d_g, dn->n_params * 4, s);
+  zero(w.loss, 8, s);
+  loss(w.out, w.tgt, 2 * P1, w.go, w.loss, s);
+  head_bwd(w.go, w.d1, c1, dn->d_p + dn->head_w, dn->d_g + dn->head_w, dn->d_g + dn->head_b, w.g1, P1, s);
+  // decoder level 1
+  conv_wgrad(dn, D1B, w.g1, w.d1a, c1, B, H, W, s);
+  conv_dgrad(dn, D1B, w.g1, w.g1b, c1, w.d1a, c1, B, H, W, s);
+  conv_wgrad(dn, D1A, w.g1b, w.cat1, c2 + c1, B, H, W, s);
+  conv_dgrad(dn, D1A, w.g1b, w.gcat1, c2 + c1, nullptr, 0, B, H, W, s);
+  // decoder level 2
+  up_bwd(w.gcat1, c2 + c1, w.g2, c2, w.d2, c2, B, H, W, c2, s);
+  conv_wgrad(dn, D2B, w.g2, w.d2a, c2, B, H2, W2, s);
+  conv_dgrad(dn, D2B, w.g2, w.g2b, c2, w.d2a, c2, B, H2, W2, s);
+  conv_wgrad(dn, D2A, w.g2b, w.cat2, c3 + c2, B, H2, W2, s);
+  conv_dgrad(dn, D2A, w.g2b, w.gcat2, c3 + c2, nullptr, 0, B, H2, W2, s);
+  // bottleneck
+  up_bwd(w.gcat2, c3 + c2, w.g3, c3, w.m3, c3, B, H2, W2, c3, s);
+  conv_wgrad(dn, M3B, w.g3, w.a3a, c3, B, H4, W4, s);
+  conv_dgrad(dn, M3B, w.g3, w.g3b, c3, w.a3a, c3, B, H4, W4, s);
+  conv_wgrad(dn, M3A, w.g3b, w.pool2, c2, B, H4, W4, s);
+  conv_dgrad(dn, M3A, w.g3b, w.gpool2, c2, nullptr, 0, B, H4, W4, s);
+  // encoder level 2: skip gradient plus pooled path
+  pool_bwd_add(w.gcat2 + c3, c3 + c2, w.gpool2, c2, w.cat2 + c3, c3 + c2, w.ge2, c2, B, H2, W2, c2, s);
+  conv_wgrad(dn, E2B, w.ge2, w.a2a, c2, B, H2, W2, s);
+  conv_dgrad(dn, E2B, w.ge2, w.ge2b, c2, w.a2a, c2, B, H2, W2, s);
+  conv_wgrad(dn, E2A, w.ge2b, w.pool1, c1, B, H2, W2, s);
+  conv_dgrad(dn, E2A, w.ge2b, w.gpool1, c1, nullptr, 0, B, H2, W2, s);
+  // encoder level 1
+  pool_bwd_add(w.gcat1 + c2, c2 + c1, w.gpool1, c1, w.cat1 + c2, c2 + c1, w.ge1, c1, B, H, W, c1, s);
+  conv_wgrad(dn, E1B, w.ge1, w.a1a, c1, B, H, W, s);
+  conv_dgrad(dn, E1B, w.ge1, w.ge1b, c1, w.a1a, c1, B, H, W, s);
+  conv_wgrad(dn, E1A, w.ge1b, w.x0, 8, B, H, W, s);
+  DN_HIP(hipGetLastError(), "denoiser backward launch");
+  return KP_OK;
+}
+
+kp_status check_n(kp_dn* dn, size_t n) {
+  if (n != dn->n_params) return fail(dn, KP_ERR_ARG, "n = %zu but the network has %zu parameters", n, dn->n_params);
+  return KP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kp_status kp_dn_create(int device, int32_t c1, int32_t c2, int32_t c3, kp_dn** out) {
+  if (!out) return KP_ERR_ARG;
+  *out = nullptr;
+  for (int32_t c : {c1, c2, c3})
+    if (c < 16 || c > 512 || c % 16) return KP_ERR_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return KP_ERR_DEVICE;
+  kp_dn* dn = new (std::nothrow) kp_dn;
+  if (!dn) return KP_ERR_OOM;
+  dn->device = device;
+  dn->c1 = c1;
+  dn->c2 = c2;
+  dn->c3 = c3;
+  const int io[NLAYER][2] = {{4, c1},       {c1, c1}, {c1, c2},       {c2, c2}, {c2, c3},
+                             {c3, c3},      {c3 + c2, c2}, {c2, c2},  {c2 + c1, c1}, {c1, c1}};
+  size_t off = 0, pk = 0;
+  for (int l = 0; l < NLAYER; ++l) {
+    Layer& y = dn->L[l];
+    y.cin_true = io[l][0];
+    y.cout = io[l][1];
+    y.cin = round_up(y.cin_true, 8);
+    y.kp = round_up(9 * y.cin, 32);
+    y.kpd = l == E1A ? 0 : round_up(9 * y.cout, 32);
+    y.w_off = off;
+    off += (size_t)y.cout * 9 * y.cin_true;
+    y.b_off = off;
+    off += y.cout;
+    y.pk_off = pk;
+    pk += (size_t)y.cout * y.kp;
+    pk = (pk + 127) / 128 * 128;
+    y.pkd_off = pk;
+    pk += (size_t)y.cin_true * y.kpd;
+    pk = (pk + 127) / 128 * 128;
+  }
+  dn->head_w = off;
+  off += 2 * (size_t)c1;
+  dn->head_b = off;
+  off += 2;
+  dn->n_params = off;
+  dn->pk_n = pk;
+  const size_t np = (off + 63) / 64 * 64;
+  if (hipSetDevice(device) != hipSuccess || hipMalloc(&dn->d_p, 4 * np * sizeof(float)) != hipSuccess ||
+      hipMalloc(&dn->d_pk, pk * 2) != hipSuccess) {
+    kp_dn_destroy(dn);
+    return KP_ERR_OOM;
+  }
+  dn->d_g = dn->d_p + np;
+  dn->d_m = dn->d_g + np;
+  dn->d_v = dn->d_m + np;
+  for (auto& e : dn->ev)
+    if (hipEventCreate(&e) != hipSuccess) {
+      kp_dn_destroy(dn);
+      return KP_ERR_DEVICE;
+    }
+  zero(dn->d_p, 4 * np * sizeof(float), nullptr);
+  zero(dn->d_pk, pk * 2, nullptr);
+  if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    kp_dn_destroy(dn);
+    return KP_ERR_DEVICE;
+  }
+  *out = dn;
+  return KP_OK;
+}
+
+void kp_dn_destroy(kp_dn* dn) {
+  if (!dn) return;
+  (void)hipSetDevice(dn->device);
+  (void)hipDeviceSynchronize();
+  for (void* p : {(void*)dn->d_p, (void*)dn->d_pk, dn->w.mem})
+    if (p) (void)hipFree(p);
+  for (auto& e : dn->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete dn;
+}
+
+const char* kp_dn_last_error(const kp_dn* dn) { return dn ? dn->err.c_str() : "null denoiser"; }
+
+kp_status kp_dn_num_params(const kp_dn* dn, size_t* n) {
+  if (!dn || !n) return KP_ERR_ARG;
+  *n = dn->n_params;
+  return KP_OK;
+}
+
+kp_status kp_dn_set_params(kp_dn* dn, const float* host, size_t n) {
+  if (!dn) return KP_ERR_ARG;
+  if (!host) return fail(dn, KP_ERR_ARG, "host_params is NULL");
+  if (kp_status st = check_n(dn, n)) return st;
+  for (size_t k = 0; k < n; ++k)
+    if (!std::isfinite(host[k]))
+      return fail(dn, KP_ERR_ARG, "parameter %zu is not finite", k);
+  DN_HIP(hipSetDevice(dn->device), "hipSetDevice");
+  DN_HIP(hipDeviceSynchronize(), "synchronise");
+  DN_HIP(hipMemcpy(dn->d_p, host, n * 4, hipMemcpyHostToDevice), "parameter upload");
+  zero(dn->d_m, n * 4, nullptr);
+  zero(dn->d_v, n * 4, nullptr);
+  DN_HIP(hipGetLastError(), "fill launch");
+  DN_HIP(hipDeviceSynchronize(), "synchronise");
+  dn->step = 0;
+  dn->packed = false;
+  return KP_OK;
+}
+
+static kp_status copy_out(kp_dn* dn, float* host, const float* dev, size_t n, const char* what) {
+  if (!host) return fail(dn, KP_ERR_ARG, "%s destination is NULL", what);
+  if (kp_status st = check_n(dn, n)) return st;
+  DN_HIP(hipSetDevice(dn->device), "hipSetDevice");
+  DN_HIP(hipDeviceSynchronize(), "synchronise");
+  DN_HIP(hipMemcpy(host, dev, n * 4, hipMemcpyDeviceToHost), what);
+  return KP_OK;
+}
+
+kp_status kp_dn_get_params(kp_dn* dn, float* host, size_t n) {
+  if (!dn) return KP_ERR_ARG;
+  return copy_out(dn, host, dn->d_p, n, "parameter copy");
+}
+
+kp_status kp_dn_get_grads(kp_dn* dn, float* host, size_t n) {
+  if (!dn) return KP_ERR_ARG;
+  return copy_out(dn, host, dn->d_g, n, "gradient copy");
+}
+
+kp_status kp_dn_get_adam(kp_dn* dn, float* m, float* v, size_t n, int32_t* step) {
+  if (!dn) return KP_ERR_ARG;
+  if (!step) return fail(dn, KP_ERR_ARG, "step is NULL");
+  if (kp_status st = copy_out(dn, m, dn->d_m, n, "first-moment copy")) return st;
+  if (kp_status st = copy_out(dn, v, dn->d_v, n, "second-moment copy")) return st;
+  *step = dn->step;
+  return KP_OK;
+}
+
+kp_status kp_dn_set_adam(kp_dn* dn, const float* m, const float* v, size_t n, int32_t step) {
+  if (!dn) return KP_ERR_ARG;
+  if (!m || !v) return fail(dn, KP_ERR_ARG, "moment array is NULL");
+  if (step < 0) return fail(dn, KP_ERR_ARG, "step must be >= 0 (got %d)", step);
+  if (kp_status st = check_n(dn, n)) return st;
+  for (size_t k = 0; k < n; ++k)
+    if (!std::isfinite(m[k]) || !std::isfinite(v[k]) || v[k] < 0.0f)
+      return fail(dn, KP_ERR_ARG, "moment %zu is not finite or the second moment is negative", k);
+  DN_HIP(hipSetDevice(dn->device), "hipSetDevice");
+  DN_HIP(hipDeviceSynchronize(), "synchronise");
+  DN_HIP(hipMemcpy(dn->d_m, m, n * 4, hipMemcpyHostToDevice), "first-moment upload");
+  DN_HIP(hipMemcpy(dn->d_v, v, n * 4, hipMemcpyHostToDevice), "second-moment upload");
+  dn->step = step;
+  return KP_OK;
+}
+
+kp_status kp_dn_infer(kp_dn* dn, const double* d_maps, double* d_out, int32_t B, int32_t H, int32_t W,
+                      void* stream) {
+  if (!dn) return KP_ERR_ARG;
+  if (kp_status st = check_maps(dn, d_maps, d_out, B, H, W)) return st;
+  if ((const void*)d_maps == (const void*)d_out) return fail(dn, KP_ERR_ARG, "d_out may not alias d_maps");
+  hipStream_t s = (hipStream_t)stream;
+  DN_HIP(hipSetDevice(dn->device), "hipSetDevice");
+  if (kp_status st = ensure_work(dn, (size_t)B * H * W, B)) return st;
+  marks_reset(dn);
+  dn->ev_total0 = mark_begin(dn, s);
+  if (kp_status st = ensure_packed(dn, s)) return st;
+  if (kp_status st = forward(dn, d_maps, nullptr, B, H, W, false, s)) return st;
+  output(d_maps, dn->w.out, dn->w.sum, B, H * W, d_out, s);
+  DN_HIP(hipGetLastError(), "output launch");
+  if (dn->ev_total0 >= 0) {
+    dn->ev_total1 = dn->ev_total0 + 1;
+    DN_HIP(hipEventRecord(dn->ev[dn->ev_total1], s), "event record");
+  }
+  return KP_OK;
+}
+
+kp_status kp_dn_backward(kp_dn* dn, const double* d_low, const double* d_high, int32_t B, int32_t H, int32_t W,
+                         const int32_t* host_aug, double* loss_out, void* stream) {
+  if (!dn) return KP_ERR_ARG;
+  if (kp_status st = check_maps(dn, d_low, d_high, B, H, W)) return st;
+  if (!loss_out) return fail(dn, KP_ERR_ARG, "loss is NULL");
+  if (host_aug)
+    for (int b = 0; b < B; ++b) {
+      if (host_aug[b] < 0 || host_aug[b] > 7)
+        return fail(dn, KP_ERR_ARG, "aug[%d] = %d is outside 0..7", b, host_aug[b]);
+      if ((host_aug[b] & 1) && H != W)
+        return fail(dn, KP_ERR_ARG, "aug[%d] = %d rotates by a quarter turn but the maps are %d x %d", b,
+                    host_aug[b], H, W);
+    }
+  hipStream_t s = (hipStream_t)stream;
+  DN_HIP(hipSetDevice(dn->device), "hipSetDevice");
+  if (kp_status st = ensure_work(dn, (size_t)B * H * W, B)) return st;
+  if (host_aug)
+    DN_HIP(hipMemcpyAsync(dn->w.aug, host_aug, (size_t)B * 4, hipMemcpyHostToDevice, s), "augmentation upload");
+  marks_reset(dn);
+  dn->ev_total0 = mark_begin(dn, s);
+  if (kp_status st = ensure_packed(dn, s)) return st;
+  if (kp_status st = forward(dn, d_low, d_high, B, H, W, host_aug != nullptr, s)) return st;
+  if (kp_status st = backward(dn, B, H, W, s)) return st;
+  if (dn->ev_total0 >= 0) {
+    dn->ev_total1 = dn->ev_total0 + 1;
+    DN_HIP(hipEventRecord(dn->ev[dn->ev_total1], s), "event record");
+  }
+  double l = 0.0;
+  DN_HIP(hipMemcpyAsync(&l, dn->w.loss, 8, hipMemcpyDeviceToHost, s), "loss copy");
+  DN_HIP(hipStreamSynchronize(s), "synchronise");
+  *loss_out = l / (2.0 * (double)B * H * W);
+  return KP_OK;
+}
+
+kp_status kp_dn_adam_step(kp_dn* dn, float lr, void* stream) {
+  if (!dn) return KP_ERR_ARG;
+  if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(dn, KP_ERR_ARG, "lr must be finite and > 0");
+  hipStream_t s = (hipStream_t)stream;
+  DN_HIP(hipSetDevice(dn->device), "hipSetDevice");
+  dn->step += 1;
+  adam(dn->d_p, dn->d_g, dn->d_m, dn->d_v, dn->n_params, lr, dn->step, s);
+  DN_HIP(hipGetLastError(), "Adam launch");
+  dn->packed = false;
+  return KP_OK;
+}
+
+kp_status kp_dn_train_step(kp_dn* dn, const double* d_low, const double* d_high, int32_t B, int32_t H, int32_t W,
+                           const int32_t* host_aug, float lr, double* loss_out, void* stream) {
+  if (!dn) return KP_ERR_ARG;
+  if (!(lr > 0.0f) || !std::isfinite(lr)) return fail(dn, KP_ERR_ARG, "lr must be finite and > 0");
+  if (kp_status st = kp_dn_backward(dn, d_low, d_high, B, H, W, host_aug, loss_out, stream)) return st;
+  return kp_dn_adam_step(dn, lr, stream);
+}
+
+kp_status kp_dn_get_timing(kp_dn* dn, kp_dn_timing* out) {
+  if (!dn || !out) return KP_ERR_ARG;
+  if (dn->ev_total1 < 0) return fail(dn, KP_ERR_STATE, "no timed denoiser call yet");
+  DN_HIP(hipEventSynchronize(dn->ev[dn->ev_total1]), "event synchronise");
+  kp_dn_timing t{};
+  float ms = 0.f;
+  DN_HIP(hipEventElapsedTime(&ms, dn->ev[dn->ev_total0], dn->ev[dn->ev_total1]), "event time");
+  t.ms_total = ms;
+  for (const auto& m : dn->marks) {
+    DN_HIP(hipEventElapsedTime(&ms, dn->ev[m.a], dn->ev[m.b]), "event time");
+    if (m.cat == CAT_CONV) {
+      t.ms_conv += ms;
+      t.conv_flop += m.flop;
+    } else {
+      t.ms_wgrad += ms;
+      t.wgrad_flop += m.flop;
+    }
+  }
+  t.ms_other = t.ms_total - t.ms_conv - t.ms_wgrad;
+  *out = t;
+  return KP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+// kp_dn_internal.hpp -- launch interface between the denoiser's host code
+// (kp_dn_api.cpp) and its kernels (kp_denoiser.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace kp {
+namespace dn {
+
+enum { CONV_RELU = 0, CONV_LINEAR = 1, CONV_MASK = 2 };
+
+// y[p][n] (stride ys) from x[p][c] (stride xs, cin channels per tap, cin % 8 == 0)
+// and GEMM weights w[nout][kp] (kp % 32 == 0, kp >= 9 cin, nout % 16 == 0).
+struct ConvArgs {
+  const uint16_t* x;
+  int xs, cin;
+  const uint16_t* w;
+  int kp, nout;
+  const float* bias;     // CONV_RELU / CONV_LINEAR
+  uint16_t* y;
+  int ys;
+  const uint16_t* mask;  // CONV_MASK: zero the output where mask[p][n] <= 0 (none if null)
+  int ms;
+  int B, H, W;
+};
+
+// gw[cout][9][cin_true] += gradient of a conv layer's weights from the
+// gradient gz[p][co] (stride gzs) of its pre-activation output and its input
+// x[p][c] (stride xs, cin channels per tap, cin % 8 == 0, cout % 16 == 0).
+struct WgradArgs {
+  const uint16_t* gz;
+  int gzs, cout;
+  const uint16_t* x;
+  int xs, cin, cin_true;
+  float* gw;
+  int B, H, W;
+  int chunk, ktiles;  // set by the launcher
+};
+
+void conv3(const ConvArgs& a, int mode, hipStream_t s);
+void wgrad(WgradArgs a, float* gb, hipStream_t s);
+void pool(const uint16_t* x, int xs, uint16_t* y, int ys, int B, int H, int W, int C, hipStream_t s);
+void up(const uint16_t* x, int xs, uint16_t* y, int ys, int B, int H, int W, int C, hipStream_t s);
+void up_bwd(const uint16_t* gy, int gys, uint16_t* gx, int gxs, const uint16_t* mask, int ms, int B, int H, int W,
+            int C, hipStream_t s);
+void pool_bwd_add(const uint16_t* a, int as, const uint16_t* g, int gs, const uint16_t* mask, int ms, uint16_t* dst,
+                  int ds, int B, int H, int W, int C, hipStream_t s);
+void sum_I(const double* maps, int B, int HW, double* sum, hipStream_t s);
+void prep(const double* maps, const double* target, const double* sum, const int32_t* aug, int B, int H, int W,
+          uint16_t* x, float* xq, float* tgt, hipStream_t s);
+void head(const uint16_t* d, int C, const float* hw, const float* hb, const float* xq, float* out, size_t P,
+          hipStream_t s);
+void loss(const float* out, const float* tgt, size_t n, float* go, double* l, hipStream_t s);
+void head_bwd(const float* go, const uint16_t* d, int C, const float* hw, float* ghw, float* ghb, uint16_t* gd,
+              size_t P, hipStream_t s);
+void output(const double* maps, const float* out, const double* sum, int B, int HW, double* dst, hipStream_t s);
+void adam(float* p, const float* g, float* m, float* v, size_t n, float lr, int t, hipStream_t s);
+void pack(const float* wf, int cout, int cin, int cin_true, int kp, int kpd, uint16_t* w, uint16_t* wd,
+          hipStream_t s);
+void zero(void* p, size_t bytes, hipStream_t s);
+
+}  // namespace dn
+}  // namespace kp

@@ -238,3 +238,74 @@ def pencil_slab(n_z=256, tau_total=1.0, p0=0.01, alpha3_scale=0.0, twist=True,
                 source=dict(kind=1, pos=(0.0, 0.0, start_tau), dir=(0.0, 0.0, -1.0), lum=1.0),
                 views=[view(0.0, 0.0, 4)], packets=[1],
                 opts=dict(default_opts(0), rr_wmin=0.0), precision="f64")
+
+
+# --------------------------------------------------------------------------
+# denoiser inputs: parameter initialisation, synthetic maps, training disks
+# --------------------------------------------------------------------------
+DN_WIDTHS = (48, 96, 192)
+DN_LAYERS = ("e1a", "e1b", "e2a", "e2b", "m3a", "m3b", "d2a", "d2b", "d1a", "d1b")
+
+
+def denoiser_layer_io(widths=DN_WIDTHS, cin=4):
+    """(input, output) channels of each 3x3 convolution, in parameter order."""
+    c1, c2, c3 = widths
+    return [(cin, c1), (c1, c1), (c1, c2), (c2, c2), (c2, c3), (c3, c3),
+            (c3 + c2, c2), (c2, c2), (c2 + c1, c1), (c1, c1)]
+
+
+def denoiser_params(seed=0, widths=DN_WIDTHS, bias_std=0.0, head_std=0.0) -> np.ndarray:
+    """Flat FP32 parameter vector: He-normal 3x3 weights [cout][3][3][cin]
+    (std sqrt(2 / (9 cin))) and N(0, bias_std) biases for each convolution,
+    then the head [2][c1] ~ N(0, head_std) and its bias N(0, bias_std).  With
+    head_std = 0 the untrained network is the identity on Q and U."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for cin, cout in denoiser_layer_io(widths):
+        parts.append(rng.standard_normal(cout * 9 * cin) * math.sqrt(2.0 / (9 * cin)))
+        parts.append(rng.standard_normal(cout) * bias_std)
+    parts.append(rng.standard_normal(2 * widths[0]) * head_std)
+    parts.append(rng.standard_normal(2) * bias_std)
+    return np.concatenate(parts).astype(np.float32)
+
+
+def synthetic_stokes_maps(seed, batch, height, width, p_max=0.3, noise=0.1) -> np.ndarray:
+    """[batch, 4, height, width] FP64 Stokes maps with the structure of a
+    scattered-light image: I a smooth positive blob plus a floor, a
+    polarization fraction up to p_max with a smoothly varying angle, V small,
+    and multiplicative noise of relative size `noise`."""
+    rng = np.random.default_rng(seed)
+    yy, xx = np.meshgrid(np.linspace(-1, 1, height), np.linspace(-1, 1, width), indexing="ij")
+    out = np.empty((batch, 4, height, width))
+    for b in range(batch):
+        cx, cy, r0 = rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3), rng.uniform(0.3, 0.8)
+        rr = np.hypot(xx - cx, yy - cy)
+        I = np.exp(-(rr / r0) ** 2) + 0.05
+        p = p_max * np.clip(rr / r0, 0.0, 1.0)
+        chi = np.arctan2(yy - cy, xx - cx) + rng.uniform(0, np.pi)
+        n = 1.0 + noise * rng.standard_normal((4, height, width))
+        out[b, 0] = I * np.abs(n[0])
+        out[b, 1] = I * p * np.cos(2 * chi) * n[1]
+        out[b, 2] = I * p * np.sin(2 * chi) * n[2]
+        out[b, 3] = 0.01 * I * rng.standard_normal((height, width))
+    return out
+
+
+def denoiser_disk(seed, packets, n=256, npix=None) -> dict:
+    """One member of the denoiser's training family: the flared disk with
+    cos(inclination) ~ U[0, 1] for each of 8 views (azimuth 0), h/r
+    prefactor ~ U[0.05, 0.15], and with probability 1/2 aligned oblate grains
+    in the helical field, else Rayleigh spheres.  One run images all views."""
+    rng = np.random.default_rng([seed, 4])
+    h0 = float(rng.uniform(0.05, 0.15))
+    aligned = bool(rng.uniform() < 0.5)
+    incl = np.degrees(np.arccos(rng.uniform(0.0, 1.0, 8)))
+    grid = _cube(n)
+    rho, kext = disk_density(grid, h0=h0)
+    npix = npix or n
+    dust = oblate_dust(kext, 0.5) if aligned else sphere_dust(kext, 0.5)
+    return dict(name=f"dn_disk{n}", grid=grid, rho=_flat(rho),
+                bhat=helical_field(grid) if aligned else None, dust=[dust],
+                source=dict(kind=0, pos=(0.0, 0.0, 0.0), dir=(0.0, 0.0, 1.0), lum=1.0),
+                views=[view(float(t), 0.0, npix) for t in incl], packets=[int(packets)],
+                opts=default_opts(seed), precision="f32", h0=h0, aligned=aligned)

@@ -62,3 +62,35 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     mod = importlib.util.module_from_spec(spec)
     with pytest.raises(ImportError):
         spec.loader.exec_module(mod)
+
+
+def declared_denoiser():
+    txt = open(os.path.join(ROOT, "include", "polrad_denoiser.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:kp_status|void|const char \*)\s*(kp_\w+)\s*\(", txt, re.M)))
+
+
+def test_denoiser_header_symbols_exported_and_bound():
+    from paper_2512_01283_amd import denoiser as DN
+    names = declared_denoiser()
+    for must in ("kp_dn_create", "kp_dn_destroy", "kp_dn_infer", "kp_dn_backward", "kp_dn_adam_step",
+                 "kp_dn_train_step", "kp_dn_set_params", "kp_dn_get_params", "kp_dn_get_grads",
+                 "kp_dn_get_adam", "kp_dn_set_adam", "kp_dn_num_params", "kp_dn_last_error",
+                 "kp_dn_get_timing"):
+        assert must in names
+    lib = ctypes.CDLL(DN.P.LIB_PATH)
+    assert not [n for n in names if not hasattr(lib, n)]
+    assert DN.header_symbols() == names
+    assert sorted(DN._SIGS) == names
+    assert ctypes.sizeof(DN.kp_dn_timing) == 6 * 8
+
+
+def test_denoiser_without_device_and_bad_arguments():
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present")
+    from paper_2512_01283_amd import denoiser as DN
+    h = ctypes.c_void_p()
+    assert DN._lib.kp_dn_create(0, 48, 96, 192, ctypes.byref(h)) == DN.P.KP_ERR_DEVICE
+    assert DN._lib.kp_dn_create(0, 40, 96, 192, ctypes.byref(h)) == DN.P.KP_ERR_ARG
+    assert DN._lib.kp_dn_infer(None, None, None, 1, 16, 16, None) == DN.P.KP_ERR_ARG
+    assert DN._lib.kp_dn_num_params(None, None) == DN.P.KP_ERR_ARG

@@ -1,0 +1,225 @@
+"""GPU parity of the denoiser kernels (BF16 MFMA convolutions, FP32
+accumulation) against the FP64 NumPy oracle, through the C ABI.
+
+The oracle is evaluated on exactly the operands the kernels see: the
+parameters and the normalised input rounded to BF16 (nearest even), the
+residual base (Q, U) / s and the targets in FP32.  What remains is the
+rounding of every intermediate activation and gradient to BF16 and FP32
+accumulation order.  With unit roundoff u = 2^-9 and an RMS relative error
+u / sqrt(3) per rounding, L roughly norm-preserving layers give a relative
+output error near sqrt(L) u / sqrt(3): 3.6e-3 for the 10 convolutions of
+the forward pass, 5e-3 for the 20 of forward plus backward.  The tolerances
+below allow 4x that (relative L2 norm per tensor).
+"""
+import numpy as np
+import pytest
+
+from oracle import denoiser as D
+from paper_2512_01283_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_FWD = 1.5e-2
+TOL_GRAD = 2.0e-2
+
+
+def bf16(a):
+    """Round to BF16, nearest even, returned as FP64."""
+    u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def dihedral(m, code):
+    """Transform [4, H, W] maps by code = r + 4 f (mirror the width axis if f,
+    then r quarter turns) with the spin-2 Stokes sign rules."""
+    r, f = code & 3, code >> 2
+    out = m[:, :, ::-1] if f else m
+    out = np.rot90(out, r, axes=(1, 2)).copy()
+    out[1] *= (-1) ** r
+    out[2] *= (-1) ** (r + f)
+    out[3] *= (-1) ** f
+    return out
+
+
+def oracle_pass(params32, low, high=None, widths=W.DN_WIDTHS):
+    """Oracle forward (and backward if high is given) on the kernels' operands.
+    Returns dict(head, out, loss, grads, mean)."""
+    p = D.unflatten(bf16(params32).astype(np.float64), widths)
+    # biases and the head stay FP32 on the device: use them unrounded
+    p_full = D.unflatten(params32.astype(np.float64), widths)
+    for k in p:
+        if not k.endswith(".w") or k.startswith("head"):
+            p[k] = p_full[k]
+    mean = low[:, 0].mean(axis=(1, 2))
+    inv = 1.0 / mean
+    xs = np.float32(np.moveaxis(low, 1, -1) * inv[:, None, None, None]).astype(np.float64)
+    x = bf16(xs)
+    out_o, cache = D.forward(p, x)
+    head = out_o - x[..., 1:3]
+    out = xs[..., 1:3] + head
+    res = dict(head=head, out=out, mean=mean)
+    if high is not None:
+        t = np.float32(np.moveaxis(high[:, 1:3], 1, -1) * inv[:, None, None, None]).astype(np.float64)
+        res["loss"] = D.loss(out, t)
+        res["grads"] = D.backward(p, cache, out, t)
+    return res
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def dn():
+    from paper_2512_01283_amd import denoiser as DN
+    d = DN.Denoiser(0)
+    yield d
+    d.close()
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("shape", [(2, 32, 32), (3, 20, 28)])
+def test_forward_parity(dn, shape):
+    b, h, w = shape
+    params = W.denoiser_params(11, bias_std=0.05, head_std=0.05)
+    dn.set_params(params)
+    maps = W.synthetic_stokes_maps(5, b, h, w)
+    out = dn.infer(_dev(maps)).cpu().numpy()
+    ref = oracle_pass(params, maps)
+    mean = ref["mean"][:, None, None]
+    head_gpu = np.stack([out[:, 1] / mean, out[:, 2] / mean], -1) - \
+        np.float32(np.moveaxis(maps[:, 1:3], 1, -1) / mean[..., None]).astype(np.float64)
+    e = rel(head_gpu, ref["head"])
+    print(f"forward {shape}: relative error of the correction {e:.2e}")
+    assert e < TOL_FWD
+    # I and V pass through unchanged
+    assert np.array_equal(out[:, 0], maps[:, 0]) and np.array_equal(out[:, 3], maps[:, 3])
+
+
+@pytest.mark.parametrize("shape", [(2, 32, 32), (3, 20, 28)])
+def test_gradient_parity(dn, shape):
+    b, h, w = shape
+    params = W.denoiser_params(12, bias_std=0.05, head_std=0.05)
+    dn.set_params(params)
+    low = W.synthetic_stokes_maps(6, b, h, w, noise=0.3)
+    high = W.synthetic_stokes_maps(6, b, h, w, noise=0.0)
+    loss = dn.backward(_dev(low), _dev(high))
+    g = D.unflatten(dn.grads().astype(np.float64))
+    ref = oracle_pass(params, low, high)
+    assert abs(loss - ref["loss"]) <= TOL_FWD * ref["loss"]
+    worst = 0.0
+    for k, gr in ref["grads"].items():
+        e = rel(g[k], gr)
+        worst = max(worst, e)
+        assert e < TOL_GRAD, (k, e)
+    print(f"gradients {shape}: worst relative error {worst:.2e}, loss {loss:.6e} vs {ref['loss']:.6e}")
+
+
+def test_augmented_gradients_match_transformed_maps(dn):
+    b, h, w = 8, 16, 16
+    params = W.denoiser_params(13, bias_std=0.05, head_std=0.05)
+    dn.set_params(params)
+    low = W.synthetic_stokes_maps(7, b, h, w, noise=0.3)
+    high = W.synthetic_stokes_maps(7, b, h, w, noise=0.0)
+    codes = np.arange(8, dtype=np.int32)
+    loss = dn.backward(_dev(low), _dev(high), aug=codes)
+    g = D.unflatten(dn.grads().astype(np.float64))
+    lo_t = np.stack([dihedral(low[i], int(c)) for i, c in enumerate(codes)])
+    hi_t = np.stack([dihedral(high[i], int(c)) for i, c in enumerate(codes)])
+    ref = oracle_pass(params, lo_t, hi_t)
+    assert abs(loss - ref["loss"]) <= TOL_FWD * ref["loss"]
+    for k, gr in ref["grads"].items():
+        assert rel(g[k], gr) < TOL_GRAD, k
+
+
+def test_adam_step_matches_oracle(dn):
+    params = W.denoiser_params(14, bias_std=0.05, head_std=0.05)
+    dn.set_params(params)
+    low = W.synthetic_stokes_maps(8, 2, 16, 16, noise=0.3)
+    high = W.synthetic_stokes_maps(8, 2, 16, 16, noise=0.0)
+    dn.backward(_dev(low), _dev(high))
+    g32 = dn.grads()
+    lr = 1e-3
+    dn.adam_step(lr)
+    new = dn.params()
+    p = {"a": params.astype(np.float64)}
+    m, v = {"a": np.zeros(params.size)}, {"a": np.zeros(params.size)}
+    D.adam(p, {"a": g32.astype(np.float64)}, m, v, 1, lr=lr)
+    assert np.max(np.abs(new - p["a"])) <= 1e-6 * lr + 1e-7 * np.max(np.abs(params))
+    m_d, v_d, step = dn.adam_state()
+    assert step == 1
+    assert np.allclose(m_d, m["a"], rtol=1e-6, atol=1e-30)
+    assert np.allclose(v_d, v["a"], rtol=1e-5, atol=1e-35)
+
+
+def test_training_reduces_loss(dn):
+    dn.set_params(W.denoiser_params(15))
+    low = _dev(W.synthetic_stokes_maps(9, 4, 32, 32, noise=0.3))
+    high = _dev(W.synthetic_stokes_maps(9, 4, 32, 32, noise=0.0))
+    first = dn.train_step(low, high, 1e-3)
+    for _ in range(30):
+        last = dn.train_step(low, high, 1e-3)
+    assert np.isfinite(last) and last < 0.5 * first, (first, last)
+
+
+def test_checkpoint_resume(dn):
+    from paper_2512_01283_amd import denoiser as DN
+    low = _dev(W.synthetic_stokes_maps(10, 2, 16, 16, noise=0.3))
+    high = _dev(W.synthetic_stokes_maps(10, 2, 16, 16, noise=0.0))
+    dn.set_params(W.denoiser_params(16))
+    for _ in range(3):
+        dn.train_step(low, high, 1e-3)
+    p, (m, v, t) = dn.params(), dn.adam_state()
+    dn.train_step(low, high, 1e-3)
+    cont = dn.params()
+    other = DN.Denoiser(0, params=p)
+    other.set_adam_state(m, v, t)
+    other.train_step(low, high, 1e-3)
+    resumed = other.params()
+    other.close()
+    # the two continuations differ only in the order of FP32 gradient atomics
+    assert np.max(np.abs(resumed - cont)) <= 1e-5 * 1e-3 + 1e-6 * np.max(np.abs(cont))
+
+
+def test_workspace_regrowth_and_reuse(dn):
+    params = W.denoiser_params(17, bias_std=0.05, head_std=0.05)
+    dn.set_params(params)
+    small = W.synthetic_stokes_maps(11, 1, 16, 16)
+    big = W.synthetic_stokes_maps(12, 2, 48, 48)
+    a = dn.infer(_dev(small)).cpu().numpy()
+    dn.infer(_dev(big))
+    b = dn.infer(_dev(small)).cpu().numpy()
+    assert np.allclose(a, b, rtol=0, atol=1e-12 * np.abs(a).max())
+
+
+def test_argument_errors(dn):
+    import torch
+
+    from paper_2512_01283_amd import denoiser as DN
+    from paper_2512_01283_amd import polrad as P
+    m = _dev(W.synthetic_stokes_maps(13, 1, 16, 16))
+    with pytest.raises(P.KpError):
+        DN.kp_dn_create(0, (40, 96, 192))
+    with pytest.raises(P.KpError):
+        dn.infer(_dev(W.synthetic_stokes_maps(13, 1, 18, 16)))
+    with pytest.raises(P.KpError):
+        dn.backward(m, m, aug=[8])
+    with pytest.raises(P.KpError):
+        dn.backward(_dev(W.synthetic_stokes_maps(13, 1, 16, 20)),
+                    _dev(W.synthetic_stokes_maps(13, 1, 16, 20)), aug=[1])
+    with pytest.raises(P.KpError):
+        dn.adam_step(0.0)
+    z = np.zeros(dn.n + 1, np.float32)
+    assert DN._lib.kp_dn_set_params(dn.h, z.ctypes.data, z.size) == P.KP_ERR_ARG
+    bad = W.denoiser_params(0)
+    bad[5] = np.nan
+    with pytest.raises(P.KpError):
+        dn.set_params(bad)
+    with pytest.raises(P.KpError):
+        DN.kp_dn_infer(dn.h, m, m)
+    del torch
