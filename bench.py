@@ -4,9 +4,12 @@
 
 One step = one whole pass of the path over the workload: the persistent
 transport kernel (emission, cell marching, analytic dichroic extinction,
-coherency tally, scattering, roulette) for all packets, then the imaging
-ray-march for all views.  Inputs (density grid) are resident in HBM before
-the timed region; images stay on the device.
+coherency tally, scattering, roulette) for all packets, the imaging
+ray-march for all views, and the learned denoiser's inference on the eight
+maps.  Inputs (density grid) are resident in HBM before the timed region;
+images stay on the device.  The denoiser's training step (BF16 MFMA forward
+and backward, Adam) is timed separately, after the timed steps, on batches of
+those maps, and reported with its own MFMA roofline under "detail".
 
 Prints one JSON line (see the "metric" fields below) with a "roofline"
 object for the dominant kernel (transport) and a "cpu_baseline" object (the
@@ -25,6 +28,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+BF16_PEAK_TFLOPS = 2500.0
 METRIC = "Stokes packets/s at 256^3 disk; packets to fixed Q/U error, plain vs denoised"
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per cell step of the transport kernel on Rayleigh spheres:
@@ -47,6 +51,9 @@ def parse():
                     help="only run a device-to-device copy of this size (counter calibration)")
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--no-denoiser", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=10,
+                    help="timed denoiser training steps (batch of the 8 maps)")
     return ap.parse_args()
 
 
@@ -105,21 +112,37 @@ def main():
     ctx = P.Context(0).load(cfg)
     stream = torch.cuda.current_stream()
     opts = dict(block_size=args.block_size, blocks_per_cu=args.blocks_per_cu)
+    dn = None
+    if not args.no_denoiser:
+        from paper_2512_01283_amd import denoiser as DN
+        dn = DN.Denoiser(0, params=W.denoiser_params(0))
+    nv, npix = len(cfg["views"]), cfg["views"][0]["npx"]
+    maps = torch.empty((nv, 4, npix, npix), dtype=torch.float64, device="cuda")
+    den = torch.empty_like(maps)
+
+    def one_step():
+        ctx.run(stream=stream, **opts)
+        if dn is not None:
+            ctx.images_device(out=maps.view(1, nv, 4, npix, npix), stream=stream)
+            dn.infer(maps, den, stream=stream)
 
     for w in range(args.warmup):
-        ctx.run(stream=stream, **opts)
+        one_step()
         print(f"warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    ms_t, ms_i, steps = [], [], []
+    ms_t, ms_i, ms_d, steps = [], [], [], []
     t0 = time.perf_counter()
     for k in range(args.steps):
-        ctx.run(stream=stream, **opts)
+        one_step()
         st = ctx.stats()
         ms_t.append(st["ms_transport"])
         ms_i.append(st["ms_image"])
         steps.append(st["cell_steps"])
+        if dn is not None:
+            ms_d.append(dn.timing())
         print(f"step {k + 1}/{args.steps}: transport {st['ms_transport']:.1f} ms, imaging "
-              f"{st['ms_image']:.1f} ms", file=sys.stderr, flush=True)
+              f"{st['ms_image']:.1f} ms" + (f", denoiser {ms_d[-1]['ms_total']:.2f} ms" if ms_d else ""),
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
@@ -157,6 +180,35 @@ def main():
                    "algorithmic_bytes_per_cell_step": BYTES_PER_STEP_SPHERE,
                    "scatterings": st["scatterings"], "rr_kills": st["rr_kills"]},
     }
+    if dn is not None:
+        inf = {k: float(np.mean([t[k] for t in ms_d])) for k in ms_d[0]}
+        d = {"widths": list(dn.widths), "params": dn.n, "batch": nv, "npix": npix,
+             "infer_ms": inf["ms_total"], "infer_conv_ms": inf["ms_conv"],
+             "infer_conv_tflops": inf["conv_flop"] / (inf["ms_conv"] * 1e-3) / 1e12}
+        d["infer_conv_mfma_frac"] = d["infer_conv_tflops"] / BF16_PEAK_TFLOPS
+        if args.train_steps > 0:
+            # training on the step's maps (input and target the same here: the
+            # cost of a step does not depend on the data)
+            dn.train_step(maps, den, 1e-4)
+            tr = []
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.train_steps):
+                dn.train_step(maps, den, 1e-4)
+                tr.append(dn.timing())
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t1) / args.train_steps
+            tt = {k: float(np.mean([t[k] for t in tr])) for k in tr[0]}
+            d.update({"train_step_ms_wall": 1e3 * wall, "train_step_ms_device": tt["ms_total"],
+                      "train_conv_ms": tt["ms_conv"], "train_wgrad_ms": tt["ms_wgrad"],
+                      "train_other_ms": tt["ms_other"],
+                      "train_conv_tflops": tt["conv_flop"] / (tt["ms_conv"] * 1e-3) / 1e12,
+                      "train_wgrad_tflops": tt["wgrad_flop"] / (tt["ms_wgrad"] * 1e-3) / 1e12,
+                      "train_images_per_s": nv / wall})
+            d["train_conv_mfma_frac"] = d["train_conv_tflops"] / BF16_PEAK_TFLOPS
+            d["train_wgrad_mfma_frac"] = d["train_wgrad_tflops"] / BF16_PEAK_TFLOPS
+        out["detail"]["denoiser"] = d
+        dn.close()
     if not args.no_cpu_baseline:
         print("timing the oracle on a bounded sample ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample)

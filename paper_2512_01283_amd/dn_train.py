@@ -1,0 +1,207 @@
+"""Training and evaluation driver of the Stokes-map denoiser.
+
+Pairs come from the transport itself: each member of the randomised disk
+family (workloads.denoiser_disk) is run twice with independent random
+streams, once with few packets (the input) and once with many (the target);
+one run images all eight views.  The target's own Monte Carlo noise is
+independent of the input's and has zero mean, so the mean-squared-error
+minimiser is the same as for a noiseless target (Lehtinen et al. 2018,
+"Noise2Noise"); the target only needs enough packets for a useful gradient
+signal, not the full reference count.
+
+Evaluation follows the packets-to-fixed-error protocol:
+  E(N) = sqrt( sum_w [(Q_N - Q_ref)^2 + (U_N - U_ref)^2] / sum_w I_ref^2 )
+over pixels with I_ref > 1e-3 max I_ref, per image, averaged over the test
+images; eps = E_plain(1e7); N_plain(eps) from a fit E = a N^-1/2 over plain
+runs; N_den(eps) by log-log interpolation of the denoised error over the
+input packet counts; the reference's own error is estimated from two
+independent halves and must be at most eps / 3.
+
+    python -m paper_2512_01283_amd.dn_train --out gpurun_out/dn   # full run
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import time
+
+import numpy as np
+
+from . import denoiser as DN
+from . import polrad as P
+from . import workloads as W
+
+
+def run_images(ctx, packets, seed):
+    """Images [views, 4, H, W] (CUDA float64) of one run with its own stream seed."""
+    ctx.run([int(packets)], seed=int(seed))
+    return ctx.images_device()[0].clone()
+
+
+def make_pairs(seeds, n_lo, n_hi, n=256, npix=None, log=print):
+    """Returns (lo, hi) CUDA tensors [len(seeds) * 8, 4, H, W]."""
+    import torch
+    los, his = [], []
+    t0 = time.time()
+    for k, s in enumerate(seeds):
+        cfg = W.denoiser_disk(s, n_lo, n=n, npix=npix)
+        with P.Context(0) as ctx:
+            ctx.load(cfg)
+            los.append(run_images(ctx, n_lo, 2 * s + 1))
+            his.append(run_images(ctx, n_hi, 2 * s + 2))
+        if log and (k + 1) % 8 == 0:
+            log(f"  pairs: {k + 1}/{len(seeds)} disks, {time.time() - t0:.1f} s", flush=True)
+    torch.cuda.synchronize()
+    return torch.cat(los), torch.cat(his)
+
+
+def image_error(maps, ref):
+    """Per-image E (see module docstring); maps, ref CUDA [B, 4, H, W]."""
+    import torch
+    I = ref[:, 0]
+    mask = I > 1e-3 * I.amax(dim=(1, 2), keepdim=True)
+    num = ((maps[:, 1] - ref[:, 1]) ** 2 + (maps[:, 2] - ref[:, 2]) ** 2) * mask
+    den = (I ** 2) * mask
+    return torch.sqrt(num.sum(dim=(1, 2)) / den.sum(dim=(1, 2)))
+
+
+def train(dn, lo, hi, steps, batch=8, lr=1e-3, lr_min=1e-5, seed=0, aug=True, log=print,
+          log_every=200):
+    """Adam on random minibatches with random dihedral augmentation and a
+    cosine learning-rate decay.  Returns the list of (step, loss)."""
+    rng = np.random.default_rng(seed)
+    n = lo.shape[0]
+    hist = []
+    square = lo.shape[2] == lo.shape[3]
+    t0 = time.time()
+    for it in range(steps):
+        idx = rng.choice(n, size=min(batch, n), replace=False)
+        import torch
+        ii = torch.from_numpy(idx).cuda()
+        xb, yb = lo.index_select(0, ii).contiguous(), hi.index_select(0, ii).contiguous()
+        codes = None
+        if aug:
+            codes = rng.integers(0, 8, size=len(idx)).astype(np.int32)
+            if not square:
+                codes &= ~1
+        a = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * it / max(steps, 1)))
+        loss = dn.train_step(xb, yb, a, aug=codes)
+        hist.append((it, loss))
+        if log and (it % log_every == 0 or it == steps - 1):
+            log(f"  step {it}: loss {loss:.4e} lr {a:.2e} ({time.time() - t0:.1f} s)", flush=True)
+    return hist
+
+
+def evaluate(dn, seeds, plain_counts=(1e6, 3e6, 1e7, 3e7), den_counts=(1e5, 3e5, 1e6, 3e6),
+             ref_half=1.5e8, n=256, npix=None, log=print):
+    """Packets-to-fixed-error comparison of plain and denoised maps."""
+    import torch
+    Ep = {c: [] for c in plain_counts}
+    Ed = {c: [] for c in den_counts}
+    Ein = {c: [] for c in den_counts}
+    Eref = []
+    for s in seeds:
+        cfg = W.denoiser_disk(s, 1, n=n, npix=npix)
+        with P.Context(0) as ctx:
+            ctx.load(cfg)
+            h1 = run_images(ctx, ref_half, 10 * s + 1)
+            h2 = run_images(ctx, ref_half, 10 * s + 2)
+            ref = 0.5 * (h1 + h2)
+            # E of the mean of two halves = E(half1 - half2) / 2
+            Eref += (0.5 * image_error(h1, h2)).tolist()
+            for k, c in enumerate(plain_counts):
+                Ep[c] += image_error(run_images(ctx, c, 10 * s + 3 + k), ref).tolist()
+            for k, c in enumerate(den_counts):
+                m = run_images(ctx, c, 100 * s + 7 + k)
+                Ein[c] += image_error(m, ref).tolist()
+                Ed[c] += image_error(dn.infer(m), ref).tolist()
+        torch.cuda.synchronize()
+        if log:
+            log(f"  evaluated disk {s}", flush=True)
+    mean = {k: {c: float(np.mean(v)) for c, v in d.items()} for k, d in
+            (("plain", Ep), ("denoised", Ed), ("input", Ein))}
+    eps = mean["plain"][1e7]
+    # E = a N^-1/2 fitted in log space
+    xs = np.log(np.array(plain_counts))
+    ys = np.log(np.array([mean["plain"][c] for c in plain_counts]))
+    loga = float(np.mean(ys + 0.5 * xs))
+    n_plain = math.exp(2 * (loga - math.log(eps)))
+    slope = float(np.polyfit(xs, ys, 1)[0])
+    # interpolate log E_den against log N
+    dc = np.array(den_counts, dtype=float)
+    de = np.array([mean["denoised"][c] for c in den_counts])
+    if eps >= de[0]:
+        n_den = float(dc[0])  # reached at or below the smallest count tried
+        bound = "<="
+    elif eps < de.min():
+        n_den = float("nan")
+        bound = "not reached"
+    else:
+        order = np.argsort(dc)
+        le, lc = np.log(de[order]), np.log(dc[order])
+        n_den = float("nan")
+        for j in range(len(lc) - 1):
+            if (le[j] - math.log(eps)) * (le[j + 1] - math.log(eps)) <= 0:
+                t = (math.log(eps) - le[j]) / (le[j + 1] - le[j])
+                n_den = math.exp(lc[j] + t * (lc[j + 1] - lc[j]))
+                break
+        bound = "="
+    return dict(eps=eps, E_ref=float(np.mean(Eref)), ref_ok=bool(np.mean(Eref) <= eps / 3),
+                plain_slope=slope, N_plain=n_plain, N_den=n_den, N_den_bound=bound,
+                ratio=(n_plain / n_den) if n_den == n_den else None,
+                E=mean, seeds=list(seeds))
+
+
+def main(argv=None):
+    import torch
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--out", default="gpurun_out/dn")
+    ap.add_argument("--grid", type=int, default=256)
+    ap.add_argument("--npix", type=int, default=256)
+    ap.add_argument("--train-seeds", default="1000:1064")
+    ap.add_argument("--test-seeds", default="3000:3008")
+    ap.add_argument("--n-lo", type=float, default=1e6)
+    ap.add_argument("--n-hi", type=float, default=3e7)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--ref-half", type=float, default=1.5e8)
+    ap.add_argument("--init", default=None, help="start from saved parameters (.npy)")
+    ap.add_argument("--skip-eval", action="store_true")
+    a = ap.parse_args(argv)
+    os.makedirs(a.out, exist_ok=True)
+
+    def seeds(s):
+        lo, hi = (int(v) for v in s.split(":"))
+        return list(range(lo, hi))
+
+    log = print
+    t0 = time.time()
+    log(f"generating training pairs on {torch.cuda.get_device_name(0)}", flush=True)
+    lo, hi = make_pairs(seeds(a.train_seeds), a.n_lo, a.n_hi, n=a.grid, npix=a.npix, log=log)
+    t_gen = time.time() - t0
+    dn = DN.Denoiser(0)
+    init = np.load(a.init) if a.init else W.denoiser_params(0)
+    dn.set_params(init)
+    t1 = time.time()
+    hist = train(dn, lo, hi, a.steps, batch=a.batch, lr=a.lr, log=log)
+    torch.cuda.synchronize()
+    t_train = time.time() - t1
+    del lo, hi
+    np.save(os.path.join(a.out, "params.npy"), dn.params())
+    res = dict(train_seeds=a.train_seeds, n_lo=a.n_lo, n_hi=a.n_hi, steps=a.steps, batch=a.batch,
+               lr=a.lr, t_generate_s=t_gen, t_train_s=t_train,
+               loss_first=hist[0][1], loss_last=float(np.mean([l for _, l in hist[-50:]])))
+    if not a.skip_eval:
+        log("evaluating", flush=True)
+        res["eval"] = evaluate(dn, seeds(a.test_seeds), ref_half=a.ref_half, n=a.grid, npix=a.npix, log=log)
+    with open(os.path.join(a.out, "result.json"), "w") as f:
+        json.dump(res, f, indent=1)
+    log(json.dumps(res), flush=True)
+    dn.close()
+
+
+if __name__ == "__main__":
+    main()

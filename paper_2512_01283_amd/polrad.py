@@ -340,6 +340,17 @@ class Context:
         shape = (len(self.last_counts), len(v), 4, v[0]["npy"], v[0]["npx"])
         return kp_get_images(self.h, shape)
 
+    def images_device(self, out=None, stream=None):
+        """Images of the last step 2 as a float64 CUDA tensor
+        [n_lambda, n_views, 4, npy, npx] (copied on the device)."""
+        import torch
+        v = self.cfg["views"]
+        shape = (len(self.last_counts), len(v), 4, v[0]["npy"], v[0]["npx"])
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float64, device="cuda")
+        kp_get_images_device(self.h, out, stream)
+        return out
+
     def tally(self) -> np.ndarray:
         g = self.cfg["grid"]
         return kp_get_tally(self.h, len(self.last_counts), g["nx"] * g["ny"] * g["nz"])
