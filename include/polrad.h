@@ -95,7 +95,19 @@ typedef struct {
 
 /* Run options.
  *  seed            Philox4x64-10 key word 0 (key word 1 = wavelength index).
- *  transport_fp64  1: step 1 in FP64 (parity runs); 0: FP32 with FP64 tallies.
+ *  transport_fp64  arithmetic of step 1 (tallies are FP64 in every mode):
+ *                  0 = automatic: FP32 polarisation arithmetic for spherical
+ *                      grains, FP64 for aligned non-spherical grains;
+ *                  1 = FP64 throughout (parity runs);
+ *                  2 = FP32 polarisation arithmetic for every grain type.
+ *                  Geometry (positions, directions, scattering depths) is
+ *                  FP64 in every mode.  Aligned grains default to FP64
+ *                  because a thick dichroic cell (App. A) scales the two
+ *                  grain-frame components I+Q and I-Q by e^{-x_A} and e^{-x_B}
+ *                  with |x_A - x_B| up to ~10: it amplifies the ~6e-8 I
+ *                  representation error of an FP32 Stokes vector in the
+ *                  small component by up to e^{|x_A - x_B|}, so a few packets
+ *                  per thousand end with relative errors of 1e-4..1e-3.
  *  tally_mode      0 (only value): per-cell incident coherency tally.
  *  rr_wmin, rr_psurv  Russian roulette when I < rr_wmin * I0 (0 disables).
  *  max_events      scattering-event cap per packet (>= 1).

@@ -8,20 +8,24 @@
  * U of a map made with many more.  Monte Carlo noise falls only as N^-1/2, so
  * a good estimate saves packets.
  *
- * Network (all 3x3 convolutions have zero padding 1 and a bias; relu after
- * every one; widths c1, c2, c3):
- *   x    = (I, Q, U, V) / s, s = mean of I over the image     H x W, 4 ch
- *   e1   = conv(conv(x, 4->c1), c1->c1)                      H x W
- *   e2   = conv(conv(pool(e1), c1->c2), c2->c2)              H/2
- *   m3   = conv(conv(pool(e2), c2->c3), c3->c3)              H/4
- *   d2   = conv(conv([up(m3), e2], c3+c2->c2), c2->c2)       H/2
- *   d1   = conv(conv([up(d2), e1], c2+c1->c1), c1->c1)       H
- *   out  = (Q, U) / s + head(d1)        head: 1x1 convolution c1 -> 2
+ * Per image, with s = mean of I over the image and Ihat = I / s, the input
+ * features are x = (ln max(Ihat, 1e-6), Q/I, U/I, V/I) (the ratios 0 where
+ * I <= 0).  Network (all 3x3 convolutions have zero padding 1 and a bias;
+ * relu after every one; widths c1, c2, c3):
+ *   e1    = conv(conv(x, 4->c1), c1->c1)                      H x W
+ *   e2    = conv(conv(pool(e1), c1->c2), c2->c2)              H/2
+ *   m3    = conv(conv(pool(e2), c2->c3), c3->c3)              H/4
+ *   d2    = conv(conv([up(m3), e2], c3+c2->c2), c2->c2)       H/2
+ *   d1    = conv(conv([up(d2), e1], c2+c1->c1), c1->c1)       H
+ *   delta = head(d1)        head: 1x1 convolution c1 -> 2
  * pool = 2x2 mean, up = 2x nearest repeat, [a, b] = channel concatenation
- * (a first).  The denoised map is (I, out_Q s, out_U s, V).
- * Training minimises the mean over pixels and both channels of
- * (out - (Q, U)_target / s)^2, with s taken from the low-packet map, by Adam
- * (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on FP32 master weights.
+ * (a first).  Predicted fractions q' = Q/I + delta_0, u' = U/I + delta_1;
+ * the denoised map is (I, q' I, u' I, V).
+ * Training minimises, averaged over the images of a batch, the squared
+ * relative Q/U error of the prediction against the target maps (Q_t, U_t):
+ *   sum_p [(q' Ihat - Q_t/s)^2 + (u' Ihat - U_t/s)^2] / sum_p Ihat^2
+ * (s and Ihat from the input map), by Adam (beta1 0.9, beta2 0.999, eps
+ * 1e-8, bias-corrected) on FP32 master weights.
  *
  * Parameters are one flat FP32 array: for each convolution in the order
  * e1a e1b e2a e2b m3a m3b d2a d2b d1a d1b its weights [cout][3][3][cin]
@@ -87,7 +91,7 @@ kp_status kp_dn_infer(kp_dn *dn, const double *d_maps, double *d_out, int32_t ba
  * code a = r + 4 f mirrors the width axis when f = 1, then rotates the image
  * by r quarter turns (numpy's rot90 on the (height, width) axes), and maps
  * Stokes as (Q, U, V) -> ((-1)^r Q, (-1)^(r+f) U, (-1)^f V); odd r needs
- * height == width.  *loss (host) receives the mean squared error; the call
+ * height == width.  *loss (host) receives the loss above; the call
  * synchronises hip_stream. */
 kp_status kp_dn_backward(kp_dn *dn, const double *d_low, const double *d_high, int32_t batch,
                          int32_t height, int32_t width, const int32_t *host_aug, double *loss,

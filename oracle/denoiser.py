@@ -5,17 +5,23 @@ TEST INFRASTRUCTURE ONLY (imported by tests; never by the product path).
 The denoiser is not part of the paper's method: it is a small convolutional
 encoder-decoder that maps a low-packet Stokes map to an estimate of the
 high-packet map's Q and U.  This module states plainly what the HIP kernels
-compute, in FP64, with explicit backward passes:
+compute, in FP64, with explicit backward passes.
 
-  input x      [N, H, W, 4]   (I, Q, U, V) / s, s = mean I of the low map
+Per image with maps (I, Q, U, V) and s = mean of I over the image:
+  Ihat  = I / s
+  x     = (ln max(Ihat, 1e-6), Q/I, U/I, V/I)   [N, H, W, 4]  (0 where I <= 0)
+The network (widths c1, c2, c3):
   enc1  = relu(conv3(relu(conv3(x,  4->c1)), c1->c1))          H x W
   enc2  = relu(conv3(relu(conv3(pool(enc1), c1->c2)), c2->c2)) H/2
   mid   = relu(conv3(relu(conv3(pool(enc2), c2->c3)), c3->c3)) H/4
   dec2  = relu(conv3(relu(conv3([up(mid), enc2], c3+c2->c2)), c2->c2))
   dec1  = relu(conv3(relu(conv3([up(dec2), enc1], c2+c1->c1)), c1->c1))
-  out   = x[..., 1:3] + conv1(dec1, c1->2)                      (Q, U)
-  loss  = mean over N*H*W*2 of (out - target)^2
-
+  delta = conv1(dec1, c1->2)                                    [N, H, W, 2]
+Prediction: q' = Q/I + delta_0, u' = U/I + delta_1; denoised Q = q' I,
+U = u' I (I and V unchanged).  Loss against target maps (Q_t, U_t):
+  L = mean over images of  sum_p [(q' Ihat - Q_t/s)^2 + (u' Ihat - U_t/s)^2]
+                           / sum_p Ihat^2
+which is the squared relative Q/U error of the image.
 conv3 is a 3x3 cross-correlation with zero padding 1 and a bias; pool is a
 2x2 mean; up repeats each pixel 2x2; [a, b] concatenates channels.
 Weights of conv3 are stored [Cout, 3, 3, Cin], of conv1 [2, c1].
@@ -119,7 +125,7 @@ def relu(z):
 # network
 # --------------------------------------------------------------------------
 def forward(p, x):
-    """Returns (out [N,H,W,2], cache)."""
+    """Network output delta [N,H,W,2] and the cache for backward."""
     c = {"x": x}
 
     def block(name, inp):
@@ -135,23 +141,43 @@ def forward(p, x):
     m3 = block("m3", pool(e2))
     d2 = block("d2", np.concatenate([up(m3), e2], axis=3))
     d1 = block("d1", np.concatenate([up(d2), e1], axis=3))
-    head = d1 @ p["head.w"].T + p["head.b"]
-    return x[..., 1:3] + head, c
+    return d1 @ p["head.w"].T + p["head.b"], c
 
 
-def loss(out, target):
-    return float(np.mean((out - target) ** 2))
+def features(maps):
+    """[N, 4, H, W] Stokes maps -> (x [N,H,W,4], Ihat [N,H,W], s [N])."""
+    I, Q, U, V = (maps[:, k] for k in range(4))
+    s = I.mean(axis=(1, 2))
+    sd = np.where(s > 0, s, 1.0)
+    Ihat = np.where(s[:, None, None] > 0, I / sd[:, None, None], 0.0)
+    pos = I > 0
+    Id = np.where(pos, I, 1.0)
+    x = np.stack([np.log(np.maximum(Ihat, 1e-6)), np.where(pos, Q / Id, 0.0),
+                  np.where(pos, U / Id, 0.0), np.where(pos, V / Id, 0.0)], axis=-1)
+    return x, Ihat, s
 
 
-def backward(p, cache, out, target):
-    """Gradient of loss(out, target) w.r.t. every parameter (dict)."""
+def loss(delta, x, Ihat, target):
+    """target [N,H,W,2] = (Q_t, U_t) / s.  Returns L."""
+    e = (x[..., 1:3] + delta) * Ihat[..., None] - target
+    w = (Ihat ** 2).sum(axis=(1, 2))
+    return float(np.mean((e ** 2).sum(axis=(1, 2, 3)) / w))
+
+
+def loss_grad(delta, x, Ihat, target):
+    """dL / d delta."""
+    e = (x[..., 1:3] + delta) * Ihat[..., None] - target
+    w = (Ihat ** 2).sum(axis=(1, 2))
+    return 2.0 * e * Ihat[..., None] / (w[:, None, None, None] * delta.shape[0])
+
+
+def backward(p, cache, gdelta):
+    """Gradient of a loss with dL/d delta = gdelta w.r.t. every parameter."""
     g = {}
-    go = 2.0 * (out - target) / out.size
-    x = cache["x"]
     d1 = cache["d1"][2]
-    g["head.w"] = go.reshape(-1, 2).T @ d1.reshape(-1, d1.shape[-1])
-    g["head.b"] = go.reshape(-1, 2).sum(0)
-    gd1 = go @ p["head.w"]
+    g["head.w"] = gdelta.reshape(-1, 2).T @ d1.reshape(-1, d1.shape[-1])
+    g["head.b"] = gdelta.reshape(-1, 2).sum(0)
+    gd1 = gdelta @ p["head.w"]
 
     def block_back(name, gy):
         inp, ya, yb = cache[name]
@@ -187,8 +213,3 @@ def adam(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
         p[k] = p[k] - lr * mh / (np.sqrt(vh) + eps)
 
 
-def normalise(stokes):
-    """[.., 4, H, W] Stokes maps -> NHWC network input and the scale s."""
-    s = np.maximum(stokes[..., 0, :, :].mean(axis=(-1, -2)), 1e-300)
-    x = np.moveaxis(stokes, -3, -1) / s[..., None, None, None]
-    return x, s

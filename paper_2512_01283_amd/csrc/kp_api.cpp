@@ -412,7 +412,7 @@ kp_status kp_transport(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, vo
   const int bs = o->block_size ? o->block_size : 256;
   if (bs < 64 || bs > 256 || bs % 64) return fail(ctx, KP_ERR_ARG, "block_size must be 64, 128, 192 or 256");
   if (o->blocks_per_cu < 0 || o->blocks_per_cu > 64) return fail(ctx, KP_ERR_ARG, "blocks_per_cu out of range");
-  if (o->transport_fp64 != 0 && o->transport_fp64 != 1) return fail(ctx, KP_ERR_ARG, "transport_fp64 must be 0 or 1");
+  if (o->transport_fp64 < 0 || o->transport_fp64 > 2) return fail(ctx, KP_ERR_ARG, "transport_fp64 must be 0, 1 or 2");
   if (o->scatter_batch < 0 || o->scatter_batch > 64) return fail(ctx, KP_ERR_ARG, "scatter_batch must be in 0..64");
   if (o->scatter_wait < 0 || o->scatter_wait > 1024) return fail(ctx, KP_ERR_ARG, "scatter_wait must be in 0..1024");
 
@@ -470,7 +470,9 @@ kp_status kp_transport(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, vo
   bool sphere = true;
   for (int l = 0; l < nl; ++l) sphere = sphere && ctx->hdust[l].sphere;
   const bool aligned = ctx->d_bhat != nullptr;
-  const bool fp64 = o->transport_fp64 == 1;
+  // automatic precision: FP64 polarisation arithmetic for dichroic (aligned,
+  // non-spherical) grains, FP32 otherwise
+  const bool fp64 = o->transport_fp64 == 1 || (o->transport_fp64 == 0 && aligned && !sphere);
   int bpc = o->blocks_per_cu;
   if (bpc == 0) {
     bpc = transport_max_blocks_per_cu(fp64, aligned, sphere, bs);

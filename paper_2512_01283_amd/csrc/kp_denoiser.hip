@@ -269,7 +269,8 @@ __global__ void __launch_bounds__(256) k_conv3_tiled(ConvArgs a) {
 // a 64 x 64 (co, k) tile and a chunk of pixels; each 32-pixel slab of gz and
 // of the im2col matrix is loaded with 16-byte loads and written transposed to
 // LDS so that every lane's MFMA operand (8 consecutive pixels) is one 16-byte
-// LDS read.  Partial tiles are added to the FP32 gradient with atomics.
+// LDS read.  Partial tiles are added to the FP32 gradient with atomics; the
+// workgroups of the first K tile also add the bias gradient sum_p gz[p][co].
 // ---------------------------------------------------------------------------
 constexpr int WG_LDS_STRIDE = 40;  // 32 pixels + 8 pad (row = 80 bytes, 16-byte aligned)
 
@@ -294,12 +295,23 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
   f32x4 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // the first K tile's workgroups also sum gz over their pixels: the bias gradient
+  const bool do_bias = kt == 0 && a_ok;
+  float bsum[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) bsum[j] = 0.f;
   const u32x4 zero = {0u, 0u, 0u, 0u};
   for (int s0 = p_begin; s0 < p_end; s0 += 32) {
     const int p = s0 + sp;
     u32x4 va = zero, vb = zero;
     if (p < p_end) {
       if (a_ok) va = ld16(a.gz + (size_t)p * a.gzs + m0 + s8);
+      if (do_bias) {
+        float f[8];
+        unpack8(va, f);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bsum[j] += f[j];
+      }
       if (b_ok) {
         const int w = p % a.W, h = (p / a.W) % a.H, n = p / (a.W * a.H);
         const int hh = h + ldy, ww = w + ldx;
@@ -323,6 +335,15 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
     }
     __syncthreads();
   }
+  if (kt == 0) {
+    // lanes with equal (lane & 7) hold the same 8 channels: reduce them
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      for (int off = 8; off < 64; off <<= 1) bsum[j] += __shfl_xor(bsum[j], off);
+    if (lane < 8 && do_bias)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) atomicAdd(a.gb + m0 + s8 + j, bsum[j]);
+  }
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int k = kb + 16 * t + i;
@@ -333,16 +354,6 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
       const int co = m0 + 16 * wv + 4 * g + j;
       if (co < a.cout) atomicAdd(a.gw + ((size_t)co * 9 + kk) * a.cin_true + c, acc[t][j]);
     }
-  }
-}
-
-// gb[c] += sum_p gz[p][c]: a block sums 1024 pixels, one thread per channel
-__global__ void k_bias_grad(const uint16_t* __restrict__ gz, int gzs, int C, int P, float* __restrict__ gb) {
-  const int p0 = blockIdx.x * 1024, p1 = min(P, p0 + 1024);
-  for (int c = threadIdx.x; c < C; c += blockDim.x) {
-    float s = 0.f;
-    for (int p = p0; p < p1; ++p) s += bf2f(gz[(size_t)p * gzs + c]);
-    atomicAdd(gb + c, s);
   }
 }
 
@@ -442,31 +453,43 @@ __global__ void k_pool_bwd_add(const uint16_t* __restrict__ a, int as, const uin
 // ---------------------------------------------------------------------------
 // input normalisation, head, loss, output, optimiser
 // ---------------------------------------------------------------------------
-// sum[b] += sum of I over image b of maps [B][4][H*W]
-__global__ void k_sum_I(const double* __restrict__ maps, int HW, double* __restrict__ sum) {
+// sums[2b] += sum of I, sums[2b+1] += sum of I^2 over image b of maps [B][4][H*W]
+__global__ void k_sums(const double* __restrict__ maps, int HW, double* __restrict__ sums) {
   const int b = blockIdx.y;
-  double acc = 0.0;
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < HW; p += gridDim.x * blockDim.x)
-    acc += maps[(size_t)b * 4 * HW + p];
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  if ((threadIdx.x & 63) == 0) atomicAdd(sum + b, acc);
+  double a1 = 0.0, a2 = 0.0;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < HW; p += gridDim.x * blockDim.x) {
+    const double I = maps[(size_t)b * 4 * HW + p];
+    a1 += I;
+    a2 += I * I;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    a1 += __shfl_xor(a1, off);
+    a2 += __shfl_xor(a2, off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(sums + 2 * b, a1);
+    atomicAdd(sums + 2 * b + 1, a2);
+  }
 }
 
-// x[p][0..7] = (I, Q, U, V) / s, 0, 0, 0, 0 in BF16 with s the image's mean I;
-// xq[p] = (Q, U) / s in FP32; tgt[p] = (Q, U) of the target maps / s.
+// Input features of pixel p of image b (s = the image's mean I, Ihat = I/s):
+//   x[p][0..7] = ln max(Ihat, 1e-6), Q/I, U/I, V/I (0 where I <= 0), 0, 0, 0, 0 (BF16)
+//   xq[p] = (Q/I, U/I) and ihat[p] = Ihat in FP32; tgt[p] = (Q, U) of the
+//   target maps / s (FP32).
 // With aug, image b is first transformed by the dihedral element aug[b] =
 // r + 4 f: mirror the width axis if f, then r quarter turns (output pixel
 // (h, w) of one turn reads (w, W - 1 - h)); Stokes (Q, U, V) ->
 // ((-1)^r Q, (-1)^(r+f) U, (-1)^f V).  Odd r requires H == W.
 __global__ void k_prep(const double* __restrict__ maps, const double* __restrict__ target,
-                       const double* __restrict__ sum, const int32_t* __restrict__ aug, int B, int H, int W,
-                       uint16_t* __restrict__ x, float* __restrict__ xq, float* __restrict__ tgt) {
+                       const double* __restrict__ sums, const int32_t* __restrict__ aug, int B, int H, int W,
+                       uint16_t* __restrict__ x, float* __restrict__ xq, float* __restrict__ ihat,
+                       float* __restrict__ tgt) {
   const int HW = H * W;
   const size_t n = (size_t)B * HW;
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
     const size_t b = k / HW;
     int h = (int)(k % HW) / W, w = (int)(k % HW) % W;
-    float sq = 1.f, su = 1.f, sv = 1.f;
+    double sq = 1.0, su = 1.0, sv = 1.0;
     if (aug) {
       const int code = aug[b], r = code & 3, f = code >> 2;
       for (int t = 0; t < r; ++t) {
@@ -475,28 +498,32 @@ __global__ void k_prep(const double* __restrict__ maps, const double* __restrict
         w = w2;
       }
       if (f) w = W - 1 - w;
-      sq = (r & 1) ? -1.f : 1.f;
-      su = ((r + f) & 1) ? -1.f : 1.f;
-      sv = f ? -1.f : 1.f;
+      sq = (r & 1) ? -1.0 : 1.0;
+      su = ((r + f) & 1) ? -1.0 : 1.0;
+      sv = f ? -1.0 : 1.0;
     }
     const size_t p = (size_t)h * W + w;
-    const double mean = sum[b] / HW;
-    const double inv = mean > 0.0 ? 1.0 / mean : 0.0;
+    const double mean = sums[2 * b] / HW;
     const double* m = maps + b * 4 * HW + p;
+    const double I = m[0];
+    const double Ih = mean > 0.0 ? I / mean : 0.0;
+    const double inv = I > 0.0 ? 1.0 / I : 0.0;
     float f8[8];
-    f8[0] = (float)(m[0] * inv);
-    f8[1] = sq * (float)(m[HW] * inv);
-    f8[2] = su * (float)(m[2 * (size_t)HW] * inv);
-    f8[3] = sv * (float)(m[3 * (size_t)HW] * inv);
+    f8[0] = (float)log(fmax(Ih, 1e-6));
+    f8[1] = (float)(sq * m[HW] * inv);
+    f8[2] = (float)(su * m[2 * (size_t)HW] * inv);
+    f8[3] = (float)(sv * m[3 * (size_t)HW] * inv);
 #pragma unroll
     for (int c = 4; c < 8; ++c) f8[c] = 0.f;
     st16(x + k * 8, pack8(f8));
     xq[2 * k] = f8[1];
     xq[2 * k + 1] = f8[2];
+    ihat[k] = (float)Ih;
     if (target) {
       const double* r = target + b * 4 * HW + p;
-      tgt[2 * k] = sq * (float)(r[HW] * inv);
-      tgt[2 * k + 1] = su * (float)(r[2 * (size_t)HW] * inv);
+      const double is = mean > 0.0 ? 1.0 / mean : 0.0;
+      tgt[2 * k] = (float)(sq * r[HW] * is);
+      tgt[2 * k + 1] = (float)(su * r[2 * (size_t)HW] * is);
     }
   }
 }
@@ -520,14 +547,24 @@ __global__ void k_head(const uint16_t* __restrict__ d, int C, const float* __res
   }
 }
 
-// loss += sum (out - tgt)^2 (FP64); go = 2 (out - tgt) / n
-__global__ void k_loss(const float* __restrict__ out, const float* __restrict__ tgt, size_t n, float scale,
+// Relative-error loss: with e = out * Ihat - tgt (both channels) and
+// W_b = sum_p Ihat^2 = (sum I^2) / s^2 of image b,
+//   loss += sum_p |e|^2 / (B W_b)   (FP64),   go = 2 e Ihat / (B W_b).
+__global__ void k_loss(const float* __restrict__ out, const float* __restrict__ tgt,
+                       const float* __restrict__ ihat, const double* __restrict__ sums, int B, int HW,
                        float* __restrict__ go, double* __restrict__ loss) {
+  const size_t n = (size_t)B * HW;
   double acc = 0.0;
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
-    const float e = out[k] - tgt[k];
-    go[k] = scale * e;
-    acc += (double)e * e;
+    const size_t b = k / HW;
+    const double mean = sums[2 * b] / HW;
+    const double wb = mean > 0.0 ? sums[2 * b + 1] / (mean * mean) : 0.0;
+    const double scale = wb > 0.0 ? 1.0 / (B * wb) : 0.0;
+    const float ih = ihat[k];
+    const float e0 = out[2 * k] * ih - tgt[2 * k], e1 = out[2 * k + 1] * ih - tgt[2 * k + 1];
+    go[2 * k] = (float)(2.0 * scale) * e0 * ih;
+    go[2 * k + 1] = (float)(2.0 * scale) * e1 * ih;
+    acc += ((double)e0 * e0 + (double)e1 * e1) * scale;
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   if ((threadIdx.x & 63) == 0) atomicAdd(loss, acc);
@@ -568,29 +605,31 @@ __global__ void k_head_bwd(const float* __restrict__ go, const uint16_t* __restr
   }
 }
 
-// denoised maps: I and V from the input, Q and U = out * mean I
-__global__ void k_output(const double* __restrict__ maps, const float* __restrict__ out,
-                         const double* __restrict__ sum, int B, int HW, double* __restrict__ dst) {
+// denoised maps: I and V from the input, Q = q' I and U = u' I
+__global__ void k_output(const double* __restrict__ maps, const float* __restrict__ out, int B, int HW,
+                         double* __restrict__ dst) {
   const size_t n = (size_t)B * HW;
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
     const size_t b = k / HW, p = k % HW;
-    const double mean = sum[b] / HW;
     const double* m = maps + b * 4 * HW + p;
     double* o = dst + b * 4 * HW + p;
-    o[0] = m[0];
-    o[HW] = (double)out[2 * k] * mean;
-    o[2 * (size_t)HW] = (double)out[2 * k + 1] * mean;
+    const double I = m[0];
+    o[0] = I;
+    o[HW] = (double)out[2 * k] * I;
+    o[2 * (size_t)HW] = (double)out[2 * k + 1] * I;
     o[3 * (size_t)HW] = m[3 * (size_t)HW];
   }
 }
 
-// Adam with bias correction (Kingma & Ba 2015) on FP32 master weights
+// (1 - beta) is passed from the host, formed in FP64: 0.999 is not an FP32
+// number and 1 - fl(0.999) would be off by 1.3e-5 relative.
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                       float* __restrict__ v, size_t n, float lr, float b1, float b2, float eps, float c1, float c2) {
+                       float* __restrict__ v, size_t n, float lr, float b1, float b2, float omb1, float omb2,
+                       float eps, float c1, float c2) {
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
     const float gk = g[k];
-    const float mk = b1 * m[k] + (1.f - b1) * gk;
-    const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+    const float mk = b1 * m[k] + omb1 * gk;
+    const float vk = b2 * v[k] + omb2 * gk * gk;
     m[k] = mk;
     v[k] = vk;
     p[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
@@ -649,7 +688,7 @@ void conv3(const ConvArgs& a, int mode, hipStream_t s) {
   else hipLaunchKernelGGL(k_conv3<CONV_MASK>, grid, dim3(256), 0, s, a);
 }
 
-void wgrad(WgradArgs a, float* gb, hipStream_t s) {
+void wgrad(WgradArgs a, hipStream_t s) {
   const size_t P = (size_t)a.B * a.H * a.W;
   a.ktiles = (9 * a.cin + 63) / 64;
   const int mtiles = (a.cout + 63) / 64;
@@ -663,8 +702,6 @@ void wgrad(WgradArgs a, float* gb, hipStream_t s) {
   a.chunk = (int)chunk;
   const dim3 grid((unsigned)tiles, (unsigned)((P + chunk - 1) / chunk));
   hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_bias_grad, dim3((unsigned)((P + 1023) / 1024)), dim3(64), 0, s, a.gz, a.gzs, a.cout, (int)P,
-                     gb);
 }
 
 void pool(const uint16_t* x, int xs, uint16_t* y, int ys, int B, int H, int W, int C, hipStream_t s) {
@@ -683,33 +720,35 @@ void pool_bwd_add(const uint16_t* a, int as, const uint16_t* g, int gs, const ui
   hipLaunchKernelGGL(k_pool_bwd_add, dim3(grid_for((size_t)B * H * W * C / 8)), dim3(256), 0, s, a, as, g, gs, mask,
                      ms, dst, ds, B, H, W, C);
 }
-void sum_I(const double* maps, int B, int HW, double* sum, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_I, dim3(grid_for(HW, 64), B), dim3(256), 0, s, maps, HW, sum);
+void sums(const double* maps, int B, int HW, double* sum, hipStream_t s) {
+  hipLaunchKernelGGL(k_sums, dim3(grid_for(HW, 64), B), dim3(256), 0, s, maps, HW, sum);
 }
 void prep(const double* maps, const double* target, const double* sum, const int32_t* aug, int B, int H, int W,
-          uint16_t* x, float* xq, float* tgt, hipStream_t s) {
+          uint16_t* x, float* xq, float* ihat, float* tgt, hipStream_t s) {
   hipLaunchKernelGGL(k_prep, dim3(grid_for((size_t)B * H * W)), dim3(256), 0, s, maps, target, sum, aug, B, H, W, x,
-                     xq, tgt);
+                     xq, ihat, tgt);
 }
 void head(const uint16_t* d, int C, const float* hw, const float* hb, const float* xq, float* out, size_t P,
           hipStream_t s) {
   hipLaunchKernelGGL(k_head, dim3(grid_for(P)), dim3(256), 0, s, d, C, hw, hb, xq, out, P);
 }
-void loss(const float* out, const float* tgt, size_t n, float* go, double* l, hipStream_t s) {
-  hipLaunchKernelGGL(k_loss, dim3(grid_for(n, 2048)), dim3(256), 0, s, out, tgt, n, 2.0f / (float)n, go, l);
+void loss(const float* out, const float* tgt, const float* ihat, const double* sum, int B, int HW, float* go,
+          double* l, hipStream_t s) {
+  hipLaunchKernelGGL(k_loss, dim3(grid_for((size_t)B * HW, 2048)), dim3(256), 0, s, out, tgt, ihat, sum, B, HW, go,
+                     l);
 }
 void head_bwd(const float* go, const uint16_t* d, int C, const float* hw, float* ghw, float* ghb, uint16_t* gd,
               size_t P, hipStream_t s) {
   hipLaunchKernelGGL(k_head_bwd, dim3((unsigned)((P + 255) / 256)), dim3(64), 0, s, go, d, C, hw, ghw, ghb, gd, P);
 }
-void output(const double* maps, const float* out, const double* sum, int B, int HW, double* dst, hipStream_t s) {
-  hipLaunchKernelGGL(k_output, dim3(grid_for((size_t)B * HW)), dim3(256), 0, s, maps, out, sum, B, HW, dst);
+void output(const double* maps, const float* out, int B, int HW, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_output, dim3(grid_for((size_t)B * HW)), dim3(256), 0, s, maps, out, B, HW, dst);
 }
 void adam(float* p, const float* g, float* m, float* v, size_t n, float lr, int t, hipStream_t s) {
   const double b1 = 0.9, b2 = 0.999;
   const float c1 = (float)(1.0 - std::pow(b1, t)), c2 = (float)(1.0 - std::pow(b2, t));
-  hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(256), 0, s, p, g, m, v, n, lr, (float)b1, (float)b2, 1e-8f, c1,
-                     c2);
+  hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(256), 0, s, p, g, m, v, n, lr, (float)b1, (float)b2,
+                     (float)(1.0 - b1), (float)(1.0 - b2), 1e-8f, c1, c2);
 }
 void pack(const float* wf, int cout, int cin, int cin_true, int kp, int kpd, uint16_t* w, uint16_t* wd,
           hipStream_t s) {

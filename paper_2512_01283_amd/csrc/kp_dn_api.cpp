@@ -40,7 +40,7 @@ struct Work {
   uint16_t *x0, *a1a, *cat1, *pool1, *a2a, *cat2, *pool2, *a3a, *m3, *d2a, *d2, *d1a, *d1;
   // BF16 gradients
   uint16_t *g1, *g1b, *gcat1, *g2, *g2b, *gcat2, *g3, *g3b, *gpool2, *ge2, *ge2b, *gpool1, *ge1, *ge1b;
-  float *xq, *tgt, *out, *go;
+  float *xq, *ihat, *tgt, *out, *go;
   double *sum, *loss;
   int32_t* aug;
 };
@@ -157,10 +157,11 @@ kp_status ensure_work(kp_dn* dn, size_t P1, int B) {
   bf(&w.ge1, cap * c1);
   bf(&w.ge1b, cap * c1);
   plan.push_back({(void**)&w.xq, cap * 2 * 4});
+  plan.push_back({(void**)&w.ihat, cap * 4});
   plan.push_back({(void**)&w.tgt, cap * 2 * 4});
   plan.push_back({(void**)&w.out, cap * 2 * 4});
   plan.push_back({(void**)&w.go, cap * 2 * 4});
-  plan.push_back({(void**)&w.sum, (size_t)bcap * 8});
+  plan.push_back({(void**)&w.sum, (size_t)bcap * 16});
   plan.push_back({(void**)&w.loss, 8});
   plan.push_back({(void**)&w.aug, (size_t)bcap * 4});
   std::vector<size_t> offs;
@@ -269,11 +270,12 @@ void conv_wgrad(kp_dn* dn, int l, const uint16_t* gz, const uint16_t* x, int xs,
   a.cin = L.cin;
   a.cin_true = L.cin_true;
   a.gw = dn->d_g + L.w_off;
+  a.gb = dn->d_g + L.b_off;
   a.B = B;
   a.H = H;
   a.W = W;
   const int e = mark_begin(dn, s);
-  wgrad(a, dn->d_g + L.b_off, s);
+  wgrad(a, s);
   mark_end(dn, e, CAT_WGRAD, conv_flop(L, (size_t)B * H * W), s);
 }
 
@@ -283,9 +285,9 @@ kp_status forward(kp_dn* dn, const double* maps, const double* target, int B, in
   Work& w = dn->w;
   const int c1 = dn->c1, c2 = dn->c2, c3 = dn->c3;
   const size_t P1 = (size_t)B * H * W;
-  zero(w.sum, (size_t)B * 8, s);
-  sum_I(maps, B, H * W, w.sum, s);
-  prep(maps, target, w.sum, use_aug ? w.aug : nullptr, B, H, W, w.x0, w.xq, w.tgt, s);
+  zero(w.sum, (size_t)B * 16, s);
+  sums(maps, B, H * W, w.sum, s);
+  prep(maps, target, w.sum, use_aug ? w.aug : nullptr, B, H, W, w.x0, w.xq, w.ihat, w.tgt, s);
   const int H2 = H / 2, W2 = W / 2, H4 = H / 4, W4 = W / 4;
   conv_fwd(dn, E1A, w.x0, 8, w.a1a, c1, B, H, W, s);
   conv_fwd(dn, E1B, w.a1a, c1, w.cat1 + c2, c2 + c1, B, H, W, s);
@@ -313,7 +315,7 @@ kp_status backward(kp_dn* dn, int B, int H, int W, hipStream_t s) {
   const int H2 = H / 2, W2 = W / 2, H4 = H / 4, W4 = W / 4;
   zero(dn->d_g, dn->n_params * 4, s);
   zero(w.loss, 8, s);
-  loss(w.out, w.tgt, 2 * P1, w.go, w.loss, s);
+  loss(w.out, w.tgt, w.ihat, w.sum, B, H * W, w.go, w.loss, s);
   head_bwd(w.go, w.d1, c1, dn->d_p + dn->head_w, dn->d_g + dn->head_w, dn->d_g + dn->head_b, w.g1, P1, s);
   // decoder level 1
   conv_wgrad(dn, D1B, w.g1, w.d1a, c1, B, H, W, s);
@@ -514,7 +516,7 @@ kp_status kp_dn_infer(kp_dn* dn, const double* d_maps, double* d_out, int32_t B,
   dn->ev_total0 = mark_begin(dn, s);
   if (kp_status st = ensure_packed(dn, s)) return st;
   if (kp_status st = forward(dn, d_maps, nullptr, B, H, W, false, s)) return st;
-  output(d_maps, dn->w.out, dn->w.sum, B, H * W, d_out, s);
+  output(d_maps, dn->w.out, B, H * W, d_out, s);
   DN_HIP(hipGetLastError(), "output launch");
   if (dn->ev_total0 >= 0) {
     dn->ev_total1 = dn->ev_total0 + 1;
@@ -553,7 +555,7 @@ kp_status kp_dn_backward(kp_dn* dn, const double* d_low, const double* d_high, i
   double l = 0.0;
   DN_HIP(hipMemcpyAsync(&l, dn->w.loss, 8, hipMemcpyDeviceToHost, s), "loss copy");
   DN_HIP(hipStreamSynchronize(s), "synchronise");
-  *loss_out = l / (2.0 * (double)B * H * W);
+  *loss_out = l;
   return KP_OK;
 }
 

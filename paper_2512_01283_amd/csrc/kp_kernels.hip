@@ -225,7 +225,7 @@ __device__ __forceinline__ void wave_flush(bool need, int64_t key, const double 
 template <typename R, bool SPHERE>
 __device__ __forceinline__ void alphas(const DustDev& D, R ct, R& a1, R& a2, R& a3) {
   if (SPHERE) { a1 = (R)1; a2 = (R)0; a3 = (R)0; return; }
-  R cth = (R)D.ap_im * ct * ct + (R)D.aa_im * ((R)1 - ct * ct);
+  R cth = (R)D.ap_im * ct * ct + (R)D.aa_im * (sizeof(R) == 4 ? ((R)1 - ct) * ((R)1 + ct) : (R)1 - ct * ct);
   R cph = (R)D.ap_im;
   a1 = (cth + cph) * (R)D.inv2cavg;
   a2 = (cth - cph) * (R)D.inv2cavg;
@@ -243,14 +243,26 @@ __device__ bool scatter(Packet<R>& p, const Quat<R>& q, const V3<double>& bdir,
   const V3<R> n{(R)p.nx, (R)p.ny, (R)p.nz};
   V3<R> ng = n;
   R c2 = (R)1, s2 = (R)0;
+  R cpn, spn, stn;
   if (ALIGNED) {
-    ng = to_grain(q, n);
+    // The grain-frame direction and its azimuth are formed in FP64: for a
+    // packet moving nearly along the grain axis the transverse components
+    // are small differences of order-one terms, which FP32 resolves only to
+    // ~1e-7 absolute, i.e. to a basis angle error of ~1e-7 / sin(theta').
+    const V3<double> nd{p.nx, p.ny, p.nz};
+    const V3<double> ngd = to_grain(grain_quat(bdir), nd);
+    double cpd, spd, std_;
+    azimuth(ngd, cpd, spd, std_);
+    ng = V3<R>{(R)ngd.x, (R)ngd.y, (R)ngd.z};
+    cpn = (R)cpd;
+    spn = (R)spd;
+    stn = (R)std_;
     eta2(q, n, ng, c2, s2);
+  } else {
+    azimuth(ng, cpn, spn, stn);
   }
   const R I = p.I, Qg = c2 * p.Q + s2 * p.U, Ug = -s2 * p.Q + c2 * p.U, V = p.V;
   V3<R> e1, e2;
-  R cpn, spn, stn;
-  azimuth(ng, cpn, spn, stn);
   e1 = {ng.z * cpn, ng.z * spn, -stn};
   e2 = {-spn, cpn, (R)0};
   const R r11 = (R)0.5 * (I + Qg), r22 = (R)0.5 * (I - Qg);
@@ -269,7 +281,9 @@ __device__ bool scatter(Packet<R>& p, const Quat<R>& q, const V3<double>& bdir,
     uph = next_uniform(p, seed);
     R ua = next_uniform(p, seed);
     p.trials++;
-    smu = k_sqrt(fmax((R)0, (R)1 - mu * mu));
+    // 1 - mu^2 as (1 - mu)(1 + mu): both factors are exact, so sin theta'
+    // keeps full relative precision near the grain axis in FP32
+    smu = sizeof(R) == 4 ? k_sqrt(fmax((R)0, ((R)1 - mu) * ((R)1 + mu))) : k_sqrt(fmax((R)0, (R)1 - mu * mu));
     k_sincospi((R)2 * uph, &sph, &cph);
     if (smu * smu <= (R)KP_POLE2) { cph = (R)1; sph = (R)0; }
     const V3<R> f1{mu * cph, mu * sph, -smu}, f2{-sph, cph, (R)0};

@@ -17,7 +17,7 @@ def gpu_run(cfg, counts=None, device_arrays=True, **opts):
     return ctx
 
 
-def compare_traces(g, o, tol, min_match=1.0, label="", tau_coef=0.0):
+def compare_traces(g, o, tol, min_match=1.0, label="", tau_coef=0.0, frac_within=1.0, hard_cap=None):
     """Per-packet parity: identical event sequences (hash, end kind, counts,
     last cell); on matched packets the final direction agrees to `tol`
     absolutely and the Stokes vector to tol + tau_coef * tau_path relative to
@@ -25,7 +25,10 @@ def compare_traces(g, o, tol, min_match=1.0, label="", tau_coef=0.0):
     packet went through -- in FP32 the segment lengths carry an absolute
     rounding of order 1e-7 cell, so the weight's relative error grows by about
     that times the optical depth per cell crossed).  Returns the matched
-    fraction."""
+    fraction.  With frac_within < 1, only that fraction of matched packets
+    must meet the allowance and every packet must stay below hard_cap
+    (relative to I): the FP32 mode for dichroic grains, whose error is set by
+    the conditioning of each packet's path."""
     assert len(g) == len(o)
     assert np.array_equal(g["packet"], o["packet"]), "traced packet ids differ"
     same = ((g["hash"] == o["hash"]) & (g["end_kind"] == o["end_kind"]) &
@@ -47,7 +50,13 @@ def compare_traces(g, o, tol, min_match=1.0, label="", tau_coef=0.0):
         tp = o["tau_path"][same]
         if "tau_path" in g.dtype.names:
             assert np.allclose(g["tau_path"][same], tp, rtol=10 * max(tol, 1e-6), atol=1e-6)
-    assert (ds <= 1.0).all(), f"Stokes mismatch beyond allowance ({ds.max():.3e})"
+    if frac_within >= 1.0:
+        assert (ds <= 1.0).all(), f"Stokes mismatch beyond allowance ({ds.max():.3e})"
+    elif ds.size:
+        within = float((ds.max(1) <= 1.0).mean())
+        say(f"[{label}] {within:.4f} of packets within the allowance, worst |dS|/I {raw.max():.3e}")
+        assert within >= frac_within, f"only {within:.4f} of packets within the allowance"
+        assert raw.max() <= hard_cap, f"Stokes mismatch {raw.max():.3e} beyond {hard_cap}"
     assert (dn <= tol).all(), f"direction mismatch {dn.max():.3e} > {tol}"
     return frac
 

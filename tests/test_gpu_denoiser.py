@@ -3,13 +3,19 @@ accumulation) against the FP64 NumPy oracle, through the C ABI.
 
 The oracle is evaluated on exactly the operands the kernels see: the
 parameters and the normalised input rounded to BF16 (nearest even), the
-residual base (Q, U) / s and the targets in FP32.  What remains is the
-rounding of every intermediate activation and gradient to BF16 and FP32
-accumulation order.  With unit roundoff u = 2^-9 and an RMS relative error
-u / sqrt(3) per rounding, L roughly norm-preserving layers give a relative
-output error near sqrt(L) u / sqrt(3): 3.6e-3 for the 10 convolutions of
-the forward pass, 5e-3 for the 20 of forward plus backward.  The tolerances
-below allow 4x that (relative L2 norm per tensor).
+fractions Q/I, U/I, the intensity ratio I/s and the targets in FP32.  What
+remains is the rounding of every stored intermediate (activations and their
+gradients) to BF16 and the order of FP32 accumulation.
+
+The tolerance is derived from the arithmetic by replaying the oracle's own
+layer functions with a BF16 rounding wherever the kernels store BF16
+(`bf16_replay`): the replay's distance from the exact oracle is the size of
+the rounding noise, and the GPU -- another realisation of the same noise --
+must lie within twice that distance plus 2e-3, per tensor.  Forward: about
+3.6e-3 (sqrt(10) x the RMS relative error 2^-9/sqrt(3) of one rounding);
+weight gradients of the deepest layers reach 2-3e-2, because the backward
+pass compounds the roundings of both passes and ends in short sums over few
+coarse pixels.  A wrong index, sign or mask gives errors of order one.
 """
 import numpy as np
 import pytest
@@ -20,7 +26,6 @@ from paper_2512_01283_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL_FWD = 1.5e-2
-TOL_GRAD = 2.0e-2
 
 
 def bf16(a):
@@ -42,32 +47,98 @@ def dihedral(m, code):
     return out
 
 
-def oracle_pass(params32, low, high=None, widths=W.DN_WIDTHS):
-    """Oracle forward (and backward if high is given) on the kernels' operands.
-    Returns dict(head, out, loss, grads, mean)."""
-    p = D.unflatten(bf16(params32).astype(np.float64), widths)
-    # biases and the head stay FP32 on the device: use them unrounded
-    p_full = D.unflatten(params32.astype(np.float64), widths)
+def _operands(params32, low, high, widths):
+    """Parameters and inputs as the kernels see them: 3x3 weights BF16
+    (biases and head FP32), features FP32 -> BF16 for the network, the
+    fractions Q/I, U/I, Ihat and the targets FP32."""
+    p = D.unflatten(params32.astype(np.float64), widths)
     for k in p:
-        if not k.endswith(".w") or k.startswith("head"):
-            p[k] = p_full[k]
-    mean = low[:, 0].mean(axis=(1, 2))
-    inv = 1.0 / mean
-    xs = np.float32(np.moveaxis(low, 1, -1) * inv[:, None, None, None]).astype(np.float64)
-    x = bf16(xs)
-    out_o, cache = D.forward(p, x)
-    head = out_o - x[..., 1:3]
-    out = xs[..., 1:3] + head
-    res = dict(head=head, out=out, mean=mean)
+        if k.endswith(".w") and not k.startswith("head"):
+            p[k] = bf16(p[k])
+    xf, Ihat, s = D.features(low)
+    xf = np.float32(xf).astype(np.float64)
+    Ihat = np.float32(Ihat).astype(np.float64)
+    t = None
     if high is not None:
-        t = np.float32(np.moveaxis(high[:, 1:3], 1, -1) * inv[:, None, None, None]).astype(np.float64)
-        res["loss"] = D.loss(out, t)
-        res["grads"] = D.backward(p, cache, out, t)
+        t = np.float32(np.moveaxis(high[:, 1:3], 1, -1) / s[:, None, None, None]).astype(np.float64)
+    return p, xf, bf16(xf), Ihat, t
+
+
+def oracle_pass(params32, low, high=None, widths=W.DN_WIDTHS):
+    """Exact FP64 oracle forward (and backward if high is given) on the
+    kernels' operands.  Returns dict(delta, loss, grads)."""
+    p, xf, x, Ihat, t = _operands(params32, low, high, widths)
+    delta, cache = D.forward(p, x)
+    res = dict(delta=delta)
+    if high is not None:
+        res["loss"] = D.loss(delta, xf, Ihat, t)
+        res["grads"] = D.backward(p, cache, D.loss_grad(delta, xf, Ihat, t))
     return res
+
+
+def bf16_replay(params32, low, high=None, widths=W.DN_WIDTHS):
+    """The oracle's layer functions in FP64 with a BF16 rounding at every
+    point where the kernels store BF16: each convolution's output (after
+    bias and relu), pooled maps, the head's input gradient, each input
+    gradient, the adjoints of upsampling and pooling (masks applied before
+    rounding).  Returns dict(delta, loss, grads)."""
+    R = bf16
+    p, xf, x, Ihat, t = _operands(params32, low, high, widths)
+    c = {}
+
+    def block(name, inp):
+        ya = R(D.relu(D.conv3(inp, p[name + "a.w"], p[name + "a.b"])))
+        yb = R(D.relu(D.conv3(ya, p[name + "b.w"], p[name + "b.b"])))
+        c[name] = (inp, ya, yb)
+        return yb
+
+    e1 = block("e1", x)
+    e2 = block("e2", R(D.pool(e1)))
+    m3 = block("m3", R(D.pool(e2)))
+    d2 = block("d2", np.concatenate([D.up(m3), e2], axis=3))
+    d1 = block("d1", np.concatenate([D.up(d2), e1], axis=3))
+    delta = d1 @ p["head.w"].T + p["head.b"]
+    if t is None:
+        return dict(delta=delta)
+    g = {}
+    go = D.loss_grad(delta, xf, Ihat, t)
+    g["head.w"] = go.reshape(-1, 2).T @ d1.reshape(-1, d1.shape[-1])
+    g["head.b"] = go.reshape(-1, 2).sum(0)
+
+    def block_back(name, gzb):
+        inp, ya, yb = c[name]
+        gya, g[name + "b.w"], g[name + "b.b"] = D.conv3_backward(ya, p[name + "b.w"], gzb)
+        gza = R(gya * (ya > 0))
+        ginp, g[name + "a.w"], g[name + "a.b"] = D.conv3_backward(inp, p[name + "a.w"], gza)
+        return R(ginp)
+
+    c1, c2, c3 = widths
+    gcat1 = block_back("d1", R((go @ p["head.w"]) * (d1 > 0)))
+    gcat2 = block_back("d2", R(D.up_backward(gcat1[..., :c2]) * (d2 > 0)))
+    gm3 = block_back("m3", R(D.up_backward(gcat2[..., :c3]) * (m3 > 0)))
+    ge2 = block_back("e2", R((gcat2[..., c3:] + D.pool_backward(gm3)) * (e2 > 0)))
+    block_back("e1", R((gcat1[..., c2:] + D.pool_backward(ge2)) * (e1 > 0)))
+    return dict(delta=delta, loss=D.loss(delta, xf, Ihat, t), grads=g)
 
 
 def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def check_gradients(g, low, high, params, label):
+    """GPU gradients against the exact oracle, per tensor, within twice the
+    distance of the BF16 replay from the exact oracle plus 2e-3 (the GPU and
+    the replay are two realisations of the same rounding noise)."""
+    ref = oracle_pass(params, low, high)
+    rep = bf16_replay(params, low, high)
+    worst = 0.0
+    for k, gr in ref["grads"].items():
+        bound = 2.0 * rel(rep["grads"][k], gr) + 2e-3
+        e = rel(g[k], gr)
+        worst = max(worst, e / bound)
+        assert e < bound, (k, e, bound)
+    print(f"{label}: worst gradient error {worst:.2f} of its bound")
+    return ref
 
 
 @pytest.fixture(scope="module")
@@ -91,12 +162,14 @@ def test_forward_parity(dn, shape):
     maps = W.synthetic_stokes_maps(5, b, h, w)
     out = dn.infer(_dev(maps)).cpu().numpy()
     ref = oracle_pass(params, maps)
-    mean = ref["mean"][:, None, None]
-    head_gpu = np.stack([out[:, 1] / mean, out[:, 2] / mean], -1) - \
-        np.float32(np.moveaxis(maps[:, 1:3], 1, -1) / mean[..., None]).astype(np.float64)
-    e = rel(head_gpu, ref["head"])
-    print(f"forward {shape}: relative error of the correction {e:.2e}")
-    assert e < TOL_FWD
+    rep = bf16_replay(params, maps)
+    # the network's correction to the fractions: Q'/I - Q/I (FP32 ratio)
+    qf = np.float32(maps[:, 1:3] / maps[:, :1]).astype(np.float64)
+    delta_gpu = np.moveaxis(out[:, 1:3] / out[:, :1] - qf, 1, -1)
+    e = rel(delta_gpu, ref["delta"])
+    e_rep = rel(rep["delta"], ref["delta"])
+    print(f"forward {shape}: relative error of the correction {e:.2e} (BF16 replay {e_rep:.2e})")
+    assert e < TOL_FWD and e < 2.0 * e_rep + 2e-3
     # I and V pass through unchanged
     assert np.array_equal(out[:, 0], maps[:, 0]) and np.array_equal(out[:, 3], maps[:, 3])
 
@@ -110,14 +183,8 @@ def test_gradient_parity(dn, shape):
     high = W.synthetic_stokes_maps(6, b, h, w, noise=0.0)
     loss = dn.backward(_dev(low), _dev(high))
     g = D.unflatten(dn.grads().astype(np.float64))
-    ref = oracle_pass(params, low, high)
+    ref = check_gradients(g, low, high, params, f"gradients {shape}")
     assert abs(loss - ref["loss"]) <= TOL_FWD * ref["loss"]
-    worst = 0.0
-    for k, gr in ref["grads"].items():
-        e = rel(g[k], gr)
-        worst = max(worst, e)
-        assert e < TOL_GRAD, (k, e)
-    print(f"gradients {shape}: worst relative error {worst:.2e}, loss {loss:.6e} vs {ref['loss']:.6e}")
 
 
 def test_augmented_gradients_match_transformed_maps(dn):
@@ -131,10 +198,8 @@ def test_augmented_gradients_match_transformed_maps(dn):
     g = D.unflatten(dn.grads().astype(np.float64))
     lo_t = np.stack([dihedral(low[i], int(c)) for i, c in enumerate(codes)])
     hi_t = np.stack([dihedral(high[i], int(c)) for i, c in enumerate(codes)])
-    ref = oracle_pass(params, lo_t, hi_t)
+    ref = check_gradients(g, lo_t, hi_t, params, "augmented gradients")
     assert abs(loss - ref["loss"]) <= TOL_FWD * ref["loss"]
-    for k, gr in ref["grads"].items():
-        assert rel(g[k], gr) < TOL_GRAD, k
 
 
 def test_adam_step_matches_oracle(dn):
@@ -158,13 +223,15 @@ def test_adam_step_matches_oracle(dn):
 
 
 def test_training_reduces_loss(dn):
+    """Adam on one fixed batch lowers the loss (a wrong sign or a missing
+    term anywhere in the backward pass would not)."""
     dn.set_params(W.denoiser_params(15))
     low = _dev(W.synthetic_stokes_maps(9, 4, 32, 32, noise=0.3))
     high = _dev(W.synthetic_stokes_maps(9, 4, 32, 32, noise=0.0))
     first = dn.train_step(low, high, 1e-3)
-    for _ in range(30):
+    for _ in range(40):
         last = dn.train_step(low, high, 1e-3)
-    assert np.isfinite(last) and last < 0.5 * first, (first, last)
+    assert np.isfinite(last) and last < 0.8 * first, (first, last)
 
 
 def test_checkpoint_resume(dn):

@@ -88,22 +88,44 @@ def test_schedule_independence():
 
 def test_aligned_slab_clump(O):
     """128^3 log-normal slab + clump with aligned oblate grains (dichroic
-    extinction, thick cells up to tau = 100), FP32 transport, 4 views."""
-    say("case: slab_clump128 fp32 3e4 packets")
+    extinction, thick cells up to tau = 100), 4 views.  Automatic precision:
+    dichroic grains run the polarisation arithmetic in FP64, so every packet
+    matches the oracle to rounding."""
+    say("case: slab_clump128 automatic precision 3e4 packets")
     cfg = W.slab_clump(packets=30000)
     ctx = gpu_run(cfg, trace_packets=3000)
     _, tr_o, st_o = O.transport(cfg, p_end=3000, tally=False, traces=True)
     tr_g = ctx.traces()
-    compare_traces(tr_g, tr_o, 1e-5, 0.98, "slab_clump fp32", tau_coef=1e-6)
+    compare_traces(tr_g, tr_o, 1e-10, 1.0, "slab_clump auto")
     s = tr_g["stokes"]
-    assert (s[:, 0] * (1 + 1e-5) >= np.sqrt((s[:, 1:] ** 2).sum(1))).all()
+    assert (s[:, 0] * (1 + 1e-12) >= np.sqrt((s[:, 1:] ** 2).sum(1))).all()
+    img_o, batches = oracle_batches(cfg)
+    img_g = ctx.images()[0]
+    compare_images_stat(img_g, img_o, batches, label="slab_clump auto")
+    assert stokes_bound(img_g, 1e-6, 1e-6)
+    st = ctx.stats()
+    bal = st["e_escaped"] + st["e_absorbed"] + st["e_rr_killed"] - st["e_rr_gained"] + st["e_budget"]
+    assert abs(bal - st["e_emitted"] - st["e_scat_delta"]) < 1e-9 * st["e_emitted"]
+
+
+def test_aligned_slab_clump_forced_fp32(O):
+    """The same workload with FP32 polarisation arithmetic forced
+    (transport_fp64 = 2).  A thick dichroic cell multiplies the grain-frame
+    components I+Q and I-Q by e^{-x_A} and e^{-x_B} with |x_A - x_B| up to
+    ~10, amplifying the FP32 representation error (~6e-8 I) of the smaller
+    one by up to e^{|x_A - x_B|}: most packets meet 1e-5 + 1e-6 tau_path, a
+    few per thousand do not, none exceeds 2e-3; the images agree within the
+    Monte Carlo noise."""
+    say("case: slab_clump128 forced fp32 3e4 packets")
+    cfg = W.slab_clump(packets=30000)
+    ctx = gpu_run(cfg, trace_packets=3000, transport_fp64=2)
+    _, tr_o, _ = O.transport(cfg, p_end=3000, tally=False, traces=True)
+    compare_traces(ctx.traces(), tr_o, 1e-5, 0.98, "slab_clump fp32", tau_coef=1e-6,
+                   frac_within=0.98, hard_cap=2e-3)
     img_o, batches = oracle_batches(cfg)
     img_g = ctx.images()[0]
     compare_images_stat(img_g, img_o, batches, label="slab_clump fp32")
     assert stokes_bound(img_g, 1e-6, 1e-6)
-    st = ctx.stats()
-    bal = st["e_escaped"] + st["e_absorbed"] + st["e_rr_killed"] - st["e_rr_gained"] + st["e_budget"]
-    assert abs(bal - st["e_emitted"] - st["e_scat_delta"]) < 1e-4 * st["e_emitted"]
 
 
 def test_disk_small_images(O):
@@ -139,17 +161,19 @@ def test_disk_full_size_sampled(O):
     assert st["packets"] == 100_000_000 and st["numeric"] == 0
 
 
-@pytest.mark.parametrize("fp64", [1, 0])
+@pytest.mark.parametrize("fp64", [1, 0, 2])
 @pytest.mark.parametrize("a3s", [0.0, -1.0])
 def test_twisted_slab(O, fp64, a3s):
     """Pencil beam through the twisted-field slab (Sec. 3.2) -- quaternion
-    grain frames, signed eta rotations, dichroic extinction and the U-V term."""
+    grain frames, signed eta rotations, dichroic extinction and the U-V term.
+    Modes 1 (FP64) and 0 (automatic: FP64 for these dichroic grains) match to
+    rounding; forced FP32 (2) on this thin, weakly dichroic slab to 2e-6."""
     for start in (0.3, 1.0):
         cfg = W.pencil_slab(n_z=64, p0=0.05, alpha3_scale=a3s, start_tau=start)
         cfg["packets"] = [3]
         ctx = gpu_run(cfg, trace_packets=3, transport_fp64=fp64)
         tr_o = O.trace_packets(cfg, np.arange(3, dtype=np.uint64))
-        compare_traces(ctx.traces(), tr_o, 1e-12 if fp64 else 2e-6, 1.0, f"twisted fp64={fp64}")
+        compare_traces(ctx.traces(), tr_o, 2e-6 if fp64 == 2 else 1e-12, 1.0, f"twisted fp64={fp64}")
 
 
 @pytest.mark.parametrize("tau", [1e-3, 1.0, 10.0, 40.0])
@@ -180,7 +204,8 @@ def test_image_source_dichroic_emission(O, tau):
 def test_batched_wavelengths(O):
     """Several wavelengths with uneven (and one empty) packet counts in one
     persistent launch: each wavelength follows its own streams exactly as a
-    single-wavelength oracle run does."""
+    single-wavelength oracle run does (aligned grains: automatic precision
+    runs them in FP64)."""
     say("case: batched disk48 x4 wavelengths")
     counts = [3000, 0, 1700, 2500]
     cfg = W.batched_disk(n=48, n_lambda=4, npix=32, counts=counts)
@@ -192,7 +217,7 @@ def test_batched_wavelengths(O):
             assert np.all(img_g[lam] == 0)
             continue
         _, tr_o, _ = O.transport(cfg, lam=lam, p_end=min(n, 500), tally=False, traces=True)
-        compare_traces(tr[lam][: min(n, 500)], tr_o, 1e-5, 0.98, f"batched lam={lam}", tau_coef=1e-6)
+        compare_traces(tr[lam][: min(n, 500)], tr_o, 1e-10, 1.0, f"batched lam={lam}")
         img_o, batches = oracle_batches(cfg, nb=6, lam=lam)
         compare_images_stat(img_g[lam], img_o, batches, label=f"batched lam={lam}")
 
@@ -245,7 +270,8 @@ def test_argument_errors():
     assert e.value.status == P.KP_ERR_ARG
     ctx.load(cfg)
     for kw in (dict(block_size=100), dict(max_events=0), dict(rr_psurv=0.0), dict(tally_mode=3),
-               dict(scatter_batch=65), dict(scatter_wait=-1)):
+               dict(scatter_batch=65), dict(scatter_wait=-1), dict(transport_fp64=3),
+               dict(transport_fp64=-1)):
         with pytest.raises(P.KpError) as e:
             P.kp_run(ctx.h, [10], ctx.opts(**kw))
         assert e.value.status == P.KP_ERR_ARG, kw
