@@ -38,6 +38,23 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_STEP_SPHERE = 4 + 2 * 6 * 8
 
 
+def counter_traffic():
+    """HBM bytes per transport launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs (scaled by a 1 GiB copy's readings), in GB; None when the
+    transport kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_transport_disk256_1e8.counters.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    csrc = os.path.join(ROOT, "paper_2512_01283_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read()
+                   for f in ("kp_kernels.hip", "kp_device.hpp", "kp_internal.hpp"))
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["traffic_bytes"] / 1e9
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,8 +189,11 @@ def main():
                    "midplane_tau": 1.0e4, "albedo": 0.5, "grains": "Rayleigh spheres",
                    "transport": "fp32, fp64 coherency tally", "seed": cfg["opts"]["seed"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic()},
         "detail": {"kernel": "k_transport<float,false,true>",
+                   "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, "
+                                   "profiles/k_transport_disk256_1e8.md)",
+                   "algorithmic_gb_per_launch": bytes_launch / 1e9,
                    "transport_ms": avg_t, "imaging_ms": float(np.mean(ms_i)),
                    "cell_steps_per_launch": float(np.mean(steps)),
                    "cell_steps_per_s": float(np.mean(steps)) / (avg_t * 1e-3),

@@ -9,8 +9,8 @@
  * a good estimate saves packets.
  *
  * Per image, with s = mean of I over the image and Ihat = I / s, the input
- * features are x = (ln max(Ihat, 1e-6), Q/I, U/I, V/I) (the ratios 0 where
- * I <= 0).  Network (all 3x3 convolutions have zero padding 1 and a bias;
+ * features are x = (ln max(Ihat, 1e-6), Q/I, U/I, V/I) (the ratios clamped to
+ * [-1, 1], the range of a physical Stokes vector, and 0 where I <= 0).  Network (all 3x3 convolutions have zero padding 1 and a bias;
  * relu after every one; widths c1, c2, c3):
  *   e1    = conv(conv(x, 4->c1), c1->c1)                      H x W
  *   e2    = conv(conv(pool(e1), c1->c2), c2->c2)              H/2

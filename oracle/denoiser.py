@@ -9,7 +9,8 @@ compute, in FP64, with explicit backward passes.
 
 Per image with maps (I, Q, U, V) and s = mean of I over the image:
   Ihat  = I / s
-  x     = (ln max(Ihat, 1e-6), Q/I, U/I, V/I)   [N, H, W, 4]  (0 where I <= 0)
+  x     = (ln max(Ihat, 1e-6), Q/I, U/I, V/I)   [N, H, W, 4]
+          (fractions clipped to [-1, 1], their physical range; 0 where I <= 0)
 The network (widths c1, c2, c3):
   enc1  = relu(conv3(relu(conv3(x,  4->c1)), c1->c1))          H x W
   enc2  = relu(conv3(relu(conv3(pool(enc1), c1->c2)), c2->c2)) H/2
@@ -152,8 +153,9 @@ def features(maps):
     Ihat = np.where(s[:, None, None] > 0, I / sd[:, None, None], 0.0)
     pos = I > 0
     Id = np.where(pos, I, 1.0)
-    x = np.stack([np.log(np.maximum(Ihat, 1e-6)), np.where(pos, Q / Id, 0.0),
-                  np.where(pos, U / Id, 0.0), np.where(pos, V / Id, 0.0)], axis=-1)
+    with np.errstate(over="ignore"):
+        fr = [np.where(pos, np.clip(c / Id, -1.0, 1.0), 0.0) for c in (Q, U, V)]
+    x = np.stack([np.log(np.maximum(Ihat, 1e-6))] + fr, axis=-1)
     return x, Ihat, s
 
 

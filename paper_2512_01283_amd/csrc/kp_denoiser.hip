@@ -507,12 +507,16 @@ __global__ void k_prep(const double* __restrict__ maps, const double* __restrict
     const double* m = maps + b * 4 * HW + p;
     const double I = m[0];
     const double Ih = mean > 0.0 ? I / mean : 0.0;
-    const double inv = I > 0.0 ? 1.0 / I : 0.0;
+    // ratios by division (in the wings of a thick disk I can be subnormal,
+    // where 1 / I overflows), clamped to [-1, 1], the range of a physical
+    // Stokes vector (I >= |(Q, U, V)|)
+    const bool pos = I > 0.0;
+    auto frac = [&](double x) { return pos ? (float)fmin(1.0, fmax(-1.0, x / I)) : 0.f; };
     float f8[8];
     f8[0] = (float)log(fmax(Ih, 1e-6));
-    f8[1] = (float)(sq * m[HW] * inv);
-    f8[2] = (float)(su * m[2 * (size_t)HW] * inv);
-    f8[3] = (float)(sv * m[3 * (size_t)HW] * inv);
+    f8[1] = (float)sq * frac(m[HW]);
+    f8[2] = (float)su * frac(m[2 * (size_t)HW]);
+    f8[3] = (float)sv * frac(m[3 * (size_t)HW]);
 #pragma unroll
     for (int c = 4; c < 8; ++c) f8[c] = 0.f;
     st16(x + k * 8, pack8(f8));

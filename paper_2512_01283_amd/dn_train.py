@@ -34,6 +34,25 @@ from . import polrad as P
 from . import workloads as W
 
 
+def _disks(seeds, n, npix, lookahead=2):
+    """Yield (seed, workload) with the next workloads built on a worker
+    thread while the GPU runs the current one (numpy releases the GIL)."""
+    from collections import deque
+    from concurrent.futures import ThreadPoolExecutor
+    seeds = list(seeds)
+    with ThreadPoolExecutor(1) as ex:
+        q = deque()
+        for s in seeds[:lookahead]:
+            q.append((s, ex.submit(W.denoiser_disk, s, 1, n=n, npix=npix)))
+        k = lookahead
+        while q:
+            s, f = q.popleft()
+            if k < len(seeds):
+                q.append((seeds[k], ex.submit(W.denoiser_disk, seeds[k], 1, n=n, npix=npix)))
+                k += 1
+            yield s, f.result()
+
+
 def run_images(ctx, packets, seed):
     """Images [views, 4, H, W] (CUDA float64) of one run with its own stream seed."""
     ctx.run([int(packets)], seed=int(seed))
@@ -45,8 +64,7 @@ def make_pairs(seeds, n_lo, n_hi, n=256, npix=None, log=print):
     import torch
     los, his = [], []
     t0 = time.time()
-    for k, s in enumerate(seeds):
-        cfg = W.denoiser_disk(s, n_lo, n=n, npix=npix)
+    for k, (s, cfg) in enumerate(_disks(seeds, n, npix)):
         with P.Context(0) as ctx:
             ctx.load(cfg)
             los.append(run_images(ctx, n_lo, 2 * s + 1))
@@ -88,6 +106,8 @@ def train(dn, lo, hi, steps, batch=8, lr=1e-3, lr_min=1e-5, seed=0, aug=True, lo
                 codes &= ~1
         a = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * it / max(steps, 1)))
         loss = dn.train_step(xb, yb, a, aug=codes)
+        if not math.isfinite(loss):
+            raise FloatingPointError(f"training loss is {loss} at step {it}")
         hist.append((it, loss))
         if log and (it % log_every == 0 or it == steps - 1):
             log(f"  step {it}: loss {loss:.4e} lr {a:.2e} ({time.time() - t0:.1f} s)", flush=True)
@@ -102,8 +122,7 @@ def evaluate(dn, seeds, plain_counts=(1e6, 3e6, 1e7, 3e7), den_counts=(1e5, 3e5,
     Ed = {c: [] for c in den_counts}
     Ein = {c: [] for c in den_counts}
     Eref = []
-    for s in seeds:
-        cfg = W.denoiser_disk(s, 1, n=n, npix=npix)
+    for s, cfg in _disks(seeds, n, npix):
         with P.Context(0) as ctx:
             ctx.load(cfg)
             h1 = run_images(ctx, ref_half, 10 * s + 1)

@@ -102,6 +102,9 @@ def test_features_and_loss_at_zero_correction_is_relative_error():
     assert np.allclose(s, maps[:, 0].mean(axis=(1, 2)))
     assert x[0, 0, 0, 0] == np.log(1e-6) and np.all(x[0, 0, 0, 1:] == 0)
     assert np.allclose(x[1, ..., 1], maps[1, 1] / maps[1, 0])
+    bad = maps.copy()
+    bad[0, 0, 2, 2], bad[0, 1, 2, 2] = 1e-310, 0.3  # |Q| > I: fraction clipped to 1
+    assert D.features(bad)[0][0, 2, 2, 1] == 1.0
     assert np.allclose(np.exp(x[1, ..., 0]), maps[1, 0] / s[1])
     tgt = maps.copy()
     tgt[:, 1:3] += 0.05 * RNG.standard_normal(tgt[:, 1:3].shape)

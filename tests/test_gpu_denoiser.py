@@ -264,6 +264,26 @@ def test_workspace_regrowth_and_reuse(dn):
     assert np.allclose(a, b, rtol=0, atol=1e-12 * np.abs(a).max())
 
 
+def test_dark_and_subnormal_pixels_stay_finite(dn):
+    """Maps of thick disks have pixels with I = 0 and subnormal I (light
+    attenuated through optical depths of hundreds): features, loss, gradients
+    and the denoised map stay finite there, and match the oracle."""
+    params = W.denoiser_params(18, bias_std=0.05, head_std=0.05)
+    dn.set_params(params)
+    low = W.synthetic_stokes_maps(14, 2, 16, 16, noise=0.3)
+    high = W.synthetic_stokes_maps(14, 2, 16, 16, noise=0.0)
+    for m in (low, high):
+        m[:, :, 0, :4] = 0.0
+        m[:, :, 1, :4] *= 1e-310      # subnormal but physical: |(Q, U, V)| <= I
+        m[:, 0, 2, :2] = 1e-310       # a pixel violating I >= |Q| (clamped fractions)
+    out = dn.infer(_dev(low)).cpu().numpy()
+    assert np.isfinite(out).all()
+    loss = dn.backward(_dev(low), _dev(high))
+    assert np.isfinite(loss) and np.isfinite(dn.grads()).all()
+    ref = oracle_pass(params, low, high)
+    assert abs(loss - ref["loss"]) <= TOL_FWD * ref["loss"]
+
+
 def test_argument_errors(dn):
     import torch
 
@@ -304,6 +324,7 @@ def test_trained_denoiser_beats_plain_maps_at_equal_packets():
     lo, hi = T.make_pairs(range(1000, 1016), 1e5, 3e6, n=64, npix=64, log=None)
     dn = DN.Denoiser(0, params=W.denoiser_params(0))
     hist = T.train(dn, lo, hi, 300, batch=16, lr=2e-3, log=None)
+    print(f"training loss {hist[0][1]:.4e} -> {hist[-1][1]:.4e}")
     assert hist[-1][1] < hist[0][1]
     plain, den = [], []
     for s in range(3000, 3004):
