@@ -433,7 +433,10 @@ kp_status kp_transport(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, vo
 
   fill_dust(ctx, counts, ctx->hdust);
   if ((st = upload_small(ctx, s))) return st;
-  KP_HIP(launch_fill_zero(ctx->d_tally, tally_need * sizeof(double), s), "tally clear");
+  KP_HIP(launch_tally_init(ctx->d_tally, ctx->d_rho, ctx->d_bhat,
+                           ctx->d_bhat ? ctx->d_bhat + ctx->ncell : nullptr,
+                           ctx->d_bhat ? ctx->d_bhat + 2 * ctx->ncell : nullptr, ctx->ncell, nl, all_sphere, s),
+         "tally initialisation");
   KP_HIP(launch_fill_zero(ctx->d_stats, sizeof(StatsDev), s), "stats clear");
   KP_HIP(launch_fill_zero(ctx->d_counter, sizeof(unsigned long long), s), "counter clear");
   if (trace_need) KP_HIP(launch_fill_zero(ctx->d_traces, trace_need * sizeof(TraceDev), s), "trace clear");

@@ -269,14 +269,16 @@ __global__ void __launch_bounds__(256) k_conv3_tiled(ConvArgs a) {
 // a 64 x 64 (co, k) tile and a chunk of pixels; each 32-pixel slab of gz and
 // of the im2col matrix is loaded with 16-byte loads and written transposed to
 // LDS so that every lane's MFMA operand (8 consecutive pixels) is one 16-byte
-// LDS read.  Partial tiles are added to the FP32 gradient with atomics; the
-// workgroups of the first K tile also add the bias gradient sum_p gz[p][co].
+// LDS read; the next slab's global loads are in flight during the current
+// slab's MFMAs (double-buffered LDS, one barrier per slab).  Partial tiles are
+// added to the FP32 gradient with atomics; the workgroups of the first K tile
+// also add the bias gradient sum_p gz[p][co].
 // ---------------------------------------------------------------------------
 constexpr int WG_LDS_STRIDE = 40;  // 32 pixels + 8 pad (row = 80 bytes, 16-byte aligned)
 
 __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[64 * WG_LDS_STRIDE];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[64 * WG_LDS_STRIDE];
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][64 * WG_LDS_STRIDE];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][64 * WG_LDS_STRIDE];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int i = lane & 15, g = lane >> 4;
@@ -292,26 +294,19 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
   const int lkk = kx / a.cin, lc = kx - lkk * a.cin;
   const bool b_ok = lkk < 9;
   const int ldy = lkk / 3 - 1, ldx = lkk % 3 - 1;
-  f32x4 acc[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
   // the first K tile's workgroups also sum gz over their pixels: the bias gradient
   const bool do_bias = kt == 0 && a_ok;
   float bsum[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) bsum[j] = 0.f;
   const u32x4 zero = {0u, 0u, 0u, 0u};
-  for (int s0 = p_begin; s0 < p_end; s0 += 32) {
+  // global loads of one 32-pixel slab into registers
+  auto load = [&](int s0, u32x4& va, u32x4& vb) {
     const int p = s0 + sp;
-    u32x4 va = zero, vb = zero;
+    va = zero;
+    vb = zero;
     if (p < p_end) {
       if (a_ok) va = ld16(a.gz + (size_t)p * a.gzs + m0 + s8);
-      if (do_bias) {
-        float f[8];
-        unpack8(va, f);
-#pragma unroll
-        for (int j = 0; j < 8; ++j) bsum[j] += f[j];
-      }
       if (b_ok) {
         const int w = p % a.W, h = (p / a.W) % a.H, n = p / (a.W * a.H);
         const int hh = h + ldy, ww = w + ldx;
@@ -319,21 +314,43 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
           vb = ld16(a.x + ((size_t)(n * a.H + hh) * a.W + ww) * a.xs + lc);
       }
     }
+  };
+  // transposed store of a slab into LDS buffer `buf` (+ bias partial sums)
+  auto stage = [&](int buf, const u32x4& va, const u32x4& vb) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      As[(s8 + 2 * j) * WG_LDS_STRIDE + sp] = (uint16_t)(va[j] & 0xFFFFu);
-      As[(s8 + 2 * j + 1) * WG_LDS_STRIDE + sp] = (uint16_t)(va[j] >> 16);
-      Bs[(s8 + 2 * j) * WG_LDS_STRIDE + sp] = (uint16_t)(vb[j] & 0xFFFFu);
-      Bs[(s8 + 2 * j + 1) * WG_LDS_STRIDE + sp] = (uint16_t)(vb[j] >> 16);
+      As[buf][(s8 + 2 * j) * WG_LDS_STRIDE + sp] = (uint16_t)(va[j] & 0xFFFFu);
+      As[buf][(s8 + 2 * j + 1) * WG_LDS_STRIDE + sp] = (uint16_t)(va[j] >> 16);
+      Bs[buf][(s8 + 2 * j) * WG_LDS_STRIDE + sp] = (uint16_t)(vb[j] & 0xFFFFu);
+      Bs[buf][(s8 + 2 * j + 1) * WG_LDS_STRIDE + sp] = (uint16_t)(vb[j] >> 16);
     }
-    __syncthreads();
-    const u32x4 av = *(const u32x4*)(As + (16 * wv + i) * WG_LDS_STRIDE + 8 * g);
+    if (do_bias) {
+      float f[8];
+      unpack8(va, f);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) bsum[j] += f[j];
+    }
+  };
+  f32x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  u32x4 va, vb;
+  load(p_begin, va, vb);
+  stage(0, va, vb);
+  __syncthreads();
+  int cur = 0;
+  for (int s0 = p_begin; s0 < p_end; s0 += 32) {
+    const bool more = s0 + 32 < p_end;
+    if (more) load(s0 + 32, va, vb);  // in flight during the MFMAs below
+    const u32x4 av = *(const u32x4*)(&As[cur][(16 * wv + i) * WG_LDS_STRIDE + 8 * g]);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      const u32x4 bv = *(const u32x4*)(Bs + (16 * t + i) * WG_LDS_STRIDE + 8 * g);
+      const u32x4 bv = *(const u32x4*)(&Bs[cur][(16 * t + i) * WG_LDS_STRIDE + 8 * g]);
       acc[t] = mfma(av, bv, acc[t]);
     }
+    if (more) stage(cur ^ 1, va, vb);
     __syncthreads();
+    cur ^= 1;
   }
   if (kt == 0) {
     // lanes with equal (lane & 7) hold the same 8 channels: reduce them

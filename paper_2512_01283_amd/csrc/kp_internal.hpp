@@ -93,6 +93,9 @@ struct ImageArgs {
 
 // Tally layout [lambda][cell][stride] FP64: 6 reals (stride 8, one 64-B block
 // per cell) when every wavelength has spherical grains, else 9 (stride 16).
+// The slot after the coherency holds the cell's density, and with stride 16
+// the next three the alignment direction (read by the transport step from
+// the same line its atomics update).
 inline int tally_components(bool sphere) { return sphere ? 6 : 9; }
 inline int tally_stride(bool sphere) { return sphere ? 8 : 16; }
 
@@ -102,6 +105,8 @@ hipError_t launch_transport(const TransportArgs& a, bool fp64, bool aligned, boo
 hipError_t launch_image(const ImageArgs& a, bool aligned, bool sphere, bool user_source,
                         hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_tally_init(double* tally, const float* rho, const float* bx, const float* by,
+                             const float* bz, uint64_t ncell, int n_lambda, bool sphere, hipStream_t s);
 hipError_t launch_validate(const float* rho, const float* bx, const float* by, const float* bz,
                            uint64_t n, unsigned long long* bad, hipStream_t s);
 int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, int block_size);

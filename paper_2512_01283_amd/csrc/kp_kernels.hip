@@ -179,10 +179,25 @@ __device__ __forceinline__ void coherency(const V3<R>& n, R JI, R JQ, R JU, R JV
 // Components of the tally kept per cell and the per-cell stride in doubles:
 // spheres never create circular polarisation from unpolarised light, so the
 // antisymmetric (V) part of the coherency is identically zero.
+// Per-cell tally block of TS doubles (one 64- or 128-byte aligned block):
+// slots [0, NC) the coherency sums, slot NC the cell's density, and for
+// non-spherical grains slots NC+1..NC+3 the alignment direction.  The step
+// that enters a cell reads its density (and direction) from the block whose
+// coherency it adds to when it leaves, so the line the atomics need is
+// usually already in L2 and a cell costs one line from HBM instead of two.
 template <bool SPHERE> struct TallyShape {
   static constexpr int NC = SPHERE ? 6 : 9;
   static constexpr int TS = SPHERE ? 8 : 16;
+  static constexpr int RHO = NC;
+  static constexpr bool HAS_B = !SPHERE;  // direction in slots NC+1..NC+3
 };
+
+template <bool ALIGNED, bool SPHERE>
+__device__ __forceinline__ V3<double> cell_bdir(const TransportArgs& a, const double* blk, uint64_t c) {
+  using TSh = TallyShape<SPHERE>;
+  if (TSh::HAS_B) return V3<double>{blk[TSh::RHO + 1], blk[TSh::RHO + 2], blk[TSh::RHO + 3]};
+  return V3<double>{(double)a.bx[c], (double)a.by[c], (double)a.bz[c]};
+}
 
 // Wave-cooperative flush of the lanes whose `need` is set: every such lane
 // stages (key, NC values) in this wavefront's LDS area; then lane L adds
@@ -374,7 +389,8 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
   if (tz < td) { td = tz; axis = 2; }
   if (!(td < inf)) return END_NUMERIC;
   const DustDev& D = a.dust[p.lam];
-  const double rhod = (double)a.rho[c];
+  const double* blk = a.tally + ((uint64_t)p.lam * a.ncell + c) * TallyShape<SPHERE>::TS;
+  const double rhod = blk[TallyShape<SPHERE>::RHO];
   const double kbd = rhod * D.ks_cell;
   double tld;
   bool scat;
@@ -385,7 +401,7 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
   Quat<R> q{(R)1, (R)0, (R)0, (R)0};
   V3<double> bdir{0.0, 0.0, 1.0};
   if (ALIGNED && rho > (R)0) {
-    bdir = V3<double>{(double)a.bx[c], (double)a.by[c], (double)a.bz[c]};
+    bdir = cell_bdir<ALIGNED, SPHERE>(a, blk, c);
     q = grain_quat(V3<R>{(R)bdir.x, (R)bdir.y, (R)bdir.z});
   }
   if (rho > (R)0 && tl > (R)0) {
@@ -502,7 +518,8 @@ __device__ uint32_t scatter_step(Packet<R>& p, const TransportArgs& a) {
   Quat<R> q{(R)1, (R)0, (R)0, (R)0};
   V3<double> bdir{0.0, 0.0, 1.0};
   if (ALIGNED) {
-    bdir = V3<double>{(double)a.bx[c], (double)a.by[c], (double)a.bz[c]};
+    const double* blk = a.tally + ((uint64_t)p.lam * a.ncell + c) * TallyShape<SPHERE>::TS;
+    bdir = cell_bdir<ALIGNED, SPHERE>(a, blk, c);
     q = grain_quat(V3<R>{(R)bdir.x, (R)bdir.y, (R)bdir.z});
   }
   if (!scatter<R, ALIGNED, SPHERE>(p, q, bdir, D, a.seed)) return END_NUMERIC;
@@ -873,6 +890,26 @@ __global__ void k_fill_zero(uint64_t* p, uint64_t nwords, unsigned char* tail, i
   if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0;
 }
 
+// Tally blocks before a transport run: coherency slots zero, the density in
+// slot nc, and (co_b) the alignment direction in slots nc+1..nc+3, for every
+// (wavelength, cell); the rest of each block zero.
+__global__ void k_tally_init(double* tally, const float* rho, const float* bx, const float* by,
+                             const float* bz, uint64_t ncell, int n_lambda, int ts, int nc, int co_b) {
+  const uint64_t n = (uint64_t)n_lambda * ncell;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const uint64_t c = i % ncell;
+    double* b = tally + i * ts;
+    for (int k = 0; k < ts; ++k) b[k] = 0.0;
+    b[nc] = (double)rho[c];
+    if (co_b) {
+      b[nc + 1] = (double)bx[c];
+      b[nc + 2] = (double)by[c];
+      b[nc + 3] = (double)bz[c];
+    }
+  }
+}
+
 __global__ void k_validate(const float* rho, const float* bx, const float* by, const float* bz,
                            uint64_t n, unsigned long long* bad) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -950,6 +987,18 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   if (blocks == 0) blocks = 1;
   hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)blocks), dim3(256), 0, s, (uint64_t*)p, nwords,
                      (unsigned char*)p + nwords * 8, ntail);
+  return hipGetLastError();
+}
+
+hipError_t launch_tally_init(double* tally, const float* rho, const float* bx, const float* by,
+                             const float* bz, uint64_t ncell, int n_lambda, bool sphere, hipStream_t s) {
+  const int ts = tally_stride(sphere), nc = tally_components(sphere);
+  const int co_b = (!sphere && bx) ? 1 : 0;
+  uint64_t blocks = ((uint64_t)n_lambda * ncell + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_tally_init, dim3((unsigned)blocks), dim3(256), 0, s, tally, rho, bx, by, bz, ncell,
+                     n_lambda, ts, nc, co_b);
   return hipGetLastError();
 }
 
