@@ -75,6 +75,8 @@ struct Packet {
   R tau_path;         // sum of |continuous extinction exponent| along the path
   R u0, u1, u2, u3;   // uniforms of the Philox block `blk`
   double e_abs, e_scat, e_gain;
+  double ks, ke;      // per-wavelength kappa_sca and kappa_ext times the cell size, held
+  R ka;               // in registers (no dependent load per step); ka = kappa_abs dx
   uint64_t pid, hash;
   int64_t last;
   int ci, cj, ck;
@@ -126,6 +128,9 @@ __device__ bool init_packet(Packet<R>& p, uint64_t g, const TransportArgs& a) {
   }
   p.tau = -log((double)next_uniform(p, a.seed));
   p.w0 = (R)a.dust[lo].w0;
+  p.ks = a.dust[lo].ks_cell;
+  p.ke = a.dust[lo].ke_cell;
+  p.ka = (R)a.dust[lo].ka_cell;
   p.I = p.w0; p.Q = (R)0; p.U = (R)0; p.V = (R)0;
   p.e_abs = 0.0; p.e_scat = 0.0; p.e_gain = 0.0;
   p.tau_path = (R)0;
@@ -180,16 +185,20 @@ __device__ __forceinline__ void coherency(const V3<R>& n, R JI, R JQ, R JU, R JV
 // spheres never create circular polarisation from unpolarised light, so the
 // antisymmetric (V) part of the coherency is identically zero.
 // Per-cell tally block of TS doubles (one 64- or 128-byte aligned block):
-// slots [0, NC) the coherency sums, slot NC the cell's density, and for
-// non-spherical grains slots NC+1..NC+3 the alignment direction.  The step
-// that enters a cell reads its density (and direction) from the block whose
-// coherency it adds to when it leaves, so the line the atomics need is
-// usually already in L2 and a cell costs one line from HBM instead of two.
+// slots [0, NC) the coherency sums.  For non-spherical grains slot NC holds
+// the cell's density and slots NC+1..NC+3 its alignment direction: the step
+// that enters a cell reads them from the block whose coherency it adds to
+// when it leaves, one 128-byte line instead of four (density and three
+// direction planes, 256 MB at 256^3, too large to stay in the Infinity
+// Cache).  Spherical grains read the density from the compact FP32 array
+// (64 MB at 256^3), which stays cache-resident; there the density load is
+// the step's critical-path latency and the tally line's fetch is better
+// left to the atomics, off that path.
 template <bool SPHERE> struct TallyShape {
   static constexpr int NC = SPHERE ? 6 : 9;
   static constexpr int TS = SPHERE ? 8 : 16;
   static constexpr int RHO = NC;
-  static constexpr bool HAS_B = !SPHERE;  // direction in slots NC+1..NC+3
+  static constexpr bool HAS_B = !SPHERE;  // density and direction in slots NC..NC+3
 };
 
 template <bool ALIGNED, bool SPHERE>
@@ -390,8 +399,8 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
   if (!(td < inf)) return END_NUMERIC;
   const DustDev& D = a.dust[p.lam];
   const double* blk = a.tally + ((uint64_t)p.lam * a.ncell + c) * TallyShape<SPHERE>::TS;
-  const double rhod = blk[TallyShape<SPHERE>::RHO];
-  const double kbd = rhod * D.ks_cell;
+  const double rhod = TallyShape<SPHERE>::HAS_B ? blk[TallyShape<SPHERE>::RHO] : (double)a.rho[c];
+  const double kbd = rhod * p.ks;
   double tld;
   bool scat;
   if (kbd > 0.0 && p.tau < kbd * td) { tld = p.tau / kbd; scat = true; }
@@ -410,7 +419,7 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
     R JI, JQ, JU, JV;
     if (SPHERE && !ALIGNED) {
       // spheres: extinction is the scalar absorption e^{-rho kappa_abs l}
-      const R m1 = rho * (R)D.ka_cell;
+      const R m1 = rho * p.ka;
       const R E = k_exp(-m1 * tl), G = tl * phi1(m1 * tl);
       p.tau_path += m1 * tl;
       JI = p.I * G; JQ = p.Q * G; JU = p.U * G; JV = p.V * G;
@@ -427,7 +436,7 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
       if (ALIGNED) eta2(q, n, V3<R>{(R)ngd.x, (R)ngd.y, (R)ngd.z}, c2, s2);
       double a1, a2, a3;
       alphas<double, SPHERE>(D, ngd.z, a1, a2, a3);
-      const double ked = rhod * D.ke_cell;
+      const double ked = rhod * p.ke;
       const double xAd = (ked * (a1 + a2) - kbd) * tld, xBd = (ked * (a1 - a2) - kbd) * tld;
       const double xUd = (ked * a1 - kbd) * tld, yd = ked * a3 * tld;
       const R xA = (R)xAd, xB = (R)xBd, xU = (R)xUd;
@@ -890,9 +899,10 @@ __global__ void k_fill_zero(uint64_t* p, uint64_t nwords, unsigned char* tail, i
   if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0;
 }
 
-// Tally blocks before a transport run: coherency slots zero, the density in
-// slot nc, and (co_b) the alignment direction in slots nc+1..nc+3, for every
-// (wavelength, cell); the rest of each block zero.
+// Tally blocks before a transport run: coherency slots zero and, with co_b
+// (non-spherical grains), the density in slot nc and the alignment direction
+// in slots nc+1..nc+3, for every (wavelength, cell); the rest of each block
+// zero.
 __global__ void k_tally_init(double* tally, const float* rho, const float* bx, const float* by,
                              const float* bz, uint64_t ncell, int n_lambda, int ts, int nc, int co_b) {
   const uint64_t n = (uint64_t)n_lambda * ncell;
@@ -901,11 +911,11 @@ __global__ void k_tally_init(double* tally, const float* rho, const float* bx, c
     const uint64_t c = i % ncell;
     double* b = tally + i * ts;
     for (int k = 0; k < ts; ++k) b[k] = 0.0;
-    b[nc] = (double)rho[c];
     if (co_b) {
-      b[nc + 1] = (double)bx[c];
-      b[nc + 2] = (double)by[c];
-      b[nc + 3] = (double)bz[c];
+      b[nc] = (double)rho[c];
+      b[nc + 1] = bx ? (double)bx[c] : 0.0;
+      b[nc + 2] = by ? (double)by[c] : 0.0;
+      b[nc + 3] = bz ? (double)bz[c] : 1.0;
     }
   }
 }
@@ -993,7 +1003,7 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
 hipError_t launch_tally_init(double* tally, const float* rho, const float* bx, const float* by,
                              const float* bz, uint64_t ncell, int n_lambda, bool sphere, hipStream_t s) {
   const int ts = tally_stride(sphere), nc = tally_components(sphere);
-  const int co_b = (!sphere && bx) ? 1 : 0;
+  const int co_b = sphere ? 0 : 1;
   uint64_t blocks = ((uint64_t)n_lambda * ncell + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (blocks == 0) blocks = 1;
