@@ -128,7 +128,14 @@ def main():
     cfg = W.flared_disk(packets=args.packets)
     ctx = P.Context(0).load(cfg)
     stream = torch.cuda.current_stream()
-    opts = dict(block_size=args.block_size, blocks_per_cu=args.blocks_per_cu)
+    # launch schedule: the autotuner's cached choice for this workload and
+    # device (paper_2512_01283_amd/tuning.json), overridden by the flags
+    from paper_2512_01283_amd import autotune as A
+    opts = A.tuned_opts(cfg, torch.cuda.get_device_name(0))
+    if args.block_size:
+        opts["block_size"] = args.block_size
+    if args.blocks_per_cu:
+        opts["blocks_per_cu"] = args.blocks_per_cu
     dn = None
     if not args.no_denoiser:
         from paper_2512_01283_amd import denoiser as DN
@@ -191,6 +198,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic()},
         "detail": {"kernel": "k_transport<float,false,true>",
+                   "schedule": opts,
                    "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, "
                                    "profiles/k_transport_disk256_1e8.md)",
                    "algorithmic_gb_per_launch": bytes_launch / 1e9,

@@ -13,6 +13,9 @@ workload's structure and the device name, so that a production run or the
 benchmark picks the tuned schedule without searching again:
 
     python -m paper_2512_01283_amd.autotune disk      # tune the 256^3 disk
+    python -m paper_2512_01283_amd.autotune disk batched --measure
+        # tune both, then time each whole workload with the default and the
+        # tuned schedule (one warm-up run each) and print one JSON line
 """
 from __future__ import annotations
 
@@ -109,24 +112,52 @@ def save(cfg, device_name: str, opts: dict, ms: float, scale: float) -> None:
     os.replace(CACHE + ".tmp", CACHE)
 
 
+def measure(cfg, opts, label):
+    """Whole-workload kp_run with the given schedule: one warm-up run, then
+    one timed run (HIP-event kernel times, wall clock around kp_run)."""
+    import torch
+
+    from . import polrad as P
+    ctx = P.Context(0).load(cfg)
+    ctx.run(**opts)
+    t0 = time.perf_counter()
+    ctx.run(**opts)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = ctx.stats()
+    ctx.close()
+    return {"schedule": label, "opts": opts, "ms_transport": st["ms_transport"], "ms_image": st["ms_image"],
+            "wall_s": wall, "packets": int(st["packets"]), "packets_per_s": st["packets"] / wall,
+            "cell_steps": int(st["cell_steps"]), "scatterings": int(st["scatterings"])}
+
+
 def main(argv):
     import torch
 
     from . import workloads as W
-    which = argv[1] if len(argv) > 1 else "disk"
-    if which == "disk":
-        cfg, scale = W.flared_disk(), 0.1
-    elif which == "batched":
-        cfg, scale = W.batched_disk(), 0.05
-    elif which == "slab":
-        cfg, scale = W.slab_clump(), 0.5
-    else:
-        raise SystemExit(f"unknown workload {which!r} (disk, batched, slab)")
+    names = [a for a in argv[1:] if not a.startswith("--")] or ["disk"]
     dev = torch.cuda.get_device_name(0)
-    print(f"tuning {cfg['name']} on {dev} at {scale} x packets", flush=True)
-    opts, ms, _ = tune(cfg, scale=scale)
-    save(cfg, dev, opts, ms, scale)
-    print(json.dumps({"workload": cfg["name"], "device": dev, "opts": opts, "ms": ms}))
+    out = {"device": dev}
+    for which in names:
+        if which == "disk":
+            cfg, scale = W.flared_disk(), 0.1
+        elif which == "batched":
+            cfg, scale = W.batched_disk(), 0.05
+        elif which == "slab":
+            cfg, scale = W.slab_clump(), 0.5
+        else:
+            raise SystemExit(f"unknown workload {which!r} (disk, batched, slab)")
+        print(f"tuning {cfg['name']} on {dev} at {scale} x packets", flush=True)
+        opts, ms, trials = tune(cfg, scale=scale, log=lambda m: print(m, flush=True))
+        save(cfg, dev, opts, ms, scale)
+        rec = {"opts": opts, "ms_at_scale": ms, "packet_scale": scale,
+               "trials": [{"opts": o, "ms": t} for o, t in trials]}
+        if "--measure" in argv:
+            rec["whole"] = [measure(cfg, {}, "default"), measure(cfg, opts, "tuned")]
+            for r in rec["whole"]:
+                print(json.dumps(r), flush=True)
+        out[cfg["name"]] = rec
+    print(json.dumps(out))
 
 
 if __name__ == "__main__":
