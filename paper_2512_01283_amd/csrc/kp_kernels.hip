@@ -228,14 +228,28 @@ __device__ __forceinline__ void wave_flush(bool need, int64_t key, const double 
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   constexpr int G = 64 / NC;
+  constexpr int U = 4;  // rounds whose LDS reads are issued before one wait
   const int slot = lane / NC, k = lane - slot * NC;
   if (slot < G) {
-    for (int base = 0; base < n; base += G) {
-      const int e = base + slot;
-      if (e < n) {
-        const double v = sv[e * NC + k];
-        if (v != 0.0) unsafeAtomicAdd(tally + (uint64_t)sk[e] * TS + k, v);
+    for (int base = 0; base < n; base += U * G) {
+      double v[U];
+      long long key_r[U];
+      // reads of entries beyond n stay inside the 64-entry staging area
+      // (index clamped) and their atomics are masked below
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = min(base + u * G + slot, 63);
+        v[u] = sv[e * NC + k];
+        key_r[u] = sk[e];
       }
+      // keep every key read ahead of the branches below (one LDS wait
+      // for all of them instead of one per round)
+#pragma unroll
+      for (int u = 0; u < U; ++u) asm volatile("" : : "v"(key_r[u]));
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (base + u * G + slot < n && v[u] != 0.0)
+          unsafeAtomicAdd(tally + (uint64_t)key_r[u] * TS + k, v[u]);
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
