@@ -10,14 +10,18 @@
  *
  * Per image, with s = mean of I over the image and Ihat = I / s, the input
  * features are x = (ln max(Ihat, 1e-6), Q/I, U/I, V/I) (the ratios clamped to
- * [-1, 1], the range of a physical Stokes vector, and 0 where I <= 0).  Network (all 3x3 convolutions have zero padding 1 and a bias;
- * relu after every one; widths c1, c2, c3):
- *   e1    = conv(conv(x, 4->c1), c1->c1)                      H x W
- *   e2    = conv(conv(pool(e1), c1->c2), c2->c2)              H/2
- *   m3    = conv(conv(pool(e2), c2->c3), c3->c3)              H/4
- *   d2    = conv(conv([up(m3), e2], c3+c2->c2), c2->c2)       H/2
- *   d1    = conv(conv([up(d2), e1], c2+c1->c1), c1->c1)       H
+ * [-1, 1], the range of a physical Stokes vector, and 0 where I <= 0).
+ * Network: a U-Net of L levels (2..6) with widths c1..cL; every 3x3
+ * convolution has zero padding 1, a bias and a relu; a block is two of them.
+ * For L = 3:
+ *   e1    = block(x, 4->c1)                                  H x W
+ *   e2    = block(pool(e1), c1->c2)                          H/2
+ *   m3    = block(pool(e2), c2->c3)                          H/4
+ *   d2    = block([up(m3), e2], c3+c2->c2)                   H/2
+ *   d1    = block([up(d2), e1], c2+c1->c1)                   H
  *   delta = head(d1)        head: 1x1 convolution c1 -> 2
+ * and in general encoder blocks e1..e(L-1), each followed by pool, the block
+ * mL at H / 2^(L-1), and decoder blocks d(L-1)..d1 on [up(below), e_l].
  * pool = 2x2 mean, up = 2x nearest repeat, [a, b] = channel concatenation
  * (a first).  Predicted fractions q' = Q/I + delta_0, u' = U/I + delta_1;
  * the denoised map is (I, q' I, u' I, V).
@@ -28,7 +32,8 @@
  * 1e-8, bias-corrected) on FP32 master weights.
  *
  * Parameters are one flat FP32 array: for each convolution in the order
- * e1a e1b e2a e2b m3a m3b d2a d2b d1a d1b its weights [cout][3][3][cin]
+ * e1a e1b ... e(L-1)a e(L-1)b mLa mLb d(L-1)a d(L-1)b ... d1a d1b
+ * (L = 3: e1a e1b e2a e2b m3a m3b d2a d2b d1a d1b) its weights [cout][3][3][cin]
  * (w[o][dy][dx][c] multiplies x[h + dy - 1][w + dx - 1][c]) then its bias
  * [cout]; then the head's weights [2][c1] and bias [2].
  *
@@ -38,8 +43,8 @@
  *
  * Maps are FP64 device arrays [batch][4][height][width] (I, Q, U, V), the
  * layout of kp_get_images_device for one wavelength's views, so images of a
- * run can be passed straight in.  height and width must be multiples of 4
- * (two pooling levels); batch * height * width <= 2^24.
+ * run can be passed straight in.  height and width must be multiples of
+ * 2^(L-1) (L-1 pooling levels); batch * height * width <= 2^24.
  *
  * Errors follow polrad.h: every call returns kp_status, arguments are
  * validated before any launch, kp_dn_last_error() gives the message.  A
@@ -59,10 +64,11 @@ extern "C" {
 
 typedef struct kp_dn kp_dn;
 
-/* Create a denoiser of widths c1, c2, c3 (each a multiple of 16 in
- * [16, 512]) on HIP device `device`, with all parameters zero.  *out
- * receives an owned handle (release with kp_dn_destroy). */
-kp_status kp_dn_create(int device, int32_t c1, int32_t c2, int32_t c3, kp_dn **out);
+/* Create a denoiser of n_levels (2..6) levels with widths[n_levels] (host;
+ * each a multiple of 16 in [16, 512]) on HIP device `device`, with all
+ * parameters zero.  *out receives an owned handle (release with
+ * kp_dn_destroy). */
+kp_status kp_dn_create(int device, const int32_t *widths, int32_t n_levels, kp_dn **out);
 void kp_dn_destroy(kp_dn *dn);
 const char *kp_dn_last_error(const kp_dn *dn);
 

@@ -11,13 +11,16 @@ Per image with maps (I, Q, U, V) and s = mean of I over the image:
   Ihat  = I / s
   x     = (ln max(Ihat, 1e-6), Q/I, U/I, V/I)   [N, H, W, 4]
           (fractions clipped to [-1, 1], their physical range; 0 where I <= 0)
-The network (widths c1, c2, c3):
+The network: a U-Net of L levels with widths c1..cL (two 3x3 convolutions
++ relu per block; for L = 3):
   enc1  = relu(conv3(relu(conv3(x,  4->c1)), c1->c1))          H x W
   enc2  = relu(conv3(relu(conv3(pool(enc1), c1->c2)), c2->c2)) H/2
   mid   = relu(conv3(relu(conv3(pool(enc2), c2->c3)), c3->c3)) H/4
   dec2  = relu(conv3(relu(conv3([up(mid), enc2], c3+c2->c2)), c2->c2))
   dec1  = relu(conv3(relu(conv3([up(dec2), enc1], c2+c1->c1)), c1->c1))
   delta = conv1(dec1, c1->2)                                    [N, H, W, 2]
+and in general encoder blocks e1..e(L-1) (each followed by pool), the block
+mL at H / 2^(L-1), decoder blocks d(L-1)..d1 on [up(below), skip].
 Prediction: q' = Q/I + delta_0, u' = U/I + delta_1; denoised Q = q' I,
 U = u' I (I and V unchanged).  Loss against target maps (Q_t, U_t):
   L = mean over images of  sum_p [(q' Ihat - Q_t/s)^2 + (u' Ihat - U_t/s)^2]
@@ -33,20 +36,30 @@ from __future__ import annotations
 import numpy as np
 
 WIDTHS = (48, 96, 192)
-LAYERS = ("e1a", "e1b", "e2a", "e2b", "m3a", "m3b", "d2a", "d2b", "d1a", "d1b")
+
+
+def layer_names(widths=WIDTHS):
+    L = len(widths)
+    enc = [f"e{l}" for l in range(1, L)]
+    dec = [f"d{l}" for l in range(L - 1, 0, -1)]
+    return [b + s for b in enc + [f"m{L}"] + dec for s in ("a", "b")]
 
 
 def layer_shapes(widths=WIDTHS, cin=4):
-    c1, c2, c3 = widths
-    io = {"e1a": (cin, c1), "e1b": (c1, c1), "e2a": (c1, c2), "e2b": (c2, c2),
-          "m3a": (c2, c3), "m3b": (c3, c3), "d2a": (c3 + c2, c2), "d2b": (c2, c2),
-          "d1a": (c2 + c1, c1), "d1b": (c1, c1)}
+    c = list(widths)
+    L = len(c)
+    io = {"e1a": (cin, c[0]), "e1b": (c[0], c[0])}
+    for l in range(2, L):
+        io[f"e{l}a"], io[f"e{l}b"] = (c[l - 2], c[l - 1]), (c[l - 1], c[l - 1])
+    io[f"m{L}a"], io[f"m{L}b"] = (c[L - 2], c[L - 1]), (c[L - 1], c[L - 1])
+    for l in range(L - 1, 0, -1):
+        io[f"d{l}a"], io[f"d{l}b"] = (c[l] + c[l - 1], c[l - 1]), (c[l - 1], c[l - 1])
     shapes = {}
-    for k in LAYERS:
+    for k in layer_names(widths):
         ci, co = io[k]
         shapes[k + ".w"] = (co, 3, 3, ci)
         shapes[k + ".b"] = (co,)
-    shapes["head.w"] = (2, c1)
+    shapes["head.w"] = (2, c[0])
     shapes["head.b"] = (2,)
     return shapes
 
@@ -127,7 +140,8 @@ def relu(z):
 # --------------------------------------------------------------------------
 def forward(p, x):
     """Network output delta [N,H,W,2] and the cache for backward."""
-    c = {"x": x}
+    L = 1 + sum(1 for k in p if k[0] == "e" and k.endswith("a.w"))
+    c = {"x": x, "L": L}
 
     def block(name, inp):
         za = conv3(inp, p[name + "a.w"], p[name + "a.b"])
@@ -137,12 +151,15 @@ def forward(p, x):
         c[name] = (inp, ya, yb)
         return yb
 
-    e1 = block("e1", x)
-    e2 = block("e2", pool(e1))
-    m3 = block("m3", pool(e2))
-    d2 = block("d2", np.concatenate([up(m3), e2], axis=3))
-    d1 = block("d1", np.concatenate([up(d2), e1], axis=3))
-    return d1 @ p["head.w"].T + p["head.b"], c
+    skips, h = [], x
+    for l in range(1, L):
+        h = block(f"e{l}", h)
+        skips.append(h)
+        h = pool(h)
+    h = block(f"m{L}", h)
+    for l in range(L - 1, 0, -1):
+        h = block(f"d{l}", np.concatenate([up(h), skips[l - 1]], axis=3))
+    return h @ p["head.w"].T + p["head.b"], c
 
 
 def features(maps):
@@ -176,10 +193,11 @@ def loss_grad(delta, x, Ihat, target):
 def backward(p, cache, gdelta):
     """Gradient of a loss with dL/d delta = gdelta w.r.t. every parameter."""
     g = {}
+    L = cache["L"]
     d1 = cache["d1"][2]
     g["head.w"] = gdelta.reshape(-1, 2).T @ d1.reshape(-1, d1.shape[-1])
     g["head.b"] = gdelta.reshape(-1, 2).sum(0)
-    gd1 = gdelta @ p["head.w"]
+    gh = gdelta @ p["head.w"]
 
     def block_back(name, gy):
         inp, ya, yb = cache[name]
@@ -189,19 +207,15 @@ def backward(p, cache, gdelta):
         ginp, g[name + "a.w"], g[name + "a.b"] = conv3_backward(inp, p[name + "a.w"], gza)
         return ginp
 
-    c1 = cache["e1"][2].shape[-1]
-    c2 = cache["e2"][2].shape[-1]
-    gcat1 = block_back("d1", gd1)
-    gup2, ge1 = gcat1[..., :c2], gcat1[..., c2:]
-    gcat2 = block_back("d2", up_backward(gup2))
-    c3 = gcat2.shape[-1] - c2
-    gup3, ge2 = gcat2[..., :c3], gcat2[..., c3:]
-    gm3_in = block_back("m3", up_backward(gup3))
-    ge2 = ge2 + pool_backward(gm3_in)
-    ge2_in = block_back("e2", ge2)
-    ge1 = ge1 + pool_backward(ge2_in)
-    block_back("e1", ge1)
-    assert gcat1.shape[-1] == c2 + c1
+    gskip = {}
+    for l in range(1, L):                       # decoder, top level first
+        gcat = block_back(f"d{l}", gh)
+        cb = cache[f"d{l}"][0].shape[-1] - cache[f"e{l}"][2].shape[-1]   # channels of up(below)
+        gskip[l] = gcat[..., cb:]
+        gh = up_backward(gcat[..., :cb])        # gradient of the block below's output
+    gin = block_back(f"m{L}", gh)               # gradient of pool(e(L-1))
+    for l in range(L - 1, 0, -1):
+        gin = block_back(f"e{l}", gskip[l] + pool_backward(gin))
     return g
 
 

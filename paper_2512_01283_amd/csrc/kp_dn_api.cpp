@@ -18,7 +18,7 @@ using namespace kp::dn;
 
 namespace {
 
-enum { E1A, E1B, E2A, E2B, M3A, M3B, D2A, D2B, D1A, D1B, NLAYER };
+constexpr int MAX_LEVELS = 6;
 
 struct Layer {
   int cin_true = 0;  // input channels of the network layer
@@ -30,22 +30,30 @@ struct Layer {
   size_t pk_off = 0, pkd_off = 0;       // offsets into the packed BF16 weights
 };
 
-// workspace buffers (element offsets into the BF16 / FP32 / FP64 arenas)
+// Workspace of one batch shape.  Level l (0 = full resolution) holds
+// cap / 4^l pixels; widths c[l].  Encoder level l < L-1: block input (x0 at
+// l = 0, pooled map otherwise), conv-a output, and the block output written
+// into the skip part (channels c[l+1]..) of cat[l]; the bottleneck l = L-1:
+// input pool, conv-a output, output; decoder level l: cat[l] (up(below) in
+// channels 0..c[l+1]-1), conv-a output, output.  Gradients mirror them.
 struct Work {
-  size_t cap = 0;    // level-1 pixel capacity
+  size_t cap = 0;    // level-0 pixel capacity
   int bcap = 0;      // batch capacity
   void* mem = nullptr;
   size_t bytes = 0;
-  // BF16 activations
-  uint16_t *x0, *a1a, *cat1, *pool1, *a2a, *cat2, *pool2, *a3a, *m3, *d2a, *d2, *d1a, *d1;
-  // BF16 gradients
-  uint16_t *g1, *g1b, *gcat1, *g2, *g2b, *gcat2, *g3, *g3b, *gpool2, *ge2, *ge2b, *gpool1, *ge1, *ge1b;
+  uint16_t* x0 = nullptr;
+  uint16_t *pool[MAX_LEVELS] = {}, *ea[MAX_LEVELS] = {}, *cat[MAX_LEVELS] = {}, *da[MAX_LEVELS] = {},
+           *dout[MAX_LEVELS] = {};
+  uint16_t *ma = nullptr, *mout = nullptr;
+  uint16_t *gd[MAX_LEVELS] = {}, *gdb[MAX_LEVELS] = {}, *gcat[MAX_LEVELS] = {}, *ge[MAX_LEVELS] = {},
+           *geb[MAX_LEVELS] = {}, *gpool[MAX_LEVELS] = {};
+  uint16_t *gm = nullptr, *gmb = nullptr;
   float *xq, *ihat, *tgt, *out, *go;
   double *sum, *loss;
   int32_t* aug;
 };
 
-constexpr int NEVENT = 128;
+constexpr int NEVENT = 320;
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
@@ -54,8 +62,9 @@ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 struct kp_dn {
   int device = 0;
   std::string err;
-  int c1 = 0, c2 = 0, c3 = 0;
-  Layer L[NLAYER];
+  int L = 0;
+  int c[MAX_LEVELS] = {};
+  std::vector<Layer> layers;
   size_t head_w = 0, head_b = 0, n_params = 0;
   float* d_p = nullptr;  // params, grads, m, v: 4 x n_params
   float* d_g = nullptr;
@@ -72,6 +81,10 @@ struct kp_dn {
   std::vector<Mark> marks;
   int nev = 0;
   int ev_total0 = -1, ev_total1 = -1;
+  // layer index of encoder block l, the bottleneck and decoder block l (conv a; b = +1)
+  int E(int l) const { return 2 * l; }
+  int M() const { return 2 * (L - 1); }
+  int D(int l) const { return 2 * (L - 1) + 2 + 2 * (L - 2 - l); }
 };
 
 namespace {
@@ -124,38 +137,33 @@ kp_status ensure_work(kp_dn* dn, size_t P1, int B) {
   if (P1 <= w.cap && B <= w.bcap) return KP_OK;
   const size_t cap = P1 > w.cap ? P1 : w.cap;
   const int bcap = B > w.bcap ? B : w.bcap;
-  const size_t c1 = dn->c1, c2 = dn->c2, c3 = dn->c3;
-  const size_t P2 = cap / 4, P3 = cap / 16;
+  const int L = dn->L;
+  size_t c[MAX_LEVELS];
+  for (int l = 0; l < L; ++l) c[l] = (size_t)dn->c[l];
+  auto Pl = [&](int l) { return cap >> (2 * l); };
   size_t off = 0;
   std::vector<std::pair<void**, size_t>> plan;  // (pointer, bytes)
   auto bf = [&](uint16_t** p, size_t elems) { plan.push_back({(void**)p, elems * 2}); };
   bf(&w.x0, cap * 8);
-  bf(&w.a1a, cap * c1);
-  bf(&w.cat1, cap * (c2 + c1));
-  bf(&w.pool1, P2 * c1);
-  bf(&w.a2a, P2 * c2);
-  bf(&w.cat2, P2 * (c3 + c2));
-  bf(&w.pool2, P3 * c2);
-  bf(&w.a3a, P3 * c3);
-  bf(&w.m3, P3 * c3);
-  bf(&w.d2a, P2 * c2);
-  bf(&w.d2, P2 * c2);
-  bf(&w.d1a, cap * c1);
-  bf(&w.d1, cap * c1);
-  bf(&w.g1, cap * c1);
-  bf(&w.g1b, cap * c1);
-  bf(&w.gcat1, cap * (c2 + c1));
-  bf(&w.g2, P2 * c2);
-  bf(&w.g2b, P2 * c2);
-  bf(&w.gcat2, P2 * (c3 + c2));
-  bf(&w.g3, P3 * c3);
-  bf(&w.g3b, P3 * c3);
-  bf(&w.gpool2, P3 * c2);
-  bf(&w.ge2, P2 * c2);
-  bf(&w.ge2b, P2 * c2);
-  bf(&w.gpool1, P2 * c1);
-  bf(&w.ge1, cap * c1);
-  bf(&w.ge1b, cap * c1);
+  for (int l = 0; l < L - 1; ++l) {
+    if (l > 0) bf(&w.pool[l], Pl(l) * c[l - 1]);
+    bf(&w.ea[l], Pl(l) * c[l]);
+    bf(&w.cat[l], Pl(l) * (c[l + 1] + c[l]));
+    bf(&w.da[l], Pl(l) * c[l]);
+    bf(&w.dout[l], Pl(l) * c[l]);
+    bf(&w.gd[l], Pl(l) * c[l]);
+    bf(&w.gdb[l], Pl(l) * c[l]);
+    bf(&w.gcat[l], Pl(l) * (c[l + 1] + c[l]));
+    bf(&w.ge[l], Pl(l) * c[l]);
+    bf(&w.geb[l], Pl(l) * c[l]);
+    if (l > 0) bf(&w.gpool[l], Pl(l) * c[l - 1]);
+  }
+  bf(&w.pool[L - 1], Pl(L - 1) * c[L - 2]);
+  bf(&w.ma, Pl(L - 1) * c[L - 1]);
+  bf(&w.mout, Pl(L - 1) * c[L - 1]);
+  bf(&w.gm, Pl(L - 1) * c[L - 1]);
+  bf(&w.gmb, Pl(L - 1) * c[L - 1]);
+  bf(&w.gpool[L - 1], Pl(L - 1) * c[L - 2]);
   plan.push_back({(void**)&w.xq, cap * 2 * 4});
   plan.push_back({(void**)&w.ihat, cap * 4});
   plan.push_back({(void**)&w.tgt, cap * 2 * 4});
@@ -192,11 +200,9 @@ kp_status ensure_work(kp_dn* dn, size_t P1, int B) {
 
 kp_status ensure_packed(kp_dn* dn, hipStream_t s) {
   if (dn->packed) return KP_OK;
-  for (int l = 0; l < NLAYER; ++l) {
-    const Layer& y = dn->L[l];
+  for (const Layer& y : dn->layers)
     pack(dn->d_p + y.w_off, y.cout, y.cin, y.cin_true, y.kp, y.kpd, dn->d_pk + y.pk_off,
          y.kpd ? dn->d_pk + y.pkd_off : nullptr, s);
-  }
   DN_HIP(hipGetLastError(), "weight packing launch");
   dn->packed = true;
   return KP_OK;
@@ -205,8 +211,9 @@ kp_status ensure_packed(kp_dn* dn, hipStream_t s) {
 kp_status check_maps(kp_dn* dn, const void* a, const void* b, int32_t B, int32_t H, int32_t W) {
   if (!a || !b) return fail(dn, KP_ERR_ARG, "map pointer is NULL");
   if (B < 1) return fail(dn, KP_ERR_ARG, "batch must be >= 1 (got %d)", B);
-  if (H < 4 || W < 4 || H % 4 || W % 4)
-    return fail(dn, KP_ERR_ARG, "height and width must be positive multiples of 4 (got %d x %d)", H, W);
+  const int m = 1 << (dn->L - 1);
+  if (H < m || W < m || H % m || W % m)
+    return fail(dn, KP_ERR_ARG, "height and width must be positive multiples of %d (got %d x %d)", m, H, W);
   if ((uint64_t)B * H * W > (1ull << 24))
     return fail(dn, KP_ERR_ARG, "batch * height * width = %llu exceeds 2^24",
                 (unsigned long long)((uint64_t)B * H * W));
@@ -217,7 +224,7 @@ kp_status check_maps(kp_dn* dn, const void* a, const void* b, int32_t B, int32_t
 double conv_flop(const Layer& y, size_t P) { return 2.0 * (double)P * 9.0 * y.cin_true * y.cout; }
 
 void conv_fwd(kp_dn* dn, int l, const uint16_t* x, int xs, uint16_t* y, int ys, int B, int H, int W, hipStream_t s) {
-  const Layer& L = dn->L[l];
+  const Layer& L = dn->layers[l];
   ConvArgs a{};
   a.x = x;
   a.xs = xs;
@@ -236,10 +243,10 @@ void conv_fwd(kp_dn* dn, int l, const uint16_t* x, int xs, uint16_t* y, int ys, 
   mark_end(dn, e, CAT_CONV, conv_flop(L, (size_t)B * H * W), s);
 }
 
-// input gradient of layer l: gx (stride cin_true) from gz (stride cout), zero where mask <= 0
+// input gradient of layer l: gx (stride gxs) from gz (stride cout), zero where mask <= 0
 void conv_dgrad(kp_dn* dn, int l, const uint16_t* gz, uint16_t* gx, int gxs, const uint16_t* mask, int ms, int B,
                 int H, int W, hipStream_t s) {
-  const Layer& L = dn->L[l];
+  const Layer& L = dn->layers[l];
   ConvArgs a{};
   a.x = gz;
   a.xs = L.cout;
@@ -260,7 +267,7 @@ void conv_dgrad(kp_dn* dn, int l, const uint16_t* gz, uint16_t* gx, int gxs, con
 }
 
 void conv_wgrad(kp_dn* dn, int l, const uint16_t* gz, const uint16_t* x, int xs, int B, int H, int W, hipStream_t s) {
-  const Layer& L = dn->L[l];
+  const Layer& L = dn->layers[l];
   WgradArgs a{};
   a.gz = gz;
   a.gzs = L.cout;
@@ -279,72 +286,86 @@ void conv_wgrad(kp_dn* dn, int l, const uint16_t* gz, const uint16_t* x, int xs,
   mark_end(dn, e, CAT_WGRAD, conv_flop(L, (size_t)B * H * W), s);
 }
 
-// maps -> w.out (network output, FP32 (Q, U) / s per pixel); all activations kept
+// maps -> w.out (network output: predicted fractions q', u'); activations kept
 kp_status forward(kp_dn* dn, const double* maps, const double* target, int B, int H, int W, bool use_aug,
                   hipStream_t s) {
   Work& w = dn->w;
-  const int c1 = dn->c1, c2 = dn->c2, c3 = dn->c3;
+  const int L = dn->L;
+  const int* c = dn->c;
   const size_t P1 = (size_t)B * H * W;
+  auto Hl = [&](int l) { return H >> l; };
+  auto Wl = [&](int l) { return W >> l; };
   zero(w.sum, (size_t)B * 16, s);
   sums(maps, B, H * W, w.sum, s);
   prep(maps, target, w.sum, use_aug ? w.aug : nullptr, B, H, W, w.x0, w.xq, w.ihat, w.tgt, s);
-  const int H2 = H / 2, W2 = W / 2, H4 = H / 4, W4 = W / 4;
-  conv_fwd(dn, E1A, w.x0, 8, w.a1a, c1, B, H, W, s);
-  conv_fwd(dn, E1B, w.a1a, c1, w.cat1 + c2, c2 + c1, B, H, W, s);
-  pool(w.cat1 + c2, c2 + c1, w.pool1, c1, B, H, W, c1, s);
-  conv_fwd(dn, E2A, w.pool1, c1, w.a2a, c2, B, H2, W2, s);
-  conv_fwd(dn, E2B, w.a2a, c2, w.cat2 + c3, c3 + c2, B, H2, W2, s);
-  pool(w.cat2 + c3, c3 + c2, w.pool2, c2, B, H2, W2, c2, s);
-  conv_fwd(dn, M3A, w.pool2, c2, w.a3a, c3, B, H4, W4, s);
-  conv_fwd(dn, M3B, w.a3a, c3, w.m3, c3, B, H4, W4, s);
-  up(w.m3, c3, w.cat2, c3 + c2, B, H2, W2, c3, s);
-  conv_fwd(dn, D2A, w.cat2, c3 + c2, w.d2a, c2, B, H2, W2, s);
-  conv_fwd(dn, D2B, w.d2a, c2, w.d2, c2, B, H2, W2, s);
-  up(w.d2, c2, w.cat1, c2 + c1, B, H, W, c2, s);
-  conv_fwd(dn, D1A, w.cat1, c2 + c1, w.d1a, c1, B, H, W, s);
-  conv_fwd(dn, D1B, w.d1a, c1, w.d1, c1, B, H, W, s);
-  head(w.d1, c1, dn->d_p + dn->head_w, dn->d_p + dn->head_b, w.xq, w.out, P1, s);
+  // encoder
+  for (int l = 0; l < L - 1; ++l) {
+    const uint16_t* in = l == 0 ? w.x0 : w.pool[l];
+    const int ins = l == 0 ? 8 : c[l - 1];
+    conv_fwd(dn, dn->E(l), in, ins, w.ea[l], c[l], B, Hl(l), Wl(l), s);
+    conv_fwd(dn, dn->E(l) + 1, w.ea[l], c[l], w.cat[l] + c[l + 1], c[l + 1] + c[l], B, Hl(l), Wl(l), s);
+    pool(w.cat[l] + c[l + 1], c[l + 1] + c[l], w.pool[l + 1], c[l], B, Hl(l), Wl(l), c[l], s);
+  }
+  // bottleneck
+  conv_fwd(dn, dn->M(), w.pool[L - 1], c[L - 2], w.ma, c[L - 1], B, Hl(L - 1), Wl(L - 1), s);
+  conv_fwd(dn, dn->M() + 1, w.ma, c[L - 1], w.mout, c[L - 1], B, Hl(L - 1), Wl(L - 1), s);
+  // decoder
+  const uint16_t* below = w.mout;
+  int bs = c[L - 1];
+  for (int l = L - 2; l >= 0; --l) {
+    up(below, bs, w.cat[l], c[l + 1] + c[l], B, Hl(l), Wl(l), c[l + 1], s);
+    conv_fwd(dn, dn->D(l), w.cat[l], c[l + 1] + c[l], w.da[l], c[l], B, Hl(l), Wl(l), s);
+    conv_fwd(dn, dn->D(l) + 1, w.da[l], c[l], w.dout[l], c[l], B, Hl(l), Wl(l), s);
+    below = w.dout[l];
+    bs = c[l];
+  }
+  head(w.dout[0], c[0], dn->d_p + dn->head_w, dn->d_p + dn->head_b, w.xq, w.out, P1, s);
   DN_HIP(hipGetLastError(), "denoiser forward launch");
   return KP_OK;
 }
 
 kp_status backward(kp_dn* dn, int B, int H, int W, hipStream_t s) {
   Work& w = dn->w;
-  const int c1 = dn->c1, c2 = dn->c2, c3 = dn->c3;
+  const int L = dn->L;
+  const int* c = dn->c;
   const size_t P1 = (size_t)B * H * W;
-  const int H2 = H / 2, W2 = W / 2, H4 = H / 4, W4 = W / 4;
+  auto Hl = [&](int l) { return H >> l; };
+  auto Wl = [&](int l) { return W >> l; };
   zero(dn->d_g, dn->n_params * 4, s);
   zero(w.loss, 8, s);
   loss(w.out, w.tgt, w.ihat, w.sum, B, H * W, w.go, w.loss, s);
-  head_bwd(w.go, w.d1, c1, dn->d_p + dn->head_w, dn->d_g + dn->head_w, dn->d_g + dn->head_b, w.g1, P1, s);
-  // decoder level 1
-  conv_wgrad(dn, D1B, w.g1, w.d1a, c1, B, H, W, s);
-  conv_dgrad(dn, D1B, w.g1, w.g1b, c1, w.d1a, c1, B, H, W, s);
-  conv_wgrad(dn, D1A, w.g1b, w.cat1, c2 + c1, B, H, W, s);
-  conv_dgrad(dn, D1A, w.g1b, w.gcat1, c2 + c1, nullptr, 0, B, H, W, s);
-  // decoder level 2
-  up_bwd(w.gcat1, c2 + c1, w.g2, c2, w.d2, c2, B, H, W, c2, s);
-  conv_wgrad(dn, D2B, w.g2, w.d2a, c2, B, H2, W2, s);
-  conv_dgrad(dn, D2B, w.g2, w.g2b, c2, w.d2a, c2, B, H2, W2, s);
-  conv_wgrad(dn, D2A, w.g2b, w.cat2, c3 + c2, B, H2, W2, s);
-  conv_dgrad(dn, D2A, w.g2b, w.gcat2, c3 + c2, nullptr, 0, B, H2, W2, s);
+  head_bwd(w.go, w.dout[0], c[0], dn->d_p + dn->head_w, dn->d_g + dn->head_w, dn->d_g + dn->head_b, w.gd[0], P1,
+           s);
+  // decoder, finest level first
+  for (int l = 0; l < L - 1; ++l) {
+    const int cc = c[l + 1] + c[l];
+    conv_wgrad(dn, dn->D(l) + 1, w.gd[l], w.da[l], c[l], B, Hl(l), Wl(l), s);
+    conv_dgrad(dn, dn->D(l) + 1, w.gd[l], w.gdb[l], c[l], w.da[l], c[l], B, Hl(l), Wl(l), s);
+    conv_wgrad(dn, dn->D(l), w.gdb[l], w.cat[l], cc, B, Hl(l), Wl(l), s);
+    conv_dgrad(dn, dn->D(l), w.gdb[l], w.gcat[l], cc, nullptr, 0, B, Hl(l), Wl(l), s);
+    // gradient of the block below's output: adjoint of up, masked by its relu
+    if (l + 1 < L - 1) up_bwd(w.gcat[l], cc, w.gd[l + 1], c[l + 1], w.dout[l + 1], c[l + 1], B, Hl(l), Wl(l), c[l + 1], s);
+    else up_bwd(w.gcat[l], cc, w.gm, c[L - 1], w.mout, c[L - 1], B, Hl(l), Wl(l), c[L - 1], s);
+  }
   // bottleneck
-  up_bwd(w.gcat2, c3 + c2, w.g3, c3, w.m3, c3, B, H2, W2, c3, s);
-  conv_wgrad(dn, M3B, w.g3, w.a3a, c3, B, H4, W4, s);
-  conv_dgrad(dn, M3B, w.g3, w.g3b, c3, w.a3a, c3, B, H4, W4, s);
-  conv_wgrad(dn, M3A, w.g3b, w.pool2, c2, B, H4, W4, s);
-  conv_dgrad(dn, M3A, w.g3b, w.gpool2, c2, nullptr, 0, B, H4, W4, s);
-  // encoder level 2: skip gradient plus pooled path
-  pool_bwd_add(w.gcat2 + c3, c3 + c2, w.gpool2, c2, w.cat2 + c3, c3 + c2, w.ge2, c2, B, H2, W2, c2, s);
-  conv_wgrad(dn, E2B, w.ge2, w.a2a, c2, B, H2, W2, s);
-  conv_dgrad(dn, E2B, w.ge2, w.ge2b, c2, w.a2a, c2, B, H2, W2, s);
-  conv_wgrad(dn, E2A, w.ge2b, w.pool1, c1, B, H2, W2, s);
-  conv_dgrad(dn, E2A, w.ge2b, w.gpool1, c1, nullptr, 0, B, H2, W2, s);
-  // encoder level 1
-  pool_bwd_add(w.gcat1 + c2, c2 + c1, w.gpool1, c1, w.cat1 + c2, c2 + c1, w.ge1, c1, B, H, W, c1, s);
-  conv_wgrad(dn, E1B, w.ge1, w.a1a, c1, B, H, W, s);
-  conv_dgrad(dn, E1B, w.ge1, w.ge1b, c1, w.a1a, c1, B, H, W, s);
-  conv_wgrad(dn, E1A, w.ge1b, w.x0, 8, B, H, W, s);
+  conv_wgrad(dn, dn->M() + 1, w.gm, w.ma, c[L - 1], B, Hl(L - 1), Wl(L - 1), s);
+  conv_dgrad(dn, dn->M() + 1, w.gm, w.gmb, c[L - 1], w.ma, c[L - 1], B, Hl(L - 1), Wl(L - 1), s);
+  conv_wgrad(dn, dn->M(), w.gmb, w.pool[L - 1], c[L - 2], B, Hl(L - 1), Wl(L - 1), s);
+  conv_dgrad(dn, dn->M(), w.gmb, w.gpool[L - 1], c[L - 2], nullptr, 0, B, Hl(L - 1), Wl(L - 1), s);
+  // encoder, coarsest level first: skip gradient plus the pooled path
+  for (int l = L - 2; l >= 0; --l) {
+    const int cc = c[l + 1] + c[l];
+    pool_bwd_add(w.gcat[l] + c[l + 1], cc, w.gpool[l + 1], c[l], w.cat[l] + c[l + 1], cc, w.ge[l], c[l], B, Hl(l),
+                 Wl(l), c[l], s);
+    conv_wgrad(dn, dn->E(l) + 1, w.ge[l], w.ea[l], c[l], B, Hl(l), Wl(l), s);
+    conv_dgrad(dn, dn->E(l) + 1, w.ge[l], w.geb[l], c[l], w.ea[l], c[l], B, Hl(l), Wl(l), s);
+    if (l > 0) {
+      conv_wgrad(dn, dn->E(l), w.geb[l], w.pool[l], c[l - 1], B, Hl(l), Wl(l), s);
+      conv_dgrad(dn, dn->E(l), w.geb[l], w.gpool[l], c[l - 1], nullptr, 0, B, Hl(l), Wl(l), s);
+    } else {
+      conv_wgrad(dn, dn->E(0), w.geb[0], w.x0, 8, B, H, W, s);
+    }
+  }
   DN_HIP(hipGetLastError(), "denoiser backward launch");
   return KP_OK;
 }
@@ -358,29 +379,42 @@ kp_status check_n(kp_dn* dn, size_t n) {
 
 extern "C" {
 
-kp_status kp_dn_create(int device, int32_t c1, int32_t c2, int32_t c3, kp_dn** out) {
+kp_status kp_dn_create(int device, const int32_t* widths, int32_t n_levels, kp_dn** out) {
   if (!out) return KP_ERR_ARG;
   *out = nullptr;
-  for (int32_t c : {c1, c2, c3})
-    if (c < 16 || c > 512 || c % 16) return KP_ERR_ARG;
+  if (!widths || n_levels < 2 || n_levels > MAX_LEVELS) return KP_ERR_ARG;
+  for (int l = 0; l < n_levels; ++l)
+    if (widths[l] < 16 || widths[l] > 512 || widths[l] % 16) return KP_ERR_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return KP_ERR_DEVICE;
   kp_dn* dn = new (std::nothrow) kp_dn;
   if (!dn) return KP_ERR_OOM;
   dn->device = device;
-  dn->c1 = c1;
-  dn->c2 = c2;
-  dn->c3 = c3;
-  const int io[NLAYER][2] = {{4, c1},       {c1, c1}, {c1, c2},       {c2, c2}, {c2, c3},
-                             {c3, c3},      {c3 + c2, c2}, {c2, c2},  {c2 + c1, c1}, {c1, c1}};
+  dn->L = n_levels;
+  for (int l = 0; l < n_levels; ++l) dn->c[l] = widths[l];
+  const int L = n_levels;
+  const int* c = dn->c;
+  // (cin, cout) in parameter order: encoder blocks, bottleneck, decoder blocks
+  std::vector<std::pair<int, int>> io;
+  for (int l = 0; l < L - 1; ++l) {
+    io.push_back({l == 0 ? 4 : c[l - 1], c[l]});
+    io.push_back({c[l], c[l]});
+  }
+  io.push_back({c[L - 2], c[L - 1]});
+  io.push_back({c[L - 1], c[L - 1]});
+  for (int l = L - 2; l >= 0; --l) {
+    io.push_back({c[l + 1] + c[l], c[l]});
+    io.push_back({c[l], c[l]});
+  }
   size_t off = 0, pk = 0;
-  for (int l = 0; l < NLAYER; ++l) {
-    Layer& y = dn->L[l];
-    y.cin_true = io[l][0];
-    y.cout = io[l][1];
+  dn->layers.resize(io.size());
+  for (size_t l = 0; l < io.size(); ++l) {
+    Layer& y = dn->layers[l];
+    y.cin_true = io[l].first;
+    y.cout = io[l].second;
     y.cin = round_up(y.cin_true, 8);
     y.kp = round_up(9 * y.cin, 32);
-    y.kpd = l == E1A ? 0 : round_up(9 * y.cout, 32);
+    y.kpd = l == 0 ? 0 : round_up(9 * y.cout, 32);  // the first layer needs no input gradient
     y.w_off = off;
     off += (size_t)y.cout * 9 * y.cin_true;
     y.b_off = off;
@@ -393,7 +427,7 @@ kp_status kp_dn_create(int device, int32_t c1, int32_t c2, int32_t c3, kp_dn** o
     pk = (pk + 127) / 128 * 128;
   }
   dn->head_w = off;
-  off += 2 * (size_t)c1;
+  off += 2 * (size_t)c[0];
   dn->head_b = off;
   off += 2;
   dn->n_params = off;

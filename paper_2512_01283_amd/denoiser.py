@@ -19,7 +19,6 @@ from . import polrad as P
 _lib = P._lib
 HEADER = os.path.join(os.path.dirname(P.HEADER), "polrad_denoiser.h")
 WIDTHS = (48, 96, 192)
-LAYERS = ("e1a", "e1b", "e2a", "e2b", "m3a", "m3b", "d2a", "d2b", "d1a", "d1b")
 
 
 class kp_dn_timing(C.Structure):
@@ -29,7 +28,7 @@ class kp_dn_timing(C.Structure):
 
 _Pv = C.c_void_p
 _SIGS = {
-    "kp_dn_create": ([C.c_int, C.c_int32, C.c_int32, C.c_int32, C.POINTER(_Pv)], C.c_int),
+    "kp_dn_create": ([C.c_int, _Pv, C.c_int32, C.POINTER(_Pv)], C.c_int),
     "kp_dn_destroy": ([_Pv], None),
     "kp_dn_last_error": ([_Pv], C.c_char_p),
     "kp_dn_num_params": ([_Pv, C.POINTER(C.c_size_t)], C.c_int),
@@ -72,7 +71,8 @@ def _f32(a, n):
 
 def kp_dn_create(device=0, widths=WIDTHS):
     h = _Pv()
-    st = _lib.kp_dn_create(int(device), *[int(c) for c in widths], C.byref(h))
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    st = _lib.kp_dn_create(int(device), w.ctypes.data, int(w.size), C.byref(h))
     if st != P.KP_OK:
         raise P.KpError(st, f"kp_dn_create(device={device}, widths={tuple(widths)}) failed")
     return h

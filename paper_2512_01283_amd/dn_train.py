@@ -187,6 +187,7 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--ref-half", type=float, default=1.5e8)
+    ap.add_argument("--widths", default="48,96,192", help="channel widths, one per U-Net level")
     ap.add_argument("--init", default=None, help="start from saved parameters (.npy)")
     ap.add_argument("--skip-eval", action="store_true")
     a = ap.parse_args(argv)
@@ -201,8 +202,9 @@ def main(argv=None):
     log(f"generating training pairs on {torch.cuda.get_device_name(0)}", flush=True)
     lo, hi = make_pairs(seeds(a.train_seeds), a.n_lo, a.n_hi, n=a.grid, npix=a.npix, log=log)
     t_gen = time.time() - t0
-    dn = DN.Denoiser(0)
-    init = np.load(a.init) if a.init else W.denoiser_params(0)
+    widths = tuple(int(v) for v in a.widths.split(","))
+    dn = DN.Denoiser(0, widths=widths)
+    init = np.load(a.init) if a.init else W.denoiser_params(0, widths=widths)
     dn.set_params(init)
     t1 = time.time()
     hist = train(dn, lo, hi, a.steps, batch=a.batch, lr=a.lr, log=log)
@@ -210,7 +212,8 @@ def main(argv=None):
     t_train = time.time() - t1
     del lo, hi
     np.save(os.path.join(a.out, "params.npy"), dn.params())
-    res = dict(train_seeds=a.train_seeds, n_lo=a.n_lo, n_hi=a.n_hi, steps=a.steps, batch=a.batch,
+    res = dict(widths=list(widths), params=dn.n, train_seeds=a.train_seeds, n_lo=a.n_lo, n_hi=a.n_hi,
+               steps=a.steps, batch=a.batch,
                lr=a.lr, t_generate_s=t_gen, t_train_s=t_train,
                loss_first=hist[0][1], loss_last=float(np.mean([l for _, l in hist[-50:]])))
     if not a.skip_eval:

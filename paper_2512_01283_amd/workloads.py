@@ -244,14 +244,20 @@ def pencil_slab(n_z=256, tau_total=1.0, p0=0.01, alpha3_scale=0.0, twist=True,
 # denoiser inputs: parameter initialisation, synthetic maps, training disks
 # --------------------------------------------------------------------------
 DN_WIDTHS = (48, 96, 192)
-DN_LAYERS = ("e1a", "e1b", "e2a", "e2b", "m3a", "m3b", "d2a", "d2b", "d1a", "d1b")
 
 
 def denoiser_layer_io(widths=DN_WIDTHS, cin=4):
-    """(input, output) channels of each 3x3 convolution, in parameter order."""
-    c1, c2, c3 = widths
-    return [(cin, c1), (c1, c1), (c1, c2), (c2, c2), (c2, c3), (c3, c3),
-            (c3 + c2, c2), (c2, c2), (c2 + c1, c1), (c1, c1)]
+    """(input, output) channels of each 3x3 convolution, in parameter order:
+    encoder blocks, the bottleneck, decoder blocks (two convolutions each)."""
+    c = list(widths)
+    L = len(c)
+    io = []
+    for l in range(L - 1):
+        io += [(cin if l == 0 else c[l - 1], c[l]), (c[l], c[l])]
+    io += [(c[L - 2], c[L - 1]), (c[L - 1], c[L - 1])]
+    for l in range(L - 2, -1, -1):
+        io += [(c[l + 1] + c[l], c[l]), (c[l], c[l])]
+    return io
 
 
 def denoiser_params(seed=0, widths=DN_WIDTHS, bias_std=0.0, head_std=0.0) -> np.ndarray:

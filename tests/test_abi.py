@@ -89,8 +89,13 @@ def test_denoiser_without_device_and_bad_arguments():
     if torch.cuda.device_count() > 0:
         pytest.skip("a GPU is present")
     from paper_2512_01283_amd import denoiser as DN
+    import numpy as np
     h = ctypes.c_void_p()
-    assert DN._lib.kp_dn_create(0, 48, 96, 192, ctypes.byref(h)) == DN.P.KP_ERR_DEVICE
-    assert DN._lib.kp_dn_create(0, 40, 96, 192, ctypes.byref(h)) == DN.P.KP_ERR_ARG
+    good = np.array([48, 96, 192], np.int32)
+    bad = np.array([40, 96, 192], np.int32)
+    assert DN._lib.kp_dn_create(0, good.ctypes.data, 3, ctypes.byref(h)) == DN.P.KP_ERR_DEVICE
+    assert DN._lib.kp_dn_create(0, bad.ctypes.data, 3, ctypes.byref(h)) == DN.P.KP_ERR_ARG
+    assert DN._lib.kp_dn_create(0, good.ctypes.data, 1, ctypes.byref(h)) == DN.P.KP_ERR_ARG
+    assert DN._lib.kp_dn_create(0, good.ctypes.data, 7, ctypes.byref(h)) == DN.P.KP_ERR_ARG
     assert DN._lib.kp_dn_infer(None, None, None, 1, 16, 16, None) == DN.P.KP_ERR_ARG
     assert DN._lib.kp_dn_num_params(None, None) == DN.P.KP_ERR_ARG

@@ -145,3 +145,32 @@ def test_bf16_rounding_model_stays_near_the_exact_oracle():
     assert T.rel(rep["delta"], ref["delta"]) < 8e-3
     errs = [T.rel(rep["grads"][k], g) for k, g in ref["grads"].items()]
     assert max(errs) < 6e-2 and min(errs) < 2e-3
+
+
+def test_four_level_network_gradient_finite_differences():
+    widths = (2, 3, 4, 5)
+    shapes = D.layer_shapes(widths)
+    assert list(shapes)[:4] == ["e1a.w", "e1a.b", "e1b.w", "e1b.b"]
+    p = {k: RNG.standard_normal(s) * 0.4 for k, s in shapes.items()}
+    maps = _maps(RNG, 1, 16, 8)
+    x, Ihat, _ = D.features(maps)
+    t = RNG.standard_normal((1, 16, 8, 2)) * 0.1
+    delta, cache = D.forward(p, x)
+    g = D.backward(p, cache, D.loss_grad(delta, x, Ihat, t))
+    h = 1e-6
+    for k in ("e1a.w", "e3b.w", "m4a.w", "d3a.w", "d1b.b", "head.w"):
+        flat = p[k].ravel()
+        idx = 1
+        old = flat[idx]
+        flat[idx] = old + h
+        lp = D.loss(D.forward(p, x)[0], x, Ihat, t)
+        flat[idx] = old - h
+        lm = D.loss(D.forward(p, x)[0], x, Ihat, t)
+        flat[idx] = old
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - g[k].ravel()[idx]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, k
+
+
+def test_parameter_layout_of_three_levels_unchanged():
+    names = D.layer_names((48, 96, 192))
+    assert names == ["e1a", "e1b", "e2a", "e2b", "m3a", "m3b", "d2a", "d2b", "d1a", "d1b"]

@@ -84,6 +84,7 @@ def bf16_replay(params32, low, high=None, widths=W.DN_WIDTHS):
     rounding).  Returns dict(delta, loss, grads)."""
     R = bf16
     p, xf, x, Ihat, t = _operands(params32, low, high, widths)
+    L = len(widths)
     c = {}
 
     def block(name, inp):
@@ -92,17 +93,20 @@ def bf16_replay(params32, low, high=None, widths=W.DN_WIDTHS):
         c[name] = (inp, ya, yb)
         return yb
 
-    e1 = block("e1", x)
-    e2 = block("e2", R(D.pool(e1)))
-    m3 = block("m3", R(D.pool(e2)))
-    d2 = block("d2", np.concatenate([D.up(m3), e2], axis=3))
-    d1 = block("d1", np.concatenate([D.up(d2), e1], axis=3))
-    delta = d1 @ p["head.w"].T + p["head.b"]
+    skips, h = [], x
+    for l in range(1, L):
+        h = block(f"e{l}", h)
+        skips.append(h)
+        h = R(D.pool(h))
+    h = block(f"m{L}", h)
+    for l in range(L - 1, 0, -1):
+        h = block(f"d{l}", np.concatenate([D.up(h), skips[l - 1]], axis=3))
+    delta = h @ p["head.w"].T + p["head.b"]
     if t is None:
         return dict(delta=delta)
     g = {}
     go = D.loss_grad(delta, xf, Ihat, t)
-    g["head.w"] = go.reshape(-1, 2).T @ d1.reshape(-1, d1.shape[-1])
+    g["head.w"] = go.reshape(-1, 2).T @ h.reshape(-1, h.shape[-1])
     g["head.b"] = go.reshape(-1, 2).sum(0)
 
     def block_back(name, gzb):
@@ -112,12 +116,17 @@ def bf16_replay(params32, low, high=None, widths=W.DN_WIDTHS):
         ginp, g[name + "a.w"], g[name + "a.b"] = D.conv3_backward(inp, p[name + "a.w"], gza)
         return R(ginp)
 
-    c1, c2, c3 = widths
-    gcat1 = block_back("d1", R((go @ p["head.w"]) * (d1 > 0)))
-    gcat2 = block_back("d2", R(D.up_backward(gcat1[..., :c2]) * (d2 > 0)))
-    gm3 = block_back("m3", R(D.up_backward(gcat2[..., :c3]) * (m3 > 0)))
-    ge2 = block_back("e2", R((gcat2[..., c3:] + D.pool_backward(gm3)) * (e2 > 0)))
-    block_back("e1", R((gcat1[..., c2:] + D.pool_backward(ge2)) * (e1 > 0)))
+    gy = R((go @ p["head.w"]) * (h > 0))
+    gskip = {}
+    for l in range(1, L):
+        gcat = block_back(f"d{l}", gy)
+        cb = widths[l]
+        gskip[l] = gcat[..., cb:]
+        below = c[f"d{l + 1}"][2] if l + 1 < L else c[f"m{L}"][2]
+        gy = R(D.up_backward(gcat[..., :cb]) * (below > 0))
+    gin = block_back(f"m{L}", gy)
+    for l in range(L - 1, 0, -1):
+        gin = block_back(f"e{l}", R((gskip[l] + D.pool_backward(gin)) * (c[f"e{l}"][2] > 0)))
     return dict(delta=delta, loss=D.loss(delta, xf, Ihat, t), grads=g)
 
 
@@ -125,12 +134,12 @@ def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
 
 
-def check_gradients(g, low, high, params, label):
+def check_gradients(g, low, high, params, label, widths=W.DN_WIDTHS):
     """GPU gradients against the exact oracle, per tensor, within twice the
     distance of the BF16 replay from the exact oracle plus 2e-3 (the GPU and
     the replay are two realisations of the same rounding noise)."""
-    ref = oracle_pass(params, low, high)
-    rep = bf16_replay(params, low, high)
+    ref = oracle_pass(params, low, high, widths)
+    rep = bf16_replay(params, low, high, widths)
     worst = 0.0
     for k, gr in ref["grads"].items():
         bound = 2.0 * rel(rep["grads"][k], gr) + 2e-3
@@ -200,6 +209,30 @@ def test_augmented_gradients_match_transformed_maps(dn):
     hi_t = np.stack([dihedral(high[i], int(c)) for i, c in enumerate(codes)])
     ref = check_gradients(g, lo_t, hi_t, params, "augmented gradients")
     assert abs(loss - ref["loss"]) <= TOL_FWD * ref["loss"]
+
+
+@pytest.mark.parametrize("widths,shape", [((16, 32, 48, 64), (2, 32, 24)), ((16, 32), (3, 12, 20))])
+def test_other_depths_forward_and_gradient_parity(widths, shape):
+    """The same kernels and schedule at 4 and 2 levels (ragged coarse levels)."""
+    from paper_2512_01283_amd import denoiser as DN
+    b, h, w = shape
+    params = W.denoiser_params(19, widths=widths, bias_std=0.05, head_std=0.05)
+    d = DN.Denoiser(0, widths=widths, params=params)
+    low = W.synthetic_stokes_maps(15, b, h, w, noise=0.3)
+    high = W.synthetic_stokes_maps(15, b, h, w, noise=0.0)
+    out = d.infer(_dev(low)).cpu().numpy()
+    ref = oracle_pass(params, low, None, widths)
+    rep = bf16_replay(params, low, None, widths)
+    qf = np.float32(low[:, 1:3] / low[:, :1]).astype(np.float64)
+    e = rel(np.moveaxis(out[:, 1:3] / out[:, :1] - qf, 1, -1), ref["delta"])
+    assert e < TOL_FWD and e < 2.0 * rel(rep["delta"], ref["delta"]) + 2e-3, e
+    loss = d.backward(_dev(low), _dev(high))
+    g = D.unflatten(d.grads().astype(np.float64), widths)
+    refg = check_gradients(g, low, high, params, f"widths {widths}", widths)
+    assert abs(loss - refg["loss"]) <= TOL_FWD * refg["loss"]
+    with pytest.raises(Exception):
+        d.infer(_dev(W.synthetic_stokes_maps(15, 1, h + 2 ** (len(widths) - 2), w)))
+    d.close()
 
 
 def test_adam_step_matches_oracle(dn):
