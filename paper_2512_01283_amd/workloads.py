@@ -279,7 +279,8 @@ def synthetic_stokes_maps(seed, batch, height, width, p_max=0.3, noise=0.1) -> n
     """[batch, 4, height, width] FP64 Stokes maps with the structure of a
     scattered-light image: I a smooth positive blob plus a floor, a
     polarization fraction up to p_max with a smoothly varying angle, V small,
-    and multiplicative noise of relative size `noise`."""
+    and multiplicative noise of relative size `noise`; I is raised where the
+    noise would leave I < |(Q, U, V)|."""
     rng = np.random.default_rng(seed)
     yy, xx = np.meshgrid(np.linspace(-1, 1, height), np.linspace(-1, 1, width), indexing="ij")
     out = np.empty((batch, 4, height, width))
@@ -294,6 +295,8 @@ def synthetic_stokes_maps(seed, batch, height, width, p_max=0.3, noise=0.1) -> n
         out[b, 1] = I * p * np.cos(2 * chi) * n[1]
         out[b, 2] = I * p * np.sin(2 * chi) * n[2]
         out[b, 3] = 0.01 * I * rng.standard_normal((height, width))
+        # keep every pixel a physical Stokes vector, I >= |(Q, U, V)|
+        out[b, 0] = np.maximum(out[b, 0], 1.001 * np.sqrt((out[b, 1:] ** 2).sum(0)))
     return out
 
 

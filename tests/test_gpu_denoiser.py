@@ -130,6 +130,11 @@ def bf16_replay(params32, low, high=None, widths=W.DN_WIDTHS):
     return dict(delta=delta, loss=D.loss(delta, xf, Ihat, t), grads=g)
 
 
+def fractions(maps):
+    """(Q/I, U/I) as the kernels form them (clamped to [-1, 1], FP32)."""
+    return np.float32(D.features(maps)[0][..., 1:3]).astype(np.float64)
+
+
 def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
 
@@ -172,9 +177,8 @@ def test_forward_parity(dn, shape):
     out = dn.infer(_dev(maps)).cpu().numpy()
     ref = oracle_pass(params, maps)
     rep = bf16_replay(params, maps)
-    # the network's correction to the fractions: Q'/I - Q/I (FP32 ratio)
-    qf = np.float32(maps[:, 1:3] / maps[:, :1]).astype(np.float64)
-    delta_gpu = np.moveaxis(out[:, 1:3] / out[:, :1] - qf, 1, -1)
+    # the network's correction to the fractions: Q'/I - Q/I
+    delta_gpu = np.moveaxis(out[:, 1:3] / out[:, :1], 1, -1) - fractions(maps)
     e = rel(delta_gpu, ref["delta"])
     e_rep = rel(rep["delta"], ref["delta"])
     print(f"forward {shape}: relative error of the correction {e:.2e} (BF16 replay {e_rep:.2e})")
@@ -223,8 +227,7 @@ def test_other_depths_forward_and_gradient_parity(widths, shape):
     out = d.infer(_dev(low)).cpu().numpy()
     ref = oracle_pass(params, low, None, widths)
     rep = bf16_replay(params, low, None, widths)
-    qf = np.float32(low[:, 1:3] / low[:, :1]).astype(np.float64)
-    e = rel(np.moveaxis(out[:, 1:3] / out[:, :1] - qf, 1, -1), ref["delta"])
+    e = rel(np.moveaxis(out[:, 1:3] / out[:, :1], 1, -1) - fractions(low), ref["delta"])
     assert e < TOL_FWD and e < 2.0 * rel(rep["delta"], ref["delta"]) + 2e-3, e
     loss = d.backward(_dev(low), _dev(high))
     g = D.unflatten(d.grads().astype(np.float64), widths)
