@@ -613,7 +613,7 @@ __device__ void finish(const Packet<R>& p, uint32_t end, const TransportArgs& a,
 }
 
 template <typename R, bool ALIGNED, bool SPHERE>
-__global__ void __launch_bounds__(256) k_transport(TransportArgs a) {
+__device__ __forceinline__ void transport_body(const TransportArgs& a) {
   constexpr int NC = TallyShape<SPHERE>::NC, TS = TallyShape<SPHERE>::TS;
   __shared__ unsigned long long sc[SC_N];
   __shared__ double se[SE_N];
@@ -703,6 +703,22 @@ __global__ void __launch_bounds__(256) k_transport(TransportArgs a) {
   __syncthreads();
   if (threadIdx.x < SC_N) atomicAdd(&(&a.stats->cell_steps)[threadIdx.x], sc[threadIdx.x]);
   if (threadIdx.x < SE_N) unsafeAtomicAdd(&(&a.stats->e_emitted)[threadIdx.x], se[threadIdx.x]);
+}
+
+// The persistent transport kernels.  FP32 variants are held to two waves per
+// SIMD (at most 256 registers): the non-spherical FP32 bodies need 264-272
+// unconstrained and would run one wave per SIMD; the bound costs them about a
+// dozen spills and makes them 1.5x faster.  The FP64 variants need 297-361;
+// holding them to two waves spills 50-190 registers and halves their speed,
+// so they run unbounded at one wave per SIMD.
+template <bool ALIGNED, bool SPHERE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_transport32(TransportArgs a) {
+  transport_body<float, ALIGNED, SPHERE>(a);
+}
+template <bool ALIGNED, bool SPHERE>
+__global__ void __launch_bounds__(256) k_transport64(TransportArgs a) {
+  transport_body<double, ALIGNED, SPHERE>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -952,35 +968,34 @@ __global__ void k_validate(const float* rho, const float* bx, const float* by, c
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <typename R>
-static hipError_t launch_t(const TransportArgs& a, bool aligned, bool sphere, int blocks, int bs,
-                           hipStream_t s) {
-  if (aligned && sphere) hipLaunchKernelGGL((k_transport<R, true, true>), dim3(blocks), dim3(bs), 0, s, a);
-  else if (aligned) hipLaunchKernelGGL((k_transport<R, true, false>), dim3(blocks), dim3(bs), 0, s, a);
-  else if (sphere) hipLaunchKernelGGL((k_transport<R, false, true>), dim3(blocks), dim3(bs), 0, s, a);
-  else hipLaunchKernelGGL((k_transport<R, false, false>), dim3(blocks), dim3(bs), 0, s, a);
-  return hipGetLastError();
+template <bool A, bool S>
+static void launch_one(const TransportArgs& a, bool fp64, int blocks, int bs, hipStream_t s) {
+  if (fp64) hipLaunchKernelGGL((k_transport64<A, S>), dim3(blocks), dim3(bs), 0, s, a);
+  else hipLaunchKernelGGL((k_transport32<A, S>), dim3(blocks), dim3(bs), 0, s, a);
 }
 
 hipError_t launch_transport(const TransportArgs& a, bool fp64, bool aligned, bool sphere,
                             int blocks, int block_size, hipStream_t s) {
-  return fp64 ? launch_t<double>(a, aligned, sphere, blocks, block_size, s)
-              : launch_t<float>(a, aligned, sphere, blocks, block_size, s);
+  if (aligned && sphere) launch_one<true, true>(a, fp64, blocks, block_size, s);
+  else if (aligned) launch_one<true, false>(a, fp64, blocks, block_size, s);
+  else if (sphere) launch_one<false, true>(a, fp64, blocks, block_size, s);
+  else launch_one<false, false>(a, fp64, blocks, block_size, s);
+  return hipGetLastError();
 }
 
-template <typename R>
-static int occ_t(bool aligned, bool sphere, int bs) {
+template <bool A, bool S>
+static int occ_one(bool fp64, int bs) {
   int n = 0;
-  hipError_t e;
-  if (aligned && sphere) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport<R, true, true>, bs, 0);
-  else if (aligned) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport<R, true, false>, bs, 0);
-  else if (sphere) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport<R, false, true>, bs, 0);
-  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport<R, false, false>, bs, 0);
+  const hipError_t e = fp64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport64<A, S>, bs, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport32<A, S>, bs, 0);
   return e == hipSuccess ? n : 0;
 }
 
 int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, int block_size) {
-  return fp64 ? occ_t<double>(aligned, sphere, block_size) : occ_t<float>(aligned, sphere, block_size);
+  if (aligned && sphere) return occ_one<true, true>(fp64, block_size);
+  if (aligned) return occ_one<true, false>(fp64, block_size);
+  if (sphere) return occ_one<false, true>(fp64, block_size);
+  return occ_one<false, false>(fp64, block_size);
 }
 
 hipError_t launch_image(const ImageArgs& a, bool aligned, bool sphere, bool user_source,
