@@ -266,100 +266,186 @@ __global__ void __launch_bounds__(256) k_conv3_tiled(ConvArgs a) {
 // ---------------------------------------------------------------------------
 // Weight gradient:  gw[co][kk][c] += sum_p gz[p][co] * x[p + off(kk)][c]
 // GEMM M = co, N = k = kk * cin + c, reduction over pixels.  A workgroup owns
-// a 64 x 64 (co, k) tile and a chunk of pixels; each 32-pixel slab of gz and
-// of the im2col matrix is loaded with 16-byte loads and written transposed to
-// LDS so that every lane's MFMA operand (8 consecutive pixels) is one 16-byte
-// LDS read; the next slab's global loads are in flight during the current
-// slab's MFMAs (double-buffered LDS, one barrier per slab).  Partial tiles are
-// added to the FP32 gradient with atomics; the workgroups of the first K tile
-// also add the bias gradient sum_p gz[p][co].
+// a 64 x 64 (co, k) tile and a chunk of pixels, taken in slabs of 128 pixels.
+// A thread loads 4 consecutive pixels x 8 channels of gz and of the im2col
+// matrix (16-byte buffer loads, 8 lanes cover one pixel's 64 channels) and
+// writes them transposed to LDS, one 8-byte store per channel (4 pixels).
+// Buffer loads give 0 outside the resource's byte range, so the zero padding
+// of the im2col matrix, the channels past cout and the pixels past the chunk
+// cost no branches: an invalid lane takes an offset past the range.  LDS rows
+// are a channel's 128 pixels; the 16-byte chunk c of row r sits at chunk
+// position c ^ ((r ^ (r >> 3)) & 7), which keeps both the transposing stores
+// and the MFMA operand reads (8 consecutive pixels, one 16-byte read) free of
+// bank conflicts.  Each wave runs 16 MFMAs per slab; the next slab's global
+// loads are in flight meanwhile (double-buffered LDS, one barrier per slab).
+// Partial tiles are added to the FP32 gradient with atomics; the workgroups
+// of the first K tile also add the bias gradient sum_p gz[p][co].  About 1024
+// workgroups per launch (two passes of two per CU) keep the atomics few.
 // ---------------------------------------------------------------------------
-constexpr int WG_LDS_STRIDE = 40;  // 32 pixels + 8 pad (row = 80 bytes, 16-byte aligned)
+constexpr int WG_PPT = 4;                 // pixels per thread per slab
+constexpr int BUF_DWORD3 = 0x00020000;    // buffer resource word 3: raw 32-bit data
+constexpr int BUF_OUT = 0x7FFFFFF0;       // an offset past every resource's range
+
+__device__ __forceinline__ int wg_swz(int r, int c) { return c ^ ((r ^ (r >> 3)) & 7); }
+
+// q = p / d, r = p - q d for 0 <= p < 2^24, d >= 1, with rd = 1 / d
+__device__ __forceinline__ void wg_divmod(int p, int d, float rd, int& q, int& r) {
+  q = (int)((float)p * rd);
+  r = p - q * d;
+  if (r < 0) {
+    --q;
+    r += d;
+  } else if (r >= d) {
+    ++q;
+    r -= d;
+  }
+}
+
+// (low half of x, low half of y) and (high half of x, high half of y) as one
+// word each: v_perm_b32 picks bytes of {S0 = y, S1 = x}, 0..3 from x, 4..7 from y
+__device__ __forceinline__ uint32_t lo16x2(uint32_t x, uint32_t y) { return __builtin_amdgcn_perm(y, x, 0x05040100u); }
+__device__ __forceinline__ uint32_t hi16x2(uint32_t x, uint32_t y) { return __builtin_amdgcn_perm(y, x, 0x07060302u); }
+
+__device__ __forceinline__ u32x4 bload16(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+}
 
 __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[2][64 * WG_LDS_STRIDE];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][64 * WG_LDS_STRIDE];
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][64 * WG_SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][64 * WG_SLAB];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int i = lane & 15, g = lane >> 4;
   const int P = a.B * a.H * a.W;
-  const int mt = blockIdx.x / a.ktiles, kt = blockIdx.x - mt * a.ktiles;
+  // Workgroups are handed to the 8 XCDs round-robin by launch index; regroup
+  // them so that one XCD runs all tiles of consecutive pixel chunks and its L2
+  // serves their shared gz and x rows (the last N % 8 keep their own index).
+  const int tiles = a.mtiles * a.ktiles, nwg = tiles * a.nch;
+  int wg = blockIdx.x;
+  if (wg < nwg - nwg % 8) wg = (wg & 7) * (nwg / 8) + (wg >> 3);
+  const int chn = wg / tiles, tile = wg - chn * tiles;
+  const int mt = tile / a.ktiles, kt = tile - mt * a.ktiles;
   const int m0 = mt * 64, kb = kt * 64;
-  const int p_begin = blockIdx.y * a.chunk;
+  const int p_begin = chn * a.chunk;
   const int p_end = min(P, p_begin + a.chunk);
-  // this thread's load slots: pixel row sp of the slab and 8-column group s8
+  // this thread's load slots: pixels 4 sp .. 4 sp + 3 of the slab, 8-column group s8
   const int sp = tid >> 3, s8 = (tid & 7) * 8;
   const bool a_ok = m0 + s8 < a.cout;
   const int kx = kb + s8;
   const int lkk = kx / a.cin, lc = kx - lkk * a.cin;
   const bool b_ok = lkk < 9;
   const int ldy = lkk / 3 - 1, ldx = lkk % 3 - 1;
+  const int rel = ldy * a.W + ldx;  // pixel offset of the tap
+  const float rW = 1.f / (float)a.W, rH = 1.f / (float)a.H;
+  // LDS element offsets: the transposing stores of columns s8 + j ...
+  int st_off[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) st_off[j] = (s8 + j) * WG_SLAB + 8 * wg_swz(s8 + j, sp >> 1) + (sp & 1) * 4;
+  // ... and the MFMA operand reads: chunk 4 m + g of row 16 wv + i (A), 16 t + i (B)
+  int ra_off[4], rb_off[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int ra = 16 * wv + i;
+    ra_off[m] = ra * WG_SLAB + 8 * wg_swz(ra, 4 * m + g);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int rb = 16 * t + i;
+      rb_off[t][m] = rb * WG_SLAB + 8 * wg_swz(rb, 4 * m + g);
+    }
+  }
   // the first K tile's workgroups also sum gz over their pixels: the bias gradient
   const bool do_bias = kt == 0 && a_ok;
   float bsum[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) bsum[j] = 0.f;
-  const u32x4 zero = {0u, 0u, 0u, 0u};
-  // global loads of one 32-pixel slab into registers
-  auto load = [&](int s0, u32x4& va, u32x4& vb) {
-    const int p = s0 + sp;
-    va = zero;
-    vb = zero;
-    if (p < p_end) {
-      if (a_ok) va = ld16(a.gz + (size_t)p * a.gzs + m0 + s8);
-      if (b_ok) {
-        const int w = p % a.W, h = (p / a.W) % a.H, n = p / (a.W * a.H);
-        const int hh = h + ldy, ww = w + ldx;
-        if (hh >= 0 && hh < a.H && ww >= 0 && ww < a.W)
-          vb = ld16(a.x + ((size_t)(n * a.H + hh) * a.W + ww) * a.xs + lc);
+  // global loads of this thread's 4 pixels of the slab at s0 into registers
+  auto load = [&](int s0, u32x4* va, u32x4* vb) {
+    // gz rows s0 .. min(s0 + 128, p_end) - 1, channels from m0
+    const int nv = min(WG_SLAB, p_end - s0);
+    const __amdgpu_buffer_rsrc_t ra =
+        __builtin_amdgcn_make_buffer_rsrc((void*)(a.gz + (size_t)s0 * a.gzs + m0), (short)0,
+                                          (nv * a.gzs - m0) * 2, BUF_DWORD3);
+    // x rows the slab's taps can reach
+    const int bp = max(0, s0 - a.W - 1), ep = min(P, s0 + WG_SLAB + a.W + 1);
+    const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(a.x + (size_t)bp * a.xs), (short)0, (ep - bp) * a.xs * 2, BUF_DWORD3);
+    const int p0 = s0 + WG_PPT * sp;
+    int hw, w, n, h;
+    wg_divmod(min(p0, P - 1), a.W, rW, hw, w);
+    wg_divmod(hw, a.H, rH, n, h);
+#pragma unroll
+    for (int q = 0; q < WG_PPT; ++q) {
+      va[q] = bload16(ra, a_ok ? ((WG_PPT * sp + q) * a.gzs + s8) * 2 : BUF_OUT);
+      const int hh = h + ldy, ww = w + ldx;
+      const bool ok = b_ok && (unsigned)hh < (unsigned)a.H && (unsigned)ww < (unsigned)a.W;
+      vb[q] = bload16(rx, ok ? ((p0 + q + rel - bp) * a.xs + lc) * 2 : BUF_OUT);
+      if (++w == a.W) {
+        w = 0;
+        if (++h == a.H) h = 0;
       }
     }
   };
-  // transposed store of a slab into LDS buffer `buf` (+ bias partial sums)
-  auto stage = [&](int buf, const u32x4& va, const u32x4& vb) {
+  // transposed store of the 4 pixels into LDS buffer `buf` (+ bias partial sums)
+  auto stage = [&](int buf, const u32x4* va, const u32x4* vb) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      As[buf][(s8 + 2 * j) * WG_LDS_STRIDE + sp] = (uint16_t)(va[j] & 0xFFFFu);
-      As[buf][(s8 + 2 * j + 1) * WG_LDS_STRIDE + sp] = (uint16_t)(va[j] >> 16);
-      Bs[buf][(s8 + 2 * j) * WG_LDS_STRIDE + sp] = (uint16_t)(vb[j] & 0xFFFFu);
-      Bs[buf][(s8 + 2 * j + 1) * WG_LDS_STRIDE + sp] = (uint16_t)(vb[j] >> 16);
+      *(uint2*)&As[buf][st_off[2 * j]] = uint2{lo16x2(va[0][j], va[1][j]), lo16x2(va[2][j], va[3][j])};
+      *(uint2*)&As[buf][st_off[2 * j + 1]] = uint2{hi16x2(va[0][j], va[1][j]), hi16x2(va[2][j], va[3][j])};
+      *(uint2*)&Bs[buf][st_off[2 * j]] = uint2{lo16x2(vb[0][j], vb[1][j]), lo16x2(vb[2][j], vb[3][j])};
+      *(uint2*)&Bs[buf][st_off[2 * j + 1]] = uint2{hi16x2(vb[0][j], vb[1][j]), hi16x2(vb[2][j], vb[3][j])};
     }
     if (do_bias) {
-      float f[8];
-      unpack8(va, f);
 #pragma unroll
-      for (int j = 0; j < 8; ++j) bsum[j] += f[j];
+      for (int q = 0; q < WG_PPT; ++q) {
+        float f[8];
+        unpack8(va[q], f);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bsum[j] += f[j];
+      }
     }
   };
   f32x4 acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  u32x4 va, vb;
-  load(p_begin, va, vb);
-  stage(0, va, vb);
-  __syncthreads();
-  int cur = 0;
-  for (int s0 = p_begin; s0 < p_end; s0 += 32) {
-    const bool more = s0 + 32 < p_end;
-    if (more) load(s0 + 32, va, vb);  // in flight during the MFMAs below
-    const u32x4 av = *(const u32x4*)(&As[cur][(16 * wv + i) * WG_LDS_STRIDE + 8 * g]);
+  u32x4 va[WG_PPT], vb[WG_PPT];
+  // one slab from LDS buffer `cur` (a literal at each use), the next slab's
+  // loads in flight and staged into the other buffer; false after the last
+  auto slab = [&](int s0, int cur) {
+    const bool more = s0 + WG_SLAB < p_end;
+    if (more) load(s0 + WG_SLAB, va, vb);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const u32x4 bv = *(const u32x4*)(&Bs[cur][(16 * t + i) * WG_LDS_STRIDE + 8 * g]);
-      acc[t] = mfma(av, bv, acc[t]);
+    for (int m = 0; m < WG_SLAB / 32; ++m) {
+      const u32x4 av = *(const u32x4*)(&As[cur][ra_off[m]]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const u32x4 bv = *(const u32x4*)(&Bs[cur][rb_off[t][m]]);
+        acc[t] = mfma(av, bv, acc[t]);
+      }
     }
     if (more) stage(cur ^ 1, va, vb);
     __syncthreads();
-    cur ^= 1;
+    return more;
+  };
+  load(p_begin, va, vb);
+  stage(0, va, vb);
+  __syncthreads();
+  for (int s0 = p_begin;; s0 += 2 * WG_SLAB) {
+    if (!slab(s0, 0)) break;
+    if (!slab(s0 + WG_SLAB, 1)) break;
   }
   if (kt == 0) {
-    // lanes with equal (lane & 7) hold the same 8 channels: reduce them
+    // lanes with equal (lane & 7) hold the same 8 channels: reduce them, then
+    // over the 4 waves through LDS (free after the loop's last barrier)
 #pragma unroll
     for (int j = 0; j < 8; ++j)
       for (int off = 8; off < 64; off <<= 1) bsum[j] += __shfl_xor(bsum[j], off);
-    if (lane < 8 && do_bias)
+    float* red = (float*)&As[0][0];
+    if (lane < 8)
 #pragma unroll
-      for (int j = 0; j < 8; ++j) atomicAdd(a.gb + m0 + s8 + j, bsum[j]);
+      for (int j = 0; j < 8; ++j) red[wv * 64 + s8 + j] = bsum[j];
+    __syncthreads();
+    if (tid < 64 && m0 + tid < a.cout)
+      atomicAdd(a.gb + m0 + tid, red[tid] + red[64 + tid] + red[128 + tid] + red[192 + tid]);
   }
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -709,20 +795,31 @@ void conv3(const ConvArgs& a, int mode, hipStream_t s) {
   else hipLaunchKernelGGL(k_conv3<CONV_MASK>, grid, dim3(256), 0, s, a);
 }
 
+WgradPlan wgrad_plan(int cout, int cin, size_t P) {
+  WgradPlan w;
+  w.ktiles = (9 * cin + 63) / 64;
+  w.mtiles = (cout + 63) / 64;
+  const size_t tiles = (size_t)w.mtiles * w.ktiles;
+  // about WG_TARGET workgroups in all, each chunk at least WG_MIN_CHUNK
+  // pixels and a whole number of slabs: few partial tiles to add atomically
+  size_t nch = (WG_TARGET + tiles - 1) / tiles;
+  const size_t most = (P + WG_MIN_CHUNK - 1) / WG_MIN_CHUNK;
+  if (nch > most) nch = most;
+  if (nch < 1) nch = 1;
+  size_t chunk = (P + nch - 1) / nch;
+  chunk = (chunk + WG_SLAB - 1) / WG_SLAB * WG_SLAB;
+  w.chunk = (int)chunk;
+  w.nch = (int)((P + chunk - 1) / chunk);
+  return w;
+}
+
 void wgrad(WgradArgs a, hipStream_t s) {
-  const size_t P = (size_t)a.B * a.H * a.W;
-  a.ktiles = (9 * a.cin + 63) / 64;
-  const int mtiles = (a.cout + 63) / 64;
-  // pixels per workgroup: enough workgroups to fill the chip several times,
-  // few enough partial tiles to keep the atomics small
-  const size_t tiles = (size_t)mtiles * a.ktiles;
-  size_t chunk = (P * tiles + 4095) / 4096;
-  chunk = ((chunk + 31) / 32) * 32;
-  if (chunk < 256) chunk = 256;
-  if (chunk > 8192) chunk = 8192;
-  a.chunk = (int)chunk;
-  const dim3 grid((unsigned)tiles, (unsigned)((P + chunk - 1) / chunk));
-  hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, s, a);
+  const WgradPlan w = wgrad_plan(a.cout, a.cin, (size_t)a.B * a.H * a.W);
+  a.ktiles = w.ktiles;
+  a.mtiles = w.mtiles;
+  a.nch = w.nch;
+  a.chunk = w.chunk;
+  hipLaunchKernelGGL(k_wgrad, dim3((unsigned)(w.mtiles * w.ktiles * w.nch)), dim3(256), 0, s, a);
 }
 
 void pool(const uint16_t* x, int xs, uint16_t* y, int ys, int B, int H, int W, int C, hipStream_t s) {

@@ -36,11 +36,21 @@ struct WgradArgs {
   int gzs, cout;
   const uint16_t* x;
   int xs, cin, cin_true;
-  float* gw;
-  float* gb;  // bias gradient [cout], accumulated too
+  float* gw;  // weight gradient [cout][9][cin_true], accumulated
+  float* gb;  // bias gradient [cout], accumulated
   int B, H, W;
-  int chunk, ktiles;  // set by the launcher
+  int chunk, nch, ktiles, mtiles;  // set by the launcher
 };
+
+// Weight-gradient work split: 64 x 64 (cout, 9 cin) tiles times nch pixel
+// chunks of `chunk` pixels.
+constexpr int WG_SLAB = 128;        // pixels per LDS slab
+constexpr int WG_TARGET = 1024;     // workgroups per launch to aim for
+constexpr int WG_MIN_CHUNK = 1024;  // fewest pixels per chunk
+struct WgradPlan {
+  int ktiles, mtiles, nch, chunk;
+};
+WgradPlan wgrad_plan(int cout, int cin, size_t P);
 
 void conv3(const ConvArgs& a, int mode, hipStream_t s);
 void wgrad(WgradArgs a, hipStream_t s);
