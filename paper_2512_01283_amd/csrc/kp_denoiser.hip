@@ -263,6 +263,130 @@ __global__ void __launch_bounds__(256) k_conv3_tiled(ConvArgs a) {
   }
 }
 
+// The same convolution with the input tile staged in LDS: a workgroup owns a
+// 16 x 16 block of output pixels of one image x 16 NT output channels; each
+// wave computes 4 rows of it (64 pixels) x 16 NT channels (4 x NT MFMA tiles).
+// NT (1..4) divides cout / 16, so no tile is partial and no MFMA is wasted.  The K
+// loop runs over blocks of 32 input channels: per block the 18 x 18 input
+// halo (zero outside the image and past cin) and the weights of all 9 taps
+// for these channels go to LDS once, and the 9 taps then read their operands
+// from it, so each input value is fetched from memory once instead of once
+// per tap.  LDS rows (a pixel's or an output channel's 32 channels) are
+// padded to 80 bytes, which keeps 16-byte operand reads conflict-free and
+// turns every operand address into a per-lane base plus an immediate.  The
+// next block's loads are in flight in registers during the current block's
+// 144 MFMAs per wave.
+constexpr int CH_E = 18;                  // halo edge (16 + 2)
+constexpr int CH_ROWB = 80;               // LDS bytes per row: 64 data + 16 pad
+constexpr int CH_HALO_B = CH_E * CH_E * CH_ROWB;
+constexpr int CH_LDS_B = CH_HALO_B + 9 * 64 * CH_ROWB;
+constexpr int CH_NH = (CH_E * CH_E * 4 + 255) / 256;  // halo chunks per thread (6)
+
+template <int MODE, int NT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_conv3_halo(ConvArgs a) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[CH_LDS_B];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int ngroups = a.nout / (16 * NT);
+  const int txn = (a.W + 15) >> 4, tyn = (a.H + 15) >> 4;
+  int bid = blockIdx.x;
+  const int ng = bid % ngroups;
+  bid /= ngroups;
+  const int tx = bid % txn;
+  bid /= txn;
+  const int ty = bid % tyn;
+  const int img = bid / tyn;
+  const int n0 = ng * 16 * NT;
+  const int y0 = ty * 16, x0 = tx * 16;
+  // loader slots: 16-byte chunk c = tid & 3 (channels 8c..8c+7 of the block)
+  // of halo pixels (tid >> 2) + 64 u and of weight rows (tap u, channel tid >> 2)
+  const int c8 = (tid & 3) * 8;
+  int hpix[CH_NH];  // input pixel of each halo slot, -1 outside the image or the halo
+#pragma unroll
+  for (int u = 0; u < CH_NH; ++u) {
+    const int hp = (tid >> 2) + 64 * u;
+    const int hy = hp / CH_E, hx = hp - hy * CH_E;
+    const int yy = y0 + hy - 1, xx = x0 + hx - 1;
+    const bool ok = hp < CH_E * CH_E && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+    hpix[u] = ok ? (img * a.H + yy) * a.W + xx : -1;
+  }
+  const int hdst = (tid >> 2) * CH_ROWB + (tid & 3) * 16;  // + 64 u rows
+  const int wco = tid >> 2;
+  const uint16_t* wsrc = wco < 16 * NT ? a.w + (size_t)(n0 + wco) * a.kp + c8 : nullptr;
+  const int wdst = CH_HALO_B + wco * CH_ROWB + (tid & 3) * 16;  // + 64 u rows
+  const u32x4 zero = {0u, 0u, 0u, 0u};
+  u32x4 hv[CH_NH], wvv[9];
+  auto load = [&](int cb) {
+    const int ch = cb * 32 + c8;
+    const bool cok = ch < a.cin;
+#pragma unroll
+    for (int u = 0; u < CH_NH; ++u)
+      hv[u] = (cok && hpix[u] >= 0) ? ld16(a.x + (size_t)hpix[u] * a.xs + ch) : zero;
+#pragma unroll
+    for (int u = 0; u < 9; ++u) wvv[u] = (cok && wsrc) ? ld16(wsrc + u * a.cin + cb * 32) : zero;
+  };
+  auto store = [&]() {
+#pragma unroll
+    for (int u = 0; u < CH_NH; ++u)
+      if ((tid >> 2) + 64 * u < CH_E * CH_E) *(u32x4*)(lds + hdst + u * 64 * CH_ROWB) = hv[u];
+    if (wsrc)
+#pragma unroll
+      for (int u = 0; u < 9; ++u) *(u32x4*)(lds + wdst + u * 64 * CH_ROWB) = wvv[u];
+  };
+  f32x4 acc[4][NT];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[r][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // operand bases: pixel (4 wv, i) of the tile is halo pixel (4 wv + 1, i + 1)
+  const unsigned char* abase = lds + (4 * wv * CH_E + i) * CH_ROWB + 16 * g;
+  const unsigned char* bbase = lds + CH_HALO_B + i * CH_ROWB + 16 * g;
+  const int nb = (a.cin + 31) >> 5;
+  load(0);
+  for (int cb = 0; cb < nb; ++cb) {
+    if (cb > 0) __syncthreads();
+    store();
+    __syncthreads();
+    if (cb + 1 < nb) load(cb + 1);
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3, dx = tap % 3;  // halo offsets 0..2
+      u32x4 av[4], bv[NT];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) av[r] = *(const u32x4*)(abase + ((r + dy) * CH_E + dx) * CH_ROWB);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) bv[t] = *(const u32x4*)(bbase + (tap * 64 + 16 * t) * CH_ROWB);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r][t] = mfma(av[r], bv[t], acc[r][t]);
+      // keep the scheduler from hoisting later taps' operand reads (registers)
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int n = n0 + 16 * t + i;
+    const float bn_v = MODE == CONV_MASK ? 0.f : a.bias[n];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int yy = y0 + 4 * wv + r;
+      if (yy >= a.H) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int xx = x0 + 4 * g + j;
+        if (xx >= a.W) continue;
+        const size_t p = (size_t)(img * a.H + yy) * a.W + xx;
+        float v = acc[r][t][j] + bn_v;
+        if (MODE == CONV_RELU) v = fmaxf(v, 0.f);
+        if (MODE == CONV_MASK && a.mask && !bf_pos(a.mask[p * a.ms + n])) v = 0.f;
+        a.y[p * a.ys + n] = f2bf(v);
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Weight gradient:  gw[co][kk][c] += sum_p gz[p][co] * x[p + off(kk)][c]
 // GEMM M = co, N = k = kk * cin + c, reduction over pixels.  A workgroup owns
@@ -782,10 +906,19 @@ void conv3(const ConvArgs& a, int mode, hipStream_t s) {
   const size_t P = (size_t)a.B * a.H * a.W;
   const unsigned ngroups = (unsigned)((a.nout + 63) / 64);
   if (P >= CONV_TILED_MIN_PIXELS) {
-    const dim3 grid((unsigned)((P + 255) / 256) * ngroups);
-    if (mode == CONV_RELU) hipLaunchKernelGGL(k_conv3_tiled<CONV_RELU>, grid, dim3(256), 0, s, a);
-    else if (mode == CONV_LINEAR) hipLaunchKernelGGL(k_conv3_tiled<CONV_LINEAR>, grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_conv3_tiled<CONV_MASK>, grid, dim3(256), 0, s, a);
+    // widest channel group (16 NT, NT <= 4) that divides cout
+    const int t16 = a.nout / 16;
+    const int nt = t16 % 4 == 0 ? 4 : t16 % 3 == 0 ? 3 : t16 % 2 == 0 ? 2 : 1;
+    const dim3 grid((unsigned)(a.B * ((a.H + 15) / 16) * ((a.W + 15) / 16) * (t16 / nt)));
+    switch (mode * 4 + nt - 1) {
+#define KP_HALO_CASE(M, N) \
+  case M * 4 + N - 1: hipLaunchKernelGGL((k_conv3_halo<M, N>), grid, dim3(256), 0, s, a); break;
+      KP_HALO_CASE(CONV_RELU, 1) KP_HALO_CASE(CONV_RELU, 2) KP_HALO_CASE(CONV_RELU, 3) KP_HALO_CASE(CONV_RELU, 4)
+      KP_HALO_CASE(CONV_LINEAR, 1) KP_HALO_CASE(CONV_LINEAR, 2) KP_HALO_CASE(CONV_LINEAR, 3)
+      KP_HALO_CASE(CONV_LINEAR, 4) KP_HALO_CASE(CONV_MASK, 1) KP_HALO_CASE(CONV_MASK, 2)
+      KP_HALO_CASE(CONV_MASK, 3) KP_HALO_CASE(CONV_MASK, 4)
+#undef KP_HALO_CASE
+    }
     return;
   }
   const size_t waves = ((P + 31) / 32) * ngroups;
