@@ -681,7 +681,9 @@ __global__ void k_pool_bwd_add(const uint16_t* __restrict__ a, int as, const uin
 // input normalisation, head, loss, output, optimiser
 // ---------------------------------------------------------------------------
 // sums[2b] += sum of I, sums[2b+1] += sum of I^2 over image b of maps [B][4][H*W]
+// (256-thread blocks; one pair of atomics per block)
 __global__ void k_sums(const double* __restrict__ maps, int HW, double* __restrict__ sums) {
+  __shared__ double red[2][4];
   const int b = blockIdx.y;
   double a1 = 0.0, a2 = 0.0;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < HW; p += gridDim.x * blockDim.x) {
@@ -694,9 +696,13 @@ __global__ void k_sums(const double* __restrict__ maps, int HW, double* __restri
     a2 += __shfl_xor(a2, off);
   }
   if ((threadIdx.x & 63) == 0) {
-    atomicAdd(sums + 2 * b, a1);
-    atomicAdd(sums + 2 * b + 1, a2);
+    red[0][threadIdx.x >> 6] = a1;
+    red[1][threadIdx.x >> 6] = a2;
   }
+  __syncthreads();
+  if (threadIdx.x < 2)
+    atomicAdd(sums + 2 * b + threadIdx.x,
+              red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3]);
 }
 
 // Input features of pixel p of image b (s = the image's mean I, Ihat = I/s):
@@ -781,59 +787,85 @@ __global__ void k_head(const uint16_t* __restrict__ d, int C, const float* __res
 // Relative-error loss: with e = out * Ihat - tgt (both channels) and
 // W_b = sum_p Ihat^2 = (sum I^2) / s^2 of image b,
 //   loss += sum_p |e|^2 / (B W_b)   (FP64),   go = 2 e Ihat / (B W_b).
+// Grid (blocks, B) of 256-thread blocks: image b = blockIdx.y, so the scale
+// is formed once per thread; one atomic per block.
 __global__ void k_loss(const float* __restrict__ out, const float* __restrict__ tgt,
                        const float* __restrict__ ihat, const double* __restrict__ sums, int B, int HW,
                        float* __restrict__ go, double* __restrict__ loss) {
-  const size_t n = (size_t)B * HW;
+  __shared__ double red[4];
+  const int b = blockIdx.y;
+  const double mean = sums[2 * b] / HW;
+  const double wb = mean > 0.0 ? sums[2 * b + 1] / (mean * mean) : 0.0;
+  const double scale = wb > 0.0 ? 1.0 / (B * wb) : 0.0;
+  const float s2 = (float)(2.0 * scale);
   double acc = 0.0;
-  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
-    const size_t b = k / HW;
-    const double mean = sums[2 * b] / HW;
-    const double wb = mean > 0.0 ? sums[2 * b + 1] / (mean * mean) : 0.0;
-    const double scale = wb > 0.0 ? 1.0 / (B * wb) : 0.0;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < HW; p += gridDim.x * blockDim.x) {
+    const size_t k = (size_t)b * HW + p;
     const float ih = ihat[k];
-    const float e0 = out[2 * k] * ih - tgt[2 * k], e1 = out[2 * k + 1] * ih - tgt[2 * k + 1];
-    go[2 * k] = (float)(2.0 * scale) * e0 * ih;
-    go[2 * k + 1] = (float)(2.0 * scale) * e1 * ih;
-    acc += ((double)e0 * e0 + (double)e1 * e1) * scale;
+    const float2 o = *(const float2*)(out + 2 * k), t = *(const float2*)(tgt + 2 * k);
+    const float e0 = o.x * ih - t.x, e1 = o.y * ih - t.y;
+    *(float2*)(go + 2 * k) = float2{s2 * e0 * ih, s2 * e1 * ih};
+    acc += (double)e0 * e0 + (double)e1 * e1;
   }
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  if ((threadIdx.x & 63) == 0) atomicAdd(loss, acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(loss, (red[0] + red[1] + red[2] + red[3]) * scale);
 }
 
-// Head backward over a block of 256 pixels, one thread per channel:
+// Head backward over a chunk of pixels (256-thread blocks): thread t owns
+// channels 8 (t % C8) .. +7 (C8 = C / 8) of pixels t / C8, + 256 / C8, ...:
 // ghw[o][c] += sum_p go[p][o] d[p][c]; ghb[o] += sum_p go[p][o];
 // gd[p][c] = (sum_o go[p][o] hw[o][c]) where d[p][c] > 0, else 0.
+// Per-thread sums are combined in LDS, then one atomic per weight per block.
+constexpr int HB_CHUNK = 1024;  // pixels per block
 __global__ void k_head_bwd(const float* __restrict__ go, const uint16_t* __restrict__ d, int C,
                            const float* __restrict__ hw, float* __restrict__ ghw, float* __restrict__ ghb,
                            uint16_t* __restrict__ gd, size_t P) {
-  __shared__ float sgo[256][2];
-  const size_t p0 = (size_t)blockIdx.x * 256;
-  const int np = (int)((P - p0) < 256 ? (P - p0) : 256);
-  for (int k = threadIdx.x; k < np; k += blockDim.x) {
-    sgo[k][0] = go[2 * (p0 + k)];
-    sgo[k][1] = go[2 * (p0 + k) + 1];
+  __shared__ float red[2 * 512 + 2];
+  const int tid = threadIdx.x;
+  const int C8 = C >> 3, pp = 256 / C8;
+  for (int k = tid; k < 2 * C + 2; k += 256) red[k] = 0.f;
+  __syncthreads();
+  const int g = tid % C8, pl = tid / C8;
+  if (pl < pp) {
+    float h0[8], h1[8], a0[8], a1[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      h0[j] = hw[8 * g + j];
+      h1[j] = hw[C + 8 * g + j];
+      a0[j] = a1[j] = 0.f;
+    }
+    float sb0 = 0.f, sb1 = 0.f;
+    const size_t p0 = (size_t)blockIdx.x * HB_CHUNK;
+    const size_t pe = P - p0 < (size_t)HB_CHUNK ? P : p0 + HB_CHUNK;
+    for (size_t p = p0 + pl; p < pe; p += pp) {
+      const float2 o = *(const float2*)(go + 2 * p);
+      float v[8], r[8];
+      unpack8(ld16(d + p * C + 8 * g), v);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        a0[j] += o.x * v[j];
+        a1[j] += o.y * v[j];
+        r[j] = v[j] > 0.f ? o.x * h0[j] + o.y * h1[j] : 0.f;
+      }
+      st16(gd + p * C + 8 * g, pack8(r));
+      sb0 += o.x;
+      sb1 += o.y;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      atomicAdd(&red[8 * g + j], a0[j]);
+      atomicAdd(&red[C + 8 * g + j], a1[j]);
+    }
+    if (g == 0) {
+      atomicAdd(&red[2 * C], sb0);
+      atomicAdd(&red[2 * C + 1], sb1);
+    }
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < C; c += blockDim.x) {
-    const float h0 = hw[c], h1 = hw[C + c];
-    float a0 = 0.f, a1 = 0.f;
-    for (int k = 0; k < np; ++k) {
-      const size_t p = p0 + k;
-      const uint16_t db = d[p * C + c];
-      const float v = bf2f(db);
-      a0 += sgo[k][0] * v;
-      a1 += sgo[k][1] * v;
-      gd[p * C + c] = bf_pos(db) ? f2bf(sgo[k][0] * h0 + sgo[k][1] * h1) : (uint16_t)0;
-    }
-    atomicAdd(ghw + c, a0);
-    atomicAdd(ghw + C + c, a1);
-  }
-  if (threadIdx.x < 2) {
-    float s = 0.f;
-    for (int k = 0; k < np; ++k) s += sgo[k][threadIdx.x];
-    atomicAdd(ghb + threadIdx.x, s);
-  }
+  for (int k = tid; k < 2 * C; k += 256) atomicAdd(ghw + k, red[k]);
+  if (tid < 2) atomicAdd(ghb + tid, red[2 * C + tid]);
 }
 
 // denoised maps: I and V from the input, Q = q' I and U = u' I
@@ -985,12 +1017,12 @@ void head(const uint16_t* d, int C, const float* hw, const float* hb, const floa
 }
 void loss(const float* out, const float* tgt, const float* ihat, const double* sum, int B, int HW, float* go,
           double* l, hipStream_t s) {
-  hipLaunchKernelGGL(k_loss, dim3(grid_for((size_t)B * HW, 2048)), dim3(256), 0, s, out, tgt, ihat, sum, B, HW, go,
-                     l);
+  hipLaunchKernelGGL(k_loss, dim3(grid_for(HW, 256), B), dim3(256), 0, s, out, tgt, ihat, sum, B, HW, go, l);
 }
 void head_bwd(const float* go, const uint16_t* d, int C, const float* hw, float* ghw, float* ghb, uint16_t* gd,
               size_t P, hipStream_t s) {
-  hipLaunchKernelGGL(k_head_bwd, dim3((unsigned)((P + 255) / 256)), dim3(64), 0, s, go, d, C, hw, ghw, ghb, gd, P);
+  hipLaunchKernelGGL(k_head_bwd, dim3((unsigned)((P + HB_CHUNK - 1) / HB_CHUNK)), dim3(256), 0, s, go, d, C, hw, ghw,
+                     ghb, gd, P);
 }
 void output(const double* maps, const float* out, int B, int HW, double* dst, hipStream_t s) {
   hipLaunchKernelGGL(k_output, dim3(grid_for((size_t)B * HW)), dim3(256), 0, s, maps, out, B, HW, dst);
