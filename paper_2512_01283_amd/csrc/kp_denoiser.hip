@@ -153,116 +153,6 @@ __global__ void __launch_bounds__(256) k_conv3(ConvArgs a) {
   }
 }
 
-// The same convolution for large pixel counts: a workgroup (4 waves) owns 256
-// pixels x 64 output channels; each wave computes 64 pixels x 64 channels
-// (4 x 4 MFMA tiles), so every weight operand feeds 4 MFMAs and every input
-// operand up to 4.  The weight slab of one K step (64 channels x 32 k, 4 KB)
-// is loaded once per workgroup into LDS, double-buffered, while the input
-// operands of the next K step are fetched into registers during the MFMAs of
-// the current one.  LDS rows are padded to 80 bytes so that the 16 lanes of a
-// 16-byte read touch disjoint banks.
-constexpr int CT_ROW = 5;  // u32x4 per LDS row (4 data + 1 pad)
-
-template <int MODE>
-__global__ void __launch_bounds__(256) k_conv3_tiled(ConvArgs a) {
-  __shared__ u32x4 Bs[2][64 * CT_ROW];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6;
-  const int i = lane & 15, g = lane >> 4;
-  const int P = a.B * a.H * a.W;
-  const int ngroups = (a.nout + 63) >> 6;
-  const int ptile = blockIdx.x / ngroups, ng = blockIdx.x - ptile * ngroups;
-  const int n0 = ng * 64;
-  const int ntile = min(4, (a.nout - n0) >> 4);
-  const int pbase = ptile * 256 + 64 * wv;
-  int ph[4], pw[4], pn[4];
-  bool pv[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int p = pbase + 16 * r + i;
-    pv[r] = p < P;
-    const int q = pv[r] ? p : 0;
-    pw[r] = q % a.W;
-    ph[r] = (q / a.W) % a.H;
-    pn[r] = q / (a.W * a.H);
-  }
-  // weight loader slot of this thread: row bn (output channel n0 + bn), 8-wide k group bg
-  const int bn = tid >> 2, bg = tid & 3;
-  const bool b_ok = n0 + bn < a.nout;
-  const uint16_t* wsrc = a.w + (size_t)(b_ok ? n0 + bn : 0) * a.kp + 8 * bg;
-  const int K = 9 * a.cin;
-  const int nsteps = (K + 31) / 32;
-  const u32x4 zero = {0u, 0u, 0u, 0u};
-  int kk = 0, c = 8 * g;
-  while (c >= a.cin) {
-    c -= a.cin;
-    ++kk;
-  }
-  auto load_a = [&](u32x4* av) {
-    const int dy = kk / 3 - 1, dx = kk % 3 - 1;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int hh = ph[r] + dy, ww = pw[r] + dx;
-      const bool ok = pv[r] && kk < 9 && hh >= 0 && hh < a.H && ww >= 0 && ww < a.W;
-      av[r] = ok ? ld16(a.x + ((size_t)(pn[r] * a.H + hh) * a.W + ww) * a.xs + c) : zero;
-    }
-    c += 32;
-    while (c >= a.cin) {
-      c -= a.cin;
-      ++kk;
-    }
-  };
-  f32x4 acc[4][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int t = 0; t < 4; ++t) acc[r][t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  u32x4 av[4], an[4];
-  u32x4 bv = b_ok ? ld16(wsrc) : zero;
-  load_a(av);
-  Bs[0][bn * CT_ROW + bg] = bv;
-  __syncthreads();
-  for (int s = 0; s < nsteps; ++s) {
-    const int cur = s & 1;
-    const bool more = s + 1 < nsteps;
-    if (more) {
-      bv = b_ok ? ld16(wsrc + 32 * (s + 1)) : zero;
-      load_a(an);
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      if (t < ntile) {
-        const u32x4 b = Bs[cur][(16 * t + i) * CT_ROW + g];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[r][t] = mfma(av[r], b, acc[r][t]);
-      }
-    }
-    if (more) {
-      Bs[cur ^ 1][bn * CT_ROW + bg] = bv;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) av[r] = an[r];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    if (t >= ntile) continue;
-    const int n = n0 + 16 * t + i;
-    const float bn_v = MODE == CONV_MASK ? 0.f : a.bias[n];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int p = pbase + 16 * r + 4 * g + j;
-        if (p >= P) continue;
-        float v = acc[r][t][j] + bn_v;
-        if (MODE == CONV_RELU) v = fmaxf(v, 0.f);
-        if (MODE == CONV_MASK && a.mask && !bf_pos(a.mask[(size_t)p * a.ms + n])) v = 0.f;
-        a.y[(size_t)p * a.ys + n] = f2bf(v);
-      }
-  }
-}
-
 // LDS access rule of gfx950 used by the layouts below (measured with the
 // SQ_LDS_BANK_CONFLICT counter on access patterns of known shape): 64 banks
 // of 4 bytes; a 16-byte access is served in four passes of 16 lanes, the
@@ -1020,7 +910,7 @@ void pool_bwd_add(const uint16_t* a, int as, const uint16_t* g, int gs, const ui
                      ms, dst, ds, B, H, W, C);
 }
 void sums(const double* maps, int B, int HW, double* sum, hipStream_t s) {
-  hipLaunchKernelGGL(k_sums, dim3(grid_for(HW, 64), B), dim3(256), 0, s, maps, HW, sum);
+  hipLaunchKernelGGL(k_sums, dim3(grid_for(HW, 32), B), dim3(256), 0, s, maps, HW, sum);
 }
 void prep(const double* maps, const double* target, const double* sum, const int32_t* aug, int B, int H, int W,
           uint16_t* x, float* xq, float* ihat, float* tgt, hipStream_t s) {
@@ -1033,7 +923,8 @@ void head(const uint16_t* d, int C, const float* hw, const float* hb, const floa
 }
 void loss(const float* out, const float* tgt, const float* ihat, const double* sum, int B, int HW, float* go,
           double* l, hipStream_t s) {
-  hipLaunchKernelGGL(k_loss, dim3(grid_for(HW, 256), B), dim3(256), 0, s, out, tgt, ihat, sum, B, HW, go, l);
+  // few blocks per image: the per-block results meet in one FP64 atomic
+  hipLaunchKernelGGL(k_loss, dim3(grid_for(HW, 32), B), dim3(256), 0, s, out, tgt, ihat, sum, B, HW, go, l);
 }
 void head_bwd(const float* go, const uint16_t* d, int C, const float* hw, float* ghw, float* ghb, uint16_t* gd,
               size_t P, hipStream_t s) {

@@ -11,7 +11,7 @@ namespace dn {
 enum { CONV_RELU = 0, CONV_LINEAR = 1, CONV_MASK = 2 };
 
 // pixel count from which convolutions use the LDS-tiled kernel (256 pixels per workgroup)
-constexpr size_t CONV_TILED_MIN_PIXELS = 1024;
+constexpr size_t CONV_TILED_MIN_PIXELS = 1024;  // from here on the LDS-staged kernel
 
 // y[p][n] (stride ys) from x[p][c] (stride xs, cin channels per tap, cin % 8 == 0)
 // and GEMM weights w[nout][kp] (kp % 32 == 0, kp >= 9 cin, nout % 16 == 0).
