@@ -60,15 +60,20 @@ def run_images(ctx, packets, seed):
 
 
 def make_pairs(seeds, n_lo, n_hi, n=256, npix=None, log=print):
-    """Returns (lo, hi) CUDA tensors [len(seeds) * 8, 4, H, W]."""
+    """Returns (lo, hi) CUDA tensors [len(seeds) * 8 * len(n_lo), 4, H, W].
+    n_lo is one input packet count or a sequence of them: each disk then
+    gives one input per count, all paired with the same target run."""
     import torch
+    counts = [n_lo] if np.isscalar(n_lo) else list(n_lo)
     los, his = [], []
     t0 = time.time()
     for k, (s, cfg) in enumerate(_disks(seeds, n, npix)):
         with P.Context(0) as ctx:
             ctx.load(cfg)
-            los.append(run_images(ctx, n_lo, 2 * s + 1))
-            his.append(run_images(ctx, n_hi, 2 * s + 2))
+            hi = run_images(ctx, n_hi, 2 * s + 2)
+            for j, c in enumerate(counts):
+                los.append(run_images(ctx, c, 2 * s + 1 + 1000003 * j))
+                his.append(hi)
         if log and (k + 1) % 8 == 0:
             log(f"  pairs: {k + 1}/{len(seeds)} disks, {time.time() - t0:.1f} s", flush=True)
     torch.cuda.synchronize()
@@ -181,7 +186,7 @@ def main(argv=None):
     ap.add_argument("--npix", type=int, default=256)
     ap.add_argument("--train-seeds", default="1000:1064")
     ap.add_argument("--test-seeds", default="3000:3008")
-    ap.add_argument("--n-lo", type=float, default=1e6)
+    ap.add_argument("--n-lo", default="1e6", help="input packet count(s), comma-separated")
     ap.add_argument("--n-hi", type=float, default=3e7)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--batch", type=int, default=8)
@@ -200,7 +205,8 @@ def main(argv=None):
     log = print
     t0 = time.time()
     log(f"generating training pairs on {torch.cuda.get_device_name(0)}", flush=True)
-    lo, hi = make_pairs(seeds(a.train_seeds), a.n_lo, a.n_hi, n=a.grid, npix=a.npix, log=log)
+    n_lo = [float(v) for v in str(a.n_lo).split(",")]
+    lo, hi = make_pairs(seeds(a.train_seeds), n_lo, a.n_hi, n=a.grid, npix=a.npix, log=log)
     t_gen = time.time() - t0
     widths = tuple(int(v) for v in a.widths.split(","))
     dn = DN.Denoiser(0, widths=widths)
@@ -212,7 +218,7 @@ def main(argv=None):
     t_train = time.time() - t1
     del lo, hi
     np.save(os.path.join(a.out, "params.npy"), dn.params())
-    res = dict(widths=list(widths), params=dn.n, train_seeds=a.train_seeds, n_lo=a.n_lo, n_hi=a.n_hi,
+    res = dict(widths=list(widths), params=dn.n, train_seeds=a.train_seeds, n_lo=n_lo, n_hi=a.n_hi,
                steps=a.steps, batch=a.batch,
                lr=a.lr, t_generate_s=t_gen, t_train_s=t_train,
                loss_first=hist[0][1], loss_last=float(np.mean([l for _, l in hist[-50:]])))
