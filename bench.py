@@ -38,9 +38,9 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_STEP_SPHERE = 4 + 2 * 6 * 8
 
 
-def counter_traffic():
-    """HBM bytes per transport launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE runs (scaled by a 1 GiB copy's readings), in GB; None when the
+def counter_record():
+    """The committed rocprofv3 counter record of one transport launch
+    (profiles/k_transport_disk256_1e8.counters.json), or None when the
     transport kernel's source has changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_transport_disk256_1e8.counters.json")
@@ -52,7 +52,44 @@ def counter_traffic():
                    for f in ("kp_kernels.hip", "kp_device.hpp", "kp_internal.hpp"))
     if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
         return None
-    return rec["traffic_bytes"] / 1e9
+    return rec
+
+
+def counter_traffic():
+    """HBM bytes per transport launch from the committed FETCH_SIZE /
+    WRITE_SIZE runs (scaled by a 1 GiB copy's readings), in GB, or None."""
+    rec = counter_record()
+    return None if rec is None else rec["traffic_bytes"] / 1e9
+
+
+ATOMIC_CAL_LINES = 1 << 24
+
+
+def atomic_calibration(lines: int = ATOMIC_CAL_LINES, reps: int = 3) -> float:
+    """Random 64-byte-line FP64 atomics the device sustains, in lines/s: a
+    plain scatter-add (torch index_add_) of `lines` rows of 6 FP64 values at
+    uniformly random rows of a [256^3, 8] FP64 array -- the shape of the
+    transport's tally flush (one 64-byte block per cell, six coherency reals),
+    without its locality.  Best of `reps` launches, HIP events."""
+    import torch
+    ncell = 256 ** 3
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    t = torch.zeros(ncell, 8, dtype=torch.float64, device="cuda")
+    idx = torch.randint(0, ncell, (lines,), device="cuda", generator=g)
+    src = torch.rand(lines, 6, dtype=torch.float64, device="cuda", generator=g)
+    view = t[:, :6]
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        view.index_add_(0, idx, src)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del t, idx, src
+    return lines / (best * 1e-3)
 
 
 def parse():
@@ -66,6 +103,8 @@ def parse():
                     help="packets of the oracle's timed sample")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device-to-device copy of this size (counter calibration)")
+    ap.add_argument("--atomic-calibration", action="store_true",
+                    help="only run the random 64-byte-line atomic calibration")
     ap.add_argument("--block-size", type=int, default=0)
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--no-denoiser", action="store_true")
@@ -118,6 +157,10 @@ def main():
     if args.copy_calibration_mib:
         copy_calibration(args.copy_calibration_mib)
         return
+    if args.atomic_calibration:
+        print(json.dumps({"atomic_calibration_lines": ATOMIC_CAL_LINES,
+                          "lines_per_s": atomic_calibration()}))
+        return
 
     import numpy as np
     import torch
@@ -154,7 +197,7 @@ def main():
         one_step()
         print(f"warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    ms_t, ms_i, ms_d, steps = [], [], [], []
+    ms_t, ms_i, ms_d, steps, flushes = [], [], [], [], []
     t0 = time.perf_counter()
     for k in range(args.steps):
         one_step()
@@ -162,6 +205,7 @@ def main():
         ms_t.append(st["ms_transport"])
         ms_i.append(st["ms_image"])
         steps.append(st["cell_steps"])
+        flushes.append(st["tally_flushes"])
         if dn is not None:
             ms_d.append(dn.timing())
         print(f"step {k + 1}/{args.steps}: transport {st['ms_transport']:.1f} ms, imaging "
@@ -237,6 +281,18 @@ def main():
             d["train_wgrad_mfma_frac"] = d["train_wgrad_tflops"] / BF16_PEAK_TFLOPS
         out["detail"]["denoiser"] = d
         dn.close()
+    # the transport's binding resource: random tally-line atomics, against
+    # what a plain scatter-add of the same shape sustains on this device
+    cal = atomic_calibration()
+    lines = float(np.mean(flushes))
+    out["detail"]["atomic_roofline"] = {
+        "bound": "random 64-byte-line FP64 atomics (tally flush)",
+        "achieved_lines_per_s": lines / (avg_t * 1e-3), "calibrated_lines_per_s": cal,
+        "frac": lines / (avg_t * 1e-3) / cal, "lines_per_launch": lines,
+        "lines_unit": "tally cell blocks flushed per transport launch (kp_stats.tally_flushes), "
+                      "one 64-byte block of six FP64 each",
+        "calibration": "torch index_add_ of 2^24 rows of 6 FP64 at uniform random rows of a "
+                       "[256^3, 8] FP64 array, best of 3 (bench.py --atomic-calibration)"}
     if not args.no_cpu_baseline:
         print("timing the oracle on a bounded sample ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample)

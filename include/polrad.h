@@ -149,6 +149,8 @@ typedef struct {
   double ms_transport; /* transport kernel time (HIP events on the run's stream) */
   double ms_image;     /* imaging kernel time */
   int64_t packets;
+  int64_t tally_flushes; /* per-cell tally blocks added to the source tally
+                            (one atomic read-modify-write of the block each) */
 } kp_stats;
 
 /* Final state of a traced packet. end_kind: 2 escaped, 4 roulette kill or

@@ -498,6 +498,7 @@ kp_status kp_transport(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, vo
   r.trials = (int64_t)h.trials; r.rr_kills = (int64_t)h.rr_kills;
   r.rr_survivals = (int64_t)h.rr_survivals; r.escaped = (int64_t)h.escaped;
   r.budget = (int64_t)h.budget; r.numeric = (int64_t)h.numeric; r.packets = (int64_t)h.packets;
+  r.tally_flushes = (int64_t)h.tally_flushes;
   r.e_emitted = h.e_emitted; r.e_escaped = h.e_escaped; r.e_absorbed = h.e_absorbed;
   r.e_rr_killed = h.e_rr_killed; r.e_rr_gained = h.e_rr_gained; r.e_budget = h.e_budget;
   r.e_scat_delta = h.e_scat_delta;

@@ -33,7 +33,7 @@ struct ViewDev {
 
 struct StatsDev {
   unsigned long long cell_steps, scatterings, trials, rr_kills, rr_survivals, escaped,
-      budget, numeric, packets;
+      budget, numeric, packets, tally_flushes;
   double e_emitted, e_escaped, e_absorbed, e_rr_killed, e_rr_gained, e_budget, e_scat_delta;
 };
 

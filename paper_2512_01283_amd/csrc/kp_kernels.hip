@@ -212,11 +212,12 @@ __device__ __forceinline__ V3<double> cell_bdir(const TransportArgs& a, const do
 // stages (key, NC values) in this wavefront's LDS area; then lane L adds
 // component L % NC of staged entry L / NC, so one atomic instruction covers
 // 64 / NC whole cells.  Must be reached by all lanes of the wavefront.
+// Returns the number of cells flushed (the same in every lane).
 template <int NC, int TS>
-__device__ __forceinline__ void wave_flush(bool need, int64_t key, const double acc[NC],
-                                           double* tally, double* sv, long long* sk, int lane) {
+__device__ __forceinline__ int wave_flush(bool need, int64_t key, const double acc[NC],
+                                          double* tally, double* sv, long long* sk, int lane) {
   const unsigned long long mask = __ballot(need);
-  if (mask == 0ull) return;
+  if (mask == 0ull) return 0;
   const int n = __popcll(mask);
   if (need) {
     const int r = __popcll(mask & ((1ull << lane) - 1ull));
@@ -255,6 +256,7 @@ __device__ __forceinline__ void wave_flush(bool need, int64_t key, const double 
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  return n;
 }
 
 // Dimensionless extinction coefficients for a direction with cos(theta') =
@@ -574,7 +576,7 @@ __device__ uint32_t roulette(Packet<R>& p, const TransportArgs& a) {
 }
 
 // stats slots in LDS
-enum { SC_STEPS, SC_SCAT, SC_TRIALS, SC_KILL, SC_SURV, SC_ESC, SC_BUDGET, SC_NUM, SC_PACK, SC_N };
+enum { SC_STEPS, SC_SCAT, SC_TRIALS, SC_KILL, SC_SURV, SC_ESC, SC_BUDGET, SC_NUM, SC_PACK, SC_FLUSH, SC_N };
 enum { SE_EMIT, SE_ESC, SE_ABS, SE_KILL, SE_GAIN, SE_BUDGET, SE_SCAT, SE_N };
 
 template <typename R>
@@ -631,6 +633,7 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
   bool active = false, exhausted = false, pending = false;
   int waited = 0;
   int64_t acc_key = -1;
+  unsigned long long flushes = 0;  // tally cells flushed by this wavefront
   double acc[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) acc[k] = 0.0;
@@ -667,7 +670,7 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
       }
     }
     // a lane entering another (wavelength, cell) hands its running sum over
-    wave_flush<NC, TS>(has && key != acc_key && acc_key >= 0, acc_key, acc, a.tally, sv, sk, lane);
+    flushes += wave_flush<NC, TS>(has && key != acc_key && acc_key >= 0, acc_key, acc, a.tally, sv, sk, lane);
     if (has) {
       if (key == acc_key) {
 #pragma unroll
@@ -699,7 +702,8 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
       }
     }
   }
-  wave_flush<NC, TS>(acc_key >= 0, acc_key, acc, a.tally, sv, sk, lane);
+  flushes += wave_flush<NC, TS>(acc_key >= 0, acc_key, acc, a.tally, sv, sk, lane);
+  if (lane == 0) atomicAdd(&sc[SC_FLUSH], flushes);
   __syncthreads();
   if (threadIdx.x < SC_N) atomicAdd(&(&a.stats->cell_steps)[threadIdx.x], sc[threadIdx.x]);
   if (threadIdx.x < SE_N) unsafeAtomicAdd(&(&a.stats->e_emitted)[threadIdx.x], se[threadIdx.x]);

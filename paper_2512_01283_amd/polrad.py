@@ -81,7 +81,7 @@ class kp_stats(C.Structure):
                [(k, C.c_double) for k in
                 ("e_emitted", "e_escaped", "e_absorbed", "e_rr_killed", "e_rr_gained",
                  "e_budget", "e_scat_delta", "ms_transport", "ms_image")] + \
-               [("packets", C.c_int64)]
+               [("packets", C.c_int64), ("tally_flushes", C.c_int64)]
 
 
 TRACE_DTYPE = np.dtype([("packet", "<u8"), ("end_kind", "<i4"), ("events", "<i4"),

@@ -53,6 +53,8 @@ def test_config0_fp64_path_by_path(O):
         if k in st_o:
             assert st[k] == st_o[k], k
     assert st["packets"] == 100_000
+    # each flushed tally block closes a run of steps in one cell
+    assert 0 < st["tally_flushes"] <= st["cell_steps"]
     assert abs(st["e_escaped"] - st_o["e_escaped"]) < 1e-12
     scale = np.abs(img_o[:, 0]).max()
     d = np.abs(img_g - img_o).max() / scale
@@ -159,6 +161,7 @@ def test_disk_full_size_sampled(O):
     bal = st["e_escaped"] + st["e_absorbed"] + st["e_rr_killed"] - st["e_rr_gained"] + st["e_budget"]
     assert abs(bal - st["e_emitted"]) < 1e-5 * st["e_emitted"]
     assert st["packets"] == 100_000_000 and st["numeric"] == 0
+    assert 0 < st["tally_flushes"] <= st["cell_steps"]
 
 
 @pytest.mark.parametrize("fp64", [1, 0, 2])
