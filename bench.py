@@ -66,30 +66,23 @@ ATOMIC_CAL_LINES = 1 << 24
 
 
 def atomic_calibration(lines: int = ATOMIC_CAL_LINES, reps: int = 3) -> float:
-    """Random 64-byte-line FP64 atomics the device sustains, in lines/s: a
-    plain scatter-add (torch index_add_) of `lines` rows of 6 FP64 values at
-    uniformly random rows of a [256^3, 8] FP64 array -- the shape of the
-    transport's tally flush (one 64-byte block per cell, six coherency reals),
-    without its locality.  Best of `reps` launches, HIP events."""
-    import torch
-    ncell = 256 ** 3
-    g = torch.Generator(device="cuda")
-    g.manual_seed(0)
-    t = torch.zeros(ncell, 8, dtype=torch.float64, device="cuda")
-    idx = torch.randint(0, ncell, (lines,), device="cuda", generator=g)
-    src = torch.rand(lines, 6, dtype=torch.float64, device="cuda", generator=g)
-    view = t[:, :6]
-    best = None
-    for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        view.index_add_(0, idx, src)
-        e1.record()
-        e1.synchronize()
-        ms = e0.elapsed_time(e1)
-        best = ms if best is None else min(best, ms)
-    del t, idx, src
-    return lines / (best * 1e-3)
+    """Random 64-byte-line FP64 atomics the device sustains, in lines/s: the
+    tally flush's own access pattern (lane L adds component L % 6 of block
+    L / 6, one wave covering 10 blocks) over uniformly random blocks of a
+    [256^3][8] FP64 array, in libkpcalib.so (csrc/kp_calib.hip); best of
+    `reps` launches, HIP events."""
+    import ctypes as C
+    path = os.path.join(ROOT, "paper_2512_01283_amd", "libkpcalib.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: run python -m paper_2512_01283_amd.build")
+    lib = C.CDLL(path)
+    lib.kpcal_atomic_lines.argtypes = [C.c_int, C.c_int64, C.c_int, C.c_int, C.POINTER(C.c_double)]
+    lib.kpcal_atomic_lines.restype = C.c_int
+    out = C.c_double()
+    st = lib.kpcal_atomic_lines(0, lines, 6, reps, C.byref(out))
+    if st != 0:
+        raise RuntimeError(f"kpcal_atomic_lines failed ({st})")
+    return float(out.value)
 
 
 def parse():
@@ -291,8 +284,9 @@ def main():
         "frac": lines / (avg_t * 1e-3) / cal, "lines_per_launch": lines,
         "lines_unit": "tally cell blocks flushed per transport launch (kp_stats.tally_flushes), "
                       "one 64-byte block of six FP64 each",
-        "calibration": "torch index_add_ of 2^24 rows of 6 FP64 at uniform random rows of a "
-                       "[256^3, 8] FP64 array, best of 3 (bench.py --atomic-calibration)"}
+        "calibration": "2^24 uniformly random 64-byte blocks of a [256^3][8] FP64 array, six FP64 "
+                       "atomics each in the flush's lane pattern, best of 3 (bench.py --atomic-calibration, "
+                       "csrc/kp_calib.hip)"}
     if not args.no_cpu_baseline:
         print("timing the oracle on a bounded sample ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample)

@@ -29,6 +29,20 @@ FLAGS = [
 ]
 
 
+CALIB_SOURCE = "kp_calib.hip"
+CALIB_LIB = os.path.join(HERE, "libkpcalib.so")
+
+
+def build_calib(verbose: bool = False) -> str:
+    """The device-calibration library that bench.py loads (not the method)."""
+    cmd = ["hipcc", *FLAGS, "-shared", "-x", "hip", os.path.join(CSRC, CALIB_SOURCE), "-o", CALIB_LIB + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(CALIB_LIB + ".tmp", CALIB_LIB)
+    return CALIB_LIB
+
+
 def build(verbose: bool = False, extra=()) -> str:
     objs = []
     tmp = os.path.join(HERE, "_build")
@@ -48,4 +62,6 @@ def build(verbose: bool = False, extra=()) -> str:
 
 if __name__ == "__main__":
     build(verbose="-v" in sys.argv)
+    build_calib(verbose="-v" in sys.argv)
     print(LIB)
+    print(CALIB_LIB)
