@@ -40,6 +40,36 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(P.kp_view) == 2 * 8 + 2 * 4 + 8
     assert ctypes.sizeof(P.kp_opts) == 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4 + 4 + 4 + 4 + 4 + 4 + 4
     assert P.TRACE_DTYPE.itemsize == 8 + 4 + 4 + 8 + 8 + 24 + 32 + 8 + 8
+    # kp_stats: 8 int64 counters, 7 energies and 2 times (double), packets, tally_flushes
+    assert ctypes.sizeof(P.kp_stats) == 8 * 8 + 9 * 8 + 2 * 8
+
+
+def test_stats_fields_follow_the_header_order():
+    import re
+    from paper_2512_01283_amd import polrad as P
+    txt = open(P.HEADER).read()
+    body = txt[txt.index("typedef struct {", txt.index("Counters of the last")):txt.index("} kp_stats;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"([a-z_0-9]+)\s*[,;]", body)
+    assert names == [k for k, _ in P.kp_stats._fields_]
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_calibration_library_exports_its_entry_point():
+    from paper_2512_01283_amd import build as B
+    if not os.path.exists(B.CALIB_LIB):
+        pytest.skip("libkpcalib.so not built")
+    lib = ctypes.CDLL(B.CALIB_LIB)
+    assert hasattr(lib, "kpcal_atomic_lines")
 
 
 def test_no_device_is_reported_cleanly():
