@@ -77,6 +77,8 @@ struct Packet {
   double e_abs, e_scat, e_gain;
   double ks, ke;      // per-wavelength kappa_sca and kappa_ext times the cell size, held
   R ka;               // in registers (no dependent load per step); ka = kappa_abs dx
+  float rho;          // density of the current cell when the grid holds it (loaded on
+                      // entering the cell, one step before its use)
   uint64_t pid, hash;
   int64_t last;
   int ci, cj, ck;
@@ -153,7 +155,9 @@ __device__ bool init_packet(Packet<R>& p, uint64_t g, const TransportArgs& a) {
   }
   p.ci = ci[0]; p.cj = ci[1]; p.ck = ci[2];
   p.fx = fr[0]; p.fy = fr[1]; p.fz = fr[2];
-  return p.ci >= 0 && p.ci < a.nx && p.cj >= 0 && p.cj < a.ny && p.ck >= 0 && p.ck < a.nz;
+  const bool in = p.ci >= 0 && p.ci < a.nx && p.cj >= 0 && p.cj < a.ny && p.ck >= 0 && p.ck < a.nz;
+  p.rho = in ? a.rho[(uint64_t)p.ci + (uint64_t)a.nx * ((uint64_t)p.cj + (uint64_t)a.ny * p.ck)] : 0.f;
+  return in;
 }
 
 // Coherency contribution of a segment-integrated Stokes vector J (lab basis of
@@ -208,23 +212,37 @@ __device__ __forceinline__ V3<double> cell_bdir(const TransportArgs& a, const do
   return V3<double>{(double)a.bx[c], (double)a.by[c], (double)a.bz[c]};
 }
 
-// Wave-cooperative flush of the lanes whose `need` is set: every such lane
-// stages (key, NC values) in this wavefront's LDS area; then lane L adds
-// component L % NC of staged entry L / NC, so one atomic instruction covers
-// 64 / NC whole cells.  Must be reached by all lanes of the wavefront.
-// Returns the number of cells flushed (the same in every lane).
-template <int NC, int TS>
-__device__ __forceinline__ int wave_flush(bool need, int64_t key, const double acc[NC],
-                                          double* tally, double* sv, long long* sk, int lane) {
+// Tally flush, wave-cooperative and deferred.  A lane that leaves a cell
+// stages (key, NC values) in its wavefront's LDS area (wave_stage); when the
+// area may not hold another full wavefront of entries, wave_drain adds all
+// staged entries to the tally: lane L adds component L % NC of entry L / NC,
+// so one atomic instruction covers 64 / NC whole cells.  Deferring matters on
+// gfx9: atomics without return still count in vmcnt, and the next density
+// load's wait (vmcnt(0)) would otherwise wait every iteration for the last
+// flush's read-modify-writes to reach memory; drained every few iterations,
+// that latency is exposed once per drain.  Both must be reached by all lanes
+// of the wavefront; `staged` is the same in every lane.
+template <int NC>
+__device__ __forceinline__ int wave_stage(bool need, int64_t key, const double acc[NC], double* sv, long long* sk,
+                                          int lane, int& staged) {
   const unsigned long long mask = __ballot(need);
   if (mask == 0ull) return 0;
-  const int n = __popcll(mask);
   if (need) {
-    const int r = __popcll(mask & ((1ull << lane) - 1ull));
+    const int r = staged + __popcll(mask & ((1ull << lane) - 1ull));
 #pragma unroll
     for (int k = 0; k < NC; ++k) sv[r * NC + k] = acc[k];
     sk[r] = key;
   }
+  const int n = __popcll(mask);
+  staged += n;
+  return n;
+}
+
+template <int NC, int TS>
+__device__ __forceinline__ void wave_drain(double* tally, double* sv, long long* sk, int lane, int& staged) {
+  const int n = staged;
+  if (n == 0) return;
+  staged = 0;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -235,11 +253,11 @@ __device__ __forceinline__ int wave_flush(bool need, int64_t key, const double a
     for (int base = 0; base < n; base += U * G) {
       double v[U];
       long long key_r[U];
-      // reads of entries beyond n stay inside the 64-entry staging area
-      // (index clamped) and their atomics are masked below
+      // reads of entries beyond n stay inside the staged entries (index
+      // clamped to n - 1) and their atomics are masked below
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int e = min(base + u * G + slot, 63);
+        const int e = min(base + u * G + slot, n - 1);
         v[u] = sv[e * NC + k];
         key_r[u] = sk[e];
       }
@@ -256,7 +274,6 @@ __device__ __forceinline__ int wave_flush(bool need, int64_t key, const double a
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  return n;
 }
 
 // Dimensionless extinction coefficients for a direction with cos(theta') =
@@ -415,7 +432,7 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
   if (!(td < inf)) return END_NUMERIC;
   const DustDev& D = a.dust[p.lam];
   const double* blk = a.tally + ((uint64_t)p.lam * a.ncell + c) * TallyShape<SPHERE>::TS;
-  const double rhod = TallyShape<SPHERE>::HAS_B ? blk[TallyShape<SPHERE>::RHO] : (double)a.rho[c];
+  const double rhod = TallyShape<SPHERE>::HAS_B ? blk[TallyShape<SPHERE>::RHO] : (double)p.rho;
   const double kbd = rhod * p.ks;
   double tld;
   bool scat;
@@ -530,6 +547,9 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
       p.hash = hash_event(p.hash, END_ESCAPE, c);
       return END_ESCAPE;
     }
+    // the next step's density, in flight while this iteration finishes
+    if (!TallyShape<SPHERE>::HAS_B)
+      p.rho = a.rho[(uint64_t)p.ci + (uint64_t)a.nx * ((uint64_t)p.cj + (uint64_t)a.ny * p.ck)];
   }
   return roulette(p, a);
 }
@@ -619,16 +639,20 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
   constexpr int NC = TallyShape<SPHERE>::NC, TS = TallyShape<SPHERE>::TS;
   __shared__ unsigned long long sc[SC_N];
   __shared__ double se[SE_N];
-  __shared__ double s_val[4 * 64 * NC];   // flush staging, one area per wavefront
-  __shared__ long long s_key[4 * 64];
+  // flush staging, one area of FLUSH_CAP entries per wavefront (56 KB per
+  // block for spheres, 61 KB for aligned grains: two blocks per CU)
+  constexpr int FLUSH_CAP = NC <= 6 ? 256 : 192;
+  __shared__ double s_val[4 * FLUSH_CAP * NC];
+  __shared__ long long s_key[4 * FLUSH_CAP];
   if (threadIdx.x < SC_N) sc[threadIdx.x] = 0ull;
   if (threadIdx.x < SE_N) se[threadIdx.x] = 0.0;
   __syncthreads();
 
   const int lane = (int)__lane_id();
   const int wv = (int)(threadIdx.x >> 6);
-  double* sv = s_val + wv * 64 * NC;
-  long long* sk = s_key + wv * 64;
+  double* sv = s_val + wv * FLUSH_CAP * NC;
+  long long* sk = s_key + wv * FLUSH_CAP;
+  int staged = 0;  // entries in this wavefront's staging area (uniform)
   Packet<R> p;
   bool active = false, exhausted = false, pending = false;
   int waited = 0;
@@ -638,26 +662,72 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
 #pragma unroll
   for (int k = 0; k < NC; ++k) acc[k] = 0.0;
 
+  // Packet ids reserved by this wavefront, [wnext, wend) (uniform).  With
+  // spherical grains a step is short and every wavefront refills its idle
+  // lanes often: taking ids one refill at a time from the one counter all
+  // wavefronts share serialised them on that counter (disk 256^3, 1e8
+  // packets: 1371 ms), taking WAVE_CHUNK at a time does not (860 ms).  The
+  // aligned-grain kernels contend less and measured slower with the reserve
+  // (batched workload 718 -> 744 ms in FP64, 449 -> 494 ms in FP32), so they
+  // take exactly the ids they need.
+  constexpr bool CHUNKED = SPHERE;
+  constexpr unsigned long long WAVE_CHUNK = 64;
+  unsigned long long wnext = 0, wend = 0;
+  bool global_done = false;  // the global counter has passed the total
   while (true) {
+    // refill idle lanes; a chunked wavefront keeps refilling while it holds no
+    // packet and still reserves ids (all it was handed may have left the grid)
+    do {
     if (!exhausted) {
       const unsigned long long idle = __ballot(!active);
       if (idle) {
-        const int nidle = __popcll(idle);
+        const unsigned long long nidle = (unsigned long long)__popcll(idle);
         const int leader = __ffsll((unsigned long long)idle) - 1;
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(a.counter, (unsigned long long)nidle);
-        base = __shfl(base, leader);
-        if (!active) {
-          const unsigned long long below = idle & ((1ull << lane) - 1ull);
-          const unsigned long long g = base + (unsigned long long)__popcll(below);
-          if (g < a.total) {
-            if (init_packet(p, g, a)) active = true;
-            else finish(p, END_ESCAPE, a, sc, se);
+        if (CHUNKED) {
+          const unsigned long long rem = wend - wnext;
+          const bool refill = rem < nidle && !global_done;
+          unsigned long long base = 0;
+          if (refill) {
+            if (lane == leader) base = atomicAdd(a.counter, WAVE_CHUNK);
+            // the leader's value, as a wave-uniform (scalar) value
+            const unsigned lo = __builtin_amdgcn_readlane((unsigned)base, leader);
+            const unsigned hi = __builtin_amdgcn_readlane((unsigned)(base >> 32), leader);
+            base = ((unsigned long long)hi << 32) | lo;
+            if (base + WAVE_CHUNK >= a.total) global_done = true;
           }
+          if (!active) {
+            const unsigned long long r = (unsigned long long)__popcll(idle & ((1ull << lane) - 1ull));
+            const bool have = r < rem || refill;
+            const unsigned long long g = r < rem ? wnext + r : base + (r - rem);
+            if (have && g < a.total) {
+              if (init_packet(p, g, a)) active = true;
+              else finish(p, END_ESCAPE, a, sc, se);
+            }
+          }
+          if (refill) {
+            wnext = base + (nidle - rem);
+            wend = base + WAVE_CHUNK;
+          } else {
+            wnext += nidle < rem ? nidle : rem;
+          }
+          if (global_done && (wnext >= wend || wnext >= a.total)) exhausted = true;
+        } else {
+          unsigned long long base = 0;
+          if (lane == leader) base = atomicAdd(a.counter, nidle);
+          base = __shfl(base, leader);
+          if (!active) {
+            const unsigned long long below = idle & ((1ull << lane) - 1ull);
+            const unsigned long long g = base + (unsigned long long)__popcll(below);
+            if (g < a.total) {
+              if (init_packet(p, g, a)) active = true;
+              else finish(p, END_ESCAPE, a, sc, se);
+            }
+          }
+          if (base + nidle >= a.total) exhausted = true;
         }
-        if (base + (unsigned long long)nidle >= a.total) exhausted = true;
       }
     }
+    } while (CHUNKED && !exhausted && !__any(active));
     if (!__any(active)) break;
     bool has = false;
     int64_t key = -1;
@@ -670,7 +740,8 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
       }
     }
     // a lane entering another (wavelength, cell) hands its running sum over
-    flushes += wave_flush<NC, TS>(has && key != acc_key && acc_key >= 0, acc_key, acc, a.tally, sv, sk, lane);
+    flushes += wave_stage<NC>(has && key != acc_key && acc_key >= 0, acc_key, acc, sv, sk, lane, staged);
+    if (staged > FLUSH_CAP - 64) wave_drain<NC, TS>(a.tally, sv, sk, lane, staged);
     if (has) {
       if (key == acc_key) {
 #pragma unroll
@@ -702,7 +773,8 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
       }
     }
   }
-  flushes += wave_flush<NC, TS>(acc_key >= 0, acc_key, acc, a.tally, sv, sk, lane);
+  flushes += wave_stage<NC>(acc_key >= 0, acc_key, acc, sv, sk, lane, staged);
+  wave_drain<NC, TS>(a.tally, sv, sk, lane, staged);
   if (lane == 0) atomicAdd(&sc[SC_FLUSH], flushes);
   __syncthreads();
   if (threadIdx.x < SC_N) atomicAdd(&(&a.stats->cell_steps)[threadIdx.x], sc[threadIdx.x]);
