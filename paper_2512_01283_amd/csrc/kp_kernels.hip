@@ -672,6 +672,8 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
   // take exactly the ids they need.
   constexpr bool CHUNKED = SPHERE;
   constexpr unsigned long long WAVE_CHUNK = 64;
+  // a refill hands up to 64 idle lanes ids from one new chunk
+  static_assert(WAVE_CHUNK >= 64, "a chunk must cover a whole wavefront");
   unsigned long long wnext = 0, wend = 0;
   bool global_done = false;  // the global counter has passed the total
   while (true) {
