@@ -69,6 +69,7 @@ struct Packet {
   // weight error -- so only the polarisation arithmetic runs in R.
   double fx, fy, fz;
   double nx, ny, nz;
+  double rnx, rny, rnz;  // 1 / n per axis (inf for a zero component), set with n
   double tau;
   R I, Q, U, V;       // Stokes vector in the lab basis of n
   R w0;               // initial weight
@@ -128,6 +129,7 @@ __device__ bool init_packet(Packet<R>& p, uint64_t g, const TransportArgs& a) {
     sincospi(2.0 * u1, &sp, &cp);
     p.nx = s * cp; p.ny = s * sp; p.nz = mu;
   }
+  p.rnx = 1.0 / p.nx; p.rny = 1.0 / p.ny; p.rnz = 1.0 / p.nz;
   p.tau = -log((double)next_uniform(p, a.seed));
   p.w0 = (R)a.dust[lo].w0;
   p.ks = a.dust[lo].ks_cell;
@@ -394,6 +396,7 @@ __device__ bool scatter(Packet<R>& p, const Quat<R>& q, const V3<double>& bdir,
     eta2(q, V3<R>{(R)md.x, (R)md.y, (R)md.z}, V3<R>{(R)mgd.x, (R)mgd.y, (R)mgd.z}, cm, sm);
   }
   p.nx = md.x; p.ny = md.y; p.nz = md.z;
+  p.rnx = 1.0 / p.nx; p.rny = 1.0 / p.ny; p.rnz = 1.0 / p.nz;
   p.e_scat += (double)(sig - I);
   p.I = So;
   p.Q = cm * Qo - sm * Uo;
@@ -422,9 +425,10 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
   }
   const double inf = __builtin_huge_val();
   const double dnx = p.nx, dny = p.ny, dnz = p.nz;
-  double tx = dnx > 0.0 ? (1.0 - p.fx) / dnx : (dnx < 0.0 ? -p.fx / dnx : inf);
-  double ty = dny > 0.0 ? (1.0 - p.fy) / dny : (dny < 0.0 ? -p.fy / dny : inf);
-  double tz = dnz > 0.0 ? (1.0 - p.fz) / dnz : (dnz < 0.0 ? -p.fz / dnz : inf);
+  // distances to the exit faces (reciprocals of n formed when n changes)
+  double tx = dnx > 0.0 ? (1.0 - p.fx) * p.rnx : (dnx < 0.0 ? -p.fx * p.rnx : inf);
+  double ty = dny > 0.0 ? (1.0 - p.fy) * p.rny : (dny < 0.0 ? -p.fy * p.rny : inf);
+  double tz = dnz > 0.0 ? (1.0 - p.fz) * p.rnz : (dnz < 0.0 ? -p.fz * p.rnz : inf);
   double td = tx;
   int axis = 0;
   if (ty < td) { td = ty; axis = 1; }
