@@ -43,7 +43,17 @@
  *
  * Maps are FP64 device arrays [batch][4][height][width] (I, Q, U, V), the
  * layout of kp_get_images_device for one wavelength's views, so images of a
- * run can be passed straight in.  height and width must be multiples of
+ * run can be passed straight in.
+ *
+ * Two-run inputs (kp_dn_create_runs with runs = 2): an input image is two
+ * independent runs A and B of the same scene with the same packet count,
+ * [batch][8][height][width] (A's I, Q, U, V, then B's).  (I, Q, U, V) above
+ * are then the two runs' mean -- the map of one run with both runs' packets
+ * -- and four more features follow, |S_A - S_B| / (2 I) for S = I, Q, U, V
+ * (clamped to [0, 1], 0 where I <= 0): a per-pixel sample of the mean's
+ * Monte Carlo noise, which one map alone does not carry.  The first
+ * convolution then has cin = 8; the output (kp_dn_infer) and the training
+ * targets (kp_dn_backward) stay [batch][4][height][width].  height and width must be multiples of
  * 2^(L-1) (L-1 pooling levels); batch * height * width <= 2^24.
  *
  * Errors follow polrad.h: every call returns kp_status, arguments are
@@ -69,6 +79,9 @@ typedef struct kp_dn kp_dn;
  * parameters zero.  *out receives an owned handle (release with
  * kp_dn_destroy). */
 kp_status kp_dn_create(int device, const int32_t *widths, int32_t n_levels, kp_dn **out);
+/* As kp_dn_create for inputs of `runs` (1 or 2) independent runs per image
+ * (see two-run inputs above); kp_dn_create is runs = 1. */
+kp_status kp_dn_create_runs(int device, const int32_t *widths, int32_t n_levels, int32_t runs, kp_dn **out);
 void kp_dn_destroy(kp_dn *dn);
 const char *kp_dn_last_error(const kp_dn *dn);
 
@@ -86,12 +99,14 @@ kp_status kp_dn_get_grads(kp_dn *dn, float *host_grads, size_t n);
 kp_status kp_dn_get_adam(kp_dn *dn, float *host_m, float *host_v, size_t n, int32_t *step);
 kp_status kp_dn_set_adam(kp_dn *dn, const float *host_m, const float *host_v, size_t n, int32_t step);
 
-/* Denoise: d_maps (device, read) -> d_out (device, written; may not alias
- * d_maps).  Asynchronous on hip_stream. */
+/* Denoise: d_maps (device, read; [batch][4 runs][height][width]) -> d_out
+ * (device, written, [batch][4][height][width]; may not alias d_maps).
+ * Asynchronous on hip_stream. */
 kp_status kp_dn_infer(kp_dn *dn, const double *d_maps, double *d_out, int32_t batch, int32_t height,
                       int32_t width, void *hip_stream);
 
-/* Loss and gradients for the pairs (d_low[b], d_high[b]) (device maps).
+/* Loss and gradients for the pairs (d_low[b], d_high[b]) (device maps;
+ * d_low [batch][4 runs][height][width], d_high [batch][4][height][width]).
  * host_aug (NULL = identity) holds one code per image, 0..7, of the
  * dihedral transform applied to both maps of a pair before the network:
  * code a = r + 4 f mirrors the width axis when f = 1, then rotates the image

@@ -11,6 +11,10 @@ Per image with maps (I, Q, U, V) and s = mean of I over the image:
   Ihat  = I / s
   x     = (ln max(Ihat, 1e-6), Q/I, U/I, V/I)   [N, H, W, 4]
           (fractions clipped to [-1, 1], their physical range; 0 where I <= 0)
+With two independent runs A and B of an image ([N, 8, H, W]: A's I, Q, U, V,
+then B's), (I, Q, U, V) above are the runs' mean and four more features
+follow: |S_A - S_B| / (2 I) for S = I, Q, U, V (clipped to 1; 0 where
+I <= 0), so x is [N, H, W, 8] and the first convolution has 8 inputs.
 The network: a U-Net of L levels with widths c1..cL (two 3x3 convolutions
 + relu per block; for L = 3):
   enc1  = relu(conv3(relu(conv3(x,  4->c1)), c1->c1))          H x W
@@ -64,14 +68,14 @@ def layer_shapes(widths=WIDTHS, cin=4):
     return shapes
 
 
-def n_params(widths=WIDTHS) -> int:
-    return int(sum(np.prod(s) for s in layer_shapes(widths).values()))
+def n_params(widths=WIDTHS, cin=4) -> int:
+    return int(sum(np.prod(s) for s in layer_shapes(widths, cin).values()))
 
 
-def unflatten(flat, widths=WIDTHS):
+def unflatten(flat, widths=WIDTHS, cin=4):
     """Parameters from one flat array in the order of layer_shapes()."""
     out, o = {}, 0
-    for k, s in layer_shapes(widths).items():
+    for k, s in layer_shapes(widths, cin).items():
         n = int(np.prod(s))
         out[k] = np.asarray(flat[o:o + n], dtype=np.float64).reshape(s)
         o += n
@@ -163,7 +167,18 @@ def forward(p, x):
 
 
 def features(maps):
-    """[N, 4, H, W] Stokes maps -> (x [N,H,W,4], Ihat [N,H,W], s [N])."""
+    """[N, 4, H, W] Stokes maps -> (x [N,H,W,4], Ihat [N,H,W], s [N]);
+    [N, 8, H, W] two-run maps -> (x [N,H,W,8], Ihat, s) of their mean."""
+    if maps.shape[1] == 8:
+        mean = 0.5 * (maps[:, :4] + maps[:, 4:])
+        x, Ihat, s = features(mean)
+        I = mean[:, 0]
+        pos = I > 0
+        Id = np.where(pos, I, 1.0)
+        with np.errstate(over="ignore"):
+            noise = [np.where(pos, np.minimum(0.5 * np.abs(maps[:, k] - maps[:, 4 + k]) / Id, 1.0), 0.0)
+                     for k in range(4)]
+        return np.concatenate([x, np.stack(noise, axis=-1)], axis=-1), Ihat, s
     I, Q, U, V = (maps[:, k] for k in range(4))
     s = I.mean(axis=(1, 2))
     sd = np.where(s > 0, s, 1.0)

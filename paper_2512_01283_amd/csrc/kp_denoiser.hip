@@ -588,12 +588,13 @@ __global__ void k_pool_bwd_add(const uint16_t* __restrict__ a, int as, const uin
 // ---------------------------------------------------------------------------
 // sums[2b] += sum of I, sums[2b+1] += sum of I^2 over image b of maps [B][4][H*W]
 // (256-thread blocks; one pair of atomics per block)
-__global__ void k_sums(const double* __restrict__ maps, int HW, double* __restrict__ sums) {
+__global__ void k_sums(const double* __restrict__ maps, int HW, int runs, double* __restrict__ sums) {
   __shared__ double red[2][4];
   const int b = blockIdx.y;
   double a1 = 0.0, a2 = 0.0;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < HW; p += gridDim.x * blockDim.x) {
-    const double I = maps[(size_t)b * 4 * HW + p];
+    const double* m = maps + (size_t)b * 4 * runs * HW + p;
+    const double I = runs == 2 ? 0.5 * (m[0] + m[4 * (size_t)HW]) : m[0];
     a1 += I;
     a2 += I * I;
   }
@@ -615,13 +616,18 @@ __global__ void k_sums(const double* __restrict__ maps, int HW, double* __restri
 //   x[p][0..7] = ln max(Ihat, 1e-6), Q/I, U/I, V/I (0 where I <= 0), 0, 0, 0, 0 (BF16)
 //   xq[p] = (Q/I, U/I) and ihat[p] = Ihat in FP32; tgt[p] = (Q, U) of the
 //   target maps / s (FP32).
+// With runs == 2 an input image is two independent runs A and B ([8][H][W]:
+// A's I, Q, U, V, then B's); (I, Q, U, V) above are then their mean, and
+// x[p][4..7] = |S_A - S_B| / (2 I) for S = I, Q, U, V (clamped to 1, 0 where
+// I <= 0): a one-sample estimate of the mean's per-pixel noise, unchanged by
+// swapping the runs and by the dihedral transforms' signs.
 // With aug, image b is first transformed by the dihedral element aug[b] =
 // r + 4 f: mirror the width axis if f, then r quarter turns (output pixel
 // (h, w) of one turn reads (w, W - 1 - h)); Stokes (Q, U, V) ->
 // ((-1)^r Q, (-1)^(r+f) U, (-1)^f V).  Odd r requires H == W.
 __global__ void k_prep(const double* __restrict__ maps, const double* __restrict__ target,
                        const double* __restrict__ sums, const int32_t* __restrict__ aug, int B, int H, int W,
-                       uint16_t* __restrict__ x, float* __restrict__ xq, float* __restrict__ ihat,
+                       int runs, uint16_t* __restrict__ x, float* __restrict__ xq, float* __restrict__ ihat,
                        float* __restrict__ tgt) {
   const int HW = H * W;
   const size_t n = (size_t)B * HW;
@@ -643,8 +649,10 @@ __global__ void k_prep(const double* __restrict__ maps, const double* __restrict
     }
     const size_t p = (size_t)h * W + w;
     const double mean = sums[2 * b] / HW;
-    const double* m = maps + b * 4 * HW + p;
-    const double I = m[0];
+    const double* m = maps + b * 4 * runs * HW + p;
+    const size_t rb = 4 * (size_t)HW;  // run B's maps (runs == 2)
+    auto stokes = [&](int c) { return runs == 2 ? 0.5 * (m[c * (size_t)HW] + m[rb + c * (size_t)HW]) : m[c * (size_t)HW]; };
+    const double I = stokes(0);
     const double Ih = mean > 0.0 ? I / mean : 0.0;
     // ratios by division (in the wings of a thick disk I can be subnormal,
     // where 1 / I overflows), clamped to [-1, 1], the range of a physical
@@ -653,11 +661,12 @@ __global__ void k_prep(const double* __restrict__ maps, const double* __restrict
     auto frac = [&](double x) { return pos ? (float)fmin(1.0, fmax(-1.0, x / I)) : 0.f; };
     float f8[8];
     f8[0] = (float)log(fmax(Ih, 1e-6));
-    f8[1] = (float)sq * frac(m[HW]);
-    f8[2] = (float)su * frac(m[2 * (size_t)HW]);
-    f8[3] = (float)sv * frac(m[3 * (size_t)HW]);
+    f8[1] = (float)sq * frac(stokes(1));
+    f8[2] = (float)su * frac(stokes(2));
+    f8[3] = (float)sv * frac(stokes(3));
 #pragma unroll
-    for (int c = 4; c < 8; ++c) f8[c] = 0.f;
+    for (int c = 0; c < 4; ++c)
+      f8[4 + c] = runs == 2 ? frac(0.5 * fabs(m[c * (size_t)HW] - m[rb + c * (size_t)HW])) : 0.f;
     st16(x + k * 8, pack8(f8));
     xq[2 * k] = f8[1];
     xq[2 * k + 1] = f8[2];
@@ -774,19 +783,21 @@ __global__ void k_head_bwd(const float* __restrict__ go, const uint16_t* __restr
   if (tid < 2) atomicAdd(ghb + tid, red[2 * C + tid]);
 }
 
-// denoised maps: I and V from the input, Q = q' I and U = u' I
-__global__ void k_output(const double* __restrict__ maps, const float* __restrict__ out, int B, int HW,
+// denoised maps: I and V from the input (the two runs' mean if runs == 2),
+// Q = q' I and U = u' I
+__global__ void k_output(const double* __restrict__ maps, const float* __restrict__ out, int B, int HW, int runs,
                          double* __restrict__ dst) {
   const size_t n = (size_t)B * HW;
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
     const size_t b = k / HW, p = k % HW;
-    const double* m = maps + b * 4 * HW + p;
+    const double* m = maps + b * 4 * runs * HW + p;
     double* o = dst + b * 4 * HW + p;
-    const double I = m[0];
+    const size_t rb = 4 * (size_t)HW;
+    const double I = runs == 2 ? 0.5 * (m[0] + m[rb]) : m[0];
     o[0] = I;
     o[HW] = (double)out[2 * k] * I;
     o[2 * (size_t)HW] = (double)out[2 * k + 1] * I;
-    o[3 * (size_t)HW] = m[3 * (size_t)HW];
+    o[3 * (size_t)HW] = runs == 2 ? 0.5 * (m[3 * (size_t)HW] + m[rb + 3 * (size_t)HW]) : m[3 * (size_t)HW];
   }
 }
 
@@ -909,13 +920,13 @@ void pool_bwd_add(const uint16_t* a, int as, const uint16_t* g, int gs, const ui
   hipLaunchKernelGGL(k_pool_bwd_add, dim3(grid_for((size_t)B * H * W * C / 8)), dim3(256), 0, s, a, as, g, gs, mask,
                      ms, dst, ds, B, H, W, C);
 }
-void sums(const double* maps, int B, int HW, double* sum, hipStream_t s) {
-  hipLaunchKernelGGL(k_sums, dim3(grid_for(HW, 32), B), dim3(256), 0, s, maps, HW, sum);
+void sums(const double* maps, int B, int HW, int runs, double* sum, hipStream_t s) {
+  hipLaunchKernelGGL(k_sums, dim3(grid_for(HW, 32), B), dim3(256), 0, s, maps, HW, runs, sum);
 }
 void prep(const double* maps, const double* target, const double* sum, const int32_t* aug, int B, int H, int W,
-          uint16_t* x, float* xq, float* ihat, float* tgt, hipStream_t s) {
-  hipLaunchKernelGGL(k_prep, dim3(grid_for((size_t)B * H * W)), dim3(256), 0, s, maps, target, sum, aug, B, H, W, x,
-                     xq, ihat, tgt);
+          int runs, uint16_t* x, float* xq, float* ihat, float* tgt, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep, dim3(grid_for((size_t)B * H * W)), dim3(256), 0, s, maps, target, sum, aug, B, H, W,
+                     runs, x, xq, ihat, tgt);
 }
 void head(const uint16_t* d, int C, const float* hw, const float* hb, const float* xq, float* out, size_t P,
           hipStream_t s) {
@@ -931,8 +942,8 @@ void head_bwd(const float* go, const uint16_t* d, int C, const float* hw, float*
   hipLaunchKernelGGL(k_head_bwd, dim3((unsigned)((P + HB_CHUNK - 1) / HB_CHUNK)), dim3(256), 0, s, go, d, C, hw, ghw,
                      ghb, gd, P);
 }
-void output(const double* maps, const float* out, int B, int HW, double* dst, hipStream_t s) {
-  hipLaunchKernelGGL(k_output, dim3(grid_for((size_t)B * HW)), dim3(256), 0, s, maps, out, B, HW, dst);
+void output(const double* maps, const float* out, int B, int HW, int runs, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_output, dim3(grid_for((size_t)B * HW)), dim3(256), 0, s, maps, out, B, HW, runs, dst);
 }
 void adam(float* p, const float* g, float* m, float* v, size_t n, float lr, int t, hipStream_t s) {
   const double b1 = 0.9, b2 = 0.999;

@@ -63,6 +63,7 @@ struct kp_dn {
   int device = 0;
   std::string err;
   int L = 0;
+  int runs = 1;  // independent Monte Carlo runs per input image (1 or 2)
   int c[MAX_LEVELS] = {};
   std::vector<Layer> layers;
   size_t head_w = 0, head_b = 0, n_params = 0;
@@ -296,8 +297,8 @@ kp_status forward(kp_dn* dn, const double* maps, const double* target, int B, in
   auto Hl = [&](int l) { return H >> l; };
   auto Wl = [&](int l) { return W >> l; };
   zero(w.sum, (size_t)B * 16, s);
-  sums(maps, B, H * W, w.sum, s);
-  prep(maps, target, w.sum, use_aug ? w.aug : nullptr, B, H, W, w.x0, w.xq, w.ihat, w.tgt, s);
+  sums(maps, B, H * W, dn->runs, w.sum, s);
+  prep(maps, target, w.sum, use_aug ? w.aug : nullptr, B, H, W, dn->runs, w.x0, w.xq, w.ihat, w.tgt, s);
   // encoder
   for (int l = 0; l < L - 1; ++l) {
     const uint16_t* in = l == 0 ? w.x0 : w.pool[l];
@@ -380,9 +381,13 @@ kp_status check_n(kp_dn* dn, size_t n) {
 extern "C" {
 
 kp_status kp_dn_create(int device, const int32_t* widths, int32_t n_levels, kp_dn** out) {
+  return kp_dn_create_runs(device, widths, n_levels, 1, out);
+}
+
+kp_status kp_dn_create_runs(int device, const int32_t* widths, int32_t n_levels, int32_t runs, kp_dn** out) {
   if (!out) return KP_ERR_ARG;
   *out = nullptr;
-  if (!widths || n_levels < 2 || n_levels > MAX_LEVELS) return KP_ERR_ARG;
+  if (!widths || n_levels < 2 || n_levels > MAX_LEVELS || (runs != 1 && runs != 2)) return KP_ERR_ARG;
   for (int l = 0; l < n_levels; ++l)
     if (widths[l] < 16 || widths[l] > 512 || widths[l] % 16) return KP_ERR_ARG;
   int ndev = 0;
@@ -391,13 +396,14 @@ kp_status kp_dn_create(int device, const int32_t* widths, int32_t n_levels, kp_d
   if (!dn) return KP_ERR_OOM;
   dn->device = device;
   dn->L = n_levels;
+  dn->runs = runs;
   for (int l = 0; l < n_levels; ++l) dn->c[l] = widths[l];
   const int L = n_levels;
   const int* c = dn->c;
   // (cin, cout) in parameter order: encoder blocks, bottleneck, decoder blocks
   std::vector<std::pair<int, int>> io;
   for (int l = 0; l < L - 1; ++l) {
-    io.push_back({l == 0 ? 4 : c[l - 1], c[l]});
+    io.push_back({l == 0 ? 4 * runs : c[l - 1], c[l]});
     io.push_back({c[l], c[l]});
   }
   io.push_back({c[L - 2], c[L - 1]});
@@ -550,7 +556,7 @@ kp_status kp_dn_infer(kp_dn* dn, const double* d_maps, double* d_out, int32_t B,
   dn->ev_total0 = mark_begin(dn, s);
   if (kp_status st = ensure_packed(dn, s)) return st;
   if (kp_status st = forward(dn, d_maps, nullptr, B, H, W, false, s)) return st;
-  output(d_maps, dn->w.out, B, H * W, d_out, s);
+  output(d_maps, dn->w.out, B, H * W, dn->runs, d_out, s);
   DN_HIP(hipGetLastError(), "output launch");
   if (dn->ev_total0 >= 0) {
     dn->ev_total1 = dn->ev_total0 + 1;

@@ -29,6 +29,7 @@ class kp_dn_timing(C.Structure):
 _Pv = C.c_void_p
 _SIGS = {
     "kp_dn_create": ([C.c_int, _Pv, C.c_int32, C.POINTER(_Pv)], C.c_int),
+    "kp_dn_create_runs": ([C.c_int, _Pv, C.c_int32, C.c_int32, C.POINTER(_Pv)], C.c_int),
     "kp_dn_destroy": ([_Pv], None),
     "kp_dn_last_error": ([_Pv], C.c_char_p),
     "kp_dn_num_params": ([_Pv, C.POINTER(C.c_size_t)], C.c_int),
@@ -78,6 +79,15 @@ def kp_dn_create(device=0, widths=WIDTHS):
     return h
 
 
+def kp_dn_create_runs(device=0, widths=WIDTHS, runs=1):
+    h = _Pv()
+    w = np.ascontiguousarray(widths, dtype=np.int32)
+    st = _lib.kp_dn_create_runs(int(device), w.ctypes.data, int(w.size), int(runs), C.byref(h))
+    if st != P.KP_OK:
+        raise P.KpError(st, f"kp_dn_create_runs(device={device}, widths={tuple(widths)}, runs={runs}) failed")
+    return h
+
+
 def kp_dn_destroy(h):
     _lib.kp_dn_destroy(h)
 
@@ -122,11 +132,20 @@ def kp_dn_set_adam(h, m, v, step):
     _check(h, _lib.kp_dn_set_adam(h, m.ctypes.data, v.ctypes.data, n, int(step)))
 
 
-def _maps_args(t):
+def _maps_args(t, channels=4):
     import torch
-    if t.dtype != torch.float64 or not t.is_cuda or t.dim() != 4 or t.shape[1] != 4 or not t.is_contiguous():
-        raise ValueError("maps must be contiguous float64 CUDA tensors [batch, 4, height, width]")
+    if (t.dtype != torch.float64 or not t.is_cuda or t.dim() != 4 or t.shape[1] != channels
+            or not t.is_contiguous()):
+        raise ValueError(f"maps must be contiguous float64 CUDA tensors [batch, {channels}, height, width]")
     return int(t.shape[0]), int(t.shape[2]), int(t.shape[3])
+
+
+def _pair_args(low, high, runs):
+    b, hh, ww = _maps_args(low, 4 * runs)
+    if tuple(high.shape) != (b, 4, hh, ww):
+        raise ValueError(f"high must be [batch, 4, height, width] = {(b, 4, hh, ww)}")
+    _maps_args(high)
+    return b, hh, ww
 
 
 def _aug_arg(aug, b):
@@ -138,17 +157,16 @@ def _aug_arg(aug, b):
     return a, C.c_void_p(a.ctypes.data)
 
 
-def kp_dn_infer(h, maps, out, stream=None):
-    b, hh, ww = _maps_args(maps)
-    if tuple(out.shape) != tuple(maps.shape):
-        raise ValueError("out must have the shape of maps")
+def kp_dn_infer(h, maps, out, stream=None, runs=1):
+    b, hh, ww = _maps_args(maps, 4 * runs)
+    _maps_args(out)
+    if tuple(out.shape) != (b, 4, hh, ww):
+        raise ValueError(f"out must be [batch, 4, height, width] = {(b, 4, hh, ww)}")
     _check(h, _lib.kp_dn_infer(h, P._ptr(maps), P._ptr(out), b, hh, ww, P._stream_ptr(stream)))
 
 
-def kp_dn_backward(h, low, high, aug=None, stream=None) -> float:
-    b, hh, ww = _maps_args(low)
-    if tuple(high.shape) != tuple(low.shape):
-        raise ValueError("high must have the shape of low")
+def kp_dn_backward(h, low, high, aug=None, stream=None, runs=1) -> float:
+    b, hh, ww = _pair_args(low, high, runs)
     keep, ap = _aug_arg(aug, b)
     loss = C.c_double()
     _check(h, _lib.kp_dn_backward(h, P._ptr(low), P._ptr(high), b, hh, ww, ap, C.byref(loss),
@@ -161,10 +179,8 @@ def kp_dn_adam_step(h, lr, stream=None):
     _check(h, _lib.kp_dn_adam_step(h, float(lr), P._stream_ptr(stream)))
 
 
-def kp_dn_train_step(h, low, high, lr, aug=None, stream=None) -> float:
-    b, hh, ww = _maps_args(low)
-    if tuple(high.shape) != tuple(low.shape):
-        raise ValueError("high must have the shape of low")
+def kp_dn_train_step(h, low, high, lr, aug=None, stream=None, runs=1) -> float:
+    b, hh, ww = _pair_args(low, high, runs)
     keep, ap = _aug_arg(aug, b)
     loss = C.c_double()
     _check(h, _lib.kp_dn_train_step(h, P._ptr(low), P._ptr(high), b, hh, ww, ap, float(lr),
@@ -186,9 +202,10 @@ class Denoiser:
     """Owns one kp_dn handle.  Parameters are FP32 master weights on the
     device; ``params``/``grads`` return host copies in the flat layout."""
 
-    def __init__(self, device=0, widths=WIDTHS, params=None):
+    def __init__(self, device=0, widths=WIDTHS, params=None, runs=1):
         self.widths = tuple(int(c) for c in widths)
-        self.h = kp_dn_create(device, self.widths)
+        self.runs = int(runs)
+        self.h = kp_dn_create_runs(device, self.widths, self.runs)
         self.n = kp_dn_num_params(self.h)
         if params is not None:
             self.set_params(params)
@@ -222,18 +239,18 @@ class Denoiser:
     def infer(self, maps, out=None, stream=None):
         import torch
         if out is None:
-            out = torch.empty_like(maps)
-        kp_dn_infer(self.h, maps, out, stream)
+            out = torch.empty((maps.shape[0], 4) + tuple(maps.shape[2:]), dtype=maps.dtype, device=maps.device)
+        kp_dn_infer(self.h, maps, out, stream, self.runs)
         return out
 
     def backward(self, low, high, aug=None, stream=None):
-        return kp_dn_backward(self.h, low, high, aug, stream)
+        return kp_dn_backward(self.h, low, high, aug, stream, self.runs)
 
     def adam_step(self, lr, stream=None):
         kp_dn_adam_step(self.h, lr, stream)
 
     def train_step(self, low, high, lr, aug=None, stream=None):
-        return kp_dn_train_step(self.h, low, high, lr, aug, stream)
+        return kp_dn_train_step(self.h, low, high, lr, aug, stream, self.runs)
 
     def timing(self):
         return kp_dn_get_timing(self.h)

@@ -59,10 +59,21 @@ def run_images(ctx, packets, seed):
     return ctx.images_device()[0].clone()
 
 
-def make_pairs(seeds, n_lo, n_hi, n=256, npix=None, log=print):
-    """Returns (lo, hi) CUDA tensors [len(seeds) * 8 * len(n_lo), 4, H, W].
-    n_lo is one input packet count or a sequence of them: each disk then
-    gives one input per count, all paired with the same target run."""
+def run_input(ctx, packets, seed, runs=1):
+    """Denoiser input of `packets` packets: one run [views, 4, H, W], or with
+    runs = 2 two independent runs of packets / 2 each, [views, 8, H, W]."""
+    import torch
+    if runs == 1:
+        return run_images(ctx, packets, seed)
+    half = packets / 2
+    return torch.cat([run_images(ctx, half, seed), run_images(ctx, half, seed + 500009)], dim=1)
+
+
+def make_pairs(seeds, n_lo, n_hi, n=256, npix=None, log=print, runs=1):
+    """Returns (lo, hi) CUDA tensors [len(seeds) * 8 * len(n_lo), 4 runs, H, W]
+    and [..., 4, H, W].  n_lo is one input packet count or a sequence of
+    them: each disk then gives one input per count, all paired with the same
+    target run."""
     import torch
     counts = [n_lo] if np.isscalar(n_lo) else list(n_lo)
     los, his = [], []
@@ -72,7 +83,7 @@ def make_pairs(seeds, n_lo, n_hi, n=256, npix=None, log=print):
             ctx.load(cfg)
             hi = run_images(ctx, n_hi, 2 * s + 2)
             for j, c in enumerate(counts):
-                los.append(run_images(ctx, c, 2 * s + 1 + 1000003 * j))
+                los.append(run_input(ctx, c, 2 * s + 1 + 1000003 * j, runs))
                 his.append(hi)
         if log and (k + 1) % 8 == 0:
             log(f"  pairs: {k + 1}/{len(seeds)} disks, {time.time() - t0:.1f} s", flush=True)
@@ -121,7 +132,9 @@ def train(dn, lo, hi, steps, batch=8, lr=1e-3, lr_min=1e-5, seed=0, aug=True, lo
 
 def evaluate(dn, seeds, plain_counts=(1e6, 3e6, 1e7, 3e7), den_counts=(1e5, 3e5, 1e6, 3e6),
              ref_half=1.5e8, n=256, npix=None, log=print):
-    """Packets-to-fixed-error comparison of plain and denoised maps."""
+    """Packets-to-fixed-error comparison of plain and denoised maps.  A
+    two-run denoiser gets each count as two runs of half the packets; its
+    "input" error is that of their mean, the plain map of that count."""
     import torch
     Ep = {c: [] for c in plain_counts}
     Ed = {c: [] for c in den_counts}
@@ -138,8 +151,8 @@ def evaluate(dn, seeds, plain_counts=(1e6, 3e6, 1e7, 3e7), den_counts=(1e5, 3e5,
             for k, c in enumerate(plain_counts):
                 Ep[c] += image_error(run_images(ctx, c, 10 * s + 3 + k), ref).tolist()
             for k, c in enumerate(den_counts):
-                m = run_images(ctx, c, 100 * s + 7 + k)
-                Ein[c] += image_error(m, ref).tolist()
+                m = run_input(ctx, c, 100 * s + 7 + k, dn.runs)
+                Ein[c] += image_error(0.5 * (m[:, :4] + m[:, 4:]) if dn.runs == 2 else m, ref).tolist()
                 Ed[c] += image_error(dn.infer(m), ref).tolist()
         torch.cuda.synchronize()
         if log:
@@ -193,6 +206,8 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--ref-half", type=float, default=1.5e8)
     ap.add_argument("--widths", default="48,96,192", help="channel widths, one per U-Net level")
+    ap.add_argument("--runs", type=int, default=1, choices=(1, 2),
+                    help="2: inputs are two independent runs of half the packets each")
     ap.add_argument("--init", default=None, help="start from saved parameters (.npy)")
     ap.add_argument("--skip-eval", action="store_true")
     a = ap.parse_args(argv)
@@ -206,11 +221,11 @@ def main(argv=None):
     t0 = time.time()
     log(f"generating training pairs on {torch.cuda.get_device_name(0)}", flush=True)
     n_lo = [float(v) for v in str(a.n_lo).split(",")]
-    lo, hi = make_pairs(seeds(a.train_seeds), n_lo, a.n_hi, n=a.grid, npix=a.npix, log=log)
+    lo, hi = make_pairs(seeds(a.train_seeds), n_lo, a.n_hi, n=a.grid, npix=a.npix, log=log, runs=a.runs)
     t_gen = time.time() - t0
     widths = tuple(int(v) for v in a.widths.split(","))
-    dn = DN.Denoiser(0, widths=widths)
-    init = np.load(a.init) if a.init else W.denoiser_params(0, widths=widths)
+    dn = DN.Denoiser(0, widths=widths, runs=a.runs)
+    init = np.load(a.init) if a.init else W.denoiser_params(0, widths=widths, cin=4 * a.runs)
     dn.set_params(init)
     t1 = time.time()
     hist = train(dn, lo, hi, a.steps, batch=a.batch, lr=a.lr, log=log)
@@ -218,7 +233,7 @@ def main(argv=None):
     t_train = time.time() - t1
     del lo, hi
     np.save(os.path.join(a.out, "params.npy"), dn.params())
-    res = dict(widths=list(widths), params=dn.n, train_seeds=a.train_seeds, n_lo=n_lo, n_hi=a.n_hi,
+    res = dict(widths=list(widths), runs=a.runs, params=dn.n, train_seeds=a.train_seeds, n_lo=n_lo, n_hi=a.n_hi,
                steps=a.steps, batch=a.batch,
                lr=a.lr, t_generate_s=t_gen, t_train_s=t_train,
                loss_first=hist[0][1], loss_last=float(np.mean([l for _, l in hist[-50:]])))

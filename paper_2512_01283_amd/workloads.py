@@ -260,43 +260,48 @@ def denoiser_layer_io(widths=DN_WIDTHS, cin=4):
     return io
 
 
-def denoiser_params(seed=0, widths=DN_WIDTHS, bias_std=0.0, head_std=0.0) -> np.ndarray:
+def denoiser_params(seed=0, widths=DN_WIDTHS, bias_std=0.0, head_std=0.0, cin=4) -> np.ndarray:
     """Flat FP32 parameter vector: He-normal 3x3 weights [cout][3][3][cin]
     (std sqrt(2 / (9 cin))) and N(0, bias_std) biases for each convolution,
     then the head [2][c1] ~ N(0, head_std) and its bias N(0, bias_std).  With
-    head_std = 0 the untrained network is the identity on Q and U."""
+    head_std = 0 the untrained network is the identity on Q and U.  cin is
+    the number of input features (8 for two-run inputs)."""
     rng = np.random.default_rng(seed)
     parts = []
-    for cin, cout in denoiser_layer_io(widths):
-        parts.append(rng.standard_normal(cout * 9 * cin) * math.sqrt(2.0 / (9 * cin)))
+    for ci, cout in denoiser_layer_io(widths, cin):
+        parts.append(rng.standard_normal(cout * 9 * ci) * math.sqrt(2.0 / (9 * ci)))
         parts.append(rng.standard_normal(cout) * bias_std)
     parts.append(rng.standard_normal(2 * widths[0]) * head_std)
     parts.append(rng.standard_normal(2) * bias_std)
     return np.concatenate(parts).astype(np.float32)
 
 
-def synthetic_stokes_maps(seed, batch, height, width, p_max=0.3, noise=0.1) -> np.ndarray:
+def synthetic_stokes_maps(seed, batch, height, width, p_max=0.3, noise=0.1, runs=1) -> np.ndarray:
     """[batch, 4, height, width] FP64 Stokes maps with the structure of a
     scattered-light image: I a smooth positive blob plus a floor, a
     polarization fraction up to p_max with a smoothly varying angle, V small,
     and multiplicative noise of relative size `noise`; I is raised where the
-    noise would leave I < |(Q, U, V)|."""
+    noise would leave I < |(Q, U, V)|.  With runs = 2: [batch, 8, height,
+    width], two realisations of each scene with independent noise (the
+    first run's four maps, then the second's)."""
     rng = np.random.default_rng(seed)
     yy, xx = np.meshgrid(np.linspace(-1, 1, height), np.linspace(-1, 1, width), indexing="ij")
-    out = np.empty((batch, 4, height, width))
+    out = np.empty((batch, 4 * runs, height, width))
     for b in range(batch):
         cx, cy, r0 = rng.uniform(-0.3, 0.3), rng.uniform(-0.3, 0.3), rng.uniform(0.3, 0.8)
         rr = np.hypot(xx - cx, yy - cy)
         I = np.exp(-(rr / r0) ** 2) + 0.05
         p = p_max * np.clip(rr / r0, 0.0, 1.0)
         chi = np.arctan2(yy - cy, xx - cx) + rng.uniform(0, np.pi)
-        n = 1.0 + noise * rng.standard_normal((4, height, width))
-        out[b, 0] = I * np.abs(n[0])
-        out[b, 1] = I * p * np.cos(2 * chi) * n[1]
-        out[b, 2] = I * p * np.sin(2 * chi) * n[2]
-        out[b, 3] = 0.01 * I * rng.standard_normal((height, width))
-        # keep every pixel a physical Stokes vector, I >= |(Q, U, V)|
-        out[b, 0] = np.maximum(out[b, 0], 1.001 * np.sqrt((out[b, 1:] ** 2).sum(0)))
+        for r in range(runs):
+            o = out[b, 4 * r:4 * r + 4]
+            n = 1.0 + noise * rng.standard_normal((4, height, width))
+            o[0] = I * np.abs(n[0])
+            o[1] = I * p * np.cos(2 * chi) * n[1]
+            o[2] = I * p * np.sin(2 * chi) * n[2]
+            o[3] = 0.01 * I * rng.standard_normal((height, width))
+            # keep every pixel a physical Stokes vector, I >= |(Q, U, V)|
+            o[0] = np.maximum(o[0], 1.001 * np.sqrt((o[1:] ** 2).sum(0)))
     return out
 
 

@@ -114,6 +114,40 @@ def test_features_and_loss_at_zero_correction_is_relative_error():
     assert abs(L - np.mean(E2)) <= 1e-12 * L
 
 
+def test_two_run_features_worked_pixel_and_invariances():
+    """Two runs A, B of an image: the first four features are those of the
+    mean map, the last four |S_A - S_B| / (2 I_mean).  Worked pixel:
+    A = (2, 0.4, -0.2, 0), B = (1, 0.1, 0.1, 0.05) -> mean (1.5, 0.25, -0.05,
+    0.025): fractions (1/6, -1/30, 1/60), noise features (1/3, 0.1, 0.1, 1/60)."""
+    maps = np.ones((1, 8, 2, 2))
+    maps[0, 4:] = maps[0, :4]
+    maps[0, :, 0, 0] = [2.0, 0.4, -0.2, 0.0, 1.0, 0.1, 0.1, 0.05]
+    maps[0, 1:4, 1, 1] = maps[0, 5:8, 1, 1] = 0.0
+    x, Ihat, s = D.features(maps)
+    assert x.shape == (1, 2, 2, 8)
+    assert np.allclose(x[0, 0, 0, 1:], [1 / 6, -1 / 30, 1 / 60, 1 / 3, 0.1, 0.1, 1 / 60], rtol=1e-14, atol=0)
+    assert np.isclose(s[0], (1.5 + 3.0) / 4) and np.isclose(Ihat[0, 0, 0], 1.5 / s[0])
+    # pixels where the runs agree carry no noise feature
+    assert np.all(x[0, 1, 1, 4:] == 0) and np.all(x[0, 0, 1, 4:] == 0)
+    # identical runs: the single-map features and zero noise features
+    m4 = _maps(RNG, 2, 6, 6)
+    x2, Ih2, s2 = D.features(np.concatenate([m4, m4], axis=1))
+    x1, Ih1, s1 = D.features(m4)
+    assert np.array_equal(x2[..., :4], x1) and np.all(x2[..., 4:] == 0)
+    assert np.array_equal(Ih2, Ih1) and np.array_equal(s2, s1)
+    # swapping the runs changes nothing
+    a, b = _maps(RNG, 2, 6, 6), _maps(RNG, 2, 6, 6)
+    assert np.array_equal(D.features(np.concatenate([a, b], 1))[0], D.features(np.concatenate([b, a], 1))[0])
+
+
+def test_two_run_network_has_eight_inputs():
+    n8, n4 = D.n_params(cin=8), D.n_params()
+    assert n8 - n4 == 4 * 9 * D.WIDTHS[0]
+    assert D.layer_shapes(cin=8)["e1a.w"] == (D.WIDTHS[0], 3, 3, 8)
+    flat = RNG.standard_normal(n8)
+    assert np.array_equal(D.flatten(D.unflatten(flat, cin=8)), flat)
+
+
 def test_adam_first_step_closed_form():
     p = {"a": np.array([1.0, -2.0, 0.5])}
     g = {"a": np.array([0.3, -0.01, 2.0])}

@@ -51,7 +51,7 @@ def _operands(params32, low, high, widths):
     """Parameters and inputs as the kernels see them: 3x3 weights BF16
     (biases and head FP32), features FP32 -> BF16 for the network, the
     fractions Q/I, U/I, Ihat and the targets FP32."""
-    p = D.unflatten(params32.astype(np.float64), widths)
+    p = D.unflatten(params32.astype(np.float64), widths, cin=low.shape[1])
     for k in p:
         if k.endswith(".w") and not k.startswith("head"):
             p[k] = bf16(p[k])
@@ -238,6 +238,49 @@ def test_other_depths_forward_and_gradient_parity(widths, shape):
     d.close()
 
 
+def dihedral_runs(m, code):
+    """dihedral() applied to each run's four maps of a two-run input."""
+    return np.concatenate([dihedral(m[:4], code), dihedral(m[4:], code)])
+
+
+@pytest.mark.parametrize("shape", [(2, 32, 32), (3, 20, 28)])
+def test_two_run_inputs_forward_and_gradient_parity(shape):
+    """Inputs of two independent runs per image ([B, 8, H, W]): the network
+    reads the mean map's features plus the per-pixel half-differences; the
+    output is the mean map with corrected Q and U."""
+    from paper_2512_01283_amd import denoiser as DN
+    b, h, w = shape
+    params = W.denoiser_params(21, bias_std=0.05, head_std=0.05, cin=8)
+    d = DN.Denoiser(0, params=params, runs=2)
+    low = W.synthetic_stokes_maps(16, b, h, w, noise=0.3, runs=2)
+    high = W.synthetic_stokes_maps(16, b, h, w, noise=0.0)
+    mean = 0.5 * (low[:, :4] + low[:, 4:])
+    out = d.infer(_dev(low)).cpu().numpy()
+    assert out.shape == (b, 4, h, w)
+    ref = oracle_pass(params, low)
+    rep = bf16_replay(params, low)
+    e = rel(np.moveaxis(out[:, 1:3] / out[:, :1], 1, -1) - fractions(mean), ref["delta"])
+    e_rep = rel(rep["delta"], ref["delta"])
+    print(f"two-run forward {shape}: relative error of the correction {e:.2e} (BF16 replay {e_rep:.2e})")
+    assert e < TOL_FWD and e < 2.0 * e_rep + 2e-3
+    assert np.array_equal(out[:, 0], mean[:, 0]) and np.array_equal(out[:, 3], mean[:, 3])
+    loss = d.backward(_dev(low), _dev(high))
+    g = D.unflatten(d.grads().astype(np.float64), cin=8)
+    refg = check_gradients(g, low, high, params, f"two-run gradients {shape}")
+    assert abs(loss - refg["loss"]) <= TOL_FWD * refg["loss"]
+    if h == w:
+        codes = np.array([3, 6][:b] + [5] * max(0, b - 2), dtype=np.int32)
+        loss = d.backward(_dev(low), _dev(high), aug=codes)
+        g = D.unflatten(d.grads().astype(np.float64), cin=8)
+        lo_t = np.stack([dihedral_runs(low[i], int(c)) for i, c in enumerate(codes)])
+        hi_t = np.stack([dihedral(high[i], int(c)) for i, c in enumerate(codes)])
+        refa = check_gradients(g, lo_t, hi_t, params, "two-run augmented gradients")
+        assert abs(loss - refa["loss"]) <= TOL_FWD * refa["loss"]
+    with pytest.raises(ValueError):
+        d.infer(_dev(mean))  # a one-run input to a two-run network
+    d.close()
+
+
 def test_adam_step_matches_oracle(dn):
     params = W.denoiser_params(14, bias_std=0.05, head_std=0.05)
     dn.set_params(params)
@@ -328,6 +371,9 @@ def test_argument_errors(dn):
     m = _dev(W.synthetic_stokes_maps(13, 1, 16, 16))
     with pytest.raises(P.KpError):
         DN.kp_dn_create(0, (40, 96, 192))
+    for runs in (0, 3):
+        with pytest.raises(P.KpError):
+            DN.kp_dn_create_runs(0, (48, 96, 192), runs)
     with pytest.raises(P.KpError):
         dn.infer(_dev(W.synthetic_stokes_maps(13, 1, 18, 16)))
     with pytest.raises(P.KpError):
