@@ -251,6 +251,13 @@ def main():
              "infer_ms": inf["ms_total"], "infer_conv_ms": inf["ms_conv"],
              "infer_conv_tflops": inf["conv_flop"] / (inf["ms_conv"] * 1e-3) / 1e12}
         d["infer_conv_mfma_frac"] = d["infer_conv_tflops"] / BF16_PEAK_TFLOPS
+        # test-time averaging over the 8 dihedral transforms (outside the step)
+        dn.infer(maps, den, tta=True)
+        tta = []
+        for _ in range(3):
+            dn.infer(maps, den, tta=True)
+            tta.append(dn.timing()["ms_total"])
+        d["infer_tta_ms"] = float(np.mean(tta))
         if args.train_steps > 0:
             # training on the step's maps (input and target the same here: the
             # cost of a step does not depend on the data)

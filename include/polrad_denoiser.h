@@ -104,6 +104,15 @@ kp_status kp_dn_set_adam(kp_dn *dn, const float *host_m, const float *host_v, si
  * Asynchronous on hip_stream. */
 kp_status kp_dn_infer(kp_dn *dn, const double *d_maps, double *d_out, int32_t batch, int32_t height,
                       int32_t width, void *hip_stream);
+/* Test-time averaging: as kp_dn_infer, with q' and u' the mean over the
+ * eight dihedral transforms of each input (the aug codes of kp_dn_backward)
+ * of the network's prediction for the transformed image, mapped back to the
+ * original pixels and Stokes signs; only the four codes without a quarter
+ * turn when height != width.  Eight (four) forward passes.  The average is
+ * exactly equivariant under the group, and by convexity its squared Q/U
+ * error is at most the mean of the single passes' squared errors. */
+kp_status kp_dn_infer_tta(kp_dn *dn, const double *d_maps, double *d_out, int32_t batch, int32_t height,
+                          int32_t width, void *hip_stream);
 
 /* Loss and gradients for the pairs (d_low[b], d_high[b]) (device maps;
  * d_low [batch][4 runs][height][width], d_high [batch][4][height][width]).

@@ -622,12 +622,38 @@ __global__ void k_sums(const double* __restrict__ maps, int HW, int runs, double
 // I <= 0): a one-sample estimate of the mean's per-pixel noise, unchanged by
 // swapping the runs and by the dihedral transforms' signs.
 // With aug, image b is first transformed by the dihedral element aug[b] =
-// r + 4 f: mirror the width axis if f, then r quarter turns (output pixel
-// (h, w) of one turn reads (w, W - 1 - h)); Stokes (Q, U, V) ->
+// r + 4 f: mirror the width axis if f, then r quarter turns (numpy's rot90;
+// dihedral_source gives the pixel read); Stokes (Q, U, V) ->
 // ((-1)^r Q, (-1)^(r+f) U, (-1)^f V).  Odd r requires H == W.
+// Pixel (h, w) of the image T = rot^r(mirror^f(m)) of an H x W image m
+// (code = r + 4 f; rot = numpy's rot90 on (H, W), T is W x H for odd r): on
+// return (h, w) is the pixel of m it reads and (sq, su, sv) the signs of its
+// Q, U, V.  Source in mirror^f(m): r = 1: (w, W-1-h); r = 2: (H-1-h,
+// W-1-w); r = 3: (H-1-w, h); then the mirror flips the column.
+__device__ __forceinline__ void dihedral_source(int code, int H, int W, int& h, int& w, double& sq, double& su,
+                                                double& sv) {
+  const int r = code & 3, f = code >> 2;
+  const int h0 = h, w0 = w;
+  if (r == 1) {
+    h = w0;
+    w = W - 1 - h0;
+  } else if (r == 2) {
+    h = H - 1 - h0;
+    w = W - 1 - w0;
+  } else if (r == 3) {
+    h = H - 1 - w0;
+    w = h0;
+  }
+  if (f) w = W - 1 - w;
+  sq = (r & 1) ? -1.0 : 1.0;
+  su = ((r + f) & 1) ? -1.0 : 1.0;
+  sv = f ? -1.0 : 1.0;
+}
+
+// code_all >= 0 (with aug == nullptr) applies that one element to every image.
 __global__ void k_prep(const double* __restrict__ maps, const double* __restrict__ target,
-                       const double* __restrict__ sums, const int32_t* __restrict__ aug, int B, int H, int W,
-                       int runs, uint16_t* __restrict__ x, float* __restrict__ xq, float* __restrict__ ihat,
+                       const double* __restrict__ sums, const int32_t* __restrict__ aug, int code_all, int B, int H,
+                       int W, int runs, uint16_t* __restrict__ x, float* __restrict__ xq, float* __restrict__ ihat,
                        float* __restrict__ tgt) {
   const int HW = H * W;
   const size_t n = (size_t)B * HW;
@@ -635,18 +661,8 @@ __global__ void k_prep(const double* __restrict__ maps, const double* __restrict
     const size_t b = k / HW;
     int h = (int)(k % HW) / W, w = (int)(k % HW) % W;
     double sq = 1.0, su = 1.0, sv = 1.0;
-    if (aug) {
-      const int code = aug[b], r = code & 3, f = code >> 2;
-      for (int t = 0; t < r; ++t) {
-        const int h2 = w, w2 = W - 1 - h;
-        h = h2;
-        w = w2;
-      }
-      if (f) w = W - 1 - w;
-      sq = (r & 1) ? -1.0 : 1.0;
-      su = ((r + f) & 1) ? -1.0 : 1.0;
-      sv = f ? -1.0 : 1.0;
-    }
+    if (aug) dihedral_source(aug[b], H, W, h, w, sq, su, sv);
+    else if (code_all >= 0) dihedral_source(code_all, H, W, h, w, sq, su, sv);
     const size_t p = (size_t)h * W + w;
     const double mean = sums[2 * b] / HW;
     const double* m = maps + b * 4 * runs * HW + p;
@@ -783,10 +799,32 @@ __global__ void k_head_bwd(const float* __restrict__ go, const uint16_t* __restr
   if (tid < 2) atomicAdd(ghb + tid, red[2 * C + tid]);
 }
 
+// Test-time averaging: out holds the network's fractions (q', u') of the
+// images transformed by `code`; each is moved back to its source pixel with
+// the inverse Stokes signs (the signs are their own inverses) and added to
+// acc ([B][HW][2] in the original pixel order), or stored there if first.
+// The transform is a bijection of each image's pixels: no two threads write
+// the same element.
+__global__ void k_tta_acc(const float* __restrict__ out, int B, int H, int W, int code, int first,
+                          float* __restrict__ acc) {
+  const int HW = H * W;
+  const size_t n = (size_t)B * HW;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    const size_t b = k / HW;
+    int h = (int)(k % HW) / W, w = (int)(k % HW) % W;
+    double sq, su, sv;
+    dihedral_source(code, H, W, h, w, sq, su, sv);
+    const size_t src = b * HW + (size_t)h * W + w;
+    const float q = (float)sq * out[2 * k], u = (float)su * out[2 * k + 1];
+    acc[2 * src] = first ? q : acc[2 * src] + q;
+    acc[2 * src + 1] = first ? u : acc[2 * src + 1] + u;
+  }
+}
+
 // denoised maps: I and V from the input (the two runs' mean if runs == 2),
-// Q = q' I and U = u' I
+// Q = scale q' I and U = scale u' I
 __global__ void k_output(const double* __restrict__ maps, const float* __restrict__ out, int B, int HW, int runs,
-                         double* __restrict__ dst) {
+                         double scale, double* __restrict__ dst) {
   const size_t n = (size_t)B * HW;
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
     const size_t b = k / HW, p = k % HW;
@@ -795,8 +833,8 @@ __global__ void k_output(const double* __restrict__ maps, const float* __restric
     const size_t rb = 4 * (size_t)HW;
     const double I = runs == 2 ? 0.5 * (m[0] + m[rb]) : m[0];
     o[0] = I;
-    o[HW] = (double)out[2 * k] * I;
-    o[2 * (size_t)HW] = (double)out[2 * k + 1] * I;
+    o[HW] = (double)out[2 * k] * scale * I;
+    o[2 * (size_t)HW] = (double)out[2 * k + 1] * scale * I;
     o[3 * (size_t)HW] = runs == 2 ? 0.5 * (m[3 * (size_t)HW] + m[rb + 3 * (size_t)HW]) : m[3 * (size_t)HW];
   }
 }
@@ -923,10 +961,10 @@ void pool_bwd_add(const uint16_t* a, int as, const uint16_t* g, int gs, const ui
 void sums(const double* maps, int B, int HW, int runs, double* sum, hipStream_t s) {
   hipLaunchKernelGGL(k_sums, dim3(grid_for(HW, 32), B), dim3(256), 0, s, maps, HW, runs, sum);
 }
-void prep(const double* maps, const double* target, const double* sum, const int32_t* aug, int B, int H, int W,
-          int runs, uint16_t* x, float* xq, float* ihat, float* tgt, hipStream_t s) {
-  hipLaunchKernelGGL(k_prep, dim3(grid_for((size_t)B * H * W)), dim3(256), 0, s, maps, target, sum, aug, B, H, W,
-                     runs, x, xq, ihat, tgt);
+void prep(const double* maps, const double* target, const double* sum, const int32_t* aug, int code_all, int B,
+          int H, int W, int runs, uint16_t* x, float* xq, float* ihat, float* tgt, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep, dim3(grid_for((size_t)B * H * W)), dim3(256), 0, s, maps, target, sum, aug, code_all,
+                     B, H, W, runs, x, xq, ihat, tgt);
 }
 void head(const uint16_t* d, int C, const float* hw, const float* hb, const float* xq, float* out, size_t P,
           hipStream_t s) {
@@ -942,8 +980,13 @@ void head_bwd(const float* go, const uint16_t* d, int C, const float* hw, float*
   hipLaunchKernelGGL(k_head_bwd, dim3((unsigned)((P + HB_CHUNK - 1) / HB_CHUNK)), dim3(256), 0, s, go, d, C, hw, ghw,
                      ghb, gd, P);
 }
-void output(const double* maps, const float* out, int B, int HW, int runs, double* dst, hipStream_t s) {
-  hipLaunchKernelGGL(k_output, dim3(grid_for((size_t)B * HW)), dim3(256), 0, s, maps, out, B, HW, runs, dst);
+void tta_acc(const float* out, int B, int H, int W, int code, bool first, float* acc, hipStream_t s) {
+  hipLaunchKernelGGL(k_tta_acc, dim3(grid_for((size_t)B * H * W)), dim3(256), 0, s, out, B, H, W, code, (int)first,
+                     acc);
+}
+void output(const double* maps, const float* out, int B, int HW, int runs, double scale, double* dst,
+            hipStream_t s) {
+  hipLaunchKernelGGL(k_output, dim3(grid_for((size_t)B * HW)), dim3(256), 0, s, maps, out, B, HW, runs, scale, dst);
 }
 void adam(float* p, const float* g, float* m, float* v, size_t n, float lr, int t, hipStream_t s) {
   const double b1 = 0.9, b2 = 0.999;

@@ -288,8 +288,9 @@ void conv_wgrad(kp_dn* dn, int l, const uint16_t* gz, const uint16_t* x, int xs,
 }
 
 // maps -> w.out (network output: predicted fractions q', u'); activations kept
+// code_all >= 0: every image transformed by that dihedral element (test-time averaging)
 kp_status forward(kp_dn* dn, const double* maps, const double* target, int B, int H, int W, bool use_aug,
-                  hipStream_t s) {
+                  hipStream_t s, int code_all = -1) {
   Work& w = dn->w;
   const int L = dn->L;
   const int* c = dn->c;
@@ -298,7 +299,7 @@ kp_status forward(kp_dn* dn, const double* maps, const double* target, int B, in
   auto Wl = [&](int l) { return W >> l; };
   zero(w.sum, (size_t)B * 16, s);
   sums(maps, B, H * W, dn->runs, w.sum, s);
-  prep(maps, target, w.sum, use_aug ? w.aug : nullptr, B, H, W, dn->runs, w.x0, w.xq, w.ihat, w.tgt, s);
+  prep(maps, target, w.sum, use_aug ? w.aug : nullptr, code_all, B, H, W, dn->runs, w.x0, w.xq, w.ihat, w.tgt, s);
   // encoder
   for (int l = 0; l < L - 1; ++l) {
     const uint16_t* in = l == 0 ? w.x0 : w.pool[l];
@@ -556,7 +557,34 @@ kp_status kp_dn_infer(kp_dn* dn, const double* d_maps, double* d_out, int32_t B,
   dn->ev_total0 = mark_begin(dn, s);
   if (kp_status st = ensure_packed(dn, s)) return st;
   if (kp_status st = forward(dn, d_maps, nullptr, B, H, W, false, s)) return st;
-  output(d_maps, dn->w.out, B, H * W, dn->runs, d_out, s);
+  output(d_maps, dn->w.out, B, H * W, dn->runs, 1.0, d_out, s);
+  DN_HIP(hipGetLastError(), "output launch");
+  if (dn->ev_total0 >= 0) {
+    dn->ev_total1 = dn->ev_total0 + 1;
+    DN_HIP(hipEventRecord(dn->ev[dn->ev_total1], s), "event record");
+  }
+  return KP_OK;
+}
+
+kp_status kp_dn_infer_tta(kp_dn* dn, const double* d_maps, double* d_out, int32_t B, int32_t H, int32_t W,
+                          void* stream) {
+  if (!dn) return KP_ERR_ARG;
+  if (kp_status st = check_maps(dn, d_maps, d_out, B, H, W)) return st;
+  if ((const void*)d_maps == (const void*)d_out) return fail(dn, KP_ERR_ARG, "d_out may not alias d_maps");
+  hipStream_t s = (hipStream_t)stream;
+  DN_HIP(hipSetDevice(dn->device), "hipSetDevice");
+  if (kp_status st = ensure_work(dn, (size_t)B * H * W, B)) return st;
+  marks_reset(dn);
+  dn->ev_total0 = mark_begin(dn, s);
+  if (kp_status st = ensure_packed(dn, s)) return st;
+  // quarter turns need square images; otherwise the four elements without one
+  const int step = H == W ? 1 : 2, n = 8 / step;
+  // the loss gradient buffer (unused by inference) accumulates the fractions
+  for (int code = 0; code < 8; code += step) {
+    if (kp_status st = forward(dn, d_maps, nullptr, B, H, W, false, s, code)) return st;
+    tta_acc(dn->w.out, B, H, W, code, code == 0, dn->w.go, s);
+  }
+  output(d_maps, dn->w.go, B, H * W, dn->runs, 1.0 / n, d_out, s);
   DN_HIP(hipGetLastError(), "output launch");
   if (dn->ev_total0 >= 0) {
     dn->ev_total1 = dn->ev_total0 + 1;

@@ -61,15 +61,17 @@ void up_bwd(const uint16_t* gy, int gys, uint16_t* gx, int gxs, const uint16_t* 
 void pool_bwd_add(const uint16_t* a, int as, const uint16_t* g, int gs, const uint16_t* mask, int ms, uint16_t* dst,
                   int ds, int B, int H, int W, int C, hipStream_t s);
 void sums(const double* maps, int B, int HW, int runs, double* sum, hipStream_t s);
-void prep(const double* maps, const double* target, const double* sum, const int32_t* aug, int B, int H, int W,
-          int runs, uint16_t* x, float* xq, float* ihat, float* tgt, hipStream_t s);
+void prep(const double* maps, const double* target, const double* sum, const int32_t* aug, int code_all, int B,
+          int H, int W, int runs, uint16_t* x, float* xq, float* ihat, float* tgt, hipStream_t s);
 void head(const uint16_t* d, int C, const float* hw, const float* hb, const float* xq, float* out, size_t P,
           hipStream_t s);
 void loss(const float* out, const float* tgt, const float* ihat, const double* sum, int B, int HW, float* go,
           double* l, hipStream_t s);
 void head_bwd(const float* go, const uint16_t* d, int C, const float* hw, float* ghw, float* ghb, uint16_t* gd,
               size_t P, hipStream_t s);
-void output(const double* maps, const float* out, int B, int HW, int runs, double* dst, hipStream_t s);
+void tta_acc(const float* out, int B, int H, int W, int code, bool first, float* acc, hipStream_t s);
+void output(const double* maps, const float* out, int B, int HW, int runs, double scale, double* dst,
+            hipStream_t s);
 void adam(float* p, const float* g, float* m, float* v, size_t n, float lr, int t, hipStream_t s);
 void pack(const float* wf, int cout, int cin, int cin_true, int kp, int kpd, uint16_t* w, uint16_t* wd,
           hipStream_t s);

@@ -39,6 +39,7 @@ _SIGS = {
     "kp_dn_get_adam": ([_Pv, _Pv, _Pv, C.c_size_t, C.POINTER(C.c_int32)], C.c_int),
     "kp_dn_set_adam": ([_Pv, _Pv, _Pv, C.c_size_t, C.c_int32], C.c_int),
     "kp_dn_infer": ([_Pv, _Pv, _Pv, C.c_int32, C.c_int32, C.c_int32, _Pv], C.c_int),
+    "kp_dn_infer_tta": ([_Pv, _Pv, _Pv, C.c_int32, C.c_int32, C.c_int32, _Pv], C.c_int),
     "kp_dn_backward": ([_Pv, _Pv, _Pv, C.c_int32, C.c_int32, C.c_int32, _Pv,
                         C.POINTER(C.c_double), _Pv], C.c_int),
     "kp_dn_adam_step": ([_Pv, C.c_float, _Pv], C.c_int),
@@ -157,12 +158,13 @@ def _aug_arg(aug, b):
     return a, C.c_void_p(a.ctypes.data)
 
 
-def kp_dn_infer(h, maps, out, stream=None, runs=1):
+def kp_dn_infer(h, maps, out, stream=None, runs=1, tta=False):
     b, hh, ww = _maps_args(maps, 4 * runs)
     _maps_args(out)
     if tuple(out.shape) != (b, 4, hh, ww):
         raise ValueError(f"out must be [batch, 4, height, width] = {(b, 4, hh, ww)}")
-    _check(h, _lib.kp_dn_infer(h, P._ptr(maps), P._ptr(out), b, hh, ww, P._stream_ptr(stream)))
+    f = _lib.kp_dn_infer_tta if tta else _lib.kp_dn_infer
+    _check(h, f(h, P._ptr(maps), P._ptr(out), b, hh, ww, P._stream_ptr(stream)))
 
 
 def kp_dn_backward(h, low, high, aug=None, stream=None, runs=1) -> float:
@@ -236,11 +238,12 @@ class Denoiser:
     def set_adam_state(self, m, v, step):
         kp_dn_set_adam(self.h, m, v, step)
 
-    def infer(self, maps, out=None, stream=None):
+    def infer(self, maps, out=None, stream=None, tta=False):
+        """Denoised maps; tta=True averages over the dihedral transforms."""
         import torch
         if out is None:
             out = torch.empty((maps.shape[0], 4) + tuple(maps.shape[2:]), dtype=maps.dtype, device=maps.device)
-        kp_dn_infer(self.h, maps, out, stream, self.runs)
+        kp_dn_infer(self.h, maps, out, stream, self.runs, tta)
         return out
 
     def backward(self, low, high, aug=None, stream=None):

@@ -130,8 +130,26 @@ def train(dn, lo, hi, steps, batch=8, lr=1e-3, lr_min=1e-5, seed=0, aug=True, lo
     return hist
 
 
+def _packets_to_eps(counts, errors, eps):
+    """(N, bound): the input count at which the error curve reaches eps, by
+    log-log interpolation of errors[count] over the counts tried."""
+    dc = np.array(counts, dtype=float)
+    de = np.array([errors[c] for c in counts])
+    if eps >= de[0]:
+        return float(dc[0]), "<="  # reached at or below the smallest count tried
+    if eps < de.min():
+        return float("nan"), "not reached"
+    order = np.argsort(dc)
+    le, lc = np.log(de[order]), np.log(dc[order])
+    for j in range(len(lc) - 1):
+        if (le[j] - math.log(eps)) * (le[j + 1] - math.log(eps)) <= 0:
+            t = (math.log(eps) - le[j]) / (le[j + 1] - le[j])
+            return math.exp(lc[j] + t * (lc[j + 1] - lc[j])), "="
+    return float("nan"), "="
+
+
 def evaluate(dn, seeds, plain_counts=(1e6, 3e6, 1e7, 3e7), den_counts=(1e5, 3e5, 1e6, 3e6),
-             ref_half=1.5e8, n=256, npix=None, log=print):
+             ref_half=1.5e8, n=256, npix=None, log=print, tta=False):
     """Packets-to-fixed-error comparison of plain and denoised maps.  A
     two-run denoiser gets each count as two runs of half the packets; its
     "input" error is that of their mean, the plain map of that count."""
@@ -139,6 +157,7 @@ def evaluate(dn, seeds, plain_counts=(1e6, 3e6, 1e7, 3e7), den_counts=(1e5, 3e5,
     Ep = {c: [] for c in plain_counts}
     Ed = {c: [] for c in den_counts}
     Ein = {c: [] for c in den_counts}
+    Etta = {c: [] for c in den_counts}
     Eref = []
     for s, cfg in _disks(seeds, n, npix):
         with P.Context(0) as ctx:
@@ -154,11 +173,13 @@ def evaluate(dn, seeds, plain_counts=(1e6, 3e6, 1e7, 3e7), den_counts=(1e5, 3e5,
                 m = run_input(ctx, c, 100 * s + 7 + k, dn.runs)
                 Ein[c] += image_error(0.5 * (m[:, :4] + m[:, 4:]) if dn.runs == 2 else m, ref).tolist()
                 Ed[c] += image_error(dn.infer(m), ref).tolist()
+                if tta:
+                    Etta[c] += image_error(dn.infer(m, tta=True), ref).tolist()
         torch.cuda.synchronize()
         if log:
             log(f"  evaluated disk {s}", flush=True)
     mean = {k: {c: float(np.mean(v)) for c, v in d.items()} for k, d in
-            (("plain", Ep), ("denoised", Ed), ("input", Ein))}
+            (("plain", Ep), ("denoised", Ed), ("input", Ein)) + ((("denoised_tta", Etta),) if tta else ())}
     eps = mean["plain"][1e7]
     # E = a N^-1/2 fitted in log space
     xs = np.log(np.array(plain_counts))
@@ -166,29 +187,16 @@ def evaluate(dn, seeds, plain_counts=(1e6, 3e6, 1e7, 3e7), den_counts=(1e5, 3e5,
     loga = float(np.mean(ys + 0.5 * xs))
     n_plain = math.exp(2 * (loga - math.log(eps)))
     slope = float(np.polyfit(xs, ys, 1)[0])
-    # interpolate log E_den against log N
-    dc = np.array(den_counts, dtype=float)
-    de = np.array([mean["denoised"][c] for c in den_counts])
-    if eps >= de[0]:
-        n_den = float(dc[0])  # reached at or below the smallest count tried
-        bound = "<="
-    elif eps < de.min():
-        n_den = float("nan")
-        bound = "not reached"
-    else:
-        order = np.argsort(dc)
-        le, lc = np.log(de[order]), np.log(dc[order])
-        n_den = float("nan")
-        for j in range(len(lc) - 1):
-            if (le[j] - math.log(eps)) * (le[j + 1] - math.log(eps)) <= 0:
-                t = (math.log(eps) - le[j]) / (le[j + 1] - le[j])
-                n_den = math.exp(lc[j] + t * (lc[j + 1] - lc[j]))
-                break
-        bound = "="
-    return dict(eps=eps, E_ref=float(np.mean(Eref)), ref_ok=bool(np.mean(Eref) <= eps / 3),
+    n_den, bound = _packets_to_eps(den_counts, mean["denoised"], eps)
+    res = dict(eps=eps, E_ref=float(np.mean(Eref)), ref_ok=bool(np.mean(Eref) <= eps / 3),
                 plain_slope=slope, N_plain=n_plain, N_den=n_den, N_den_bound=bound,
                 ratio=(n_plain / n_den) if n_den == n_den else None,
                 E=mean, seeds=list(seeds))
+    if tta:
+        n_tta, bound_tta = _packets_to_eps(den_counts, mean["denoised_tta"], eps)
+        res.update(N_den_tta=n_tta, N_den_tta_bound=bound_tta,
+                   ratio_tta=(n_plain / n_tta) if n_tta == n_tta else None)
+    return res
 
 
 def main(argv=None):
@@ -210,6 +218,8 @@ def main(argv=None):
                     help="2: inputs are two independent runs of half the packets each")
     ap.add_argument("--init", default=None, help="start from saved parameters (.npy)")
     ap.add_argument("--skip-eval", action="store_true")
+    ap.add_argument("--tta", action="store_true",
+                    help="also evaluate the mean over the 8 dihedral transforms of each input")
     a = ap.parse_args(argv)
     os.makedirs(a.out, exist_ok=True)
 
@@ -221,17 +231,20 @@ def main(argv=None):
     t0 = time.time()
     log(f"generating training pairs on {torch.cuda.get_device_name(0)}", flush=True)
     n_lo = [float(v) for v in str(a.n_lo).split(",")]
-    lo, hi = make_pairs(seeds(a.train_seeds), n_lo, a.n_hi, n=a.grid, npix=a.npix, log=log, runs=a.runs)
+    if a.steps > 0:
+        lo, hi = make_pairs(seeds(a.train_seeds), n_lo, a.n_hi, n=a.grid, npix=a.npix, log=log, runs=a.runs)
     t_gen = time.time() - t0
     widths = tuple(int(v) for v in a.widths.split(","))
     dn = DN.Denoiser(0, widths=widths, runs=a.runs)
     init = np.load(a.init) if a.init else W.denoiser_params(0, widths=widths, cin=4 * a.runs)
     dn.set_params(init)
     t1 = time.time()
-    hist = train(dn, lo, hi, a.steps, batch=a.batch, lr=a.lr, log=log)
+    hist = [(0, float("nan"))]
+    if a.steps > 0:  # 0: evaluate the --init parameters only
+        hist = train(dn, lo, hi, a.steps, batch=a.batch, lr=a.lr, log=log)
+        del lo, hi
     torch.cuda.synchronize()
     t_train = time.time() - t1
-    del lo, hi
     np.save(os.path.join(a.out, "params.npy"), dn.params())
     res = dict(widths=list(widths), runs=a.runs, params=dn.n, train_seeds=a.train_seeds, n_lo=n_lo, n_hi=a.n_hi,
                steps=a.steps, batch=a.batch,
@@ -239,7 +252,8 @@ def main(argv=None):
                loss_first=hist[0][1], loss_last=float(np.mean([l for _, l in hist[-50:]])))
     if not a.skip_eval:
         log("evaluating", flush=True)
-        res["eval"] = evaluate(dn, seeds(a.test_seeds), ref_half=a.ref_half, n=a.grid, npix=a.npix, log=log)
+        res["eval"] = evaluate(dn, seeds(a.test_seeds), ref_half=a.ref_half, n=a.grid, npix=a.npix, log=log,
+                               tta=a.tta)
     with open(os.path.join(a.out, "result.json"), "w") as f:
         json.dump(res, f, indent=1)
     log(json.dumps(res), flush=True)

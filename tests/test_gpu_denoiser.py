@@ -47,6 +47,17 @@ def dihedral(m, code):
     return out
 
 
+def dihedral_inverse(m, code):
+    """The inverse of dihedral(m, code)."""
+    r, f = code & 3, code >> 2
+    out = m.copy()
+    out[1] *= (-1) ** r
+    out[2] *= (-1) ** (r + f)
+    out[3] *= (-1) ** f
+    out = np.rot90(out, -r, axes=(1, 2))
+    return (out[:, :, ::-1] if f else out).copy()
+
+
 def _operands(params32, low, high, widths):
     """Parameters and inputs as the kernels see them: 3x3 weights BF16
     (biases and head FP32), features FP32 -> BF16 for the network, the
@@ -213,6 +224,59 @@ def test_augmented_gradients_match_transformed_maps(dn):
     hi_t = np.stack([dihedral(high[i], int(c)) for i, c in enumerate(codes)])
     ref = check_gradients(g, lo_t, hi_t, params, "augmented gradients")
     assert abs(loss - ref["loss"]) <= TOL_FWD * ref["loss"]
+
+
+def test_non_square_augmented_gradients(dn):
+    """Half turns and mirrors of non-square maps (quarter turns need square
+    ones and are refused)."""
+    b, h, w = 4, 16, 24
+    params = W.denoiser_params(23, bias_std=0.05, head_std=0.05)
+    dn.set_params(params)
+    low = W.synthetic_stokes_maps(18, b, h, w, noise=0.3)
+    high = W.synthetic_stokes_maps(18, b, h, w, noise=0.0)
+    codes = np.array([0, 2, 4, 6], dtype=np.int32)
+    loss = dn.backward(_dev(low), _dev(high), aug=codes)
+    g = D.unflatten(dn.grads().astype(np.float64))
+    lo_t = np.stack([dihedral(low[i], int(c)) for i, c in enumerate(codes)])
+    hi_t = np.stack([dihedral(high[i], int(c)) for i, c in enumerate(codes)])
+    ref = check_gradients(g, lo_t, hi_t, params, "non-square augmented gradients")
+    assert abs(loss - ref["loss"]) <= TOL_FWD * ref["loss"]
+
+
+@pytest.mark.parametrize("shape", [(2, 16, 16), (3, 16, 24)])
+def test_test_time_averaging_parity(dn, shape):
+    """kp_dn_infer_tta against the oracle's forward pass on each transformed
+    input, mapped back to the original pixels and signs and averaged (all
+    eight elements for square maps, the four without a quarter turn
+    otherwise)."""
+    b, h, w = shape
+    params = W.denoiser_params(22, bias_std=0.05, head_std=0.05)
+    dn.set_params(params)
+    maps = W.synthetic_stokes_maps(17, b, h, w, noise=0.3)
+    out = dn.infer(_dev(maps), tta=True).cpu().numpy()
+    single = dn.infer(_dev(maps)).cpu().numpy()
+    codes = range(8) if h == w else (0, 2, 4, 6)
+
+    def back(delta, c):
+        dm = np.zeros((delta.shape[0], 4) + delta.shape[1:3])
+        dm[:, 1], dm[:, 2] = delta[..., 0], delta[..., 1]
+        return np.stack([dihedral_inverse(x, c) for x in dm])[:, 1:3]
+
+    ref, rep = 0.0, 0.0
+    for c in codes:
+        mt = np.stack([dihedral(m, c) for m in maps])
+        assert np.array_equal(np.stack([dihedral_inverse(x, c) for x in mt]), maps)
+        ref = ref + back(oracle_pass(params, mt)["delta"], c)
+        rep = rep + back(bf16_replay(params, mt)["delta"], c)
+    ref = np.moveaxis(ref / len(codes), 1, -1)
+    rep = np.moveaxis(rep / len(codes), 1, -1)
+    delta_gpu = np.moveaxis(out[:, 1:3] / out[:, :1], 1, -1) - fractions(maps)
+    e, e_rep = rel(delta_gpu, ref), rel(rep, ref)
+    print(f"test-time averaging {shape}: relative error {e:.2e} (BF16 replay {e_rep:.2e})")
+    assert e < TOL_FWD and e < 2.0 * e_rep + 2e-3
+    assert np.array_equal(out[:, 0], maps[:, 0]) and np.array_equal(out[:, 3], maps[:, 3])
+    # the average differs from one pass (the random network is not equivariant)
+    assert rel(out[:, 1:3], single[:, 1:3]) > 1e-4
 
 
 @pytest.mark.parametrize("widths,shape", [((16, 32, 48, 64), (2, 32, 24)), ((16, 32), (3, 12, 20))])
