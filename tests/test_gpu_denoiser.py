@@ -463,7 +463,8 @@ def test_trained_denoiser_beats_plain_maps_at_equal_packets():
     reduced disk family (64^3 grid, 64^2 maps, 32 disks x 8 views, inputs
     1e5 packets, targets 3e6), it must cut the Q/U error E against a
     3e7-packet reference on held-out disks by at least 10 % at the input's
-    packet count (the full-size run of the driver measures the real gain)."""
+    packet count (the full-size run of the driver measures the real gain);
+    averaging over the dihedral transforms must not lose to one pass."""
     import torch
 
     from paper_2512_01283_amd import denoiser as DN
@@ -473,7 +474,7 @@ def test_trained_denoiser_beats_plain_maps_at_equal_packets():
     dn = DN.Denoiser(0, params=W.denoiser_params(0))
     hist = T.train(dn, lo, hi, 1500, batch=16, lr=1e-3, log=None)
     print(f"training loss {hist[0][1]:.4e} -> {np.mean([l for _, l in hist[-50:]]):.4e}")
-    plain, den = [], []
+    plain, den, tta = [], [], []
     for s in range(3000, 3004):
         cfg = W.denoiser_disk(s, 1, n=64, npix=64)
         with P.Context(0) as ctx:
@@ -482,8 +483,11 @@ def test_trained_denoiser_beats_plain_maps_at_equal_packets():
             m = T.run_images(ctx, 1e5, 10 * s + 3)
             plain += T.image_error(m, ref).tolist()
             den += T.image_error(dn.infer(m), ref).tolist()
+            tta += T.image_error(dn.infer(m, tta=True), ref).tolist()
     torch.cuda.synchronize()
     dn.close()
-    e_plain, e_den = float(np.mean(plain)), float(np.mean(den))
-    print(f"E plain {e_plain:.4f}, denoised {e_den:.4f} (ratio {e_den / e_plain:.3f})")
+    e_plain, e_den, e_tta = float(np.mean(plain)), float(np.mean(den)), float(np.mean(tta))
+    print(f"E plain {e_plain:.4f}, denoised {e_den:.4f} (ratio {e_den / e_plain:.3f}), "
+          f"averaged over transforms {e_tta:.4f}")
     assert e_den < 0.9 * e_plain
+    assert e_tta <= 1.01 * e_den
