@@ -6,7 +6,7 @@ One step = one whole pass of the path over the workload: the persistent
 transport kernel (emission, cell marching, analytic dichroic extinction,
 coherency tally, scattering, roulette) for all packets, the imaging
 ray-march for all views, and the learned denoiser's inference on the eight
-maps.  Inputs (density grid) are resident in HBM before the timed region;
+maps (widths 64/128/256, averaged over the 8 dihedral transforms).  Inputs (density grid) are resident in HBM before the timed region;
 images stay on the device.  The denoiser's training step (BF16 MFMA forward
 and backward, Adam) is timed separately, after the timed steps, on batches of
 those maps, and reported with its own MFMA roofline under "detail".
@@ -29,6 +29,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 BF16_PEAK_TFLOPS = 2500.0
+# the denoiser configuration whose packets-to-error gain is quoted: widths
+# 64/128/256, averaged over the 8 dihedral transforms of each map
+DN_WIDTHS = (64, 128, 256)
 METRIC = "Stokes packets/s at 256^3 disk; packets to fixed Q/U error, plain vs denoised"
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per cell step of the transport kernel on Rayleigh spheres:
@@ -175,7 +178,7 @@ def main():
     dn = None
     if not args.no_denoiser:
         from paper_2512_01283_amd import denoiser as DN
-        dn = DN.Denoiser(0, params=W.denoiser_params(0))
+        dn = DN.Denoiser(0, widths=DN_WIDTHS, params=W.denoiser_params(0, widths=DN_WIDTHS))
     nv, npix = len(cfg["views"]), cfg["views"][0]["npx"]
     maps = torch.empty((nv, 4, npix, npix), dtype=torch.float64, device="cuda")
     den = torch.empty_like(maps)
@@ -184,7 +187,7 @@ def main():
         ctx.run(stream=stream, **opts)
         if dn is not None:
             ctx.images_device(out=maps.view(1, nv, 4, npix, npix), stream=stream)
-            dn.infer(maps, den, stream=stream)
+            dn.infer(maps, den, stream=stream, tta=True)
 
     for w in range(args.warmup):
         one_step()
@@ -248,16 +251,16 @@ def main():
     if dn is not None:
         inf = {k: float(np.mean([t[k] for t in ms_d])) for k in ms_d[0]}
         d = {"widths": list(dn.widths), "params": dn.n, "batch": nv, "npix": npix,
+             "infer": "mean over the 8 dihedral transforms (8 forward passes)",
              "infer_ms": inf["ms_total"], "infer_conv_ms": inf["ms_conv"],
              "infer_conv_tflops": inf["conv_flop"] / (inf["ms_conv"] * 1e-3) / 1e12}
         d["infer_conv_mfma_frac"] = d["infer_conv_tflops"] / BF16_PEAK_TFLOPS
-        # test-time averaging over the 8 dihedral transforms (outside the step)
-        dn.infer(maps, den, tta=True)
-        tta = []
-        for _ in range(3):
-            dn.infer(maps, den, tta=True)
-            tta.append(dn.timing()["ms_total"])
-        d["infer_tta_ms"] = float(np.mean(tta))
+        # one forward pass, for reference (outside the step)
+        one = []
+        for _ in range(4):
+            dn.infer(maps, den)
+            one.append(dn.timing()["ms_total"])
+        d["infer_one_pass_ms"] = float(np.mean(one[1:]))
         if args.train_steps > 0:
             # training on the step's maps (input and target the same here: the
             # cost of a step does not depend on the data)

@@ -129,3 +129,19 @@ def test_denoiser_without_device_and_bad_arguments():
     assert DN._lib.kp_dn_create(0, good.ctypes.data, 7, ctypes.byref(h)) == DN.P.KP_ERR_ARG
     assert DN._lib.kp_dn_infer(None, None, None, 1, 16, 16, None) == DN.P.KP_ERR_ARG
     assert DN._lib.kp_dn_num_params(None, None) == DN.P.KP_ERR_ARG
+
+
+def test_packets_to_fixed_error_interpolation():
+    """The evaluation's N_den: log-log interpolation between the counts that
+    bracket eps, the smallest count if eps is already met there, NaN if it
+    is never met."""
+    import math
+
+    from paper_2512_01283_amd.dn_train import _packets_to_eps
+    counts = (1e5, 1e6, 1e7)
+    errs = {1e5: 0.1, 1e6: 0.1 / math.sqrt(10), 1e7: 0.01}  # E = a N^-1/2
+    n, b = _packets_to_eps(counts, errs, 0.02)
+    assert b == "=" and abs(n - 2.5e6) < 1e-6 * 2.5e6  # (0.1 / 0.02)^2 * 1e5
+    assert _packets_to_eps(counts, errs, 0.2) == (1e5, "<=")
+    n, b = _packets_to_eps(counts, errs, 0.005)
+    assert b == "not reached" and n != n
