@@ -279,6 +279,22 @@ def test_test_time_averaging_parity(dn, shape):
     assert rel(out[:, 1:3], single[:, 1:3]) > 1e-4
 
 
+def test_test_time_averaging_timing_covers_every_pass():
+    """The timing of an averaged inference counts the convolutions of all
+    eight passes, also for the deepest network (6 levels)."""
+    from paper_2512_01283_amd import denoiser as DN
+    widths = (16,) * 6
+    d = DN.Denoiser(0, widths=widths, params=W.denoiser_params(24, widths=widths))
+    maps = _dev(W.synthetic_stokes_maps(19, 1, 64, 64))
+    d.infer(maps)
+    one = d.timing()
+    d.infer(maps, tta=True)
+    avg = d.timing()
+    d.close()
+    assert one["conv_flop"] > 0 and avg["conv_flop"] == 8 * one["conv_flop"]
+    assert avg["ms_total"] >= avg["ms_conv"] > 0
+
+
 @pytest.mark.parametrize("widths,shape", [((16, 32, 48, 64), (2, 32, 24)), ((16, 32), (3, 12, 20))])
 def test_other_depths_forward_and_gradient_parity(widths, shape):
     """The same kernels and schedule at 4 and 2 levels (ragged coarse levels)."""
