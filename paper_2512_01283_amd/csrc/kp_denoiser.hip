@@ -697,11 +697,19 @@ __global__ void k_prep(const double* __restrict__ maps, const double* __restrict
 }
 
 // out[p][o] = xq[p][o] + hb[o] + sum_c d[p][c] hw[o][c]   (C % 8 == 0)
+// Eight lanes per pixel: lane g of a group reads channels 8g + 64i (16 bytes
+// each), so a group's loads of one pixel are contiguous and each load
+// instruction of a wave reads eight whole pixels (one lane per pixel made
+// every instruction touch 64 lines, re-fetched from L2 eight times over).
+// The partial sums meet by lane shuffles inside the group; all eight lanes
+// of a group take the same p, so a shuffle never reads an inactive lane.
 __global__ void k_head(const uint16_t* __restrict__ d, int C, const float* __restrict__ hw,
                        const float* __restrict__ hb, const float* __restrict__ xq, float* __restrict__ out, size_t P) {
-  for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (size_t)gridDim.x * blockDim.x) {
-    float a0 = hb[0], a1 = hb[1];
-    for (int c = 0; c < C; c += 8) {
+  const int g = threadIdx.x & 7;
+  const size_t stride = ((size_t)gridDim.x * blockDim.x) >> 3;
+  for (size_t p = ((size_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3; p < P; p += stride) {
+    float a0 = 0.f, a1 = 0.f;
+    for (int c = 8 * g; c < C; c += 64) {
       float v[8];
       unpack8(ld16(d + p * C + c), v);
 #pragma unroll
@@ -710,8 +718,15 @@ __global__ void k_head(const uint16_t* __restrict__ d, int C, const float* __res
         a1 += v[j] * hw[C + c + j];
       }
     }
-    out[2 * p] = xq[2 * p] + a0;
-    out[2 * p + 1] = xq[2 * p + 1] + a1;
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+      a0 += __shfl_xor(a0, off);
+      a1 += __shfl_xor(a1, off);
+    }
+    if (g == 0) {
+      out[2 * p] = xq[2 * p] + hb[0] + a0;
+      out[2 * p + 1] = xq[2 * p + 1] + hb[1] + a1;
+    }
   }
 }
 
@@ -968,7 +983,7 @@ void prep(const double* maps, const double* target, const double* sum, const int
 }
 void head(const uint16_t* d, int C, const float* hw, const float* hb, const float* xq, float* out, size_t P,
           hipStream_t s) {
-  hipLaunchKernelGGL(k_head, dim3(grid_for(P)), dim3(256), 0, s, d, C, hw, hb, xq, out, P);
+  hipLaunchKernelGGL(k_head, dim3(grid_for(P * 8)), dim3(256), 0, s, d, C, hw, hb, xq, out, P);
 }
 void loss(const float* out, const float* tgt, const float* ihat, const double* sum, int B, int HW, float* go,
           double* l, hipStream_t s) {
