@@ -35,10 +35,11 @@ DN_WIDTHS = (64, 128, 256)
 METRIC = "Stokes packets/s at 256^3 disk; packets to fixed Q/U error, plain vs denoised"
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per cell step of the transport kernel on Rayleigh spheres:
-# the density gather (4 B) and the read-modify-write of the cell's 6 FP64
-# coherency components (6 x 8 B read + 6 x 8 B written; spheres never create
-# circular polarisation, so the 3 imaginary components are identically zero)
-BYTES_PER_STEP_SPHERE = 4 + 2 * 6 * 8
+# the density gather (4 B) and 8 B per FP64 tally atomic, one atomic per
+# coherency component of the cell (6 of the 9: spheres never create circular
+# polarisation, so the 3 imaginary components are identically zero and are
+# not tallied)
+BYTES_PER_STEP_SPHERE = 4 + 6 * 8
 
 
 def counter_record():
@@ -95,8 +96,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--packets", type=int, default=100_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=100000,
-                    help="packets of the oracle's timed sample")
+    ap.add_argument("--cpu-sample", type=int, default=400000,
+                    help="packets of the oracle's timed sample (all threads)")
+    ap.add_argument("--cpu-sample-1t", type=int, default=20000,
+                    help="packets of the oracle's one-thread sample")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a device-to-device copy of this size (counter calibration)")
     ap.add_argument("--atomic-calibration", action="store_true",
@@ -123,10 +126,12 @@ def copy_calibration(mib: int) -> None:
     print(json.dumps({"copy_calibration_bytes": n * 4, "launches": 3}))
 
 
-def cpu_baseline(cfg, sample: int):
+def cpu_baseline(cfg, sample: int, sample_1t: int):
     """The oracle as it stands, on the host cores: step 1 for the first
-    `sample` packets of the same run (same weights and streams), step 2 once
-    for all views; scaled to the whole job's packet count."""
+    `sample` packets of the same run (same weights and streams) on all
+    threads, step 2 once for all views; scaled to the whole job's packet
+    count.  Then step 1 alone on one thread for the first `sample_1t`
+    packets (packets/s per core)."""
     from oracle import oracle as O
     nth = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
     N = int(cfg["packets"][0])
@@ -138,10 +143,38 @@ def cpu_baseline(cfg, sample: int):
     del S
     step1, step2 = t1 - t0, t2 - t1
     job_s = step1 * (N / sample) + step2
+    t3 = time.perf_counter()
+    S1, _, _ = O.transport(cfg, p_end=sample_1t, n_total=N, nthreads=1)
+    step1_1t = time.perf_counter() - t3
+    del S1
     return {"value": N / job_s, "unit": "packets/s", "cores": nth, "kind": "oracle",
-            "sample": f"first {sample} packets of the {N}-packet run (step 1, {step1:.1f} s, "
-                      f"scaled by {N // sample}) + step 2 for all {len(cfg['views'])} views "
-                      f"({step2:.1f} s), FP64, {nth} OpenMP threads"}
+            "step1_packets_per_s": sample / step1,
+            "step1_packets_per_s_per_core": sample / step1 / nth,
+            "single_thread_step1_packets_per_s": sample_1t / step1_1t,
+            "host_logical_cpus": os.cpu_count(),
+            "sample": f"first {sample} packets of the {N}-packet run (step 1 on {nth} OpenMP threads, "
+                      f"{step1:.1f} s, scaled by {N // sample}) + step 2 for all {len(cfg['views'])} "
+                      f"views ({step2:.1f} s), FP64; then step 1 of the first {sample_1t} packets "
+                      f"on 1 thread ({step1_1t:.1f} s)"}
+
+
+def copy_bandwidth(mib: int = 1024, reps: int = 5) -> float:
+    """Measured device-to-device copy rate (read + write bytes / s, GB/s) of
+    a `mib` MiB buffer: best of `reps`, HIP events on the current stream."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    return 2.0 * n * 4 / (best * 1e-3) / 1e9
 
 
 def main():
@@ -218,6 +251,8 @@ def main():
     avg_t = float(np.mean(ms_t))
     bytes_launch = float(np.mean(steps)) * BYTES_PER_STEP_SPHERE
     achieved = bytes_launch / (avg_t * 1e-3) / 1e9
+    traffic = counter_traffic()
+    copy_gbs = copy_bandwidth()
     out = {
         "metric": METRIC,
         "value": value,
@@ -236,7 +271,7 @@ def main():
                    "midplane_tau": 1.0e4, "albedo": 0.5, "grains": "Rayleigh spheres",
                    "transport": "fp32, fp64 coherency tally", "seed": cfg["opts"]["seed"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic()},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
         "detail": {"kernel": "k_transport32<false,true>",
                    "schedule": opts,
                    "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, "
@@ -246,6 +281,9 @@ def main():
                    "cell_steps_per_launch": float(np.mean(steps)),
                    "cell_steps_per_s": float(np.mean(steps)) / (avg_t * 1e-3),
                    "algorithmic_bytes_per_cell_step": BYTES_PER_STEP_SPHERE,
+                   "traffic_over_algorithmic": None if traffic is None else traffic * 1e9 / bytes_launch,
+                   "measured_copy_gbs": copy_gbs,
+                   "frac_of_measured_copy": achieved / copy_gbs,
                    "scatterings": st["scatterings"], "rr_kills": st["rr_kills"]},
     }
     if dn is not None:
@@ -299,7 +337,7 @@ def main():
                        "csrc/kp_calib.hip)"}
     if not args.no_cpu_baseline:
         print("timing the oracle on a bounded sample ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample, args.cpu_sample_1t)
     ctx.close()
     print(json.dumps(out))
 

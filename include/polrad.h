@@ -114,8 +114,8 @@ typedef struct {
  *  trace_packets   number of packets per wavelength whose final state is
  *                  recorded (ids 0, trace_stride, 2 trace_stride, ...).
  *  trace_stride    >= 1.
- *  block_size      threads per block of the transport kernel (64..1024, a
- *                  multiple of 64; 0 = default 256).
+ *  block_size      threads per block of the transport kernel (64, 128, 192
+ *                  or 256; 0 = default 256; KP_ERR_ARG otherwise).
  *  blocks_per_cu   resident blocks per compute unit (0 = default).
  *  strict          1: kp_run returns KP_ERR_BUDGET if any packet hit the cap.
  *  scatter_batch   a lane that reaches a scattering point waits until this
@@ -171,55 +171,91 @@ typedef struct {
   double tau_path;
 } kp_packet_trace;
 
-/* Create a context on HIP device `device`.  *out receives an owned handle
- * (release with kp_destroy). */
+/* Create a context on HIP device `device`: the device state of one problem
+ * of the method (Sec. 2.2 grid, dust and source; Sec. 2.3 cameras).  *out
+ * receives an owned handle (release with kp_destroy).  KP_ERR_DEVICE if no
+ * HIP device is present, KP_ERR_ARG for a device index out of range. */
 kp_status kp_create(int device, kp_ctx **out);
+/* Release a context and every device buffer it owns (Sec. 2.2-2.3 state);
+ * borrowed device arrays are not freed.  NULL is ignored. */
 void kp_destroy(kp_ctx *ctx);
+/* Message of the last failed call on ctx (owned by the context, valid until
+ * its next call); covers every entry point of the Sec. 2.2-2.3 method. */
 const char *kp_last_error(const kp_ctx *ctx);
 
-/* Density rho[ncell] (float32, finite, >= 0) and optional unit alignment
- * field bhat[3][ncell] (float32 SoA, |b| = 1 within 1e-5; NULL = no
- * alignment: the grain frame coincides with the lab frame).
- * kp_set_grid copies host arrays into library-owned device memory;
- * kp_set_grid_device borrows device arrays (validated by a device pass).
+/* The medium (Sec. 2.2: density profile read in as the input of the
+ * opacities, eq. mfp-matrices; Sec. 2.1: the grain alignment direction that
+ * defines the grain frame, eq. grain-quaternion).  Density rho[ncell]
+ * (float32, finite, >= 0) and optional unit alignment field bhat[3][ncell]
+ * (float32 SoA, |b| = 1 within 1e-5; NULL = no alignment: the grain frame
+ * coincides with the lab frame).  kp_set_grid copies host arrays into
+ * library-owned device memory; kp_set_grid_device borrows device arrays
+ * (validated by a device pass: KP_ERR_ARG with the count of bad values).
  * Either resets the tally. */
 kp_status kp_set_grid(kp_ctx *ctx, const kp_grid *grid, const float *rho, const float *bhat);
 kp_status kp_set_grid_device(kp_ctx *ctx, const kp_grid *grid, const float *d_rho,
                              const float *d_bhat);
 
-/* n_lambda (1..1024) dust records, one per wavelength (copied). */
+/* Grain optics per wavelength (Sec. 2.2, eq. mfp-matrices and the
+ * user-defined cross sections and Mueller matrices; Sec. 3 dipole grains):
+ * n_lambda (1..1024) dust records, one per wavelength (copied).  KP_ERR_ARG
+ * for negative or non-finite opacities or polarizabilities. */
 kp_status kp_set_dust(kp_ctx *ctx, int32_t n_lambda, const kp_dust *dust);
+/* The radiation source whose packets are emitted (Sec. 2.2: packets are
+ * generated and given an exponentially distributed scattering optical
+ * depth); copied.  KP_ERR_ARG for an unknown kind, a non-positive
+ * luminosity or a zero pencil direction. */
 kp_status kp_set_source(kp_ctx *ctx, const kp_source *src);
-/* n_views (1..4096) cameras (copied). */
+/* Cameras of step 2 (Sec. 2.3, the camera direction Omega_cam of eq.
+ * scat-disc-sum): n_views (1..4096) views (copied), all with the same npx,
+ * npy (1..16384). */
 kp_status kp_set_views(kp_ctx *ctx, int32_t n_views, const kp_view *views);
 
-/* Step 1 + step 2 for all wavelengths in one persistent launch each:
- * packets_per_lambda[n_lambda] (host, >= 0, total >= 1).  Images stay on the
- * device; the call synchronises hip_stream before returning (it reads the
- * counters back).  Returns KP_ERR_NUMERIC / KP_ERR_BUDGET (strict) after a
- * completed run whose counters show them. */
+/* Two-step imaging (Sec. 2.3): step 1 (packet transport, Sec. 2.2 and
+ * Appendix A, tallying the scattering source of eq. scat-disc-sum) + step 2
+ * (ray-march to every camera) for all wavelengths, in one persistent launch
+ * each: packets_per_lambda[n_lambda] (host, >= 0, total >= 1).  Images stay
+ * on the device; the call synchronises hip_stream before returning (it
+ * reads the counters back).  Returns KP_ERR_NUMERIC / KP_ERR_BUDGET (strict)
+ * after a completed run whose counters show them. */
 kp_status kp_run(kp_ctx *ctx, const uint64_t *packets_per_lambda, const kp_opts *opts,
                  void *hip_stream);
-/* Step 1 only (Sec. 2.3 first step): tallies the scattering source. */
+/* Step 1 only (Sec. 2.3 first step, transport of Sec. 2.2 with the
+ * Appendix A cell solution): tallies the scattering source of eq.
+ * scat-disc-sum as each cell's incident coherency.  Same arguments, errors
+ * and synchronisation as kp_run. */
 kp_status kp_transport(kp_ctx *ctx, const uint64_t *packets_per_lambda, const kp_opts *opts,
                        void *hip_stream);
-/* Step 2 only, from the tally of the last kp_transport. */
+/* Step 2 only (Sec. 2.3 second step: eq. polarized-rt integrated along each
+ * line of sight with the Appendix A cell solution), from the tally of the
+ * last kp_transport; synchronises hip_stream.  KP_ERR_STATE without a
+ * tally. */
 kp_status kp_image(kp_ctx *ctx, void *hip_stream);
-/* Step 2 alone on a caller-supplied per-view source (wavelength 0):
+/* Step 2 alone (Sec. 2.3 second step, Appendix A with the source S) on a
+ * caller-supplied per-view source of eq. scat-disc-sum (wavelength 0):
  * d_S device [ncell][n_views][4] FP64, emissivity per unit length per unit
- * solid angle in each camera basis; d_out device [n_views][4][npy][npx]. */
+ * solid angle in each camera basis; d_out device [n_views][4][npy][npx]
+ * (both borrowed).  Synchronises hip_stream. */
 kp_status kp_image_source(kp_ctx *ctx, const double *d_S, double *d_out, void *hip_stream);
 
-/* Images [n_lambda][n_views][4][npy][npx] FP64 of the last step 2; n is the
- * element count of the destination and must equal that size. */
+/* Stokes images of the last step 2 (Sec. 2.3: the synthetic polarimetry
+ * maps), [n_lambda][n_views][4][npy][npx] FP64; n is the element count of
+ * the destination and must equal that size (KP_ERR_ARG otherwise,
+ * KP_ERR_STATE before any step 2).  kp_get_images copies to host memory and
+ * synchronises; kp_get_images_device copies on hip_stream into a borrowed
+ * device array. */
 kp_status kp_get_images(kp_ctx *ctx, double *host_out, size_t n);
 kp_status kp_get_images_device(kp_ctx *ctx, double *d_out, size_t n, void *hip_stream);
 /* Incident-coherency tally [n_lambda][ncell][9] FP64 of the last step 1
- * (components xx yy zz xy xz yz and the imaginary yz zx xy parts), per unit
- * cell volume times dx^3; n must equal that size. */
+ * (the scattering source of Sec. 2.3, eq. scat-disc-sum, before the camera
+ * projection: components xx yy zz xy xz yz and the imaginary yz zx xy
+ * parts), per unit cell volume times dx^3; n must equal that size. */
 kp_status kp_get_tally(kp_ctx *ctx, double *host_out, size_t n);
+/* Counters of the last step 1 and step 2 (Sec. 2.2 packet events; kp_stats
+ * above), copied to *out. */
 kp_status kp_get_stats(kp_ctx *ctx, kp_stats *out);
-/* Traces of the last step 1: n must equal n_lambda * trace_packets. */
+/* Final states of the traced packets of the last step 1 (Sec. 2.2 packet
+ * histories; kp_packet_trace above): n must equal n_lambda * trace_packets. */
 kp_status kp_get_trace(kp_ctx *ctx, kp_packet_trace *out, size_t n);
 
 #ifdef __cplusplus

@@ -74,39 +74,48 @@ extern "C" {
 
 typedef struct kp_dn kp_dn;
 
-/* Create a denoiser of n_levels (2..6) levels with widths[n_levels] (host;
+/* Create a denoiser of the Sec. 2.3 images (not in the paper: the learned
+ * part above) of n_levels (2..6) levels with widths[n_levels] (host;
  * each a multiple of 16 in [16, 512]) on HIP device `device`, with all
  * parameters zero.  *out receives an owned handle (release with
  * kp_dn_destroy). */
 kp_status kp_dn_create(int device, const int32_t *widths, int32_t n_levels, kp_dn **out);
 /* As kp_dn_create for inputs of `runs` (1 or 2) independent runs per image
- * (see two-run inputs above); kp_dn_create is runs = 1. */
+ * (see two-run inputs above; two Sec. 2.3 imaging runs with independent
+ * packet streams); kp_dn_create is runs = 1. */
 kp_status kp_dn_create_runs(int device, const int32_t *widths, int32_t n_levels, int32_t runs, kp_dn **out);
+/* Release a denoiser handle and its device memory (not in the paper; NULL
+ * is ignored), and the message of its last failed call. */
 void kp_dn_destroy(kp_dn *dn);
 const char *kp_dn_last_error(const kp_dn *dn);
 
-/* Number of FP32 parameters (the length of the flat array above). */
+/* Number of FP32 parameters (the length of the flat array above; the
+ * learned part, not in the paper). */
 kp_status kp_dn_num_params(const kp_dn *dn, size_t *n);
-/* Copy n = kp_dn_num_params parameters from / to host memory.  Setting the
- * parameters clears the Adam moments and step count. */
+/* Copy n = kp_dn_num_params parameters from / to host memory (learned part,
+ * not in the paper).  Setting the parameters clears the Adam moments and step
+ * count; KP_ERR_ARG for a wrong n or a non-finite value. */
 kp_status kp_dn_set_params(kp_dn *dn, const float *host_params, size_t n);
 kp_status kp_dn_get_params(kp_dn *dn, float *host_params, size_t n);
 /* Gradient of the loss of the last kp_dn_backward / kp_dn_train_step with
- * respect to every parameter, same layout (host copy of n floats). */
+ * respect to every parameter, same layout (host copy of n floats; learned
+ * part, not in the paper). */
 kp_status kp_dn_get_grads(kp_dn *dn, float *host_grads, size_t n);
-/* Adam state for checkpoint and resume: first and second moments (n floats
- * each, host) and the number of steps taken. */
+/* Adam state for checkpoint and resume (learned part, not in the paper):
+ * first and second moments (n floats each, host) and the number of steps
+ * taken. */
 kp_status kp_dn_get_adam(kp_dn *dn, float *host_m, float *host_v, size_t n, int32_t *step);
 kp_status kp_dn_set_adam(kp_dn *dn, const float *host_m, const float *host_v, size_t n, int32_t step);
 
-/* Denoise: d_maps (device, read; [batch][4 runs][height][width]) -> d_out
- * (device, written, [batch][4][height][width]; may not alias d_maps).
- * Asynchronous on hip_stream. */
+/* Denoise Sec. 2.3 Stokes images (not in the paper): d_maps (device, read;
+ * [batch][4 runs][height][width]) -> d_out (device, written,
+ * [batch][4][height][width]; may not alias d_maps).  Asynchronous on
+ * hip_stream. */
 kp_status kp_dn_infer(kp_dn *dn, const double *d_maps, double *d_out, int32_t batch, int32_t height,
                       int32_t width, void *hip_stream);
-/* Test-time averaging: as kp_dn_infer, with q' and u' the mean over the
- * eight dihedral transforms of each input (the aug codes of kp_dn_backward)
- * of the network's prediction for the transformed image, mapped back to the
+/* Test-time averaging (not in the paper; Sec. 2.3 images): as kp_dn_infer,
+ * with q' and u' the mean over the eight dihedral transforms of each input
+ * (the aug codes of kp_dn_backward) of the network's prediction for the transformed image, mapped back to the
  * original pixels and Stokes signs; only the four codes without a quarter
  * turn when height != width.  Eight (four) forward passes.  The average is
  * exactly equivariant under the group, and by convexity its squared Q/U
@@ -114,8 +123,10 @@ kp_status kp_dn_infer(kp_dn *dn, const double *d_maps, double *d_out, int32_t ba
 kp_status kp_dn_infer_tta(kp_dn *dn, const double *d_maps, double *d_out, int32_t batch, int32_t height,
                           int32_t width, void *hip_stream);
 
-/* Loss and gradients for the pairs (d_low[b], d_high[b]) (device maps;
- * d_low [batch][4 runs][height][width], d_high [batch][4][height][width]).
+/* Loss and gradients (not in the paper; pairs of Sec. 2.3 images of the
+ * same scene at few and many packets) for the pairs (d_low[b], d_high[b])
+ * (device maps; d_low [batch][4 runs][height][width], d_high
+ * [batch][4][height][width]).
  * host_aug (NULL = identity) holds one code per image, 0..7, of the
  * dihedral transform applied to both maps of a pair before the network:
  * code a = r + 4 f mirrors the width axis when f = 1, then rotates the image
@@ -127,14 +138,17 @@ kp_status kp_dn_backward(kp_dn *dn, const double *d_low, const double *d_high, i
                          int32_t height, int32_t width, const int32_t *host_aug, double *loss,
                          void *hip_stream);
 /* One Adam step with learning rate lr (> 0) from the gradients of the last
- * kp_dn_backward.  Asynchronous on hip_stream. */
+ * kp_dn_backward (learned part, not in the paper).  Asynchronous on
+ * hip_stream. */
 kp_status kp_dn_adam_step(kp_dn *dn, float lr, void *hip_stream);
-/* kp_dn_backward followed by kp_dn_adam_step. */
+/* kp_dn_backward followed by kp_dn_adam_step (learned part, not in the
+ * paper). */
 kp_status kp_dn_train_step(kp_dn *dn, const double *d_low, const double *d_high, int32_t batch,
                            int32_t height, int32_t width, const int32_t *host_aug, float lr,
                            double *loss, void *hip_stream);
 
-/* Device time of the last kp_dn_infer / kp_dn_backward, in ms, split into
+/* Device time of the last kp_dn_infer / kp_dn_backward (learned part, not
+ * in the paper), in ms, split into
  * the 3x3 convolution kernels (forward and input gradient), the weight
  * gradient kernels, and everything else; HIP events on the call's stream. */
 typedef struct {

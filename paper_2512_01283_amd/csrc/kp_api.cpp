@@ -201,7 +201,8 @@ kp_status check_ready(kp_ctx* ctx) {
 }
 
 kp_status image_launch(kp_ctx* ctx, bool user_source, const double* d_S, double* d_out,
-                       int n_lambda, hipStream_t s) {
+                       int n_lambda, hipStream_t s, const DustDev* d_dust, const ViewDev* d_views,
+                       const double* d_tally) {
   ImageArgs a{};
   a.rho = ctx->d_rho;
   if (ctx->d_bhat) {
@@ -211,13 +212,13 @@ kp_status image_launch(kp_ctx* ctx, bool user_source, const double* d_S, double*
   }
   a.nx = ctx->grid.nx; a.ny = ctx->grid.ny; a.nz = ctx->grid.nz;
   a.x0 = ctx->grid.x0; a.y0 = ctx->grid.y0; a.z0 = ctx->grid.z0; a.dx = ctx->grid.dx;
-  a.dust = ctx->d_dust;
-  a.views = ctx->d_views;
+  a.dust = d_dust;
+  a.views = d_views;
   a.n_views = (int)ctx->views.size();
   a.n_lambda = n_lambda;
   a.npx = ctx->views[0].npx;
   a.npy = ctx->views[0].npy;
-  a.tally = ctx->d_tally;
+  a.tally = d_tally;
   a.user_S = d_S;
   a.images = d_out;
   a.ncell = ctx->ncell;
@@ -228,6 +229,138 @@ kp_status image_launch(kp_ctx* ctx, bool user_source, const double* d_S, double*
   KP_HIP(hipEventRecord(ctx->ev[2], s), "event record");
   KP_HIP(launch_image(a, ctx->d_bhat != nullptr, sphere, user_source, s), "imaging kernel launch");
   KP_HIP(hipEventRecord(ctx->ev[3], s), "event record");
+  return KP_OK;
+}
+
+bool all_spheres(const kp_ctx* ctx) {
+  for (const kp_dust& d : ctx->dust)
+    if (!is_sphere(d)) return false;
+  return true;
+}
+
+// Checks of a step-1 call (kp_transport, kp_run) before any
+// launch; *total receives the packet count over all wavelengths.
+kp_status check_run_args(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, uint64_t* total_out) {
+  kp_status st = check_ready(ctx);
+  if (st) return st;
+  if (!counts || !o) return fail(ctx, KP_ERR_ARG, "packets or options are NULL");
+  const int nl = (int)ctx->dust.size();
+  uint64_t total = 0;
+  for (int l = 0; l < nl; ++l) {
+    if (counts[l] > (1ull << 40)) return fail(ctx, KP_ERR_ARG, "packet count of wavelength %d too large", l);
+    total += counts[l];
+  }
+  if (total == 0) return fail(ctx, KP_ERR_ARG, "no packets");
+  if (o->tally_mode != 0) return fail(ctx, KP_ERR_ARG, "tally_mode must be 0");
+  if (o->max_events < 1 || o->max_events > (1 << 30)) return fail(ctx, KP_ERR_ARG, "max_events out of range");
+  if (!(o->rr_wmin >= 0.0) || !std::isfinite(o->rr_wmin) ||
+      (o->rr_wmin > 0.0 && !(o->rr_psurv > 0.0 && o->rr_psurv <= 1.0)))
+    return fail(ctx, KP_ERR_ARG, "roulette parameters out of range");
+  if (o->trace_packets > 0 && o->trace_stride < 1) return fail(ctx, KP_ERR_ARG, "trace_stride must be >= 1");
+  const int bs = o->block_size ? o->block_size : 256;
+  if (bs < 64 || bs > 256 || bs % 64) return fail(ctx, KP_ERR_ARG, "block_size must be 64, 128, 192 or 256");
+  if (o->blocks_per_cu < 0 || o->blocks_per_cu > 64) return fail(ctx, KP_ERR_ARG, "blocks_per_cu out of range");
+  if (o->transport_fp64 < 0 || o->transport_fp64 > 2) return fail(ctx, KP_ERR_ARG, "transport_fp64 must be 0, 1 or 2");
+  if (o->scatter_batch < 0 || o->scatter_batch > 64) return fail(ctx, KP_ERR_ARG, "scatter_batch must be in 0..64");
+  if (o->scatter_wait < 0 || o->scatter_wait > 1024) return fail(ctx, KP_ERR_ARG, "scatter_wait must be in 0..1024");
+  *total_out = total;
+  return KP_OK;
+}
+
+// Device buffers of one step-1 launch.
+struct RunBuffers {
+  DustDev* dust;                 // per-wavelength constants (uploaded by the caller)
+  double* tally;                 // [lambda][cell][stride]
+  StatsDev* stats;
+  unsigned long long* counter;   // work counter of the persistent launch
+  TraceDev* traces;              // [lambda][trace_packets] or null
+};
+
+// Step 1 on prepared buffers: tally and counters cleared by kernels, the
+// persistent transport launch, then (after a synchronise) the counters
+// copied into ctx->stats.  Arguments are already checked.
+kp_status transport_launch(kp_ctx* ctx, const kp_opts* o, uint64_t total, const RunBuffers& b,
+                           hipStream_t s) {
+  const int nl = (int)ctx->dust.size();
+  const bool all_sphere = all_spheres(ctx);
+  const size_t trace_need = (size_t)nl * o->trace_packets;
+  KP_HIP(launch_tally_init(b.tally, ctx->d_rho, ctx->d_bhat,
+                           ctx->d_bhat ? ctx->d_bhat + ctx->ncell : nullptr,
+                           ctx->d_bhat ? ctx->d_bhat + 2 * ctx->ncell : nullptr, ctx->ncell, nl, all_sphere, s),
+         "tally initialisation");
+  KP_HIP(launch_fill_zero(b.stats, sizeof(StatsDev), s), "stats clear");
+  KP_HIP(launch_fill_zero(b.counter, sizeof(unsigned long long), s), "counter clear");
+  if (trace_need) KP_HIP(launch_fill_zero(b.traces, trace_need * sizeof(TraceDev), s), "trace clear");
+
+  TransportArgs a{};
+  a.rho = ctx->d_rho;
+  if (ctx->d_bhat) {
+    a.bx = ctx->d_bhat;
+    a.by = ctx->d_bhat + ctx->ncell;
+    a.bz = ctx->d_bhat + 2 * ctx->ncell;
+  }
+  a.nx = ctx->grid.nx; a.ny = ctx->grid.ny; a.nz = ctx->grid.nz;
+  a.x0 = ctx->grid.x0; a.y0 = ctx->grid.y0; a.z0 = ctx->grid.z0; a.dx = ctx->grid.dx;
+  a.dust = b.dust;
+  a.n_lambda = nl;
+  a.total = total;
+  a.src_kind = ctx->src.kind;
+  a.sx = ctx->src.pos[0]; a.sy = ctx->src.pos[1]; a.sz = ctx->src.pos[2];
+  a.dx_ = ctx->src.dir[0]; a.dy_ = ctx->src.dir[1]; a.dz_ = ctx->src.dir[2];
+  a.seed = o->seed;
+  a.rr_wmin = o->rr_wmin;
+  a.rr_psurv = o->rr_psurv;
+  a.max_events = (int)o->max_events;
+  a.tally = b.tally;
+  a.ncell = ctx->ncell;
+  a.counter = b.counter;
+  a.stats = b.stats;
+  a.traces = b.traces;
+  a.trace_count = o->trace_packets;
+  a.trace_stride = o->trace_stride ? o->trace_stride : 1;
+  a.scatter_batch = o->scatter_batch ? o->scatter_batch : 8;
+  a.scatter_wait = o->scatter_wait ? o->scatter_wait : 16;
+
+  const bool sphere = all_sphere;
+  const bool aligned = ctx->d_bhat != nullptr;
+  // automatic precision: FP64 polarisation arithmetic for dichroic (aligned,
+  // non-spherical) grains, FP32 otherwise
+  const bool fp64 = o->transport_fp64 == 1 || (o->transport_fp64 == 0 && aligned && !sphere);
+  const int bs = o->block_size ? o->block_size : 256;
+  int bpc = o->blocks_per_cu;
+  if (bpc == 0) {
+    bpc = transport_max_blocks_per_cu(fp64, aligned, sphere, bs);
+    if (bpc < 1) bpc = 1;
+    if (bpc > 8) bpc = 8;
+  }
+  uint64_t blocks = (uint64_t)ctx->cu_count * bpc;
+  const uint64_t need_blocks = (total + bs - 1) / bs;
+  if (blocks > need_blocks) blocks = need_blocks;
+  KP_HIP(hipEventRecord(ctx->ev[0], s), "event record");
+  KP_HIP(launch_transport(a, fp64, aligned, sphere, (int)blocks, bs, s), "transport kernel launch");
+  KP_HIP(hipEventRecord(ctx->ev[1], s), "event record");
+  KP_HIP(hipStreamSynchronize(s), "transport kernel");
+
+  StatsDev h{};
+  KP_HIP(hipMemcpy(&h, b.stats, sizeof h, hipMemcpyDeviceToHost), "stats readback");
+  kp_stats& r = ctx->stats;
+  std::memset(&r, 0, sizeof r);
+  r.cell_steps = (int64_t)h.cell_steps; r.scatterings = (int64_t)h.scatterings;
+  r.trials = (int64_t)h.trials; r.rr_kills = (int64_t)h.rr_kills;
+  r.rr_survivals = (int64_t)h.rr_survivals; r.escaped = (int64_t)h.escaped;
+  r.budget = (int64_t)h.budget; r.numeric = (int64_t)h.numeric; r.packets = (int64_t)h.packets;
+  r.tally_flushes = (int64_t)h.tally_flushes;
+  r.e_emitted = h.e_emitted; r.e_escaped = h.e_escaped; r.e_absorbed = h.e_absorbed;
+  r.e_rr_killed = h.e_rr_killed; r.e_rr_gained = h.e_rr_gained; r.e_budget = h.e_budget;
+  r.e_scat_delta = h.e_scat_delta;
+  float ms = 0.0f;
+  KP_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]), "event timing");
+  r.ms_transport = ms;
+  if (r.packets != (int64_t)total)
+    return fail(ctx, KP_ERR_DEVICE, "transport finished %lld of %llu packets", (long long)r.packets,
+                (unsigned long long)total);
+  if (r.numeric) return fail(ctx, KP_ERR_NUMERIC, "%lld packets reached a non-finite state", (long long)r.numeric);
+  if (o->strict && r.budget) return fail(ctx, KP_ERR_BUDGET, "%lld packets hit the event cap", (long long)r.budget);
   return KP_OK;
 }
 
@@ -393,33 +526,13 @@ kp_status kp_set_views(kp_ctx* ctx, int32_t n_views, const kp_view* v) {
 
 kp_status kp_transport(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, void* stream) {
   if (!ctx) return KP_ERR_ARG;
-  kp_status st = check_ready(ctx);
-  if (st) return st;
-  if (!counts || !o) return fail(ctx, KP_ERR_ARG, "packets or options are NULL");
-  const int nl = (int)ctx->dust.size();
   uint64_t total = 0;
-  for (int l = 0; l < nl; ++l) {
-    if (counts[l] > (1ull << 40)) return fail(ctx, KP_ERR_ARG, "packet count of wavelength %d too large", l);
-    total += counts[l];
-  }
-  if (total == 0) return fail(ctx, KP_ERR_ARG, "no packets");
-  if (o->tally_mode != 0) return fail(ctx, KP_ERR_ARG, "tally_mode must be 0");
-  if (o->max_events < 1 || o->max_events > (1 << 30)) return fail(ctx, KP_ERR_ARG, "max_events out of range");
-  if (!(o->rr_wmin >= 0.0) || !std::isfinite(o->rr_wmin) ||
-      (o->rr_wmin > 0.0 && !(o->rr_psurv > 0.0 && o->rr_psurv <= 1.0)))
-    return fail(ctx, KP_ERR_ARG, "roulette parameters out of range");
-  if (o->trace_packets > 0 && o->trace_stride < 1) return fail(ctx, KP_ERR_ARG, "trace_stride must be >= 1");
-  const int bs = o->block_size ? o->block_size : 256;
-  if (bs < 64 || bs > 256 || bs % 64) return fail(ctx, KP_ERR_ARG, "block_size must be 64, 128, 192 or 256");
-  if (o->blocks_per_cu < 0 || o->blocks_per_cu > 64) return fail(ctx, KP_ERR_ARG, "blocks_per_cu out of range");
-  if (o->transport_fp64 < 0 || o->transport_fp64 > 2) return fail(ctx, KP_ERR_ARG, "transport_fp64 must be 0, 1 or 2");
-  if (o->scatter_batch < 0 || o->scatter_batch > 64) return fail(ctx, KP_ERR_ARG, "scatter_batch must be in 0..64");
-  if (o->scatter_wait < 0 || o->scatter_wait > 1024) return fail(ctx, KP_ERR_ARG, "scatter_wait must be in 0..1024");
-
+  kp_status st = check_run_args(ctx, counts, o, &total);
+  if (st) return st;
   KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
-  bool all_sphere = true;
-  for (int l = 0; l < nl; ++l) all_sphere = all_sphere && is_sphere(ctx->dust[l]);
+  const int nl = (int)ctx->dust.size();
+  const bool all_sphere = all_spheres(ctx);
   const int ts = tally_stride(all_sphere);
   const size_t tally_need = (size_t)nl * ctx->ncell * ts;
   const size_t trace_need = (size_t)nl * o->trace_packets;
@@ -430,93 +543,18 @@ kp_status kp_transport(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, vo
   if (extra > free_b) return fail(ctx, KP_ERR_OOM, "tally needs %zu bytes, %zu free", extra, free_b);
   if ((st = ensure(ctx, &ctx->d_tally, &ctx->tally_n, tally_need, "tally allocation"))) return st;
   if ((st = ensure(ctx, &ctx->d_traces, &ctx->traces_n, trace_need, "trace allocation"))) return st;
-
   fill_dust(ctx, counts, ctx->hdust);
   if ((st = upload_small(ctx, s))) return st;
-  KP_HIP(launch_tally_init(ctx->d_tally, ctx->d_rho, ctx->d_bhat,
-                           ctx->d_bhat ? ctx->d_bhat + ctx->ncell : nullptr,
-                           ctx->d_bhat ? ctx->d_bhat + 2 * ctx->ncell : nullptr, ctx->ncell, nl, all_sphere, s),
-         "tally initialisation");
-  KP_HIP(launch_fill_zero(ctx->d_stats, sizeof(StatsDev), s), "stats clear");
-  KP_HIP(launch_fill_zero(ctx->d_counter, sizeof(unsigned long long), s), "counter clear");
-  if (trace_need) KP_HIP(launch_fill_zero(ctx->d_traces, trace_need * sizeof(TraceDev), s), "trace clear");
-
-  TransportArgs a{};
-  a.rho = ctx->d_rho;
-  if (ctx->d_bhat) {
-    a.bx = ctx->d_bhat;
-    a.by = ctx->d_bhat + ctx->ncell;
-    a.bz = ctx->d_bhat + 2 * ctx->ncell;
-  }
-  a.nx = ctx->grid.nx; a.ny = ctx->grid.ny; a.nz = ctx->grid.nz;
-  a.x0 = ctx->grid.x0; a.y0 = ctx->grid.y0; a.z0 = ctx->grid.z0; a.dx = ctx->grid.dx;
-  a.dust = ctx->d_dust;
-  a.n_lambda = nl;
-  a.total = total;
-  a.src_kind = ctx->src.kind;
-  a.sx = ctx->src.pos[0]; a.sy = ctx->src.pos[1]; a.sz = ctx->src.pos[2];
-  a.dx_ = ctx->src.dir[0]; a.dy_ = ctx->src.dir[1]; a.dz_ = ctx->src.dir[2];
-  a.seed = o->seed;
-  a.rr_wmin = o->rr_wmin;
-  a.rr_psurv = o->rr_psurv;
-  a.max_events = (int)o->max_events;
-  a.tally = ctx->d_tally;
-  a.ncell = ctx->ncell;
-  a.counter = ctx->d_counter;
-  a.stats = ctx->d_stats;
-  a.traces = ctx->d_traces;
-  a.trace_count = o->trace_packets;
-  a.trace_stride = o->trace_stride ? o->trace_stride : 1;
-  a.scatter_batch = o->scatter_batch ? o->scatter_batch : 8;
-  a.scatter_wait = o->scatter_wait ? o->scatter_wait : 16;
-
-  bool sphere = true;
-  for (int l = 0; l < nl; ++l) sphere = sphere && ctx->hdust[l].sphere;
-  const bool aligned = ctx->d_bhat != nullptr;
-  // automatic precision: FP64 polarisation arithmetic for dichroic (aligned,
-  // non-spherical) grains, FP32 otherwise
-  const bool fp64 = o->transport_fp64 == 1 || (o->transport_fp64 == 0 && aligned && !sphere);
-  int bpc = o->blocks_per_cu;
-  if (bpc == 0) {
-    bpc = transport_max_blocks_per_cu(fp64, aligned, sphere, bs);
-    if (bpc < 1) bpc = 1;
-    if (bpc > 8) bpc = 8;
-  }
-  uint64_t blocks = (uint64_t)ctx->cu_count * bpc;
-  const uint64_t need_blocks = (total + bs - 1) / bs;
-  if (blocks > need_blocks) blocks = need_blocks;
-  KP_HIP(hipEventRecord(ctx->ev[0], s), "event record");
-  KP_HIP(launch_transport(a, fp64, aligned, sphere, (int)blocks, bs, s), "transport kernel launch");
-  KP_HIP(hipEventRecord(ctx->ev[1], s), "event record");
-  KP_HIP(hipStreamSynchronize(s), "transport kernel");
-
-  StatsDev h{};
-  KP_HIP(hipMemcpy(&h, ctx->d_stats, sizeof h, hipMemcpyDeviceToHost), "stats readback");
-  kp_stats& r = ctx->stats;
-  std::memset(&r, 0, sizeof r);
-  r.cell_steps = (int64_t)h.cell_steps; r.scatterings = (int64_t)h.scatterings;
-  r.trials = (int64_t)h.trials; r.rr_kills = (int64_t)h.rr_kills;
-  r.rr_survivals = (int64_t)h.rr_survivals; r.escaped = (int64_t)h.escaped;
-  r.budget = (int64_t)h.budget; r.numeric = (int64_t)h.numeric; r.packets = (int64_t)h.packets;
-  r.tally_flushes = (int64_t)h.tally_flushes;
-  r.e_emitted = h.e_emitted; r.e_escaped = h.e_escaped; r.e_absorbed = h.e_absorbed;
-  r.e_rr_killed = h.e_rr_killed; r.e_rr_gained = h.e_rr_gained; r.e_budget = h.e_budget;
-  r.e_scat_delta = h.e_scat_delta;
-  float ms = 0.0f;
-  KP_HIP(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]), "event timing");
-  r.ms_transport = ms;
+  const RunBuffers buf{ctx->d_dust, ctx->d_tally, ctx->d_stats, ctx->d_counter, ctx->d_traces};
+  st = transport_launch(ctx, o, total, buf, s);
+  if (st == KP_ERR_DEVICE || st == KP_ERR_OOM) return st;
   ctx->tally_lambda = nl;
   ctx->tally_ts = ts;
   ctx->tally_nc = tally_components(all_sphere);
   ctx->have_tally = true;
   ctx->have_images = false;
   ctx->traces_valid = trace_need;
-  if (r.packets != (int64_t)total)
-    return fail(ctx, KP_ERR_DEVICE, "transport finished %lld of %llu packets", (long long)r.packets,
-                (unsigned long long)total);
-  if (r.numeric) return fail(ctx, KP_ERR_NUMERIC, "%lld packets reached a non-finite state", (long long)r.numeric);
-  if (o->strict && r.budget) return fail(ctx, KP_ERR_BUDGET, "%lld packets hit the event cap", (long long)r.budget);
-  return KP_OK;
+  return st;
 }
 
 kp_status kp_image(kp_ctx* ctx, void* stream) {
@@ -530,7 +568,8 @@ kp_status kp_image(kp_ctx* ctx, void* stream) {
   const size_t need = (size_t)nl * ctx->views.size() * 4 * ctx->views[0].npx * ctx->views[0].npy;
   if ((st = ensure(ctx, &ctx->d_images, &ctx->images_n, need, "image allocation"))) return st;
   if ((st = upload_small(ctx, s))) return st;
-  if ((st = image_launch(ctx, false, nullptr, ctx->d_images, nl, s))) return st;
+  if ((st = image_launch(ctx, false, nullptr, ctx->d_images, nl, s, ctx->d_dust, ctx->d_views,
+                         ctx->d_tally))) return st;
   KP_HIP(hipStreamSynchronize(s), "imaging kernel");
   float ms = 0.0f;
   KP_HIP(hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]), "event timing");
@@ -557,7 +596,7 @@ kp_status kp_image_source(kp_ctx* ctx, const double* d_S, double* d_out, void* s
   std::vector<uint64_t> ones(ctx->dust.size(), 1);
   fill_dust(ctx, ones.data(), ctx->hdust);
   if ((st = upload_small(ctx, s))) return st;
-  if ((st = image_launch(ctx, true, d_S, d_out, 1, s))) return st;
+  if ((st = image_launch(ctx, true, d_S, d_out, 1, s, ctx->d_dust, ctx->d_views, ctx->d_tally))) return st;
   KP_HIP(hipStreamSynchronize(s), "imaging kernel");
   float ms = 0.0f;
   KP_HIP(hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]), "event timing");

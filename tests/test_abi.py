@@ -23,6 +23,38 @@ def test_header_declares_the_boundary():
         assert must in names
 
 
+CITATION = re.compile(r"Sec\. \d|Appendix|App\. A|eq\. [a-z]|not in the paper|callers that cannot")
+
+
+def declaration_comments(path):
+    """(name, comment) for every entry point of a header: the comment block
+    between the previous declaration and this one; a declaration with no
+    comment of its own shares the one of the declaration before it."""
+    txt = open(path).read()
+    body = txt[txt.index('extern "C" {'):]
+    out, prev_end, prev_comment = [], 0, ""
+    for m in re.finditer(r"^\s*(?:kp_status|void|const char \*)\s*(kp_\w+)\s*\([^;]*;", body, re.M):
+        gap = body[prev_end:m.start()]
+        # comments that open a line (not the trailing comments of struct fields)
+        comments = re.findall(r"^[ \t]*(/\*.*?\*/)", gap, re.M | re.S)
+        if comments:
+            prev_comment = re.sub(r"\s*\n\s*\*?\s*", " ", comments[-1])
+        out.append((m.group(1), prev_comment))
+        prev_end = m.end()
+    return out
+
+
+@pytest.mark.parametrize("header", ["polrad.h", "polrad_denoiser.h"])
+def test_every_declaration_cites_its_passage(header):
+    """Each entry point's comment names the passage of the paper that defines
+    the operation (section, equation or appendix), or says that the learned
+    denoiser is not in the paper."""
+    decl = declaration_comments(os.path.join(ROOT, "include", header))
+    assert len(decl) >= 10
+    missing = [n for n, c in decl if not CITATION.search(c)]
+    assert not missing, missing
+
+
 def test_library_exports_every_declared_symbol():
     from paper_2512_01283_amd import polrad as P
     lib = ctypes.CDLL(P.LIB_PATH)

@@ -2,11 +2,12 @@
 seeded inputs and the same Philox packet streams.
 
 Bars: FP64 transport -- identical event sequences and 1e-12 (Stokes relative
-to the packet weight, directions absolute); FP32 transport -- 1e-5 on the
-packets whose event sequence matches the oracle's (an FP32 rounding can flip
-a scatter/cross or accept/reject decision, which the event hash detects);
-images -- 1e-10 of the image maximum where the step-1 arithmetic is FP64 and
-the packets identical, else per-pixel agreement within 3 Monte Carlo sigma.
+to the packet weight, directions absolute); FP32 polarisation arithmetic on
+spherical grains (the default for them) -- identical event sequences for
+every traced packet and 1e-5 relative per packet; forced FP32 on dichroic
+grains -- see test_aligned_slab_clump_forced_fp32; images -- 1e-10 of the
+image maximum where the step-1 arithmetic is FP64 and the packets identical,
+else per-pixel agreement within 3 Monte Carlo sigma.
 """
 import math
 
@@ -69,7 +70,7 @@ def test_config0_fp32(O):
     ctx = gpu_run(cfg, trace_packets=2000, transport_fp64=0)
     img_o, batches = oracle_batches(cfg)
     _, tr_o, _ = O.transport(cfg, p_end=2000, tally=False, traces=True)
-    compare_traces(ctx.traces(), tr_o, 1e-5, 0.99, "sphere32 fp32", tau_coef=1e-6)
+    compare_traces(ctx.traces(), tr_o, 1e-5, 1.0, "sphere32 fp32")
     compare_images_stat(ctx.images()[0], img_o, batches, label="sphere32 fp32")
 
 
@@ -115,14 +116,17 @@ def test_aligned_slab_clump_forced_fp32(O):
     (transport_fp64 = 2).  A thick dichroic cell multiplies the grain-frame
     components I+Q and I-Q by e^{-x_A} and e^{-x_B} with |x_A - x_B| up to
     ~10, amplifying the FP32 representation error (~6e-8 I) of the smaller
-    one by up to e^{|x_A - x_B|}: most packets meet 1e-5 + 1e-6 tau_path, a
-    few per thousand do not, none exceeds 2e-3; the images agree within the
-    Monte Carlo noise."""
+    one by up to e^{|x_A - x_B|}.  Allowance per packet: 1e-5 + 1e-7 tau_path
+    (each segment's exponent x, formed in FP64, is rounded to FP32 before the
+    exponential: a relative error 2^-24 |x| of e^{-x}, summed over the path
+    ~6e-8 tau_path).  Most packets meet it; the few whose path crosses a
+    strongly dichroic thick cell need not, none exceeds 2e-3; the images agree
+    within the Monte Carlo noise."""
     say("case: slab_clump128 forced fp32 3e4 packets")
     cfg = W.slab_clump(packets=30000)
     ctx = gpu_run(cfg, trace_packets=3000, transport_fp64=2)
     _, tr_o, _ = O.transport(cfg, p_end=3000, tally=False, traces=True)
-    compare_traces(ctx.traces(), tr_o, 1e-5, 0.98, "slab_clump fp32", tau_coef=1e-6,
+    compare_traces(ctx.traces(), tr_o, 1e-5, 0.98, "slab_clump fp32", tau_coef=1e-7,
                    frac_within=0.98, hard_cap=2e-3)
     img_o, batches = oracle_batches(cfg)
     img_g = ctx.images()[0]
@@ -136,7 +140,7 @@ def test_disk_small_images(O):
     cfg = W.flared_disk(n=64, packets=40000, npix=64)
     ctx = gpu_run(cfg, trace_packets=4000)
     _, tr_o, _ = O.transport(cfg, p_end=4000, tally=False, traces=True)
-    compare_traces(ctx.traces(), tr_o, 1e-5, 0.98, "disk64 fp32", tau_coef=1e-6)
+    compare_traces(ctx.traces(), tr_o, 1e-5, 1.0, "disk64 fp32")
     img_o, batches = oracle_batches(cfg)
     compare_images_stat(ctx.images()[0], img_o, batches, label="disk64 fp32")
 
@@ -154,7 +158,7 @@ def test_disk_full_size_sampled(O):
     tr_g = ctx.traces()
     ids = np.arange(0, 100_000_000, 100_000, dtype=np.uint64)
     tr_o = O.trace_packets(cfg, ids)
-    compare_traces(tr_g, tr_o, 1e-5, 0.98, "disk256 sampled", tau_coef=1e-6)
+    compare_traces(tr_g, tr_o, 1e-5, 1.0, "disk256 sampled")
     img = ctx.images()[0]
     assert np.isfinite(img).all()
     assert stokes_bound(img, 1e-6, 1e-6)
@@ -162,6 +166,19 @@ def test_disk_full_size_sampled(O):
     assert abs(bal - st["e_emitted"]) < 1e-5 * st["e_emitted"]
     assert st["packets"] == 100_000_000 and st["numeric"] == 0
     assert 0 < st["tally_flushes"] <= st["cell_steps"]
+    # The FP64 tally is a plain (uncompensated) sum; its rounding is bounded
+    # by rerunning the same packets: only the order of the FP64 atomic
+    # additions differs between runs, so the images' difference is the size
+    # of the summation's rounding, to be compared with the Monte Carlo noise
+    # (~1e-3 of I per pixel at this packet count).
+    again = gpu_run(cfg, trace_packets=0)
+    img2 = again.images()[0]
+    imax = np.abs(img[:, 0]).max(axis=(-1, -2))[:, None, None, None]
+    d = np.abs(img2 - img) / imax
+    pmax = np.sqrt(img[:, 1] ** 2 + img[:, 2] ** 2).max(axis=(-1, -2))
+    dqu = np.abs(img2[:, 1:3] - img[:, 1:3]).max(axis=(1, 2, 3)) / pmax
+    say(f"disk256 rerun: max |dS|/I_max = {d.max():.3e}, max |d(Q,U)|/max|P| = {dqu.max():.3e}")
+    assert d.max() < 1e-11 and dqu.max() < 1e-9
 
 
 @pytest.mark.parametrize("fp64", [1, 0, 2])
@@ -223,6 +240,70 @@ def test_batched_wavelengths(O):
         compare_traces(tr[lam][: min(n, 500)], tr_o, 1e-10, 1.0, f"batched lam={lam}")
         img_o, batches = oracle_batches(cfg, nb=6, lam=lam)
         compare_images_stat(img_g[lam], img_o, batches, label=f"batched lam={lam}")
+
+
+def test_event_cap_and_strict_mode(O):
+    """Termination by the scattering-event cap (reading R8): with
+    max_events = 3 on the albedo-1 sphere of radial optical depth 3 most
+    packets reach the cap; capped packets end with kind 5 after exactly 3
+    scatterings, with the oracle's event sequence (the cap event included),
+    cell, direction and weight; the counters and the capped energy agree and
+    the energy budget closes.  Strict mode reports the cap as KP_ERR_BUDGET
+    after a completed run whose images are kept."""
+    from paper_2512_01283_amd import polrad as P
+    say("case: sphere32 fp64 tau 3, max_events 3")
+    cfg = W.uniform_sphere(packets=4000, tau_radius=3.0)
+    cfg["opts"] = dict(cfg["opts"], max_events=3)
+    ctx = gpu_run(cfg, trace_packets=4000, transport_fp64=1)
+    tr_g, st = ctx.traces(), ctx.stats()
+    _, tr_o, st_o = O.transport(cfg, traces=True, tally=False)
+    compare_traces(tr_g, tr_o, 1e-12, 1.0, "event cap")
+    capped = tr_g["end_kind"] == 5
+    say(f"event cap: {capped.sum()} of {len(tr_g)} packets capped")
+    assert capped.sum() > 400 and (tr_g["events"][capped] == 3).all()
+    assert (tr_g["events"][~capped] <= 3).all()
+    assert st["budget"] == st_o["budget"] == capped.sum()
+    assert abs(st["e_budget"] - st_o["e_budget"]) <= 1e-12 * st["e_emitted"]
+    bal = st["e_escaped"] + st["e_absorbed"] + st["e_rr_killed"] - st["e_rr_gained"] + st["e_budget"]
+    assert abs(bal - st["e_emitted"] - st["e_scat_delta"]) < 1e-12 * st["e_emitted"]
+    with pytest.raises(P.KpError) as e:
+        ctx.run(trace_packets=0, transport_fp64=1, strict=1)
+    assert e.value.status == P.KP_ERR_BUDGET
+    assert ctx.stats()["budget"] == st["budget"]
+    assert np.isfinite(ctx.images()).all()
+    # without the cap in reach, strict mode passes
+    ctx.run(trace_packets=0, transport_fp64=1, strict=1, max_events=10000)
+    assert ctx.stats()["budget"] == 0
+
+
+def test_batched_full_size_sampled(O):
+    """The 32-wavelength workload at full size (256^3 helical field, aligned
+    oblate grains, uneven counts 1e6..3e7, 2.8e8 packets, 16 views, a 68.7 GB
+    tally whose flat index passes 2^32) in one persistent launch: 30 packets
+    per wavelength sampled across its range follow the oracle's paths
+    (automatic precision: FP64 for these dichroic grains), every image is
+    finite with I >= |P|, and the energy budget closes."""
+    say("case: batched disk256 x32 wavelengths, sampled traces")
+    cfg = W.batched_disk()
+    stride, per = 33_333, 30
+    ctx = gpu_run(cfg, trace_packets=per, trace_stride=stride)
+    st = ctx.stats()
+    say(f"batched256: {st['packets']} packets, {st['cell_steps']} cell steps, "
+        f"{st['ms_transport']:.1f} ms transport, {st['ms_image']:.1f} ms imaging")
+    n_lambda = len(cfg["dust"])
+    tr = ctx.traces().reshape(n_lambda, per)
+    ids = np.arange(per, dtype=np.uint64) * stride
+    for lam in range(n_lambda):
+        assert int(cfg["packets"][lam]) > int(ids[-1])
+        tr_o = O.trace_packets(cfg, ids, lam=lam)
+        compare_traces(tr[lam], tr_o, 1e-10, 1.0, f"batched256 lam={lam}")
+    assert st["packets"] == sum(int(n) for n in cfg["packets"]) and st["numeric"] == 0
+    img = ctx.images()
+    assert img.shape == (n_lambda, 16, 4, 256, 256)
+    assert np.isfinite(img).all()
+    assert stokes_bound(img, 1e-6, 1e-6)
+    bal = st["e_escaped"] + st["e_absorbed"] + st["e_rr_killed"] - st["e_rr_gained"] + st["e_budget"]
+    assert abs(bal - st["e_emitted"] - st["e_scat_delta"]) < 1e-9 * st["e_emitted"]
 
 
 def test_edge_cases(O):
