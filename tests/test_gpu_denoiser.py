@@ -1,169 +1,18 @@
 """GPU parity of the denoiser kernels (BF16 MFMA convolutions, FP32
-accumulation) against the FP64 NumPy oracle, through the C ABI.
+accumulation) against the FP64 NumPy oracle, through the C ABI.  The bars
+(a norm bar against the exact oracle, an element-wise bar against a replay
+of the oracle with the kernels' BF16 roundings) are derived in dn_util.py.
 
-The oracle is evaluated on exactly the operands the kernels see: the
-parameters and the normalised input rounded to BF16 (nearest even), the
-fractions Q/I, U/I, the intensity ratio I/s and the targets in FP32.  What
-remains is the rounding of every stored intermediate (activations and their
-gradients) to BF16 and the order of FP32 accumulation.
-
-The tolerance is derived from the arithmetic by replaying the oracle's own
-layer functions with a BF16 rounding wherever the kernels store BF16
-(`bf16_replay`): the replay's distance from the exact oracle is the size of
-the rounding noise, and the GPU -- another realisation of the same noise --
-must lie within twice that distance plus 2e-3, per tensor.  Forward: about
-3.6e-3 (sqrt(10) x the RMS relative error 2^-9/sqrt(3) of one rounding);
-weight gradients of the deepest layers reach 2-3e-2, because the backward
-pass compounds the roundings of both passes and ends in short sums over few
-coarse pixels.  A wrong index, sign or mask gives errors of order one.
 """
 import numpy as np
 import pytest
 
+from dn_util import (TOL_FWD, bf16_replay, check_forward, check_gradients, dihedral,
+                     dihedral_inverse, fractions, linear_regime_params, oracle_pass, rel)
 from oracle import denoiser as D
 from paper_2512_01283_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
-
-TOL_FWD = 1.5e-2
-
-
-def bf16(a):
-    """Round to BF16, nearest even, returned as FP64."""
-    u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
-    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
-
-
-def dihedral(m, code):
-    """Transform [4, H, W] maps by code = r + 4 f (mirror the width axis if f,
-    then r quarter turns) with the spin-2 Stokes sign rules."""
-    r, f = code & 3, code >> 2
-    out = m[:, :, ::-1] if f else m
-    out = np.rot90(out, r, axes=(1, 2)).copy()
-    out[1] *= (-1) ** r
-    out[2] *= (-1) ** (r + f)
-    out[3] *= (-1) ** f
-    return out
-
-
-def dihedral_inverse(m, code):
-    """The inverse of dihedral(m, code)."""
-    r, f = code & 3, code >> 2
-    out = m.copy()
-    out[1] *= (-1) ** r
-    out[2] *= (-1) ** (r + f)
-    out[3] *= (-1) ** f
-    out = np.rot90(out, -r, axes=(1, 2))
-    return (out[:, :, ::-1] if f else out).copy()
-
-
-def _operands(params32, low, high, widths):
-    """Parameters and inputs as the kernels see them: 3x3 weights BF16
-    (biases and head FP32), features FP32 -> BF16 for the network, the
-    fractions Q/I, U/I, Ihat and the targets FP32."""
-    p = D.unflatten(params32.astype(np.float64), widths, cin=low.shape[1])
-    for k in p:
-        if k.endswith(".w") and not k.startswith("head"):
-            p[k] = bf16(p[k])
-    xf, Ihat, s = D.features(low)
-    xf = np.float32(xf).astype(np.float64)
-    Ihat = np.float32(Ihat).astype(np.float64)
-    t = None
-    if high is not None:
-        t = np.float32(np.moveaxis(high[:, 1:3], 1, -1) / s[:, None, None, None]).astype(np.float64)
-    return p, xf, bf16(xf), Ihat, t
-
-
-def oracle_pass(params32, low, high=None, widths=W.DN_WIDTHS):
-    """Exact FP64 oracle forward (and backward if high is given) on the
-    kernels' operands.  Returns dict(delta, loss, grads)."""
-    p, xf, x, Ihat, t = _operands(params32, low, high, widths)
-    delta, cache = D.forward(p, x)
-    res = dict(delta=delta)
-    if high is not None:
-        res["loss"] = D.loss(delta, xf, Ihat, t)
-        res["grads"] = D.backward(p, cache, D.loss_grad(delta, xf, Ihat, t))
-    return res
-
-
-def bf16_replay(params32, low, high=None, widths=W.DN_WIDTHS):
-    """The oracle's layer functions in FP64 with a BF16 rounding at every
-    point where the kernels store BF16: each convolution's output (after
-    bias and relu), pooled maps, the head's input gradient, each input
-    gradient, the adjoints of upsampling and pooling (masks applied before
-    rounding).  Returns dict(delta, loss, grads)."""
-    R = bf16
-    p, xf, x, Ihat, t = _operands(params32, low, high, widths)
-    L = len(widths)
-    c = {}
-
-    def block(name, inp):
-        ya = R(D.relu(D.conv3(inp, p[name + "a.w"], p[name + "a.b"])))
-        yb = R(D.relu(D.conv3(ya, p[name + "b.w"], p[name + "b.b"])))
-        c[name] = (inp, ya, yb)
-        return yb
-
-    skips, h = [], x
-    for l in range(1, L):
-        h = block(f"e{l}", h)
-        skips.append(h)
-        h = R(D.pool(h))
-    h = block(f"m{L}", h)
-    for l in range(L - 1, 0, -1):
-        h = block(f"d{l}", np.concatenate([D.up(h), skips[l - 1]], axis=3))
-    delta = h @ p["head.w"].T + p["head.b"]
-    if t is None:
-        return dict(delta=delta)
-    g = {}
-    go = D.loss_grad(delta, xf, Ihat, t)
-    g["head.w"] = go.reshape(-1, 2).T @ h.reshape(-1, h.shape[-1])
-    g["head.b"] = go.reshape(-1, 2).sum(0)
-
-    def block_back(name, gzb):
-        inp, ya, yb = c[name]
-        gya, g[name + "b.w"], g[name + "b.b"] = D.conv3_backward(ya, p[name + "b.w"], gzb)
-        gza = R(gya * (ya > 0))
-        ginp, g[name + "a.w"], g[name + "a.b"] = D.conv3_backward(inp, p[name + "a.w"], gza)
-        return R(ginp)
-
-    gy = R((go @ p["head.w"]) * (h > 0))
-    gskip = {}
-    for l in range(1, L):
-        gcat = block_back(f"d{l}", gy)
-        cb = widths[l]
-        gskip[l] = gcat[..., cb:]
-        below = c[f"d{l + 1}"][2] if l + 1 < L else c[f"m{L}"][2]
-        gy = R(D.up_backward(gcat[..., :cb]) * (below > 0))
-    gin = block_back(f"m{L}", gy)
-    for l in range(L - 1, 0, -1):
-        gin = block_back(f"e{l}", R((gskip[l] + D.pool_backward(gin)) * (c[f"e{l}"][2] > 0)))
-    return dict(delta=delta, loss=D.loss(delta, xf, Ihat, t), grads=g)
-
-
-def fractions(maps):
-    """(Q/I, U/I) as the kernels form them (clamped to [-1, 1], FP32)."""
-    return np.float32(D.features(maps)[0][..., 1:3]).astype(np.float64)
-
-
-def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
-
-
-def check_gradients(g, low, high, params, label, widths=W.DN_WIDTHS):
-    """GPU gradients against the exact oracle, per tensor, within twice the
-    distance of the BF16 replay from the exact oracle plus 2e-3 (the GPU and
-    the replay are two realisations of the same rounding noise)."""
-    ref = oracle_pass(params, low, high, widths)
-    rep = bf16_replay(params, low, high, widths)
-    worst = 0.0
-    for k, gr in ref["grads"].items():
-        bound = 2.0 * rel(rep["grads"][k], gr) + 2e-3
-        e = rel(g[k], gr)
-        worst = max(worst, e / bound)
-        assert e < bound, (k, e, bound)
-    print(f"{label}: worst gradient error {worst:.2f} of its bound")
-    return ref
 
 
 @pytest.fixture(scope="module")
@@ -190,10 +39,7 @@ def test_forward_parity(dn, shape):
     rep = bf16_replay(params, maps)
     # the network's correction to the fractions: Q'/I - Q/I
     delta_gpu = np.moveaxis(out[:, 1:3] / out[:, :1], 1, -1) - fractions(maps)
-    e = rel(delta_gpu, ref["delta"])
-    e_rep = rel(rep["delta"], ref["delta"])
-    print(f"forward {shape}: relative error of the correction {e:.2e} (BF16 replay {e_rep:.2e})")
-    assert e < TOL_FWD and e < 2.0 * e_rep + 2e-3
+    check_forward(delta_gpu, ref["delta"], rep["delta"], f"forward {shape}")
     # I and V pass through unchanged
     assert np.array_equal(out[:, 0], maps[:, 0]) and np.array_equal(out[:, 3], maps[:, 3])
 
@@ -271,9 +117,7 @@ def test_test_time_averaging_parity(dn, shape):
     ref = np.moveaxis(ref / len(codes), 1, -1)
     rep = np.moveaxis(rep / len(codes), 1, -1)
     delta_gpu = np.moveaxis(out[:, 1:3] / out[:, :1], 1, -1) - fractions(maps)
-    e, e_rep = rel(delta_gpu, ref), rel(rep, ref)
-    print(f"test-time averaging {shape}: relative error {e:.2e} (BF16 replay {e_rep:.2e})")
-    assert e < TOL_FWD and e < 2.0 * e_rep + 2e-3
+    check_forward(delta_gpu, ref, rep, f"test-time averaging {shape}")
     assert np.array_equal(out[:, 0], maps[:, 0]) and np.array_equal(out[:, 3], maps[:, 3])
     # the average differs from one pass (the random network is not equivariant)
     assert rel(out[:, 1:3], single[:, 1:3]) > 1e-4
@@ -307,8 +151,8 @@ def test_other_depths_forward_and_gradient_parity(widths, shape):
     out = d.infer(_dev(low)).cpu().numpy()
     ref = oracle_pass(params, low, None, widths)
     rep = bf16_replay(params, low, None, widths)
-    e = rel(np.moveaxis(out[:, 1:3] / out[:, :1], 1, -1) - fractions(low), ref["delta"])
-    assert e < TOL_FWD and e < 2.0 * rel(rep["delta"], ref["delta"]) + 2e-3, e
+    check_forward(np.moveaxis(out[:, 1:3] / out[:, :1], 1, -1) - fractions(low), ref["delta"],
+                  rep["delta"], f"widths {widths} forward")
     loss = d.backward(_dev(low), _dev(high))
     g = D.unflatten(d.grads().astype(np.float64), widths)
     refg = check_gradients(g, low, high, params, f"widths {widths}", widths)
@@ -316,6 +160,113 @@ def test_other_depths_forward_and_gradient_parity(widths, shape):
     with pytest.raises(Exception):
         d.infer(_dev(W.synthetic_stokes_maps(15, 1, h + 2 ** (len(widths) - 2), w)))
     d.close()
+
+
+def conv_tile_groups(widths, b, h, w, cin=4):
+    """Channel tiles per workgroup (NT, 16 NT channels) of every LDS-staged
+    3x3 convolution of a forward pass and of the input gradients, by the
+    launch rule of the library (at least 1024 pixels; the widest of 4, 3, 2,
+    1 tiles of 16 channels that divides the output channels)."""
+    def nt(cout):
+        t = cout // 16
+        return 4 if t % 4 == 0 else 3 if t % 3 == 0 else 2 if t % 2 == 0 else 1
+    shapes = D.layer_shapes(widths, cin)
+    L = len(widths)
+    out = set()
+    for name in D.layer_names(widths):
+        co, _, _, ci = shapes[name + ".w"]
+        lvl = int(name[1:-1])
+        pix = b * (h >> (lvl - 1)) * (w >> (lvl - 1))
+        if pix >= 1024:
+            out.add(("fwd", nt(co)))
+            if name != "e1a":
+                out.add(("dgrad", nt(ci)))
+    assert L == len(widths)
+    return out
+
+
+@pytest.mark.parametrize("widths", [(64, 128, 256), (32, 160, 224)])
+def test_bench_scale_forward_and_gradient_parity(widths):
+    """The network the bench times (64/128/256) and one whose channel counts
+    give two-tile groups (32/160/224: cout/16 = 2, 10, 14) on 4 maps of
+    64x64, so every level runs the LDS-staged convolution: four (or two)
+    16-channel tiles per workgroup in the forward pass and in the input
+    gradients, compared with the oracle by norm and element by element."""
+    from paper_2512_01283_amd import denoiser as DN
+    b, h, w = 4, 64, 64
+    groups = conv_tile_groups(widths, b, h, w)
+    want = 4 if widths[0] == 64 else 2
+    assert ("fwd", want) in groups and ("dgrad", want) in groups, groups
+    params = W.denoiser_params(25, widths=widths, bias_std=0.05, head_std=0.05)
+    d = DN.Denoiser(0, widths=widths, params=params)
+    low = W.synthetic_stokes_maps(20, b, h, w, noise=0.3)
+    high = W.synthetic_stokes_maps(20, b, h, w, noise=0.0)
+    out = d.infer(_dev(low)).cpu().numpy()
+    ref = oracle_pass(params, low, None, widths)
+    rep = bf16_replay(params, low, None, widths)
+    check_forward(np.moveaxis(out[:, 1:3] / out[:, :1], 1, -1) - fractions(low), ref["delta"],
+                  rep["delta"], f"widths {widths} forward, tiles {sorted(groups)}")
+    loss = d.backward(_dev(low), _dev(high))
+    g = D.unflatten(d.grads().astype(np.float64), widths)
+    refg = check_gradients(g, low, high, params, f"widths {widths} gradients", widths)
+    assert abs(loss - refg["loss"]) <= TOL_FWD * refg["loss"]
+    d.close()
+
+
+@pytest.mark.parametrize("widths,shape", [((48, 96, 192), (2, 32, 32)), ((64, 128, 256), (4, 64, 64)),
+                                          ((32, 160, 224), (4, 64, 64))])
+def test_gradients_elementwise_linear_regime(widths, shape):
+    """Every element of every gradient, and of the forward correction,
+    against the BF16 replay, on a network whose relus all pass (no decision
+    can flip between realisations), with three-, four- and two-tile channel
+    groups of the staged convolution in the forward pass and the input
+    gradients (widths 48/96/192 on 2 x 32^2; 64/128/256 and 32/160/224 on
+    4 x 64^2)."""
+    from paper_2512_01283_amd import denoiser as DN
+    b, h, w = shape
+    params = linear_regime_params(27, widths)
+    d = DN.Denoiser(0, widths=widths, params=params)
+    low = W.synthetic_stokes_maps(22, b, h, w, noise=0.3)
+    high = W.synthetic_stokes_maps(22, b, h, w, noise=0.0)
+    out = d.infer(_dev(low)).cpu().numpy()
+    ref = oracle_pass(params, low, None, widths)
+    rep = bf16_replay(params, low, None, widths)
+    check_forward(np.moveaxis(out[:, 1:3] / out[:, :1], 1, -1) - fractions(low), ref["delta"],
+                  rep["delta"], f"linear regime {widths} forward, tiles {sorted(conv_tile_groups(widths, b, h, w))}")
+    loss = d.backward(_dev(low), _dev(high))
+    g = D.unflatten(d.grads().astype(np.float64), widths)
+    refg = check_gradients(g, low, high, params, f"linear regime {widths} gradients", widths, elementwise=True)
+    assert abs(loss - refg["loss"]) <= TOL_FWD * refg["loss"]
+    d.close()
+
+
+def test_test_time_averaging_bench_widths():
+    """Averaged inference (eight dihedral passes) of the benched 64/128/256
+    network on 64x64 maps (four-tile staged convolutions on the two finer
+    levels) against the oracle's passes mapped back and averaged."""
+    from paper_2512_01283_amd import denoiser as DN
+    widths = (64, 128, 256)
+    b, h, w = 2, 64, 64
+    params = W.denoiser_params(26, widths=widths, bias_std=0.05, head_std=0.05)
+    d = DN.Denoiser(0, widths=widths, params=params)
+    maps = W.synthetic_stokes_maps(21, b, h, w, noise=0.3)
+    out = d.infer(_dev(maps), tta=True).cpu().numpy()
+    d.close()
+
+    def back(delta, c):
+        dm = np.zeros((delta.shape[0], 4) + delta.shape[1:3])
+        dm[:, 1], dm[:, 2] = delta[..., 0], delta[..., 1]
+        return np.stack([dihedral_inverse(x, c) for x in dm])[:, 1:3]
+
+    ref, rep = 0.0, 0.0
+    for c in range(8):
+        mt = np.stack([dihedral(m, c) for m in maps])
+        ref = ref + back(oracle_pass(params, mt, None, widths)["delta"], c)
+        rep = rep + back(bf16_replay(params, mt, None, widths)["delta"], c)
+    ref = np.moveaxis(ref / 8, 1, -1)
+    rep = np.moveaxis(rep / 8, 1, -1)
+    delta_gpu = np.moveaxis(out[:, 1:3] / out[:, :1], 1, -1) - fractions(maps)
+    check_forward(delta_gpu, ref, rep, "test-time averaging 64/128/256 on 64x64")
 
 
 def dihedral_runs(m, code):
@@ -339,10 +290,8 @@ def test_two_run_inputs_forward_and_gradient_parity(shape):
     assert out.shape == (b, 4, h, w)
     ref = oracle_pass(params, low)
     rep = bf16_replay(params, low)
-    e = rel(np.moveaxis(out[:, 1:3] / out[:, :1], 1, -1) - fractions(mean), ref["delta"])
-    e_rep = rel(rep["delta"], ref["delta"])
-    print(f"two-run forward {shape}: relative error of the correction {e:.2e} (BF16 replay {e_rep:.2e})")
-    assert e < TOL_FWD and e < 2.0 * e_rep + 2e-3
+    check_forward(np.moveaxis(out[:, 1:3] / out[:, :1], 1, -1) - fractions(mean), ref["delta"],
+                  rep["delta"], f"two-run forward {shape}")
     assert np.array_equal(out[:, 0], mean[:, 0]) and np.array_equal(out[:, 3], mean[:, 3])
     loss = d.backward(_dev(low), _dev(high))
     g = D.unflatten(d.grads().astype(np.float64), cin=8)
@@ -383,14 +332,17 @@ def test_adam_step_matches_oracle(dn):
 
 def test_training_reduces_loss(dn):
     """Adam on one fixed batch lowers the loss (a wrong sign or a missing
-    term anywhere in the backward pass would not)."""
+    term anywhere in the backward pass would not).  The first tens of steps
+    at this rate move the loss by only a few per cent either way (FP32
+    gradient atomics make the trajectory differ slightly from run to run),
+    so the check is on the last 20 of 160 steps."""
     dn.set_params(W.denoiser_params(15))
     low = _dev(W.synthetic_stokes_maps(9, 4, 32, 32, noise=0.3))
     high = _dev(W.synthetic_stokes_maps(9, 4, 32, 32, noise=0.0))
-    first = dn.train_step(low, high, 1e-3)
-    for _ in range(40):
-        last = dn.train_step(low, high, 1e-3)
-    assert np.isfinite(last) and last < 0.9 * first, (first, last)
+    hist = [dn.train_step(low, high, 1e-3) for _ in range(160)]
+    print("loss every 20 steps: " + " ".join(f"{l:.3e}" for l in hist[::20]) + f" last {hist[-1]:.3e}")
+    tail = float(np.mean(hist[-20:]))
+    assert np.isfinite(hist).all() and tail < 0.8 * hist[0], (hist[0], tail)
 
 
 def test_checkpoint_resume(dn):
