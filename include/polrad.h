@@ -220,6 +220,24 @@ kp_status kp_set_views(kp_ctx *ctx, int32_t n_views, const kp_view *views);
  * after a completed run whose counters show them. */
 kp_status kp_run(kp_ctx *ctx, const uint64_t *packets_per_lambda, const kp_opts *opts,
                  void *hip_stream);
+/* For callers that cannot allocate device memory (code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): kp_run
+ * without any allocation.  Step 1 and step 2 run as in kp_run, with the
+ * counters, the per-wavelength and camera tables and the step-1 tally held
+ * in one static device array of the library (1 MiB + 256 MiB, one copy per
+ * device, held until the process ends) instead of context buffers; the
+ * images go straight to d_images (device, borrowed, [n_lambda][n_views][4]
+ * [npy][npx] FP64, n its element count).  Limits: the tally, n_lambda x
+ * ncell x 64 B for spherical grains (x 128 B otherwise), must fit 256 MiB
+ * (KP_ERR_ARG otherwise, before any launch: use kp_run), and no traces are
+ * recorded (trace_packets must be 0).  kp_get_stats then reports this call;
+ * kp_image, kp_get_images and kp_get_tally keep referring to the last
+ * kp_run / kp_transport.  Every call on one device uses that device's one
+ * array, cleared at the start of each call by kernels: calls that overlap
+ * on one device (two streams, threads or contexts) race and must not be
+ * issued.  Synchronises hip_stream. */
+kp_status kp_run_static(kp_ctx *ctx, const uint64_t *packets_per_lambda, const kp_opts *opts,
+                        double *d_images, size_t n, void *hip_stream);
 /* Step 1 only (Sec. 2.3 first step, transport of Sec. 2.2 with the
  * Appendix A cell solution): tallies the scattering source of eq.
  * scat-disc-sum as each cell's incident coherency.  Same arguments, errors

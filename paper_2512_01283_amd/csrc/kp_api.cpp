@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -15,6 +16,44 @@
 #include "kp_internal.hpp"
 
 using namespace kp;
+
+// Device scratch of kp_run_static, the entry point that allocates nothing:
+// its counters and small tables (first KP_STATIC_HEAD bytes) and its step-1
+// tally (the next KP_STATIC_TALLY bytes).  Each device the library runs on
+// holds its own copy until the process ends.  In host code `scratch` names
+// a host-side stand-in: the device address of a device's copy comes from
+// hipGetSymbolAddress (scratch_address below) and only that address is ever
+// passed to a kernel or a copy.
+namespace {
+constexpr size_t KP_STATIC_HEAD = size_t(1) << 20;
+constexpr size_t KP_STATIC_TALLY = size_t(256) << 20;
+constexpr int KP_MAX_DEVICES = 64;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[KP_STATIC_HEAD + KP_STATIC_TALLY];
+
+namespace {
+std::mutex g_scratch_mu;
+bool g_scratch_done[KP_MAX_DEVICES] = {};
+hipError_t g_scratch_err[KP_MAX_DEVICES] = {};
+unsigned char* g_scratch_ptr[KP_MAX_DEVICES] = {};
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current (called from kp_create).
+hipError_t scratch_address(int device, unsigned char** out) {
+  *out = nullptr;
+  if (device < 0 || device >= KP_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_done[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_err[device] = e;
+    g_scratch_ptr[device] = e == hipSuccess ? (unsigned char*)p : nullptr;
+    g_scratch_done[device] = true;
+  }
+  *out = g_scratch_ptr[device];
+  return g_scratch_err[device];
+}
+}  // namespace
 
 struct kp_ctx {
   int device = 0;
@@ -58,6 +97,9 @@ struct kp_ctx {
   size_t traces_valid = 0;
   kp_stats stats{};
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // this device's copy of the static scratch (kp_run_static), or null
+  unsigned char* scratch = nullptr;
+  hipError_t scratch_err = hipSuccess;
 };
 
 namespace {
@@ -238,7 +280,7 @@ bool all_spheres(const kp_ctx* ctx) {
   return true;
 }
 
-// Checks of a step-1 call (kp_transport, kp_run) before any
+// Checks of a step-1 call (kp_transport, kp_run, kp_run_static) before any
 // launch; *total receives the packet count over all wavelengths.
 kp_status check_run_args(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, uint64_t* total_out) {
   kp_status st = check_ready(ctx);
@@ -381,6 +423,7 @@ kp_status kp_create(int device, kp_ctx** out) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete ctx; return KP_ERR_DEVICE; }
   ctx->cu_count = prop.multiProcessorCount;
+  ctx->scratch_err = scratch_address(device, &ctx->scratch);
   for (auto& e : ctx->ev)
     if (hipEventCreate(&e) != hipSuccess) { kp_destroy(ctx); return KP_ERR_DEVICE; }
   if (hipMalloc(&ctx->d_stats, sizeof(StatsDev)) != hipSuccess ||
@@ -584,6 +627,58 @@ kp_status kp_run(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, void* st
   if (st != KP_OK && st != KP_ERR_NUMERIC && st != KP_ERR_BUDGET) return st;
   kp_status st2 = kp_image(ctx, stream);
   return st2 != KP_OK ? st2 : st;
+}
+
+kp_status kp_run_static(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, double* d_images,
+                        size_t n, void* stream) {
+  if (!ctx) return KP_ERR_ARG;
+  uint64_t total = 0;
+  kp_status st = check_run_args(ctx, counts, o, &total);
+  if (st) return st;
+  if (o->trace_packets) return fail(ctx, KP_ERR_ARG, "kp_run_static records no traces: trace_packets must be 0");
+  if (!ctx->scratch)
+    return fail(ctx, KP_ERR_DEVICE, "static scratch of device %d unavailable: %s", ctx->device,
+                hipGetErrorString(ctx->scratch_err));
+  const int nl = (int)ctx->dust.size();
+  const int nv = (int)ctx->views.size();
+  const size_t img_need = (size_t)nl * nv * 4 * ctx->views[0].npx * ctx->views[0].npy;
+  if (!d_images || n != img_need) return fail(ctx, KP_ERR_ARG, "destination must hold %zu doubles", img_need);
+  const bool all_sphere = all_spheres(ctx);
+  const size_t tally_bytes = (size_t)nl * ctx->ncell * tally_stride(all_sphere) * sizeof(double);
+  if (tally_bytes > KP_STATIC_TALLY)
+    return fail(ctx, KP_ERR_ARG, "the tally needs %zu bytes, more than the %zu of the static scratch "
+                "(%d wavelengths x %llu cells x %d B): use kp_run", tally_bytes, KP_STATIC_TALLY, nl,
+                (unsigned long long)ctx->ncell, tally_stride(all_sphere) * 8);
+  // head of the scratch: stats at 0, work counter at 256, the dust table at
+  // 512, the camera table after it (at most 1024 x 144 B + 4096 x 80 B)
+  const size_t dust_off = 512, dust_bytes = (size_t)nl * sizeof(DustDev);
+  const size_t view_off = (dust_off + dust_bytes + 255) & ~size_t(255);
+  const size_t view_bytes = (size_t)nv * sizeof(ViewDev);
+  static_assert(512 + 1024 * sizeof(DustDev) + 256 + 4096 * sizeof(ViewDev) <= KP_STATIC_HEAD,
+                "tables fit the head of the static scratch");
+  unsigned char* base = ctx->scratch;
+  StatsDev* d_stats = (StatsDev*)base;
+  unsigned long long* d_counter = (unsigned long long*)(base + 256);
+  DustDev* d_dust = (DustDev*)(base + dust_off);
+  ViewDev* d_views = (ViewDev*)(base + view_off);
+  double* d_tally = (double*)(base + KP_STATIC_HEAD);
+  static_assert(sizeof(StatsDev) <= 256, "stats fit their slot");
+
+  KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  fill_dust(ctx, counts, ctx->hdust);
+  KP_HIP(hipMemcpyAsync(d_dust, ctx->hdust.data(), dust_bytes, hipMemcpyHostToDevice, s), "dust upload");
+  KP_HIP(hipMemcpyAsync(d_views, ctx->hviews.data(), view_bytes, hipMemcpyHostToDevice, s), "view upload");
+  const RunBuffers buf{d_dust, d_tally, d_stats, d_counter, nullptr};
+  st = transport_launch(ctx, o, total, buf, s);
+  if (st == KP_ERR_DEVICE || st == KP_ERR_OOM) return st;
+  kp_status st2 = image_launch(ctx, false, nullptr, d_images, nl, s, d_dust, d_views, d_tally);
+  if (st2) return st2;
+  KP_HIP(hipStreamSynchronize(s), "imaging kernel");
+  float ms = 0.0f;
+  KP_HIP(hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]), "event timing");
+  ctx->stats.ms_image = ms;
+  return st;
 }
 
 kp_status kp_image_source(kp_ctx* ctx, const double* d_S, double* d_out, void* stream) {

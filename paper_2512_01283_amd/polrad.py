@@ -100,6 +100,7 @@ _SIGS = {
     "kp_set_source": ([_P, C.POINTER(kp_source)], C.c_int),
     "kp_set_views": ([_P, C.c_int32, C.POINTER(kp_view)], C.c_int),
     "kp_run": ([_P, C.POINTER(C.c_uint64), C.POINTER(kp_opts), _P], C.c_int),
+    "kp_run_static": ([_P, C.POINTER(C.c_uint64), C.POINTER(kp_opts), _P, C.c_size_t, _P], C.c_int),
     "kp_transport": ([_P, C.POINTER(C.c_uint64), C.POINTER(kp_opts), _P], C.c_int),
     "kp_image": ([_P, _P], C.c_int),
     "kp_image_source": ([_P, _P, _P, _P], C.c_int),
@@ -220,6 +221,13 @@ def _counts(counts):
 
 def kp_run(ctx, counts, opts: kp_opts, stream=None) -> None:
     _check(ctx, _lib.kp_run(ctx, _counts(counts), C.byref(opts), _stream_ptr(stream)))
+
+
+def kp_run_static(ctx, counts, opts: kp_opts, d_images, stream=None) -> None:
+    """d_images: float64 cuda tensor [n_lambda, n_views, 4, npy, npx] (written)."""
+    assert d_images.is_cuda and d_images.is_contiguous() and str(d_images.dtype) == "torch.float64"
+    _check(ctx, _lib.kp_run_static(ctx, _counts(counts), C.byref(opts), _ptr(d_images), d_images.numel(),
+                                   _stream_ptr(stream)))
 
 
 def kp_transport(ctx, counts, opts: kp_opts, stream=None) -> None:
