@@ -45,7 +45,8 @@ class Dust(C.Structure):
 
 class Source(C.Structure):
     _fields_ = [("kind", C.c_int32), ("pos", C.c_double * 3),
-                ("dir", C.c_double * 3), ("lum", C.c_double)]
+                ("dir", C.c_double * 3), ("lum", C.c_double),
+                ("B", C.POINTER(C.c_float))]
 
 
 class View(C.Structure):
@@ -104,6 +105,13 @@ def lib():
                                         C.POINTER(Opts), C.c_void_p]
         L.kpo_image.argtypes = [C.POINTER(Grid), fp, fp, C.POINTER(Dust), C.c_int32,
                                 C.POINTER(View), dp, dp]
+        L.kpo_image_thermal.argtypes = [C.POINTER(Grid), fp, fp, C.POINTER(Dust), C.c_int32,
+                                        C.POINTER(View), dp, fp, dp]
+        L.kpo_emit_state.argtypes = [C.POINTER(Grid), fp, fp, C.POINTER(Dust), fp, C.c_uint64,
+                                     C.c_int32, C.c_uint64, C.c_double, C.POINTER(C.c_int64),
+                                     dp, dp, dp]
+        L.kpo_emission_luminosity.argtypes = [C.POINTER(Grid), fp, C.POINTER(Dust), fp]
+        L.kpo_emission_luminosity.restype = C.c_double
         L.kpo_philox.argtypes = [u64p, u64p, u64p]
         L.kpo_uniform.argtypes = [C.c_uint64] * 4
         L.kpo_uniform.restype = C.c_double
@@ -152,9 +160,20 @@ def make_dust(d) -> Dust:
                 float(d.get("alpha3_scale", 0.0)))
 
 
-def make_source(s) -> Source:
-    return Source(int(s.get("kind", 0)), (C.c_double * 3)(*s["pos"]),
-                  (C.c_double * 3)(*s.get("dir", (0.0, 0.0, 1.0))), float(s["lum"]))
+def make_source(s, B=None) -> Source:
+    """B: the source function [ncell] (float32, kept alive by the caller) of
+    the wavelength, for thermal emission (kind 2)."""
+    return Source(int(s.get("kind", 0)), (C.c_double * 3)(*s.get("pos", (0.0, 0.0, 0.0))),
+                  (C.c_double * 3)(*s.get("dir", (0.0, 0.0, 1.0))), float(s.get("lum", 1.0)),
+                  None if B is None else B.ctypes.data_as(C.POINTER(C.c_float)))
+
+
+def emission_of(cfg, lam):
+    """The source function of wavelength lam as float32 [ncell] when the
+    source is the dust's thermal emission (kind 2), else None."""
+    if int(cfg["source"].get("kind", 0)) != 2:
+        return None
+    return np.ascontiguousarray(np.asarray(cfg["emission"])[lam], dtype=np.float32)
 
 
 def make_views(vs):
@@ -182,7 +201,8 @@ def transport(cfg, lam=0, p_begin=0, p_end=None, n_total=None, tally=True,
     rho, rho_p = _f(cfg["rho"])
     bh, bh_p = _f(cfg.get("bhat"))
     dust = make_dust(cfg["dust"][lam])
-    src = make_source(cfg["source"])
+    B = emission_of(cfg, lam)
+    src = make_source(cfg["source"], B)
     views = make_views(cfg["views"])
     nv = len(cfg["views"])
     n_total = int(cfg["packets"][lam]) if n_total is None else int(n_total)
@@ -206,7 +226,8 @@ def trace_packets(cfg, ids, lam=0, n_total=None, nthreads=0):
     rho, rho_p = _f(cfg["rho"])
     bh, bh_p = _f(cfg.get("bhat"))
     dust = make_dust(cfg["dust"][lam])
-    src = make_source(cfg["source"])
+    B = emission_of(cfg, lam)
+    src = make_source(cfg["source"], B)
     ids = np.ascontiguousarray(ids, dtype=np.uint64)
     n_total = int(cfg["packets"][lam]) if n_total is None else int(n_total)
     tr = np.zeros(len(ids), dtype=TRACE_DTYPE)
@@ -220,7 +241,9 @@ def trace_packets(cfg, ids, lam=0, n_total=None, nthreads=0):
 
 
 def image(cfg, S, lam=0):
-    """Step 2 for one wavelength; returns images [view][4][npy][npx]."""
+    """Step 2 for one wavelength; returns images [view][4][npy][npx].  S may
+    be None (no scattering source); with a thermal-emission source (kind 2)
+    the dust's emission is added to the source."""
     L = lib()
     g = make_grid(cfg["grid"])
     rho, rho_p = _f(cfg["rho"])
@@ -229,10 +252,13 @@ def image(cfg, S, lam=0):
     views = make_views(cfg["views"])
     nv = len(cfg["views"])
     npx, npy = cfg["views"][0]["npx"], cfg["views"][0]["npy"]
-    S, Sp = _d(S)
+    Sp = None
+    if S is not None:
+        S, Sp = _d(S)
+    B, Bp = _f(emission_of(cfg, lam))
     out = np.zeros((nv, 4, npy, npx))
-    rc = L.kpo_image(C.byref(g), rho_p, bh_p, C.byref(dust), nv, views, Sp,
-                     out.ctypes.data_as(C.POINTER(C.c_double)))
+    rc = L.kpo_image_thermal(C.byref(g), rho_p, bh_p, C.byref(dust), nv, views, Sp, Bp,
+                             out.ctypes.data_as(C.POINTER(C.c_double)))
     if rc != 0:
         raise ValueError(f"kpo_image rejected its inputs ({rc})")
     return out
@@ -242,6 +268,35 @@ def run(cfg, lam=0, nthreads=0, traces=False):
     """Both steps for one wavelength: (images, S, traces, stats)."""
     S, tr, st = transport(cfg, lam=lam, traces=traces, nthreads=nthreads)
     return image(cfg, S, lam=lam), S, tr, st
+
+
+def emit_state(cfg, packet, lam=0, w=1.0):
+    """Thermal emission draw of one packet: (cell, position in the cell,
+    direction, Stokes vector) for a packet weight w."""
+    L = lib()
+    g = make_grid(cfg["grid"])
+    rho, rho_p = _f(cfg["rho"])
+    bh, bh_p = _f(cfg.get("bhat"))
+    dust = make_dust(cfg["dust"][lam])
+    B, Bp = _f(emission_of(cfg, lam))
+    cell = C.c_int64()
+    pos, n, s = np.zeros(3), np.zeros(3), np.zeros(4)
+    dp = C.POINTER(C.c_double)
+    rc = L.kpo_emit_state(C.byref(g), rho_p, bh_p, C.byref(dust), Bp, int(cfg["opts"]["seed"]), lam,
+                          int(packet), float(w), C.byref(cell), pos.ctypes.data_as(dp),
+                          n.ctypes.data_as(dp), s.ctypes.data_as(dp))
+    if rc != 0:
+        raise ValueError("kpo_emit_state rejected its inputs")
+    return int(cell.value), pos, n, s
+
+
+def emission_luminosity(cfg, lam=0):
+    """4 pi sum_c rho_c kappa_abs B_c V over the grid."""
+    g = make_grid(cfg["grid"])
+    rho, rho_p = _f(cfg["rho"])
+    dust = make_dust(cfg["dust"][lam])
+    B, Bp = _f(emission_of(cfg, lam))
+    return float(lib().kpo_emission_luminosity(C.byref(g), rho_p, C.byref(dust), Bp))
 
 
 def stats_dict(st: Stats) -> dict:

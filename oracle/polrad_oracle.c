@@ -30,6 +30,13 @@
  *  R7 weight after scattering: I' = tr(alpha C alpha^dagger)/N_P.
  *  R8 termination: open boundaries, Russian roulette, event cap.
  *  R9 orthographic camera, image x along phi_hat, y along -theta_hat.
+ *  E1 thermal emission of the dust (Sec. 2.2, the alpha_abs B term of eq.
+ *     polarized-rt): the absorption matrix is kappa_abs/kappa_ext times the
+ *     extinction matrix, so a cell emits rho kappa_abs (alpha1, alpha2, 0, 0) B
+ *     per unit length and solid angle in the grain-frame basis of the
+ *     direction (the source (alpha1, alpha2) B of Appendix A when all
+ *     extinction is absorption); its orientation average is rho kappa_abs B,
+ *     so a cell's luminosity is 4 pi rho kappa_abs B V.
  */
 #include "polrad_oracle.h"
 #include <complex.h>
@@ -510,7 +517,89 @@ typedef struct {
   const kpo_view *views;
   double (*vdir)[3];     /* camera directions */
   double *S;             /* [cell][view][4] or NULL */
+  const double *cdf;     /* thermal emission: running sum of cell luminosities */
 } run_t;
+
+/* Running sum over cells (flat order) of the thermal luminosity
+ * 4 pi rho kappa_abs B V of each cell (reading E1); NULL if it is zero. */
+static double *emission_cdf(const kpo_grid *g, const float *rho, const kpo_dust *d,
+                            const float *B) {
+  int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
+  double vol = g->dx * g->dx * g->dx;
+  double *cdf = malloc(sizeof(double) * (size_t)ncell);
+  if (!cdf) return NULL;
+  double run = 0.0;
+  for (int64_t c = 0; c < ncell; ++c) {
+    run += 4.0 * PI_ * (double)rho[c] * d->kappa_abs * (double)B[c] * vol;
+    cdf[c] = run;
+  }
+  if (!(run > 0.0) || !isfinite(run)) { free(cdf); return NULL; }
+  return cdf;
+}
+
+double kpo_emission_luminosity(const kpo_grid *g, const float *rho, const kpo_dust *d,
+                               const float *B) {
+  double *cdf = emission_cdf(g, rho, d, B);
+  if (!cdf) return 0.0;
+  double L = cdf[(int64_t)g->nx * g->ny * g->nz - 1];
+  free(cdf);
+  return L;
+}
+
+/* The emitting cell of a uniform u: the first cell whose running sum
+ * exceeds u L (so a cell of zero luminosity is never drawn). */
+static int64_t emission_cell(const double *cdf, int64_t ncell, double u) {
+  double t = u * cdf[ncell - 1];
+  int64_t lo = 0, hi = ncell - 1;
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (t < cdf[mid]) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
+/* Thermal emission of one packet of weight w (Sec. 2.2, reading E1): the
+ * cell drawn by luminosity, the position uniform inside it, the direction
+ * isotropic, the Stokes vector w (alpha1, alpha2, 0, 0) in the grain-frame
+ * basis of the direction carried to the lab basis (mean over directions w,
+ * the orientation average of alpha1 being 1).  Draws: cell, three
+ * coordinates, two for the direction. */
+static void emit_thermal(const kpo_grid *g, const float *bhat, const kpo_dust *d,
+                         const double *cdf, rng_t *rng, double w, gpos_t *p, double n[3],
+                         double s[4]) {
+  int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
+  int64_t c = emission_cell(cdf, ncell, draw(rng));
+  p->i[0] = c % g->nx;
+  p->i[1] = (c / g->nx) % g->ny;
+  p->i[2] = c / ((int64_t)g->nx * g->ny);
+  for (int a = 0; a < 3; ++a) p->f[a] = draw(rng);
+  double mu = 2.0 * draw(rng) - 1.0;
+  double ph = 2.0 * PI_ * draw(rng);
+  dir_from(mu, ph, n);
+  double q[4], ng[3], al[3];
+  cell_quat(bhat, ncell, c, q);
+  kpo_to_grain(q, n, ng);
+  kpo_alphas(d, ng[2], al);
+  double sg[4] = {w * al[0], w * al[1], 0.0, 0.0};
+  kpo_rotate_stokes(-eta_pair(q, n, ng), sg, s);
+}
+
+int kpo_emit_state(const kpo_grid *g, const float *rho, const float *bhat,
+                   const kpo_dust *d, const float *B, uint64_t seed, int32_t lam,
+                   uint64_t packet, double w, int64_t *cell, double pos[3], double n[3],
+                   double s[4]) {
+  if (!g || !rho || !d || !B) return -1;
+  double *cdf = emission_cdf(g, rho, d, B);
+  if (!cdf) return -1;
+  rng_t rng = {{seed, (uint64_t)lam}, packet, 0, 0, 0, {0, 0, 0, 0}};
+  gpos_t p;
+  emit_thermal(g, bhat, d, cdf, &rng, w, &p, n, s);
+  free(cdf);
+  *cell = flat(g, &p);
+  for (int a = 0; a < 3; ++a) pos[a] = p.f[a];
+  return 0;
+}
 
 static void atomic_add(double *p, double v) {
 #pragma omp atomic
@@ -526,22 +615,28 @@ static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *s
   double vol = g->dx * g->dx * g->dx;
   rng_t rng = {{R->o->seed, (uint64_t)R->lam}, pid, 0, 0, 0, {0, 0, 0, 0}};
 
-  /* emission: isotropic direction, unpolarised, exponential scattering depth */
-  double n[3];
-  double u0 = draw(&rng), u1 = draw(&rng);
-  if (R->src->kind == 1) {
-    double nn = sqrt(dot3(R->src->dir, R->src->dir));
-    for (int a = 0; a < 3; ++a) n[a] = R->src->dir[a] / nn;
+  /* emission: a point source (isotropic unpolarised or pencil) or the dust's
+   * thermal emission (reading E1), then an exponential scattering depth */
+  double n[3], s[4], w0;
+  gpos_t p;
+  if (R->src->kind == 2) {
+    w0 = R->cdf[ncell - 1] / (double)R->n_total;
+    emit_thermal(g, R->bhat, d, R->cdf, &rng, w0, &p, n, s);
   } else {
-    dir_from(2.0 * u0 - 1.0, 2.0 * PI_ * u1, n);
+    double u0 = draw(&rng), u1 = draw(&rng);
+    if (R->src->kind == 1) {
+      double nn = sqrt(dot3(R->src->dir, R->src->dir));
+      for (int a = 0; a < 3; ++a) n[a] = R->src->dir[a] / nn;
+    } else {
+      dir_from(2.0 * u0 - 1.0, 2.0 * PI_ * u1, n);
+    }
+    w0 = R->src->lum / (double)R->n_total;
+    s[0] = w0; s[1] = s[2] = s[3] = 0.0;
+    locate(g, R->src->pos, n, &p);
   }
   double tau = -log(draw(&rng));
-  double w0 = R->src->lum / (double)R->n_total;
-  double s[4] = {w0, 0.0, 0.0, 0.0};
-  st->e_emitted += w0;
+  st->e_emitted += s[0];
 
-  gpos_t p;
-  locate(g, R->src->pos, n, &p);
   int32_t events = 0, end = KPO_END_NONE;
   int64_t steps = 0, last = -1;
   double tau_path = 0.0;
@@ -675,7 +770,8 @@ static int check_inputs(const kpo_grid *g, const kpo_dust *d, const kpo_source *
   if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0 || !(g->dx > 0.0)) return -1;
   if (!(d->kappa_sca >= 0.0) || !(d->kappa_abs >= 0.0)) return -1;
   if (!is_sphere(d) && !(2.0 * d->a_perp_im + d->a_par_im > 0.0)) return -1;
-  if (src->kind != 0 && src->kind != 1) return -1;
+  if (src->kind != 0 && src->kind != 1 && src->kind != 2) return -1;
+  if (src->kind == 2 && !src->B) return -1;
   return 0;
 }
 
@@ -687,12 +783,14 @@ int kpo_transport(const kpo_grid *g, const float *rho, const float *bhat,
                   kpo_stats *stats) {
   if (check_inputs(g, d, src) || !o || n_total == 0 || p_end < p_begin) return -1;
   if (S && (n_views <= 0 || !views)) return -1;
+  double *cdf = NULL;
+  if (src->kind == 2 && !(cdf = emission_cdf(g, rho, d, src->B))) return -1;
   double (*vdir)[3] = NULL;
   if (n_views > 0) {
     vdir = malloc(sizeof(double[3]) * (size_t)n_views);
     for (int v = 0; v < n_views; ++v) view_dir(&views[v], vdir[v]);
   }
-  run_t R = {g, rho, bhat, d, src, o, lam, n_total, n_views, views, vdir, S};
+  run_t R = {g, rho, bhat, d, src, o, lam, n_total, n_views, views, vdir, S, cdf};
   kpo_stats total;
   memset(&total, 0, sizeof total);
   int nth = o->nthreads;
@@ -708,6 +806,7 @@ int kpo_transport(const kpo_grid *g, const float *rho, const float *bhat,
   }
   if (stats) stats_add(stats, &total);
   free(vdir);
+  free(cdf);
   return 0;
 }
 
@@ -716,7 +815,9 @@ int kpo_trace_packets(const kpo_grid *g, const float *rho, const float *bhat,
                       const uint64_t *ids, uint64_t n_ids, uint64_t n_total,
                       const kpo_opts *o, kpo_trace *traces) {
   if (check_inputs(g, d, src) || !o || !ids || !traces || n_total == 0) return -1;
-  run_t R = {g, rho, bhat, d, src, o, lam, n_total, 0, NULL, NULL, NULL};
+  double *cdf = NULL;
+  if (src->kind == 2 && !(cdf = emission_cdf(g, rho, d, src->B))) return -1;
+  run_t R = {g, rho, bhat, d, src, o, lam, n_total, 0, NULL, NULL, NULL, cdf};
   int nth = o->nthreads;
 #pragma omp parallel num_threads(nth > 0 ? nth : omp_get_max_threads())
   {
@@ -725,17 +826,27 @@ int kpo_trace_packets(const kpo_grid *g, const float *rho, const float *bhat,
 #pragma omp for schedule(dynamic, 4)
     for (int64_t k = 0; k < (int64_t)n_ids; ++k) run_packet(&R, ids[k], &traces[k], &local);
   }
+  free(cdf);
   return 0;
+}
+
+int kpo_image(const kpo_grid *g, const float *rho, const float *bhat,
+              const kpo_dust *d, int32_t n_views, const kpo_view *views,
+              const double *S, double *images) {
+  if (!S) return -1;
+  return kpo_image_thermal(g, rho, bhat, d, n_views, views, S, NULL, images);
 }
 
 /* Step 2 of two-step imaging (Sec. 2.3): march each pixel ray across the
  * grid toward the camera, solving Appendix A cell by cell with the source
- * S/(rho kappa_ext) per unit optical depth (reading R9 for the camera). */
-int kpo_image(const kpo_grid *g, const float *rho, const float *bhat,
-              const kpo_dust *d, int32_t n_views, const kpo_view *views,
-              const double *S, double *images) {
-  kpo_source dummy = {0, {0, 0, 0}, {0, 0, 1}, 1.0};
-  if (check_inputs(g, d, &dummy) || n_views <= 0 || !views || !S || !images) return -1;
+ * S/(rho kappa_ext) per unit optical depth (reading R9 for the camera), plus
+ * the dust's thermal emission (kappa_abs/kappa_ext)(alpha1, alpha2, 0, 0) B
+ * per unit optical depth in the grain-frame basis (eq. polarized-rt, E1). */
+int kpo_image_thermal(const kpo_grid *g, const float *rho, const float *bhat,
+                      const kpo_dust *d, int32_t n_views, const kpo_view *views,
+                      const double *S, const float *B, double *images) {
+  kpo_source dummy = {0, {0, 0, 0}, {0, 0, 1}, 1.0, NULL};
+  if (check_inputs(g, d, &dummy) || n_views <= 0 || !views || !images) return -1;
   int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
   double kext = d->kappa_sca + d->kappa_abs;
   double lo[3] = {g->x0, g->y0, g->z0};
@@ -791,10 +902,14 @@ int kpo_image(const kpo_grid *g, const float *rho, const float *bhat,
               kpo_to_grain(q, om, og);
               kpo_alphas(d, og[2], al);
               double eta = eta_pair(q, om, og);
-              const double *Sc = S + (c * n_views + v) * 4;
-              for (int k = 0; k < 4; ++k) src[k] = Sc[k] / ke;
+              for (int k = 0; k < 4; ++k) src[k] = S ? S[(c * n_views + v) * 4 + k] / ke : 0.0;
               kpo_rotate_stokes(eta, st, sg);
               kpo_rotate_stokes(eta, src, srcg);
+              if (B) {
+                double e = d->kappa_abs / kext * (double)B[c];
+                srcg[0] += e * al[0];
+                srcg[1] += e * al[1];
+              }
               double out[4];
               kpo_appA(al[0], al[1], al[2], ke * tf * g->dx, srcg, sg, out);
               kpo_rotate_stokes(-eta, out, st);

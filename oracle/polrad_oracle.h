@@ -40,9 +40,12 @@ typedef struct {
 } kpo_dust;
 
 typedef struct {
-  int32_t kind;                 /* 0 isotropic point source, 1 pencil beam along dir */
+  int32_t kind;                 /* 0 isotropic point source, 1 pencil beam along dir,
+                                   2 thermal emission of the dust (reading E1) */
   double pos[3], dir[3];
-  double lum;                   /* luminosity per wavelength */
+  double lum;                   /* luminosity per wavelength (kinds 0 and 1) */
+  const float *B;               /* kind 2: source function of every cell [ncell]
+                                   at this wavelength */
 } kpo_source;
 
 typedef struct {
@@ -105,6 +108,22 @@ int kpo_trace_packets(const kpo_grid *g, const float *rho, const float *bhat,
 int kpo_image(const kpo_grid *g, const float *rho, const float *bhat,
               const kpo_dust *d, int32_t n_views, const kpo_view *views,
               const double *S, double *images);
+/* Step 2 with the dust's thermal emission added to the source (eq.
+ * polarized-rt, alpha_abs B): B[ncell] the source function of every cell
+ * (NULL: none); S may be NULL (no scattering source). */
+int kpo_image_thermal(const kpo_grid *g, const float *rho, const float *bhat,
+                      const kpo_dust *d, int32_t n_views, const kpo_view *views,
+                      const double *S, const float *B, double *images);
+/* Thermal emission draw of packet `packet` (reading E1): its cell, position
+ * inside the cell (cell units), direction and Stokes vector (lab basis),
+ * for a packet weight w. */
+int kpo_emit_state(const kpo_grid *g, const float *rho, const float *bhat,
+                   const kpo_dust *d, const float *B, uint64_t seed, int32_t lam,
+                   uint64_t packet, double w, int64_t *cell, double pos[3], double n[3],
+                   double s[4]);
+/* Total thermal luminosity 4 pi sum_c rho_c kappa_abs B_c V of the grid. */
+double kpo_emission_luminosity(const kpo_grid *g, const float *rho, const kpo_dust *d,
+                               const float *B);
 
 /* ---- building blocks, exported for the pin tests ---- */
 void kpo_philox(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);

@@ -11,7 +11,10 @@ A workload is a plain dict:
   bhat    float32[3, ncell] or None     unit grain-alignment direction per cell
   dust    list (one per wavelength) of {kappa_sca, kappa_abs, a_perp, a_par,
           alpha3_scale}; kappas per unit density per unit length
-  source  {kind (0 isotropic point, 1 pencil), pos, dir, lum}
+  source  {kind (0 isotropic point, 1 pencil, 2 the dust's thermal emission),
+          pos, dir, lum}
+  emission float32[n_lambda, ncell]     (kind 2 only) source function B of
+          every cell at each wavelength
   views   list of {theta, phi, npx, npy, half_width}
   packets list (one per wavelength) of packet counts
   opts    {seed, rr_wmin, rr_psurv, max_events}
@@ -238,6 +241,86 @@ def pencil_slab(n_z=256, tau_total=1.0, p0=0.01, alpha3_scale=0.0, twist=True,
                 source=dict(kind=1, pos=(0.0, 0.0, start_tau), dir=(0.0, 0.0, -1.0), lum=1.0),
                 views=[view(0.0, 0.0, 4)], packets=[1],
                 opts=dict(default_opts(0), rr_wmin=0.0), precision="f64")
+
+
+# --------------------------------------------------------------------------
+# thermal emission of the dust (source kind 2)
+# --------------------------------------------------------------------------
+THERMAL_SOURCE = dict(kind=2, pos=(0.0, 0.0, 0.0), dir=(0.0, 0.0, 1.0), lum=1.0)
+
+
+def _isothermal(rho, n_lambda=1, B=1.0):
+    """Source function B of every cell, the same everywhere (isothermal
+    dust; B in units of the Planck function at the dust temperature)."""
+    return np.full((n_lambda, rho.size), B, dtype=np.float32)
+
+
+def thermal_cube(n=32, packets=1_000_000, tau_half=20.0, albedo=0.5, seed=5, npix=32) -> dict:
+    """Isothermal cube of uniform density filling [-1,1]^3, optical depth
+    tau_half from the centre to a face, Rayleigh spheres, the dust's thermal
+    emission as the only source, one face-on view."""
+    grid = _cube(n)
+    rho = np.ones(n ** 3, dtype=np.float32)
+    return dict(name=f"thermal_cube{n}", grid=grid, rho=rho, bhat=None,
+                dust=[sphere_dust(tau_half, albedo)], source=dict(THERMAL_SOURCE),
+                emission=_isothermal(rho), views=[view(0.0, 0.0, npix)],
+                packets=[int(packets)], opts=default_opts(seed), precision="f64")
+
+
+def thermal_sphere(n=64, packets=100_000, tau_radius=1.0, albedo=0.0, seed=6, npix=32) -> dict:
+    """Isothermal uniform sphere of radius 1 (density 1 where the cell centre
+    lies inside), radial optical depth tau_radius, Rayleigh spheres, thermal
+    emission as the only source (pure absorption by default)."""
+    grid = _cube(n)
+    X, Y, Z = _mesh(grid)
+    rho = _flat((X * X + Y * Y + Z * Z < 1.0).astype(np.float64))
+    return dict(name=f"thermal_sphere{n}", grid=grid, rho=rho, bhat=None,
+                dust=[sphere_dust(tau_radius, albedo)], source=dict(THERMAL_SOURCE),
+                emission=_isothermal(rho), views=[view(90.0, 0.0, npix)],
+                packets=[int(packets)], opts=default_opts(seed), precision="f64")
+
+
+def emission_slab(tau_total=1.0, p0=0.3, n_z=16, nxy=4, packets=2000, albedo=0.0) -> dict:
+    """Uniformly aligned, isothermal dichroic slab (Sec. 3.3): the grains of
+    pencil_slab (alignment along x, polarization efficiency p0 across it),
+    optical depth tau_total along z, thermal emission as the only source,
+    viewed along z.  With albedo 0 its image is eq. ptau in every pixel."""
+    cfg = pencil_slab(n_z=n_z, tau_total=tau_total, p0=p0, twist=False, start_tau=tau_total, nxy=nxy)
+    d = dict(cfg["dust"][0])
+    kext = d["kappa_abs"]
+    d["kappa_sca"], d["kappa_abs"] = albedo * kext, (1.0 - albedo) * kext
+    g = cfg["grid"]
+    cfg.update(name="emission_slab", dust=[d], source=dict(THERMAL_SOURCE),
+               emission=_isothermal(cfg["rho"]), packets=[int(packets)],
+               views=[dict(theta=0.0, phi=0.0, npx=nxy, npy=nxy, half_width=nxy * g["dx"] / 2)],
+               opts=dict(default_opts(7), rr_wmin=0.0))
+    return cfg
+
+
+def dust_cylinder(n=128, packets=10_000_000, tau_axis=1.0, r0=0.25, albedo=0.5, aligned=False,
+                  seed=8, npix=None) -> dict:
+    """The isothermal dust cylinder of Sec. 3.1 (self-scattering of thermal
+    emission): axis along x, rho = rho0 exp(-(r/r0)^2) with r the distance
+    from the axis, optical depth tau_axis through the axis along z
+    (rho0 kappa r0 sqrt(pi)); Rayleigh spheres, or with aligned=True oblate
+    grains aligned along y (across the axis, in the sky plane of the face-on
+    view); thermal emission as the only source.  Views: face-on (along z)
+    and 60 deg from it toward x."""
+    grid = _cube(n)
+    X, Y, Z = _mesh(grid)
+    rho = _flat(np.exp(-(Y * Y + Z * Z) / r0 ** 2))
+    kext = tau_axis / (r0 * math.sqrt(math.pi))
+    npix = npix or n
+    bhat = None
+    dust = sphere_dust(kext, albedo)
+    if aligned:
+        bhat = np.zeros((3, rho.size), dtype=np.float32)
+        bhat[1] = 1.0
+        dust = oblate_dust(kext, albedo)
+    return dict(name=f"dust_cylinder{n}", grid=grid, rho=rho, bhat=bhat, dust=[dust],
+                source=dict(THERMAL_SOURCE), emission=_isothermal(rho),
+                views=[view(0.0, 0.0, npix), view(60.0, 0.0, npix)],
+                packets=[int(packets)], opts=default_opts(seed), precision="f32")
 
 
 # --------------------------------------------------------------------------
