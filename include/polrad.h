@@ -75,7 +75,18 @@ typedef struct {
 /* kind 0: isotropic unpolarised point source at pos; kind 1: pencil beam from
  * pos along dir (tests).  lum is the luminosity per wavelength; each packet
  * of a wavelength with N packets starts with I = lum / N.  pos must lie in
- * the closed grid box. */
+ * the closed grid box.
+ * kind 2: thermal emission of the dust (Sec. 2.2, the alpha_abs B term of
+ * eq. polarized-rt) with the source function set by kp_set_emission; pos,
+ * dir and lum are ignored.  A cell's luminosity is 4 pi rho kappa_abs B dx^3
+ * and L the sum over cells; packets start in a cell drawn in proportion to
+ * it, uniformly inside the cell, in an isotropic direction, with the Stokes
+ * vector (L / N) (alpha1, alpha2, 0, 0) in the grain-frame basis of that
+ * direction: the absorption matrix is taken as kappa_abs / kappa_ext times
+ * the extinction matrix (Appendix A with the source (alpha1, alpha2) B when
+ * all extinction is absorption); its mean over directions is L / N.  Step 2
+ * then adds (kappa_abs / kappa_ext)(alpha1, alpha2, 0, 0) B per unit optical
+ * depth to the scattering source. */
 typedef struct {
   int32_t kind;
   double pos[3], dir[3];
@@ -204,8 +215,16 @@ kp_status kp_set_dust(kp_ctx *ctx, int32_t n_lambda, const kp_dust *dust);
 /* The radiation source whose packets are emitted (Sec. 2.2: packets are
  * generated and given an exponentially distributed scattering optical
  * depth); copied.  KP_ERR_ARG for an unknown kind, a non-positive
- * luminosity or a zero pencil direction. */
+ * luminosity or a zero pencil direction (kinds 0 and 1). */
 kp_status kp_set_source(kp_ctx *ctx, const kp_source *src);
+/* Source function of the dust's thermal emission (Sec. 2.2, B of eq.
+ * polarized-rt; used by source kind 2): B[n_lambda][ncell] (host, float32,
+ * finite, >= 0), e.g. the Planck function of each cell's temperature at each
+ * wavelength, in the units the images are wanted in (lengths in the grid's
+ * unit); copied to the device.  n_lambda must equal kp_set_dust's at the
+ * next run.  Needs a grid; kp_set_grid / kp_set_grid_device discard it.
+ * KP_ERR_ARG for a negative or non-finite value. */
+kp_status kp_set_emission(kp_ctx *ctx, int32_t n_lambda, const float *B);
 /* Cameras of step 2 (Sec. 2.3, the camera direction Omega_cam of eq.
  * scat-disc-sum): n_views (1..4096) views (copied), all with the same npx,
  * npy (1..16384). */

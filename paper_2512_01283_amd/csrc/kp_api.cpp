@@ -100,6 +100,20 @@ struct kp_ctx {
   // this device's copy of the static scratch (kp_run_static), or null
   unsigned char* scratch = nullptr;
   hipError_t scratch_err = hipSuccess;
+  // thermal emission of the dust (source kind 2): source function
+  // [n_lambda][ncell], the per-wavelength luminosity tables built from it,
+  // and each wavelength's total luminosity
+  bool have_emission = false;
+  int em_nl = 0;
+  float* d_em_B = nullptr;
+  double* d_em_cdf = nullptr;
+  size_t em_cdf_n = 0;
+  uint32_t* d_em_guide = nullptr;
+  size_t em_guide_n = 0;
+  double* d_em_partial = nullptr;
+  size_t em_partial_n = 0;
+  bool em_ready = false;  // tables match the current grid, dust and source function
+  std::vector<double> em_L;
 };
 
 namespace {
@@ -151,6 +165,11 @@ void release_grid(kp_ctx* ctx) {
   ctx->have_grid = false;
   ctx->have_tally = false;
   ctx->have_images = false;
+  // a source function belongs to the grid it was given for
+  if (ctx->d_em_B) (void)hipFree(ctx->d_em_B);
+  ctx->d_em_B = nullptr;
+  ctx->have_emission = false;
+  ctx->em_ready = false;
 }
 
 kp_status check_grid(kp_ctx* ctx, const kp_grid* g) {
@@ -211,7 +230,8 @@ void fill_dust(const kp_ctx* ctx, const uint64_t* counts, std::vector<DustDev>& 
     o.aa2_np = aa2 / np;
     o.count = counts ? counts[l] : 0;
     o.first = first;
-    o.w0 = o.count ? lum / (double)o.count : 0.0;
+    const double L = ctx->src.kind == 2 ? (l < ctx->em_L.size() ? ctx->em_L[l] : 0.0) : lum;
+    o.w0 = o.count ? L / (double)o.count : 0.0;
     first += o.count;
   }
 }
@@ -233,6 +253,14 @@ kp_status check_ready(kp_ctx* ctx) {
   if (ctx->dust.empty()) return fail(ctx, KP_ERR_STATE, "kp_set_dust has not been called");
   if (!ctx->have_source) return fail(ctx, KP_ERR_STATE, "kp_set_source has not been called");
   if (ctx->views.empty()) return fail(ctx, KP_ERR_STATE, "kp_set_views has not been called");
+  if (ctx->src.kind == 2) {
+    if (!ctx->have_emission)
+      return fail(ctx, KP_ERR_STATE, "thermal emission source: kp_set_emission has not been called for this grid");
+    if (ctx->em_nl != (int)ctx->dust.size())
+      return fail(ctx, KP_ERR_ARG, "kp_set_emission gave %d wavelengths, kp_set_dust %zu", ctx->em_nl,
+                  ctx->dust.size());
+    return KP_OK;
+  }
   const kp_grid& g = ctx->grid;
   const double lo[3] = {g.x0, g.y0, g.z0};
   const int n[3] = {g.nx, g.ny, g.nz};
@@ -264,6 +292,7 @@ kp_status image_launch(kp_ctx* ctx, bool user_source, const double* d_S, double*
   a.user_S = d_S;
   a.images = d_out;
   a.ncell = ctx->ncell;
+  a.em_B = (!user_source && ctx->src.kind == 2) ? ctx->d_em_B : nullptr;
   // every wavelength shares the grain model kind of wavelength 0 for the
   // kernel choice; mixed sphere / non-sphere tables use the general kernel
   bool sphere = true;
@@ -278,6 +307,39 @@ bool all_spheres(const kp_ctx* ctx) {
   for (const kp_dust& d : ctx->dust)
     if (!is_sphere(d)) return false;
   return true;
+}
+
+// The luminosity tables of the dust's thermal emission for every wavelength
+// (cdf, guide) and each wavelength's total luminosity, rebuilt when the
+// grid, the dust or the source function changed.  May allocate.
+kp_status prepare_emission(kp_ctx* ctx, hipStream_t s) {
+  if (ctx->em_ready) return KP_OK;
+  const int nl = (int)ctx->dust.size();
+  const uint64_t n = ctx->ncell;
+  kp_status st = ensure(ctx, &ctx->d_em_cdf, &ctx->em_cdf_n, (size_t)nl * n, "emission table");
+  if (st) return st;
+  if ((st = ensure(ctx, &ctx->d_em_guide, &ctx->em_guide_n, (size_t)nl * (n + 1), "emission guide")))
+    return st;
+  if ((st = ensure(ctx, &ctx->d_em_partial, &ctx->em_partial_n, (size_t)emission_blocks(n),
+                   "emission scan")))
+    return st;
+  const double vol = ctx->grid.dx * ctx->grid.dx * ctx->grid.dx;
+  ctx->em_L.assign(nl, 0.0);
+  for (int l = 0; l < nl; ++l) {
+    const double fac = 4.0 * M_PI * ctx->dust[l].kappa_abs * vol;
+    KP_HIP(launch_emission_table(ctx->d_rho, ctx->d_em_B + (size_t)l * n, fac, n, ctx->d_em_partial,
+                                 ctx->d_em_cdf + (size_t)l * n, ctx->d_em_guide + (size_t)l * (n + 1), s),
+           "emission table launch");
+    KP_HIP(hipMemcpyAsync(&ctx->em_L[l], ctx->d_em_cdf + (size_t)l * n + (n - 1), sizeof(double),
+                          hipMemcpyDeviceToHost, s), "emission luminosity readback");
+  }
+  KP_HIP(hipStreamSynchronize(s), "emission tables");
+  for (int l = 0; l < nl; ++l)
+    if (!(ctx->em_L[l] > 0.0) || !std::isfinite(ctx->em_L[l]))
+      return fail(ctx, KP_ERR_ARG, "wavelength %d: the dust's thermal luminosity is %g (needs rho kappa_abs B > 0 "
+                  "somewhere)", l, ctx->em_L[l]);
+  ctx->em_ready = true;
+  return KP_OK;
 }
 
 // Checks of a step-1 call (kp_transport, kp_run, kp_run_static) before any
@@ -362,6 +424,10 @@ kp_status transport_launch(kp_ctx* ctx, const kp_opts* o, uint64_t total, const 
   a.trace_stride = o->trace_stride ? o->trace_stride : 1;
   a.scatter_batch = o->scatter_batch ? o->scatter_batch : 8;
   a.scatter_wait = o->scatter_wait ? o->scatter_wait : 16;
+  if (ctx->src.kind == 2) {
+    a.em_cdf = ctx->d_em_cdf;
+    a.em_guide = ctx->d_em_guide;
+  }
 
   const bool sphere = all_sphere;
   const bool aligned = ctx->d_bhat != nullptr;
@@ -443,7 +509,8 @@ void kp_destroy(kp_ctx* ctx) {
   release_grid(ctx);
   for (void* p : {(void*)ctx->d_views, (void*)ctx->d_dust, (void*)ctx->d_tally,
                   (void*)ctx->d_images, (void*)ctx->d_stats, (void*)ctx->d_counter,
-                  (void*)ctx->d_bad, (void*)ctx->d_traces})
+                  (void*)ctx->d_bad, (void*)ctx->d_traces, (void*)ctx->d_em_cdf,
+                  (void*)ctx->d_em_guide, (void*)ctx->d_em_partial})
     if (p) (void)hipFree(p);
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
@@ -527,14 +594,15 @@ kp_status kp_set_dust(kp_ctx* ctx, int32_t n_lambda, const kp_dust* d) {
   ctx->dust.assign(d, d + n_lambda);
   ctx->have_tally = false;
   ctx->have_images = false;
+  ctx->em_ready = false;
   return KP_OK;
 }
 
 kp_status kp_set_source(kp_ctx* ctx, const kp_source* s) {
   if (!ctx) return KP_ERR_ARG;
   if (!s) return fail(ctx, KP_ERR_ARG, "source is NULL");
-  if (s->kind != 0 && s->kind != 1) return fail(ctx, KP_ERR_ARG, "source kind must be 0 or 1");
-  if (!finite3(s->pos) || !std::isfinite(s->lum) || !(s->lum > 0.0))
+  if (s->kind < 0 || s->kind > 2) return fail(ctx, KP_ERR_ARG, "source kind must be 0, 1 or 2");
+  if (s->kind != 2 && (!finite3(s->pos) || !std::isfinite(s->lum) || !(s->lum > 0.0)))
     return fail(ctx, KP_ERR_ARG, "source position/luminosity invalid");
   kp_source c = *s;
   if (s->kind == 1) {
@@ -543,8 +611,31 @@ kp_status kp_set_source(kp_ctx* ctx, const kp_source* s) {
     if (!(n > 0.0)) return fail(ctx, KP_ERR_ARG, "pencil direction is zero");
     for (int k = 0; k < 3; ++k) c.dir[k] = s->dir[k] / n;
   }
+  if (s->kind == 2) c.lum = 0.0;  // the dust's luminosity comes from the grid
   ctx->src = c;
   ctx->have_source = true;
+  return KP_OK;
+}
+
+kp_status kp_set_emission(kp_ctx* ctx, int32_t n_lambda, const float* B) {
+  if (!ctx) return KP_ERR_ARG;
+  if (!ctx->have_grid) return fail(ctx, KP_ERR_STATE, "kp_set_grid has not been called");
+  if (n_lambda < 1 || n_lambda > 1024 || !B) return fail(ctx, KP_ERR_ARG, "n_lambda must be in 1..1024");
+  const uint64_t n = ctx->ncell;
+  const size_t total = (size_t)n_lambda * n;
+  for (size_t i = 0; i < total; ++i)
+    if (!(B[i] >= 0.0f) || !std::isfinite(B[i]))
+      return fail(ctx, KP_ERR_ARG, "B[%zu] is negative or not finite", i);
+  KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  if (ctx->d_em_B) (void)hipFree(ctx->d_em_B);
+  ctx->d_em_B = nullptr;
+  ctx->have_emission = false;
+  ctx->em_ready = false;
+  KP_HIP(hipMalloc(&ctx->d_em_B, total * sizeof(float)), "emission allocation");
+  KP_HIP(hipMemcpy(ctx->d_em_B, B, total * sizeof(float), hipMemcpyHostToDevice), "emission upload");
+  ctx->em_nl = n_lambda;
+  ctx->have_emission = true;
+  ctx->have_images = false;
   return KP_OK;
 }
 
@@ -586,6 +677,7 @@ kp_status kp_transport(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, vo
   if (extra > free_b) return fail(ctx, KP_ERR_OOM, "tally needs %zu bytes, %zu free", extra, free_b);
   if ((st = ensure(ctx, &ctx->d_tally, &ctx->tally_n, tally_need, "tally allocation"))) return st;
   if ((st = ensure(ctx, &ctx->d_traces, &ctx->traces_n, trace_need, "trace allocation"))) return st;
+  if (ctx->src.kind == 2 && (st = prepare_emission(ctx, s))) return st;
   fill_dust(ctx, counts, ctx->hdust);
   if ((st = upload_small(ctx, s))) return st;
   const RunBuffers buf{ctx->d_dust, ctx->d_tally, ctx->d_stats, ctx->d_counter, ctx->d_traces};
@@ -636,6 +728,9 @@ kp_status kp_run_static(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, d
   kp_status st = check_run_args(ctx, counts, o, &total);
   if (st) return st;
   if (o->trace_packets) return fail(ctx, KP_ERR_ARG, "kp_run_static records no traces: trace_packets must be 0");
+  if (ctx->src.kind == 2 && !ctx->em_ready)
+    return fail(ctx, KP_ERR_STATE, "thermal emission: its luminosity tables are built by kp_run or kp_transport; "
+                "call one of them once after kp_set_emission, kp_set_dust or kp_set_grid");
   if (!ctx->scratch)
     return fail(ctx, KP_ERR_DEVICE, "static scratch of device %d unavailable: %s", ctx->device,
                 hipGetErrorString(ctx->scratch_err));

@@ -73,6 +73,12 @@ struct TransportArgs {
   uint32_t trace_count, trace_stride;
   int scatter_batch;  // run parked scattering events once this many lanes wait
   int scatter_wait;   // ... or after this many iterations
+  // thermal emission of the dust (src_kind 2): per wavelength the running
+  // sum of cell luminosities [lambda][ncell] and its guide table
+  // [lambda][ncell + 1] (entry k: the first cell whose running sum exceeds
+  // L k / ncell; entry ncell: the last cell)
+  const double* em_cdf;
+  const uint32_t* em_guide;
 };
 
 struct ImageArgs {
@@ -89,6 +95,8 @@ struct ImageArgs {
   const double* user_S; // [ncell][view][4]     (per-view source, wavelength 0)
   double* images;       // [lambda][view][4][npy][npx]
   uint64_t ncell;
+  const float* em_B;    // [lambda][ncell] source function of the dust's thermal
+                        // emission, or null (no thermal source term)
 };
 
 // Tally layout [lambda][cell][stride] FP64: 6 reals (stride 8, one 64-B block
@@ -110,5 +118,12 @@ hipError_t launch_tally_init(double* tally, const float* rho, const float* bx, c
 hipError_t launch_validate(const float* rho, const float* bx, const float* by, const float* bz,
                            uint64_t n, unsigned long long* bad, hipStream_t s);
 int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, int block_size);
+// Thermal emission tables of one wavelength: cdf [ncell], the running sum
+// of fac rho B (fac = 4 pi kappa_abs dx^3) in flat cell order, and its guide
+// table [ncell + 1]; `partial` holds emission_blocks(ncell) doubles of
+// scratch.
+hipError_t launch_emission_table(const float* rho, const float* B, double fac, uint64_t ncell,
+                                 double* partial, double* cdf, uint32_t* guide, hipStream_t s);
+uint64_t emission_blocks(uint64_t ncell);
 
 }  // namespace kp

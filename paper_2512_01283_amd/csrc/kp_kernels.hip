@@ -104,11 +104,59 @@ __device__ __forceinline__ R next_uniform(Packet<R>& p, uint64_t seed) {
   return k == 0 ? p.u0 : (k == 1 ? p.u1 : (k == 2 ? p.u2 : p.u3));
 }
 
-// Emission (Sec. 2.2): isotropic direction (or the pencil direction), an
-// unpolarised Stokes vector of weight lum/N, an exponential scattering depth,
-// and the cell holding the source (a coordinate on a face belongs to the cell
-// the direction points into).  Returns false if the start lies outside.
+// Dimensionless extinction coefficients for a direction with cos(theta') =
+// ct to the grain axis (dipole: cross sections from Im of the
+// polarizability, normalised by the orientation average).
+template <typename R, bool SPHERE>
+__device__ __forceinline__ void alphas(const DustDev& D, R ct, R& a1, R& a2, R& a3) {
+  if (SPHERE) { a1 = (R)1; a2 = (R)0; a3 = (R)0; return; }
+  R cth = (R)D.ap_im * ct * ct + (R)D.aa_im * (sizeof(R) == 4 ? ((R)1 - ct) * ((R)1 + ct) : (R)1 - ct * ct);
+  R cph = (R)D.ap_im;
+  a1 = (cth + cph) * (R)D.inv2cavg;
+  a2 = (cth - cph) * (R)D.inv2cavg;
+  a3 = (R)D.alpha3_scale * a2;
+}
+
+// Isotropic direction from two uniforms: mu = 2 u0 - 1, azimuth 2 pi u1.
 template <typename R>
+__device__ __forceinline__ void isotropic_dir(Packet<R>& p, double u0, double u1) {
+  const double mu = 2.0 * u0 - 1.0;
+  const double s = sqrt(fmax(0.0, 1.0 - mu * mu));
+  double sp, cp;
+  sincospi(2.0 * u1, &sp, &cp);
+  p.nx = s * cp; p.ny = s * sp; p.nz = mu;
+}
+
+// The cell emitting a packet of the dust's thermal emission: the first cell
+// whose running luminosity sum exceeds u L.  The guide table brackets it:
+// entry k - 1 (or cell 0) from below and entry k + 1 from above, k =
+// floor(u ncell), so the search spans only the cells between two guide
+// points.
+__device__ __forceinline__ uint64_t emission_cell(const double* F, const uint32_t* G, uint64_t ncell,
+                                                  double u) {
+  const double t = u * F[ncell - 1];
+  uint64_t k = (uint64_t)(u * (double)ncell);
+  if (k > ncell - 1) k = ncell - 1;
+  uint64_t lo = k > 0 ? (uint64_t)G[k - 1] : 0ull, hi = (uint64_t)G[k + 1];
+  while (lo < hi) {
+    const uint64_t mid = lo + ((hi - lo) >> 1);
+    if (t < F[mid]) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+// Emission (Sec. 2.2).  Point sources: isotropic direction (or the pencil
+// direction), an unpolarised Stokes vector of weight lum/N, and the cell
+// holding the source (a coordinate on a face belongs to the cell the
+// direction points into).  Thermal emission of the dust (the alpha_abs B
+// term of eq. polarized-rt): the cell drawn by luminosity 4 pi rho kappa_abs
+// B V, the position uniform in it, an isotropic direction and the Stokes
+// vector w (alpha1, alpha2, 0, 0) in the grain-frame basis of the direction
+// (the dichroism of absorption is that of extinction), carried to the lab
+// basis; its mean over directions is w.  Draws: cell, three coordinates,
+// two for the direction.  Then an exponential scattering depth.  Returns
+// false if a point source lies outside the grid.
+template <typename R, bool ALIGNED, bool SPHERE>
 __device__ bool init_packet(Packet<R>& p, uint64_t g, const TransportArgs& a) {
   int lo = 0, hi = a.n_lambda - 1;
   while (lo < hi) {  // last wavelength whose first index <= g
@@ -119,46 +167,74 @@ __device__ bool init_packet(Packet<R>& p, uint64_t g, const TransportArgs& a) {
   p.pid = g - a.dust[lo].first;
   p.draw = 0;
   p.blk = 0xffffffffu;
-  const double u0 = (double)next_uniform(p, a.seed), u1 = (double)next_uniform(p, a.seed);
-  if (a.src_kind == 1) {
-    p.nx = a.dx_; p.ny = a.dy_; p.nz = a.dz_;
-  } else {
-    const double mu = 2.0 * u0 - 1.0;
-    const double s = sqrt(fmax(0.0, 1.0 - mu * mu));
-    double sp, cp;
-    sincospi(2.0 * u1, &sp, &cp);
-    p.nx = s * cp; p.ny = s * sp; p.nz = mu;
-  }
-  p.rnx = 1.0 / p.nx; p.rny = 1.0 / p.ny; p.rnz = 1.0 / p.nz;
-  p.tau = -log((double)next_uniform(p, a.seed));
   p.w0 = (R)a.dust[lo].w0;
   p.ks = a.dust[lo].ks_cell;
   p.ke = a.dust[lo].ke_cell;
   p.ka = (R)a.dust[lo].ka_cell;
-  p.I = p.w0; p.Q = (R)0; p.U = (R)0; p.V = (R)0;
   p.e_abs = 0.0; p.e_scat = 0.0; p.e_gain = 0.0;
   p.tau_path = (R)0;
   p.events = 0; p.steps = 0; p.trials = 0; p.rr = 0;
   p.hash = 14695981039346656037ull;
   p.last = -1;
-  const double pos[3] = {a.sx, a.sy, a.sz}, org[3] = {a.x0, a.y0, a.z0};
-  const double dir[3] = {p.nx, p.ny, p.nz};
-  int ci[3];
-  double fr[3];
+  bool in = true;
+  if (a.src_kind == 2) {
+    const uint64_t c = emission_cell(a.em_cdf + (uint64_t)lo * a.ncell,
+                                     a.em_guide + (uint64_t)lo * (a.ncell + 1), a.ncell,
+                                     (double)next_uniform(p, a.seed));
+    p.ci = (int)(c % (uint64_t)a.nx);
+    p.cj = (int)((c / (uint64_t)a.nx) % (uint64_t)a.ny);
+    p.ck = (int)(c / ((uint64_t)a.nx * (uint64_t)a.ny));
+    p.fx = (double)next_uniform(p, a.seed);
+    p.fy = (double)next_uniform(p, a.seed);
+    p.fz = (double)next_uniform(p, a.seed);
+    const double u0 = (double)next_uniform(p, a.seed), u1 = (double)next_uniform(p, a.seed);
+    isotropic_dir(p, u0, u1);
+    const double w = a.dust[lo].w0;
+    if (SPHERE) {
+      p.I = (R)w; p.Q = (R)0; p.U = (R)0; p.V = (R)0;
+    } else {
+      const V3<double> nd{p.nx, p.ny, p.nz};
+      V3<double> ngd = nd;
+      double c2 = 1.0, s2 = 0.0;
+      if (ALIGNED) {
+        const Quat<double> qd = grain_quat(V3<double>{(double)a.bx[c], (double)a.by[c], (double)a.bz[c]});
+        ngd = to_grain(qd, nd);
+        eta2(qd, nd, ngd, c2, s2);
+      }
+      double a1, a2, a3;
+      alphas<double, SPHERE>(a.dust[lo], ngd.z, a1, a2, a3);
+      p.I = (R)(w * a1); p.Q = (R)(c2 * w * a2); p.U = (R)(s2 * w * a2); p.V = (R)0;
+    }
+    p.rho = a.rho[c];
+  } else {
+    const double u0 = (double)next_uniform(p, a.seed), u1 = (double)next_uniform(p, a.seed);
+    if (a.src_kind == 1) {
+      p.nx = a.dx_; p.ny = a.dy_; p.nz = a.dz_;
+    } else {
+      isotropic_dir(p, u0, u1);
+    }
+    p.I = p.w0; p.Q = (R)0; p.U = (R)0; p.V = (R)0;
+    const double pos[3] = {a.sx, a.sy, a.sz}, org[3] = {a.x0, a.y0, a.z0};
+    const double dir[3] = {p.nx, p.ny, p.nz};
+    int ci[3];
+    double fr[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    double t = (pos[k] - org[k]) / a.dx;
-    double fl = floor(t);
-    double f = t - fl;
-    int i = (int)fl;
-    if (f == 0.0 && dir[k] < 0.0) { i -= 1; f = 1.0; }
-    ci[k] = i;
-    fr[k] = f;
+    for (int k = 0; k < 3; ++k) {
+      double t = (pos[k] - org[k]) / a.dx;
+      double fl = floor(t);
+      double f = t - fl;
+      int i = (int)fl;
+      if (f == 0.0 && dir[k] < 0.0) { i -= 1; f = 1.0; }
+      ci[k] = i;
+      fr[k] = f;
+    }
+    p.ci = ci[0]; p.cj = ci[1]; p.ck = ci[2];
+    p.fx = fr[0]; p.fy = fr[1]; p.fz = fr[2];
+    in = p.ci >= 0 && p.ci < a.nx && p.cj >= 0 && p.cj < a.ny && p.ck >= 0 && p.ck < a.nz;
+    p.rho = in ? a.rho[(uint64_t)p.ci + (uint64_t)a.nx * ((uint64_t)p.cj + (uint64_t)a.ny * p.ck)] : 0.f;
   }
-  p.ci = ci[0]; p.cj = ci[1]; p.ck = ci[2];
-  p.fx = fr[0]; p.fy = fr[1]; p.fz = fr[2];
-  const bool in = p.ci >= 0 && p.ci < a.nx && p.cj >= 0 && p.cj < a.ny && p.ck >= 0 && p.ck < a.nz;
-  p.rho = in ? a.rho[(uint64_t)p.ci + (uint64_t)a.nx * ((uint64_t)p.cj + (uint64_t)a.ny * p.ck)] : 0.f;
+  p.rnx = 1.0 / p.nx; p.rny = 1.0 / p.ny; p.rnz = 1.0 / p.nz;
+  p.tau = -log((double)next_uniform(p, a.seed));
   return in;
 }
 
@@ -276,19 +352,6 @@ __device__ __forceinline__ void wave_drain(double* tally, double* sv, long long*
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Dimensionless extinction coefficients for a direction with cos(theta') =
-// ct to the grain axis (dipole: cross sections from Im of the
-// polarizability, normalised by the orientation average).
-template <typename R, bool SPHERE>
-__device__ __forceinline__ void alphas(const DustDev& D, R ct, R& a1, R& a2, R& a3) {
-  if (SPHERE) { a1 = (R)1; a2 = (R)0; a3 = (R)0; return; }
-  R cth = (R)D.ap_im * ct * ct + (R)D.aa_im * (sizeof(R) == 4 ? ((R)1 - ct) * ((R)1 + ct) : (R)1 - ct * ct);
-  R cph = (R)D.ap_im;
-  a1 = (cth + cph) * (R)D.inv2cavg;
-  a2 = (cth - cph) * (R)D.inv2cavg;
-  a3 = (R)D.alpha3_scale * a2;
 }
 
 // Scattering event (Sec. 2.2; rejection sampling of Sec. 3): incident state
@@ -611,7 +674,6 @@ __device__ void finish(const Packet<R>& p, uint32_t end, const TransportArgs& a,
   atomicAdd(&sc[SC_TRIALS], (unsigned long long)p.trials);
   atomicAdd(&sc[SC_PACK], 1ull);
   if (p.rr) atomicAdd(&sc[SC_SURV], (unsigned long long)p.rr);
-  atomicAdd(&se[SE_EMIT], (double)p.w0);
   if (end != END_NUMERIC) {
     atomicAdd(&se[SE_ABS], p.e_abs);
     atomicAdd(&se[SE_SCAT], p.e_scat);
@@ -706,7 +768,9 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
             const bool have = r < rem || refill;
             const unsigned long long g = r < rem ? wnext + r : base + (r - rem);
             if (have && g < a.total) {
-              if (init_packet(p, g, a)) active = true;
+              const bool in = init_packet<R, ALIGNED, SPHERE>(p, g, a);
+              atomicAdd(&se[SE_EMIT], (double)p.I);  // the emitted intensity
+              if (in) active = true;
               else finish(p, END_ESCAPE, a, sc, se);
             }
           }
@@ -725,7 +789,9 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
             const unsigned long long below = idle & ((1ull << lane) - 1ull);
             const unsigned long long g = base + (unsigned long long)__popcll(below);
             if (g < a.total) {
-              if (init_packet(p, g, a)) active = true;
+              const bool in = init_packet<R, ALIGNED, SPHERE>(p, g, a);
+              atomicAdd(&se[SE_EMIT], (double)p.I);  // the emitted intensity
+              if (in) active = true;
               else finish(p, END_ESCAPE, a, sc, se);
             }
           }
@@ -966,7 +1032,12 @@ __global__ void __launch_bounds__(256) k_image(ImageArgs a) {
         }
         const double ik = 1.0 / ke;
         double src[4] = {S[0] * ik, S[1] * ik, S[2] * ik, S[3] * ik};
+        // the dust's thermal emission per unit optical depth,
+        // (kappa_abs / kappa_ext) (alpha1, alpha2, 0, 0) B in the grain-frame
+        // basis of the ray (eq. polarized-rt)
+        const double eB = a.em_B ? D.ka_cell / D.ke_cell * (double)a.em_B[(uint64_t)lam * a.ncell + c] : 0.0;
         if (SPHERE && !ALIGNED) {
+          src[0] += eB;
           const double E = exp(-dtau), G = dtau * phi1(dtau);
 #pragma unroll
           for (int k = 0; k < 4; ++k) st[k] = st[k] * E + src[k] * G;
@@ -980,8 +1051,8 @@ __global__ void __launch_bounds__(256) k_image(ImageArgs a) {
           double a1, a2, a3;
           alphas<double, SPHERE>(D, og.z, a1, a2, a3);
           double sg[4] = {st[0], c2 * st[1] + s2 * st[2], -s2 * st[1] + c2 * st[2], st[3]};
-          const double srcg[4] = {src[0], c2 * src[1] + s2 * src[2], -s2 * src[1] + c2 * src[2],
-                                  src[3]};
+          const double srcg[4] = {src[0] + eB * a1, c2 * src[1] + s2 * src[2] + eB * a2,
+                                  -s2 * src[1] + c2 * src[2], src[3]};
           appA_eigen(a1, a2, a3, dtau, srcg, sg);
           st[0] = sg[0];
           st[1] = c2 * sg[1] - s2 * sg[2];
@@ -1045,6 +1116,113 @@ __global__ void k_validate(const float* rho, const float* bx, const float* by, c
     }
   }
   if (nbad) atomicAdd(bad, nbad);
+}
+
+// ---------------------------------------------------------------------------
+// Thermal emission tables (set-up of the dust's emission, Sec. 2.2): for one
+// wavelength the running sum F of the cell luminosities fac rho B (fac =
+// 4 pi kappa_abs dx^3) over the cells in flat order, and its guide table.
+// Blocks of EM_CHUNK cells; thread t of a block sums EM_PER consecutive cells.
+// ---------------------------------------------------------------------------
+constexpr int EM_THREADS = 256;
+constexpr int EM_PER = 16;
+constexpr uint64_t EM_CHUNK = (uint64_t)EM_THREADS * EM_PER;
+
+__device__ __forceinline__ double em_thread_sum(const float* rho, const float* B, double fac,
+                                                uint64_t first, uint64_t ncell) {
+  double sum = 0.0;
+  for (int k = 0; k < EM_PER; ++k) {
+    const uint64_t c = first + k;
+    if (c < ncell) sum += fac * (double)rho[c] * (double)B[c];
+  }
+  return sum;
+}
+
+// exclusive scan of one value per thread over a block of EM_THREADS
+__device__ __forceinline__ double em_block_exclusive(double v, double* sh, double* total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < EM_THREADS; off <<= 1) {
+    const double add = t >= off ? sh[t - off] : 0.0;
+    __syncthreads();
+    sh[t] += add;
+    __syncthreads();
+  }
+  const double incl = sh[t];
+  *total = sh[EM_THREADS - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void __launch_bounds__(EM_THREADS)
+k_em_partial(const float* rho, const float* B, double fac, uint64_t ncell, double* partial) {
+  __shared__ double sh[EM_THREADS];
+  const uint64_t first = (uint64_t)blockIdx.x * EM_CHUNK + (uint64_t)threadIdx.x * EM_PER;
+  double total;
+  em_block_exclusive(em_thread_sum(rho, B, fac, first, ncell), sh, &total);
+  if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+// one block: block totals -> exclusive block offsets, in place
+__global__ void __launch_bounds__(EM_THREADS) k_em_offsets(double* partial, uint64_t nb) {
+  __shared__ double sh[EM_THREADS];
+  const uint64_t per = (nb + EM_THREADS - 1) / EM_THREADS;
+  const uint64_t b0 = (uint64_t)threadIdx.x * per;
+  double sum = 0.0;
+  for (uint64_t b = b0; b < b0 + per && b < nb; ++b) sum += partial[b];
+  double total;
+  double run = em_block_exclusive(sum, sh, &total);
+  for (uint64_t b = b0; b < b0 + per && b < nb; ++b) {
+    const double v = partial[b];
+    partial[b] = run;
+    run += v;
+  }
+}
+
+__global__ void __launch_bounds__(EM_THREADS)
+k_em_cdf(const float* rho, const float* B, double fac, uint64_t ncell, const double* offsets,
+         double* cdf) {
+  __shared__ double sh[EM_THREADS];
+  const uint64_t first = (uint64_t)blockIdx.x * EM_CHUNK + (uint64_t)threadIdx.x * EM_PER;
+  double total;
+  double run = offsets[blockIdx.x] + em_block_exclusive(em_thread_sum(rho, B, fac, first, ncell), sh, &total);
+  for (int k = 0; k < EM_PER; ++k) {
+    const uint64_t c = first + k;
+    if (c < ncell) {
+      run += fac * (double)rho[c] * (double)B[c];
+      cdf[c] = run;
+    }
+  }
+}
+
+// guide[k] = the first cell whose running sum exceeds L k / ncell
+// (k < ncell); guide[ncell] = the last cell
+__global__ void k_em_guide(const double* cdf, uint64_t ncell, uint32_t* guide) {
+  const uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > ncell) return;
+  if (k == ncell) { guide[k] = (uint32_t)(ncell - 1); return; }
+  const double T = cdf[ncell - 1] * ((double)k / (double)ncell);
+  uint64_t lo = 0, hi = ncell - 1;
+  while (lo < hi) {
+    const uint64_t mid = lo + ((hi - lo) >> 1);
+    if (T < cdf[mid]) hi = mid; else lo = mid + 1;
+  }
+  guide[k] = (uint32_t)lo;
+}
+
+uint64_t emission_blocks(uint64_t ncell) { return (ncell + EM_CHUNK - 1) / EM_CHUNK; }
+
+hipError_t launch_emission_table(const float* rho, const float* B, double fac, uint64_t ncell,
+                                 double* partial, double* cdf, uint32_t* guide, hipStream_t s) {
+  const uint64_t nb = emission_blocks(ncell);
+  hipLaunchKernelGGL(k_em_partial, dim3((unsigned)nb), dim3(EM_THREADS), 0, s, rho, B, fac, ncell, partial);
+  hipLaunchKernelGGL(k_em_offsets, dim3(1), dim3(EM_THREADS), 0, s, partial, nb);
+  hipLaunchKernelGGL(k_em_cdf, dim3((unsigned)nb), dim3(EM_THREADS), 0, s, rho, B, fac, ncell,
+                     (const double*)partial, cdf);
+  hipLaunchKernelGGL(k_em_guide, dim3((unsigned)((ncell + 1 + 255) / 256)), dim3(256), 0, s,
+                     (const double*)cdf, ncell, guide);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

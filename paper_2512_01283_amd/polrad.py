@@ -98,6 +98,7 @@ _SIGS = {
     "kp_set_grid_device": ([_P, C.POINTER(kp_grid), _P, _P], C.c_int),
     "kp_set_dust": ([_P, C.c_int32, C.POINTER(kp_dust)], C.c_int),
     "kp_set_source": ([_P, C.POINTER(kp_source)], C.c_int),
+    "kp_set_emission": ([_P, C.c_int32, _P], C.c_int),
     "kp_set_views": ([_P, C.c_int32, C.POINTER(kp_view)], C.c_int),
     "kp_run": ([_P, C.POINTER(C.c_uint64), C.POINTER(kp_opts), _P], C.c_int),
     "kp_run_static": ([_P, C.POINTER(C.c_uint64), C.POINTER(kp_opts), _P, C.c_size_t, _P], C.c_int),
@@ -195,6 +196,14 @@ def kp_set_source(ctx, src) -> None:
     s = kp_source(int(src.get("kind", 0)), (C.c_double * 3)(*src["pos"]),
                   (C.c_double * 3)(*src.get("dir", (0.0, 0.0, 1.0))), float(src["lum"]))
     _check(ctx, _lib.kp_set_source(ctx, C.byref(s)))
+
+
+def kp_set_emission(ctx, B: np.ndarray) -> None:
+    """B: float32 [n_lambda, ncell] source function of the dust's thermal emission."""
+    B = np.ascontiguousarray(B, dtype=np.float32)
+    if B.ndim == 1:
+        B = B[None]
+    _check(ctx, _lib.kp_set_emission(ctx, B.shape[0], B.ctypes.data_as(_P)))
 
 
 def kp_set_views(ctx, views) -> None:
@@ -313,6 +322,8 @@ class Context:
             kp_set_grid_device(self.h, cfg["grid"], rho, bh)
         else:
             kp_set_grid(self.h, cfg["grid"], cfg["rho"], cfg.get("bhat"))
+        if cfg.get("emission") is not None:
+            kp_set_emission(self.h, cfg["emission"])
         kp_set_dust(self.h, cfg["dust"])
         kp_set_source(self.h, cfg["source"])
         kp_set_views(self.h, cfg["views"])

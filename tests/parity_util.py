@@ -63,18 +63,22 @@ def compare_traces(g, o, tol, min_match=1.0, label="", tau_coef=0.0, frac_within
 
 def oracle_batches(cfg, nb=8, lam=0, nthreads=0):
     """Oracle step 1 + 2 split into nb packet batches of one wavelength (same
-    packet streams and weights as the whole run): returns (image sum, per-batch
-    images)."""
+    packet streams and weights as the whole run): returns (image of the whole
+    run, per-batch images of the scattered light).  Step 2 is linear in the
+    scattering source, so the whole run's scattered light is the sum of the
+    batches'; the dust's direct thermal emission (source kind 2) is
+    deterministic and added once."""
     from oracle import oracle as O
     N = int(cfg["packets"][lam])
     edges = np.linspace(0, N, nb + 1).astype(np.int64)
+    direct = O.image(cfg, None, lam=lam) if int(cfg["source"].get("kind", 0)) == 2 else 0.0
     imgs = []
     for b in range(nb):
         S, _, _ = O.transport(cfg, lam=lam, p_begin=int(edges[b]), p_end=int(edges[b + 1]),
                               n_total=N, nthreads=nthreads)
-        imgs.append(O.image(cfg, S, lam=lam))
+        imgs.append(O.image(cfg, S, lam=lam) - direct)
     imgs = np.array(imgs)
-    return imgs.sum(0), imgs
+    return imgs.sum(0) + direct, imgs
 
 
 def compare_images_stat(img_g, img_o, batches, k_sigma=3.0, rel_floor=1e-9, label="",
