@@ -102,8 +102,8 @@ struct ImageArgs {
 // Tally layout [lambda][cell][stride] FP64: 6 reals (stride 8, one 64-B block
 // per cell) when every wavelength has spherical grains, else 9 (stride 16).
 // With stride 16 the slot after the coherency holds the cell's density and
-// the next three its alignment direction (read by the transport step from
-// the same line its atomics update).
+// the next four the unit quaternion of its grain frame (read by the
+// transport step from the same line its atomics update).
 inline int tally_components(bool sphere) { return sphere ? 6 : 9; }
 inline int tally_stride(bool sphere) { return sphere ? 8 : 16; }
 

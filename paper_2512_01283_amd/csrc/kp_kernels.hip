@@ -268,11 +268,12 @@ __device__ __forceinline__ void coherency(const V3<R>& n, R JI, R JQ, R JU, R JV
 // antisymmetric (V) part of the coherency is identically zero.
 // Per-cell tally block of TS doubles (one 64- or 128-byte aligned block):
 // slots [0, NC) the coherency sums.  For non-spherical grains slot NC holds
-// the cell's density and slots NC+1..NC+3 its alignment direction: the step
-// that enters a cell reads them from the block whose coherency it adds to
-// when it leaves, one 128-byte line instead of four (density and three
-// direction planes, 256 MB at 256^3, too large to stay in the Infinity
-// Cache).  Spherical grains read the density from the compact FP32 array
+// the cell's density and slots NC+1..NC+4 the unit quaternion (w, x, y, z) of
+// its grain frame, formed once per run from the alignment direction (eq.
+// grain-quaternion) instead of at every step and scattering: the step that
+// enters a cell reads them from the block whose coherency it adds to when it
+// leaves, one 128-byte line instead of four (density and three direction
+// planes, 256 MB at 256^3, too large to stay in the Infinity Cache).  Spherical grains read the density from the compact FP32 array
 // (64 MB at 256^3), which stays cache-resident; there the density load is
 // the step's critical-path latency and the tally line's fetch is better
 // left to the atomics, off that path.
@@ -280,14 +281,21 @@ template <bool SPHERE> struct TallyShape {
   static constexpr int NC = SPHERE ? 6 : 9;
   static constexpr int TS = SPHERE ? 8 : 16;
   static constexpr int RHO = NC;
-  static constexpr bool HAS_B = !SPHERE;  // density and direction in slots NC..NC+3
+  static constexpr bool HAS_B = !SPHERE;  // density and grain quaternion in slots NC..NC+4
 };
 
+// The grain-frame quaternion of a cell: from its tally block, or formed from
+// the alignment direction when the block does not hold it.
 template <bool ALIGNED, bool SPHERE>
-__device__ __forceinline__ V3<double> cell_bdir(const TransportArgs& a, const double* blk, uint64_t c) {
+__device__ __forceinline__ Quat<double> cell_quat(const TransportArgs& a, const double* blk, uint64_t c) {
   using TSh = TallyShape<SPHERE>;
-  if (TSh::HAS_B) return V3<double>{blk[TSh::RHO + 1], blk[TSh::RHO + 2], blk[TSh::RHO + 3]};
-  return V3<double>{(double)a.bx[c], (double)a.by[c], (double)a.bz[c]};
+  if (TSh::HAS_B) return Quat<double>{blk[TSh::RHO + 1], blk[TSh::RHO + 2], blk[TSh::RHO + 3], blk[TSh::RHO + 4]};
+  return grain_quat(V3<double>{(double)a.bx[c], (double)a.by[c], (double)a.bz[c]});
+}
+
+template <typename R>
+__device__ __forceinline__ Quat<R> quat_cast(const Quat<double>& q) {
+  return Quat<R>{(R)q.w, (R)q.x, (R)q.y, (R)q.z};
 }
 
 // Tally flush, wave-cooperative and deferred.  A lane that leaves a cell
@@ -360,7 +368,7 @@ __device__ __forceinline__ void wave_drain(double* tally, double* sv, long long*
 // u * bound <= [P s]_I, output rescaled to the scattered power, then carried
 // back to the lab frame.  Returns false on a numerical failure.
 template <typename R, bool ALIGNED, bool SPHERE>
-__device__ bool scatter(Packet<R>& p, const Quat<R>& q, const V3<double>& bdir,
+__device__ bool scatter(Packet<R>& p, const Quat<R>& q, const Quat<double>& qd,
                         const DustDev& D, uint64_t seed) {
   const V3<R> n{(R)p.nx, (R)p.ny, (R)p.nz};
   V3<R> ng = n;
@@ -372,7 +380,7 @@ __device__ bool scatter(Packet<R>& p, const Quat<R>& q, const V3<double>& bdir,
     // are small differences of order-one terms, which FP32 resolves only to
     // ~1e-7 absolute, i.e. to a basis angle error of ~1e-7 / sin(theta').
     const V3<double> nd{p.nx, p.ny, p.nz};
-    const V3<double> ngd = to_grain(grain_quat(bdir), nd);
+    const V3<double> ngd = to_grain(qd, nd);
     double cpd, spd, std_;
     azimuth(ngd, cpd, spd, std_);
     ng = V3<R>{(R)ngd.x, (R)ngd.y, (R)ngd.z};
@@ -455,7 +463,7 @@ __device__ bool scatter(Packet<R>& p, const Quat<R>& q, const V3<double>& bdir,
   V3<double> md = mgd;
   R cm = (R)1, sm = (R)0;
   if (ALIGNED) {
-    md = from_grain(grain_quat(bdir), mgd);
+    md = from_grain(qd, mgd);
     eta2(q, V3<R>{(R)md.x, (R)md.y, (R)md.z}, V3<R>{(R)mgd.x, (R)mgd.y, (R)mgd.z}, cm, sm);
   }
   p.nx = md.x; p.ny = md.y; p.nz = md.z;
@@ -508,10 +516,10 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
   const R rho = (R)rhod, kb = (R)kbd, tl = (R)tld;
   p.steps++;
   Quat<R> q{(R)1, (R)0, (R)0, (R)0};
-  V3<double> bdir{0.0, 0.0, 1.0};
+  Quat<double> qd{1.0, 0.0, 0.0, 0.0};
   if (ALIGNED && rho > (R)0) {
-    bdir = cell_bdir<ALIGNED, SPHERE>(a, blk, c);
-    q = grain_quat(V3<R>{(R)bdir.x, (R)bdir.y, (R)bdir.z});
+    qd = cell_quat<ALIGNED, SPHERE>(a, blk, c);
+    q = quat_cast<R>(qd);
   }
   if (rho > (R)0 && tl > (R)0) {
     const V3<R> n{(R)p.nx, (R)p.ny, (R)p.nz};
@@ -531,7 +539,7 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
       // FP64; the exponentials and the Stokes arithmetic run in R.
       const V3<double> nd{p.nx, p.ny, p.nz};
       V3<double> ngd = nd;
-      if (ALIGNED) ngd = to_grain(grain_quat(bdir), nd);
+      if (ALIGNED) ngd = to_grain(qd, nd);
       R c2 = (R)1, s2 = (R)0;
       if (ALIGNED) eta2(q, n, V3<R>{(R)ngd.x, (R)ngd.y, (R)ngd.z}, c2, s2);
       double a1, a2, a3;
@@ -628,13 +636,13 @@ __device__ uint32_t scatter_step(Packet<R>& p, const TransportArgs& a) {
   const uint64_t c = (uint64_t)p.ci + (uint64_t)a.nx * ((uint64_t)p.cj + (uint64_t)a.ny * p.ck);
   const DustDev& D = a.dust[p.lam];
   Quat<R> q{(R)1, (R)0, (R)0, (R)0};
-  V3<double> bdir{0.0, 0.0, 1.0};
+  Quat<double> qd{1.0, 0.0, 0.0, 0.0};
   if (ALIGNED) {
     const double* blk = a.tally + ((uint64_t)p.lam * a.ncell + c) * TallyShape<SPHERE>::TS;
-    bdir = cell_bdir<ALIGNED, SPHERE>(a, blk, c);
-    q = grain_quat(V3<R>{(R)bdir.x, (R)bdir.y, (R)bdir.z});
+    qd = cell_quat<ALIGNED, SPHERE>(a, blk, c);
+    q = quat_cast<R>(qd);
   }
-  if (!scatter<R, ALIGNED, SPHERE>(p, q, bdir, D, a.seed)) return END_NUMERIC;
+  if (!scatter<R, ALIGNED, SPHERE>(p, q, qd, D, a.seed)) return END_NUMERIC;
   p.events++;
   p.hash = hash_event(p.hash, EV_SCATTER, c);
   p.tau = -log((double)next_uniform(p, a.seed));
@@ -1083,9 +1091,9 @@ __global__ void k_fill_zero(uint64_t* p, uint64_t nwords, unsigned char* tail, i
 }
 
 // Tally blocks before a transport run: coherency slots zero and, with co_b
-// (non-spherical grains), the density in slot nc and the alignment direction
-// in slots nc+1..nc+3, for every (wavelength, cell); the rest of each block
-// zero.
+// (non-spherical grains), the density in slot nc and the grain-frame
+// quaternion of the alignment direction (identity without one) in slots
+// nc+1..nc+4, for every (wavelength, cell); the rest of each block zero.
 __global__ void k_tally_init(double* tally, const float* rho, const float* bx, const float* by,
                              const float* bz, uint64_t ncell, int n_lambda, int ts, int nc, int co_b) {
   const uint64_t n = (uint64_t)n_lambda * ncell;
@@ -1096,9 +1104,12 @@ __global__ void k_tally_init(double* tally, const float* rho, const float* bx, c
     for (int k = 0; k < ts; ++k) b[k] = 0.0;
     if (co_b) {
       b[nc] = (double)rho[c];
-      b[nc + 1] = bx ? (double)bx[c] : 0.0;
-      b[nc + 2] = by ? (double)by[c] : 0.0;
-      b[nc + 3] = bz ? (double)bz[c] : 1.0;
+      Quat<double> q{1.0, 0.0, 0.0, 0.0};
+      if (bx) q = grain_quat(V3<double>{(double)bx[c], (double)by[c], (double)bz[c]});
+      b[nc + 1] = q.w;
+      b[nc + 2] = q.x;
+      b[nc + 3] = q.y;
+      b[nc + 4] = q.z;
     }
   }
 }
