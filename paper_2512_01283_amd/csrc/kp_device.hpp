@@ -142,19 +142,24 @@ __device__ __forceinline__ V3<R> from_grain(const Quat<R>& q, const V3<R>& v) {
 // direction n (grain image ng): eta is the signed angle from the lab phi_hat
 // carried into the grain frame to the natural phi_hat' of ng, positive about
 // ng.  Stokes in the grain basis: Q' = c2 Q + s2 U, U' = -s2 Q + c2 U.
+// phi_hat of a direction times sin(theta) (a positive factor), and phi_hat
+// = (0, 1, 0) at the pole
+template <typename R>
+__device__ __forceinline__ V3<R> phi_scaled(const V3<R>& n) {
+  const R r2 = n.x * n.x + n.y * n.y;
+  return r2 <= (R)KP_POLE2 ? V3<R>{(R)0, (R)1, (R)0} : V3<R>{-n.y, n.x, (R)0};
+}
+
 template <typename R>
 __device__ __forceinline__ void eta2(const Quat<R>& q, const V3<R>& n, const V3<R>& ng,
                                      R& c2, R& s2) {
-  R cp, sp, st;
-  azimuth(n, cp, sp, st);
-  V3<R> phg = to_grain(q, V3<R>{-sp, cp, (R)0});
-  R cpg, spg, stg;
-  azimuth(ng, cpg, spg, stg);
-  V3<R> php{-spg, cpg, (R)0};
-  R c = dot(phg, php);
-  R s = dot(ng, cross(phg, php));
-  R r = c * c + s * s;
-  R ir = (R)1 / r;
+  // cos and sin of eta up to one common positive factor (the two phi_hat
+  // vectors are taken unnormalised), which cancels in cos 2 eta and sin 2 eta
+  const V3<R> phg = to_grain(q, phi_scaled(n));
+  const V3<R> php = phi_scaled(ng);
+  const R c = dot(phg, php);
+  const R s = dot(ng, cross(phg, php));
+  const R ir = (R)1 / (c * c + s * s);
   c2 = (c * c - s * s) * ir;
   s2 = (R)2 * c * s * ir;
 }

@@ -243,19 +243,31 @@ __device__ bool init_packet(Packet<R>& p, uint64_t g, const TransportArgs& a) {
 // e1 = theta_hat(n), e2 = phi_hat(n), times the weight w.  Output order: real
 // xx yy zz xy xz yz, imaginary yz zx xy (the antisymmetric part equals
 // -V/2 [n]_x in this basis).
+// With e1 = (nz cos p, nz sin p, -sin t), e2 = (-sin p, cos p, 0) every
+// product of two basis components is written with cos^2 p, sin^2 p,
+// cos p sin p (from n by one reciprocal of nx^2 + ny^2) and sin t cos p = nx,
+// sin t sin p = ny: no square root per step.  At the pole (phi = 0) cos p = 1
+// and sin t = sqrt(nx^2 + ny^2).
 template <typename R, int NC>
 __device__ __forceinline__ void coherency(const V3<R>& n, R JI, R JQ, R JU, R JV, R w,
                                           R out[NC]) {
-  V3<R> e1, e2;
-  basis(n, e1, e2);
+  const R r2 = n.x * n.x + n.y * n.y;
+  R px, py, cc, ss, cs;  // sin t cos p, sin t sin p, cos^2 p, sin^2 p, cos p sin p
+  if (r2 <= (R)KP_POLE2) {
+    px = k_sqrt(r2); py = (R)0; cc = (R)1; ss = (R)0; cs = (R)0;
+  } else {
+    const R ir = (R)1 / r2;
+    px = n.x; py = n.y; cc = n.x * n.x * ir; ss = n.y * n.y * ir; cs = n.x * n.y * ir;
+  }
   R a = (R)0.5 * (JI + JQ) * w, b = (R)0.5 * (JI - JQ) * w, u = (R)0.5 * JU * w;
   R v = (R)-0.5 * JV * w;
-  out[0] = a * e1.x * e1.x + b * e2.x * e2.x + (R)2 * u * e1.x * e2.x;
-  out[1] = a * e1.y * e1.y + b * e2.y * e2.y + (R)2 * u * e1.y * e2.y;
-  out[2] = a * e1.z * e1.z;
-  out[3] = a * e1.x * e1.y + b * e2.x * e2.y + u * (e1.x * e2.y + e2.x * e1.y);
-  out[4] = a * e1.x * e1.z + u * (e2.x * e1.z);
-  out[5] = a * e1.y * e1.z + u * (e2.y * e1.z);
+  const R an2 = a * n.z * n.z, un = u * n.z;
+  out[0] = an2 * cc + b * ss - (R)2 * un * cs;
+  out[1] = an2 * ss + b * cc + (R)2 * un * cs;
+  out[2] = a * r2;
+  out[3] = (an2 - b) * cs + un * (cc - ss);
+  out[4] = -a * n.z * px + u * py;
+  out[5] = -a * n.z * py - u * px;
   if (NC > 6) {
     out[NC > 6 ? 6 : 0] = v * n.x;
     out[NC > 7 ? 7 : 0] = v * n.y;
