@@ -33,7 +33,7 @@ def build(force: bool = True) -> str:
 class Grid(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double),
-                ("dx", C.c_double)]
+                ("dx", C.c_double), ("boundary", C.c_int32)]
 
 
 class Dust(C.Structure):
@@ -100,6 +100,10 @@ def lib():
                                     C.POINTER(Source), C.c_int32, C.POINTER(View),
                                     C.c_uint64, C.c_uint64, C.c_uint64, C.POINTER(Opts),
                                     dp, C.c_void_p, C.POINTER(Stats)]
+        L.kpo_transport_peel.argtypes = [C.POINTER(Grid), fp, fp, C.POINTER(Dust), C.c_int32,
+                                         C.POINTER(Source), C.c_int32, C.POINTER(View),
+                                         C.c_uint64, C.c_uint64, C.c_uint64, C.POINTER(Opts),
+                                         dp, dp, C.POINTER(Stats)]
         L.kpo_trace_packets.argtypes = [C.POINTER(Grid), fp, fp, C.POINTER(Dust), C.c_int32,
                                         C.POINTER(Source), u64p, C.c_uint64, C.c_uint64,
                                         C.POINTER(Opts), C.c_void_p]
@@ -150,7 +154,7 @@ def _f(a):
 
 def make_grid(g) -> Grid:
     return Grid(int(g["nx"]), int(g["ny"]), int(g["nz"]), float(g["x0"]),
-                float(g["y0"]), float(g["z0"]), float(g["dx"]))
+                float(g["y0"]), float(g["z0"]), float(g["dx"]), int(g.get("boundary", 0)))
 
 
 def make_dust(d) -> Dust:
@@ -218,6 +222,35 @@ def transport(cfg, lam=0, p_begin=0, p_end=None, n_total=None, tally=True,
     if rc != 0:
         raise ValueError(f"kpo_transport rejected its inputs ({rc})")
     return S, tr, stats_dict(st)
+
+
+def transport_peel(cfg, lam=0, p_begin=0, p_end=None, n_total=None, tally=False, nthreads=0):
+    """Step 1 for one wavelength with peel-off imaging: returns (peel-off
+    images [view][4][npy][npx], S or None, stats).  Open boundaries."""
+    L = lib()
+    g = make_grid(cfg["grid"])
+    ncell = g.nx * g.ny * g.nz
+    rho, rho_p = _f(cfg["rho"])
+    bh, bh_p = _f(cfg.get("bhat"))
+    dust = make_dust(cfg["dust"][lam])
+    B = emission_of(cfg, lam)
+    src = make_source(cfg["source"], B)
+    views = make_views(cfg["views"])
+    nv = len(cfg["views"])
+    npx, npy = cfg["views"][0]["npx"], cfg["views"][0]["npy"]
+    n_total = int(cfg["packets"][lam]) if n_total is None else int(n_total)
+    p_end = n_total if p_end is None else int(p_end)
+    S = np.zeros((ncell, nv, 4)) if tally else None
+    Sp = S.ctypes.data_as(C.POINTER(C.c_double)) if tally else None
+    peel = np.zeros((nv, 4, npy, npx))
+    st = Stats()
+    o = make_opts(cfg["opts"], nthreads)
+    rc = L.kpo_transport_peel(C.byref(g), rho_p, bh_p, C.byref(dust), lam, C.byref(src), nv,
+                              views, p_begin, p_end, n_total, C.byref(o), Sp,
+                              peel.ctypes.data_as(C.POINTER(C.c_double)), C.byref(st))
+    if rc != 0:
+        raise ValueError(f"kpo_transport_peel rejected its inputs ({rc})")
+    return peel, S, stats_dict(st)
 
 
 def trace_packets(cfg, ids, lam=0, n_total=None, nthreads=0):

@@ -28,7 +28,12 @@
  *  R6 rejection sampling (Sec. 3 intro): proposals uniform on the sphere in
  *     the grain frame, bound 3/(8 pi N_P) max(|a_perp|^2,|a_par|^2) I.
  *  R7 weight after scattering: I' = tr(alpha C alpha^dagger)/N_P.
- *  R8 termination: open boundaries, Russian roulette, event cap.
+ *  R8 termination: escape through an open face, Russian roulette, event
+ *     cap, and a cap of KPO_MAX_STEPS cell steps.
+ *  R14 boundaries (Sec. 3.1 uses periodic ones): each axis open or periodic;
+ *     a packet crossing a periodic face re-enters through the opposite one,
+ *     and a camera ray runs through the periodic copies of the grid from the
+ *     open face where it enters to the open face where it leaves.
  *  R9 orthographic camera, image x along phi_hat, y along -theta_hat.
  *  E1 thermal emission of the dust (Sec. 2.2, the alpha_abs B term of eq.
  *     polarized-rt): the absorption matrix is kappa_abs/kappa_ext times the
@@ -387,6 +392,18 @@ typedef struct {
   double f[3];
 } gpos_t;
 
+static int periodic(const kpo_grid *g, int a) { return (g->boundary >> a) & 1; }
+
+/* after crossing a face along `axis`: wrap a periodic axis, or report that
+ * the packet left the grid through an open face */
+static int leave_or_wrap(const kpo_grid *g, gpos_t *p, int axis) {
+  int64_t n = axis == 0 ? g->nx : (axis == 1 ? g->ny : g->nz);
+  if (p->i[axis] >= 0 && p->i[axis] < n) return 0;
+  if (!periodic(g, axis)) return 1;
+  p->i[axis] = p->i[axis] < 0 ? n - 1 : 0;
+  return 0;
+}
+
 static int inside(const kpo_grid *g, const gpos_t *p) {
   return p->i[0] >= 0 && p->i[0] < g->nx && p->i[1] >= 0 && p->i[1] < g->ny &&
          p->i[2] >= 0 && p->i[2] < g->nz;
@@ -518,6 +535,7 @@ typedef struct {
   double (*vdir)[3];     /* camera directions */
   double *S;             /* [cell][view][4] or NULL */
   const double *cdf;     /* thermal emission: running sum of cell luminosities */
+  double *peel;          /* peel-off images [view][4][npy][npx] or NULL */
 } run_t;
 
 /* Running sum over cells (flat order) of the thermal luminosity
@@ -606,6 +624,59 @@ static void atomic_add(double *p, double v) {
   *p += v;
 }
 
+/* Peel-off imaging at a scattering event (the Monte Carlo imaging Sec. 2.3
+ * compares two-step imaging with): for every camera, the Stokes vector the
+ * event scatters toward it per unit solid angle, P(Omega_v; n) s in the
+ * camera basis (the normalised Mueller matrix of reading R5), carried to the
+ * grid's edge through the Appendix A extinction of every cell on the way
+ * (no source), and added to the pixel the event projects to, divided by the
+ * pixel's area (reading R9 for the camera).  Open boundaries. */
+static void peel_off(const run_t *R, const gpos_t *at, const double q_ev[4], const double n[3],
+                     const double s[4]) {
+  const kpo_grid *g = R->g;
+  const kpo_dust *d = R->d;
+  int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
+  double kext = d->kappa_sca + d->kappa_abs;
+  double X[3] = {g->x0 + (at->i[0] + at->f[0]) * g->dx, g->y0 + (at->i[1] + at->f[1]) * g->dx,
+                 g->z0 + (at->i[2] + at->f[2]) * g->dx};
+  int32_t npx = R->views[0].npx, npy = R->views[0].npy;
+  for (int v = 0; v < R->n_views; ++v) {
+    const double *om = R->vdir[v];
+    double th[3], ph[3];
+    kpo_basis(om, th, ph);
+    double W = R->views[v].half_width;
+    double xi = dot3(X, ph), yi = -dot3(X, th);
+    double fx = (xi + W) / (2.0 * W / npx), fy = (yi + W) / (2.0 * W / npy);
+    if (!(fx >= 0.0 && fx < npx && fy >= 0.0 && fy < npy)) continue;
+    int ix = (int)fx, iy = (int)fy;
+    double st[4];
+    kpo_mueller_lab(d, q_ev, om, n, s, st);
+    gpos_t p = *at;
+    while (1) {
+      int axis;
+      double tf = face_dist(&p, om, &axis);
+      if (axis < 0) break;
+      int64_t c = flat(g, &p);
+      double r = (double)R->rho[c];
+      if (r > 0.0 && tf > 0.0) {
+        double q[4], og[3], al[3], sg[4], out[4], zero[4] = {0, 0, 0, 0};
+        cell_quat(R->bhat, ncell, c, q);
+        kpo_to_grain(q, om, og);
+        kpo_alphas(d, og[2], al);
+        double eta = eta_pair(q, om, og);
+        kpo_rotate_stokes(eta, st, sg);
+        kpo_appA(al[0], al[1], al[2], r * kext * tf * g->dx, zero, sg, out);
+        kpo_rotate_stokes(-eta, out, st);
+      }
+      cross_face(&p, om, tf, axis);
+      if (!inside(g, &p)) break;
+    }
+    double area = (2.0 * W / npx) * (2.0 * W / npy);
+    for (int k = 0; k < 4; ++k)
+      atomic_add(R->peel + (((int64_t)v * 4 + k) * npy + iy) * npx + ix, st[k] / area);
+  }
+}
+
 /* One packet from emission to termination (Sec. 2.2-2.3). */
 static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *st) {
   const kpo_grid *g = R->g;
@@ -633,6 +704,10 @@ static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *s
     w0 = R->src->lum / (double)R->n_total;
     s[0] = w0; s[1] = s[2] = s[3] = 0.0;
     locate(g, R->src->pos, n, &p);
+    for (int a = 0; a < 3; ++a) {
+      int64_t na = a == 0 ? g->nx : (a == 1 ? g->ny : g->nz);
+      if (periodic(g, a)) p.i[a] = ((p.i[a] % na) + na) % na;
+    }
   }
   double tau = -log(draw(&rng));
   st->e_emitted += s[0];
@@ -649,7 +724,7 @@ static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *s
   while (end == KPO_END_NONE) {
     int64_t c = flat(g, &p);
     last = c;
-    if (events >= R->o->max_events) {
+    if (events >= R->o->max_events || steps >= KPO_MAX_STEPS) {
       h = hash_event(h, KPO_END_BUDGET, c);
       end = KPO_END_BUDGET;
       st->budget++;
@@ -696,6 +771,7 @@ static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *s
 
     if (scat) {
       move_inside(&p, n, len / g->dx);
+      if (R->peel) peel_off(R, &p, q, n, s);
       double m[3], i_in = s[0];
       if (scatter_event(d, q, n, s, &rng, &st->trials, m, s) != 0) {
         end = KPO_END_NUMERIC;
@@ -710,7 +786,7 @@ static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *s
       tau = -log(draw(&rng));
     } else {
       cross_face(&p, n, tf, axis);
-      if (!inside(g, &p)) {
+      if (leave_or_wrap(g, &p, axis)) {
         h = hash_event(h, KPO_END_ESCAPE, c);
         end = KPO_END_ESCAPE;
         st->escaped++;
@@ -775,14 +851,15 @@ static int check_inputs(const kpo_grid *g, const kpo_dust *d, const kpo_source *
   return 0;
 }
 
-int kpo_transport(const kpo_grid *g, const float *rho, const float *bhat,
-                  const kpo_dust *d, int32_t lam, const kpo_source *src,
-                  int32_t n_views, const kpo_view *views,
-                  uint64_t p_begin, uint64_t p_end, uint64_t n_total,
-                  const kpo_opts *o, double *S, kpo_trace *traces,
-                  kpo_stats *stats) {
+static int transport_impl(const kpo_grid *g, const float *rho, const float *bhat,
+                          const kpo_dust *d, int32_t lam, const kpo_source *src,
+                          int32_t n_views, const kpo_view *views,
+                          uint64_t p_begin, uint64_t p_end, uint64_t n_total,
+                          const kpo_opts *o, double *S, kpo_trace *traces, double *peel,
+                          kpo_stats *stats) {
   if (check_inputs(g, d, src) || !o || n_total == 0 || p_end < p_begin) return -1;
-  if (S && (n_views <= 0 || !views)) return -1;
+  if ((S || peel) && (n_views <= 0 || !views)) return -1;
+  if (peel && g->boundary != 0) return -1;
   double *cdf = NULL;
   if (src->kind == 2 && !(cdf = emission_cdf(g, rho, d, src->B))) return -1;
   double (*vdir)[3] = NULL;
@@ -790,7 +867,7 @@ int kpo_transport(const kpo_grid *g, const float *rho, const float *bhat,
     vdir = malloc(sizeof(double[3]) * (size_t)n_views);
     for (int v = 0; v < n_views; ++v) view_dir(&views[v], vdir[v]);
   }
-  run_t R = {g, rho, bhat, d, src, o, lam, n_total, n_views, views, vdir, S, cdf};
+  run_t R = {g, rho, bhat, d, src, o, lam, n_total, n_views, views, vdir, S, cdf, peel};
   kpo_stats total;
   memset(&total, 0, sizeof total);
   int nth = o->nthreads;
@@ -810,6 +887,26 @@ int kpo_transport(const kpo_grid *g, const float *rho, const float *bhat,
   return 0;
 }
 
+int kpo_transport(const kpo_grid *g, const float *rho, const float *bhat,
+                  const kpo_dust *d, int32_t lam, const kpo_source *src,
+                  int32_t n_views, const kpo_view *views,
+                  uint64_t p_begin, uint64_t p_end, uint64_t n_total,
+                  const kpo_opts *o, double *S, kpo_trace *traces,
+                  kpo_stats *stats) {
+  return transport_impl(g, rho, bhat, d, lam, src, n_views, views, p_begin, p_end, n_total, o, S,
+                        traces, NULL, stats);
+}
+
+int kpo_transport_peel(const kpo_grid *g, const float *rho, const float *bhat,
+                       const kpo_dust *d, int32_t lam, const kpo_source *src,
+                       int32_t n_views, const kpo_view *views,
+                       uint64_t p_begin, uint64_t p_end, uint64_t n_total,
+                       const kpo_opts *o, double *S, double *peel, kpo_stats *stats) {
+  if (!peel) return -1;
+  return transport_impl(g, rho, bhat, d, lam, src, n_views, views, p_begin, p_end, n_total, o, S,
+                        NULL, peel, stats);
+}
+
 int kpo_trace_packets(const kpo_grid *g, const float *rho, const float *bhat,
                       const kpo_dust *d, int32_t lam, const kpo_source *src,
                       const uint64_t *ids, uint64_t n_ids, uint64_t n_total,
@@ -817,7 +914,7 @@ int kpo_trace_packets(const kpo_grid *g, const float *rho, const float *bhat,
   if (check_inputs(g, d, src) || !o || !ids || !traces || n_total == 0) return -1;
   double *cdf = NULL;
   if (src->kind == 2 && !(cdf = emission_cdf(g, rho, d, src->B))) return -1;
-  run_t R = {g, rho, bhat, d, src, o, lam, n_total, 0, NULL, NULL, NULL, cdf};
+  run_t R = {g, rho, bhat, d, src, o, lam, n_total, 0, NULL, NULL, NULL, cdf, NULL};
   int nth = o->nthreads;
 #pragma omp parallel num_threads(nth > 0 ? nth : omp_get_max_threads())
   {
@@ -855,6 +952,18 @@ int kpo_image_thermal(const kpo_grid *g, const float *rho, const float *bhat,
   for (int v = 0; v < n_views; ++v)
     if (views[v].npx != npx || views[v].npy != npy || npx <= 0 || npy <= 0) return -1;
   for (int v = 0; v < n_views; ++v) {
+    double om[3];
+    view_dir(&views[v], om);
+    /* a ray must leave through an open face within KPO_MAX_STEPS cell
+     * lengths (reading R14): its path through the open extent is at most
+     * n_a / |om_a| cells for every open axis a */
+    int64_t nn[3] = {g->nx, g->ny, g->nz};
+    double cells = INFINITY;
+    for (int a = 0; a < 3; ++a)
+      if (!periodic(g, a) && om[a] != 0.0) cells = fmin(cells, (double)nn[a] / fabs(om[a]));
+    if (!(cells <= (double)KPO_MAX_STEPS)) return -1;
+  }
+  for (int v = 0; v < n_views; ++v) {
     double om[3], th[3], ph[3];
     view_dir(&views[v], om);
     kpo_basis(om, th, ph);
@@ -869,6 +978,7 @@ int kpo_image_thermal(const kpo_grid *g, const float *rho, const float *bhat,
         double sn = -INFINITY, sf = INFINITY;
         int miss = 0;
         for (int a = 0; a < 3; ++a) {
+          if (periodic(g, a)) continue;  /* the copies fill the axis */
           if (om[a] != 0.0) {
             double s1 = (lo[a] - P0[a]) / om[a], s2 = (hi[a] - P0[a]) / om[a];
             sn = fmax(sn, fmin(s1, s2));
@@ -885,12 +995,17 @@ int kpo_image_thermal(const kpo_grid *g, const float *rho, const float *bhat,
             double t = (P0[a] + sn * om[a] - lo[a]) / g->dx;
             double fl = floor(t);
             int64_t i = (int64_t)fl;
+            if (periodic(g, a)) {
+              p.i[a] = ((i % nn[a]) + nn[a]) % nn[a];
+              p.f[a] = clamp01(t - fl);
+              continue;
+            }
             if (i < 0) i = 0;
             if (i > nn[a] - 1) i = nn[a] - 1;
             p.i[a] = i;
             p.f[a] = clamp01(t - (double)i);
           }
-          while (inside(g, &p)) {
+          while (1) {
             int axis;
             double tf = face_dist(&p, om, &axis);
             if (axis < 0) break;
@@ -915,6 +1030,7 @@ int kpo_image_thermal(const kpo_grid *g, const float *rho, const float *bhat,
               kpo_rotate_stokes(-eta, out, st);
             }
             cross_face(&p, om, tf, axis);
+            if (leave_or_wrap(g, &p, axis)) break;
           }
         }
         for (int k = 0; k < 4; ++k)

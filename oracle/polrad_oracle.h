@@ -30,7 +30,13 @@ extern "C" {
 typedef struct {
   int32_t nx, ny, nz;
   double x0, y0, z0, dx;        /* lower corner, cubic cell size */
+  int32_t boundary;             /* bit a set: axis a (x, y, z) periodic, else open */
 } kpo_grid;
+
+/* a packet ends as KPO_END_BUDGET after this many cell steps (a packet that
+ * cannot scatter and moves parallel to every open face of a partly periodic
+ * grid would never leave it) */
+#define KPO_MAX_STEPS (1 << 24)
 
 typedef struct {
   double kappa_sca, kappa_abs;  /* orientation-averaged, per unit rho per unit length */
@@ -96,6 +102,18 @@ int kpo_transport(const kpo_grid *g, const float *rho, const float *bhat,
                   uint64_t p_begin, uint64_t p_end, uint64_t n_total,
                   const kpo_opts *o, double *S, kpo_trace *traces,
                   kpo_stats *stats);
+
+/* The same transport, imaging by peel-off (the direct Monte Carlo imaging
+ * that Sec. 2.3 sets two-step imaging against): at every scattering event
+ * the Stokes vector scattered toward each camera, attenuated along the line
+ * of sight to the grid's edge, is added to the pixel the event projects to,
+ * divided by the pixel's area.  peel: [view][4][npy][npx], accumulated.
+ * Open boundaries only; S and traces may be NULL. */
+int kpo_transport_peel(const kpo_grid *g, const float *rho, const float *bhat,
+                       const kpo_dust *d, int32_t lam, const kpo_source *src,
+                       int32_t n_views, const kpo_view *views,
+                       uint64_t p_begin, uint64_t p_end, uint64_t n_total,
+                       const kpo_opts *o, double *S, double *peel, kpo_stats *stats);
 
 /* Same transport for an explicit list of packet ids, traces only. */
 int kpo_trace_packets(const kpo_grid *g, const float *rho, const float *bhat,

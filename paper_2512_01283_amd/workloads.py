@@ -6,7 +6,8 @@ It holds none of the transport or imaging arithmetic, and it is the only
 module that both the HIP path and the CPU oracle consume.
 
 A workload is a plain dict:
-  grid    {nx, ny, nz, x0, y0, z0, dx}  cubic cells, lower corner (x0, y0, z0)
+  grid    {nx, ny, nz, x0, y0, z0, dx[, boundary]}  cubic cells, lower corner
+          (x0, y0, z0); boundary: bit a set = axis a (x, y, z) periodic
   rho     float32[nz*ny*nx]             density, x fastest
   bhat    float32[3, ncell] or None     unit grain-alignment direction per cell
   dust    list (one per wavelength) of {kappa_sca, kappa_abs, a_perp, a_par,
@@ -321,6 +322,34 @@ def dust_cylinder(n=128, packets=10_000_000, tau_axis=1.0, r0=0.25, albedo=0.5, 
                 source=dict(THERMAL_SOURCE), emission=_isothermal(rho),
                 views=[view(0.0, 0.0, npix), view(60.0, 0.0, npix)],
                 packets=[int(packets)], opts=default_opts(seed), precision="f32")
+
+
+def periodic_slab(n=16, n_z=16, tau=1.0, albedo=0.0, packets=100_000, views=((0.0, 0.0), (60.0, 30.0)),
+                  npix=8, seed=9) -> dict:
+    """Isothermal slab of uniform density and optical thickness tau along z,
+    periodic in x and y (an infinite slab), Rayleigh spheres, thermal
+    emission as the only source; face-on and inclined views."""
+    dz = 1.0 / n_z
+    grid = dict(nx=n, ny=n, nz=n_z, x0=-n * dz / 2, y0=-n * dz / 2, z0=0.0, dx=dz, boundary=3)
+    rho = np.ones(n * n * n_z, dtype=np.float32)
+    return dict(name="periodic_slab", grid=grid, rho=rho, bhat=None,
+                dust=[sphere_dust(tau, albedo)], source=dict(THERMAL_SOURCE),
+                emission=_isothermal(rho), views=[view(t, p, npix, half_width=0.75) for t, p in views],
+                packets=[int(packets)], opts=default_opts(seed), precision="f64")
+
+
+def pencil_column(n_z=64, tau=0.02, packets=1_000_000, npix=16, seed=10) -> dict:
+    """A column one cell wide and n_z cells tall of optical depth tau
+    (Rayleigh spheres, albedo 1) with a pencil beam entering at the bottom
+    along +z, seen edge-on from +x: single scattering at exactly 90 degrees
+    toward the camera."""
+    dz = 1.0 / n_z
+    grid = dict(nx=1, ny=1, nz=n_z, x0=-dz / 2, y0=-dz / 2, z0=-0.5, dx=dz)
+    rho = np.ones(n_z, dtype=np.float32)
+    return dict(name="pencil_column", grid=grid, rho=rho, bhat=None, dust=[sphere_dust(tau, 1.0)],
+                source=dict(kind=1, pos=(0.0, 0.0, -0.5), dir=(0.0, 0.0, 1.0), lum=1.0),
+                views=[dict(theta=90.0 * DEG, phi=0.0, npx=1, npy=npix, half_width=0.5)],
+                packets=[int(packets)], opts=dict(default_opts(seed), rr_wmin=0.0), precision="f64")
 
 
 # --------------------------------------------------------------------------
