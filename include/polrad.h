@@ -49,8 +49,16 @@ typedef enum {
 
 typedef struct kp_ctx kp_ctx;
 
-/* Uniform grid of cubic cells [x0 + i dx, x0 + (i+1) dx) x ... ; boundary:
- * 0 = open (packets leaving the box escape).  Other values are rejected. */
+/* Uniform grid of cubic cells [x0 + i dx, x0 + (i+1) dx) x ... (Sec. 2.2).
+ * boundary is a bit mask over the axes x, y, z (bit 0, 1, 2): a clear bit
+ * makes both faces normal to that axis open (a packet crossing one escapes),
+ * a set bit makes the axis periodic (a packet crossing one face re-enters
+ * through the opposite one, and a camera ray runs on through the periodic
+ * copies of the grid), the boundary condition of the Sec. 3.1 test.  0..6;
+ * 7 (no open face) is rejected with KP_ERR_ARG.  With periodic axes a packet
+ * ends after 2^24 cell steps (reported as a cap packet), and step 2 refuses
+ * (KP_ERR_ARG) a camera whose rays would cross more than 2^24 cell lengths
+ * before reaching an open face. */
 typedef struct {
   int32_t nx, ny, nz;
   double x0, y0, z0, dx;
@@ -134,6 +142,18 @@ typedef struct {
  *  scatter_wait    ... or until it has waited this many iterations (1..1024;
  *                  0 = default 16).  Scheduling only: results are identical
  *                  for every setting (each packet keeps its own streams).
+ *  peel_off        1: also form peel-off images (the direct Monte Carlo
+ *                  imaging that Sec. 2.3 sets two-step imaging against): at
+ *                  every scattering event, for every camera, the Stokes
+ *                  vector scattered toward the camera per unit solid angle
+ *                  (from the packet's own incident coherency, as step 2
+ *                  forms its source from the tallied one), attenuated
+ *                  through every cell to the grid's edge with the Appendix A
+ *                  extinction, per unit pixel area, in the pixel the event
+ *                  projects to.  Scattered light only (no direct light of
+ *                  the source or the dust).  Read with kp_get_peel_images.
+ *                  Needs open boundaries (boundary 0) and kp_run or
+ *                  kp_transport (KP_ERR_ARG otherwise).  0 = off.
  * block_size, blocks_per_cu, scatter_batch and scatter_wait are what the
  * autotuner searches. */
 typedef struct {
@@ -149,6 +169,7 @@ typedef struct {
   int32_t strict;
   int32_t scatter_batch;
   int32_t scatter_wait;
+  int32_t peel_off;
 } kp_opts;
 
 /* Counters of the last kp_run/kp_transport (energies in units of lum). */
@@ -249,7 +270,8 @@ kp_status kp_run(kp_ctx *ctx, const uint64_t *packets_per_lambda, const kp_opts 
  * [npy][npx] FP64, n its element count).  Limits: the tally, n_lambda x
  * ncell x 64 B for spherical grains (x 128 B otherwise), must fit 256 MiB
  * (KP_ERR_ARG otherwise, before any launch: use kp_run), and no traces are
- * recorded (trace_packets must be 0).  kp_get_stats then reports this call;
+ * recorded (trace_packets must be 0) and no peel-off images formed
+ * (peel_off must be 0).  kp_get_stats then reports this call;
  * kp_image, kp_get_images and kp_get_tally keep referring to the last
  * kp_run / kp_transport.  Every call on one device uses that device's one
  * array, cleared at the start of each call by kernels: calls that overlap
@@ -283,6 +305,12 @@ kp_status kp_image_source(kp_ctx *ctx, const double *d_S, double *d_out, void *h
  * device array. */
 kp_status kp_get_images(kp_ctx *ctx, double *host_out, size_t n);
 kp_status kp_get_images_device(kp_ctx *ctx, double *d_out, size_t n, void *hip_stream);
+/* Peel-off images of the last step 1 run with opts.peel_off = 1 (the
+ * Monte Carlo imaging Sec. 2.3 compares two-step imaging with; kp_opts
+ * above), same layout and units as kp_get_images: [n_lambda][n_views][4]
+ * [npy][npx] FP64, copied to host memory; n must equal that size
+ * (KP_ERR_ARG otherwise, KP_ERR_STATE if the last step 1 formed none). */
+kp_status kp_get_peel_images(kp_ctx *ctx, double *host_out, size_t n);
 /* Incident-coherency tally [n_lambda][ncell][9] FP64 of the last step 1
  * (the scattering source of Sec. 2.3, eq. scat-disc-sum, before the camera
  * projection: components xx yy zz xy xz yz and the imaginary yz zx xy

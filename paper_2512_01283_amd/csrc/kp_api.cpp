@@ -114,6 +114,10 @@ struct kp_ctx {
   size_t em_partial_n = 0;
   bool em_ready = false;  // tables match the current grid, dust and source function
   std::vector<double> em_L;
+  // peel-off images of the last step 1 run with peel_off
+  double* d_peel = nullptr;
+  size_t peel_n = 0;
+  size_t peel_valid_n = 0;  // 0: the last step 1 formed none
 };
 
 namespace {
@@ -178,7 +182,8 @@ kp_status check_grid(kp_ctx* ctx, const kp_grid* g) {
   if (!(g->dx > 0.0) || !std::isfinite(g->dx)) return fail(ctx, KP_ERR_ARG, "dx must be finite and > 0");
   if (!std::isfinite(g->x0) || !std::isfinite(g->y0) || !std::isfinite(g->z0))
     return fail(ctx, KP_ERR_ARG, "grid origin must be finite");
-  if (g->boundary != 0) return fail(ctx, KP_ERR_ARG, "only open boundaries (0) are supported");
+  if (g->boundary < 0 || g->boundary > 6)
+    return fail(ctx, KP_ERR_ARG, "boundary must be a mask of periodic axes in 0..6 (7 leaves no open face)");
   const double n = (double)g->nx * g->ny * g->nz;
   if (n > 4.0e9) return fail(ctx, KP_ERR_ARG, "grid has more than 4e9 cells");
   return KP_OK;
@@ -253,6 +258,21 @@ kp_status check_ready(kp_ctx* ctx) {
   if (ctx->dust.empty()) return fail(ctx, KP_ERR_STATE, "kp_set_dust has not been called");
   if (!ctx->have_source) return fail(ctx, KP_ERR_STATE, "kp_set_source has not been called");
   if (ctx->views.empty()) return fail(ctx, KP_ERR_STATE, "kp_set_views has not been called");
+  if (ctx->grid.boundary) {
+    // with periodic axes a camera ray ends only at an open face: its path
+    // through the open extent is at most n_a / |om_a| cell lengths for every
+    // open axis a
+    const int n[3] = {ctx->grid.nx, ctx->grid.ny, ctx->grid.nz};
+    for (size_t v = 0; v < ctx->hviews.size(); ++v) {
+      const double om[3] = {ctx->hviews[v].ox, ctx->hviews[v].oy, ctx->hviews[v].oz};
+      double cells = INFINITY;
+      for (int k = 0; k < 3; ++k)
+        if (!((ctx->grid.boundary >> k) & 1) && om[k] != 0.0) cells = std::fmin(cells, n[k] / std::fabs(om[k]));
+      if (!(cells <= (double)KP_MAX_STEPS))
+        return fail(ctx, KP_ERR_ARG, "view %zu: its rays cross more than 2^24 cell lengths of the periodic "
+                    "grid before reaching an open face", v);
+    }
+  }
   if (ctx->src.kind == 2) {
     if (!ctx->have_emission)
       return fail(ctx, KP_ERR_STATE, "thermal emission source: kp_set_emission has not been called for this grid");
@@ -293,6 +313,7 @@ kp_status image_launch(kp_ctx* ctx, bool user_source, const double* d_S, double*
   a.images = d_out;
   a.ncell = ctx->ncell;
   a.em_B = (!user_source && ctx->src.kind == 2) ? ctx->d_em_B : nullptr;
+  a.boundary = ctx->grid.boundary;
   // every wavelength shares the grain model kind of wavelength 0 for the
   // kernel choice; mixed sphere / non-sphere tables use the general kernel
   bool sphere = true;
@@ -367,6 +388,9 @@ kp_status check_run_args(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, 
   if (o->transport_fp64 < 0 || o->transport_fp64 > 2) return fail(ctx, KP_ERR_ARG, "transport_fp64 must be 0, 1 or 2");
   if (o->scatter_batch < 0 || o->scatter_batch > 64) return fail(ctx, KP_ERR_ARG, "scatter_batch must be in 0..64");
   if (o->scatter_wait < 0 || o->scatter_wait > 1024) return fail(ctx, KP_ERR_ARG, "scatter_wait must be in 0..1024");
+  if (o->peel_off != 0 && o->peel_off != 1) return fail(ctx, KP_ERR_ARG, "peel_off must be 0 or 1");
+  if (o->peel_off && ctx->grid.boundary)
+    return fail(ctx, KP_ERR_ARG, "peel-off imaging needs open boundaries (boundary 0)");
   *total_out = total;
   return KP_OK;
 }
@@ -378,6 +402,8 @@ struct RunBuffers {
   StatsDev* stats;
   unsigned long long* counter;   // work counter of the persistent launch
   TraceDev* traces;              // [lambda][trace_packets] or null
+  const ViewDev* views;          // camera table (uploaded by the caller)
+  double* peel;                  // [lambda][view][4][npy][npx] peel-off images, or null
 };
 
 // Step 1 on prepared buffers: tally and counters cleared by kernels, the
@@ -395,6 +421,9 @@ kp_status transport_launch(kp_ctx* ctx, const kp_opts* o, uint64_t total, const 
   KP_HIP(launch_fill_zero(b.stats, sizeof(StatsDev), s), "stats clear");
   KP_HIP(launch_fill_zero(b.counter, sizeof(unsigned long long), s), "counter clear");
   if (trace_need) KP_HIP(launch_fill_zero(b.traces, trace_need * sizeof(TraceDev), s), "trace clear");
+  const int npx = ctx->views[0].npx, npy = ctx->views[0].npy, nv = (int)ctx->views.size();
+  if (b.peel)
+    KP_HIP(launch_fill_zero(b.peel, (size_t)nl * nv * 4 * npx * npy * sizeof(double), s), "peel-off clear");
 
   TransportArgs a{};
   a.rho = ctx->d_rho;
@@ -428,6 +457,14 @@ kp_status transport_launch(kp_ctx* ctx, const kp_opts* o, uint64_t total, const 
     a.em_cdf = ctx->d_em_cdf;
     a.em_guide = ctx->d_em_guide;
   }
+  a.boundary = ctx->grid.boundary;
+  if (b.peel) {
+    a.views = b.views;
+    a.n_views = nv;
+    a.npx = npx;
+    a.npy = npy;
+    a.peel = b.peel;
+  }
 
   const bool sphere = all_sphere;
   const bool aligned = ctx->d_bhat != nullptr;
@@ -437,7 +474,7 @@ kp_status transport_launch(kp_ctx* ctx, const kp_opts* o, uint64_t total, const 
   const int bs = o->block_size ? o->block_size : 256;
   int bpc = o->blocks_per_cu;
   if (bpc == 0) {
-    bpc = transport_max_blocks_per_cu(fp64, aligned, sphere, bs);
+    bpc = transport_max_blocks_per_cu(fp64, aligned, sphere, b.peel != nullptr, bs);
     if (bpc < 1) bpc = 1;
     if (bpc > 8) bpc = 8;
   }
@@ -445,7 +482,8 @@ kp_status transport_launch(kp_ctx* ctx, const kp_opts* o, uint64_t total, const 
   const uint64_t need_blocks = (total + bs - 1) / bs;
   if (blocks > need_blocks) blocks = need_blocks;
   KP_HIP(hipEventRecord(ctx->ev[0], s), "event record");
-  KP_HIP(launch_transport(a, fp64, aligned, sphere, (int)blocks, bs, s), "transport kernel launch");
+  KP_HIP(launch_transport(a, fp64, aligned, sphere, b.peel != nullptr, (int)blocks, bs, s),
+         "transport kernel launch");
   KP_HIP(hipEventRecord(ctx->ev[1], s), "event record");
   KP_HIP(hipStreamSynchronize(s), "transport kernel");
 
@@ -510,7 +548,7 @@ void kp_destroy(kp_ctx* ctx) {
   for (void* p : {(void*)ctx->d_views, (void*)ctx->d_dust, (void*)ctx->d_tally,
                   (void*)ctx->d_images, (void*)ctx->d_stats, (void*)ctx->d_counter,
                   (void*)ctx->d_bad, (void*)ctx->d_traces, (void*)ctx->d_em_cdf,
-                  (void*)ctx->d_em_guide, (void*)ctx->d_em_partial})
+                  (void*)ctx->d_em_guide, (void*)ctx->d_em_partial, (void*)ctx->d_peel})
     if (p) (void)hipFree(p);
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
@@ -655,6 +693,7 @@ kp_status kp_set_views(kp_ctx* ctx, int32_t n_views, const kp_view* v) {
   ctx->hviews.resize(n_views);
   for (int k = 0; k < n_views; ++k) fill_view(v[k], ctx->hviews[k]);
   ctx->have_images = false;
+  ctx->peel_valid_n = 0;
   return KP_OK;
 }
 
@@ -670,19 +709,26 @@ kp_status kp_transport(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, vo
   const int ts = tally_stride(all_sphere);
   const size_t tally_need = (size_t)nl * ctx->ncell * ts;
   const size_t trace_need = (size_t)nl * o->trace_packets;
+  const size_t peel_need =
+      o->peel_off ? (size_t)nl * ctx->views.size() * 4 * ctx->views[0].npx * ctx->views[0].npy : 0;
   size_t free_b = 0, total_b = 0;
   KP_HIP(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
   size_t extra = (tally_need > ctx->tally_n ? tally_need * 8 : 0) +
-                 (trace_need > ctx->traces_n ? trace_need * sizeof(TraceDev) : 0);
+                 (trace_need > ctx->traces_n ? trace_need * sizeof(TraceDev) : 0) +
+                 (peel_need > ctx->peel_n ? peel_need * 8 : 0);
   if (extra > free_b) return fail(ctx, KP_ERR_OOM, "tally needs %zu bytes, %zu free", extra, free_b);
   if ((st = ensure(ctx, &ctx->d_tally, &ctx->tally_n, tally_need, "tally allocation"))) return st;
   if ((st = ensure(ctx, &ctx->d_traces, &ctx->traces_n, trace_need, "trace allocation"))) return st;
+  if ((st = ensure(ctx, &ctx->d_peel, &ctx->peel_n, peel_need, "peel-off allocation"))) return st;
+  ctx->peel_valid_n = 0;
   if (ctx->src.kind == 2 && (st = prepare_emission(ctx, s))) return st;
   fill_dust(ctx, counts, ctx->hdust);
   if ((st = upload_small(ctx, s))) return st;
-  const RunBuffers buf{ctx->d_dust, ctx->d_tally, ctx->d_stats, ctx->d_counter, ctx->d_traces};
+  const RunBuffers buf{ctx->d_dust, ctx->d_tally, ctx->d_stats, ctx->d_counter, ctx->d_traces,
+                       ctx->d_views, o->peel_off ? ctx->d_peel : nullptr};
   st = transport_launch(ctx, o, total, buf, s);
   if (st == KP_ERR_DEVICE || st == KP_ERR_OOM) return st;
+  ctx->peel_valid_n = peel_need;
   ctx->tally_lambda = nl;
   ctx->tally_ts = ts;
   ctx->tally_nc = tally_components(all_sphere);
@@ -728,6 +774,7 @@ kp_status kp_run_static(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, d
   kp_status st = check_run_args(ctx, counts, o, &total);
   if (st) return st;
   if (o->trace_packets) return fail(ctx, KP_ERR_ARG, "kp_run_static records no traces: trace_packets must be 0");
+  if (o->peel_off) return fail(ctx, KP_ERR_ARG, "kp_run_static forms no peel-off images: peel_off must be 0");
   if (ctx->src.kind == 2 && !ctx->em_ready)
     return fail(ctx, KP_ERR_STATE, "thermal emission: its luminosity tables are built by kp_run or kp_transport; "
                 "call one of them once after kp_set_emission, kp_set_dust or kp_set_grid");
@@ -764,7 +811,7 @@ kp_status kp_run_static(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, d
   fill_dust(ctx, counts, ctx->hdust);
   KP_HIP(hipMemcpyAsync(d_dust, ctx->hdust.data(), dust_bytes, hipMemcpyHostToDevice, s), "dust upload");
   KP_HIP(hipMemcpyAsync(d_views, ctx->hviews.data(), view_bytes, hipMemcpyHostToDevice, s), "view upload");
-  const RunBuffers buf{d_dust, d_tally, d_stats, d_counter, nullptr};
+  const RunBuffers buf{d_dust, d_tally, d_stats, d_counter, nullptr, d_views, nullptr};
   st = transport_launch(ctx, o, total, buf, s);
   if (st == KP_ERR_DEVICE || st == KP_ERR_OOM) return st;
   kp_status st2 = image_launch(ctx, false, nullptr, d_images, nl, s, d_dust, d_views, d_tally);
@@ -810,6 +857,17 @@ kp_status kp_get_images_device(kp_ctx* ctx, double* d_out, size_t n, void* strea
   KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   KP_HIP(hipMemcpyAsync(d_out, ctx->d_images, n * sizeof(double), hipMemcpyDeviceToDevice,
                         (hipStream_t)stream), "image copy");
+  return KP_OK;
+}
+
+kp_status kp_get_peel_images(kp_ctx* ctx, double* out, size_t n) {
+  if (!ctx) return KP_ERR_ARG;
+  if (!ctx->peel_valid_n)
+    return fail(ctx, KP_ERR_STATE, "no peel-off images: the last step 1 ran without peel_off");
+  if (!out || n != ctx->peel_valid_n)
+    return fail(ctx, KP_ERR_ARG, "destination must hold %zu doubles", ctx->peel_valid_n);
+  KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  KP_HIP(hipMemcpy(out, ctx->d_peel, n * sizeof(double), hipMemcpyDeviceToHost), "peel-off copy");
   return KP_OK;
 }
 

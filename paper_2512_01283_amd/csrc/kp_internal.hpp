@@ -49,6 +49,12 @@ struct TraceDev {
   double tau_path;
 };
 
+// a packet ends as an event-cap packet after this many cell steps (one that
+// cannot scatter and moves parallel to every open face of a partly periodic
+// grid would never leave it); camera rays longer than this many cells are
+// refused
+constexpr int KP_MAX_STEPS = 1 << 24;
+
 struct TransportArgs {
   const float* rho;
   const float* bx;
@@ -79,6 +85,12 @@ struct TransportArgs {
   // L k / ncell; entry ncell: the last cell)
   const double* em_cdf;
   const uint32_t* em_guide;
+  int boundary;          // bit a: axis a periodic
+  // peel-off imaging (the kernels instantiated with it): cameras and the
+  // images [lambda][view][4][npy][npx] the scattering events are added to
+  const ViewDev* views;
+  int n_views, npx, npy;
+  double* peel;
 };
 
 struct ImageArgs {
@@ -97,6 +109,7 @@ struct ImageArgs {
   uint64_t ncell;
   const float* em_B;    // [lambda][ncell] source function of the dust's thermal
                         // emission, or null (no thermal source term)
+  int boundary;         // bit a: axis a periodic
 };
 
 // Tally layout [lambda][cell][stride] FP64: 6 reals (stride 8, one 64-B block
@@ -108,7 +121,7 @@ inline int tally_components(bool sphere) { return sphere ? 6 : 9; }
 inline int tally_stride(bool sphere) { return sphere ? 8 : 16; }
 
 // launchers (kp_kernels.hip)
-hipError_t launch_transport(const TransportArgs& a, bool fp64, bool aligned, bool sphere,
+hipError_t launch_transport(const TransportArgs& a, bool fp64, bool aligned, bool sphere, bool peel,
                             int blocks, int block_size, hipStream_t s);
 hipError_t launch_image(const ImageArgs& a, bool aligned, bool sphere, bool user_source,
                         hipStream_t s);
@@ -117,7 +130,7 @@ hipError_t launch_tally_init(double* tally, const float* rho, const float* bx, c
                              const float* bz, uint64_t ncell, int n_lambda, bool sphere, hipStream_t s);
 hipError_t launch_validate(const float* rho, const float* bx, const float* by, const float* bz,
                            uint64_t n, unsigned long long* bad, hipStream_t s);
-int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, int block_size);
+int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, bool peel, int block_size);
 // Thermal emission tables of one wavelength: cdf [ncell], the running sum
 // of fac rho B (fac = 4 pi kappa_abs dx^3) in flat cell order, and its guide
 // table [ncell + 1]; `partial` holds emission_blocks(ncell) doubles of

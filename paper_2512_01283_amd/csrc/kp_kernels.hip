@@ -228,6 +228,10 @@ __device__ bool init_packet(Packet<R>& p, uint64_t g, const TransportArgs& a) {
       ci[k] = i;
       fr[k] = f;
     }
+    const int nn[3] = {a.nx, a.ny, a.nz};
+#pragma unroll
+    for (int k = 0; k < 3; ++k)  // a periodic axis holds every coordinate
+      if ((a.boundary >> k) & 1) ci[k] = ((ci[k] % nn[k]) + nn[k]) % nn[k];
     p.ci = ci[0]; p.cj = ci[1]; p.ck = ci[2];
     p.fx = fr[0]; p.fy = fr[1]; p.fz = fr[2];
     in = p.ci >= 0 && p.ci < a.nx && p.cj >= 0 && p.cj < a.ny && p.ck >= 0 && p.ck < a.nz;
@@ -502,7 +506,7 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
   constexpr int NC = TallyShape<SPHERE>::NC;
   const uint64_t c = (uint64_t)p.ci + (uint64_t)a.nx * ((uint64_t)p.cj + (uint64_t)a.ny * p.ck);
   p.last = (int64_t)c;
-  if (p.events >= a.max_events) {
+  if (p.events >= a.max_events || p.steps >= KP_MAX_STEPS) {
     p.hash = hash_event(p.hash, END_BUDGET, c);
     return END_BUDGET;
   }
@@ -620,15 +624,21 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
     if (axis != 1) p.fy = fmin(1.0, fmax(0.0, p.fy + td * dny));
     if (axis != 2) p.fz = fmin(1.0, fmax(0.0, p.fz + td * dnz));
     bool out;
+    // leaving through an open face ends the packet; a periodic face brings
+    // it back through the opposite one
+    const bool per = (a.boundary >> axis) & 1;
     if (axis == 0) {
       if (dnx > 0.0) { p.ci++; p.fx = 0.0; } else { p.ci--; p.fx = 1.0; }
       out = p.ci < 0 || p.ci >= a.nx;
+      if (out && per) { p.ci = p.ci < 0 ? a.nx - 1 : 0; out = false; }
     } else if (axis == 1) {
       if (dny > 0.0) { p.cj++; p.fy = 0.0; } else { p.cj--; p.fy = 1.0; }
       out = p.cj < 0 || p.cj >= a.ny;
+      if (out && per) { p.cj = p.cj < 0 ? a.ny - 1 : 0; out = false; }
     } else {
       if (dnz > 0.0) { p.ck++; p.fz = 0.0; } else { p.ck--; p.fz = 1.0; }
       out = p.ck < 0 || p.ck >= a.nz;
+      if (out && per) { p.ck = p.ck < 0 ? a.nz - 1 : 0; out = false; }
     }
     if (out) {
       p.hash = hash_event(p.hash, END_ESCAPE, c);
@@ -641,9 +651,184 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
   return roulette(p, a);
 }
 
+// ---------------------------------------------------------------------------
+// Shared by step 2 and peel-off: the Appendix A solution in its eigenbasis
+// and the Stokes source toward a camera formed from an incident coherency.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void appA_eigen(double a1, double a2, double a3, double dtau,
+                                           const double src[4], double s[4]) {
+  const double a = a1 + a2, b = a1 - a2;
+  const double A = s[0] + s[1], B = s[0] - s[1];
+  const double SA = src[0] + src[1], SB = src[0] - src[1];
+  const double An = A * exp(-a * dtau) + SA * dtau * phi1(a * dtau);
+  const double Bn = B * exp(-b * dtau) + SB * dtau * phi1(b * dtau);
+  double Un, Vn;
+  if (a3 == 0.0) {
+    const double e = exp(-a1 * dtau), g = dtau * phi1(a1 * dtau);
+    Un = s[2] * e + src[2] * g;
+    Vn = s[3] * e + src[3] * g;
+  } else {
+    // U + iV relaxes as exp(-(a1 - i a3) tau) toward the stationary state
+    const double x = -a1 * dtau, y = a3 * dtau;
+    const double ex = exp(x), cy = cos(y), sy = sin(y), sh = sin(0.5 * y);
+    const Cx<double> ez{ex * cy, ex * sy};
+    const Cx<double> em1{expm1(x) * cy - 2.0 * sh * sh, ex * sy};
+    const double den = x * x + y * y;
+    const Cx<double> phic{(em1.re * x + em1.im * y) / den, (em1.im * x - em1.re * y) / den};
+    const Cx<double> Z{s[2], s[3]}, SZ{src[2], src[3]};
+    const Cx<double> Zn = cadd(cmul(Z, ez), cscale(cmul(SZ, phic), dtau));
+    Un = Zn.re; Vn = Zn.im;
+  }
+  s[0] = 0.5 * (An + Bn);
+  s[1] = 0.5 * (An - Bn);
+  s[2] = Un;
+  s[3] = Vn;
+}
+
+// Stokes vector scattered toward a camera (basis e1 = theta_hat, e2 = phi_hat
+// of its direction) by a dipole whose incident coherency is C9 (real xx yy
+// zz xy xz yz, imaginary yz zx xy): rho'_ij = h_i^T C conj(h_j) with h_i =
+// alpha e_i and the lab polarizability alpha = a_perp 1 + (a_par - a_perp)
+// b b^T (b the grain axis), times pf.
+template <bool SPHERE>
+__device__ __forceinline__ void source_toward(const double C9[9], const Quat<double>& q, const DustDev& D,
+                                              const V3<double>& e1, const V3<double>& e2, double pf,
+                                              double S[4]) {
+  const double Cr[3][3] = {{C9[0], C9[3], C9[4]}, {C9[3], C9[1], C9[5]}, {C9[4], C9[5], C9[2]}};
+  const double i6 = C9[6], i7 = C9[7], i8 = C9[8];
+  const double Ci[3][3] = {{0.0, i8, -i7}, {-i8, 0.0, i6}, {i7, -i6, 0.0}};
+  Cx<double> h1[3], h2[3];
+  const double ev1[3] = {e1.x, e1.y, e1.z}, ev2[3] = {e2.x, e2.y, e2.z};
+  if (SPHERE) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { h1[k] = {ev1[k], 0.0}; h2[k] = {ev2[k], 0.0}; }
+  } else {
+    const V3<double> b = from_grain(q, V3<double>{0.0, 0.0, 1.0});
+    const double bv[3] = {b.x, b.y, b.z};
+    const double b1 = dot(b, e1), b2 = dot(b, e2);
+    const Cx<double> ap{D.ap_re, D.ap_im}, dd{D.aa_re - D.ap_re, D.aa_im - D.ap_im};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      h1[k] = cadd(cscale(ap, ev1[k]), cscale(dd, b1 * bv[k]));
+      h2[k] = cadd(cscale(ap, ev2[k]), cscale(dd, b2 * bv[k]));
+    }
+  }
+  // g_j = C conj(h_j)
+  Cx<double> g1[3], g2[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    g1[k] = {0.0, 0.0};
+    g2[k] = {0.0, 0.0};
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const Cx<double> C{Cr[k][l], Ci[k][l]};
+      g1[k] = cadd(g1[k], cmulc(C, h1[l]));
+      g2[k] = cadd(g2[k], cmulc(C, h2[l]));
+    }
+  }
+  double r11 = 0.0, r22 = 0.0;
+  Cx<double> r12{0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    r11 += cmul(h1[k], g1[k]).re;
+    r22 += cmul(h2[k], g2[k]).re;
+    r12 = cadd(r12, cmul(h1[k], g2[k]));
+  }
+  S[0] = pf * (r11 + r22);
+  S[1] = pf * (r11 - r22);
+  S[2] = pf * 2.0 * r12.re;
+  S[3] = -pf * 2.0 * r12.im;
+}
+
+// Peel-off imaging at a scattering event (the Monte Carlo imaging that Sec.
+// 2.3 sets two-step imaging against): for every camera, the Stokes vector the
+// event scatters toward it per unit solid angle (from the packet's incident
+// coherency, as step 2 forms its source from the tallied one), carried to
+// the grid's edge through the Appendix A extinction of every cell on the way
+// (no source), added to the pixel the event projects to, per unit pixel
+// area.  FP64; open boundaries.
+template <typename R, bool ALIGNED, bool SPHERE>
+__device__ void peel_off(const Packet<R>& p, const TransportArgs& a, const Quat<double>& q_ev,
+                         const DustDev& D) {
+  double C9[9];
+  coherency<double, 9>(V3<double>{p.nx, p.ny, p.nz}, (double)p.I, (double)p.Q, (double)p.U, (double)p.V,
+                       1.0, C9);
+  const double X[3] = {a.x0 + ((double)p.ci + p.fx) * a.dx, a.y0 + ((double)p.cj + p.fy) * a.dx,
+                       a.z0 + ((double)p.ck + p.fz) * a.dx};
+  const int nn[3] = {a.nx, a.ny, a.nz};
+  for (int v = 0; v < a.n_views; ++v) {
+    const ViewDev vw = a.views[v];
+    const double W = vw.half_width;
+    const double xi = X[0] * vw.px + X[1] * vw.py + X[2] * vw.pz;
+    const double yi = -(X[0] * vw.tx + X[1] * vw.ty + X[2] * vw.tz);
+    const double fxp = (xi + W) / (2.0 * W / a.npx), fyp = (yi + W) / (2.0 * W / a.npy);
+    if (!(fxp >= 0.0 && fxp < (double)a.npx && fyp >= 0.0 && fyp < (double)a.npy)) continue;
+    const int ix = (int)fxp, iy = (int)fyp;
+    const V3<double> Om{vw.ox, vw.oy, vw.oz};
+    double st[4];
+    source_toward<SPHERE>(C9, q_ev, D, V3<double>{vw.tx, vw.ty, vw.tz}, V3<double>{vw.px, vw.py, vw.pz},
+                          D.pfac, st);
+    const double om[3] = {vw.ox, vw.oy, vw.oz};
+    int ci[3] = {p.ci, p.cj, p.ck};
+    double f[3] = {p.fx, p.fy, p.fz};
+    while (true) {
+      double tb = __builtin_huge_val();
+      int axis = -1;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        double t;
+        if (om[k] > 0.0) t = (1.0 - f[k]) / om[k];
+        else if (om[k] < 0.0) t = -f[k] / om[k];
+        else continue;
+        if (t < tb) { tb = t; axis = k; }
+      }
+      if (axis < 0) break;
+      const uint64_t c = (uint64_t)ci[0] + (uint64_t)a.nx * ((uint64_t)ci[1] + (uint64_t)a.ny * ci[2]);
+      const double rho = (double)a.rho[c];
+      if (rho > 0.0 && tb > 0.0) {
+        const double dtau = rho * D.kext * tb * a.dx;
+        if (SPHERE && !ALIGNED) {
+          const double E = exp(-dtau);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) st[k] *= E;
+        } else {
+          const double* blk = a.tally + ((uint64_t)p.lam * a.ncell + c) * TallyShape<SPHERE>::TS;
+          Quat<double> qc{1.0, 0.0, 0.0, 0.0};
+          if (ALIGNED) qc = cell_quat<ALIGNED, SPHERE>(a, blk, c);
+          V3<double> og = Om;
+          double c2 = 1.0, s2 = 0.0;
+          if (ALIGNED) {
+            og = to_grain(qc, Om);
+            eta2(qc, Om, og, c2, s2);
+          }
+          double a1, a2, a3;
+          alphas<double, SPHERE>(D, og.z, a1, a2, a3);
+          double sg[4] = {st[0], c2 * st[1] + s2 * st[2], -s2 * st[1] + c2 * st[2], st[3]};
+          const double zero[4] = {0.0, 0.0, 0.0, 0.0};
+          appA_eigen(a1, a2, a3, dtau, zero, sg);
+          st[0] = sg[0];
+          st[1] = c2 * sg[1] - s2 * sg[2];
+          st[2] = s2 * sg[1] + c2 * sg[2];
+          st[3] = sg[3];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        if (k != axis) f[k] = fmin(1.0, fmax(0.0, f[k] + tb * om[k]));
+      if (om[axis] > 0.0) { ci[axis]++; f[axis] = 0.0; } else { ci[axis]--; f[axis] = 1.0; }
+      if (ci[axis] < 0 || ci[axis] >= nn[axis]) break;
+    }
+    const double area = (2.0 * W / a.npx) * (2.0 * W / a.npy);
+    double* out = a.peel + (((uint64_t)p.lam * a.n_views + v) * 4) * ((uint64_t)a.npx * a.npy) +
+                  (uint64_t)iy * a.npx + ix;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) unsafeAtomicAdd(out + (uint64_t)k * a.npx * a.npy, st[k] / area);
+  }
+}
+
 // Scattering event at the packet's current position (Sec. 2.2), the next
 // scattering depth, and the roulette check that follows every segment.
-template <typename R, bool ALIGNED, bool SPHERE>
+template <typename R, bool ALIGNED, bool SPHERE, bool PEEL>
 __device__ uint32_t scatter_step(Packet<R>& p, const TransportArgs& a) {
   const uint64_t c = (uint64_t)p.ci + (uint64_t)a.nx * ((uint64_t)p.cj + (uint64_t)a.ny * p.ck);
   const DustDev& D = a.dust[p.lam];
@@ -654,6 +839,7 @@ __device__ uint32_t scatter_step(Packet<R>& p, const TransportArgs& a) {
     qd = cell_quat<ALIGNED, SPHERE>(a, blk, c);
     q = quat_cast<R>(qd);
   }
+  if (PEEL) peel_off<R, ALIGNED, SPHERE>(p, a, qd, D);
   if (!scatter<R, ALIGNED, SPHERE>(p, q, qd, D, a.seed)) return END_NUMERIC;
   p.events++;
   p.hash = hash_event(p.hash, EV_SCATTER, c);
@@ -720,7 +906,7 @@ __device__ void finish(const Packet<R>& p, uint32_t end, const TransportArgs& a,
   }
 }
 
-template <typename R, bool ALIGNED, bool SPHERE>
+template <typename R, bool ALIGNED, bool SPHERE, bool PEEL>
 __device__ __forceinline__ void transport_body(const TransportArgs& a) {
   constexpr int NC = TallyShape<SPHERE>::NC, TS = TallyShape<SPHERE>::TS;
   __shared__ unsigned long long sc[SC_N];
@@ -856,7 +1042,7 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
         waited = 0;
         if (pending) {
           pending = false;
-          const uint32_t end = scatter_step<R, ALIGNED, SPHERE>(p, a);
+          const uint32_t end = scatter_step<R, ALIGNED, SPHERE, PEEL>(p, a);
           if (end) {
             finish(p, end, a, sc, se);
             active = false;
@@ -878,15 +1064,17 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
 // unconstrained and would run one wave per SIMD; the bound costs them about a
 // dozen spills and makes them 1.5x faster.  The FP64 variants need 297-361;
 // holding them to two waves spills 50-190 registers and halves their speed,
-// so they run unbounded at one wave per SIMD.
-template <bool ALIGNED, bool SPHERE>
+// so they run unbounded at one wave per SIMD.  PEEL adds peel-off imaging at
+// every scattering event (a separate instantiation: the kernels without it
+// are unchanged).
+template <bool ALIGNED, bool SPHERE, bool PEEL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_transport32(TransportArgs a) {
-  transport_body<float, ALIGNED, SPHERE>(a);
+  transport_body<float, ALIGNED, SPHERE, PEEL>(a);
 }
-template <bool ALIGNED, bool SPHERE>
+template <bool ALIGNED, bool SPHERE, bool PEEL>
 __global__ void __launch_bounds__(256) k_transport64(TransportArgs a) {
-  transport_body<double, ALIGNED, SPHERE>(a);
+  transport_body<double, ALIGNED, SPHERE, PEEL>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -896,36 +1084,6 @@ __global__ void __launch_bounds__(256) k_transport64(TransportArgs a) {
 // extinction for the camera direction and the scattering source formed from
 // the coherency tally (or a caller-given per-view source).  FP64 throughout.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void appA_eigen(double a1, double a2, double a3, double dtau,
-                                           const double src[4], double s[4]) {
-  const double a = a1 + a2, b = a1 - a2;
-  const double A = s[0] + s[1], B = s[0] - s[1];
-  const double SA = src[0] + src[1], SB = src[0] - src[1];
-  const double An = A * exp(-a * dtau) + SA * dtau * phi1(a * dtau);
-  const double Bn = B * exp(-b * dtau) + SB * dtau * phi1(b * dtau);
-  double Un, Vn;
-  if (a3 == 0.0) {
-    const double e = exp(-a1 * dtau), g = dtau * phi1(a1 * dtau);
-    Un = s[2] * e + src[2] * g;
-    Vn = s[3] * e + src[3] * g;
-  } else {
-    // U + iV relaxes as exp(-(a1 - i a3) tau) toward the stationary state
-    const double x = -a1 * dtau, y = a3 * dtau;
-    const double ex = exp(x), cy = cos(y), sy = sin(y), sh = sin(0.5 * y);
-    const Cx<double> ez{ex * cy, ex * sy};
-    const Cx<double> em1{expm1(x) * cy - 2.0 * sh * sh, ex * sy};
-    const double den = x * x + y * y;
-    const Cx<double> phic{(em1.re * x + em1.im * y) / den, (em1.im * x - em1.re * y) / den};
-    const Cx<double> Z{s[2], s[3]}, SZ{src[2], src[3]};
-    const Cx<double> Zn = cadd(cmul(Z, ez), cscale(cmul(SZ, phic), dtau));
-    Un = Zn.re; Vn = Zn.im;
-  }
-  s[0] = 0.5 * (An + Bn);
-  s[1] = 0.5 * (An - Bn);
-  s[2] = Un;
-  s[3] = Vn;
-}
-
 template <bool ALIGNED, bool SPHERE, bool USER_S>
 __global__ void __launch_bounds__(256) k_image(ImageArgs a) {
   const uint64_t npix = (uint64_t)a.npx * a.npy;
@@ -949,6 +1107,7 @@ __global__ void __launch_bounds__(256) k_image(ImageArgs a) {
   bool miss = false;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
+    if ((a.boundary >> k) & 1) continue;  // the periodic copies fill the axis
     const double hi = lo[k] + nn[k] * a.dx;
     if (om[k] != 0.0) {
       const double s1 = (lo[k] - P0[k]) / om[k], s2 = (hi - P0[k]) / om[k];
@@ -965,7 +1124,14 @@ __global__ void __launch_bounds__(256) k_image(ImageArgs a) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const double t = (P0[k] + sn * om[k] - lo[k]) / a.dx;
-      int i = (int)floor(t);
+      const double fl = floor(t);
+      if ((a.boundary >> k) & 1) {
+        const long long n = nn[k], i = (long long)fl;
+        ci[k] = (int)(((i % n) + n) % n);
+        f[k] = fmin(1.0, fmax(0.0, t - fl));
+        continue;
+      }
+      int i = (int)fl;
       i = i < 0 ? 0 : (i > nn[k] - 1 ? nn[k] - 1 : i);
       ci[k] = i;
       f[k] = fmin(1.0, fmax(0.0, t - (double)i));
@@ -1003,52 +1169,9 @@ __global__ void __launch_bounds__(256) k_image(ImageArgs a) {
           // polarizability alpha = a_perp 1 + (a_par - a_perp) b b^T.
           constexpr int TS = TallyShape<SPHERE>::TS;
           const double* T = a.tally + ((uint64_t)lam * a.ncell + c) * TS;
-          const double Cr[3][3] = {{T[0], T[3], T[4]}, {T[3], T[1], T[5]}, {T[4], T[5], T[2]}};
-          double i6 = 0.0, i7 = 0.0, i8 = 0.0;
-          if (TallyShape<SPHERE>::NC == 9) { i6 = T[6]; i7 = T[7]; i8 = T[8]; }
-          const double Ci[3][3] = {{0.0, i8, -i7}, {-i8, 0.0, i6}, {i7, -i6, 0.0}};
-          Cx<double> h1[3], h2[3];
-          const double ev1[3] = {e1.x, e1.y, e1.z}, ev2[3] = {e2.x, e2.y, e2.z};
-          if (SPHERE) {
-#pragma unroll
-            for (int k = 0; k < 3; ++k) { h1[k] = {ev1[k], 0.0}; h2[k] = {ev2[k], 0.0}; }
-          } else {
-            const V3<double> b = from_grain(q, V3<double>{0.0, 0.0, 1.0});
-            const double bv[3] = {b.x, b.y, b.z};
-            const double b1 = dot(b, e1), b2 = dot(b, e2);
-            const Cx<double> ap{D.ap_re, D.ap_im}, dd{D.aa_re - D.ap_re, D.aa_im - D.ap_im};
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-              h1[k] = cadd(cscale(ap, ev1[k]), cscale(dd, b1 * bv[k]));
-              h2[k] = cadd(cscale(ap, ev2[k]), cscale(dd, b2 * bv[k]));
-            }
-          }
-          // g_j = C conj(h_j)
-          Cx<double> g1[3], g2[3];
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            g1[k] = {0.0, 0.0};
-            g2[k] = {0.0, 0.0};
-#pragma unroll
-            for (int l = 0; l < 3; ++l) {
-              const Cx<double> C{Cr[k][l], Ci[k][l]};
-              g1[k] = cadd(g1[k], cmulc(C, h1[l]));
-              g2[k] = cadd(g2[k], cmulc(C, h2[l]));
-            }
-          }
-          double r11 = 0.0, r22 = 0.0;
-          Cx<double> r12{0.0, 0.0};
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            r11 += cmul(h1[k], g1[k]).re;
-            r22 += cmul(h2[k], g2[k]).re;
-            r12 = cadd(r12, cmul(h1[k], g2[k]));
-          }
-          const double pf = D.pfac * inv_vol;
-          S[0] = pf * (r11 + r22);
-          S[1] = pf * (r11 - r22);
-          S[2] = pf * 2.0 * r12.re;
-          S[3] = -pf * 2.0 * r12.im;
+          double C9[9] = {T[0], T[1], T[2], T[3], T[4], T[5], 0.0, 0.0, 0.0};
+          if (TallyShape<SPHERE>::NC == 9) { C9[6] = T[6]; C9[7] = T[7]; C9[8] = T[8]; }
+          source_toward<SPHERE>(C9, q, D, e1, e2, D.pfac * inv_vol, S);
         }
         const double ik = 1.0 / ke;
         double src[4] = {S[0] * ik, S[1] * ik, S[2] * ik, S[3] * ik};
@@ -1084,7 +1207,10 @@ __global__ void __launch_bounds__(256) k_image(ImageArgs a) {
       for (int k = 0; k < 3; ++k)
         if (k != axis) f[k] = fmin(1.0, fmax(0.0, f[k] + tb * om[k]));
       if (om[axis] > 0.0) { ci[axis]++; f[axis] = 0.0; } else { ci[axis]--; f[axis] = 1.0; }
-      if (ci[axis] < 0 || ci[axis] >= nn[axis]) break;
+      if (ci[axis] < 0 || ci[axis] >= nn[axis]) {
+        if (!((a.boundary >> axis) & 1)) break;
+        ci[axis] = ci[axis] < 0 ? nn[axis] - 1 : 0;
+      }
     }
   }
   double* out = a.images + (((uint64_t)lam * a.n_views + v) * 4) * npix + (uint64_t)iy * a.npx + ix;
@@ -1252,33 +1378,40 @@ hipError_t launch_emission_table(const float* rho, const float* B, double fac, u
 // launchers
 // ---------------------------------------------------------------------------
 template <bool A, bool S>
-static void launch_one(const TransportArgs& a, bool fp64, int blocks, int bs, hipStream_t s) {
-  if (fp64) hipLaunchKernelGGL((k_transport64<A, S>), dim3(blocks), dim3(bs), 0, s, a);
-  else hipLaunchKernelGGL((k_transport32<A, S>), dim3(blocks), dim3(bs), 0, s, a);
+static void launch_one(const TransportArgs& a, bool fp64, bool peel, int blocks, int bs, hipStream_t s) {
+  if (fp64 && peel) hipLaunchKernelGGL((k_transport64<A, S, true>), dim3(blocks), dim3(bs), 0, s, a);
+  else if (fp64) hipLaunchKernelGGL((k_transport64<A, S, false>), dim3(blocks), dim3(bs), 0, s, a);
+  else if (peel) hipLaunchKernelGGL((k_transport32<A, S, true>), dim3(blocks), dim3(bs), 0, s, a);
+  else hipLaunchKernelGGL((k_transport32<A, S, false>), dim3(blocks), dim3(bs), 0, s, a);
 }
 
-hipError_t launch_transport(const TransportArgs& a, bool fp64, bool aligned, bool sphere,
+hipError_t launch_transport(const TransportArgs& a, bool fp64, bool aligned, bool sphere, bool peel,
                             int blocks, int block_size, hipStream_t s) {
-  if (aligned && sphere) launch_one<true, true>(a, fp64, blocks, block_size, s);
-  else if (aligned) launch_one<true, false>(a, fp64, blocks, block_size, s);
-  else if (sphere) launch_one<false, true>(a, fp64, blocks, block_size, s);
-  else launch_one<false, false>(a, fp64, blocks, block_size, s);
+  if (aligned && sphere) launch_one<true, true>(a, fp64, peel, blocks, block_size, s);
+  else if (aligned) launch_one<true, false>(a, fp64, peel, blocks, block_size, s);
+  else if (sphere) launch_one<false, true>(a, fp64, peel, blocks, block_size, s);
+  else launch_one<false, false>(a, fp64, peel, blocks, block_size, s);
   return hipGetLastError();
 }
 
-template <bool A, bool S>
+template <bool A, bool S, bool PL>
 static int occ_one(bool fp64, int bs) {
   int n = 0;
-  const hipError_t e = fp64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport64<A, S>, bs, 0)
-                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport32<A, S>, bs, 0);
+  const hipError_t e = fp64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport64<A, S, PL>, bs, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport32<A, S, PL>, bs, 0);
   return e == hipSuccess ? n : 0;
 }
 
-int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, int block_size) {
-  if (aligned && sphere) return occ_one<true, true>(fp64, block_size);
-  if (aligned) return occ_one<true, false>(fp64, block_size);
-  if (sphere) return occ_one<false, true>(fp64, block_size);
-  return occ_one<false, false>(fp64, block_size);
+template <bool A, bool S>
+static int occ_peel(bool fp64, bool peel, int bs) {
+  return peel ? occ_one<A, S, true>(fp64, bs) : occ_one<A, S, false>(fp64, bs);
+}
+
+int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, bool peel, int block_size) {
+  if (aligned && sphere) return occ_peel<true, true>(fp64, peel, block_size);
+  if (aligned) return occ_peel<true, false>(fp64, peel, block_size);
+  if (sphere) return occ_peel<false, true>(fp64, peel, block_size);
+  return occ_peel<false, false>(fp64, peel, block_size);
 }
 
 hipError_t launch_image(const ImageArgs& a, bool aligned, bool sphere, bool user_source,

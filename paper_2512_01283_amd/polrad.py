@@ -71,7 +71,7 @@ class kp_opts(C.Structure):
                 ("trace_packets", C.c_uint32), ("trace_stride", C.c_uint32),
                 ("block_size", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("strict", C.c_int32), ("scatter_batch", C.c_int32),
-                ("scatter_wait", C.c_int32)]
+                ("scatter_wait", C.c_int32), ("peel_off", C.c_int32)]
 
 
 class kp_stats(C.Structure):
@@ -107,6 +107,7 @@ _SIGS = {
     "kp_image_source": ([_P, _P, _P, _P], C.c_int),
     "kp_get_images": ([_P, _P, C.c_size_t], C.c_int),
     "kp_get_images_device": ([_P, _P, C.c_size_t, _P], C.c_int),
+    "kp_get_peel_images": ([_P, _P, C.c_size_t], C.c_int),
     "kp_get_tally": ([_P, _P, C.c_size_t], C.c_int),
     "kp_get_stats": ([_P, C.POINTER(kp_stats)], C.c_int),
     "kp_get_trace": ([_P, _P, C.c_size_t], C.c_int),
@@ -220,7 +221,8 @@ def make_opts(o=None, **kw) -> kp_opts:
                    int(o.get("max_events", 10000)), int(o.get("trace_packets", 0)),
                    int(o.get("trace_stride", 1)), int(o.get("block_size", 0)),
                    int(o.get("blocks_per_cu", 0)), int(o.get("strict", 0)),
-                   int(o.get("scatter_batch", 0)), int(o.get("scatter_wait", 0)))
+                   int(o.get("scatter_batch", 0)), int(o.get("scatter_wait", 0)),
+                   int(o.get("peel_off", 0)))
 
 
 def _counts(counts):
@@ -262,6 +264,12 @@ def kp_get_images(ctx, shape) -> np.ndarray:
 
 def kp_get_images_device(ctx, d_out, stream=None) -> None:
     _check(ctx, _lib.kp_get_images_device(ctx, _ptr(d_out), d_out.numel(), _stream_ptr(stream)))
+
+
+def kp_get_peel_images(ctx, shape) -> np.ndarray:
+    out = np.zeros(shape, dtype=np.float64)
+    _check(ctx, _lib.kp_get_peel_images(ctx, out.ctypes.data_as(_P), out.size))
+    return out
 
 
 def kp_get_tally(ctx, n_lambda, ncell) -> np.ndarray:
@@ -369,6 +377,13 @@ class Context:
             out = torch.empty(shape, dtype=torch.float64, device="cuda")
         kp_get_images_device(self.h, out, stream)
         return out
+
+    def peel_images(self) -> np.ndarray:
+        """Peel-off images of the last step 1 run with peel_off=1,
+        [n_lambda, n_views, 4, npy, npx]."""
+        v = self.cfg["views"]
+        nl = len(getattr(self, "last_counts", self.cfg["packets"]))
+        return kp_get_peel_images(self.h, (nl, len(v), 4, v[0]["npy"], v[0]["npx"]))
 
     def tally(self) -> np.ndarray:
         g = self.cfg["grid"]
