@@ -40,7 +40,8 @@ class Dust(C.Structure):
     _fields_ = [("kappa_sca", C.c_double), ("kappa_abs", C.c_double),
                 ("a_perp_re", C.c_double), ("a_perp_im", C.c_double),
                 ("a_par_re", C.c_double), ("a_par_im", C.c_double),
-                ("alpha3_scale", C.c_double)]
+                ("alpha3_scale", C.c_double), ("n_theta", C.c_int32),
+                ("Z", C.POINTER(C.c_double))]
 
 
 class Source(C.Structure):
@@ -158,10 +159,20 @@ def make_grid(g) -> Grid:
 
 
 def make_dust(d) -> Dust:
-    return Dust(float(d["kappa_sca"]), float(d["kappa_abs"]),
-                float(np.real(d["a_perp"])), float(np.imag(d["a_perp"])),
-                float(np.real(d["a_par"])), float(np.imag(d["a_par"])),
-                float(d.get("alpha3_scale", 0.0)))
+    """d["table"] (optional): [n_theta][6] scattering-plane elements S11 S12
+    S22 S33 S34 S44 at Theta uniform on [0, pi] (reading T1); the array is
+    kept alive on the returned structure."""
+    out = Dust(float(d["kappa_sca"]), float(d["kappa_abs"]),
+               float(np.real(d["a_perp"])), float(np.imag(d["a_perp"])),
+               float(np.real(d["a_par"])), float(np.imag(d["a_par"])),
+               float(d.get("alpha3_scale", 0.0)), 0, None)
+    if d.get("table") is not None:
+        Z = np.ascontiguousarray(d["table"], dtype=np.float64)
+        assert Z.ndim == 2 and Z.shape[1] == 6
+        out.n_theta = Z.shape[0]
+        out.Z = Z.ctypes.data_as(C.POINTER(C.c_double))
+        out._keep = Z
+    return out
 
 
 def make_source(s, B=None) -> Source:

@@ -35,6 +35,19 @@
  *     and a camera ray runs through the periodic copies of the grid from the
  *     open face where it enters to the open face where it leaves.
  *  R9 orthographic camera, image x along phi_hat, y along -theta_hat.
+ *  T1 tabulated optical properties (Sec. 2.2: user-defined interpolation
+ *     tables): a medium of randomly oriented grains with mirror symmetry
+ *     (or spheres), whose scattering-plane Mueller matrix has the block form
+ *     [[S11,S12,0,0],[S12,S22,0,0],[0,0,S33,S34],[0,0,-S34,S44]] of the
+ *     scattering angle only (Bohren & Huffman's convention: Q along the
+ *     scattering plane, here with V as in R10, so S34 = Im(S2 conj(S1)) for
+ *     amplitude functions S2 (parallel) and S1 (perpendicular)); tabulated at
+ *     Theta uniform on [0, pi], linear in cos Theta between nodes, normalised
+ *     so that the solid-angle integral of S11 is 1; scalar extinction.
+ *  T2 sampling of a tabulated scattering (Sec. 2.2): envelope rejection,
+ *     the envelope on each node interval the larger S11 of its two nodes
+ *     times (I + sqrt(Q^2+U^2)); draws per trial: interval (by the envelope's
+ *     cumulative mass), cos Theta uniform in the interval, azimuth, accept.
  *  E1 thermal emission of the dust (Sec. 2.2, the alpha_abs B term of eq.
  *     polarized-rt): the absorption matrix is kappa_abs/kappa_ext times the
  *     extinction matrix, so a cell emits rho kappa_abs (alpha1, alpha2, 0, 0) B
@@ -214,8 +227,10 @@ void kpo_rotate_stokes(double eta, const double s[4], double out[4]) {
 /* ------------------------------------------------------------------------ */
 /* Dipole grain optics (reading R4).                                         */
 /* ------------------------------------------------------------------------ */
+static int is_table(const kpo_dust *d) { return d->n_theta >= 2 && d->Z != NULL; }
+
 static int is_sphere(const kpo_dust *d) {
-  return d->a_perp_re == d->a_par_re && d->a_perp_im == d->a_par_im;
+  return is_table(d) || (d->a_perp_re == d->a_par_re && d->a_perp_im == d->a_par_im);
 }
 
 /* Dimensionless extinction coefficients alpha_1..3 of the transfer equation
@@ -273,8 +288,13 @@ static void mueller_grain(const kpo_dust *d, const double mg[3], const double ng
 
 /* P(m; n) s with both Stokes vectors in lab bases: into the grain frame by
  * quaternion + eta rotation, Mueller there, and back (Sec. 2.1-2.2). */
+static double table_norm(const kpo_dust *d);
+static void table_mueller_lab(const kpo_dust *d, double N, const double m[3], const double n[3],
+                              const double s[4], double out[4]);
+
 void kpo_mueller_lab(const kpo_dust *d, const double q[4], const double m[3],
                      const double n[3], const double s[4], double out[4]) {
+  if (is_table(d)) { table_mueller_lab(d, table_norm(d), m, n, s, out); return; }
   double ng[3], mg[3], sg[4], og[4];
   kpo_to_grain(q, n, ng);
   kpo_to_grain(q, m, mg);
@@ -306,10 +326,114 @@ static double scatter_weight_grain(const kpo_dust *d, const double ng[3], const 
 
 double kpo_scatter_weight(const kpo_dust *d, const double q[4], const double n[3],
                           const double s[4]) {
+  if (is_table(d)) return s[0];  /* T1: the scattered power does not depend on polarisation */
   double ng[3], sg[4];
   kpo_to_grain(q, n, ng);
   kpo_rotate_stokes(eta_pair(q, n, ng), s, sg);
   return scatter_weight_grain(d, ng, sg);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tabulated scattering matrices (Sec. 2.2: optical properties given as      */
+/* interpolation tables; readings T1, T2).                                   */
+/* ------------------------------------------------------------------------ */
+static double table_mu(const kpo_dust *d, int j) { return cos(j * PI_ / (d->n_theta - 1)); }
+
+/* 2 pi times the integral of the interpolated S11 over cos Theta (the
+ * trapezoid rule, exact for a function linear in cos Theta on each interval) */
+static double table_norm(const kpo_dust *d) {
+  double sum = 0.0;
+  for (int j = 0; j + 1 < d->n_theta; ++j)
+    sum += 0.5 * (d->Z[6 * j] + d->Z[6 * (j + 1)]) * (table_mu(d, j) - table_mu(d, j + 1));
+  return 2.0 * PI_ * sum;
+}
+
+/* the six elements at cos Theta = mu, divided by the normalisation N
+ * (bisection for the interval mu_{j+1} <= mu <= mu_j, then linear in mu) */
+static void table_at(const kpo_dust *d, double N, double mu, double z[6]) {
+  int lo = 0, hi = d->n_theta - 1;
+  if (mu > 1.0) mu = 1.0;
+  if (mu < -1.0) mu = -1.0;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) / 2;
+    if (table_mu(d, mid) >= mu) lo = mid; else hi = mid;
+  }
+  double ma = table_mu(d, lo), mb = table_mu(d, hi);
+  double t = ma > mb ? (ma - mu) / (ma - mb) : 0.0;
+  for (int k = 0; k < 6; ++k) z[k] = ((1.0 - t) * d->Z[6 * lo + k] + t * d->Z[6 * hi + k]) / N;
+}
+
+/* P(m; n) s for tabulated grains: s in the lab basis of n, into the
+ * scattering-plane basis (e_par, e_perp) with e_perp = n x m / |n x m| and
+ * e_par = e_perp x n (e_perp = phi_hat of n when m = +-n), the block matrix,
+ * then from (e_perp x m, e_perp) to the lab basis of m. */
+static void table_mueller_lab(const kpo_dust *d, double N, const double m[3], const double n[3],
+                              const double s[4], double out[4]) {
+  double thn[3], phn[3], thm[3], phm[3], w[3], ep[3], ea[3], eb[3];
+  kpo_basis(n, thn, phn);
+  kpo_basis(m, thm, phm);
+  cross3(n, m, w);
+  double w2 = dot3(w, w);
+  if (w2 > 1e-24) {
+    double r = sqrt(w2);
+    for (int k = 0; k < 3; ++k) ep[k] = w[k] / r;
+  } else {
+    for (int k = 0; k < 3; ++k) ep[k] = phn[k];
+  }
+  cross3(ep, n, ea);
+  double psi = atan2(dot3(ea, phn), dot3(ea, thn));
+  double sp[4];
+  kpo_rotate_stokes(psi, s, sp);
+  double z[6];
+  table_at(d, N, dot3(n, m), z);
+  double so[4] = {z[0] * sp[0] + z[1] * sp[1], z[1] * sp[0] + z[2] * sp[1],
+                  z[3] * sp[2] + z[4] * sp[3], -z[4] * sp[2] + z[5] * sp[3]};
+  cross3(ep, m, eb);
+  double chi = atan2(dot3(eb, phm), dot3(eb, thm));
+  kpo_rotate_stokes(-chi, so, out);
+}
+
+/* Cumulative envelope mass over the node intervals (reading T2):
+ * cum[0] = 0, cum[j+1] = cum[j] + max(S11_j, S11_{j+1}) / N (mu_j - mu_{j+1}). */
+static void table_envelope(const kpo_dust *d, double N, double *cum) {
+  cum[0] = 0.0;
+  for (int j = 0; j + 1 < d->n_theta; ++j)
+    cum[j + 1] = cum[j] + fmax(d->Z[6 * j], d->Z[6 * (j + 1)]) / N * (table_mu(d, j) - table_mu(d, j + 1));
+}
+
+static int scatter_event_table(const kpo_dust *d, double N, const double *cum, const double n[3],
+                               const double s[4], rng_t *rng, int64_t *trials, double m_out[3],
+                               double s_out[4]) {
+  double th[3], ph[3];
+  kpo_basis(n, th, ph);
+  double plin = sqrt(s[1] * s[1] + s[2] * s[2]);
+  int nt = d->n_theta;
+  for (int trial = 0; trial < 100000; ++trial) {
+    double u1 = draw(rng), u2 = draw(rng), u3 = draw(rng), u4 = draw(rng);
+    ++*trials;
+    double target = u1 * cum[nt - 1];
+    int j = 0;
+    while (j < nt - 2 && cum[j + 1] <= target) ++j;
+    double ma = table_mu(d, j), mb = table_mu(d, j + 1);
+    double mu = ma + u2 * (mb - ma);
+    double phi = 2.0 * PI_ * u3;
+    double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+    double m[3];
+    for (int k = 0; k < 3; ++k) m[k] = mu * n[k] + st * (cos(phi) * th[k] + sin(phi) * ph[k]);
+    double nm = sqrt(dot3(m, m));
+    for (int k = 0; k < 3; ++k) m[k] /= nm;
+    double o[4];
+    table_mueller_lab(d, N, m, n, s, o);
+    double env = fmax(d->Z[6 * j], d->Z[6 * (j + 1)]) / N * (s[0] + plin);
+    if (o[0] > env * (1.0 + 1e-9)) return -1;
+    if (u4 * env <= o[0]) {
+      double scale = s[0] / o[0];
+      for (int k = 0; k < 4; ++k) s_out[k] = o[k] * scale;
+      m_out[0] = m[0]; m_out[1] = m[1]; m_out[2] = m[2];
+      return 0;
+    }
+  }
+  return -1;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -482,9 +606,10 @@ static void dir_from(double mu, double phi, double n[3]) {
  * accept if u * bound <= [P s]_I (reading R6), rescale to the scattered power
  * (reading R7), back to the lab frame.  Returns 0, or -1 if the bound is
  * exceeded or no proposal is accepted within 100000 trials. */
-static int scatter_event(const kpo_dust *d, const double q[4], const double n[3],
-                         const double s[4], rng_t *rng, int64_t *trials,
+static int scatter_event(const kpo_dust *d, double tab_norm, const double *tab_cum, const double q[4],
+                         const double n[3], const double s[4], rng_t *rng, int64_t *trials,
                          double m_out[3], double s_out[4]) {
+  if (is_table(d)) return scatter_event_table(d, tab_norm, tab_cum, n, s, rng, trials, m_out, s_out);
   double ng[3], sg[4];
   kpo_to_grain(q, n, ng);
   kpo_rotate_stokes(eta_pair(q, n, ng), s, sg);
@@ -519,7 +644,15 @@ int kpo_scatter_sample(const kpo_dust *d, const double q[4], const double n[3],
                        int64_t *trials) {
   rng_t r = {{seed, lam}, packet, first_draw, 0, 0, {0, 0, 0, 0}};
   *trials = 0;
-  return scatter_event(d, q, n, s, &r, trials, m_out, s_out);
+  double *cum = NULL, N = 0.0;
+  if (is_table(d)) {
+    N = table_norm(d);
+    cum = malloc(sizeof(double) * (size_t)d->n_theta);
+    table_envelope(d, N, cum);
+  }
+  int rc = scatter_event(d, N, cum, q, n, s, &r, trials, m_out, s_out);
+  free(cum);
+  return rc;
 }
 
 typedef struct {
@@ -536,7 +669,16 @@ typedef struct {
   double *S;             /* [cell][view][4] or NULL */
   const double *cdf;     /* thermal emission: running sum of cell luminosities */
   double *peel;          /* peel-off images [view][4][npy][npx] or NULL */
+  double tab_norm;       /* tabulated scattering: 2 pi times the integral of S11 over cos Theta */
+  const double *tab_cum; /* ... and the cumulative envelope mass [n_theta] */
 } run_t;
+
+/* P(m; n) s (lab bases) with the run's table normalisation */
+static void mueller_run(const run_t *R, const double q[4], const double m[3], const double n[3],
+                        const double s[4], double out[4]) {
+  if (is_table(R->d)) table_mueller_lab(R->d, R->tab_norm, m, n, s, out);
+  else kpo_mueller_lab(R->d, q, m, n, s, out);
+}
 
 /* Running sum over cells (flat order) of the thermal luminosity
  * 4 pi rho kappa_abs B V of each cell (reading E1); NULL if it is zero. */
@@ -650,7 +792,7 @@ static void peel_off(const run_t *R, const gpos_t *at, const double q_ev[4], con
     if (!(fx >= 0.0 && fx < npx && fy >= 0.0 && fy < npy)) continue;
     int ix = (int)fx, iy = (int)fy;
     double st[4];
-    kpo_mueller_lab(d, q_ev, om, n, s, st);
+    mueller_run(R, q_ev, om, n, s, st);
     gpos_t p = *at;
     while (1) {
       int axis;
@@ -762,7 +904,7 @@ static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *s
       if (R->S && kbar > 0.0) {
         for (int v = 0; v < R->n_views; ++v) {
           double pv[4];
-          kpo_mueller_lab(d, q, R->vdir[v], n, jl, pv);
+          mueller_run(R, q, R->vdir[v], n, jl, pv);
           double *dst = R->S + (c * R->n_views + v) * 4;
           for (int k = 0; k < 4; ++k) atomic_add(dst + k, kbar / vol * pv[k]);
         }
@@ -773,7 +915,7 @@ static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *s
       move_inside(&p, n, len / g->dx);
       if (R->peel) peel_off(R, &p, q, n, s);
       double m[3], i_in = s[0];
-      if (scatter_event(d, q, n, s, &rng, &st->trials, m, s) != 0) {
+      if (scatter_event(d, R->tab_norm, R->tab_cum, q, n, s, &rng, &st->trials, m, s) != 0) {
         end = KPO_END_NUMERIC;
         st->numeric++;
         break;
@@ -846,6 +988,13 @@ static int check_inputs(const kpo_grid *g, const kpo_dust *d, const kpo_source *
   if (g->nx <= 0 || g->ny <= 0 || g->nz <= 0 || !(g->dx > 0.0)) return -1;
   if (!(d->kappa_sca >= 0.0) || !(d->kappa_abs >= 0.0)) return -1;
   if (!is_sphere(d) && !(2.0 * d->a_perp_im + d->a_par_im > 0.0)) return -1;
+  if (d->n_theta != 0) {
+    if (d->n_theta < 2 || !d->Z) return -1;
+    for (int j = 0; j < d->n_theta; ++j)
+      for (int k = 0; k < 6; ++k)
+        if (!isfinite(d->Z[6 * j + k]) || fabs(d->Z[6 * j + k]) > d->Z[6 * j]) return -1;
+    if (!(table_norm(d) > 0.0)) return -1;
+  }
   if (src->kind != 0 && src->kind != 1 && src->kind != 2) return -1;
   if (src->kind == 2 && !src->B) return -1;
   return 0;
@@ -867,7 +1016,13 @@ static int transport_impl(const kpo_grid *g, const float *rho, const float *bhat
     vdir = malloc(sizeof(double[3]) * (size_t)n_views);
     for (int v = 0; v < n_views; ++v) view_dir(&views[v], vdir[v]);
   }
-  run_t R = {g, rho, bhat, d, src, o, lam, n_total, n_views, views, vdir, S, cdf, peel};
+  double *cum = NULL, N = 0.0;
+  if (is_table(d)) {
+    N = table_norm(d);
+    cum = malloc(sizeof(double) * (size_t)d->n_theta);
+    table_envelope(d, N, cum);
+  }
+  run_t R = {g, rho, bhat, d, src, o, lam, n_total, n_views, views, vdir, S, cdf, peel, N, cum};
   kpo_stats total;
   memset(&total, 0, sizeof total);
   int nth = o->nthreads;
@@ -884,6 +1039,7 @@ static int transport_impl(const kpo_grid *g, const float *rho, const float *bhat
   if (stats) stats_add(stats, &total);
   free(vdir);
   free(cdf);
+  free(cum);
   return 0;
 }
 
@@ -914,7 +1070,13 @@ int kpo_trace_packets(const kpo_grid *g, const float *rho, const float *bhat,
   if (check_inputs(g, d, src) || !o || !ids || !traces || n_total == 0) return -1;
   double *cdf = NULL;
   if (src->kind == 2 && !(cdf = emission_cdf(g, rho, d, src->B))) return -1;
-  run_t R = {g, rho, bhat, d, src, o, lam, n_total, 0, NULL, NULL, NULL, cdf, NULL};
+  double *cum = NULL, N = 0.0;
+  if (is_table(d)) {
+    N = table_norm(d);
+    cum = malloc(sizeof(double) * (size_t)d->n_theta);
+    table_envelope(d, N, cum);
+  }
+  run_t R = {g, rho, bhat, d, src, o, lam, n_total, 0, NULL, NULL, NULL, cdf, NULL, N, cum};
   int nth = o->nthreads;
 #pragma omp parallel num_threads(nth > 0 ? nth : omp_get_max_threads())
   {
@@ -924,6 +1086,7 @@ int kpo_trace_packets(const kpo_grid *g, const float *rho, const float *bhat,
     for (int64_t k = 0; k < (int64_t)n_ids; ++k) run_packet(&R, ids[k], &traces[k], &local);
   }
   free(cdf);
+  free(cum);
   return 0;
 }
 

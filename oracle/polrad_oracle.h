@@ -43,6 +43,13 @@ typedef struct {
   double a_perp_re, a_perp_im;  /* dipole polarizability across the symmetry axis */
   double a_par_re, a_par_im;    /* dipole polarizability along the symmetry axis  */
   double alpha3_scale;          /* artificial U-V extinction term: alpha3 = scale*alpha2 */
+  /* tabulated scattering (reading T1), or n_theta = 0 for the dipole: the
+   * scattering-plane matrix elements S11 S12 S22 S33 S34 S44 (any common
+   * scale) at Theta_j = j pi / (n_theta - 1), j = 0..n_theta-1, linear in
+   * cos Theta between nodes; the extinction is then scalar (the polarizabilities
+   * are not used) */
+  int32_t n_theta;
+  const double *Z;              /* [n_theta][6] */
 } kpo_dust;
 
 typedef struct {

@@ -65,6 +65,36 @@ def oblate_dust(kappa_ext: float, albedo: float, m=2.30 + 0.0228j, aspect=2.0,
                 a_perp=complex(ap), a_par=complex(aa), alpha3_scale=alpha3_scale)
 
 
+def table_nodes(n_theta: int) -> np.ndarray:
+    """cos Theta at the nodes of a scattering table: Theta uniform on [0, pi]."""
+    return np.cos(np.linspace(0.0, math.pi, int(n_theta)))
+
+
+def hg_table(g=0.5, p_lin=0.5, p_circ=0.2, n_theta=361) -> np.ndarray:
+    """An analytic scattering-plane table [n_theta][6] (S11 S12 S22 S33 S34
+    S44): a Henyey-Greenstein S11 of asymmetry g with Rayleigh-shaped
+    polarisation of peak p_lin, a circular term of peak p_circ (S34), and
+    S22 = S11, S44 = S33 (S12^2 + S33^2 + S34^2 <= S11^2 when
+    p_lin^2 + p_circ^2 <= 1)."""
+    mu = table_nodes(n_theta)
+    s11 = (1.0 - g * g) / (1.0 + g * g - 2.0 * g * mu) ** 1.5
+    f = (1.0 - mu * mu) / (1.0 + mu * mu)
+    c = 2.0 * mu / (1.0 + mu * mu)
+    return np.stack([s11, -p_lin * s11 * f, s11, s11 * c, p_circ * s11 * f, s11 * c], axis=1)
+
+
+def rayleigh_table(n_theta=181) -> np.ndarray:
+    """The Rayleigh scattering-plane table (amplitude functions S1 = 1,
+    S2 = cos Theta), any scale."""
+    mu = table_nodes(n_theta)
+    return np.stack([1 + mu * mu, mu * mu - 1, 1 + mu * mu, 2 * mu, 0 * mu, 2 * mu], axis=1)
+
+
+def table_dust(kappa_ext: float, albedo: float, table: np.ndarray) -> dict:
+    """Grains with a tabulated scattering matrix and scalar extinction."""
+    return dict(sphere_dust(kappa_ext, albedo), table=np.ascontiguousarray(table, dtype=np.float64))
+
+
 def default_opts(seed: int) -> dict:
     return dict(seed=int(seed), rr_wmin=1e-3, rr_psurv=0.1, max_events=10000)
 
@@ -111,6 +141,17 @@ def uniform_sphere(n=32, packets=100_000, albedo=1.0, tau_radius=1.0, seed=0,
                 source=dict(kind=0, pos=(0.0, 0.0, 0.0), dir=(0.0, 0.0, 1.0), lum=1.0),
                 views=views if views is not None else [view(90.0, 0.0, npix)],
                 packets=[int(packets)], opts=default_opts(seed), precision="f64")
+
+
+def table_sphere(n=32, packets=100_000, albedo=1.0, tau_radius=1.0, g=0.5, seed=11,
+                 views=None, npix=32, n_theta=361) -> dict:
+    """The uniform sphere of uniform_sphere with grains of tabulated
+    scattering (hg_table of asymmetry g)."""
+    cfg = uniform_sphere(n=n, packets=packets, albedo=albedo, tau_radius=tau_radius, seed=seed,
+                         views=views, npix=npix)
+    cfg["name"] = f"table_sphere{n}"
+    cfg["dust"] = [table_dust(tau_radius, albedo, hg_table(g, n_theta=n_theta))]
+    return cfg
 
 
 def slab_clump(n=128, packets=10_000_000, seed=1, npix=None) -> dict:
