@@ -233,6 +233,28 @@ kp_status kp_set_grid_device(kp_ctx *ctx, const kp_grid *grid, const float *d_rh
  * n_lambda (1..1024) dust records, one per wavelength (copied).  KP_ERR_ARG
  * for negative or non-finite opacities or polarizabilities. */
 kp_status kp_set_dust(kp_ctx *ctx, int32_t n_lambda, const kp_dust *dust);
+/* Tabulated scattering for every wavelength (Sec. 2.2: the differential
+ * cross section and Mueller matrix given by the user as interpolation
+ * tables).  Z[n_lambda][n_theta][6] (host, FP64, copied) holds the
+ * scattering-plane elements S11 S12 S22 S33 S34 S44 of randomly oriented
+ * grains (or spheres) at the scattering angles Theta_j = j pi / (n_theta-1),
+ * in any common scale per wavelength; the matrix is
+ * [[S11,S12,0,0],[S12,S22,0,0],[0,0,S33,S34],[0,0,-S34,S44]] with Q along the
+ * scattering plane (Bohren & Huffman), V as in this header's Stokes
+ * convention (S34 = Im(S2 conj(S1)) for amplitude functions S2 parallel, S1
+ * perpendicular), linear in cos Theta between nodes, normalised by the
+ * library to unit solid-angle integral of S11.  With tables the extinction
+ * is scalar (kappa_sca + kappa_abs of kp_dust; the polarizabilities are not
+ * used and alignment directions are ignored), scattering directions are
+ * drawn from the table, and step 1 tallies the per-view source of Sec. 2.3
+ * (eq. scat-disc-sum: one Stokes vector per cell and camera, [n_lambda]
+ * [ncell][n_views][4] FP64, read with kp_get_view_tally) instead of the
+ * coherency, which is exact only for dipoles; kp_set_views then invalidates
+ * the tally.  n_lambda must equal kp_set_dust's (called first; kp_set_dust
+ * discards the tables); 2 <= n_theta <= 65536; every |S_ij| <= S11 at every
+ * node, finite, with a positive integral (KP_ERR_ARG otherwise).
+ * n_lambda = 0 with Z = NULL returns to dipole grains. */
+kp_status kp_set_dust_tables(kp_ctx *ctx, int32_t n_lambda, int32_t n_theta, const double *Z);
 /* The radiation source whose packets are emitted (Sec. 2.2: packets are
  * generated and given an exponentially distributed scattering optical
  * depth); copied.  KP_ERR_ARG for an unknown kind, a non-positive
@@ -316,6 +338,13 @@ kp_status kp_get_peel_images(kp_ctx *ctx, double *host_out, size_t n);
  * projection: components xx yy zz xy xz yz and the imaginary yz zx xy
  * parts), per unit cell volume times dx^3; n must equal that size. */
 kp_status kp_get_tally(kp_ctx *ctx, double *host_out, size_t n);
+/* Per-view scattering source of the last step 1 with tabulated grains (Sec.
+ * 2.3, eq. scat-disc-sum: the emissivity toward each camera per unit volume
+ * and solid angle, in that camera's basis), [n_lambda][ncell][n_views][4]
+ * FP64, copied to host memory; n must equal that size (KP_ERR_ARG), and
+ * KP_ERR_STATE when the last step 1 tallied coherencies (dipole grains,
+ * kp_get_tally) or formed none. */
+kp_status kp_get_view_tally(kp_ctx *ctx, double *host_out, size_t n);
 /* Counters of the last step 1 and step 2 (Sec. 2.2 packet events; kp_stats
  * above), copied to *out. */
 kp_status kp_get_stats(kp_ctx *ctx, kp_stats *out);

@@ -114,6 +114,17 @@ struct kp_ctx {
   size_t em_partial_n = 0;
   bool em_ready = false;  // tables match the current grid, dust and source function
   std::vector<double> em_L;
+  // tabulated scattering of every wavelength (kp_set_dust_tables): one
+  // device array holding the normalised tables [n_lambda][n][6], the node
+  // cosines [n] and the cumulative envelope masses [n_lambda][n]
+  bool have_tables = false;
+  int tab_nt = 0;
+  double* d_tab = nullptr;
+  size_t tab_n = 0;
+  // the last step 1 tallied the per-view source [lambda][cell][view][4]
+  // (tabulated grains) instead of coherency blocks
+  bool tally_views = false;
+  int tally_nv = 0;
   // peel-off images of the last step 1 run with peel_off
   double* d_peel = nullptr;
   size_t peel_n = 0;
@@ -215,7 +226,14 @@ void fill_dust(const kp_ctx* ctx, const uint64_t* counts, std::vector<DustDev>& 
     o.ka_cell = d.kappa_abs * dx;
     o.ke_cell = (d.kappa_sca + d.kappa_abs) * dx;
     o.kext = d.kappa_sca + d.kappa_abs;
-    o.sphere = is_sphere(d) ? 1 : 0;
+    o.sphere = (is_sphere(d) || ctx->have_tables) ? 1 : 0;
+    if (ctx->have_tables) {
+      const size_t nl = ctx->dust.size(), nt = (size_t)ctx->tab_nt;
+      o.tab_n = ctx->tab_nt;
+      o.tab = ctx->d_tab + l * nt * 6;
+      o.tab_mu = ctx->d_tab + nl * nt * 6;
+      o.tab_cum = ctx->d_tab + nl * nt * 6 + nt + l * nt;
+    }
     if (o.sphere) {
       o.ap_re = o.aa_re = 1.0;
       o.ap_im = o.aa_im = 0.0;
@@ -290,9 +308,13 @@ kp_status check_ready(kp_ctx* ctx) {
   return KP_OK;
 }
 
+// Step 2.  With user_source the source is the per-view array d_S (the
+// caller's, or the per-view tally of tabulated grains when from_tally),
+// else the coherency tally d_tally; the dust's thermal term is added for a
+// thermal source unless the caller supplied the source.
 kp_status image_launch(kp_ctx* ctx, bool user_source, const double* d_S, double* d_out,
                        int n_lambda, hipStream_t s, const DustDev* d_dust, const ViewDev* d_views,
-                       const double* d_tally) {
+                       const double* d_tally, bool from_tally = false) {
   ImageArgs a{};
   a.rho = ctx->d_rho;
   if (ctx->d_bhat) {
@@ -312,14 +334,17 @@ kp_status image_launch(kp_ctx* ctx, bool user_source, const double* d_S, double*
   a.user_S = d_S;
   a.images = d_out;
   a.ncell = ctx->ncell;
-  a.em_B = (!user_source && ctx->src.kind == 2) ? ctx->d_em_B : nullptr;
+  a.em_B = ((!user_source || from_tally) && ctx->src.kind == 2) ? ctx->d_em_B : nullptr;
   a.boundary = ctx->grid.boundary;
   // every wavelength shares the grain model kind of wavelength 0 for the
   // kernel choice; mixed sphere / non-sphere tables use the general kernel
   bool sphere = true;
   for (int l = 0; l < n_lambda; ++l) sphere = sphere && ctx->hdust[l].sphere;
   KP_HIP(hipEventRecord(ctx->ev[2], s), "event record");
-  KP_HIP(launch_image(a, ctx->d_bhat != nullptr, sphere, user_source, s), "imaging kernel launch");
+  // tabulated grains are randomly oriented: the alignment directions do not
+  // enter their extinction
+  const bool aligned = ctx->d_bhat != nullptr && !ctx->have_tables;
+  KP_HIP(launch_image(a, aligned, sphere, user_source, s), "imaging kernel launch");
   KP_HIP(hipEventRecord(ctx->ev[3], s), "event record");
   return KP_OK;
 }
@@ -413,15 +438,19 @@ kp_status transport_launch(kp_ctx* ctx, const kp_opts* o, uint64_t total, const 
                            hipStream_t s) {
   const int nl = (int)ctx->dust.size();
   const bool all_sphere = all_spheres(ctx);
+  const bool tab = ctx->have_tables;
   const size_t trace_need = (size_t)nl * o->trace_packets;
-  KP_HIP(launch_tally_init(b.tally, ctx->d_rho, ctx->d_bhat,
-                           ctx->d_bhat ? ctx->d_bhat + ctx->ncell : nullptr,
-                           ctx->d_bhat ? ctx->d_bhat + 2 * ctx->ncell : nullptr, ctx->ncell, nl, all_sphere, s),
-         "tally initialisation");
+  const int npx = ctx->views[0].npx, npy = ctx->views[0].npy, nv = (int)ctx->views.size();
+  if (tab)
+    KP_HIP(launch_fill_zero(b.tally, (size_t)nl * ctx->ncell * nv * 4 * sizeof(double), s), "tally clear");
+  else
+    KP_HIP(launch_tally_init(b.tally, ctx->d_rho, ctx->d_bhat,
+                             ctx->d_bhat ? ctx->d_bhat + ctx->ncell : nullptr,
+                             ctx->d_bhat ? ctx->d_bhat + 2 * ctx->ncell : nullptr, ctx->ncell, nl, all_sphere, s),
+           "tally initialisation");
   KP_HIP(launch_fill_zero(b.stats, sizeof(StatsDev), s), "stats clear");
   KP_HIP(launch_fill_zero(b.counter, sizeof(unsigned long long), s), "counter clear");
   if (trace_need) KP_HIP(launch_fill_zero(b.traces, trace_need * sizeof(TraceDev), s), "trace clear");
-  const int npx = ctx->views[0].npx, npy = ctx->views[0].npy, nv = (int)ctx->views.size();
   if (b.peel)
     KP_HIP(launch_fill_zero(b.peel, (size_t)nl * nv * 4 * npx * npy * sizeof(double), s), "peel-off clear");
 
@@ -458,23 +487,23 @@ kp_status transport_launch(kp_ctx* ctx, const kp_opts* o, uint64_t total, const 
     a.em_guide = ctx->d_em_guide;
   }
   a.boundary = ctx->grid.boundary;
+  a.views = b.views;
+  a.n_views = nv;
   if (b.peel) {
-    a.views = b.views;
-    a.n_views = nv;
     a.npx = npx;
     a.npy = npy;
     a.peel = b.peel;
   }
 
-  const bool sphere = all_sphere;
-  const bool aligned = ctx->d_bhat != nullptr;
+  const bool sphere = all_sphere || tab;
+  const bool aligned = ctx->d_bhat != nullptr && !tab;
   // automatic precision: FP64 polarisation arithmetic for dichroic (aligned,
   // non-spherical) grains, FP32 otherwise
   const bool fp64 = o->transport_fp64 == 1 || (o->transport_fp64 == 0 && aligned && !sphere);
   const int bs = o->block_size ? o->block_size : 256;
   int bpc = o->blocks_per_cu;
   if (bpc == 0) {
-    bpc = transport_max_blocks_per_cu(fp64, aligned, sphere, b.peel != nullptr, bs);
+    bpc = transport_max_blocks_per_cu(fp64, aligned, sphere, b.peel != nullptr, tab, bs);
     if (bpc < 1) bpc = 1;
     if (bpc > 8) bpc = 8;
   }
@@ -482,7 +511,7 @@ kp_status transport_launch(kp_ctx* ctx, const kp_opts* o, uint64_t total, const 
   const uint64_t need_blocks = (total + bs - 1) / bs;
   if (blocks > need_blocks) blocks = need_blocks;
   KP_HIP(hipEventRecord(ctx->ev[0], s), "event record");
-  KP_HIP(launch_transport(a, fp64, aligned, sphere, b.peel != nullptr, (int)blocks, bs, s),
+  KP_HIP(launch_transport(a, fp64, aligned, sphere, b.peel != nullptr, tab, (int)blocks, bs, s),
          "transport kernel launch");
   KP_HIP(hipEventRecord(ctx->ev[1], s), "event record");
   KP_HIP(hipStreamSynchronize(s), "transport kernel");
@@ -548,7 +577,8 @@ void kp_destroy(kp_ctx* ctx) {
   for (void* p : {(void*)ctx->d_views, (void*)ctx->d_dust, (void*)ctx->d_tally,
                   (void*)ctx->d_images, (void*)ctx->d_stats, (void*)ctx->d_counter,
                   (void*)ctx->d_bad, (void*)ctx->d_traces, (void*)ctx->d_em_cdf,
-                  (void*)ctx->d_em_guide, (void*)ctx->d_em_partial, (void*)ctx->d_peel})
+                  (void*)ctx->d_em_guide, (void*)ctx->d_em_partial, (void*)ctx->d_peel,
+                  (void*)ctx->d_tab})
     if (p) (void)hipFree(p);
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
@@ -633,6 +663,54 @@ kp_status kp_set_dust(kp_ctx* ctx, int32_t n_lambda, const kp_dust* d) {
   ctx->have_tally = false;
   ctx->have_images = false;
   ctx->em_ready = false;
+  ctx->have_tables = false;  // tables belong to the dust they were given for
+  return KP_OK;
+}
+
+kp_status kp_set_dust_tables(kp_ctx* ctx, int32_t n_lambda, int32_t n_theta, const double* Z) {
+  if (!ctx) return KP_ERR_ARG;
+  if (n_lambda == 0 && !Z) {
+    ctx->have_tables = false;
+    ctx->have_tally = false;
+    ctx->have_images = false;
+    return KP_OK;
+  }
+  if (ctx->dust.empty()) return fail(ctx, KP_ERR_STATE, "kp_set_dust has not been called");
+  if (n_lambda != (int)ctx->dust.size() || !Z)
+    return fail(ctx, KP_ERR_ARG, "tables for %d wavelengths given, kp_set_dust set %zu", n_lambda, ctx->dust.size());
+  if (n_theta < 2 || n_theta > 65536) return fail(ctx, KP_ERR_ARG, "n_theta must be in 2..65536");
+  const size_t nl = (size_t)n_lambda, nt = (size_t)n_theta;
+  std::vector<double> h(nl * nt * 6 + nt + nl * nt);
+  double* mu = h.data() + nl * nt * 6;
+  double* cum = mu + nt;
+  for (size_t j = 0; j < nt; ++j) mu[j] = std::cos((double)j * M_PI / (double)(nt - 1));
+  for (size_t l = 0; l < nl; ++l) {
+    const double* z = Z + l * nt * 6;
+    for (size_t j = 0; j < nt; ++j)
+      for (int k = 0; k < 6; ++k)
+        if (!std::isfinite(z[6 * j + k]) || std::fabs(z[6 * j + k]) > z[6 * j])
+          return fail(ctx, KP_ERR_ARG, "table %zu, node %zu: element %d is not finite or exceeds S11 in "
+                      "magnitude", l, j, k);
+    // 2 pi times the integral of S11 over cos Theta, exact for S11 linear in
+    // cos Theta on each interval
+    double sum = 0.0;
+    for (size_t j = 0; j + 1 < nt; ++j) sum += 0.5 * (z[6 * j] + z[6 * (j + 1)]) * (mu[j] - mu[j + 1]);
+    const double N = 2.0 * M_PI * sum;
+    if (!(N > 0.0) || !std::isfinite(N)) return fail(ctx, KP_ERR_ARG, "table %zu: S11 integrates to %g", l, N);
+    double* t = h.data() + l * nt * 6;
+    for (size_t i = 0; i < nt * 6; ++i) t[i] = z[i] / N;
+    double* c = cum + l * nt;
+    c[0] = 0.0;
+    for (size_t j = 0; j + 1 < nt; ++j) c[j + 1] = c[j] + std::fmax(t[6 * j], t[6 * (j + 1)]) * (mu[j] - mu[j + 1]);
+  }
+  KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  kp_status st = ensure(ctx, &ctx->d_tab, &ctx->tab_n, h.size(), "table allocation");
+  if (st) return st;
+  KP_HIP(hipMemcpy(ctx->d_tab, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice), "table upload");
+  ctx->tab_nt = n_theta;
+  ctx->have_tables = true;
+  ctx->have_tally = false;
+  ctx->have_images = false;
   return KP_OK;
 }
 
@@ -694,6 +772,7 @@ kp_status kp_set_views(kp_ctx* ctx, int32_t n_views, const kp_view* v) {
   for (int k = 0; k < n_views; ++k) fill_view(v[k], ctx->hviews[k]);
   ctx->have_images = false;
   ctx->peel_valid_n = 0;
+  if (ctx->tally_views) ctx->have_tally = false;  // a per-view tally belongs to its cameras
   return KP_OK;
 }
 
@@ -707,7 +786,8 @@ kp_status kp_transport(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, vo
   const int nl = (int)ctx->dust.size();
   const bool all_sphere = all_spheres(ctx);
   const int ts = tally_stride(all_sphere);
-  const size_t tally_need = (size_t)nl * ctx->ncell * ts;
+  const size_t tally_need = ctx->have_tables ? (size_t)nl * ctx->ncell * ctx->views.size() * 4
+                                             : (size_t)nl * ctx->ncell * ts;
   const size_t trace_need = (size_t)nl * o->trace_packets;
   const size_t peel_need =
       o->peel_off ? (size_t)nl * ctx->views.size() * 4 * ctx->views[0].npx * ctx->views[0].npy : 0;
@@ -729,6 +809,8 @@ kp_status kp_transport(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, vo
   st = transport_launch(ctx, o, total, buf, s);
   if (st == KP_ERR_DEVICE || st == KP_ERR_OOM) return st;
   ctx->peel_valid_n = peel_need;
+  ctx->tally_views = ctx->have_tables;
+  ctx->tally_nv = (int)ctx->views.size();
   ctx->tally_lambda = nl;
   ctx->tally_ts = ts;
   ctx->tally_nc = tally_components(all_sphere);
@@ -749,8 +831,14 @@ kp_status kp_image(kp_ctx* ctx, void* stream) {
   const size_t need = (size_t)nl * ctx->views.size() * 4 * ctx->views[0].npx * ctx->views[0].npy;
   if ((st = ensure(ctx, &ctx->d_images, &ctx->images_n, need, "image allocation"))) return st;
   if ((st = upload_small(ctx, s))) return st;
-  if ((st = image_launch(ctx, false, nullptr, ctx->d_images, nl, s, ctx->d_dust, ctx->d_views,
-                         ctx->d_tally))) return st;
+  if (ctx->tally_views) {
+    if (!ctx->have_tables || ctx->tally_nv != (int)ctx->views.size())
+      return fail(ctx, KP_ERR_STATE, "the per-view tally no longer matches the dust tables or cameras");
+    st = image_launch(ctx, true, ctx->d_tally, ctx->d_images, nl, s, ctx->d_dust, ctx->d_views, nullptr, true);
+  } else {
+    st = image_launch(ctx, false, nullptr, ctx->d_images, nl, s, ctx->d_dust, ctx->d_views, ctx->d_tally);
+  }
+  if (st) return st;
   KP_HIP(hipStreamSynchronize(s), "imaging kernel");
   float ms = 0.0f;
   KP_HIP(hipEventElapsedTime(&ms, ctx->ev[2], ctx->ev[3]), "event timing");
@@ -786,11 +874,13 @@ kp_status kp_run_static(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, d
   const size_t img_need = (size_t)nl * nv * 4 * ctx->views[0].npx * ctx->views[0].npy;
   if (!d_images || n != img_need) return fail(ctx, KP_ERR_ARG, "destination must hold %zu doubles", img_need);
   const bool all_sphere = all_spheres(ctx);
-  const size_t tally_bytes = (size_t)nl * ctx->ncell * tally_stride(all_sphere) * sizeof(double);
+  const size_t cell_bytes = ctx->have_tables ? (size_t)nv * 4 * sizeof(double)
+                                             : (size_t)tally_stride(all_sphere) * sizeof(double);
+  const size_t tally_bytes = (size_t)nl * ctx->ncell * cell_bytes;
   if (tally_bytes > KP_STATIC_TALLY)
     return fail(ctx, KP_ERR_ARG, "the tally needs %zu bytes, more than the %zu of the static scratch "
-                "(%d wavelengths x %llu cells x %d B): use kp_run", tally_bytes, KP_STATIC_TALLY, nl,
-                (unsigned long long)ctx->ncell, tally_stride(all_sphere) * 8);
+                "(%d wavelengths x %llu cells x %zu B): use kp_run", tally_bytes, KP_STATIC_TALLY, nl,
+                (unsigned long long)ctx->ncell, cell_bytes);
   // head of the scratch: stats at 0, work counter at 256, the dust table at
   // 512, the camera table after it (at most 1024 x 144 B + 4096 x 80 B)
   const size_t dust_off = 512, dust_bytes = (size_t)nl * sizeof(DustDev);
@@ -814,7 +904,9 @@ kp_status kp_run_static(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, d
   const RunBuffers buf{d_dust, d_tally, d_stats, d_counter, nullptr, d_views, nullptr};
   st = transport_launch(ctx, o, total, buf, s);
   if (st == KP_ERR_DEVICE || st == KP_ERR_OOM) return st;
-  kp_status st2 = image_launch(ctx, false, nullptr, d_images, nl, s, d_dust, d_views, d_tally);
+  kp_status st2 = ctx->have_tables
+                      ? image_launch(ctx, true, d_tally, d_images, nl, s, d_dust, d_views, nullptr, true)
+                      : image_launch(ctx, false, nullptr, d_images, nl, s, d_dust, d_views, d_tally);
   if (st2) return st2;
   KP_HIP(hipStreamSynchronize(s), "imaging kernel");
   float ms = 0.0f;
@@ -871,9 +963,23 @@ kp_status kp_get_peel_images(kp_ctx* ctx, double* out, size_t n) {
   return KP_OK;
 }
 
+kp_status kp_get_view_tally(kp_ctx* ctx, double* out, size_t n) {
+  if (!ctx) return KP_ERR_ARG;
+  if (!ctx->have_tally || !ctx->tally_views)
+    return fail(ctx, KP_ERR_STATE, "no per-view tally: the last step 1 (kp_transport with tabulated grains) "
+                "is missing or tallied coherencies");
+  const size_t need = (size_t)ctx->tally_lambda * ctx->ncell * ctx->tally_nv * 4;
+  if (!out || n != need) return fail(ctx, KP_ERR_ARG, "destination must hold %zu doubles", need);
+  KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  KP_HIP(hipMemcpy(out, ctx->d_tally, n * sizeof(double), hipMemcpyDeviceToHost), "tally copy");
+  return KP_OK;
+}
+
 kp_status kp_get_tally(kp_ctx* ctx, double* out, size_t n) {
   if (!ctx) return KP_ERR_ARG;
   if (!ctx->have_tally) return fail(ctx, KP_ERR_STATE, "no tally: call kp_transport first");
+  if (ctx->tally_views)
+    return fail(ctx, KP_ERR_STATE, "tabulated grains tally the per-view source: use kp_get_view_tally");
   const size_t rows = (size_t)ctx->tally_lambda * ctx->ncell;
   const size_t need = rows * 9;
   if (!out || n != need) return fail(ctx, KP_ERR_ARG, "destination must hold %zu doubles", need);

@@ -21,7 +21,15 @@ struct DustDev {
   uint64_t first;    // first global work index of this wavelength
   uint64_t count;    // packets of this wavelength
   int32_t sphere;
-  int32_t pad;
+  int32_t tab_n;     // tabulated scattering: nodes (0 = dipole grains)
+  // tabulated scattering (device arrays): the scattering-plane elements S11
+  // S12 S22 S33 S34 S44 divided by 2 pi times the integral of S11 over cos
+  // Theta [tab_n][6], cos Theta at the nodes [tab_n] (Theta uniform on
+  // [0, pi]), and the cumulative envelope mass [tab_n] (cum[j+1] - cum[j] =
+  // max(S11_j, S11_j+1) (mu_j - mu_j+1), normalised elements)
+  const double* tab;
+  const double* tab_mu;
+  const double* tab_cum;
 };
 
 struct ViewDev {
@@ -71,7 +79,8 @@ struct TransportArgs {
   uint64_t seed;
   double rr_wmin, rr_psurv;
   int max_events;
-  double* tally;  // [lambda][ncell][9]
+  double* tally;  // [lambda][ncell][stride] coherency blocks, or for tabulated
+                  // grains the per-view source [lambda][ncell][view][4]
   uint64_t ncell;
   unsigned long long* counter;
   StatsDev* stats;
@@ -86,8 +95,9 @@ struct TransportArgs {
   const double* em_cdf;
   const uint32_t* em_guide;
   int boundary;          // bit a: axis a periodic
-  // peel-off imaging (the kernels instantiated with it): cameras and the
-  // images [lambda][view][4][npy][npx] the scattering events are added to
+  // cameras (peel-off imaging, and the per-view source of tabulated grains)
+  // and the peel-off images [lambda][view][4][npy][npx] the scattering events
+  // are added to (the kernels instantiated with peel-off)
   const ViewDev* views;
   int n_views, npx, npy;
   double* peel;
@@ -104,7 +114,7 @@ struct ImageArgs {
   const ViewDev* views;
   int n_views, n_lambda, npx, npy;
   const double* tally;  // [lambda][ncell][9]   (coherency source)
-  const double* user_S; // [ncell][view][4]     (per-view source, wavelength 0)
+  const double* user_S; // [lambda][ncell][view][4] per-view source (or null)
   double* images;       // [lambda][view][4][npy][npx]
   uint64_t ncell;
   const float* em_B;    // [lambda][ncell] source function of the dust's thermal
@@ -121,7 +131,7 @@ inline int tally_components(bool sphere) { return sphere ? 6 : 9; }
 inline int tally_stride(bool sphere) { return sphere ? 8 : 16; }
 
 // launchers (kp_kernels.hip)
-hipError_t launch_transport(const TransportArgs& a, bool fp64, bool aligned, bool sphere, bool peel,
+hipError_t launch_transport(const TransportArgs& a, bool fp64, bool aligned, bool sphere, bool peel, bool tab,
                             int blocks, int block_size, hipStream_t s);
 hipError_t launch_image(const ImageArgs& a, bool aligned, bool sphere, bool user_source,
                         hipStream_t s);
@@ -130,7 +140,7 @@ hipError_t launch_tally_init(double* tally, const float* rho, const float* bx, c
                              const float* bz, uint64_t ncell, int n_lambda, bool sphere, hipStream_t s);
 hipError_t launch_validate(const float* rho, const float* bx, const float* by, const float* bz,
                            uint64_t n, unsigned long long* bad, hipStream_t s);
-int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, bool peel, int block_size);
+int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, bool peel, bool tab, int block_size);
 // Thermal emission tables of one wavelength: cdf [ncell], the running sum
 // of fac rho B (fac = 4 pi kappa_abs dx^3) in flat cell order, and its guide
 // table [ncell + 1]; `partial` holds emission_blocks(ncell) doubles of

@@ -492,6 +492,128 @@ __device__ bool scatter(Packet<R>& p, const Quat<R>& q, const Quat<double>& qd,
   return true;
 }
 
+// ---------------------------------------------------------------------------
+// Tabulated scattering (Sec. 2.2: optical properties given as interpolation
+// tables).  The table holds the scattering-plane elements S11 S12 S22 S33
+// S34 S44 of randomly oriented grains, normalised so that S11 integrates to 1
+// over solid angle, at scattering angles uniform on [0, pi]; values are linear
+// in cos Theta between nodes.  FP64 throughout.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void tab_eval(const DustDev& D, double mu, double z[6]) {
+  const int n = D.tab_n;
+  mu = fmin(1.0, fmax(-1.0, mu));
+  // the node interval from the angle, then moved past any rounding at a node
+  int j = (int)(acos(mu) * ((double)(n - 1) * (1.0 / M_PI)));
+  j = j < 0 ? 0 : (j > n - 2 ? n - 2 : j);
+  const double* M = D.tab_mu;
+  while (j > 0 && mu > M[j]) --j;
+  while (j < n - 2 && mu < M[j + 1]) ++j;
+  const double ma = M[j], mb = M[j + 1];
+  const double t = ma > mb ? (ma - mu) / (ma - mb) : 0.0;
+  const double* Z = D.tab + 6 * j;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) z[k] = (1.0 - t) * Z[k] + t * Z[6 + k];
+}
+
+// P(m; n) s per unit solid angle: s in the lab basis of n, the result in the
+// basis (tm, pm) of m.  The scattering plane's normal is e = n x m / |n x m|
+// (phi_hat of n when m = +-n); with a = m . theta_hat_n, b = m . phi_hat_n
+// (|n x m|^2 = a^2 + b^2) the rotation into the plane basis (e x n, e) is
+// cos 2psi = (a^2 - b^2) / |n x m|^2, sin 2psi = 2ab / |n x m|^2, and the
+// rotation out of (e x m, e) into (tm, pm) is by -chi with
+// cos 2chi = ((n.tm)^2 - (n.pm)^2) / |n x m|^2, sin 2chi = 2 (n.tm)(n.pm) /
+// |n x m|^2: no square root or angle is formed.
+__device__ __forceinline__ void tab_toward(const DustDev& D, const V3<double>& n, const double s[4],
+                                           const V3<double>& m, const V3<double>& tm,
+                                           const V3<double>& pm, double out[4]) {
+  V3<double> thn, phn;
+  basis(n, thn, phn);
+  const double a = dot(m, thn), b = dot(m, phn);
+  const double w2 = a * a + b * b;
+  double c2p = 1.0, s2p = 0.0, c2c, s2c;
+  if (w2 > 1e-24) {
+    const double iw = 1.0 / w2;
+    c2p = (a * a - b * b) * iw;
+    s2p = 2.0 * a * b * iw;
+    const double ct = dot(n, tm), cp = dot(n, pm);
+    c2c = (ct * ct - cp * cp) * iw;
+    s2c = 2.0 * ct * cp * iw;
+  } else {
+    const double cc = dot(phn, pm), ss = -dot(phn, tm);
+    c2c = cc * cc - ss * ss;
+    s2c = 2.0 * cc * ss;
+  }
+  const double Qp = c2p * s[1] + s2p * s[2], Up = -s2p * s[1] + c2p * s[2];
+  double z[6];
+  tab_eval(D, dot(n, m), z);
+  const double I = z[0] * s[0] + z[1] * Qp, Q = z[1] * s[0] + z[2] * Qp;
+  const double U = z[3] * Up + z[4] * s[3], V = -z[4] * Up + z[5] * s[3];
+  out[0] = I;
+  out[1] = c2c * Q - s2c * U;
+  out[2] = s2c * Q + c2c * U;
+  out[3] = V;
+}
+
+// Scattering event of tabulated grains: envelope rejection.  Per trial four
+// uniforms: the node interval by the envelope's cumulative mass (the larger
+// S11 of its two nodes times the interval's width in cos Theta), cos Theta
+// uniform inside it, the azimuth, and acceptance of u * max S11 (I + |P_lin|)
+// <= the scattered I.  The total scattered power does not depend on the
+// polarisation, so the scattered state is rescaled to the incident I.
+template <typename R>
+__device__ bool scatter_tab(Packet<R>& p, const DustDev& D, uint64_t seed) {
+  const V3<double> n{p.nx, p.ny, p.nz};
+  V3<double> th, ph;
+  basis(n, th, ph);
+  const double s[4] = {(double)p.I, (double)p.Q, (double)p.U, (double)p.V};
+  const double plin = sqrt(s[1] * s[1] + s[2] * s[2]);
+  const int nt = D.tab_n;
+  const double* cum = D.tab_cum;
+  const double total = cum[nt - 1];
+  for (int trial = 0; trial < 100000; ++trial) {
+    const double u1 = (double)next_uniform(p, seed), u2 = (double)next_uniform(p, seed);
+    const double u3 = (double)next_uniform(p, seed), u4 = (double)next_uniform(p, seed);
+    p.trials++;
+    // the first interval whose cumulative envelope mass exceeds u1 * total
+    const double target = u1 * total;
+    int lo = 0, hi = nt - 2;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (cum[mid + 1] > target) hi = mid;
+      else lo = mid + 1;
+    }
+    const int j = lo;
+    const double ma = D.tab_mu[j], mb = D.tab_mu[j + 1];
+    const double mu = ma + u2 * (mb - ma);
+    double sp, cp;
+    sincospi(2.0 * u3, &sp, &cp);
+    const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+    V3<double> m{mu * n.x + st * (cp * th.x + sp * ph.x), mu * n.y + st * (cp * th.y + sp * ph.y),
+                 mu * n.z + st * (cp * th.z + sp * ph.z)};
+    const double inm = 1.0 / sqrt(dot(m, m));
+    m = V3<double>{m.x * inm, m.y * inm, m.z * inm};
+    V3<double> tm, pm;
+    basis(m, tm, pm);
+    double o[4];
+    tab_toward(D, n, s, m, tm, pm, o);
+    const double env = fmax(D.tab[6 * j], D.tab[6 * (j + 1)]) * (s[0] + plin);
+    if (!(o[0] <= env * (1.0 + 1e-9))) return false;
+    if (u4 * env <= o[0]) {
+      const double scale = s[0] / o[0];
+      p.nx = m.x; p.ny = m.y; p.nz = m.z;
+      p.rnx = 1.0 / p.nx; p.rny = 1.0 / p.ny; p.rnz = 1.0 / p.nz;
+      const R Io = (R)(o[0] * scale);
+      p.e_scat += (double)(Io - p.I);
+      p.I = Io;
+      p.Q = (R)(o[1] * scale);
+      p.U = (R)(o[2] * scale);
+      p.V = (R)(o[3] * scale);
+      return true;
+    }
+  }
+  return false;
+}
+
 template <typename R>
 __device__ uint32_t roulette(Packet<R>& p, const TransportArgs& a);
 
@@ -500,10 +622,11 @@ __device__ uint32_t roulette(Packet<R>& p, const TransportArgs& a);
 // the analytic cell solution of Appendix A, tally of the segment into the
 // scattering source of Sec. 2.3), then a scattering event or the crossing
 // into the next cell, then Russian roulette.  Returns 0 or an end kind.
-template <typename R, bool ALIGNED, bool SPHERE>
+template <typename R, bool ALIGNED, bool SPHERE, bool TAB>
 __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_t& key,
                          R cc[TallyShape<SPHERE>::NC], bool& pending) {
   constexpr int NC = TallyShape<SPHERE>::NC;
+  static_assert(!TAB || (SPHERE && !ALIGNED), "tabulated grains have scalar extinction");
   const uint64_t c = (uint64_t)p.ci + (uint64_t)a.nx * ((uint64_t)p.cj + (uint64_t)a.ny * p.ck);
   p.last = (int64_t)c;
   if (p.events >= a.max_events || p.steps >= KP_MAX_STEPS) {
@@ -599,7 +722,13 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
     }
     p.e_abs += (double)(Ib - p.I);
     if (kb > (R)0) {
-      coherency<R, NC>(n, JI, JQ, JU, JV, kb, cc);
+      if (TAB) {
+        // tabulated grains: the segment's Stokes integral itself (in the lab
+        // basis of n), projected on every camera when it is flushed
+        cc[0] = JI * kb; cc[1] = JQ * kb; cc[2] = JU * kb; cc[3] = JV * kb;
+      } else {
+        coherency<R, NC>(n, JI, JQ, JU, JV, kb, cc);
+      }
       key = (int64_t)((uint64_t)p.lam * a.ncell + c);
       has = true;
     }
@@ -747,12 +876,12 @@ __device__ __forceinline__ void source_toward(const double C9[9], const Quat<dou
 // the grid's edge through the Appendix A extinction of every cell on the way
 // (no source), added to the pixel the event projects to, per unit pixel
 // area.  FP64; open boundaries.
-template <typename R, bool ALIGNED, bool SPHERE>
+template <typename R, bool ALIGNED, bool SPHERE, bool TAB>
 __device__ void peel_off(const Packet<R>& p, const TransportArgs& a, const Quat<double>& q_ev,
                          const DustDev& D) {
   double C9[9];
-  coherency<double, 9>(V3<double>{p.nx, p.ny, p.nz}, (double)p.I, (double)p.Q, (double)p.U, (double)p.V,
-                       1.0, C9);
+  const double s_in[4] = {(double)p.I, (double)p.Q, (double)p.U, (double)p.V};
+  if (!TAB) coherency<double, 9>(V3<double>{p.nx, p.ny, p.nz}, s_in[0], s_in[1], s_in[2], s_in[3], 1.0, C9);
   const double X[3] = {a.x0 + ((double)p.ci + p.fx) * a.dx, a.y0 + ((double)p.cj + p.fy) * a.dx,
                        a.z0 + ((double)p.ck + p.fz) * a.dx};
   const int nn[3] = {a.nx, a.ny, a.nz};
@@ -766,8 +895,12 @@ __device__ void peel_off(const Packet<R>& p, const TransportArgs& a, const Quat<
     const int ix = (int)fxp, iy = (int)fyp;
     const V3<double> Om{vw.ox, vw.oy, vw.oz};
     double st[4];
-    source_toward<SPHERE>(C9, q_ev, D, V3<double>{vw.tx, vw.ty, vw.tz}, V3<double>{vw.px, vw.py, vw.pz},
-                          D.pfac, st);
+    if (TAB)
+      tab_toward(D, V3<double>{p.nx, p.ny, p.nz}, s_in, Om, V3<double>{vw.tx, vw.ty, vw.tz},
+                 V3<double>{vw.px, vw.py, vw.pz}, st);
+    else
+      source_toward<SPHERE>(C9, q_ev, D, V3<double>{vw.tx, vw.ty, vw.tz}, V3<double>{vw.px, vw.py, vw.pz},
+                            D.pfac, st);
     const double om[3] = {vw.ox, vw.oy, vw.oz};
     int ci[3] = {p.ci, p.cj, p.ck};
     double f[3] = {p.fx, p.fy, p.fz};
@@ -826,9 +959,48 @@ __device__ void peel_off(const Packet<R>& p, const TransportArgs& a, const Quat<
   }
 }
 
+// Per-view flush of tabulated grains (the scattering source S of Sec. 2.3,
+// eq. scat-disc-sum, one Stokes vector per camera): each staged entry holds
+// the segment's weighted Stokes integral (lab basis of its direction) and the
+// direction; the wavefront takes the (entry, camera) pairs 64 at a time, one
+// per lane, projects the entry on the camera with the table and adds the four
+// components (divided by the cell volume) to S[lambda][cell][view][4] --
+// adjacent lanes write adjacent cameras of one cell, one contiguous run of
+// 32-byte vectors.  Reached by all lanes of the wavefront.
+__device__ void wave_drain_views(const TransportArgs& a, double* sv, long long* sk, int lane, int& staged) {
+  constexpr int NV = 7;  // staged values per entry: weighted J (4) and n (3)
+  const int n = staged;
+  if (n == 0) return;
+  staged = 0;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int nv = a.n_views;
+  const int items = n * nv;
+  const double inv_vol = 1.0 / (a.dx * a.dx * a.dx);
+  for (int it = lane; it < items; it += 64) {
+    const int e = it / nv, v = it - e * nv;
+    const long long key = sk[e];
+    const double* x = sv + e * NV;
+    const DustDev& D = a.dust[(uint64_t)key / a.ncell];
+    const ViewDev& vw = a.views[v];
+    const double s_in[4] = {x[0], x[1], x[2], x[3]};
+    double st[4];
+    tab_toward(D, V3<double>{x[4], x[5], x[6]}, s_in, V3<double>{vw.ox, vw.oy, vw.oz},
+               V3<double>{vw.tx, vw.ty, vw.tz}, V3<double>{vw.px, vw.py, vw.pz}, st);
+    double* dst = a.tally + ((uint64_t)key * nv + v) * 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (st[k] != 0.0) unsafeAtomicAdd(dst + k, st[k] * inv_vol);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Scattering event at the packet's current position (Sec. 2.2), the next
 // scattering depth, and the roulette check that follows every segment.
-template <typename R, bool ALIGNED, bool SPHERE, bool PEEL>
+template <typename R, bool ALIGNED, bool SPHERE, bool PEEL, bool TAB>
 __device__ uint32_t scatter_step(Packet<R>& p, const TransportArgs& a) {
   const uint64_t c = (uint64_t)p.ci + (uint64_t)a.nx * ((uint64_t)p.cj + (uint64_t)a.ny * p.ck);
   const DustDev& D = a.dust[p.lam];
@@ -839,8 +1011,12 @@ __device__ uint32_t scatter_step(Packet<R>& p, const TransportArgs& a) {
     qd = cell_quat<ALIGNED, SPHERE>(a, blk, c);
     q = quat_cast<R>(qd);
   }
-  if (PEEL) peel_off<R, ALIGNED, SPHERE>(p, a, qd, D);
-  if (!scatter<R, ALIGNED, SPHERE>(p, q, qd, D, a.seed)) return END_NUMERIC;
+  if (PEEL) peel_off<R, ALIGNED, SPHERE, TAB>(p, a, qd, D);
+  if (TAB) {
+    if (!scatter_tab<R>(p, D, a.seed)) return END_NUMERIC;
+  } else if (!scatter<R, ALIGNED, SPHERE>(p, q, qd, D, a.seed)) {
+    return END_NUMERIC;
+  }
   p.events++;
   p.hash = hash_event(p.hash, EV_SCATTER, c);
   p.tau = -log((double)next_uniform(p, a.seed));
@@ -906,15 +1082,18 @@ __device__ void finish(const Packet<R>& p, uint32_t end, const TransportArgs& a,
   }
 }
 
-template <typename R, bool ALIGNED, bool SPHERE, bool PEEL>
+template <typename R, bool ALIGNED, bool SPHERE, bool PEEL, bool TAB>
 __device__ __forceinline__ void transport_body(const TransportArgs& a) {
   constexpr int NC = TallyShape<SPHERE>::NC, TS = TallyShape<SPHERE>::TS;
   __shared__ unsigned long long sc[SC_N];
   __shared__ double se[SE_N];
   // flush staging, one area of FLUSH_CAP entries per wavefront (56 KB per
-  // block for spheres, 61 KB for aligned grains: two blocks per CU)
-  constexpr int FLUSH_CAP = NC <= 6 ? 256 : 192;
-  __shared__ double s_val[4 * FLUSH_CAP * NC];
+  // block for spheres, 61 KB for aligned grains: two blocks per CU; 32 KB
+  // for tabulated grains, whose entries are the segment's Stokes integral and
+  // direction, 7 values)
+  constexpr int NSV = TAB ? 7 : NC;
+  constexpr int FLUSH_CAP = TAB ? 128 : (NC <= 6 ? 256 : 192);
+  __shared__ double s_val[4 * FLUSH_CAP * NSV];
   __shared__ long long s_key[4 * FLUSH_CAP];
   if (threadIdx.x < SC_N) sc[threadIdx.x] = 0ull;
   if (threadIdx.x < SE_N) se[threadIdx.x] = 0.0;
@@ -922,7 +1101,7 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
 
   const int lane = (int)__lane_id();
   const int wv = (int)(threadIdx.x >> 6);
-  double* sv = s_val + wv * FLUSH_CAP * NC;
+  double* sv = s_val + wv * FLUSH_CAP * NSV;
   long long* sk = s_key + wv * FLUSH_CAP;
   int staged = 0;  // entries in this wavefront's staging area (uniform)
   Packet<R> p;
@@ -1011,12 +1190,19 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
     int64_t key = -1;
     R cc[NC];
     if (active && !pending) {
-      const uint32_t end = step<R, ALIGNED, SPHERE>(p, a, has, key, cc, pending);
+      const uint32_t end = step<R, ALIGNED, SPHERE, TAB>(p, a, has, key, cc, pending);
       if (end) {
         finish(p, end, a, sc, se);
         active = false;
       }
     }
+    if (TAB) {
+      // tabulated grains: every segment is staged with its direction (a
+      // segment's projection on the cameras depends on it)
+      const double e7[7] = {(double)cc[0], (double)cc[1], (double)cc[2], (double)cc[3], p.nx, p.ny, p.nz};
+      flushes += wave_stage<7>(has, key, e7, sv, sk, lane, staged);
+      if (staged > FLUSH_CAP - 64) wave_drain_views(a, sv, sk, lane, staged);
+    } else {
     // a lane entering another (wavelength, cell) hands its running sum over
     flushes += wave_stage<NC>(has && key != acc_key && acc_key >= 0, acc_key, acc, sv, sk, lane, staged);
     if (staged > FLUSH_CAP - 64) wave_drain<NC, TS>(a.tally, sv, sk, lane, staged);
@@ -1030,6 +1216,7 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
         for (int k = 0; k < NC; ++k) acc[k] = (double)cc[k];
       }
     }
+    }
     // Scattering events are run for the parked lanes together once enough
     // of them wait (or one has waited long enough, or nothing else can
     // move): the rejection loop then runs for many lanes at once instead of
@@ -1042,7 +1229,7 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
         waited = 0;
         if (pending) {
           pending = false;
-          const uint32_t end = scatter_step<R, ALIGNED, SPHERE, PEEL>(p, a);
+          const uint32_t end = scatter_step<R, ALIGNED, SPHERE, PEEL, TAB>(p, a);
           if (end) {
             finish(p, end, a, sc, se);
             active = false;
@@ -1051,8 +1238,12 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
       }
     }
   }
-  flushes += wave_stage<NC>(acc_key >= 0, acc_key, acc, sv, sk, lane, staged);
-  wave_drain<NC, TS>(a.tally, sv, sk, lane, staged);
+  if (TAB) {
+    wave_drain_views(a, sv, sk, lane, staged);
+  } else {
+    flushes += wave_stage<NC>(acc_key >= 0, acc_key, acc, sv, sk, lane, staged);
+    wave_drain<NC, TS>(a.tally, sv, sk, lane, staged);
+  }
   if (lane == 0) atomicAdd(&sc[SC_FLUSH], flushes);
   __syncthreads();
   if (threadIdx.x < SC_N) atomicAdd(&(&a.stats->cell_steps)[threadIdx.x], sc[threadIdx.x]);
@@ -1067,14 +1258,14 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
 // so they run unbounded at one wave per SIMD.  PEEL adds peel-off imaging at
 // every scattering event (a separate instantiation: the kernels without it
 // are unchanged).
-template <bool ALIGNED, bool SPHERE, bool PEEL>
+template <bool ALIGNED, bool SPHERE, bool PEEL, bool TAB>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_transport32(TransportArgs a) {
-  transport_body<float, ALIGNED, SPHERE, PEEL>(a);
+  transport_body<float, ALIGNED, SPHERE, PEEL, TAB>(a);
 }
-template <bool ALIGNED, bool SPHERE, bool PEEL>
+template <bool ALIGNED, bool SPHERE, bool PEEL, bool TAB>
 __global__ void __launch_bounds__(256) k_transport64(TransportArgs a) {
-  transport_body<double, ALIGNED, SPHERE, PEEL>(a);
+  transport_body<double, ALIGNED, SPHERE, PEEL, TAB>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1161,7 +1352,7 @@ __global__ void __launch_bounds__(256) k_image(ImageArgs a) {
         Quat<double> q{1.0, 0.0, 0.0, 0.0};
         if (ALIGNED) q = grain_quat(V3<double>{(double)a.bx[c], (double)a.by[c], (double)a.bz[c]});
         if (USER_S) {
-          const double* Sv = a.user_S + (c * a.n_views + v) * 4;
+          const double* Sv = a.user_S + (((uint64_t)lam * a.ncell + c) * a.n_views + v) * 4;
           S[0] = Sv[0]; S[1] = Sv[1]; S[2] = Sv[2]; S[3] = Sv[3];
         } else {
           // source toward the camera from the incident coherency C of the
@@ -1377,41 +1568,43 @@ hipError_t launch_emission_table(const float* rho, const float* B, double fac, u
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <bool A, bool S>
+template <bool A, bool S, bool T>
 static void launch_one(const TransportArgs& a, bool fp64, bool peel, int blocks, int bs, hipStream_t s) {
-  if (fp64 && peel) hipLaunchKernelGGL((k_transport64<A, S, true>), dim3(blocks), dim3(bs), 0, s, a);
-  else if (fp64) hipLaunchKernelGGL((k_transport64<A, S, false>), dim3(blocks), dim3(bs), 0, s, a);
-  else if (peel) hipLaunchKernelGGL((k_transport32<A, S, true>), dim3(blocks), dim3(bs), 0, s, a);
-  else hipLaunchKernelGGL((k_transport32<A, S, false>), dim3(blocks), dim3(bs), 0, s, a);
+  if (fp64 && peel) hipLaunchKernelGGL((k_transport64<A, S, true, T>), dim3(blocks), dim3(bs), 0, s, a);
+  else if (fp64) hipLaunchKernelGGL((k_transport64<A, S, false, T>), dim3(blocks), dim3(bs), 0, s, a);
+  else if (peel) hipLaunchKernelGGL((k_transport32<A, S, true, T>), dim3(blocks), dim3(bs), 0, s, a);
+  else hipLaunchKernelGGL((k_transport32<A, S, false, T>), dim3(blocks), dim3(bs), 0, s, a);
 }
 
-hipError_t launch_transport(const TransportArgs& a, bool fp64, bool aligned, bool sphere, bool peel,
+hipError_t launch_transport(const TransportArgs& a, bool fp64, bool aligned, bool sphere, bool peel, bool tab,
                             int blocks, int block_size, hipStream_t s) {
-  if (aligned && sphere) launch_one<true, true>(a, fp64, peel, blocks, block_size, s);
-  else if (aligned) launch_one<true, false>(a, fp64, peel, blocks, block_size, s);
-  else if (sphere) launch_one<false, true>(a, fp64, peel, blocks, block_size, s);
-  else launch_one<false, false>(a, fp64, peel, blocks, block_size, s);
+  if (tab) launch_one<false, true, true>(a, fp64, peel, blocks, block_size, s);
+  else if (aligned && sphere) launch_one<true, true, false>(a, fp64, peel, blocks, block_size, s);
+  else if (aligned) launch_one<true, false, false>(a, fp64, peel, blocks, block_size, s);
+  else if (sphere) launch_one<false, true, false>(a, fp64, peel, blocks, block_size, s);
+  else launch_one<false, false, false>(a, fp64, peel, blocks, block_size, s);
   return hipGetLastError();
 }
 
-template <bool A, bool S, bool PL>
+template <bool A, bool S, bool PL, bool T>
 static int occ_one(bool fp64, int bs) {
   int n = 0;
-  const hipError_t e = fp64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport64<A, S, PL>, bs, 0)
-                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport32<A, S, PL>, bs, 0);
+  const hipError_t e = fp64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport64<A, S, PL, T>, bs, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport32<A, S, PL, T>, bs, 0);
   return e == hipSuccess ? n : 0;
 }
 
-template <bool A, bool S>
+template <bool A, bool S, bool T>
 static int occ_peel(bool fp64, bool peel, int bs) {
-  return peel ? occ_one<A, S, true>(fp64, bs) : occ_one<A, S, false>(fp64, bs);
+  return peel ? occ_one<A, S, true, T>(fp64, bs) : occ_one<A, S, false, T>(fp64, bs);
 }
 
-int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, bool peel, int block_size) {
-  if (aligned && sphere) return occ_peel<true, true>(fp64, peel, block_size);
-  if (aligned) return occ_peel<true, false>(fp64, peel, block_size);
-  if (sphere) return occ_peel<false, true>(fp64, peel, block_size);
-  return occ_peel<false, false>(fp64, peel, block_size);
+int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, bool peel, bool tab, int block_size) {
+  if (tab) return occ_peel<false, true, true>(fp64, peel, block_size);
+  if (aligned && sphere) return occ_peel<true, true, false>(fp64, peel, block_size);
+  if (aligned) return occ_peel<true, false, false>(fp64, peel, block_size);
+  if (sphere) return occ_peel<false, true, false>(fp64, peel, block_size);
+  return occ_peel<false, false, false>(fp64, peel, block_size);
 }
 
 hipError_t launch_image(const ImageArgs& a, bool aligned, bool sphere, bool user_source,

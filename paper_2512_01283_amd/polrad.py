@@ -99,6 +99,7 @@ _SIGS = {
     "kp_set_dust": ([_P, C.c_int32, C.POINTER(kp_dust)], C.c_int),
     "kp_set_source": ([_P, C.POINTER(kp_source)], C.c_int),
     "kp_set_emission": ([_P, C.c_int32, _P], C.c_int),
+    "kp_set_dust_tables": ([_P, C.c_int32, C.c_int32, _P], C.c_int),
     "kp_set_views": ([_P, C.c_int32, C.POINTER(kp_view)], C.c_int),
     "kp_run": ([_P, C.POINTER(C.c_uint64), C.POINTER(kp_opts), _P], C.c_int),
     "kp_run_static": ([_P, C.POINTER(C.c_uint64), C.POINTER(kp_opts), _P, C.c_size_t, _P], C.c_int),
@@ -109,6 +110,7 @@ _SIGS = {
     "kp_get_images_device": ([_P, _P, C.c_size_t, _P], C.c_int),
     "kp_get_peel_images": ([_P, _P, C.c_size_t], C.c_int),
     "kp_get_tally": ([_P, _P, C.c_size_t], C.c_int),
+    "kp_get_view_tally": ([_P, _P, C.c_size_t], C.c_int),
     "kp_get_stats": ([_P, C.POINTER(kp_stats)], C.c_int),
     "kp_get_trace": ([_P, _P, C.c_size_t], C.c_int),
 }
@@ -191,6 +193,17 @@ def make_dust(d) -> kp_dust:
 def kp_set_dust(ctx, dust_list) -> None:
     arr = (kp_dust * len(dust_list))(*[make_dust(d) for d in dust_list])
     _check(ctx, _lib.kp_set_dust(ctx, len(dust_list), arr))
+
+
+def kp_set_dust_tables(ctx, Z) -> None:
+    """Z: [n_lambda][n_theta][6] scattering-plane tables (float64), or None
+    to return to dipole grains."""
+    if Z is None:
+        _check(ctx, _lib.kp_set_dust_tables(ctx, 0, 0, None))
+        return
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    assert Z.ndim == 3 and Z.shape[2] == 6
+    _check(ctx, _lib.kp_set_dust_tables(ctx, Z.shape[0], Z.shape[1], Z.ctypes.data_as(_P)))
 
 
 def kp_set_source(ctx, src) -> None:
@@ -278,6 +291,12 @@ def kp_get_tally(ctx, n_lambda, ncell) -> np.ndarray:
     return out
 
 
+def kp_get_view_tally(ctx, n_lambda, ncell, n_views) -> np.ndarray:
+    out = np.zeros((n_lambda, ncell, n_views, 4), dtype=np.float64)
+    _check(ctx, _lib.kp_get_view_tally(ctx, out.ctypes.data_as(_P), out.size))
+    return out
+
+
 def kp_get_stats(ctx) -> dict:
     s = kp_stats()
     _check(ctx, _lib.kp_get_stats(ctx, C.byref(s)))
@@ -333,6 +352,11 @@ class Context:
         if cfg.get("emission") is not None:
             kp_set_emission(self.h, cfg["emission"])
         kp_set_dust(self.h, cfg["dust"])
+        tabs = [d.get("table") for d in cfg["dust"]]
+        if any(t is not None for t in tabs):
+            if any(t is None for t in tabs) or len({np.shape(t) for t in tabs}) != 1:
+                raise ValueError("tabulated scattering needs one table of the same size per wavelength")
+            kp_set_dust_tables(self.h, np.stack(tabs))
         kp_set_source(self.h, cfg["source"])
         kp_set_views(self.h, cfg["views"])
         self.cfg = cfg
@@ -388,6 +412,13 @@ class Context:
     def tally(self) -> np.ndarray:
         g = self.cfg["grid"]
         return kp_get_tally(self.h, len(self.last_counts), g["nx"] * g["ny"] * g["nz"])
+
+    def view_tally(self) -> np.ndarray:
+        """Per-view source of the last step 1 with tabulated grains,
+        [n_lambda, ncell, n_views, 4]."""
+        g = self.cfg["grid"]
+        return kp_get_view_tally(self.h, len(self.last_counts), g["nx"] * g["ny"] * g["nz"],
+                                 len(self.cfg["views"]))
 
     def stats(self) -> dict:
         return kp_get_stats(self.h)
