@@ -2,7 +2,7 @@
 step 2) and print one JSON line per run with its counters and kernel times.
 
     python -m paper_2512_01283_amd.run WORKLOAD [--runs K] [--packets N]
-                                      [--precision auto|fp64|fp32]
+                                      [--precision auto|fp64|fp32] [--peel-off]
 
 WORKLOAD is one of the names in WORKLOADS below (sizes as in workloads.py;
 --packets overrides the packet count of a single-wavelength workload).
@@ -26,6 +26,8 @@ WORKLOADS = {
     "dust_cylinder": W.dust_cylinder,
     "dust_cylinder_aligned": lambda **kw: W.dust_cylinder(aligned=True, **kw),
     "thermal_cube": W.thermal_cube,
+    "table_disk": W.table_disk,
+    "periodic_slab": W.periodic_slab,
 }
 PRECISION = {"auto": 0, "fp64": 1, "fp32": 2}
 
@@ -36,6 +38,7 @@ def main(argv=None) -> int:
     ap.add_argument("--runs", type=int, default=2)
     ap.add_argument("--packets", type=int, default=0)
     ap.add_argument("--precision", choices=sorted(PRECISION), default="auto")
+    ap.add_argument("--peel-off", action="store_true", help="also form peel-off images")
     a = ap.parse_args(argv)
     import torch
 
@@ -47,7 +50,7 @@ def main(argv=None) -> int:
     for r in range(a.runs):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ctx.run(transport_fp64=PRECISION[a.precision])
+        ctx.run(transport_fp64=PRECISION[a.precision], peel_off=int(a.peel_off))
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         st = ctx.stats()

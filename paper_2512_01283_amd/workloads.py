@@ -218,6 +218,18 @@ def flared_disk(n=256, packets=100_000_000, seed=2, n_views=8, npix=None, albedo
                 precision="f32")
 
 
+def table_disk(n=256, packets=100_000_000, seed=2, n_views=8, npix=None, g=0.5) -> dict:
+    """The flared disk of flared_disk with grains of tabulated scattering
+    (hg_table of asymmetry g, 181 nodes): every segment is projected on
+    every camera (the per-view source)."""
+    cfg = flared_disk(n=n, packets=packets, seed=seed, n_views=n_views, npix=npix)
+    d = cfg["dust"][0]
+    cfg["dust"] = [table_dust(d["kappa_sca"] + d["kappa_abs"], d["kappa_sca"] / (d["kappa_sca"] + d["kappa_abs"]),
+                              hg_table(g, n_theta=181))]
+    cfg["name"] = f"table_disk{n}"
+    return cfg
+
+
 def bitrev5(k: int) -> int:
     return int(f"{k:05b}"[::-1], 2)
 
