@@ -30,10 +30,15 @@ def build(force: bool = True) -> str:
     return LIB
 
 
+class Mesh(C.Structure):
+    _fields_ = [("rx", C.c_int32), ("ry", C.c_int32), ("rz", C.c_int32), ("block", C.c_int32),
+                ("max_level", C.c_int32), ("n_nodes", C.c_int32), ("child", C.POINTER(C.c_int32))]
+
+
 class Grid(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double),
-                ("dx", C.c_double), ("boundary", C.c_int32)]
+                ("dx", C.c_double), ("boundary", C.c_int32), ("mesh", C.POINTER(Mesh))]
 
 
 class Dust(C.Structure):
@@ -153,9 +158,27 @@ def _f(a):
     return a, a.ctypes.data_as(C.POINTER(C.c_float))
 
 
+def cell_count(g) -> int:
+    """Cells of a grid record: nx ny nz, or block^3 per leaf of its mesh."""
+    m = g.get("mesh")
+    if m is None:
+        return int(g["nx"]) * int(g["ny"]) * int(g["nz"])
+    return int(np.sum(np.asarray(m["child"]) == -1)) * int(m["block"]) ** 3
+
+
 def make_grid(g) -> Grid:
-    return Grid(int(g["nx"]), int(g["ny"]), int(g["nz"]), float(g["x0"]),
-                float(g["y0"]), float(g["z0"]), float(g["dx"]), int(g.get("boundary", 0)))
+    """g["mesh"] (optional): dict(rx, ry, rz, block, max_level, child) of a
+    composite mesh (reading M1); the arrays are kept alive on the result."""
+    out = Grid(int(g["nx"]), int(g["ny"]), int(g["nz"]), float(g["x0"]),
+               float(g["y0"]), float(g["z0"]), float(g["dx"]), int(g.get("boundary", 0)), None)
+    m = g.get("mesh")
+    if m is not None:
+        child = np.ascontiguousarray(m["child"], dtype=np.int32)
+        mesh = Mesh(int(m["rx"]), int(m["ry"]), int(m["rz"]), int(m["block"]), int(m["max_level"]),
+                    len(child), child.ctypes.data_as(C.POINTER(C.c_int32)))
+        out.mesh = C.pointer(mesh)
+        out._keep = (child, mesh)
+    return out
 
 
 def make_dust(d) -> Dust:
@@ -212,7 +235,7 @@ def transport(cfg, lam=0, p_begin=0, p_end=None, n_total=None, tally=True,
     """Step 1 for one wavelength.  Returns (S or None, traces or None, stats)."""
     L = lib()
     g = make_grid(cfg["grid"])
-    ncell = g.nx * g.ny * g.nz
+    ncell = cell_count(cfg["grid"])
     rho, rho_p = _f(cfg["rho"])
     bh, bh_p = _f(cfg.get("bhat"))
     dust = make_dust(cfg["dust"][lam])
@@ -240,7 +263,7 @@ def transport_peel(cfg, lam=0, p_begin=0, p_end=None, n_total=None, tally=False,
     images [view][4][npy][npx], S or None, stats).  Open boundaries."""
     L = lib()
     g = make_grid(cfg["grid"])
-    ncell = g.nx * g.ny * g.nz
+    ncell = cell_count(cfg["grid"])
     rho, rho_p = _f(cfg["rho"])
     bh, bh_p = _f(cfg.get("bhat"))
     dust = make_dust(cfg["dust"][lam])

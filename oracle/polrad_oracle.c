@@ -48,6 +48,14 @@
  *     the envelope on each node interval the larger S11 of its two nodes
  *     times (I + sqrt(Q^2+U^2)); draws per trial: interval (by the envelope's
  *     cumulative mass), cos Theta uniform in the interval, azimuth, accept.
+ *  M1 static mesh refinement (Sec. 2: a composite mesh, optionally with
+ *     static refinement): root blocks of block^3 cells on a uniform array,
+ *     each refinable into its 8 octants recursively (see kpo_mesh); packets
+ *     and camera rays cross cells of a leaf block as on a uniform grid and,
+ *     leaving it, continue in the leaf holding the exit point, found in
+ *     units of the finest cell with the face rule of R12.  Cell lengths and
+ *     volumes are those of the cell's level.  Open boundaries and point
+ *     sources (thermal emission and peel-off on uniform grids only).
  *  E1 thermal emission of the dust (Sec. 2.2, the alpha_abs B term of eq.
  *     polarized-rt): the absorption matrix is kappa_abs/kappa_ext times the
  *     extinction matrix, so a cell emits rho kappa_abs (alpha1, alpha2, 0, 0) B
@@ -514,6 +522,7 @@ void kpo_segment(double m1, double m2, double m3, double len,
 typedef struct {
   int64_t i[3];
   double f[3];
+  int64_t leaf;         /* mesh: the leaf block, i[] its local cell; uniform grid: -1 */
 } gpos_t;
 
 static int periodic(const kpo_grid *g, int a) { return (g->boundary >> a) & 1; }
@@ -535,6 +544,169 @@ static int inside(const kpo_grid *g, const gpos_t *p) {
 static int64_t flat(const kpo_grid *g, const gpos_t *p) {
   return p->i[0] + (int64_t)g->nx * (p->i[1] + (int64_t)g->ny * p->i[2]);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Composite mesh with static refinement (Sec. 2, the mesh the packets       */
+/* cross; reading M1).  Positions are kept as (leaf, local cell, fraction);  */
+/* on leaving a leaf the point is expressed in units of the finest cell      */
+/* (2^-max_level of a root cell) and the leaf holding it is found by         */
+/* descending from its root block.                                           */
+/* ------------------------------------------------------------------------ */
+static double clamp01(double v);
+
+typedef struct {
+  int64_t n_leaves;
+  int32_t *leaf_of_node;  /* [n_nodes]: leaf id or -1 */
+  int64_t *node_of_leaf;  /* [n_leaves] */
+  int64_t (*org)[3];      /* [n_leaves]: lower corner in finest cells */
+  int32_t *level;         /* [n_leaves] */
+  int64_t nfine[3];       /* domain extent in finest cells */
+} mesh_ix_t;
+
+static void mesh_free(mesh_ix_t *mx) {
+  free(mx->leaf_of_node);
+  free(mx->node_of_leaf);
+  free(mx->org);
+  free(mx->level);
+  memset(mx, 0, sizeof *mx);
+}
+
+/* Checks the tree (every non-root node the child of exactly one refined
+ * node, children after their parent, depth <= max_level) and numbers the
+ * leaves in node order with their origins and levels.  0 or -1. */
+static int mesh_build(const kpo_grid *g, mesh_ix_t *mx) {
+  memset(mx, 0, sizeof *mx);
+  const kpo_mesh *m = g->mesh;
+  if (!m || !m->child || m->block < 1 || m->max_level < 0 || m->max_level > 20) return -1;
+  int64_t R = (int64_t)m->rx * m->ry * m->rz;
+  if (m->rx < 1 || m->ry < 1 || m->rz < 1 || m->n_nodes < R) return -1;
+  if (g->nx != (int64_t)m->rx * m->block || g->ny != (int64_t)m->ry * m->block ||
+      g->nz != (int64_t)m->rz * m->block || g->boundary != 0)
+    return -1;
+  int32_t N = m->n_nodes;
+  int32_t *parents = calloc((size_t)N, sizeof(int32_t));
+  int32_t *lev = calloc((size_t)N, sizeof(int32_t));
+  int64_t (*org)[3] = calloc((size_t)N, sizeof *org);
+  int rc = 0;
+  int64_t full = (int64_t)m->block << m->max_level;  /* a root block's edge in finest cells */
+  for (int64_t r = 0; r < R; ++r) {
+    org[r][0] = (r % m->rx) * full;
+    org[r][1] = ((r / m->rx) % m->ry) * full;
+    org[r][2] = (r / ((int64_t)m->rx * m->ry)) * full;
+  }
+  for (int32_t i = 0; i < N && rc == 0; ++i) {
+    int32_t c = m->child[i];
+    if (c == -1) continue;
+    if (c < R || c <= i || (int64_t)c + 8 > N || lev[i] + 1 > m->max_level) { rc = -1; break; }
+    int64_t half = full >> (lev[i] + 1);
+    for (int k = 0; k < 8; ++k) {
+      if (parents[c + k]++) { rc = -1; break; }
+      lev[c + k] = lev[i] + 1;
+      org[c + k][0] = org[i][0] + ((k & 1) ? half : 0);
+      org[c + k][1] = org[i][1] + ((k & 2) ? half : 0);
+      org[c + k][2] = org[i][2] + ((k & 4) ? half : 0);
+    }
+  }
+  for (int32_t i = (int32_t)R; i < N && rc == 0; ++i)
+    if (parents[i] != 1) rc = -1;
+  if (rc == 0) {
+    mx->leaf_of_node = malloc(sizeof(int32_t) * (size_t)N);
+    for (int32_t i = 0; i < N; ++i) mx->leaf_of_node[i] = m->child[i] == -1 ? (int32_t)mx->n_leaves++ : -1;
+    mx->node_of_leaf = malloc(sizeof(int64_t) * (size_t)mx->n_leaves);
+    mx->org = malloc(sizeof *mx->org * (size_t)mx->n_leaves);
+    mx->level = malloc(sizeof(int32_t) * (size_t)mx->n_leaves);
+    for (int32_t i = 0; i < N; ++i) {
+      int32_t j = mx->leaf_of_node[i];
+      if (j < 0) continue;
+      mx->node_of_leaf[j] = i;
+      for (int a = 0; a < 3; ++a) mx->org[j][a] = org[i][a];
+      mx->level[j] = lev[i];
+    }
+    mx->nfine[0] = m->rx * full;
+    mx->nfine[1] = m->ry * full;
+    mx->nfine[2] = m->rz * full;
+  }
+  free(parents);
+  free(lev);
+  free(org);
+  return rc;
+}
+
+/* the leaf holding finest cell X (inside the domain) */
+static int64_t mesh_find(const kpo_grid *g, const mesh_ix_t *mx, const int64_t X[3]) {
+  const kpo_mesh *m = g->mesh;
+  int64_t full = (int64_t)m->block << m->max_level;
+  int64_t r[3] = {X[0] / full, X[1] / full, X[2] / full};
+  int64_t node = r[0] + m->rx * (r[1] + (int64_t)m->ry * r[2]);
+  int64_t o[3] = {r[0] * full, r[1] * full, r[2] * full}, size = full;
+  while (m->child[node] != -1) {
+    size /= 2;
+    int oct = 0;
+    for (int a = 0; a < 3; ++a)
+      if (X[a] - o[a] >= size) { oct |= 1 << a; o[a] += size; }
+    node = m->child[node] + oct;
+  }
+  return mx->leaf_of_node[node];
+}
+
+/* Position t (finest-cell units) in finest cell X -> leaf, local cell, fraction. */
+static void mesh_place(const kpo_grid *g, const mesh_ix_t *mx, const double t[3], const int64_t X[3],
+                       gpos_t *p) {
+  int64_t j = mesh_find(g, mx, X);
+  int64_t s = (int64_t)1 << (g->mesh->max_level - mx->level[j]);
+  p->leaf = j;
+  for (int a = 0; a < 3; ++a) {
+    p->i[a] = (X[a] - mx->org[j][a]) / s;
+    p->f[a] = clamp01((t[a] - (double)mx->org[j][a]) / (double)s - (double)p->i[a]);
+  }
+}
+
+/* finest cell of finest-unit coordinate t: a coordinate on a face belongs
+ * to the cell the direction points into (R12) */
+static int64_t finest_cell(double t, double n) {
+  double fl = floor(t);
+  int64_t X = (int64_t)fl;
+  if (fl == t && n < 0.0) X -= 1;
+  return X;
+}
+
+/* After cross_face moved the local index of `axis` out of the leaf: the
+ * leaf beyond, or 1 if the packet left the domain. */
+static int mesh_cross(const kpo_grid *g, const mesh_ix_t *mx, gpos_t *p, const double n[3]) {
+  int64_t j = p->leaf;
+  double s = (double)((int64_t)1 << (g->mesh->max_level - mx->level[j]));
+  double t[3];
+  int64_t X[3];
+  for (int a = 0; a < 3; ++a) {
+    t[a] = (double)mx->org[j][a] + ((double)p->i[a] + p->f[a]) * s;
+    X[a] = finest_cell(t[a], n[a]);
+    if (X[a] < 0 || X[a] >= mx->nfine[a]) return 1;
+  }
+  mesh_place(g, mx, t, X, p);
+  return 0;
+}
+
+/* edge length of the packet's cell */
+static double cell_len(const kpo_grid *g, const mesh_ix_t *mx, const gpos_t *p) {
+  if (!g->mesh) return g->dx;
+  return ldexp(g->dx, -mx->level[p->leaf]);
+}
+
+/* flat index of the packet's cell */
+static int64_t cell_of(const kpo_grid *g, const gpos_t *p) {
+  if (!g->mesh) return flat(g, p);
+  int64_t B = g->mesh->block;
+  return p->leaf * B * B * B + p->i[0] + B * (p->i[1] + B * p->i[2]);
+}
+
+static int64_t cell_count(const kpo_grid *g, const mesh_ix_t *mx) {
+  if (!g->mesh) return (int64_t)g->nx * g->ny * g->nz;
+  int64_t B = g->mesh->block;
+  return mx->n_leaves * B * B * B;
+}
+
+/* after cross_face along `axis`: 1 if the packet left the domain */
+static int after_cross(const kpo_grid *g, const mesh_ix_t *mx, gpos_t *p, int axis, const double n[3]);
 
 /* Cell holding a point; a coordinate exactly on a face belongs to the cell the
  * direction points into. */
@@ -574,6 +746,37 @@ static void cross_face(gpos_t *p, const double n[3], double t, int axis) {
     if (a != axis) p->f[a] = clamp01(p->f[a] + t * n[a]);
   if (n[axis] > 0.0) { p->i[axis] += 1; p->f[axis] = 0.0; }
   else { p->i[axis] -= 1; p->f[axis] = 1.0; }
+}
+
+static int after_cross(const kpo_grid *g, const mesh_ix_t *mx, gpos_t *p, int axis, const double n[3]) {
+  if (!g->mesh) return leave_or_wrap(g, p, axis);
+  if (p->i[axis] >= 0 && p->i[axis] < g->mesh->block) return 0;
+  return mesh_cross(g, mx, p, n);
+}
+
+/* The cell holding point x (direction n for points on faces, R12): 1 if it
+ * lies inside the grid, periodic axes wrapped. */
+static int locate_in(const kpo_grid *g, const mesh_ix_t *mx, const double x[3], const double n[3],
+                     gpos_t *p) {
+  p->leaf = -1;
+  if (!g->mesh) {
+    locate(g, x, n, p);
+    for (int a = 0; a < 3; ++a) {
+      int64_t na = a == 0 ? g->nx : (a == 1 ? g->ny : g->nz);
+      if (periodic(g, a)) p->i[a] = ((p->i[a] % na) + na) % na;
+    }
+    return inside(g, p);
+  }
+  double o[3] = {g->x0, g->y0, g->z0}, fine = ldexp(g->dx, -g->mesh->max_level);
+  double t[3];
+  int64_t X[3];
+  for (int a = 0; a < 3; ++a) {
+    t[a] = (x[a] - o[a]) / fine;
+    X[a] = finest_cell(t[a], n[a]);
+    if (X[a] < 0 || X[a] >= mx->nfine[a]) return 0;
+  }
+  mesh_place(g, mx, t, X, p);
+  return 1;
 }
 
 static void cell_quat(const float *bhat, int64_t ncell, int64_t c, double q[4]) {
@@ -671,6 +874,8 @@ typedef struct {
   double *peel;          /* peel-off images [view][4][npy][npx] or NULL */
   double tab_norm;       /* tabulated scattering: 2 pi times the integral of S11 over cos Theta */
   const double *tab_cum; /* ... and the cumulative envelope mass [n_theta] */
+  const mesh_ix_t *mx;   /* the mesh's leaf table (unused on a uniform grid) */
+  int64_t ncell;
 } run_t;
 
 /* P(m; n) s (lab bases) with the run's table normalisation */
@@ -699,6 +904,7 @@ static double *emission_cdf(const kpo_grid *g, const float *rho, const kpo_dust 
 
 double kpo_emission_luminosity(const kpo_grid *g, const float *rho, const kpo_dust *d,
                                const float *B) {
+  if (g->mesh) return 0.0;  /* thermal emission: uniform grids only (reading M1) */
   double *cdf = emission_cdf(g, rho, d, B);
   if (!cdf) return 0.0;
   double L = cdf[(int64_t)g->nx * g->ny * g->nz - 1];
@@ -749,7 +955,7 @@ int kpo_emit_state(const kpo_grid *g, const float *rho, const float *bhat,
                    const kpo_dust *d, const float *B, uint64_t seed, int32_t lam,
                    uint64_t packet, double w, int64_t *cell, double pos[3], double n[3],
                    double s[4]) {
-  if (!g || !rho || !d || !B) return -1;
+  if (!g || !rho || !d || !B || g->mesh) return -1;
   double *cdf = emission_cdf(g, rho, d, B);
   if (!cdf) return -1;
   rng_t rng = {{seed, (uint64_t)lam}, packet, 0, 0, 0, {0, 0, 0, 0}};
@@ -823,18 +1029,19 @@ static void peel_off(const run_t *R, const gpos_t *at, const double q_ev[4], con
 static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *st) {
   const kpo_grid *g = R->g;
   const kpo_dust *d = R->d;
-  int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
+  int64_t ncell = R->ncell;
   double kext = d->kappa_sca + d->kappa_abs;
-  double vol = g->dx * g->dx * g->dx;
   rng_t rng = {{R->o->seed, (uint64_t)R->lam}, pid, 0, 0, 0, {0, 0, 0, 0}};
 
   /* emission: a point source (isotropic unpolarised or pencil) or the dust's
    * thermal emission (reading E1), then an exponential scattering depth */
   double n[3], s[4], w0;
   gpos_t p;
+  int in = 1;
   if (R->src->kind == 2) {
     w0 = R->cdf[ncell - 1] / (double)R->n_total;
     emit_thermal(g, R->bhat, d, R->cdf, &rng, w0, &p, n, s);
+    p.leaf = -1;
   } else {
     double u0 = draw(&rng), u1 = draw(&rng);
     if (R->src->kind == 1) {
@@ -845,11 +1052,7 @@ static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *s
     }
     w0 = R->src->lum / (double)R->n_total;
     s[0] = w0; s[1] = s[2] = s[3] = 0.0;
-    locate(g, R->src->pos, n, &p);
-    for (int a = 0; a < 3; ++a) {
-      int64_t na = a == 0 ? g->nx : (a == 1 ? g->ny : g->nz);
-      if (periodic(g, a)) p.i[a] = ((p.i[a] % na) + na) % na;
-    }
+    in = locate_in(g, R->mx, R->src->pos, n, &p);
   }
   double tau = -log(draw(&rng));
   st->e_emitted += s[0];
@@ -858,13 +1061,14 @@ static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *s
   int64_t steps = 0, last = -1;
   double tau_path = 0.0;
   uint64_t h = 14695981039346656037ULL;
-  if (!inside(g, &p)) {
+  if (!in) {
     end = KPO_END_ESCAPE;
     st->escaped++;
     st->e_escaped += s[0];
   }
   while (end == KPO_END_NONE) {
-    int64_t c = flat(g, &p);
+    int64_t c = cell_of(g, &p);
+    double clen = cell_len(g, R->mx, &p), vol = clen * clen * clen;
     last = c;
     if (events >= R->o->max_events || steps >= KPO_MAX_STEPS) {
       h = hash_event(h, KPO_END_BUDGET, c);
@@ -878,7 +1082,7 @@ static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *s
     if (axis < 0 || !isfinite(tf)) { end = KPO_END_NUMERIC; st->numeric++; break; }
     double rho = (double)R->rho[c];
     double kbar = rho * d->kappa_sca, ke = rho * kext;
-    double lface = tf * g->dx, len;
+    double lface = tf * clen, len;
     int scat;
     if (kbar > 0.0 && tau < kbar * lface) { len = tau / kbar; scat = 1; }
     else { len = lface; tau -= kbar * lface; scat = 0; }
@@ -912,7 +1116,7 @@ static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *s
     }
 
     if (scat) {
-      move_inside(&p, n, len / g->dx);
+      move_inside(&p, n, len / clen);
       if (R->peel) peel_off(R, &p, q, n, s);
       double m[3], i_in = s[0];
       if (scatter_event(d, R->tab_norm, R->tab_cum, q, n, s, &rng, &st->trials, m, s) != 0) {
@@ -928,7 +1132,7 @@ static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *s
       tau = -log(draw(&rng));
     } else {
       cross_face(&p, n, tf, axis);
-      if (leave_or_wrap(g, &p, axis)) {
+      if (after_cross(g, R->mx, &p, axis, n)) {
         h = hash_event(h, KPO_END_ESCAPE, c);
         end = KPO_END_ESCAPE;
         st->escaped++;
@@ -945,11 +1149,11 @@ static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *s
         for (int k = 0; k < 4; ++k) s[k] /= R->o->rr_psurv;
         st->rr_survivals++;
         st->e_rr_gained += s[0] - before;
-        h = hash_event(h, KPO_EV_RR_SURVIVE, flat(g, &p));
+        h = hash_event(h, KPO_EV_RR_SURVIVE, cell_of(g, &p));
       } else {
         st->rr_kills++;
         st->e_rr_killed += s[0];
-        h = hash_event(h, KPO_END_RR_KILL, flat(g, &p));
+        h = hash_event(h, KPO_END_RR_KILL, cell_of(g, &p));
         end = KPO_END_RR_KILL;
         break;
       }
@@ -1009,6 +1213,10 @@ static int transport_impl(const kpo_grid *g, const float *rho, const float *bhat
   if (check_inputs(g, d, src) || !o || n_total == 0 || p_end < p_begin) return -1;
   if ((S || peel) && (n_views <= 0 || !views)) return -1;
   if (peel && g->boundary != 0) return -1;
+  /* the mesh: point sources only, no peel-off (reading M1) */
+  mesh_ix_t mx;
+  memset(&mx, 0, sizeof mx);
+  if (g->mesh && (src->kind == 2 || peel || mesh_build(g, &mx))) { mesh_free(&mx); return -1; }
   double *cdf = NULL;
   if (src->kind == 2 && !(cdf = emission_cdf(g, rho, d, src->B))) return -1;
   double (*vdir)[3] = NULL;
@@ -1022,7 +1230,8 @@ static int transport_impl(const kpo_grid *g, const float *rho, const float *bhat
     cum = malloc(sizeof(double) * (size_t)d->n_theta);
     table_envelope(d, N, cum);
   }
-  run_t R = {g, rho, bhat, d, src, o, lam, n_total, n_views, views, vdir, S, cdf, peel, N, cum};
+  run_t R = {g, rho, bhat, d, src, o, lam, n_total, n_views, views, vdir, S, cdf, peel, N, cum,
+             &mx, cell_count(g, &mx)};
   kpo_stats total;
   memset(&total, 0, sizeof total);
   int nth = o->nthreads;
@@ -1040,6 +1249,7 @@ static int transport_impl(const kpo_grid *g, const float *rho, const float *bhat
   free(vdir);
   free(cdf);
   free(cum);
+  mesh_free(&mx);
   return 0;
 }
 
@@ -1068,6 +1278,9 @@ int kpo_trace_packets(const kpo_grid *g, const float *rho, const float *bhat,
                       const uint64_t *ids, uint64_t n_ids, uint64_t n_total,
                       const kpo_opts *o, kpo_trace *traces) {
   if (check_inputs(g, d, src) || !o || !ids || !traces || n_total == 0) return -1;
+  mesh_ix_t mx;
+  memset(&mx, 0, sizeof mx);
+  if (g->mesh && (src->kind == 2 || mesh_build(g, &mx))) { mesh_free(&mx); return -1; }
   double *cdf = NULL;
   if (src->kind == 2 && !(cdf = emission_cdf(g, rho, d, src->B))) return -1;
   double *cum = NULL, N = 0.0;
@@ -1076,7 +1289,8 @@ int kpo_trace_packets(const kpo_grid *g, const float *rho, const float *bhat,
     cum = malloc(sizeof(double) * (size_t)d->n_theta);
     table_envelope(d, N, cum);
   }
-  run_t R = {g, rho, bhat, d, src, o, lam, n_total, 0, NULL, NULL, NULL, cdf, NULL, N, cum};
+  run_t R = {g, rho, bhat, d, src, o, lam, n_total, 0, NULL, NULL, NULL, cdf, NULL, N, cum,
+             &mx, cell_count(g, &mx)};
   int nth = o->nthreads;
 #pragma omp parallel num_threads(nth > 0 ? nth : omp_get_max_threads())
   {
@@ -1087,6 +1301,7 @@ int kpo_trace_packets(const kpo_grid *g, const float *rho, const float *bhat,
   }
   free(cdf);
   free(cum);
+  mesh_free(&mx);
   return 0;
 }
 
@@ -1107,7 +1322,11 @@ int kpo_image_thermal(const kpo_grid *g, const float *rho, const float *bhat,
                       const double *S, const float *B, double *images) {
   kpo_source dummy = {0, {0, 0, 0}, {0, 0, 1}, 1.0, NULL};
   if (check_inputs(g, d, &dummy) || n_views <= 0 || !views || !images) return -1;
-  int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
+  mesh_ix_t mx;
+  memset(&mx, 0, sizeof mx);
+  if (g->mesh && (B || mesh_build(g, &mx))) { mesh_free(&mx); return -1; }
+  int64_t ncell = cell_count(g, &mx);
+  double fine = g->mesh ? ldexp(g->dx, -g->mesh->max_level) : g->dx;
   double kext = d->kappa_sca + d->kappa_abs;
   double lo[3] = {g->x0, g->y0, g->z0};
   double hi[3] = {g->x0 + g->nx * g->dx, g->y0 + g->ny * g->dx, g->z0 + g->nz * g->dx};
@@ -1124,7 +1343,7 @@ int kpo_image_thermal(const kpo_grid *g, const float *rho, const float *bhat,
     double cells = INFINITY;
     for (int a = 0; a < 3; ++a)
       if (!periodic(g, a) && om[a] != 0.0) cells = fmin(cells, (double)nn[a] / fabs(om[a]));
-    if (!(cells <= (double)KPO_MAX_STEPS)) return -1;
+    if (!(cells <= (double)KPO_MAX_STEPS)) { mesh_free(&mx); return -1; }
   }
   for (int v = 0; v < n_views; ++v) {
     double om[3], th[3], ph[3];
@@ -1153,8 +1372,21 @@ int kpo_image_thermal(const kpo_grid *g, const float *rho, const float *bhat,
         double st[4] = {0, 0, 0, 0};
         if (!miss && sn < sf) {
           gpos_t p;
+          p.leaf = -1;
           int64_t nn[3] = {g->nx, g->ny, g->nz};
-          for (int a = 0; a < 3; ++a) {
+          if (g->mesh) {
+            /* the entry point in finest cells, clamped into the domain */
+            double t[3];
+            int64_t X[3];
+            for (int a = 0; a < 3; ++a) {
+              t[a] = (P0[a] + sn * om[a] - lo[a]) / fine;
+              X[a] = (int64_t)floor(t[a]);
+              if (X[a] < 0) X[a] = 0;
+              if (X[a] > mx.nfine[a] - 1) X[a] = mx.nfine[a] - 1;
+            }
+            mesh_place(g, &mx, t, X, &p);
+          }
+          for (int a = 0; a < 3 && !g->mesh; ++a) {
             double t = (P0[a] + sn * om[a] - lo[a]) / g->dx;
             double fl = floor(t);
             int64_t i = (int64_t)fl;
@@ -1172,7 +1404,8 @@ int kpo_image_thermal(const kpo_grid *g, const float *rho, const float *bhat,
             int axis;
             double tf = face_dist(&p, om, &axis);
             if (axis < 0) break;
-            int64_t c = flat(g, &p);
+            int64_t c = cell_of(g, &p);
+            double clen = cell_len(g, &mx, &p);
             double r = (double)rho[c];
             if (r > 0.0) {
               double ke = r * kext, q[4], og[3], al[3], sg[4], srcg[4], src[4];
@@ -1189,16 +1422,17 @@ int kpo_image_thermal(const kpo_grid *g, const float *rho, const float *bhat,
                 srcg[1] += e * al[1];
               }
               double out[4];
-              kpo_appA(al[0], al[1], al[2], ke * tf * g->dx, srcg, sg, out);
+              kpo_appA(al[0], al[1], al[2], ke * tf * clen, srcg, sg, out);
               kpo_rotate_stokes(-eta, out, st);
             }
             cross_face(&p, om, tf, axis);
-            if (leave_or_wrap(g, &p, axis)) break;
+            if (after_cross(g, &mx, &p, axis, om)) break;
           }
         }
         for (int k = 0; k < 4; ++k)
           images[(((int64_t)v * 4 + k) * npy + iy) * npx + ix] = st[k];
       }
   }
+  mesh_free(&mx);
   return 0;
 }

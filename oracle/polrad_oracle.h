@@ -27,10 +27,28 @@
 extern "C" {
 #endif
 
+/* Composite mesh with static refinement (reading M1): rx*ry*rz root blocks
+ * of block^3 cells (x fastest), each the root of a tree of blocks; a block
+ * is either a leaf holding block^3 cells or refined into its 8 octants
+ * (octant bit 0: upper half in x, bit 1: y, bit 2: z), blocks of block^3
+ * cells of half the size.  Nodes: the roots first (node r for root r), then
+ * the children of each refined node as 8 consecutive nodes; child[i] is -1
+ * for a leaf, else the index of its first child.  Leaves are numbered in
+ * node order; cell k (x fastest) of leaf j has the flat index
+ * j * block^3 + k.  max_level bounds the depth (0..20). */
+typedef struct {
+  int32_t rx, ry, rz, block, max_level;
+  int32_t n_nodes;
+  const int32_t *child;
+} kpo_mesh;
+
 typedef struct {
   int32_t nx, ny, nz;
   double x0, y0, z0, dx;        /* lower corner, cubic cell size */
   int32_t boundary;             /* bit a set: axis a (x, y, z) periodic, else open */
+  const kpo_mesh *mesh;         /* NULL: the uniform grid nx*ny*nz; else the mesh,
+                                   with nx = rx*block (likewise y, z) and dx the
+                                   cell size of the root blocks; open boundaries */
 } kpo_grid;
 
 /* a packet ends as KPO_END_BUDGET after this many cell steps (a packet that

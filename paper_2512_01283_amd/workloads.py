@@ -143,6 +143,116 @@ def uniform_sphere(n=32, packets=100_000, albedo=1.0, tau_radius=1.0, seed=0,
                 packets=[int(packets)], opts=default_opts(seed), precision="f64")
 
 
+def mesh_tree(rx, ry, rz, block, max_level, refine):
+    """The child array of a composite mesh (roots first, x fastest; the 8
+    children of a refined node consecutive, octant bit 0 = upper x half,
+    bit 1 = y, bit 2 = z; -1 = leaf) and, per node, (level, lower corner in
+    finest cells).  refine(level, corner, edge) decides, for a block at
+    `level` with lower corner and edge in finest cells, whether it is split
+    (never beyond max_level)."""
+    full = block << max_level
+    child = []
+    info = []
+    for r in range(rx * ry * rz):
+        child.append(-1)
+        info.append((0, (r % rx * full, r // rx % ry * full, r // (rx * ry) * full)))
+    i = 0
+    while i < len(child):
+        lev, org = info[i]
+        if lev < max_level and refine(lev, org, full >> lev):
+            child[i] = len(child)
+            half = full >> (lev + 1)
+            for k in range(8):
+                child.append(-1)
+                info.append((lev + 1, (org[0] + (k & 1) * half, org[1] + ((k >> 1) & 1) * half,
+                                       org[2] + ((k >> 2) & 1) * half)))
+        i += 1
+    return np.array(child, dtype=np.int32), info
+
+
+def mesh_cells(grid) -> tuple[np.ndarray, np.ndarray]:
+    """Centres [ncell, 3] and levels [ncell] of the cells of grid["mesh"] in
+    flat order (leaves in node order, cells x fastest within a leaf)."""
+    m = grid["mesh"]
+    B, L = int(m["block"]), int(m["max_level"])
+    child = np.asarray(m["child"])
+    full = B << L
+    rx, ry, rz = int(m["rx"]), int(m["ry"]), int(m["rz"])
+    info = [(0, (r % rx * full, r // rx % ry * full, r // (rx * ry) * full)) for r in range(rx * ry * rz)]
+    info += [None] * (len(child) - len(info))
+    for i, c in enumerate(child):  # children follow their parents
+        if c >= 0:
+            lev, org = info[i]
+            half = full >> (lev + 1)
+            for k in range(8):
+                info[c + k] = (lev + 1, (org[0] + (k & 1) * half, org[1] + ((k >> 1) & 1) * half,
+                                         org[2] + ((k >> 2) & 1) * half))
+    fine = grid["dx"] / (1 << L)
+    k = np.arange(B)
+    loc = np.stack(np.meshgrid(k, k, k, indexing="ij"), axis=-1)[..., ::-1].reshape(-1, 3)  # x fastest
+    cen, lev = [], []
+    for node in np.nonzero(child == -1)[0]:
+        l, org = info[node]
+        sz = 1 << (L - l)
+        cen.append(np.array([grid["x0"], grid["y0"], grid["z0"]]) + (np.array(org) + (loc + 0.5) * sz) * fine)
+        lev.append(np.full(B ** 3, l))
+    return np.concatenate(cen), np.concatenate(lev)
+
+
+def make_mesh_grid(x0, y0, z0, dx, rx, ry, rz, block, max_level, refine) -> dict:
+    """A grid record with a composite mesh: root cells of size dx, rx*ry*rz
+    root blocks of block^3 cells, refined by refine (see mesh_tree)."""
+    child, _ = mesh_tree(rx, ry, rz, block, max_level, refine)
+    return dict(nx=rx * block, ny=ry * block, nz=rz * block, x0=x0, y0=y0, z0=z0, dx=dx,
+                mesh=dict(rx=rx, ry=ry, rz=rz, block=block, max_level=max_level, child=child))
+
+
+def mesh_sphere(rx=4, block=8, max_level=2, packets=100_000, albedo=1.0, tau_radius=1.0, seed=12,
+                views=None, npix=32) -> dict:
+    """The uniform sphere of radius 1 in [-1,1]^3 (density 1 where a cell's
+    centre lies inside) on a composite mesh refined toward the central star:
+    blocks reaching within 0.6 of the centre split to level 1, within 0.3 to
+    level 2."""
+    n = rx * block
+    reach = (0.6, 0.3, 0.15)
+
+    def refine(lev, org, edge):
+        fine = 2.0 / (n << max_level)
+        lo = -1.0 + np.array(org) * fine
+        hi = lo + edge * fine
+        d = np.linalg.norm(np.maximum(0.0, np.maximum(lo, -hi)))  # distance from the centre to the block
+        return d < reach[min(lev, 2)]
+
+    grid = make_mesh_grid(-1.0, -1.0, -1.0, 2.0 / n, rx, rx, rx, block, max_level, refine)
+    cen, _ = mesh_cells(grid)
+    rho = (np.einsum("ij,ij->i", cen, cen) < 1.0).astype(np.float32) * np.float32(tau_radius)
+    return dict(name=f"mesh_sphere{n}", grid=grid, rho=rho, bhat=None,
+                dust=[sphere_dust(1.0, albedo)],
+                source=dict(kind=0, pos=(0.0, 0.0, 0.0), dir=(0.0, 0.0, 1.0), lum=1.0),
+                views=views if views is not None else [view(90.0, 0.0, npix), view(30.0, 40.0, npix)],
+                packets=[int(packets)], opts=default_opts(seed), precision="f64")
+
+
+def mesh_of_uniform(cfg, block, max_level, p_split=0.4, seed=0) -> dict:
+    """The same medium as the uniform grid of cfg (nx divisible by block)
+    on a composite mesh refined at random (each block split with probability
+    p_split): every cell takes the density (and alignment) of the root cell
+    holding it, so the optical properties are the same function of position."""
+    g = cfg["grid"]
+    rx, ry, rz = g["nx"] // block, g["ny"] // block, g["nz"] // block
+    rng = np.random.default_rng(seed)
+    grid = make_mesh_grid(g["x0"], g["y0"], g["z0"], g["dx"], rx, ry, rz, block, max_level,
+                          lambda lev, org, edge: rng.uniform() < p_split)
+    cen, _ = mesh_cells(grid)
+    ijk = np.floor((cen - np.array([g["x0"], g["y0"], g["z0"]])) / g["dx"]).astype(np.int64)
+    root = ijk[:, 0] + g["nx"] * (ijk[:, 1] + g["ny"] * ijk[:, 2])
+    out = dict(cfg, grid=grid, rho=np.ascontiguousarray(np.asarray(cfg["rho"])[root], dtype=np.float32))
+    if cfg.get("bhat") is not None:
+        out["bhat"] = np.ascontiguousarray(np.asarray(cfg["bhat"])[:, root], dtype=np.float32)
+    out["name"] = cfg["name"] + "_mesh"
+    return out
+
+
 def table_sphere(n=32, packets=100_000, albedo=1.0, tau_radius=1.0, g=0.5, seed=11,
                  views=None, npix=32, n_theta=361) -> dict:
     """The uniform sphere of uniform_sphere with grains of tabulated
