@@ -228,6 +228,39 @@ kp_status kp_set_grid(kp_ctx *ctx, const kp_grid *grid, const float *rho, const 
 kp_status kp_set_grid_device(kp_ctx *ctx, const kp_grid *grid, const float *d_rho,
                              const float *d_bhat);
 
+/* Composite mesh with static refinement (Sec. 2: the mesh grid the packets
+ * cross, optionally statically refined).  rx*ry*rz root blocks (x fastest)
+ * of block^3 cubic cells of edge dx tile the box from (x0, y0, z0); each
+ * block is a leaf or is refined into its 8 octants (octant bit 0: the upper
+ * half in x, bit 1: y, bit 2: z), blocks of block^3 cells of half the edge,
+ * to at most max_level refinements.  child[n_nodes] lists the blocks: the
+ * roots first (node r for root block r), then the 8 children of each
+ * refined node as 8 consecutive nodes after it; child[i] is -1 for a leaf,
+ * else the index of its first child.  Leaves are numbered in node order and
+ * cell k (x fastest) of leaf j is cell j*block^3 + k of every per-cell
+ * array: rho[ncell] (float32, finite, >= 0) and the optional alignment
+ * field bhat[3][ncell] as in kp_set_grid, ncell = leaves * block^3.  A
+ * packet or camera ray crosses a leaf's cells as on a uniform grid; leaving
+ * the block it continues in the leaf holding the exit point (a coordinate
+ * on a face belongs to the cell the direction points into).  Open
+ * boundaries; point sources (kinds 0, 1) and dipole grains only: thermal
+ * emission, peel-off and tabulated scattering are refused (KP_ERR_ARG) on a
+ * mesh.  1 <= block <= 64, 0 <= max_level <= 16, the box at most 2^30
+ * finest cells along each axis, ncell <= 4e9; KP_ERR_ARG for a malformed
+ * tree (a node with two parents or none, children before their parent or
+ * past the list, depth beyond max_level).  Copies the arrays to the
+ * device; replaces any grid (kp_set_grid replaces the mesh) and resets the
+ * tally. */
+typedef struct {
+  int32_t rx, ry, rz;
+  int32_t block;
+  int32_t max_level;
+  int32_t n_nodes;
+  double x0, y0, z0, dx;
+} kp_mesh;
+kp_status kp_set_mesh(kp_ctx *ctx, const kp_mesh *mesh, const int32_t *child, const float *rho,
+                      const float *bhat);
+
 /* Grain optics per wavelength (Sec. 2.2, eq. mfp-matrices and the
  * user-defined cross sections and Mueller matrices; Sec. 3 dipole grains):
  * n_lambda (1..1024) dust records, one per wavelength (copied).  KP_ERR_ARG

@@ -114,6 +114,14 @@ struct kp_ctx {
   size_t em_partial_n = 0;
   bool em_ready = false;  // tables match the current grid, dust and source function
   std::vector<double> em_L;
+  // composite mesh (kp_set_mesh): the tree and per-leaf origins and levels on
+  // the device; grid then holds the root-cell box
+  bool have_mesh = false;
+  kp_mesh mesh{};
+  int32_t* d_child = nullptr;
+  int32_t* d_leaf_of_node = nullptr;
+  int32_t* d_leaf_org = nullptr;  // [leaves][4]
+  int nfine[3] = {0, 0, 0};
   // tabulated scattering of every wavelength (kp_set_dust_tables): one
   // device array holding the normalised tables [n_lambda][n][6], the node
   // cosines [n] and the cumulative envelope masses [n_lambda][n]
@@ -173,6 +181,11 @@ kp_status ensure(kp_ctx* ctx, T** p, size_t* have, size_t need, const char* what
 }
 
 void release_grid(kp_ctx* ctx) {
+  for (int32_t** q : {&ctx->d_child, &ctx->d_leaf_of_node, &ctx->d_leaf_org}) {
+    if (*q) (void)hipFree(*q);
+    *q = nullptr;
+  }
+  ctx->have_mesh = false;
   if (ctx->own_rho) (void)hipFree(ctx->own_rho);
   if (ctx->own_bhat) (void)hipFree(ctx->own_bhat);
   ctx->own_rho = ctx->own_bhat = nullptr;
@@ -271,8 +284,26 @@ kp_status upload_small(kp_ctx* ctx, hipStream_t s) {
   return KP_OK;
 }
 
+MeshDev mesh_dev(const kp_ctx* ctx) {
+  MeshDev m{};
+  if (!ctx->have_mesh) return m;
+  m.child = ctx->d_child;
+  m.leaf_of_node = ctx->d_leaf_of_node;
+  m.leaf_org = ctx->d_leaf_org;
+  m.rx = ctx->mesh.rx; m.ry = ctx->mesh.ry; m.rz = ctx->mesh.rz;
+  m.block = ctx->mesh.block;
+  m.max_level = ctx->mesh.max_level;
+  for (int k = 0; k < 3; ++k) m.nfine[k] = ctx->nfine[k];
+  m.fine = std::ldexp(ctx->mesh.dx, -ctx->mesh.max_level);
+  return m;
+}
+
 kp_status check_ready(kp_ctx* ctx) {
   if (!ctx->have_grid) return fail(ctx, KP_ERR_STATE, "kp_set_grid has not been called");
+  if (ctx->have_mesh && ctx->src.kind == 2)
+    return fail(ctx, KP_ERR_ARG, "thermal emission is not supported on a composite mesh");
+  if (ctx->have_mesh && ctx->have_tables)
+    return fail(ctx, KP_ERR_ARG, "tabulated scattering is not supported on a composite mesh");
   if (ctx->dust.empty()) return fail(ctx, KP_ERR_STATE, "kp_set_dust has not been called");
   if (!ctx->have_source) return fail(ctx, KP_ERR_STATE, "kp_set_source has not been called");
   if (ctx->views.empty()) return fail(ctx, KP_ERR_STATE, "kp_set_views has not been called");
@@ -336,6 +367,7 @@ kp_status image_launch(kp_ctx* ctx, bool user_source, const double* d_S, double*
   a.ncell = ctx->ncell;
   a.em_B = ((!user_source || from_tally) && ctx->src.kind == 2) ? ctx->d_em_B : nullptr;
   a.boundary = ctx->grid.boundary;
+  a.mesh = mesh_dev(ctx);
   // every wavelength shares the grain model kind of wavelength 0 for the
   // kernel choice; mixed sphere / non-sphere tables use the general kernel
   bool sphere = true;
@@ -344,7 +376,7 @@ kp_status image_launch(kp_ctx* ctx, bool user_source, const double* d_S, double*
   // tabulated grains are randomly oriented: the alignment directions do not
   // enter their extinction
   const bool aligned = ctx->d_bhat != nullptr && !ctx->have_tables;
-  KP_HIP(launch_image(a, aligned, sphere, user_source, s), "imaging kernel launch");
+  KP_HIP(launch_image(a, aligned, sphere, user_source, ctx->have_mesh, s), "imaging kernel launch");
   KP_HIP(hipEventRecord(ctx->ev[3], s), "event record");
   return KP_OK;
 }
@@ -416,6 +448,8 @@ kp_status check_run_args(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, 
   if (o->peel_off != 0 && o->peel_off != 1) return fail(ctx, KP_ERR_ARG, "peel_off must be 0 or 1");
   if (o->peel_off && ctx->grid.boundary)
     return fail(ctx, KP_ERR_ARG, "peel-off imaging needs open boundaries (boundary 0)");
+  if (o->peel_off && ctx->have_mesh)
+    return fail(ctx, KP_ERR_ARG, "peel-off imaging is not supported on a composite mesh");
   *total_out = total;
   return KP_OK;
 }
@@ -487,6 +521,7 @@ kp_status transport_launch(kp_ctx* ctx, const kp_opts* o, uint64_t total, const 
     a.em_guide = ctx->d_em_guide;
   }
   a.boundary = ctx->grid.boundary;
+  a.mesh = mesh_dev(ctx);
   a.views = b.views;
   a.n_views = nv;
   if (b.peel) {
@@ -503,7 +538,7 @@ kp_status transport_launch(kp_ctx* ctx, const kp_opts* o, uint64_t total, const 
   const int bs = o->block_size ? o->block_size : 256;
   int bpc = o->blocks_per_cu;
   if (bpc == 0) {
-    bpc = transport_max_blocks_per_cu(fp64, aligned, sphere, b.peel != nullptr, tab, bs);
+    bpc = transport_max_blocks_per_cu(fp64, aligned, sphere, b.peel != nullptr, tab, ctx->have_mesh, bs);
     if (bpc < 1) bpc = 1;
     if (bpc > 8) bpc = 8;
   }
@@ -511,7 +546,7 @@ kp_status transport_launch(kp_ctx* ctx, const kp_opts* o, uint64_t total, const 
   const uint64_t need_blocks = (total + bs - 1) / bs;
   if (blocks > need_blocks) blocks = need_blocks;
   KP_HIP(hipEventRecord(ctx->ev[0], s), "event record");
-  KP_HIP(launch_transport(a, fp64, aligned, sphere, b.peel != nullptr, tab, (int)blocks, bs, s),
+  KP_HIP(launch_transport(a, fp64, aligned, sphere, b.peel != nullptr, tab, ctx->have_mesh, (int)blocks, bs, s),
          "transport kernel launch");
   KP_HIP(hipEventRecord(ctx->ev[1], s), "event record");
   KP_HIP(hipStreamSynchronize(s), "transport kernel");
@@ -637,6 +672,96 @@ kp_status kp_set_grid_device(kp_ctx* ctx, const kp_grid* g, const float* d_rho, 
   ctx->d_bhat = const_cast<float*>(d_bhat);
   ctx->grid = *g;
   ctx->ncell = n;
+  ctx->have_grid = true;
+  return KP_OK;
+}
+
+kp_status kp_set_mesh(kp_ctx* ctx, const kp_mesh* m, const int32_t* child, const float* rho,
+                      const float* bhat) {
+  if (!ctx) return KP_ERR_ARG;
+  if (!m || !child || !rho) return fail(ctx, KP_ERR_ARG, "mesh, child or rho is NULL");
+  if (m->rx < 1 || m->ry < 1 || m->rz < 1 || m->block < 1 || m->block > 64)
+    return fail(ctx, KP_ERR_ARG, "root blocks must be >= 1 per axis and block in 1..64");
+  if (m->max_level < 0 || m->max_level > 16) return fail(ctx, KP_ERR_ARG, "max_level must be in 0..16");
+  if (!(m->dx > 0.0) || !std::isfinite(m->dx) || !std::isfinite(m->x0) || !std::isfinite(m->y0) ||
+      !std::isfinite(m->z0))
+    return fail(ctx, KP_ERR_ARG, "dx must be finite and > 0 and the corner finite");
+  const int64_t full = (int64_t)m->block << m->max_level;
+  const int64_t R = (int64_t)m->rx * m->ry * m->rz;
+  const int64_t ext[3] = {m->rx * full, m->ry * full, m->rz * full};
+  for (int k = 0; k < 3; ++k)
+    if (ext[k] > ((int64_t)1 << 30)) return fail(ctx, KP_ERR_ARG, "the box exceeds 2^30 finest cells along an axis");
+  if (m->n_nodes < R || m->n_nodes > (1 << 30)) return fail(ctx, KP_ERR_ARG, "n_nodes must cover the root blocks");
+  // parents, levels and origins of every node; children after their parent
+  const int32_t N = m->n_nodes;
+  std::vector<int32_t> parents(N, 0), lev(N, 0);
+  std::vector<int64_t> org(3 * (size_t)N, 0);
+  for (int64_t r = 0; r < R; ++r) {
+    org[3 * r] = (r % m->rx) * full;
+    org[3 * r + 1] = ((r / m->rx) % m->ry) * full;
+    org[3 * r + 2] = (r / ((int64_t)m->rx * m->ry)) * full;
+  }
+  for (int32_t i = 0; i < N; ++i) {
+    const int32_t c = child[i];
+    if (c == -1) continue;
+    if (c < R || c <= i || (int64_t)c + 8 > N || lev[i] + 1 > m->max_level)
+      return fail(ctx, KP_ERR_ARG, "node %d: child index %d invalid (before its parent, past the list or "
+                  "deeper than max_level)", i, c);
+    const int64_t half = full >> (lev[i] + 1);
+    for (int k = 0; k < 8; ++k) {
+      if (parents[c + k]++) return fail(ctx, KP_ERR_ARG, "node %d has two parents", c + k);
+      lev[c + k] = lev[i] + 1;
+      org[3 * (size_t)(c + k)] = org[3 * (size_t)i] + ((k & 1) ? half : 0);
+      org[3 * (size_t)(c + k) + 1] = org[3 * (size_t)i + 1] + ((k & 2) ? half : 0);
+      org[3 * (size_t)(c + k) + 2] = org[3 * (size_t)i + 2] + ((k & 4) ? half : 0);
+    }
+  }
+  for (int32_t i = (int32_t)R; i < N; ++i)
+    if (parents[i] != 1) return fail(ctx, KP_ERR_ARG, "node %d is nobody's child", i);
+  std::vector<int32_t> leaf_of_node(N, -1), leaf_org;
+  int64_t nleaf = 0;
+  for (int32_t i = 0; i < N; ++i) {
+    if (child[i] != -1) continue;
+    leaf_of_node[i] = (int32_t)nleaf++;
+    leaf_org.insert(leaf_org.end(), {(int32_t)org[3 * (size_t)i], (int32_t)org[3 * (size_t)i + 1],
+                                     (int32_t)org[3 * (size_t)i + 2], lev[i]});
+  }
+  const uint64_t B3 = (uint64_t)m->block * m->block * m->block;
+  const uint64_t n = (uint64_t)nleaf * B3;
+  if ((double)n > 4.0e9) return fail(ctx, KP_ERR_ARG, "the mesh has more than 4e9 cells");
+  for (uint64_t i = 0; i < n; ++i)
+    if (!(rho[i] >= 0.0f) || !std::isfinite(rho[i]))
+      return fail(ctx, KP_ERR_ARG, "rho[%llu] is negative or not finite", (unsigned long long)i);
+  if (bhat)
+    for (uint64_t i = 0; i < n; ++i) {
+      const double b = std::sqrt((double)bhat[i] * bhat[i] + (double)bhat[n + i] * bhat[n + i] +
+                                 (double)bhat[2 * n + i] * bhat[2 * n + i]);
+      if (!(std::fabs(b - 1.0) <= 1e-5))
+        return fail(ctx, KP_ERR_ARG, "bhat[:, %llu] is not a unit vector", (unsigned long long)i);
+    }
+  KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+  release_grid(ctx);
+  KP_HIP(hipMalloc(&ctx->own_rho, n * sizeof(float)), "rho allocation");
+  KP_HIP(hipMemcpy(ctx->own_rho, rho, n * sizeof(float), hipMemcpyHostToDevice), "rho upload");
+  if (bhat) {
+    KP_HIP(hipMalloc(&ctx->own_bhat, 3 * n * sizeof(float)), "bhat allocation");
+    KP_HIP(hipMemcpy(ctx->own_bhat, bhat, 3 * n * sizeof(float), hipMemcpyHostToDevice), "bhat upload");
+  }
+  KP_HIP(hipMalloc(&ctx->d_child, N * sizeof(int32_t)), "mesh allocation");
+  KP_HIP(hipMalloc(&ctx->d_leaf_of_node, N * sizeof(int32_t)), "mesh allocation");
+  KP_HIP(hipMalloc(&ctx->d_leaf_org, leaf_org.size() * sizeof(int32_t)), "mesh allocation");
+  KP_HIP(hipMemcpy(ctx->d_child, child, N * sizeof(int32_t), hipMemcpyHostToDevice), "mesh upload");
+  KP_HIP(hipMemcpy(ctx->d_leaf_of_node, leaf_of_node.data(), N * sizeof(int32_t), hipMemcpyHostToDevice),
+         "mesh upload");
+  KP_HIP(hipMemcpy(ctx->d_leaf_org, leaf_org.data(), leaf_org.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+         "mesh upload");
+  ctx->d_rho = ctx->own_rho;
+  ctx->d_bhat = ctx->own_bhat;
+  ctx->grid = kp_grid{m->rx * m->block, m->ry * m->block, m->rz * m->block, m->x0, m->y0, m->z0, m->dx, 0};
+  ctx->ncell = n;
+  ctx->mesh = *m;
+  for (int k = 0; k < 3; ++k) ctx->nfine[k] = (int)ext[k];
+  ctx->have_mesh = true;
   ctx->have_grid = true;
   return KP_OK;
 }

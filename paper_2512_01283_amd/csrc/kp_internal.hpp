@@ -57,6 +57,20 @@ struct TraceDev {
   double tau_path;
 };
 
+// Composite mesh with static refinement (device view): root blocks of
+// block^3 cells on an rx*ry*rz array, each the root of a tree of blocks split
+// into octants; cells of leaf j have flat indices j*block^3 + local (x
+// fastest).  Positions in units of the finest cell (2^-max_level of a root
+// cell) locate leaves.
+struct MeshDev {
+  const int32_t* child;         // [n_nodes]: -1 leaf, else the first of 8 children
+  const int32_t* leaf_of_node;  // [n_nodes]: leaf id or -1
+  const int32_t* leaf_org;      // [n_leaves][4]: lower corner (finest cells), level
+  int rx, ry, rz, block, max_level;
+  int nfine[3];                 // domain extent in finest cells
+  double fine;                  // finest cell edge
+};
+
 // a packet ends as an event-cap packet after this many cell steps (one that
 // cannot scatter and moves parallel to every open face of a partly periodic
 // grid would never leave it); camera rays longer than this many cells are
@@ -101,6 +115,7 @@ struct TransportArgs {
   const ViewDev* views;
   int n_views, npx, npy;
   double* peel;
+  MeshDev mesh;          // the kernels instantiated for a composite mesh
 };
 
 struct ImageArgs {
@@ -120,6 +135,7 @@ struct ImageArgs {
   const float* em_B;    // [lambda][ncell] source function of the dust's thermal
                         // emission, or null (no thermal source term)
   int boundary;         // bit a: axis a periodic
+  MeshDev mesh;         // the kernels instantiated for a composite mesh
 };
 
 // Tally layout [lambda][cell][stride] FP64: 6 reals (stride 8, one 64-B block
@@ -132,15 +148,16 @@ inline int tally_stride(bool sphere) { return sphere ? 8 : 16; }
 
 // launchers (kp_kernels.hip)
 hipError_t launch_transport(const TransportArgs& a, bool fp64, bool aligned, bool sphere, bool peel, bool tab,
-                            int blocks, int block_size, hipStream_t s);
-hipError_t launch_image(const ImageArgs& a, bool aligned, bool sphere, bool user_source,
+                            bool mesh, int blocks, int block_size, hipStream_t s);
+hipError_t launch_image(const ImageArgs& a, bool aligned, bool sphere, bool user_source, bool mesh,
                         hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_tally_init(double* tally, const float* rho, const float* bx, const float* by,
                              const float* bz, uint64_t ncell, int n_lambda, bool sphere, hipStream_t s);
 hipError_t launch_validate(const float* rho, const float* bx, const float* by, const float* bz,
                            uint64_t n, unsigned long long* bad, hipStream_t s);
-int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, bool peel, bool tab, int block_size);
+int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, bool peel, bool tab, bool mesh,
+                                int block_size);
 // Thermal emission tables of one wavelength: cdf [ncell], the running sum
 // of fac rho B (fac = 4 pi kappa_abs dx^3) in flat cell order, and its guide
 // table [ncell + 1]; `partial` holds emission_blocks(ncell) doubles of

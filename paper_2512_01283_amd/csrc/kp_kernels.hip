@@ -83,6 +83,7 @@ struct Packet {
   uint64_t pid, hash;
   int64_t last;
   int ci, cj, ck;
+  int leaf, lvl;      // composite mesh: the leaf block (ci..ck local to it) and its level
   uint32_t draw, blk;
   int events, steps, trials, lam, rr;
 };
@@ -156,7 +157,93 @@ __device__ __forceinline__ uint64_t emission_cell(const double* F, const uint32_
 // basis; its mean over directions is w.  Draws: cell, three coordinates,
 // two for the direction.  Then an exponential scattering depth.  Returns
 // false if a point source lies outside the grid.
-template <typename R, bool ALIGNED, bool SPHERE>
+// ---------------------------------------------------------------------------
+// Composite mesh with static refinement (Sec. 2: the mesh the packets
+// cross).  Inside a leaf block the cell walk is the uniform one; leaving it,
+// the point is expressed in finest-cell units (exact on the crossed face,
+// since cell edges are powers of two of the finest one), its finest cell
+// taken with the face rule (a coordinate on a face belongs to the cell the
+// direction points into), and the leaf holding that cell found by
+// descending from its root block.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long long finest_cell(double t, double n) {
+  const double fl = floor(t);
+  long long X = (long long)fl;
+  if (fl == t && n < 0.0) X -= 1;
+  return X;
+}
+
+__device__ __forceinline__ int mesh_find(const MeshDev& m, const long long X[3]) {
+  const long long full = (long long)m.block << m.max_level;
+  const long long r0 = X[0] / full, r1 = X[1] / full, r2 = X[2] / full;
+  int node = (int)(r0 + (long long)m.rx * (r1 + (long long)m.ry * r2));
+  long long o0 = r0 * full, o1 = r1 * full, o2 = r2 * full, size = full;
+  for (int c = m.child[node]; c >= 0; c = m.child[node]) {
+    size >>= 1;
+    int oct = 0;
+    if (X[0] - o0 >= size) { oct |= 1; o0 += size; }
+    if (X[1] - o1 >= size) { oct |= 2; o1 += size; }
+    if (X[2] - o2 >= size) { oct |= 4; o2 += size; }
+    node = c + oct;
+  }
+  return m.leaf_of_node[node];
+}
+
+// the packet at finest-unit position t in finest cell X: leaf, local cell,
+// fractions, and the cell-length constants of the leaf's level
+template <typename R>
+__device__ __forceinline__ void mesh_place(Packet<R>& p, const TransportArgs& a, const double t[3],
+                                           const long long X[3]) {
+  const MeshDev& m = a.mesh;
+  const int j = mesh_find(m, X);
+  const int4 o = reinterpret_cast<const int4*>(m.leaf_org)[j];
+  const int sh = m.max_level - o.w;
+  const double s = (double)(1ll << sh);
+  p.leaf = j;
+  p.lvl = o.w;
+  const long long i0 = (X[0] - o.x) >> sh, i1 = (X[1] - o.y) >> sh, i2 = (X[2] - o.z) >> sh;
+  p.ci = (int)i0; p.cj = (int)i1; p.ck = (int)i2;
+  p.fx = fmin(1.0, fmax(0.0, (t[0] - (double)o.x) / s - (double)i0));
+  p.fy = fmin(1.0, fmax(0.0, (t[1] - (double)o.y) / s - (double)i1));
+  p.fz = fmin(1.0, fmax(0.0, (t[2] - (double)o.z) / s - (double)i2));
+  const DustDev& D = a.dust[p.lam];
+  const double sc = ldexp(1.0, -o.w);
+  p.ks = D.ks_cell * sc;
+  p.ke = D.ke_cell * sc;
+  p.ka = (R)(D.ka_cell * sc);
+}
+
+// after a face crossing moved a local index out of the leaf block: the leaf
+// beyond, or true if the packet left the domain
+template <typename R>
+__device__ bool mesh_cross(Packet<R>& p, const TransportArgs& a) {
+  const MeshDev& m = a.mesh;
+  const int4 o = reinterpret_cast<const int4*>(m.leaf_org)[p.leaf];
+  const double s = (double)(1ll << (m.max_level - o.w));
+  const double t[3] = {(double)o.x + ((double)p.ci + p.fx) * s, (double)o.y + ((double)p.cj + p.fy) * s,
+                       (double)o.z + ((double)p.ck + p.fz) * s};
+  const double n[3] = {p.nx, p.ny, p.nz};
+  long long X[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    X[k] = finest_cell(t[k], n[k]);
+    if (X[k] < 0 || X[k] >= m.nfine[k]) return true;
+  }
+  mesh_place(p, a, t, X);
+  return false;
+}
+
+// flat index of the packet's cell
+template <bool MESH, typename R>
+__device__ __forceinline__ uint64_t cell_index(const Packet<R>& p, const TransportArgs& a) {
+  if (MESH) {
+    const uint64_t B = (uint64_t)a.mesh.block;
+    return (uint64_t)p.leaf * B * B * B + (uint64_t)p.ci + B * ((uint64_t)p.cj + B * (uint64_t)p.ck);
+  }
+  return (uint64_t)p.ci + (uint64_t)a.nx * ((uint64_t)p.cj + (uint64_t)a.ny * p.ck);
+}
+
+template <typename R, bool ALIGNED, bool SPHERE, bool MESH>
 __device__ bool init_packet(Packet<R>& p, uint64_t g, const TransportArgs& a) {
   int lo = 0, hi = a.n_lambda - 1;
   while (lo < hi) {  // last wavelength whose first index <= g
@@ -216,6 +303,23 @@ __device__ bool init_packet(Packet<R>& p, uint64_t g, const TransportArgs& a) {
     p.I = p.w0; p.Q = (R)0; p.U = (R)0; p.V = (R)0;
     const double pos[3] = {a.sx, a.sy, a.sz}, org[3] = {a.x0, a.y0, a.z0};
     const double dir[3] = {p.nx, p.ny, p.nz};
+    if (MESH) {
+      // the finest cell holding the source (face rule), then its leaf
+      double t[3];
+      long long X[3];
+      in = true;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        t[k] = (pos[k] - org[k]) / a.mesh.fine;
+        X[k] = finest_cell(t[k], dir[k]);
+        in = in && X[k] >= 0 && X[k] < a.mesh.nfine[k];
+      }
+      if (in) mesh_place(p, a, t, X);
+      p.rho = in ? a.rho[cell_index<true>(p, a)] : 0.f;
+      p.rnx = 1.0 / p.nx; p.rny = 1.0 / p.ny; p.rnz = 1.0 / p.nz;
+      p.tau = -log((double)next_uniform(p, a.seed));
+      return in;
+    }
     int ci[3];
     double fr[3];
 #pragma unroll
@@ -615,19 +719,19 @@ __device__ bool scatter_tab(Packet<R>& p, const DustDev& D, uint64_t seed) {
 }
 
 template <typename R>
-__device__ uint32_t roulette(Packet<R>& p, const TransportArgs& a);
+__device__ uint32_t roulette(Packet<R>& p, const TransportArgs& a, uint64_t cn);
 
 // One loop iteration: one cell segment (Sec. 2.2: cell-to-cell traversal,
 // exponential scattering depth, continuous extinction across the segment by
 // the analytic cell solution of Appendix A, tally of the segment into the
 // scattering source of Sec. 2.3), then a scattering event or the crossing
 // into the next cell, then Russian roulette.  Returns 0 or an end kind.
-template <typename R, bool ALIGNED, bool SPHERE, bool TAB>
+template <typename R, bool ALIGNED, bool SPHERE, bool TAB, bool MESH>
 __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_t& key,
                          R cc[TallyShape<SPHERE>::NC], bool& pending) {
   constexpr int NC = TallyShape<SPHERE>::NC;
   static_assert(!TAB || (SPHERE && !ALIGNED), "tabulated grains have scalar extinction");
-  const uint64_t c = (uint64_t)p.ci + (uint64_t)a.nx * ((uint64_t)p.cj + (uint64_t)a.ny * p.ck);
+  const uint64_t c = cell_index<MESH>(p, a);
   p.last = (int64_t)c;
   if (p.events >= a.max_events || p.steps >= KP_MAX_STEPS) {
     p.hash = hash_event(p.hash, END_BUDGET, c);
@@ -754,30 +858,33 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
     if (axis != 2) p.fz = fmin(1.0, fmax(0.0, p.fz + td * dnz));
     bool out;
     // leaving through an open face ends the packet; a periodic face brings
-    // it back through the opposite one
+    // it back through the opposite one; on a mesh, leaving the leaf block
+    // moves it into the leaf beyond
     const bool per = (a.boundary >> axis) & 1;
+    const int nbx = MESH ? a.mesh.block : a.nx, nby = MESH ? a.mesh.block : a.ny;
+    const int nbz = MESH ? a.mesh.block : a.nz;
     if (axis == 0) {
       if (dnx > 0.0) { p.ci++; p.fx = 0.0; } else { p.ci--; p.fx = 1.0; }
-      out = p.ci < 0 || p.ci >= a.nx;
+      out = p.ci < 0 || p.ci >= nbx;
       if (out && per) { p.ci = p.ci < 0 ? a.nx - 1 : 0; out = false; }
     } else if (axis == 1) {
       if (dny > 0.0) { p.cj++; p.fy = 0.0; } else { p.cj--; p.fy = 1.0; }
-      out = p.cj < 0 || p.cj >= a.ny;
+      out = p.cj < 0 || p.cj >= nby;
       if (out && per) { p.cj = p.cj < 0 ? a.ny - 1 : 0; out = false; }
     } else {
       if (dnz > 0.0) { p.ck++; p.fz = 0.0; } else { p.ck--; p.fz = 1.0; }
-      out = p.ck < 0 || p.ck >= a.nz;
+      out = p.ck < 0 || p.ck >= nbz;
       if (out && per) { p.ck = p.ck < 0 ? a.nz - 1 : 0; out = false; }
     }
+    if (MESH && out) out = mesh_cross(p, a);
     if (out) {
       p.hash = hash_event(p.hash, END_ESCAPE, c);
       return END_ESCAPE;
     }
     // the next step's density, in flight while this iteration finishes
-    if (!TallyShape<SPHERE>::HAS_B)
-      p.rho = a.rho[(uint64_t)p.ci + (uint64_t)a.nx * ((uint64_t)p.cj + (uint64_t)a.ny * p.ck)];
+    if (!TallyShape<SPHERE>::HAS_B) p.rho = a.rho[cell_index<MESH>(p, a)];
   }
-  return roulette(p, a);
+  return roulette(p, a, cell_index<MESH>(p, a));
 }
 
 // ---------------------------------------------------------------------------
@@ -1000,9 +1107,9 @@ __device__ void wave_drain_views(const TransportArgs& a, double* sv, long long* 
 
 // Scattering event at the packet's current position (Sec. 2.2), the next
 // scattering depth, and the roulette check that follows every segment.
-template <typename R, bool ALIGNED, bool SPHERE, bool PEEL, bool TAB>
+template <typename R, bool ALIGNED, bool SPHERE, bool PEEL, bool TAB, bool MESH>
 __device__ uint32_t scatter_step(Packet<R>& p, const TransportArgs& a) {
-  const uint64_t c = (uint64_t)p.ci + (uint64_t)a.nx * ((uint64_t)p.cj + (uint64_t)a.ny * p.ck);
+  const uint64_t c = cell_index<MESH>(p, a);
   const DustDev& D = a.dust[p.lam];
   Quat<R> q{(R)1, (R)0, (R)0, (R)0};
   Quat<double> qd{1.0, 0.0, 0.0, 0.0};
@@ -1020,15 +1127,14 @@ __device__ uint32_t scatter_step(Packet<R>& p, const TransportArgs& a) {
   p.events++;
   p.hash = hash_event(p.hash, EV_SCATTER, c);
   p.tau = -log((double)next_uniform(p, a.seed));
-  return roulette(p, a);
+  return roulette(p, a, c);
 }
 
+// Russian roulette after a segment or an event in cell cn (reading R8).
 template <typename R>
-__device__ uint32_t roulette(Packet<R>& p, const TransportArgs& a) {
+__device__ uint32_t roulette(Packet<R>& p, const TransportArgs& a, uint64_t cn) {
   if (!isfinite(p.I)) return END_NUMERIC;
   if (a.rr_wmin > 0.0 && p.I < (R)a.rr_wmin * p.w0) {
-    const uint64_t cn =
-        (uint64_t)p.ci + (uint64_t)a.nx * ((uint64_t)p.cj + (uint64_t)a.ny * p.ck);
     R u = next_uniform(p, a.seed);
     if (u < (R)a.rr_psurv) {
       const R before = p.I, inv = (R)1 / (R)a.rr_psurv;
@@ -1082,7 +1188,7 @@ __device__ void finish(const Packet<R>& p, uint32_t end, const TransportArgs& a,
   }
 }
 
-template <typename R, bool ALIGNED, bool SPHERE, bool PEEL, bool TAB>
+template <typename R, bool ALIGNED, bool SPHERE, bool PEEL, bool TAB, bool MESH>
 __device__ __forceinline__ void transport_body(const TransportArgs& a) {
   constexpr int NC = TallyShape<SPHERE>::NC, TS = TallyShape<SPHERE>::TS;
   __shared__ unsigned long long sc[SC_N];
@@ -1153,7 +1259,7 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
             const bool have = r < rem || refill;
             const unsigned long long g = r < rem ? wnext + r : base + (r - rem);
             if (have && g < a.total) {
-              const bool in = init_packet<R, ALIGNED, SPHERE>(p, g, a);
+              const bool in = init_packet<R, ALIGNED, SPHERE, MESH>(p, g, a);
               atomicAdd(&se[SE_EMIT], (double)p.I);  // the emitted intensity
               if (in) active = true;
               else finish(p, END_ESCAPE, a, sc, se);
@@ -1174,7 +1280,7 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
             const unsigned long long below = idle & ((1ull << lane) - 1ull);
             const unsigned long long g = base + (unsigned long long)__popcll(below);
             if (g < a.total) {
-              const bool in = init_packet<R, ALIGNED, SPHERE>(p, g, a);
+              const bool in = init_packet<R, ALIGNED, SPHERE, MESH>(p, g, a);
               atomicAdd(&se[SE_EMIT], (double)p.I);  // the emitted intensity
               if (in) active = true;
               else finish(p, END_ESCAPE, a, sc, se);
@@ -1190,7 +1296,7 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
     int64_t key = -1;
     R cc[NC];
     if (active && !pending) {
-      const uint32_t end = step<R, ALIGNED, SPHERE, TAB>(p, a, has, key, cc, pending);
+      const uint32_t end = step<R, ALIGNED, SPHERE, TAB, MESH>(p, a, has, key, cc, pending);
       if (end) {
         finish(p, end, a, sc, se);
         active = false;
@@ -1229,7 +1335,7 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
         waited = 0;
         if (pending) {
           pending = false;
-          const uint32_t end = scatter_step<R, ALIGNED, SPHERE, PEEL, TAB>(p, a);
+          const uint32_t end = scatter_step<R, ALIGNED, SPHERE, PEEL, TAB, MESH>(p, a);
           if (end) {
             finish(p, end, a, sc, se);
             active = false;
@@ -1258,14 +1364,14 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
 // so they run unbounded at one wave per SIMD.  PEEL adds peel-off imaging at
 // every scattering event (a separate instantiation: the kernels without it
 // are unchanged).
-template <bool ALIGNED, bool SPHERE, bool PEEL, bool TAB>
+template <bool ALIGNED, bool SPHERE, bool PEEL, bool TAB, bool MESH>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_transport32(TransportArgs a) {
-  transport_body<float, ALIGNED, SPHERE, PEEL, TAB>(a);
+  transport_body<float, ALIGNED, SPHERE, PEEL, TAB, MESH>(a);
 }
-template <bool ALIGNED, bool SPHERE, bool PEEL, bool TAB>
+template <bool ALIGNED, bool SPHERE, bool PEEL, bool TAB, bool MESH>
 __global__ void __launch_bounds__(256) k_transport64(TransportArgs a) {
-  transport_body<double, ALIGNED, SPHERE, PEEL, TAB>(a);
+  transport_body<double, ALIGNED, SPHERE, PEEL, TAB, MESH>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1275,8 +1381,12 @@ __global__ void __launch_bounds__(256) k_transport64(TransportArgs a) {
 // extinction for the camera direction and the scattering source formed from
 // the coherency tally (or a caller-given per-view source).  FP64 throughout.
 // ---------------------------------------------------------------------------
-template <bool ALIGNED, bool SPHERE, bool USER_S>
+template <bool ALIGNED, bool SPHERE, bool USER_S, bool MESH>
 __global__ void __launch_bounds__(256) k_image(ImageArgs a) {
+  // No fused multiply-adds: a ray that grazes a cell face (a pixel centre on
+  // a face, drifting off it by ~1e-16 per cell) then takes the face-side
+  // decisions of a plain (unfused) evaluation of the same expressions.
+#pragma clang fp contract(off)
   const uint64_t npix = (uint64_t)a.npx * a.npy;
   const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t total = npix * a.n_views * a.n_lambda;
@@ -1312,8 +1422,35 @@ __global__ void __launch_bounds__(256) k_image(ImageArgs a) {
   if (!miss && sn < sf) {
     int ci[3];
     double f[3];
+    // composite mesh: the leaf block of the ray, its level and origin
+    int leaf = 0, lvl = 0, sh = 0;
+    int4 org{0, 0, 0, 0};
+    const MeshDev& m = a.mesh;
+    const uint64_t B = MESH ? (uint64_t)m.block : 0;
+    if (MESH) {
+      // the entry point in finest cells, clamped into the domain
+      double t[3];
+      long long X[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
+      for (int k = 0; k < 3; ++k) {
+        t[k] = (P0[k] + sn * om[k] - lo[k]) / m.fine;
+        X[k] = (long long)floor(t[k]);
+        X[k] = X[k] < 0 ? 0 : (X[k] > m.nfine[k] - 1 ? m.nfine[k] - 1 : X[k]);
+      }
+      leaf = mesh_find(m, X);
+      org = reinterpret_cast<const int4*>(m.leaf_org)[leaf];
+      lvl = org.w;
+      sh = m.max_level - lvl;
+      const long long X0[3] = {org.x, org.y, org.z};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const long long i = (X[k] - X0[k]) >> sh;
+        ci[k] = (int)i;
+        f[k] = fmin(1.0, fmax(0.0, (t[k] - (double)X0[k]) / (double)(1ll << sh) - (double)i));
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 3 && !MESH; ++k) {
       const double t = (P0[k] + sn * om[k] - lo[k]) / a.dx;
       const double fl = floor(t);
       if ((a.boundary >> k) & 1) {
@@ -1330,7 +1467,8 @@ __global__ void __launch_bounds__(256) k_image(ImageArgs a) {
     const V3<double> Om{om[0], om[1], om[2]};
     const V3<double> e1{vw.tx, vw.ty, vw.tz}, e2{vw.px, vw.py, vw.pz};
     const double kext = D.kext;
-    const double inv_vol = 1.0 / (a.dx * a.dx * a.dx);
+    double clen = MESH ? ldexp(a.dx, -lvl) : a.dx;
+    double inv_vol = 1.0 / (clen * clen * clen);
     while (true) {
       double tb = __builtin_huge_val();
       int axis = -1;
@@ -1343,11 +1481,12 @@ __global__ void __launch_bounds__(256) k_image(ImageArgs a) {
         if (t < tb) { tb = t; axis = k; }
       }
       if (axis < 0) break;
-      const uint64_t c = (uint64_t)ci[0] + (uint64_t)a.nx * ((uint64_t)ci[1] + (uint64_t)a.ny * ci[2]);
+      const uint64_t c = MESH ? (uint64_t)leaf * B * B * B + (uint64_t)ci[0] + B * ((uint64_t)ci[1] + B * ci[2])
+                              : (uint64_t)ci[0] + (uint64_t)a.nx * ((uint64_t)ci[1] + (uint64_t)a.ny * ci[2]);
       const double rho = (double)a.rho[c];
       if (rho > 0.0) {
         const double ke = rho * kext;
-        const double dtau = ke * tb * a.dx;
+        const double dtau = ke * tb * clen;
         double S[4];
         Quat<double> q{1.0, 0.0, 0.0, 0.0};
         if (ALIGNED) q = grain_quat(V3<double>{(double)a.bx[c], (double)a.by[c], (double)a.bz[c]});
@@ -1398,6 +1537,36 @@ __global__ void __launch_bounds__(256) k_image(ImageArgs a) {
       for (int k = 0; k < 3; ++k)
         if (k != axis) f[k] = fmin(1.0, fmax(0.0, f[k] + tb * om[k]));
       if (om[axis] > 0.0) { ci[axis]++; f[axis] = 0.0; } else { ci[axis]--; f[axis] = 1.0; }
+      if (MESH) {
+        if (ci[axis] >= 0 && ci[axis] < (int)B) continue;
+        // the leaf beyond the block face (finest-cell units, face rule)
+        const double sz = (double)(1ll << sh);
+        const long long X0[3] = {org.x, org.y, org.z};
+        double t[3];
+        long long X[3];
+        bool left = false;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          t[k] = (double)X0[k] + ((double)ci[k] + f[k]) * sz;
+          X[k] = finest_cell(t[k], om[k]);
+          left = left || X[k] < 0 || X[k] >= m.nfine[k];
+        }
+        if (left) break;
+        leaf = mesh_find(m, X);
+        org = reinterpret_cast<const int4*>(m.leaf_org)[leaf];
+        lvl = org.w;
+        sh = m.max_level - lvl;
+        const long long X1[3] = {org.x, org.y, org.z};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const long long i = (X[k] - X1[k]) >> sh;
+          ci[k] = (int)i;
+          f[k] = fmin(1.0, fmax(0.0, (t[k] - (double)X1[k]) / (double)(1ll << sh) - (double)i));
+        }
+        clen = ldexp(a.dx, -lvl);
+        inv_vol = 1.0 / (clen * clen * clen);
+        continue;
+      }
       if (ci[axis] < 0 || ci[axis] >= nn[axis]) {
         if (!((a.boundary >> axis) & 1)) break;
         ci[axis] = ci[axis] < 0 ? nn[axis] - 1 : 0;
@@ -1568,38 +1737,63 @@ hipError_t launch_emission_table(const float* rho, const float* B, double fac, u
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <bool A, bool S, bool T>
+template <bool A, bool S, bool T, bool M>
 static void launch_one(const TransportArgs& a, bool fp64, bool peel, int blocks, int bs, hipStream_t s) {
-  if (fp64 && peel) hipLaunchKernelGGL((k_transport64<A, S, true, T>), dim3(blocks), dim3(bs), 0, s, a);
-  else if (fp64) hipLaunchKernelGGL((k_transport64<A, S, false, T>), dim3(blocks), dim3(bs), 0, s, a);
-  else if (peel) hipLaunchKernelGGL((k_transport32<A, S, true, T>), dim3(blocks), dim3(bs), 0, s, a);
-  else hipLaunchKernelGGL((k_transport32<A, S, false, T>), dim3(blocks), dim3(bs), 0, s, a);
+  if (fp64 && peel) hipLaunchKernelGGL((k_transport64<A, S, true, T, M>), dim3(blocks), dim3(bs), 0, s, a);
+  else if (fp64) hipLaunchKernelGGL((k_transport64<A, S, false, T, M>), dim3(blocks), dim3(bs), 0, s, a);
+  else if (peel) hipLaunchKernelGGL((k_transport32<A, S, true, T, M>), dim3(blocks), dim3(bs), 0, s, a);
+  else hipLaunchKernelGGL((k_transport32<A, S, false, T, M>), dim3(blocks), dim3(bs), 0, s, a);
+}
+
+// the composite-mesh kernels: no peel-off or tables (refused by the host)
+template <bool A, bool S>
+static void launch_mesh(const TransportArgs& a, bool fp64, int blocks, int bs, hipStream_t s) {
+  if (fp64) hipLaunchKernelGGL((k_transport64<A, S, false, false, true>), dim3(blocks), dim3(bs), 0, s, a);
+  else hipLaunchKernelGGL((k_transport32<A, S, false, false, true>), dim3(blocks), dim3(bs), 0, s, a);
 }
 
 hipError_t launch_transport(const TransportArgs& a, bool fp64, bool aligned, bool sphere, bool peel, bool tab,
-                            int blocks, int block_size, hipStream_t s) {
-  if (tab) launch_one<false, true, true>(a, fp64, peel, blocks, block_size, s);
-  else if (aligned && sphere) launch_one<true, true, false>(a, fp64, peel, blocks, block_size, s);
-  else if (aligned) launch_one<true, false, false>(a, fp64, peel, blocks, block_size, s);
-  else if (sphere) launch_one<false, true, false>(a, fp64, peel, blocks, block_size, s);
-  else launch_one<false, false, false>(a, fp64, peel, blocks, block_size, s);
+                            bool mesh, int blocks, int block_size, hipStream_t s) {
+  if (mesh) {
+    if (aligned && sphere) launch_mesh<true, true>(a, fp64, blocks, block_size, s);
+    else if (aligned) launch_mesh<true, false>(a, fp64, blocks, block_size, s);
+    else if (sphere) launch_mesh<false, true>(a, fp64, blocks, block_size, s);
+    else launch_mesh<false, false>(a, fp64, blocks, block_size, s);
+  } else if (tab) {
+    launch_one<false, true, true, false>(a, fp64, peel, blocks, block_size, s);
+  } else if (aligned && sphere) {
+    launch_one<true, true, false, false>(a, fp64, peel, blocks, block_size, s);
+  } else if (aligned) {
+    launch_one<true, false, false, false>(a, fp64, peel, blocks, block_size, s);
+  } else if (sphere) {
+    launch_one<false, true, false, false>(a, fp64, peel, blocks, block_size, s);
+  } else {
+    launch_one<false, false, false, false>(a, fp64, peel, blocks, block_size, s);
+  }
   return hipGetLastError();
 }
 
-template <bool A, bool S, bool PL, bool T>
+template <bool A, bool S, bool PL, bool T, bool M>
 static int occ_one(bool fp64, int bs) {
   int n = 0;
-  const hipError_t e = fp64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport64<A, S, PL, T>, bs, 0)
-                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport32<A, S, PL, T>, bs, 0);
+  const hipError_t e = fp64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport64<A, S, PL, T, M>, bs, 0)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_transport32<A, S, PL, T, M>, bs, 0);
   return e == hipSuccess ? n : 0;
 }
 
 template <bool A, bool S, bool T>
 static int occ_peel(bool fp64, bool peel, int bs) {
-  return peel ? occ_one<A, S, true, T>(fp64, bs) : occ_one<A, S, false, T>(fp64, bs);
+  return peel ? occ_one<A, S, true, T, false>(fp64, bs) : occ_one<A, S, false, T, false>(fp64, bs);
 }
 
-int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, bool peel, bool tab, int block_size) {
+int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, bool peel, bool tab, bool mesh,
+                                int block_size) {
+  if (mesh) {
+    if (aligned && sphere) return occ_one<true, true, false, false, true>(fp64, block_size);
+    if (aligned) return occ_one<true, false, false, false, true>(fp64, block_size);
+    if (sphere) return occ_one<false, true, false, false, true>(fp64, block_size);
+    return occ_one<false, false, false, false, true>(fp64, block_size);
+  }
   if (tab) return occ_peel<false, true, true>(fp64, peel, block_size);
   if (aligned && sphere) return occ_peel<true, true, false>(fp64, peel, block_size);
   if (aligned) return occ_peel<true, false, false>(fp64, peel, block_size);
@@ -1607,22 +1801,23 @@ int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, bool peel,
   return occ_peel<false, false, false>(fp64, peel, block_size);
 }
 
-hipError_t launch_image(const ImageArgs& a, bool aligned, bool sphere, bool user_source,
+template <bool U, bool M>
+static void launch_image_one(const ImageArgs& a, bool aligned, bool sphere, dim3 grid, int bs, hipStream_t s) {
+  if (aligned && sphere) hipLaunchKernelGGL((k_image<true, true, U, M>), grid, dim3(bs), 0, s, a);
+  else if (aligned) hipLaunchKernelGGL((k_image<true, false, U, M>), grid, dim3(bs), 0, s, a);
+  else if (sphere) hipLaunchKernelGGL((k_image<false, true, U, M>), grid, dim3(bs), 0, s, a);
+  else hipLaunchKernelGGL((k_image<false, false, U, M>), grid, dim3(bs), 0, s, a);
+}
+
+hipError_t launch_image(const ImageArgs& a, bool aligned, bool sphere, bool user_source, bool mesh,
                         hipStream_t s) {
   const uint64_t total = (uint64_t)a.npx * a.npy * a.n_views * a.n_lambda;
   const int bs = 128;
   const dim3 grid((unsigned)((total + bs - 1) / bs));
-  if (user_source) {
-    if (aligned && sphere) hipLaunchKernelGGL((k_image<true, true, true>), grid, dim3(bs), 0, s, a);
-    else if (aligned) hipLaunchKernelGGL((k_image<true, false, true>), grid, dim3(bs), 0, s, a);
-    else if (sphere) hipLaunchKernelGGL((k_image<false, true, true>), grid, dim3(bs), 0, s, a);
-    else hipLaunchKernelGGL((k_image<false, false, true>), grid, dim3(bs), 0, s, a);
-  } else {
-    if (aligned && sphere) hipLaunchKernelGGL((k_image<true, true, false>), grid, dim3(bs), 0, s, a);
-    else if (aligned) hipLaunchKernelGGL((k_image<true, false, false>), grid, dim3(bs), 0, s, a);
-    else if (sphere) hipLaunchKernelGGL((k_image<false, true, false>), grid, dim3(bs), 0, s, a);
-    else hipLaunchKernelGGL((k_image<false, false, false>), grid, dim3(bs), 0, s, a);
-  }
+  if (user_source && mesh) launch_image_one<true, true>(a, aligned, sphere, grid, bs, s);
+  else if (user_source) launch_image_one<true, false>(a, aligned, sphere, grid, bs, s);
+  else if (mesh) launch_image_one<false, true>(a, aligned, sphere, grid, bs, s);
+  else launch_image_one<false, false>(a, aligned, sphere, grid, bs, s);
   return hipGetLastError();
 }
 

@@ -64,6 +64,12 @@ class kp_view(C.Structure):
                 ("npy", C.c_int32), ("half_width", C.c_double)]
 
 
+class kp_mesh(C.Structure):
+    _fields_ = [("rx", C.c_int32), ("ry", C.c_int32), ("rz", C.c_int32), ("block", C.c_int32),
+                ("max_level", C.c_int32), ("n_nodes", C.c_int32), ("x0", C.c_double), ("y0", C.c_double),
+                ("z0", C.c_double), ("dx", C.c_double)]
+
+
 class kp_opts(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("transport_fp64", C.c_int32),
                 ("tally_mode", C.c_int32), ("rr_wmin", C.c_double),
@@ -96,6 +102,7 @@ _SIGS = {
     "kp_last_error": ([_P], C.c_char_p),
     "kp_set_grid": ([_P, C.POINTER(kp_grid), _P, _P], C.c_int),
     "kp_set_grid_device": ([_P, C.POINTER(kp_grid), _P, _P], C.c_int),
+    "kp_set_mesh": ([_P, C.POINTER(kp_mesh), _P, _P, _P], C.c_int),
     "kp_set_dust": ([_P, C.c_int32, C.POINTER(kp_dust)], C.c_int),
     "kp_set_source": ([_P, C.POINTER(kp_source)], C.c_int),
     "kp_set_emission": ([_P, C.c_int32, _P], C.c_int),
@@ -182,6 +189,20 @@ def kp_set_grid_device(ctx, grid, d_rho, d_bhat=None) -> None:
             assert t.is_cuda and t.is_contiguous() and str(t.dtype) == "torch.float32"
     g = make_grid(grid)
     _check(ctx, _lib.kp_set_grid_device(ctx, C.byref(g), _ptr(d_rho), _ptr(d_bhat)))
+
+
+def kp_set_mesh(ctx, grid, rho: np.ndarray, bhat: np.ndarray | None) -> None:
+    """grid: a grid record with a "mesh" entry (see workloads.make_mesh_grid)."""
+    m = grid["mesh"]
+    child = np.ascontiguousarray(m["child"], dtype=np.int32)
+    rho = np.ascontiguousarray(rho, dtype=np.float32)
+    mm = kp_mesh(int(m["rx"]), int(m["ry"]), int(m["rz"]), int(m["block"]), int(m["max_level"]), len(child),
+                 float(grid["x0"]), float(grid["y0"]), float(grid["z0"]), float(grid["dx"]))
+    bp = None
+    if bhat is not None:
+        bhat = np.ascontiguousarray(bhat, dtype=np.float32)
+        bp = bhat.ctypes.data_as(_P)
+    _check(ctx, _lib.kp_set_mesh(ctx, C.byref(mm), child.ctypes.data_as(_P), rho.ctypes.data_as(_P), bp))
 
 
 def make_dust(d) -> kp_dust:
@@ -339,7 +360,9 @@ class Context:
     def load(self, cfg, device_arrays: bool = True):
         """Upload a workload dict (see workloads.py): grid, dust, source, views."""
         import torch
-        if device_arrays:
+        if cfg["grid"].get("mesh") is not None:
+            kp_set_mesh(self.h, cfg["grid"], cfg["rho"], cfg.get("bhat"))
+        elif device_arrays:
             rho = torch.from_numpy(np.ascontiguousarray(cfg["rho"], np.float32)).cuda()
             bh = None
             if cfg.get("bhat") is not None:
@@ -410,14 +433,12 @@ class Context:
         return kp_get_peel_images(self.h, (nl, len(v), 4, v[0]["npy"], v[0]["npx"]))
 
     def tally(self) -> np.ndarray:
-        g = self.cfg["grid"]
-        return kp_get_tally(self.h, len(self.last_counts), g["nx"] * g["ny"] * g["nz"])
+        return kp_get_tally(self.h, len(self.last_counts), np.asarray(self.cfg["rho"]).size)
 
     def view_tally(self) -> np.ndarray:
         """Per-view source of the last step 1 with tabulated grains,
         [n_lambda, ncell, n_views, 4]."""
-        g = self.cfg["grid"]
-        return kp_get_view_tally(self.h, len(self.last_counts), g["nx"] * g["ny"] * g["nz"],
+        return kp_get_view_tally(self.h, len(self.last_counts), np.asarray(self.cfg["rho"]).size,
                                  len(self.cfg["views"]))
 
     def stats(self) -> dict:

@@ -1,0 +1,185 @@
+"""GPU parity of the composite mesh with static refinement (Sec. 2: the mesh
+the packets cross, optionally statically refined; reading M1) with the FP64
+oracle, through the C ABI, on the same seeded inputs and Philox streams.
+
+Bars as in test_gpu_parity.py: FP64 transport 1e-12 per packet (1e-10 for
+aligned grains) with identical event sequences, images to 1e-10 of their
+maximum; FP32 transport 1e-5 per traced packet and images within 3 Monte
+Carlo sigma.  Besides the oracle, the GPU's mesh is checked against the
+GPU's own uniform grid carrying the same medium.
+"""
+import numpy as np
+import pytest
+
+from paper_2512_01283_amd import workloads as W
+from parity_util import compare_images_stat, compare_traces, gpu_run, oracle_batches, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle as o
+    o.lib()
+    return o
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2512_01283_amd import polrad as p
+    return p
+
+
+def rel_img(img, ref):
+    return np.abs(img - ref).max() / np.abs(ref[:, 0]).max()
+
+
+def test_mesh_sphere_fp64_path_by_path(O):
+    """The sphere refined twice toward its star: every packet follows the
+    oracle's path (events, cells, final state to 1e-12); images to 1e-10."""
+    cfg = W.mesh_sphere(packets=20_000)
+    N = cfg["packets"][0]
+    say(f"case: mesh sphere (32^3 roots, 2 levels) fp64 {N} packets")
+    ctx = gpu_run(cfg, trace_packets=N, transport_fp64=1)
+    try:
+        img_o, _, tr_o, st_o = O.run(cfg, traces=True)
+        compare_traces(ctx.traces(), tr_o, 1e-12, 1.0, "mesh sphere fp64")
+        st = ctx.stats()
+        for k in ("cell_steps", "scatterings", "trials", "escaped", "rr_kills"):
+            assert st[k] == st_o[k], k
+        d = rel_img(ctx.images()[0], img_o)
+        say(f"[mesh sphere fp64] image max |d|/I_max = {d:.3e}")
+        assert d < 1e-10
+    finally:
+        ctx.close()
+
+
+def test_mesh_sphere_fp32(O):
+    cfg = W.mesh_sphere(packets=20_000)
+    say("case: mesh sphere fp32 20000 packets")
+    ctx = gpu_run(cfg, trace_packets=4000, transport_fp64=0)
+    try:
+        _, tr_o, _ = O.transport(cfg, p_end=4000, tally=False, traces=True)
+        compare_traces(ctx.traces(), tr_o, 1e-5, 1.0, "mesh sphere fp32")
+        img_o, batches = oracle_batches(cfg)
+        compare_images_stat(ctx.images()[0], img_o, batches, label="mesh sphere fp32")
+    finally:
+        ctx.close()
+
+
+def test_mesh_aligned_grains(O):
+    """The clumpy slab of aligned oblate grains on a randomly refined mesh
+    (automatic precision: FP64): paths to 1e-10, images to 1e-10."""
+    base = W.slab_clump(n=32, packets=6000, npix=24)
+    base["views"] = [W.view(30, 20, 24), W.view(75, 200, 24)]
+    cfg = W.mesh_of_uniform(base, 4, 2, p_split=0.35, seed=7)
+    say("case: slab clump on a refined mesh, aligned grains, 6000 packets")
+    ctx = gpu_run(cfg, trace_packets=6000)
+    try:
+        img_o, _, tr_o, _ = O.run(cfg, traces=True)
+        compare_traces(ctx.traces(), tr_o, 1e-10, 1.0, "mesh aligned")
+        d = rel_img(ctx.images()[0], img_o)
+        say(f"[mesh aligned] image max |d|/I_max = {d:.3e}")
+        assert d < 1e-10
+    finally:
+        ctx.close()
+
+
+def test_mesh_matches_the_uniform_grid_of_the_same_medium():
+    """On the GPU alone: the same packets through the same medium on the
+    uniform grid and on a randomly refined mesh (roulette off) end with the
+    same events, directions and Stokes vectors to 1e-9."""
+    base = W.uniform_sphere(n=32, packets=20_000, albedo=0.8, npix=16)
+    base["opts"] = dict(base["opts"], rr_wmin=0.0)
+    mesh = W.mesh_of_uniform(base, 8, 2, p_split=0.4, seed=11)
+    say("case: uniform sphere vs the same medium on a refined mesh, fp64")
+    a = gpu_run(base, trace_packets=20_000, transport_fp64=1)
+    b = gpu_run(mesh, trace_packets=20_000, transport_fp64=1)
+    try:
+        ta, tb = a.traces(), b.traces()
+        assert b.stats()["cell_steps"] > a.stats()["cell_steps"]
+        assert np.array_equal(ta["end_kind"], tb["end_kind"]) and np.array_equal(ta["events"], tb["events"])
+        assert (np.abs(ta["stokes"] - tb["stokes"]) <= 1e-9 * np.abs(ta["stokes"][:, :1]) + 1e-300).all()
+        assert np.abs(ta["n"] - tb["n"]).max() <= 1e-9
+    finally:
+        a.close()
+        b.close()
+
+
+def test_mesh_batched_wavelengths(O):
+    """Two wavelengths (different opacities and albedos) on the mesh in one
+    launch, FP64: each follows its own streams."""
+    cfg = W.mesh_sphere(packets=1)
+    cfg["dust"] = [W.sphere_dust(0.5, 0.9), W.sphere_dust(2.0, 0.6)]
+    cfg["packets"] = [3000, 2000]
+    say("case: mesh sphere, 2 wavelengths, fp64")
+    ctx = gpu_run(cfg, trace_packets=2000, transport_fp64=1)
+    try:
+        tr = ctx.traces().reshape(2, 2000)
+        img = ctx.images()
+        for lam in range(2):
+            img_o, _, tr_o, _ = O.run(cfg, lam=lam, traces=True)
+            compare_traces(tr[lam], tr_o[:2000], 1e-12, 1.0, f"mesh lam={lam}")
+            assert rel_img(img[lam], img_o) < 1e-10
+    finally:
+        ctx.close()
+
+
+def test_mesh_image_source_and_static_entry_point(O, P):
+    """kp_image_source with a per-cell, per-camera source on the mesh equals
+    the oracle's step 2; kp_run_static on the mesh gives kp_run's images."""
+    import torch
+    cfg = W.mesh_sphere(packets=4000, npix=24)
+    ncell = len(cfg["rho"])
+    nv = len(cfg["views"])
+    rng = np.random.default_rng(9)
+    S = np.asarray(cfg["rho"], float)[:, None, None] * rng.uniform(0.5, 1.5, size=(ncell, nv, 4))
+    ctx = P.Context(0).load(cfg)
+    try:
+        out = torch.zeros((nv, 4, 24, 24), dtype=torch.float64, device="cuda")
+        P.kp_image_source(ctx.h, torch.from_numpy(S).cuda(), out)
+        ref = O.image(cfg, S)
+        assert rel_img(out.cpu().numpy(), ref) < 1e-12
+        ctx.run(transport_fp64=1)
+        img = ctx.images()
+        st = torch.zeros(img.shape, dtype=torch.float64, device="cuda")
+        P.kp_run_static(ctx.h, cfg["packets"], ctx.opts(transport_fp64=1), st)
+        d = np.abs(st.cpu().numpy() - img).max() / np.abs(img[:, :, 0]).max()
+        assert d <= 1e-12, d
+    finally:
+        ctx.close()
+
+
+def test_mesh_errors(P):
+    cfg = W.mesh_of_uniform(W.uniform_sphere(n=8, packets=100, npix=8), 4, 1, p_split=1.0, seed=1)
+    child = cfg["grid"]["mesh"]["child"]
+    ctx = P.Context(0)
+    try:
+        for bad in (np.where(np.arange(len(child)) == 0, 0, child),      # own child
+                    np.where(np.arange(len(child)) == 1, child[0], child)):  # two parents
+            g = dict(cfg["grid"], mesh=dict(cfg["grid"]["mesh"], child=bad.astype(np.int32)))
+            with pytest.raises(P.KpError) as e:
+                P.kp_set_mesh(ctx.h, g, cfg["rho"], None)
+            assert e.value.status == P.KP_ERR_ARG
+        g = dict(cfg["grid"], mesh=dict(cfg["grid"]["mesh"], max_level=0))  # deeper than max_level
+        with pytest.raises(P.KpError) as e:
+            P.kp_set_mesh(ctx.h, g, cfg["rho"], None)
+        assert e.value.status == P.KP_ERR_ARG
+        ctx.load(cfg)
+        with pytest.raises(P.KpError) as e:
+            ctx.run(peel_off=1)
+        assert e.value.status == P.KP_ERR_ARG
+        th = dict(cfg, source=dict(W.THERMAL_SOURCE), emission=np.ones((1, len(cfg["rho"])), np.float32))
+        ctx.load(th)
+        with pytest.raises(P.KpError) as e:
+            ctx.run()
+        assert e.value.status == P.KP_ERR_ARG
+        tab = dict(cfg, dust=[W.table_dust(1.0, 1.0, W.hg_table(0.5, n_theta=31))])
+        ctx.load(tab)
+        with pytest.raises(P.KpError) as e:
+            ctx.run()
+        assert e.value.status == P.KP_ERR_ARG
+        ctx.load(W.uniform_sphere(n=8, packets=100, npix=8))  # back to a uniform grid
+        ctx.run()
+    finally:
+        ctx.close()
