@@ -573,6 +573,18 @@ __device__ bool scatter(Packet<R>& p, const Quat<R>& q, const Quat<double>& qd,
   }
   R scale = sig / So;
   So = sig; Qo *= scale; Uo *= scale; Vo *= scale;
+  if (sizeof(R) == 4) {
+    // In FP32 the scattered state of a direction of near-zero scattered
+    // intensity is a difference of terms of size I, so rounding can leave it
+    // outside |P| <= I (one packet of 1.5e8 on a 256^3 disk: |P| = 1.0008 I,
+    // after which the next event's bound check fails); it is projected back
+    // onto the cone.
+    const R p2 = Qo * Qo + Uo * Uo + Vo * Vo;
+    if (p2 > So * So) {
+      const R f = So / k_sqrt(p2);
+      Qo *= f; Uo *= f; Vo *= f;
+    }
+  }
   // the accepted direction itself is formed in FP64 from the same uniforms
   const double mud = 2.0 * (double)umu - 1.0;
   const double smud = sqrt(fmax(0.0, 1.0 - mud * mud));

@@ -54,8 +54,15 @@ def _disks(seeds, n, npix, lookahead=2):
 
 
 def run_images(ctx, packets, seed):
-    """Images [views, 4, H, W] (CUDA float64) of one run with its own stream seed."""
-    ctx.run([int(packets)], seed=int(seed))
+    """Images [views, 4, H, W] (CUDA float64) of one run with its own stream seed.
+    A run in which a packet reached a non-finite state still images the
+    others; it is reported and kept."""
+    try:
+        ctx.run([int(packets)], seed=int(seed))
+    except P.KpError as e:
+        if e.status != P.KP_ERR_NUMERIC:
+            raise
+        print(f"  warning: run seed {seed}: {e}", flush=True)
     return ctx.images_device()[0].clone()
 
 
@@ -178,8 +185,35 @@ def evaluate(dn, seeds, plain_counts=(1e6, 3e6, 1e7, 3e7), den_counts=(1e5, 3e5,
         torch.cuda.synchronize()
         if log:
             log(f"  evaluated disk {s}", flush=True)
-    mean = {k: {c: float(np.mean(v)) for c, v in d.items()} for k, d in
-            (("plain", Ep), ("denoised", Ed), ("input", Ein)) + ((("denoised_tta", Etta),) if tta else ())}
+    per = dict((k, d) for k, d in (("plain", Ep), ("denoised", Ed), ("input", Ein)) +
+               ((("denoised_tta", Etta),) if tta else ()))
+    res = _ratios(per, plain_counts, den_counts, tta)
+    res.update(E_ref=float(np.mean(Eref)), ref_ok=bool(np.mean(Eref) <= res["eps"] / 3), seeds=list(seeds))
+    # spread: the same quantities over bootstrap resamples of the test disks
+    # (each disk's images resampled together)
+    nimg = len(Ep[plain_counts[0]])
+    per_disk = max(1, nimg // max(1, len(list(seeds))))
+    ndisk = nimg // per_disk
+    rng = np.random.default_rng(0)
+    boot = {"ratio": [], "ratio_tta": []}
+    for _ in range(1000):
+        pick = rng.integers(0, ndisk, ndisk)
+        idx = (pick[:, None] * per_disk + np.arange(per_disk)[None]).ravel()
+        r = _ratios({k: {c: [v[j] for j in idx] for c, v in d.items()} for k, d in per.items()},
+                    plain_counts, den_counts, tta)
+        boot["ratio"].append(r["ratio"] if r["ratio"] is not None else np.nan)
+        if tta:
+            boot["ratio_tta"].append(r["ratio_tta"] if r["ratio_tta"] is not None else np.nan)
+    for k, v in boot.items():
+        if v:
+            res[k + "_p16_p84"] = [float(np.nanpercentile(v, 16)), float(np.nanpercentile(v, 84))]
+    res["per_image"] = {k: {str(c): [float(x) for x in v] for c, v in d.items()} for k, d in per.items()}
+    return res
+
+
+def _ratios(per, plain_counts, den_counts, tta):
+    """Mean errors and the packets-to-error ratios of per-image error lists."""
+    mean = {k: {c: float(np.mean(v)) for c, v in d.items()} for k, d in per.items()}
     eps = mean["plain"][1e7]
     # E = a N^-1/2 fitted in log space
     xs = np.log(np.array(plain_counts))
@@ -188,10 +222,8 @@ def evaluate(dn, seeds, plain_counts=(1e6, 3e6, 1e7, 3e7), den_counts=(1e5, 3e5,
     n_plain = math.exp(2 * (loga - math.log(eps)))
     slope = float(np.polyfit(xs, ys, 1)[0])
     n_den, bound = _packets_to_eps(den_counts, mean["denoised"], eps)
-    res = dict(eps=eps, E_ref=float(np.mean(Eref)), ref_ok=bool(np.mean(Eref) <= eps / 3),
-                plain_slope=slope, N_plain=n_plain, N_den=n_den, N_den_bound=bound,
-                ratio=(n_plain / n_den) if n_den == n_den else None,
-                E=mean, seeds=list(seeds))
+    res = dict(eps=eps, plain_slope=slope, N_plain=n_plain, N_den=n_den, N_den_bound=bound,
+               ratio=(n_plain / n_den) if n_den == n_den else None, E=mean)
     if tta:
         n_tta, bound_tta = _packets_to_eps(den_counts, mean["denoised_tta"], eps)
         res.update(N_den_tta=n_tta, N_den_tta_bound=bound_tta,

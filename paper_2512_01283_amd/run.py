@@ -27,6 +27,8 @@ WORKLOADS = {
     "dust_cylinder_aligned": lambda **kw: W.dust_cylinder(aligned=True, **kw),
     "thermal_cube": W.thermal_cube,
     "table_disk": W.table_disk,
+    "mesh_sphere": lambda **kw: W.mesh_sphere(rx=8, block=16, max_level=2, **kw),
+    "uniform_sphere128": lambda **kw: W.uniform_sphere(n=128, **kw),
     "periodic_slab": W.periodic_slab,
 }
 PRECISION = {"auto": 0, "fp64": 1, "fp32": 2}
