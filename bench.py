@@ -272,7 +272,7 @@ def main():
                    "transport": "fp32, fp64 coherency tally", "seed": cfg["opts"]["seed"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
-        "detail": {"kernel": "k_transport32<false,true>",
+        "detail": {"kernel": "k_transport32<false,true,false,false,false>",
                    "schedule": opts,
                    "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, "
                                    "profiles/k_transport_disk256_1e8.md)",
