@@ -129,6 +129,8 @@ struct kp_ctx {
   int tab_nt = 0;
   double* d_tab = nullptr;
   size_t tab_n = 0;
+  int32_t* d_tab_guide = nullptr;  // [8 (n - 1)] node interval of each cos Theta bin
+  size_t tab_guide_n = 0;
   // the last step 1 tallied the per-view source [lambda][cell][view][4]
   // (tabulated grains) instead of coherency blocks
   bool tally_views = false;
@@ -246,6 +248,8 @@ void fill_dust(const kp_ctx* ctx, const uint64_t* counts, std::vector<DustDev>& 
       o.tab = ctx->d_tab + l * nt * 6;
       o.tab_mu = ctx->d_tab + nl * nt * 6;
       o.tab_cum = ctx->d_tab + nl * nt * 6 + nt + l * nt;
+      o.tab_guide = ctx->d_tab_guide;
+      o.tab_g = 8 * (ctx->tab_nt - 1);
     }
     if (o.sphere) {
       o.ap_re = o.aa_re = 1.0;
@@ -613,7 +617,7 @@ void kp_destroy(kp_ctx* ctx) {
                   (void*)ctx->d_images, (void*)ctx->d_stats, (void*)ctx->d_counter,
                   (void*)ctx->d_bad, (void*)ctx->d_traces, (void*)ctx->d_em_cdf,
                   (void*)ctx->d_em_guide, (void*)ctx->d_em_partial, (void*)ctx->d_peel,
-                  (void*)ctx->d_tab})
+                  (void*)ctx->d_tab, (void*)ctx->d_tab_guide})
     if (p) (void)hipFree(p);
   for (auto& e : ctx->ev)
     if (e) (void)hipEventDestroy(e);
@@ -828,10 +832,22 @@ kp_status kp_set_dust_tables(kp_ctx* ctx, int32_t n_lambda, int32_t n_theta, con
     c[0] = 0.0;
     for (size_t j = 0; j + 1 < nt; ++j) c[j + 1] = c[j] + std::fmax(t[6 * j], t[6 * (j + 1)]) * (mu[j] - mu[j + 1]);
   }
+  // guide: bin b of G = 8 (n - 1) uniform bins of cos Theta from 1 down to -1
+  // holds the interval j (mu_j+1 <= mu <= mu_j) of its upper end 1 - 2 b / G
+  const int G = 8 * (n_theta - 1);
+  std::vector<int32_t> guide(G);
+  for (int b = 0, j = 0; b < G; ++b) {
+    const double top = 1.0 - 2.0 * b / G;
+    while (j < n_theta - 2 && mu[j + 1] >= top) ++j;
+    guide[b] = j;
+  }
   KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
   kp_status st = ensure(ctx, &ctx->d_tab, &ctx->tab_n, h.size(), "table allocation");
   if (st) return st;
+  if ((st = ensure(ctx, &ctx->d_tab_guide, &ctx->tab_guide_n, guide.size(), "table guide allocation"))) return st;
   KP_HIP(hipMemcpy(ctx->d_tab, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice), "table upload");
+  KP_HIP(hipMemcpy(ctx->d_tab_guide, guide.data(), guide.size() * sizeof(int32_t), hipMemcpyHostToDevice),
+         "table guide upload");
   ctx->tab_nt = n_theta;
   ctx->have_tables = true;
   ctx->have_tally = false;

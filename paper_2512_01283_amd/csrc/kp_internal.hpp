@@ -30,6 +30,11 @@ struct DustDev {
   const double* tab;
   const double* tab_mu;
   const double* tab_cum;
+  // guide to the node interval of a cos Theta: [tab_g] over cos Theta uniform
+  // on [-1, 1] from 1 down, entry b the interval holding 1 - 2 b / tab_g
+  const int32_t* tab_guide;
+  int32_t tab_g;
+  int32_t pad2;
 };
 
 struct ViewDev {

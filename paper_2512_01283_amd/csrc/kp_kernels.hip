@@ -618,12 +618,15 @@ __device__ bool scatter(Packet<R>& p, const Quat<R>& q, const Quat<double>& qd,
 __device__ __forceinline__ void tab_eval(const DustDev& D, double mu, double z[6]) {
   const int n = D.tab_n;
   mu = fmin(1.0, fmax(-1.0, mu));
-  // the node interval from the angle, then moved past any rounding at a node
-  int j = (int)(acos(mu) * ((double)(n - 1) * (1.0 / M_PI)));
-  j = j < 0 ? 0 : (j > n - 2 ? n - 2 : j);
+  // the node interval: the guide's entry for the cos Theta bin (no inverse
+  // cosine on the dependency chain), then forward to the interval holding mu
+  const int G = D.tab_g;
+  int b = (int)((1.0 - mu) * (0.5 * (double)G));
+  b = b < 0 ? 0 : (b > G - 1 ? G - 1 : b);
+  int j = D.tab_guide[b];
   const double* M = D.tab_mu;
-  while (j > 0 && mu > M[j]) --j;
   while (j < n - 2 && mu < M[j + 1]) ++j;
+  while (j > 0 && mu > M[j]) --j;
   const double ma = M[j], mb = M[j + 1];
   const double t = ma > mb ? (ma - mu) / (ma - mb) : 0.0;
   const double* Z = D.tab + 6 * j;
@@ -1081,12 +1084,17 @@ __device__ void peel_off(const Packet<R>& p, const TransportArgs& a, const Quat<
 // Per-view flush of tabulated grains (the scattering source S of Sec. 2.3,
 // eq. scat-disc-sum, one Stokes vector per camera): each staged entry holds
 // the segment's weighted Stokes integral (lab basis of its direction) and the
-// direction; the wavefront takes the (entry, camera) pairs 64 at a time, one
-// per lane, projects the entry on the camera with the table and adds the four
-// components (divided by the cell volume) to S[lambda][cell][view][4] --
-// adjacent lanes write adjacent cameras of one cell, one contiguous run of
-// 32-byte vectors.  Reached by all lanes of the wavefront.
-__device__ void wave_drain_views(const TransportArgs& a, double* sv, long long* sk, int lane, int& staged) {
+// direction.  The wavefront takes the (entry, camera) pairs 64 at a time, one
+// per lane, and projects the entry on the camera with the table; the four
+// components then go through the wavefront's LDS area `sp` (64 x 4 doubles)
+// so that each atomic instruction writes 64 consecutive doubles: the pairs of
+// one entry are adjacent in S[lambda][cell][view][4], so an instruction
+// covers whole 128-byte lines (two per entry with 8 cameras) instead of
+// putting one component of every pair on its own line -- the drain is bound
+// by the L2's atomic line requests, and this cuts them four-fold.  Reached by
+// all lanes of the wavefront.
+__device__ void wave_drain_views(const TransportArgs& a, double* sv, long long* sk, double* sp, int lane,
+                                 int& staged) {
   constexpr int NV = 7;  // staged values per entry: weighted J (4) and n (3)
   const int n = staged;
   if (n == 0) return;
@@ -1097,24 +1105,37 @@ __device__ void wave_drain_views(const TransportArgs& a, double* sv, long long* 
   const int nv = a.n_views;
   const int items = n * nv;
   const double inv_vol = 1.0 / (a.dx * a.dx * a.dx);
-  for (int it = lane; it < items; it += 64) {
-    const int e = it / nv, v = it - e * nv;
-    const long long key = sk[e];
-    const double* x = sv + e * NV;
-    const DustDev& D = a.dust[(uint64_t)key / a.ncell];
-    const ViewDev& vw = a.views[v];
-    const double s_in[4] = {x[0], x[1], x[2], x[3]};
-    double st[4];
-    tab_toward(D, V3<double>{x[4], x[5], x[6]}, s_in, V3<double>{vw.ox, vw.oy, vw.oz},
-               V3<double>{vw.tx, vw.ty, vw.tz}, V3<double>{vw.px, vw.py, vw.pz}, st);
-    double* dst = a.tally + ((uint64_t)key * nv + v) * 4;
+  for (int base = 0; base < items; base += 64) {
+    const int it = base + lane;
+    double st[4] = {0.0, 0.0, 0.0, 0.0};
+    if (it < items) {
+      const int e = it / nv, v = it - e * nv;
+      const double* x = sv + e * NV;
+      const DustDev& D = a.dust[(uint64_t)sk[e] / a.ncell];
+      const ViewDev& vw = a.views[v];
+      const double s_in[4] = {x[0], x[1], x[2], x[3]};
+      tab_toward(D, V3<double>{x[4], x[5], x[6]}, s_in, V3<double>{vw.ox, vw.oy, vw.oz},
+                 V3<double>{vw.tx, vw.ty, vw.tz}, V3<double>{vw.px, vw.py, vw.pz}, st);
+    }
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (st[k] != 0.0) unsafeAtomicAdd(dst + k, st[k] * inv_vol);
+    for (int k = 0; k < 4; ++k) sp[4 * lane + k] = st[k] * inv_vol;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int d = 64 * j + lane;      // component d & 3 of pair d >> 2 of this round
+      const int pit = base + (d >> 2);
+      const double val = sp[d];
+      if (pit < items && val != 0.0) {
+        const int e = pit / nv, v = pit - e * nv;
+        unsafeAtomicAdd(a.tally + ((uint64_t)sk[e] * nv + v) * 4 + (d & 3), val);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Scattering event at the packet's current position (Sec. 2.2), the next
@@ -1212,6 +1233,8 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
   constexpr int NSV = TAB ? 7 : NC;
   constexpr int FLUSH_CAP = TAB ? 128 : (NC <= 6 ? 256 : 192);
   __shared__ double s_val[4 * FLUSH_CAP * NSV];
+  // tabulated grains: per wavefront the projections of one drain round
+  __shared__ double s_proj[TAB ? 4 * 256 : 1];
   __shared__ long long s_key[4 * FLUSH_CAP];
   if (threadIdx.x < SC_N) sc[threadIdx.x] = 0ull;
   if (threadIdx.x < SE_N) se[threadIdx.x] = 0.0;
@@ -1220,6 +1243,7 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
   const int lane = (int)__lane_id();
   const int wv = (int)(threadIdx.x >> 6);
   double* sv = s_val + wv * FLUSH_CAP * NSV;
+  double* sp = s_proj + (TAB ? wv * 256 : 0);
   long long* sk = s_key + wv * FLUSH_CAP;
   int staged = 0;  // entries in this wavefront's staging area (uniform)
   Packet<R> p;
@@ -1319,7 +1343,7 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
       // segment's projection on the cameras depends on it)
       const double e7[7] = {(double)cc[0], (double)cc[1], (double)cc[2], (double)cc[3], p.nx, p.ny, p.nz};
       flushes += wave_stage<7>(has, key, e7, sv, sk, lane, staged);
-      if (staged > FLUSH_CAP - 64) wave_drain_views(a, sv, sk, lane, staged);
+      if (staged > FLUSH_CAP - 64) wave_drain_views(a, sv, sk, sp, lane, staged);
     } else {
     // a lane entering another (wavelength, cell) hands its running sum over
     flushes += wave_stage<NC>(has && key != acc_key && acc_key >= 0, acc_key, acc, sv, sk, lane, staged);
@@ -1357,7 +1381,7 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
     }
   }
   if (TAB) {
-    wave_drain_views(a, sv, sk, lane, staged);
+    wave_drain_views(a, sv, sk, sp, lane, staged);
   } else {
     flushes += wave_stage<NC>(acc_key >= 0, acc_key, acc, sv, sk, lane, staged);
     wave_drain<NC, TS>(a.tally, sv, sk, lane, staged);
