@@ -54,8 +54,9 @@
  *     and camera rays cross cells of a leaf block as on a uniform grid and,
  *     leaving it, continue in the leaf holding the exit point, found in
  *     units of the finest cell with the face rule of R12.  Cell lengths and
- *     volumes are those of the cell's level.  Open boundaries and point
- *     sources (thermal emission and peel-off on uniform grids only).
+ *     volumes are those of the cell's level (a cell's thermal luminosity
+ *     4 pi rho kappa_abs B V with its own V).  Open boundaries; peel-off on
+ *     uniform grids only.
  *  E1 thermal emission of the dust (Sec. 2.2, the alpha_abs B term of eq.
  *     polarized-rt): the absorption matrix is kappa_abs/kappa_ext times the
  *     extinction matrix, so a cell emits rho kappa_abs (alpha1, alpha2, 0, 0) B
@@ -887,14 +888,16 @@ static void mueller_run(const run_t *R, const double q[4], const double m[3], co
 
 /* Running sum over cells (flat order) of the thermal luminosity
  * 4 pi rho kappa_abs B V of each cell (reading E1); NULL if it is zero. */
-static double *emission_cdf(const kpo_grid *g, const float *rho, const kpo_dust *d,
+static double *emission_cdf(const kpo_grid *g, const mesh_ix_t *mx, const float *rho, const kpo_dust *d,
                             const float *B) {
-  int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
-  double vol = g->dx * g->dx * g->dx;
+  int64_t ncell = cell_count(g, mx);
   double *cdf = malloc(sizeof(double) * (size_t)ncell);
   if (!cdf) return NULL;
   double run = 0.0;
+  int64_t B3 = g->mesh ? (int64_t)g->mesh->block * g->mesh->block * g->mesh->block : 1;
   for (int64_t c = 0; c < ncell; ++c) {
+    double len = g->mesh ? ldexp(g->dx, -mx->level[c / B3]) : g->dx;  /* the cell's edge (M1) */
+    double vol = len * len * len;
     run += 4.0 * PI_ * (double)rho[c] * d->kappa_abs * (double)B[c] * vol;
     cdf[c] = run;
   }
@@ -904,11 +907,13 @@ static double *emission_cdf(const kpo_grid *g, const float *rho, const kpo_dust 
 
 double kpo_emission_luminosity(const kpo_grid *g, const float *rho, const kpo_dust *d,
                                const float *B) {
-  if (g->mesh) return 0.0;  /* thermal emission: uniform grids only (reading M1) */
-  double *cdf = emission_cdf(g, rho, d, B);
-  if (!cdf) return 0.0;
-  double L = cdf[(int64_t)g->nx * g->ny * g->nz - 1];
+  mesh_ix_t mx;
+  memset(&mx, 0, sizeof mx);
+  if (g->mesh && mesh_build(g, &mx)) { mesh_free(&mx); return 0.0; }
+  double *cdf = emission_cdf(g, &mx, rho, d, B);
+  double L = cdf ? cdf[cell_count(g, &mx) - 1] : 0.0;
   free(cdf);
+  mesh_free(&mx);
   return L;
 }
 
@@ -931,14 +936,24 @@ static int64_t emission_cell(const double *cdf, int64_t ncell, double u) {
  * basis of the direction carried to the lab basis (mean over directions w,
  * the orientation average of alpha1 being 1).  Draws: cell, three
  * coordinates, two for the direction. */
-static void emit_thermal(const kpo_grid *g, const float *bhat, const kpo_dust *d,
+static void emit_thermal(const kpo_grid *g, const mesh_ix_t *mx, const float *bhat, const kpo_dust *d,
                          const double *cdf, rng_t *rng, double w, gpos_t *p, double n[3],
                          double s[4]) {
-  int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
+  int64_t ncell = cell_count(g, mx);
   int64_t c = emission_cell(cdf, ncell, draw(rng));
-  p->i[0] = c % g->nx;
-  p->i[1] = (c / g->nx) % g->ny;
-  p->i[2] = c / ((int64_t)g->nx * g->ny);
+  if (g->mesh) {
+    /* cell c of the mesh: leaf c / block^3, local cell x fastest (M1) */
+    int64_t Bk = g->mesh->block, r = c % (Bk * Bk * Bk);
+    p->leaf = c / (Bk * Bk * Bk);
+    p->i[0] = r % Bk;
+    p->i[1] = (r / Bk) % Bk;
+    p->i[2] = r / (Bk * Bk);
+  } else {
+    p->leaf = -1;
+    p->i[0] = c % g->nx;
+    p->i[1] = (c / g->nx) % g->ny;
+    p->i[2] = c / ((int64_t)g->nx * g->ny);
+  }
   for (int a = 0; a < 3; ++a) p->f[a] = draw(rng);
   double mu = 2.0 * draw(rng) - 1.0;
   double ph = 2.0 * PI_ * draw(rng);
@@ -955,14 +970,18 @@ int kpo_emit_state(const kpo_grid *g, const float *rho, const float *bhat,
                    const kpo_dust *d, const float *B, uint64_t seed, int32_t lam,
                    uint64_t packet, double w, int64_t *cell, double pos[3], double n[3],
                    double s[4]) {
-  if (!g || !rho || !d || !B || g->mesh) return -1;
-  double *cdf = emission_cdf(g, rho, d, B);
-  if (!cdf) return -1;
+  if (!g || !rho || !d || !B) return -1;
+  mesh_ix_t mx;
+  memset(&mx, 0, sizeof mx);
+  if (g->mesh && mesh_build(g, &mx)) { mesh_free(&mx); return -1; }
+  double *cdf = emission_cdf(g, &mx, rho, d, B);
+  if (!cdf) { mesh_free(&mx); return -1; }
   rng_t rng = {{seed, (uint64_t)lam}, packet, 0, 0, 0, {0, 0, 0, 0}};
   gpos_t p;
-  emit_thermal(g, bhat, d, cdf, &rng, w, &p, n, s);
+  emit_thermal(g, &mx, bhat, d, cdf, &rng, w, &p, n, s);
   free(cdf);
-  *cell = flat(g, &p);
+  mesh_free(&mx);
+  *cell = cell_of(g, &p);
   for (int a = 0; a < 3; ++a) pos[a] = p.f[a];
   return 0;
 }
@@ -1040,8 +1059,7 @@ static void run_packet(const run_t *R, uint64_t pid, kpo_trace *tr, kpo_stats *s
   int in = 1;
   if (R->src->kind == 2) {
     w0 = R->cdf[ncell - 1] / (double)R->n_total;
-    emit_thermal(g, R->bhat, d, R->cdf, &rng, w0, &p, n, s);
-    p.leaf = -1;
+    emit_thermal(g, R->mx, R->bhat, d, R->cdf, &rng, w0, &p, n, s);
   } else {
     double u0 = draw(&rng), u1 = draw(&rng);
     if (R->src->kind == 1) {
@@ -1213,12 +1231,12 @@ static int transport_impl(const kpo_grid *g, const float *rho, const float *bhat
   if (check_inputs(g, d, src) || !o || n_total == 0 || p_end < p_begin) return -1;
   if ((S || peel) && (n_views <= 0 || !views)) return -1;
   if (peel && g->boundary != 0) return -1;
-  /* the mesh: point sources only, no peel-off (reading M1) */
+  /* the mesh: no peel-off (reading M1) */
   mesh_ix_t mx;
   memset(&mx, 0, sizeof mx);
-  if (g->mesh && (src->kind == 2 || peel || mesh_build(g, &mx))) { mesh_free(&mx); return -1; }
+  if (g->mesh && (peel || mesh_build(g, &mx))) { mesh_free(&mx); return -1; }
   double *cdf = NULL;
-  if (src->kind == 2 && !(cdf = emission_cdf(g, rho, d, src->B))) return -1;
+  if (src->kind == 2 && !(cdf = emission_cdf(g, &mx, rho, d, src->B))) { mesh_free(&mx); return -1; }
   double (*vdir)[3] = NULL;
   if (n_views > 0) {
     vdir = malloc(sizeof(double[3]) * (size_t)n_views);
@@ -1280,9 +1298,9 @@ int kpo_trace_packets(const kpo_grid *g, const float *rho, const float *bhat,
   if (check_inputs(g, d, src) || !o || !ids || !traces || n_total == 0) return -1;
   mesh_ix_t mx;
   memset(&mx, 0, sizeof mx);
-  if (g->mesh && (src->kind == 2 || mesh_build(g, &mx))) { mesh_free(&mx); return -1; }
+  if (g->mesh && mesh_build(g, &mx)) { mesh_free(&mx); return -1; }
   double *cdf = NULL;
-  if (src->kind == 2 && !(cdf = emission_cdf(g, rho, d, src->B))) return -1;
+  if (src->kind == 2 && !(cdf = emission_cdf(g, &mx, rho, d, src->B))) { mesh_free(&mx); return -1; }
   double *cum = NULL, N = 0.0;
   if (is_table(d)) {
     N = table_norm(d);
@@ -1324,7 +1342,7 @@ int kpo_image_thermal(const kpo_grid *g, const float *rho, const float *bhat,
   if (check_inputs(g, d, &dummy) || n_views <= 0 || !views || !images) return -1;
   mesh_ix_t mx;
   memset(&mx, 0, sizeof mx);
-  if (g->mesh && (B || mesh_build(g, &mx))) { mesh_free(&mx); return -1; }
+  if (g->mesh && mesh_build(g, &mx)) { mesh_free(&mx); return -1; }
   int64_t ncell = cell_count(g, &mx);
   double fine = g->mesh ? ldexp(g->dx, -g->mesh->max_level) : g->dx;
   double kext = d->kappa_sca + d->kappa_abs;

@@ -304,8 +304,6 @@ MeshDev mesh_dev(const kp_ctx* ctx) {
 
 kp_status check_ready(kp_ctx* ctx) {
   if (!ctx->have_grid) return fail(ctx, KP_ERR_STATE, "kp_set_grid has not been called");
-  if (ctx->have_mesh && ctx->src.kind == 2)
-    return fail(ctx, KP_ERR_ARG, "thermal emission is not supported on a composite mesh");
   if (ctx->have_mesh && ctx->have_tables)
     return fail(ctx, KP_ERR_ARG, "tabulated scattering is not supported on a composite mesh");
   if (ctx->dust.empty()) return fail(ctx, KP_ERR_STATE, "kp_set_dust has not been called");
@@ -409,7 +407,9 @@ kp_status prepare_emission(kp_ctx* ctx, hipStream_t s) {
   ctx->em_L.assign(nl, 0.0);
   for (int l = 0; l < nl; ++l) {
     const double fac = 4.0 * M_PI * ctx->dust[l].kappa_abs * vol;
-    KP_HIP(launch_emission_table(ctx->d_rho, ctx->d_em_B + (size_t)l * n, fac, n, ctx->d_em_partial,
+    const uint64_t b3 = ctx->have_mesh ? (uint64_t)ctx->mesh.block * ctx->mesh.block * ctx->mesh.block : 1;
+    KP_HIP(launch_emission_table(ctx->d_rho, ctx->d_em_B + (size_t)l * n, fac,
+                                 ctx->have_mesh ? ctx->d_leaf_org : nullptr, b3, n, ctx->d_em_partial,
                                  ctx->d_em_cdf + (size_t)l * n, ctx->d_em_guide + (size_t)l * (n + 1), s),
            "emission table launch");
     KP_HIP(hipMemcpyAsync(&ctx->em_L[l], ctx->d_em_cdf + (size_t)l * n + (n - 1), sizeof(double),

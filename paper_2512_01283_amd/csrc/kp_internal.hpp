@@ -164,11 +164,13 @@ hipError_t launch_validate(const float* rho, const float* bx, const float* by, c
 int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, bool peel, bool tab, bool mesh,
                                 int block_size);
 // Thermal emission tables of one wavelength: cdf [ncell], the running sum
-// of fac rho B (fac = 4 pi kappa_abs dx^3) in flat cell order, and its guide
-// table [ncell + 1]; `partial` holds emission_blocks(ncell) doubles of
-// scratch.
-hipError_t launch_emission_table(const float* rho, const float* B, double fac, uint64_t ncell,
-                                 double* partial, double* cdf, uint32_t* guide, hipStream_t s);
+// of fac rho B (fac = 4 pi kappa_abs dx^3; on a composite mesh, leaf_org
+// non-null, times 2^-3 level of each cell's leaf, block3 cells per leaf) in
+// flat cell order, and its guide table [ncell + 1]; `partial` holds
+// emission_blocks(ncell) doubles of scratch.
+hipError_t launch_emission_table(const float* rho, const float* B, double fac, const int32_t* leaf_org,
+                                 uint64_t block3, uint64_t ncell, double* partial, double* cdf, uint32_t* guide,
+                                 hipStream_t s);
 uint64_t emission_blocks(uint64_t ncell);
 
 }  // namespace kp

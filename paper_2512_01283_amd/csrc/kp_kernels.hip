@@ -268,9 +268,24 @@ __device__ bool init_packet(Packet<R>& p, uint64_t g, const TransportArgs& a) {
     const uint64_t c = emission_cell(a.em_cdf + (uint64_t)lo * a.ncell,
                                      a.em_guide + (uint64_t)lo * (a.ncell + 1), a.ncell,
                                      (double)next_uniform(p, a.seed));
-    p.ci = (int)(c % (uint64_t)a.nx);
-    p.cj = (int)((c / (uint64_t)a.nx) % (uint64_t)a.ny);
-    p.ck = (int)(c / ((uint64_t)a.nx * (uint64_t)a.ny));
+    if (MESH) {
+      // cell c of the mesh: leaf c / block^3, local cell x fastest; the
+      // cell-length constants of the leaf's level
+      const uint64_t Bm = (uint64_t)a.mesh.block, r = c % (Bm * Bm * Bm);
+      p.leaf = (int)(c / (Bm * Bm * Bm));
+      p.ci = (int)(r % Bm);
+      p.cj = (int)((r / Bm) % Bm);
+      p.ck = (int)(r / (Bm * Bm));
+      p.lvl = a.mesh.leaf_org[4 * p.leaf + 3];
+      const double sc = ldexp(1.0, -p.lvl);
+      p.ks = a.dust[lo].ks_cell * sc;
+      p.ke = a.dust[lo].ke_cell * sc;
+      p.ka = (R)(a.dust[lo].ka_cell * sc);
+    } else {
+      p.ci = (int)(c % (uint64_t)a.nx);
+      p.cj = (int)((c / (uint64_t)a.nx) % (uint64_t)a.ny);
+      p.ck = (int)(c / ((uint64_t)a.nx * (uint64_t)a.ny));
+    }
     p.fx = (double)next_uniform(p, a.seed);
     p.fy = (double)next_uniform(p, a.seed);
     p.fz = (double)next_uniform(p, a.seed);
@@ -1667,18 +1682,28 @@ __global__ void k_validate(const float* rho, const float* bx, const float* by, c
 // Thermal emission tables (set-up of the dust's emission, Sec. 2.2): for one
 // wavelength the running sum F of the cell luminosities fac rho B (fac =
 // 4 pi kappa_abs dx^3) over the cells in flat order, and its guide table.
-// Blocks of EM_CHUNK cells; thread t of a block sums EM_PER consecutive cells.
+// On a composite mesh (lorg non-null: leaf origins and levels, b3 = block^3
+// cells per leaf) a cell's luminosity carries its own volume, 2^-3 level of
+// a root cell's.  Blocks of EM_CHUNK cells; thread t of a block sums EM_PER
+// consecutive cells.
 // ---------------------------------------------------------------------------
 constexpr int EM_THREADS = 256;
 constexpr int EM_PER = 16;
 constexpr uint64_t EM_CHUNK = (uint64_t)EM_THREADS * EM_PER;
 
+__device__ __forceinline__ double em_lum(const float* rho, const float* B, double fac, const int32_t* lorg,
+                                         uint64_t b3, uint64_t c) {
+  const double l = fac * (double)rho[c] * (double)B[c];
+  return lorg ? ldexp(l, -3 * lorg[4 * (c / b3) + 3]) : l;
+}
+
 __device__ __forceinline__ double em_thread_sum(const float* rho, const float* B, double fac,
-                                                uint64_t first, uint64_t ncell) {
+                                                const int32_t* lorg, uint64_t b3, uint64_t first,
+                                                uint64_t ncell) {
   double sum = 0.0;
   for (int k = 0; k < EM_PER; ++k) {
     const uint64_t c = first + k;
-    if (c < ncell) sum += fac * (double)rho[c] * (double)B[c];
+    if (c < ncell) sum += em_lum(rho, B, fac, lorg, b3, c);
   }
   return sum;
 }
@@ -1701,11 +1726,12 @@ __device__ __forceinline__ double em_block_exclusive(double v, double* sh, doubl
 }
 
 __global__ void __launch_bounds__(EM_THREADS)
-k_em_partial(const float* rho, const float* B, double fac, uint64_t ncell, double* partial) {
+k_em_partial(const float* rho, const float* B, double fac, const int32_t* lorg, uint64_t b3, uint64_t ncell,
+             double* partial) {
   __shared__ double sh[EM_THREADS];
   const uint64_t first = (uint64_t)blockIdx.x * EM_CHUNK + (uint64_t)threadIdx.x * EM_PER;
   double total;
-  em_block_exclusive(em_thread_sum(rho, B, fac, first, ncell), sh, &total);
+  em_block_exclusive(em_thread_sum(rho, B, fac, lorg, b3, first, ncell), sh, &total);
   if (threadIdx.x == 0) partial[blockIdx.x] = total;
 }
 
@@ -1726,16 +1752,17 @@ __global__ void __launch_bounds__(EM_THREADS) k_em_offsets(double* partial, uint
 }
 
 __global__ void __launch_bounds__(EM_THREADS)
-k_em_cdf(const float* rho, const float* B, double fac, uint64_t ncell, const double* offsets,
-         double* cdf) {
+k_em_cdf(const float* rho, const float* B, double fac, const int32_t* lorg, uint64_t b3, uint64_t ncell,
+         const double* offsets, double* cdf) {
   __shared__ double sh[EM_THREADS];
   const uint64_t first = (uint64_t)blockIdx.x * EM_CHUNK + (uint64_t)threadIdx.x * EM_PER;
   double total;
-  double run = offsets[blockIdx.x] + em_block_exclusive(em_thread_sum(rho, B, fac, first, ncell), sh, &total);
+  double run = offsets[blockIdx.x] +
+               em_block_exclusive(em_thread_sum(rho, B, fac, lorg, b3, first, ncell), sh, &total);
   for (int k = 0; k < EM_PER; ++k) {
     const uint64_t c = first + k;
     if (c < ncell) {
-      run += fac * (double)rho[c] * (double)B[c];
+      run += em_lum(rho, B, fac, lorg, b3, c);
       cdf[c] = run;
     }
   }
@@ -1758,12 +1785,14 @@ __global__ void k_em_guide(const double* cdf, uint64_t ncell, uint32_t* guide) {
 
 uint64_t emission_blocks(uint64_t ncell) { return (ncell + EM_CHUNK - 1) / EM_CHUNK; }
 
-hipError_t launch_emission_table(const float* rho, const float* B, double fac, uint64_t ncell,
-                                 double* partial, double* cdf, uint32_t* guide, hipStream_t s) {
+hipError_t launch_emission_table(const float* rho, const float* B, double fac, const int32_t* leaf_org,
+                                 uint64_t block3, uint64_t ncell, double* partial, double* cdf, uint32_t* guide,
+                                 hipStream_t s) {
   const uint64_t nb = emission_blocks(ncell);
-  hipLaunchKernelGGL(k_em_partial, dim3((unsigned)nb), dim3(EM_THREADS), 0, s, rho, B, fac, ncell, partial);
+  hipLaunchKernelGGL(k_em_partial, dim3((unsigned)nb), dim3(EM_THREADS), 0, s, rho, B, fac, leaf_org, block3,
+                     ncell, partial);
   hipLaunchKernelGGL(k_em_offsets, dim3(1), dim3(EM_THREADS), 0, s, partial, nb);
-  hipLaunchKernelGGL(k_em_cdf, dim3((unsigned)nb), dim3(EM_THREADS), 0, s, rho, B, fac, ncell,
+  hipLaunchKernelGGL(k_em_cdf, dim3((unsigned)nb), dim3(EM_THREADS), 0, s, rho, B, fac, leaf_org, block3, ncell,
                      (const double*)partial, cdf);
   hipLaunchKernelGGL(k_em_guide, dim3((unsigned)((ncell + 1 + 255) / 256)), dim3(256), 0, s,
                      (const double*)cdf, ncell, guide);

@@ -236,8 +236,9 @@ def mesh_sphere(rx=4, block=8, max_level=2, packets=100_000, albedo=1.0, tau_rad
 def mesh_of_uniform(cfg, block, max_level, p_split=0.4, seed=0) -> dict:
     """The same medium as the uniform grid of cfg (nx divisible by block)
     on a composite mesh refined at random (each block split with probability
-    p_split): every cell takes the density (and alignment) of the root cell
-    holding it, so the optical properties are the same function of position."""
+    p_split): every cell takes the density (and alignment and thermal source
+    function) of the root cell holding it, so the optical properties are the
+    same function of position."""
     g = cfg["grid"]
     rx, ry, rz = g["nx"] // block, g["ny"] // block, g["nz"] // block
     rng = np.random.default_rng(seed)
@@ -249,6 +250,8 @@ def mesh_of_uniform(cfg, block, max_level, p_split=0.4, seed=0) -> dict:
     out = dict(cfg, grid=grid, rho=np.ascontiguousarray(np.asarray(cfg["rho"])[root], dtype=np.float32))
     if cfg.get("bhat") is not None:
         out["bhat"] = np.ascontiguousarray(np.asarray(cfg["bhat"])[:, root], dtype=np.float32)
+    if cfg.get("emission") is not None:
+        out["emission"] = np.ascontiguousarray(np.asarray(cfg["emission"])[:, root], dtype=np.float32)
     out["name"] = cfg["name"] + "_mesh"
     return out
 

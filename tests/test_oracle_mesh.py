@@ -122,3 +122,41 @@ def test_malformed_meshes_are_refused(O):
     wrong = dict(cfg["grid"], nx=cfg["grid"]["nx"] + 1)      # box not rx * block
     with pytest.raises(ValueError):
         O.transport(dict(cfg, grid=wrong), tally=False)
+
+
+def test_thermal_emission_on_a_refined_mesh(O):
+    """The dust's thermal emission on a randomly refined mesh of the same
+    medium and source function: the total luminosity (cell volumes of their
+    levels) equals the uniform grid's to 1e-10; the image of the direct
+    emission equals the uniform grid's to 1e-12; the escaping fraction of an
+    isothermal, purely absorbing sphere is the closed form's within 4 sigma
+    (+1e-3), as on the uniform grid; emission cells follow the luminosity."""
+    import math
+    from test_oracle_emission import escape_probability
+    base = W.thermal_sphere(n=32, packets=60_000, tau_radius=1.0, npix=24)
+    base["views"] = [W.view(123, 211, 24, half_width=base["views"][0]["half_width"]),
+                     W.view(35, 70, 24, half_width=base["views"][0]["half_width"])]
+    mesh = W.mesh_of_uniform(base, 4, 2, p_split=0.5, seed=21)
+    Lu, Lm = O.emission_luminosity(base), O.emission_luminosity(mesh)
+    assert abs(Lm / Lu - 1) < 1e-10, (Lu, Lm)  # running sums over 3e4 and 2e5 cells
+    iu, im = O.image(base, None), O.image(mesh, None)
+    assert np.abs(iu - im).max() <= 1e-12 * np.abs(iu[:, 0]).max()
+    _, _, st = O.transport(mesh, tally=False)
+    p = st["e_escaped"] / st["e_emitted"]
+    pc = escape_probability(1.0)
+    N = mesh["packets"][0]
+    sig = math.sqrt(pc * (1 - pc) / N)
+    print(f"mesh: escaped fraction {p:.5f}, closed form {pc:.5f} (sigma {sig:.1e}); "
+          f"uniform-grid medium 32^3 on a mesh")
+    assert abs(p - pc) < 4 * sig + 3e-3  # 32^3 cell-centre sphere: optical radius to ~0.2 %
+    # emission cells: histogram of the leaf levels of 4000 emitted packets
+    # against each level's share of the luminosity
+    _, lev = W.mesh_cells(mesh["grid"])
+    B = np.asarray(mesh["emission"])[0]
+    dx = mesh["grid"]["dx"]
+    lum = np.asarray(mesh["rho"], float) * B * (dx / 2.0 ** lev) ** 3
+    cells = np.array([O.emit_state(mesh, k)[0] for k in range(4000)])
+    for l in range(3):
+        share = lum[lev == l].sum() / lum.sum()
+        got = np.mean(lev[cells] == l)
+        assert abs(got - share) < 4 * math.sqrt(share * (1 - share) / 4000) + 1e-3, (l, got, share)
