@@ -244,8 +244,7 @@ kp_status kp_set_grid_device(kp_ctx *ctx, const kp_grid *grid, const float *d_rh
  * the block it continues in the leaf holding the exit point (a coordinate
  * on a face belongs to the cell the direction points into); every cell's
  * length, volume and thermal luminosity are those of its level.  Open
- * boundaries and dipole grains: peel-off and tabulated scattering are
- * refused (KP_ERR_ARG) on a mesh.  1 <= block <= 64, 0 <= max_level <= 16, the box at most 2^30
+ * boundaries.  1 <= block <= 64, 0 <= max_level <= 16, the box at most 2^30
  * finest cells along each axis, ncell <= 4e9; KP_ERR_ARG for a malformed
  * tree (a node with two parents or none, children before their parent or
  * past the list, depth beyond max_level).  Copies the arrays to the

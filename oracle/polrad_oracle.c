@@ -55,8 +55,7 @@
  *     leaving it, continue in the leaf holding the exit point, found in
  *     units of the finest cell with the face rule of R12.  Cell lengths and
  *     volumes are those of the cell's level (a cell's thermal luminosity
- *     4 pi rho kappa_abs B V with its own V).  Open boundaries; peel-off on
- *     uniform grids only.
+ *     4 pi rho kappa_abs B V with its own V).  Open boundaries.
  *  E1 thermal emission of the dust (Sec. 2.2, the alpha_abs B term of eq.
  *     polarized-rt): the absorption matrix is kappa_abs/kappa_ext times the
  *     extinction matrix, so a cell emits rho kappa_abs (alpha1, alpha2, 0, 0) B
@@ -1002,10 +1001,19 @@ static void peel_off(const run_t *R, const gpos_t *at, const double q_ev[4], con
                      const double s[4]) {
   const kpo_grid *g = R->g;
   const kpo_dust *d = R->d;
-  int64_t ncell = (int64_t)g->nx * g->ny * g->nz;
+  int64_t ncell = R->ncell;
   double kext = d->kappa_sca + d->kappa_abs;
   double X[3] = {g->x0 + (at->i[0] + at->f[0]) * g->dx, g->y0 + (at->i[1] + at->f[1]) * g->dx,
                  g->z0 + (at->i[2] + at->f[2]) * g->dx};
+  if (g->mesh) {
+    /* the event's position: its leaf's corner plus the local cell and
+     * fraction, in finest cells (M1) */
+    const mesh_ix_t *mx = R->mx;
+    double s = (double)((int64_t)1 << (g->mesh->max_level - mx->level[at->leaf]));
+    double fine = ldexp(g->dx, -g->mesh->max_level), o[3] = {g->x0, g->y0, g->z0};
+    for (int a = 0; a < 3; ++a)
+      X[a] = o[a] + ((double)mx->org[at->leaf][a] + ((double)at->i[a] + at->f[a]) * s) * fine;
+  }
   int32_t npx = R->views[0].npx, npy = R->views[0].npy;
   for (int v = 0; v < R->n_views; ++v) {
     const double *om = R->vdir[v];
@@ -1023,7 +1031,7 @@ static void peel_off(const run_t *R, const gpos_t *at, const double q_ev[4], con
       int axis;
       double tf = face_dist(&p, om, &axis);
       if (axis < 0) break;
-      int64_t c = flat(g, &p);
+      int64_t c = cell_of(g, &p);
       double r = (double)R->rho[c];
       if (r > 0.0 && tf > 0.0) {
         double q[4], og[3], al[3], sg[4], out[4], zero[4] = {0, 0, 0, 0};
@@ -1032,11 +1040,11 @@ static void peel_off(const run_t *R, const gpos_t *at, const double q_ev[4], con
         kpo_alphas(d, og[2], al);
         double eta = eta_pair(q, om, og);
         kpo_rotate_stokes(eta, st, sg);
-        kpo_appA(al[0], al[1], al[2], r * kext * tf * g->dx, zero, sg, out);
+        kpo_appA(al[0], al[1], al[2], r * kext * tf * cell_len(g, R->mx, &p), zero, sg, out);
         kpo_rotate_stokes(-eta, out, st);
       }
       cross_face(&p, om, tf, axis);
-      if (!inside(g, &p)) break;
+      if (after_cross(g, R->mx, &p, axis, om)) break;
     }
     double area = (2.0 * W / npx) * (2.0 * W / npy);
     for (int k = 0; k < 4; ++k)
@@ -1231,10 +1239,9 @@ static int transport_impl(const kpo_grid *g, const float *rho, const float *bhat
   if (check_inputs(g, d, src) || !o || n_total == 0 || p_end < p_begin) return -1;
   if ((S || peel) && (n_views <= 0 || !views)) return -1;
   if (peel && g->boundary != 0) return -1;
-  /* the mesh: no peel-off (reading M1) */
   mesh_ix_t mx;
   memset(&mx, 0, sizeof mx);
-  if (g->mesh && (peel || mesh_build(g, &mx))) { mesh_free(&mx); return -1; }
+  if (g->mesh && mesh_build(g, &mx)) { mesh_free(&mx); return -1; }
   double *cdf = NULL;
   if (src->kind == 2 && !(cdf = emission_cdf(g, &mx, rho, d, src->B))) { mesh_free(&mx); return -1; }
   double (*vdir)[3] = NULL;

@@ -304,8 +304,6 @@ MeshDev mesh_dev(const kp_ctx* ctx) {
 
 kp_status check_ready(kp_ctx* ctx) {
   if (!ctx->have_grid) return fail(ctx, KP_ERR_STATE, "kp_set_grid has not been called");
-  if (ctx->have_mesh && ctx->have_tables)
-    return fail(ctx, KP_ERR_ARG, "tabulated scattering is not supported on a composite mesh");
   if (ctx->dust.empty()) return fail(ctx, KP_ERR_STATE, "kp_set_dust has not been called");
   if (!ctx->have_source) return fail(ctx, KP_ERR_STATE, "kp_set_source has not been called");
   if (ctx->views.empty()) return fail(ctx, KP_ERR_STATE, "kp_set_views has not been called");
@@ -452,8 +450,6 @@ kp_status check_run_args(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, 
   if (o->peel_off != 0 && o->peel_off != 1) return fail(ctx, KP_ERR_ARG, "peel_off must be 0 or 1");
   if (o->peel_off && ctx->grid.boundary)
     return fail(ctx, KP_ERR_ARG, "peel-off imaging needs open boundaries (boundary 0)");
-  if (o->peel_off && ctx->have_mesh)
-    return fail(ctx, KP_ERR_ARG, "peel-off imaging is not supported on a composite mesh");
   *total_out = total;
   return KP_OK;
 }

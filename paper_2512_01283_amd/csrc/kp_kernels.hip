@@ -233,6 +233,36 @@ __device__ bool mesh_cross(Packet<R>& p, const TransportArgs& a) {
   return false;
 }
 
+// A ray (direction om) in leaf `leaf` at local cell ci, fraction f whose
+// index on some axis left the leaf: the leaf beyond (leaf, lvl, ci, f
+// updated), or false if the ray left the domain.
+__device__ __forceinline__ bool mesh_ray_cross(const MeshDev& m, int& leaf, int& lvl, int ci[3], double f[3],
+                                               const double om[3]) {
+  const int4 o = reinterpret_cast<const int4*>(m.leaf_org)[leaf];
+  const double sz = (double)(1ll << (m.max_level - o.w));
+  const long long X0[3] = {o.x, o.y, o.z};
+  double t[3];
+  long long X[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    t[k] = (double)X0[k] + ((double)ci[k] + f[k]) * sz;
+    X[k] = finest_cell(t[k], om[k]);
+    if (X[k] < 0 || X[k] >= m.nfine[k]) return false;
+  }
+  leaf = mesh_find(m, X);
+  const int4 o1 = reinterpret_cast<const int4*>(m.leaf_org)[leaf];
+  lvl = o1.w;
+  const int sh = m.max_level - lvl;
+  const long long X1[3] = {o1.x, o1.y, o1.z};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const long long i = (X[k] - X1[k]) >> sh;
+    ci[k] = (int)i;
+    f[k] = fmin(1.0, fmax(0.0, (t[k] - (double)X1[k]) / (double)(1ll << sh) - (double)i));
+  }
+  return true;
+}
+
 // flat index of the packet's cell
 template <bool MESH, typename R>
 __device__ __forceinline__ uint64_t cell_index(const Packet<R>& p, const TransportArgs& a) {
@@ -1013,14 +1043,22 @@ __device__ __forceinline__ void source_toward(const double C9[9], const Quat<dou
 // the grid's edge through the Appendix A extinction of every cell on the way
 // (no source), added to the pixel the event projects to, per unit pixel
 // area.  FP64; open boundaries.
-template <typename R, bool ALIGNED, bool SPHERE, bool TAB>
+template <typename R, bool ALIGNED, bool SPHERE, bool TAB, bool MESH>
 __device__ void peel_off(const Packet<R>& p, const TransportArgs& a, const Quat<double>& q_ev,
                          const DustDev& D) {
   double C9[9];
   const double s_in[4] = {(double)p.I, (double)p.Q, (double)p.U, (double)p.V};
   if (!TAB) coherency<double, 9>(V3<double>{p.nx, p.ny, p.nz}, s_in[0], s_in[1], s_in[2], s_in[3], 1.0, C9);
-  const double X[3] = {a.x0 + ((double)p.ci + p.fx) * a.dx, a.y0 + ((double)p.cj + p.fy) * a.dx,
-                       a.z0 + ((double)p.ck + p.fz) * a.dx};
+  double X[3] = {a.x0 + ((double)p.ci + p.fx) * a.dx, a.y0 + ((double)p.cj + p.fy) * a.dx,
+                 a.z0 + ((double)p.ck + p.fz) * a.dx};
+  if (MESH) {
+    // the event's position from its leaf's corner, in finest cells
+    const int4 o = reinterpret_cast<const int4*>(a.mesh.leaf_org)[p.leaf];
+    const double sz = (double)(1ll << (a.mesh.max_level - o.w));
+    X[0] = a.x0 + ((double)o.x + ((double)p.ci + p.fx) * sz) * a.mesh.fine;
+    X[1] = a.y0 + ((double)o.y + ((double)p.cj + p.fy) * sz) * a.mesh.fine;
+    X[2] = a.z0 + ((double)o.z + ((double)p.ck + p.fz) * sz) * a.mesh.fine;
+  }
   const int nn[3] = {a.nx, a.ny, a.nz};
   for (int v = 0; v < a.n_views; ++v) {
     const ViewDev vw = a.views[v];
@@ -1041,6 +1079,8 @@ __device__ void peel_off(const Packet<R>& p, const TransportArgs& a, const Quat<
     const double om[3] = {vw.ox, vw.oy, vw.oz};
     int ci[3] = {p.ci, p.cj, p.ck};
     double f[3] = {p.fx, p.fy, p.fz};
+    int leaf = MESH ? p.leaf : 0, lvl = MESH ? p.lvl : 0;
+    const uint64_t Bm = MESH ? (uint64_t)a.mesh.block : 0;
     while (true) {
       double tb = __builtin_huge_val();
       int axis = -1;
@@ -1053,10 +1093,11 @@ __device__ void peel_off(const Packet<R>& p, const TransportArgs& a, const Quat<
         if (t < tb) { tb = t; axis = k; }
       }
       if (axis < 0) break;
-      const uint64_t c = (uint64_t)ci[0] + (uint64_t)a.nx * ((uint64_t)ci[1] + (uint64_t)a.ny * ci[2]);
+      const uint64_t c = MESH ? (uint64_t)leaf * Bm * Bm * Bm + (uint64_t)ci[0] + Bm * ((uint64_t)ci[1] + Bm * ci[2])
+                              : (uint64_t)ci[0] + (uint64_t)a.nx * ((uint64_t)ci[1] + (uint64_t)a.ny * ci[2]);
       const double rho = (double)a.rho[c];
       if (rho > 0.0 && tb > 0.0) {
-        const double dtau = rho * D.kext * tb * a.dx;
+        const double dtau = rho * D.kext * tb * (MESH ? ldexp(a.dx, -lvl) : a.dx);
         if (SPHERE && !ALIGNED) {
           const double E = exp(-dtau);
 #pragma unroll
@@ -1086,6 +1127,10 @@ __device__ void peel_off(const Packet<R>& p, const TransportArgs& a, const Quat<
       for (int k = 0; k < 3; ++k)
         if (k != axis) f[k] = fmin(1.0, fmax(0.0, f[k] + tb * om[k]));
       if (om[axis] > 0.0) { ci[axis]++; f[axis] = 0.0; } else { ci[axis]--; f[axis] = 1.0; }
+      if (MESH) {
+        if ((ci[axis] < 0 || ci[axis] >= (int)Bm) && !mesh_ray_cross(a.mesh, leaf, lvl, ci, f, om)) break;
+        continue;
+      }
       if (ci[axis] < 0 || ci[axis] >= nn[axis]) break;
     }
     const double area = (2.0 * W / a.npx) * (2.0 * W / a.npy);
@@ -1107,7 +1152,9 @@ __device__ void peel_off(const Packet<R>& p, const TransportArgs& a, const Quat<
 // covers whole 128-byte lines (two per entry with 8 cameras) instead of
 // putting one component of every pair on its own line -- the drain is bound
 // by the L2's atomic line requests, and this cuts them four-fold.  Reached by
-// all lanes of the wavefront.
+// all lanes of the wavefront.  The source is per unit volume of the entry's
+// cell: on a composite mesh a cell of level l has (dx 2^-l)^3.
+template <bool MESH>
 __device__ void wave_drain_views(const TransportArgs& a, double* sv, long long* sk, double* sp, int lane,
                                  int& staged) {
   constexpr int NV = 7;  // staged values per entry: weighted J (4) and n (3)
@@ -1123,17 +1170,23 @@ __device__ void wave_drain_views(const TransportArgs& a, double* sv, long long* 
   for (int base = 0; base < items; base += 64) {
     const int it = base + lane;
     double st[4] = {0.0, 0.0, 0.0, 0.0};
+    double iv = inv_vol;
     if (it < items) {
       const int e = it / nv, v = it - e * nv;
       const double* x = sv + e * NV;
-      const DustDev& D = a.dust[(uint64_t)sk[e] / a.ncell];
+      const uint64_t key = (uint64_t)sk[e];
+      const DustDev& D = a.dust[key / a.ncell];
       const ViewDev& vw = a.views[v];
       const double s_in[4] = {x[0], x[1], x[2], x[3]};
       tab_toward(D, V3<double>{x[4], x[5], x[6]}, s_in, V3<double>{vw.ox, vw.oy, vw.oz},
                  V3<double>{vw.tx, vw.ty, vw.tz}, V3<double>{vw.px, vw.py, vw.pz}, st);
+      if (MESH) {
+        const uint64_t b = (uint64_t)a.mesh.block;
+        iv = ldexp(inv_vol, 3 * a.mesh.leaf_org[4 * ((key % a.ncell) / (b * b * b)) + 3]);
+      }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) sp[4 * lane + k] = st[k] * inv_vol;
+    for (int k = 0; k < 4; ++k) sp[4 * lane + k] = st[k] * iv;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1166,7 +1219,7 @@ __device__ uint32_t scatter_step(Packet<R>& p, const TransportArgs& a) {
     qd = cell_quat<ALIGNED, SPHERE>(a, blk, c);
     q = quat_cast<R>(qd);
   }
-  if (PEEL) peel_off<R, ALIGNED, SPHERE, TAB>(p, a, qd, D);
+  if (PEEL) peel_off<R, ALIGNED, SPHERE, TAB, MESH>(p, a, qd, D);
   if (TAB) {
     if (!scatter_tab<R>(p, D, a.seed)) return END_NUMERIC;
   } else if (!scatter<R, ALIGNED, SPHERE>(p, q, qd, D, a.seed)) {
@@ -1358,7 +1411,7 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
       // segment's projection on the cameras depends on it)
       const double e7[7] = {(double)cc[0], (double)cc[1], (double)cc[2], (double)cc[3], p.nx, p.ny, p.nz};
       flushes += wave_stage<7>(has, key, e7, sv, sk, lane, staged);
-      if (staged > FLUSH_CAP - 64) wave_drain_views(a, sv, sk, sp, lane, staged);
+      if (staged > FLUSH_CAP - 64) wave_drain_views<MESH>(a, sv, sk, sp, lane, staged);
     } else {
     // a lane entering another (wavelength, cell) hands its running sum over
     flushes += wave_stage<NC>(has && key != acc_key && acc_key >= 0, acc_key, acc, sv, sk, lane, staged);
@@ -1396,7 +1449,7 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
     }
   }
   if (TAB) {
-    wave_drain_views(a, sv, sk, sp, lane, staged);
+    wave_drain_views<MESH>(a, sv, sk, sp, lane, staged);
   } else {
     flushes += wave_stage<NC>(acc_key >= 0, acc_key, acc, sv, sk, lane, staged);
     wave_drain<NC, TS>(a.tally, sv, sk, lane, staged);
@@ -1810,20 +1863,17 @@ static void launch_one(const TransportArgs& a, bool fp64, bool peel, int blocks,
   else hipLaunchKernelGGL((k_transport32<A, S, false, T, M>), dim3(blocks), dim3(bs), 0, s, a);
 }
 
-// the composite-mesh kernels: no peel-off or tables (refused by the host)
-template <bool A, bool S>
-static void launch_mesh(const TransportArgs& a, bool fp64, int blocks, int bs, hipStream_t s) {
-  if (fp64) hipLaunchKernelGGL((k_transport64<A, S, false, false, true>), dim3(blocks), dim3(bs), 0, s, a);
-  else hipLaunchKernelGGL((k_transport32<A, S, false, false, true>), dim3(blocks), dim3(bs), 0, s, a);
-}
+
 
 hipError_t launch_transport(const TransportArgs& a, bool fp64, bool aligned, bool sphere, bool peel, bool tab,
                             bool mesh, int blocks, int block_size, hipStream_t s) {
-  if (mesh) {
-    if (aligned && sphere) launch_mesh<true, true>(a, fp64, blocks, block_size, s);
-    else if (aligned) launch_mesh<true, false>(a, fp64, blocks, block_size, s);
-    else if (sphere) launch_mesh<false, true>(a, fp64, blocks, block_size, s);
-    else launch_mesh<false, false>(a, fp64, blocks, block_size, s);
+  if (mesh && tab) {
+    launch_one<false, true, true, true>(a, fp64, peel, blocks, block_size, s);
+  } else if (mesh) {
+    if (aligned && sphere) launch_one<true, true, false, true>(a, fp64, peel, blocks, block_size, s);
+    else if (aligned) launch_one<true, false, false, true>(a, fp64, peel, blocks, block_size, s);
+    else if (sphere) launch_one<false, true, false, true>(a, fp64, peel, blocks, block_size, s);
+    else launch_one<false, false, false, true>(a, fp64, peel, blocks, block_size, s);
   } else if (tab) {
     launch_one<false, true, true, false>(a, fp64, peel, blocks, block_size, s);
   } else if (aligned && sphere) {
@@ -1846,24 +1896,25 @@ static int occ_one(bool fp64, int bs) {
   return e == hipSuccess ? n : 0;
 }
 
-template <bool A, bool S, bool T>
+template <bool A, bool S, bool T, bool M>
 static int occ_peel(bool fp64, bool peel, int bs) {
-  return peel ? occ_one<A, S, true, T, false>(fp64, bs) : occ_one<A, S, false, T, false>(fp64, bs);
+  return peel ? occ_one<A, S, true, T, M>(fp64, bs) : occ_one<A, S, false, T, M>(fp64, bs);
 }
 
 int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, bool peel, bool tab, bool mesh,
                                 int block_size) {
+  if (mesh && tab) return occ_peel<false, true, true, true>(fp64, peel, block_size);
   if (mesh) {
-    if (aligned && sphere) return occ_one<true, true, false, false, true>(fp64, block_size);
-    if (aligned) return occ_one<true, false, false, false, true>(fp64, block_size);
-    if (sphere) return occ_one<false, true, false, false, true>(fp64, block_size);
-    return occ_one<false, false, false, false, true>(fp64, block_size);
+    if (aligned && sphere) return occ_peel<true, true, false, true>(fp64, peel, block_size);
+    if (aligned) return occ_peel<true, false, false, true>(fp64, peel, block_size);
+    if (sphere) return occ_peel<false, true, false, true>(fp64, peel, block_size);
+    return occ_peel<false, false, false, true>(fp64, peel, block_size);
   }
-  if (tab) return occ_peel<false, true, true>(fp64, peel, block_size);
-  if (aligned && sphere) return occ_peel<true, true, false>(fp64, peel, block_size);
-  if (aligned) return occ_peel<true, false, false>(fp64, peel, block_size);
-  if (sphere) return occ_peel<false, true, false>(fp64, peel, block_size);
-  return occ_peel<false, false, false>(fp64, peel, block_size);
+  if (tab) return occ_peel<false, true, true, false>(fp64, peel, block_size);
+  if (aligned && sphere) return occ_peel<true, true, false, false>(fp64, peel, block_size);
+  if (aligned) return occ_peel<true, false, false, false>(fp64, peel, block_size);
+  if (sphere) return occ_peel<false, true, false, false>(fp64, peel, block_size);
+  return occ_peel<false, false, false, false>(fp64, peel, block_size);
 }
 
 template <bool U, bool M>

@@ -177,6 +177,53 @@ def test_mesh_thermal_emission(O):
         ctx.close()
 
 
+def test_mesh_tabulated_scattering(O):
+    """Grains of tabulated scattering on the refined sphere mesh, FP64:
+    every packet's path, the per-view source of every mesh cell and the
+    images equal the oracle's."""
+    cfg = W.mesh_sphere(packets=20_000, views=[W.view(t, p, 24) for t, p in ((123, 211), (35, 70), (0, 0))])
+    cfg["dust"] = [W.table_dust(1.0, 1.0, W.hg_table(0.6, n_theta=181))]
+    say("case: table grains on the refined sphere mesh, fp64 20000 packets")
+    ctx = gpu_run(cfg, trace_packets=20_000, transport_fp64=1)
+    try:
+        img_o, S_o, tr_o, _ = O.run(cfg, traces=True)
+        compare_traces(ctx.traces(), tr_o, 1e-12, 1.0, "mesh tables")
+        S = ctx.view_tally()[0]
+        dS = np.abs(S - S_o).max() / np.abs(S_o).max()
+        d = rel_img(ctx.images()[0], img_o)
+        say(f"[mesh tables] view tally max |d|/max = {dS:.3e}; image max |d|/I_max = {d:.3e}")
+        assert dS < 1e-10 and d < 1e-10
+    finally:
+        ctx.close()
+
+
+@pytest.mark.parametrize("aligned", [False, True])
+def test_mesh_peel_off(O, aligned):
+    """Peel-off imaging (reading P1) on a refined mesh, FP64: the GPU's
+    peel-off images equal the oracle's on the same packets to 1e-10 of
+    their maximum: spheres on the sphere mesh, aligned grains (dichroic
+    attenuation toward the camera) on the randomly refined clumpy slab."""
+    if aligned:
+        base = W.slab_clump(n=32, packets=6000, npix=24)
+        base["views"] = [W.view(30, 20, 24), W.view(75, 200, 24)]
+        cfg = W.mesh_of_uniform(base, 4, 2, p_split=0.35, seed=7)
+    else:
+        cfg = W.mesh_sphere(packets=20_000, views=[W.view(t, p, 24) for t, p in ((123, 211), (35, 70), (0, 0))])
+    label = "mesh peel-off aligned" if aligned else "mesh peel-off sphere"
+    say(f"case: {label} fp64 {cfg['packets'][0]} packets")
+    ctx = gpu_run(cfg, transport_fp64=1, peel_off=1)
+    try:
+        pg = ctx.peel_images()[0]
+        st = ctx.stats()
+    finally:
+        ctx.close()
+    po, _, st_o = O.transport_peel(cfg)
+    assert st["scatterings"] == st_o["scatterings"]
+    d = np.abs(pg - po).max() / np.abs(po[:, 0]).max()
+    say(f"[{label}] max |d|/I_max = {d:.3e}")
+    assert d < 1e-10 and np.abs(po[:, 0]).max() > 0
+
+
 def test_mesh_errors(P):
     cfg = W.mesh_of_uniform(W.uniform_sphere(n=8, packets=100, npix=8), 4, 1, p_split=1.0, seed=1)
     child = cfg["grid"]["mesh"]["child"]
@@ -193,14 +240,8 @@ def test_mesh_errors(P):
             P.kp_set_mesh(ctx.h, g, cfg["rho"], None)
         assert e.value.status == P.KP_ERR_ARG
         ctx.load(cfg)
-        with pytest.raises(P.KpError) as e:
-            ctx.run(peel_off=1)
-        assert e.value.status == P.KP_ERR_ARG
-        tab = dict(cfg, dust=[W.table_dust(1.0, 1.0, W.hg_table(0.5, n_theta=31))])
-        ctx.load(tab)
-        with pytest.raises(P.KpError) as e:
-            ctx.run()
-        assert e.value.status == P.KP_ERR_ARG
+        ctx.run(peel_off=1)  # peel-off runs on a mesh
+        assert ctx.peel_images().shape == (1, len(cfg["views"]), 4, 8, 8)
         ctx.load(W.uniform_sphere(n=8, packets=100, npix=8))  # back to a uniform grid
         ctx.run()
     finally:

@@ -160,3 +160,53 @@ def test_thermal_emission_on_a_refined_mesh(O):
         share = lum[lev == l].sum() / lum.sum()
         got = np.mean(lev[cells] == l)
         assert abs(got - share) < 4 * math.sqrt(share * (1 - share) / 4000) + 1e-3, (l, got, share)
+
+
+@pytest.mark.parametrize("aligned", [False, True])
+def test_peel_off_on_a_refined_mesh_of_the_same_medium(O, aligned):
+    """Peel-off imaging (reading P1) on a randomly refined mesh of the same
+    medium as a uniform grid, roulette off: the same events, seen along the
+    same lines through the same medium cut into more cells, give the uniform
+    grid's peel-off images to 1e-9 of their maximum.  A single unrefined
+    block gives them to 1e-14 (the oracle's threads add their events into
+    the images in any order, so even two runs on one grid differ at 1e-16)."""
+    if aligned:
+        base = W.slab_clump(n=16, packets=3000, npix=16)
+        base["precision"] = "f64"
+    else:
+        base = W.uniform_sphere(n=16, packets=10_000, npix=16, albedo=0.7)
+    base["views"] = [W.view(123, 211, 16, half_width=base["views"][0]["half_width"]),
+                     W.view(35, 70, 16, half_width=base["views"][0]["half_width"])]
+    base["opts"] = dict(base["opts"], rr_wmin=0.0)
+    mesh = W.mesh_of_uniform(base, 4, 2, p_split=0.45, seed=31)
+    pu, _, st_u = O.transport_peel(base)
+    pm, _, st_m = O.transport_peel(mesh)
+    assert st_m["cell_steps"] > st_u["cell_steps"] and st_m["scatterings"] == st_u["scatterings"]
+    d = np.abs(pu - pm).max() / np.abs(pu[:, 0]).max()
+    print(f"peel-off on the mesh: max |uniform - mesh| / I_max = {d:.2e}")
+    assert d < 1e-9 and np.abs(pu[:, 0]).max() > 0
+    p1, _, _ = O.transport_peel(single_block(base))
+    assert np.abs(p1 - pu).max() <= 1e-14 * np.abs(pu[:, 0]).max()
+
+
+def test_tabulated_grains_on_a_refined_mesh_of_the_same_medium(O):
+    """Tabulated scattering (readings T1, T2) on a randomly refined mesh of
+    the uniform sphere's medium, roulette off: the same histories to 1e-9,
+    and the per-view source's volume integral per camera (sum over cells of
+    S V, each cell's volume of its level) equal to 1e-9."""
+    base = W.table_sphere(n=16, packets=10_000, tau_radius=1.0, albedo=0.8, g=0.6,
+                          views=[W.view(123, 211, 16), W.view(35, 70, 16)])
+    base["opts"] = dict(base["opts"], rr_wmin=0.0)
+    mesh = W.mesh_of_uniform(base, 4, 2, p_split=0.45, seed=5)
+    _, S_u, tr_u, _ = O.run(base, traces=True)
+    _, S_m, tr_m, _ = O.run(mesh, traces=True)
+    for k in ("end_kind", "events"):
+        assert np.array_equal(tr_u[k], tr_m[k]), k
+    assert (np.abs(tr_u["stokes"] - tr_m["stokes"]) <= 1e-9 * np.abs(tr_u["stokes"][:, :1]) + 1e-300).all()
+    _, lev = W.mesh_cells(mesh["grid"])
+    dx = base["grid"]["dx"]
+    tot_u = S_u.sum(0) * dx ** 3
+    tot_m = np.einsum("c,cvk->vk", (dx / 2.0 ** lev) ** 3, S_m)
+    d = np.abs(tot_u - tot_m).max() / np.abs(tot_u[:, 0]).max()
+    print(f"tables on the mesh: volume integral of S, max rel. difference {d:.2e}")
+    assert d <= 1e-9 and (lev > 0).any()
