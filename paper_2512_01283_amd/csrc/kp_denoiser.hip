@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "kp_dn_internal.hpp"
@@ -491,6 +492,230 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// Weight gradient with the input staged once for all nine taps (cin >= 48):
+// a workgroup owns 64 output channels (co) x 64 input channels (c) x the 9
+// taps, i.e. a 64 x 576 block of the gradient, and a chunk of pixel tiles of
+// 8 rows x 16 columns of one image.  Per tile the 128 pixels of gz (as a
+// channel-major gz^T, the layout and swizzle of k_wgrad's slab) and the
+// 10 x 18 halo of x (zero outside the image) go to LDS once; each tap then
+// reads its operand at its (dy, dx) offset inside the halo, so x is fetched
+// 1.4 times per tile instead of once per tap, and gz once per 576 gradient
+// columns instead of once per 64 -- k_wgrad is bound by those re-fetches.
+// x^T rows: channel c, halo row hr, 32 columns (64 bytes, 18 used), channel
+// stride 672 bytes, the 16-byte chunk k of a row at slot k ^ ((c >> 3) & 3):
+// every 16-byte operand read is conflict-free under the LDS access rule used
+// for the kernels above (16 lanes = 16 channels); the transposing 8-byte
+// stores take about two cycles per pass.  A tap's operand is columns
+// col..col+7 of a halo row with col = 8 (g & 1) + dx: two aligned 16-byte
+// reads per (row, dy) give the three dx shifts (dx = 1 by byte alignment, dx
+// = 2 by a dword shift).  Wave w computes channels 16 w..16 w+15 of every
+// tap for all 64 co: 4 x 9 MFMA tiles, 36 MFMAs per 32 pixels against 10
+// operand reads.  Each workgroup writes its partial 64 x 576 block to a
+// scratch area with plain stores, and k_wgrad_sum adds the chunks into the
+// gradient: with two workgroups per CU resident, the blocks of all of them
+// land at the end of the launch, and as FP32 atomics (about 1.2e6 64-byte
+// requests per launch) they took as long as the MFMAs.  The workgroups of
+// the first channel tile add the bias gradient with atomics (64 each).
+// ---------------------------------------------------------------------------
+constexpr int WH_TH = 8, WH_TW = 16;          // pixel tile (128 pixels)
+constexpr int WH_HR = WH_TH + 2;              // halo rows
+constexpr int WH_NQ = 5;                      // 4-pixel quads per halo row (20 >= 18 columns)
+constexpr int WH_NU = WH_HR * WH_NQ;          // quads per halo (50)
+constexpr int WH_ROWB = 64;                   // LDS bytes per halo row of one channel
+constexpr int WH_CHB = WH_HR * WH_ROWB + 32;  // LDS bytes per channel (672)
+constexpr int WH_GZB = 64 * 128 * 2;          // gz^T: 64 channels x 128 pixels
+constexpr int WH_LDS = WH_GZB + 64 * WH_CHB;  // 59392 bytes: two workgroups per CU
+constexpr int WH_TARGET = 512;                // workgroups per launch (two per CU)
+constexpr int WH_MIN_CIN = 48;                // narrower inputs keep k_wgrad
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_wgrad_halo(WgradArgs a) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[WH_LDS];
+  uint16_t* gzT = (uint16_t*)lds;
+  unsigned char* xT = lds + WH_GZB;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int tyn = (a.H + WH_TH - 1) / WH_TH, txn = (a.W + WH_TW - 1) / WH_TW;
+  const int ntile = a.B * tyn * txn;
+  // the 8 XCDs take workgroups round-robin: regroup so that one XCD runs all
+  // channel blocks of consecutive chunks (they share gz and x rows in its L2)
+  const int tiles = a.mtiles * a.ktiles, nwg = tiles * a.nch;
+  int wg = blockIdx.x;
+  if (wg < nwg - nwg % 8) wg = (wg & 7) * (nwg / 8) + (wg >> 3);
+  const int chn = wg / tiles, tile = wg - chn * tiles;
+  const int mt = tile / a.ktiles, ct = tile - mt * a.ktiles;
+  const int m0 = mt * 64, c0 = ct * 64;
+  const int t_begin = chn * a.chunk, t_end = min(ntile, t_begin + a.chunk);
+  // loader slots: gz pixels 4 sp .. 4 sp + 3 of the tile (row sp >> 2,
+  // columns 4 (sp & 3) ..), channels m0 + s8 ..; x halo quads u0 and u0 + 32
+  // (halo row u % 10, columns 4 (u / 10) ..), channels c0 + s8 ..
+  const int sp = tid >> 3, a8 = tid & 7, s8 = 8 * a8;
+  const bool a_ok = m0 + s8 < a.cout, x_ok = c0 + s8 < a.cin;
+  const int u0 = tid >> 3;
+  const bool u1_ok = u0 + 32 < WH_NU;
+  int xst[2];  // byte offset of channel s8's row slot for each quad; + j * WH_CHB per channel
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+    const int u = u0 + 32 * v, hr = u % WH_HR, q = u / WH_HR;
+    xst[v] = s8 * WH_CHB + hr * WH_ROWB + 16 * ((q >> 1) ^ (a8 & 3)) + 8 * (q & 1);
+  }
+  // operand reads: A rows 16 mb + i (chunk 4 kc + g); B channel 16 wv + i,
+  // halo row 2 kc + (g >> 1) + dy, chunks (g & 1) and (g & 1) + 1
+  // A row 16 mb + i: chunk 4 kc + g sits at slot (4 kc + g) ^ ra_sw[mb]
+  int ra_sw[4];
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) ra_sw[mb] = wg_swz(16 * mb + i, 0);
+  const int cx = 16 * wv + i, xsw = (cx >> 3) & 3;
+  const int bx = cx * WH_CHB + (g >> 1) * WH_ROWB;
+  const int bs0 = 16 * ((g & 1) ^ xsw), bs1 = 16 * (((g & 1) + 1) ^ xsw);
+  const bool do_bias = ct == 0 && a_ok;
+  float bsum[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) bsum[j] = 0.f;
+  const u32x4 zero = {0u, 0u, 0u, 0u};
+  u32x4 va[4], vx[2][4];
+  auto load = [&](int t) {
+    const int img = t / (tyn * txn), rt = t - img * tyn * txn;
+    const int y0 = (rt / txn) * WH_TH, x0 = (rt % txn) * WH_TW;
+    {
+      const int yy = y0 + (sp >> 2), xb = x0 + 4 * (sp & 3);
+      const size_t prow = (size_t)(img * a.H + yy) * a.W;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const bool ok = a_ok && yy < a.H && xb + q < a.W;
+        va[q] = ok ? ld16(a.gz + (prow + xb + q) * a.gzs + m0 + s8) : zero;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int u = u0 + 32 * v, hr = u % WH_HR, q = u / WH_HR;
+      const int yy = y0 + hr - 1, xb = x0 + 4 * q - 1;
+      const bool rok = x_ok && (v == 0 || u1_ok) && yy >= 0 && yy < a.H;
+      const size_t prow = (size_t)(img * a.H + yy) * a.W;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int xx = xb + e;
+        const bool ok = rok && 4 * q + e < WH_TW + 2 && xx >= 0 && xx < a.W;
+        vx[v][e] = ok ? ld16(a.x + (prow + xx) * a.xs + c0 + s8) : zero;
+      }
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int r0 = s8 + 2 * j, r1 = r0 + 1;
+      *(uint2*)&gzT[r0 * 128 + 8 * wg_swz(r0, sp >> 1) + (sp & 1) * 4] =
+          uint2{lo16x2(va[0][j], va[1][j]), lo16x2(va[2][j], va[3][j])};
+      *(uint2*)&gzT[r1 * 128 + 8 * wg_swz(r1, sp >> 1) + (sp & 1) * 4] =
+          uint2{hi16x2(va[0][j], va[1][j]), hi16x2(va[2][j], va[3][j])};
+    }
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      if (v == 1 && !u1_ok) break;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        *(uint2*)(xT + xst[v] + (2 * j) * WH_CHB) =
+            uint2{lo16x2(vx[v][0][j], vx[v][1][j]), lo16x2(vx[v][2][j], vx[v][3][j])};
+        *(uint2*)(xT + xst[v] + (2 * j + 1) * WH_CHB) =
+            uint2{hi16x2(vx[v][0][j], vx[v][1][j]), hi16x2(vx[v][2][j], vx[v][3][j])};
+      }
+    }
+    if (do_bias) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float f[8];
+        unpack8(va[q], f);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bsum[j] += f[j];
+      }
+    }
+  };
+  f32x4 acc[4][9];
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) acc[mb][tap] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int t = t_begin; t < t_end; ++t) {
+    load(t);
+    if (t > t_begin) __syncthreads();  // the previous tile's operand reads are done
+    stage();
+    __syncthreads();
+#pragma unroll
+    for (int kc = 0; kc < 4; ++kc) {
+      u32x4 av[4];
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) av[mb] = *(const u32x4*)&gzT[(16 * mb + i) * 128 + 8 * ((4 * kc + g) ^ ra_sw[mb])];
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const unsigned char* row = xT + bx + (2 * kc + dy) * WH_ROWB;
+        const u32x4 w0 = *(const u32x4*)(row + bs0), w1 = *(const u32x4*)(row + bs1);
+        const u32x4 b1 = {__builtin_amdgcn_alignbyte(w0[1], w0[0], 2), __builtin_amdgcn_alignbyte(w0[2], w0[1], 2),
+                          __builtin_amdgcn_alignbyte(w0[3], w0[2], 2), __builtin_amdgcn_alignbyte(w1[0], w0[3], 2)};
+        const u32x4 b2 = {w0[1], w0[2], w0[3], w1[0]};
+#pragma unroll
+        for (int mb = 0; mb < 4; ++mb) {
+          acc[mb][3 * dy] = mfma(av[mb], w0, acc[mb][3 * dy]);
+          acc[mb][3 * dy + 1] = mfma(av[mb], b1, acc[mb][3 * dy + 1]);
+          acc[mb][3 * dy + 2] = mfma(av[mb], b2, acc[mb][3 * dy + 2]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+  if (ct == 0) {
+    // lanes with equal (lane & 7) hold the same 8 channels: reduce them, then
+    // over the 4 waves through LDS
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      for (int off = 8; off < 64; off <<= 1) bsum[j] += __shfl_xor(bsum[j], off);
+    __syncthreads();
+    float* red = (float*)lds;
+    if (lane < 8)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) red[wv * 64 + s8 + j] = bsum[j];
+    __syncthreads();
+    if (tid < 64 && m0 + tid < a.cout)
+      atomicAdd(a.gb + m0 + tid, red[tid] + red[64 + tid] + red[128 + tid] + red[192 + tid]);
+  }
+  // partial block [co 64][tap 9][c 64] of this chunk and channel tile
+  float* pb = a.part + ((size_t)chn * tiles + tile) * (64 * 576);
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int tap = 0; tap < 9; ++tap) pb[((16 * mb + 4 * g + j) * 9 + tap) * 64 + cx] = acc[mb][tap][j];
+}
+
+// gw[co][tap][c] += sum over the nch chunks of the partial blocks of
+// k_wgrad_halo.  A 256-thread block takes 16 consecutive elements of the
+// (tiles x 64 x 576) blocks; its 16 groups of 16 lanes sum every 16th chunk
+// (coalesced 64-byte reads) and meet in LDS.
+__global__ void __launch_bounds__(256) k_wgrad_sum(const float* __restrict__ part, int tiles, int nch, int ktiles,
+                                                   int cout, int cin_true, float* __restrict__ gw) {
+  __shared__ float red[16][16];
+  const size_t blk = (size_t)64 * 576;
+  const size_t e = (size_t)blockIdx.x * 16 + (threadIdx.x & 15);
+  const int grp = threadIdx.x >> 4;
+  float s = 0.f;
+  if (e < (size_t)tiles * blk) {
+    const int tile = (int)(e / blk);
+    const size_t r = e % blk;
+    for (int k = grp; k < nch; k += 16) s += part[((size_t)k * tiles + tile) * blk + r];
+  }
+  red[grp][threadIdx.x & 15] = s;
+  __syncthreads();
+  if (threadIdx.x < 16 && e < (size_t)tiles * blk) {
+    float t = 0.f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) t += red[k][threadIdx.x];
+    const int tile = (int)(e / blk), r = (int)(e % blk);
+    const int co = (tile / ktiles) * 64 + r / 576, tap = (r % 576) / 64, c = (tile % ktiles) * 64 + r % 64;
+    if (co < cout && c < cin_true) gw[((size_t)co * 9 + tap) * cin_true + c] += t;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // resampling, 8 channels per thread.  Sizes: fine grid H x W, coarse H/2 x W/2.
 // ---------------------------------------------------------------------------
 // y (coarse) = mean of each 2x2 block of x (fine)
@@ -948,7 +1173,41 @@ WgradPlan wgrad_plan(int cout, int cin, size_t P) {
   return w;
 }
 
+WgradPlan wgrad_halo_plan(int cout, int cin, int B, int H, int W) {
+  WgradPlan w;
+  w.mtiles = (cout + 63) / 64;
+  w.ktiles = (cin + 63) / 64;  // input-channel tiles
+  const long ntile = (long)B * ((H + WH_TH - 1) / WH_TH) * ((W + WH_TW - 1) / WH_TW);
+  const long tiles = (long)w.mtiles * w.ktiles;
+  long nch = (WH_TARGET + tiles / 2) / tiles;
+  if (nch > ntile) nch = ntile;
+  if (nch < 1) nch = 1;
+  const long chunk = (ntile + nch - 1) / nch;
+  w.chunk = (int)chunk;
+  w.nch = (int)((ntile + chunk - 1) / chunk);
+  return w;
+}
+
+size_t wgrad_part_floats(int cout, int cin) {
+  if (cin < WH_MIN_CIN) return 0;
+  // nch * tiles <= max(WH_TARGET + tiles / 2, tiles) for every image size
+  const size_t tiles = (size_t)((cout + 63) / 64) * ((cin + 63) / 64);
+  return std::max((size_t)WH_TARGET + tiles / 2, tiles) * (64 * 576);
+}
+
 void wgrad(WgradArgs a, hipStream_t s) {
+  if (a.cin >= WH_MIN_CIN) {
+    const WgradPlan w = wgrad_halo_plan(a.cout, a.cin, a.B, a.H, a.W);
+    a.ktiles = w.ktiles;
+    a.mtiles = w.mtiles;
+    a.nch = w.nch;
+    a.chunk = w.chunk;
+    hipLaunchKernelGGL(k_wgrad_halo, dim3((unsigned)(w.mtiles * w.ktiles * w.nch)), dim3(256), 0, s, a);
+    const int tiles = w.mtiles * w.ktiles;
+    hipLaunchKernelGGL(k_wgrad_sum, dim3((unsigned)((size_t)tiles * 64 * 576 / 16)), dim3(256), 0, s, a.part, tiles,
+                       w.nch, w.ktiles, a.cout, a.cin_true, a.gw);
+    return;
+  }
   const WgradPlan w = wgrad_plan(a.cout, a.cin, (size_t)a.B * a.H * a.W);
   a.ktiles = w.ktiles;
   a.mtiles = w.mtiles;

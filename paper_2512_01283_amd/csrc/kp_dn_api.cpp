@@ -9,6 +9,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/polrad_denoiser.h"
@@ -49,6 +50,7 @@ struct Work {
            *geb[MAX_LEVELS] = {}, *gpool[MAX_LEVELS] = {};
   uint16_t *gm = nullptr, *gmb = nullptr;
   float *xq, *ihat, *tgt, *out, *go;
+  float* wpart = nullptr;  // partial weight-gradient blocks (k_wgrad_halo)
   double *sum, *loss;
   int32_t* aug;
 };
@@ -173,6 +175,9 @@ kp_status ensure_work(kp_dn* dn, size_t P1, int B) {
   plan.push_back({(void**)&w.sum, (size_t)bcap * 16});
   plan.push_back({(void**)&w.loss, 8});
   plan.push_back({(void**)&w.aug, (size_t)bcap * 4});
+  size_t part = 0;
+  for (const Layer& y : dn->layers) part = std::max(part, wgrad_part_floats(y.cout, y.cin));
+  plan.push_back({(void**)&w.wpart, part * 4});
   std::vector<size_t> offs;
   for (auto& e : plan) {
     offs.push_back(off);
@@ -279,6 +284,7 @@ void conv_wgrad(kp_dn* dn, int l, const uint16_t* gz, const uint16_t* x, int xs,
   a.cin_true = L.cin_true;
   a.gw = dn->d_g + L.w_off;
   a.gb = dn->d_g + L.b_off;
+  a.part = dn->w.wpart;
   a.B = B;
   a.H = H;
   a.W = W;

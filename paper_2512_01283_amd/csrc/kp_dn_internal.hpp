@@ -38,6 +38,7 @@ struct WgradArgs {
   int xs, cin, cin_true;
   float* gw;  // weight gradient [cout][9][cin_true], accumulated
   float* gb;  // bias gradient [cout], accumulated
+  float* part;  // k_wgrad_halo's partial blocks, wgrad_part_floats(cout, cin) floats
   int B, H, W;
   int chunk, nch, ktiles, mtiles;  // set by the launcher
 };
@@ -51,6 +52,12 @@ struct WgradPlan {
   int ktiles, mtiles, nch, chunk;
 };
 WgradPlan wgrad_plan(int cout, int cin, size_t P);
+// k_wgrad_halo (cin >= 48): 64 x 64 (co, c) channel tiles times nch chunks of
+// `chunk` pixel tiles of 8 x 16
+WgradPlan wgrad_halo_plan(int cout, int cin, int B, int H, int W);
+// scratch of the partial blocks k_wgrad_halo writes for a layer at any image
+// size (0 where the layer keeps k_wgrad)
+size_t wgrad_part_floats(int cout, int cin);
 
 void conv3(const ConvArgs& a, int mode, hipStream_t s);
 void wgrad(WgradArgs a, hipStream_t s);
