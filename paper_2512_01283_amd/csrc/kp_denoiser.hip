@@ -508,14 +508,18 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
 // stores take about two cycles per pass.  A tap's operand is columns
 // col..col+7 of a halo row with col = 8 (g & 1) + dx: two aligned 16-byte
 // reads per (row, dy) give the three dx shifts (dx = 1 by byte alignment, dx
-// = 2 by a dword shift).  Wave w computes channels 16 w..16 w+15 of every
-// tap for all 64 co: 4 x 9 MFMA tiles, 36 MFMAs per 32 pixels against 10
-// operand reads.  Each workgroup writes its partial 64 x 576 block to a
-// scratch area with plain stores, and k_wgrad_sum adds the chunks into the
-// gradient: with two workgroups per CU resident, the blocks of all of them
-// land at the end of the launch, and as FP32 atomics (about 1.2e6 64-byte
-// requests per launch) they took as long as the MFMAs.  The workgroups of
-// the first channel tile add the bias gradient with atomics (64 each).
+// = 2 by a dword shift).  Eight waves: waves 0-3 load and stage gz, waves
+// 4-7 the x halo; wave w computes output channels 32 (w >> 2)..+31 x input
+// channels 16 (w & 3)..+15 of every tap (2 x 9 MFMA tiles, 18 MFMAs per 32
+// pixels against 8 operand reads).  The next tile's loads are in flight in
+// registers during the current tile's MFMAs (double-buffered LDS, one
+// barrier per tile, one workgroup per CU).  Each workgroup writes its
+// partial 64 x 576 block to a scratch area with plain stores and
+// k_wgrad_sum adds the chunks into the gradient: the blocks of all resident
+// workgroups land at the end of the launch, and as FP32 atomics (1.2e6
+// 64-byte requests per launch at two 4-wave workgroups per CU) they took
+// as long as the MFMAs.  The workgroups of the first channel tile add the
+// bias gradient with atomics (64 each).
 // ---------------------------------------------------------------------------
 constexpr int WH_TH = 8, WH_TW = 16;          // pixel tile (128 pixels)
 constexpr int WH_HR = WH_TH + 2;              // halo rows
@@ -524,14 +528,12 @@ constexpr int WH_NU = WH_HR * WH_NQ;          // quads per halo (50)
 constexpr int WH_ROWB = 64;                   // LDS bytes per halo row of one channel
 constexpr int WH_CHB = WH_HR * WH_ROWB + 32;  // LDS bytes per channel (672)
 constexpr int WH_GZB = 64 * 128 * 2;          // gz^T: 64 channels x 128 pixels
-constexpr int WH_LDS = WH_GZB + 64 * WH_CHB;  // 59392 bytes: two workgroups per CU
-constexpr int WH_TARGET = 512;                // workgroups per launch (two per CU)
+constexpr int WH_BUF = WH_GZB + 64 * WH_CHB;  // one tile's operands (59392 bytes)
+constexpr int WH_TARGET = 256;                // workgroups per launch (one per CU)
 constexpr int WH_MIN_CIN = 48;                // narrower inputs keep k_wgrad
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_wgrad_halo(WgradArgs a) {
-  __shared__ __attribute__((aligned(16))) unsigned char lds[WH_LDS];
-  uint16_t* gzT = (uint16_t*)lds;
-  unsigned char* xT = lds + WH_GZB;
+__global__ void __launch_bounds__(512) k_wgrad_halo(WgradArgs a) {
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2 * WH_BUF];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int i = lane & 15, g = lane >> 4;
@@ -546,131 +548,156 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   const int mt = tile / a.ktiles, ct = tile - mt * a.ktiles;
   const int m0 = mt * 64, c0 = ct * 64;
   const int t_begin = chn * a.chunk, t_end = min(ntile, t_begin + a.chunk);
-  // loader slots: gz pixels 4 sp .. 4 sp + 3 of the tile (row sp >> 2,
-  // columns 4 (sp & 3) ..), channels m0 + s8 ..; x halo quads u0 and u0 + 32
-  // (halo row u % 10, columns 4 (u / 10) ..), channels c0 + s8 ..
-  const int sp = tid >> 3, a8 = tid & 7, s8 = 8 * a8;
+  // loaders: waves 0-3 stage gz (pixels 4 sp .. 4 sp + 3 of the tile: row
+  // sp >> 2, columns 4 (sp & 3) ..; channels m0 + s8 ..), waves 4-7 the x
+  // halo (quads u0 and u0 + 32: halo row u % 10, columns 4 (u / 10) ..;
+  // channels c0 + s8 ..); both hold their loads in the same registers
+  const bool gz_role = wv < 4;
+  const int lt = tid & 255;
+  const int sp = lt >> 3, a8 = lt & 7, s8 = 8 * a8;
   const bool a_ok = m0 + s8 < a.cout, x_ok = c0 + s8 < a.cin;
-  const int u0 = tid >> 3;
+  const int u0 = lt >> 3;
   const bool u1_ok = u0 + 32 < WH_NU;
   int xst[2];  // byte offset of channel s8's row slot for each quad; + j * WH_CHB per channel
 #pragma unroll
   for (int v = 0; v < 2; ++v) {
     const int u = u0 + 32 * v, hr = u % WH_HR, q = u / WH_HR;
-    xst[v] = s8 * WH_CHB + hr * WH_ROWB + 16 * ((q >> 1) ^ (a8 & 3)) + 8 * (q & 1);
+    xst[v] = WH_GZB + s8 * WH_CHB + hr * WH_ROWB + 16 * ((q >> 1) ^ (a8 & 3)) + 8 * (q & 1);
   }
-  // operand reads: A rows 16 mb + i (chunk 4 kc + g); B channel 16 wv + i,
-  // halo row 2 kc + (g >> 1) + dy, chunks (g & 1) and (g & 1) + 1
-  // A row 16 mb + i: chunk 4 kc + g sits at slot (4 kc + g) ^ ra_sw[mb]
-  int ra_sw[4];
+  // wave w computes output channels 32 (w >> 2) .. + 31 (two MFMA rows of
+  // 16) x input channels 16 (w & 3) .. + 15 of all nine taps.  A row 16 mb +
+  // i: chunk 4 kc + g sits at slot (4 kc + g) ^ ra_sw[m]; B channel cx, halo
+  // row 2 kc + (g >> 1) + dy, chunks (g & 1) and (g & 1) + 1
+  const int mh = wv >> 2;
+  int ra_sw[2];
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb) ra_sw[mb] = wg_swz(16 * mb + i, 0);
-  const int cx = 16 * wv + i, xsw = (cx >> 3) & 3;
-  const int bx = cx * WH_CHB + (g >> 1) * WH_ROWB;
+  for (int m = 0; m < 2; ++m) ra_sw[m] = wg_swz(16 * (2 * mh + m) + i, 0);
+  const int cx = 16 * (wv & 3) + i, xsw = (cx >> 3) & 3;
+  const int bx = WH_GZB + cx * WH_CHB + (g >> 1) * WH_ROWB;
   const int bs0 = 16 * ((g & 1) ^ xsw), bs1 = 16 * (((g & 1) + 1) ^ xsw);
-  const bool do_bias = ct == 0 && a_ok;
+  const bool do_bias = ct == 0 && gz_role && a_ok;
   float bsum[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) bsum[j] = 0.f;
   const u32x4 zero = {0u, 0u, 0u, 0u};
-  u32x4 va[4], vx[2][4];
+  u32x4 pre[8];  // gz role: pixels 0..3; x role: quad u0 (0..3) and u0 + 32 (4..7)
   auto load = [&](int t) {
     const int img = t / (tyn * txn), rt = t - img * tyn * txn;
     const int y0 = (rt / txn) * WH_TH, x0 = (rt % txn) * WH_TW;
-    {
+    if (gz_role) {
       const int yy = y0 + (sp >> 2), xb = x0 + 4 * (sp & 3);
       const size_t prow = (size_t)(img * a.H + yy) * a.W;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const bool ok = a_ok && yy < a.H && xb + q < a.W;
-        va[q] = ok ? ld16(a.gz + (prow + xb + q) * a.gzs + m0 + s8) : zero;
+        pre[q] = ok ? ld16(a.gz + (prow + xb + q) * a.gzs + m0 + s8) : zero;
       }
-    }
+    } else {
 #pragma unroll
-    for (int v = 0; v < 2; ++v) {
-      const int u = u0 + 32 * v, hr = u % WH_HR, q = u / WH_HR;
-      const int yy = y0 + hr - 1, xb = x0 + 4 * q - 1;
-      const bool rok = x_ok && (v == 0 || u1_ok) && yy >= 0 && yy < a.H;
-      const size_t prow = (size_t)(img * a.H + yy) * a.W;
+      for (int v = 0; v < 2; ++v) {
+        const int u = u0 + 32 * v, hr = u % WH_HR, q = u / WH_HR;
+        const int yy = y0 + hr - 1, xb = x0 + 4 * q - 1;
+        const bool rok = x_ok && (v == 0 || u1_ok) && yy >= 0 && yy < a.H;
+        const size_t prow = (size_t)(img * a.H + yy) * a.W;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int xx = xb + e;
-        const bool ok = rok && 4 * q + e < WH_TW + 2 && xx >= 0 && xx < a.W;
-        vx[v][e] = ok ? ld16(a.x + (prow + xx) * a.xs + c0 + s8) : zero;
+        for (int e = 0; e < 4; ++e) {
+          const int xx = xb + e;
+          const bool ok = rok && 4 * q + e < WH_TW + 2 && xx >= 0 && xx < a.W;
+          pre[4 * v + e] = ok ? ld16(a.x + (prow + xx) * a.xs + c0 + s8) : zero;
+        }
       }
     }
   };
-  auto stage = [&]() {
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r0 = s8 + 2 * j, r1 = r0 + 1;
-      *(uint2*)&gzT[r0 * 128 + 8 * wg_swz(r0, sp >> 1) + (sp & 1) * 4] =
-          uint2{lo16x2(va[0][j], va[1][j]), lo16x2(va[2][j], va[3][j])};
-      *(uint2*)&gzT[r1 * 128 + 8 * wg_swz(r1, sp >> 1) + (sp & 1) * 4] =
-          uint2{hi16x2(va[0][j], va[1][j]), hi16x2(va[2][j], va[3][j])};
-    }
-#pragma unroll
-    for (int v = 0; v < 2; ++v) {
-      if (v == 1 && !u1_ok) break;
+  // transposed stores of the loaded tile into LDS buffer `buf`
+  auto stage = [&](int buf) {
+    unsigned char* b = lds + buf * WH_BUF;
+    if (gz_role) {
+      uint16_t* gzT = (uint16_t*)b;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        *(uint2*)(xT + xst[v] + (2 * j) * WH_CHB) =
-            uint2{lo16x2(vx[v][0][j], vx[v][1][j]), lo16x2(vx[v][2][j], vx[v][3][j])};
-        *(uint2*)(xT + xst[v] + (2 * j + 1) * WH_CHB) =
-            uint2{hi16x2(vx[v][0][j], vx[v][1][j]), hi16x2(vx[v][2][j], vx[v][3][j])};
+        const int r0 = s8 + 2 * j, r1 = r0 + 1;
+        *(uint2*)&gzT[r0 * 128 + 8 * wg_swz(r0, sp >> 1) + (sp & 1) * 4] =
+            uint2{lo16x2(pre[0][j], pre[1][j]), lo16x2(pre[2][j], pre[3][j])};
+        *(uint2*)&gzT[r1 * 128 + 8 * wg_swz(r1, sp >> 1) + (sp & 1) * 4] =
+            uint2{hi16x2(pre[0][j], pre[1][j]), hi16x2(pre[2][j], pre[3][j])};
       }
-    }
-    if (do_bias) {
+      if (do_bias) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        float f[8];
-        unpack8(va[q], f);
+        for (int q = 0; q < 4; ++q) {
+          float f[8];
+          unpack8(pre[q], f);
 #pragma unroll
-        for (int j = 0; j < 8; ++j) bsum[j] += f[j];
+          for (int j = 0; j < 8; ++j) bsum[j] += f[j];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        if (v == 1 && !u1_ok) break;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          *(uint2*)(b + xst[v] + (2 * j) * WH_CHB) =
+              uint2{lo16x2(pre[4 * v][j], pre[4 * v + 1][j]), lo16x2(pre[4 * v + 2][j], pre[4 * v + 3][j])};
+          *(uint2*)(b + xst[v] + (2 * j + 1) * WH_CHB) =
+              uint2{hi16x2(pre[4 * v][j], pre[4 * v + 1][j]), hi16x2(pre[4 * v + 2][j], pre[4 * v + 3][j])};
+        }
       }
     }
   };
-  f32x4 acc[4][9];
+  f32x4 acc[2][9];
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
+  for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) acc[mb][tap] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int t = t_begin; t < t_end; ++t) {
-    load(t);
-    if (t > t_begin) __syncthreads();  // the previous tile's operand reads are done
-    stage();
-    __syncthreads();
+    for (int tap = 0; tap < 9; ++tap) acc[m][tap] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // one tile from LDS buffer `cur` (a literal at each use), the next tile's
+  // loads in flight and staged into the other buffer; false after the last
+  auto step = [&](int t, int cur) {
+    const bool more = t + 1 < t_end;
+    if (more) load(t + 1);
+    const unsigned char* b = lds + cur * WH_BUF;
+    const uint16_t* gzT = (const uint16_t*)b;
 #pragma unroll
     for (int kc = 0; kc < 4; ++kc) {
-      u32x4 av[4];
+      u32x4 av[2];
 #pragma unroll
-      for (int mb = 0; mb < 4; ++mb) av[mb] = *(const u32x4*)&gzT[(16 * mb + i) * 128 + 8 * ((4 * kc + g) ^ ra_sw[mb])];
+      for (int m = 0; m < 2; ++m)
+        av[m] = *(const u32x4*)&gzT[(16 * (2 * mh + m) + i) * 128 + 8 * ((4 * kc + g) ^ ra_sw[m])];
 #pragma unroll
       for (int dy = 0; dy < 3; ++dy) {
-        const unsigned char* row = xT + bx + (2 * kc + dy) * WH_ROWB;
+        const unsigned char* row = b + bx + (2 * kc + dy) * WH_ROWB;
         const u32x4 w0 = *(const u32x4*)(row + bs0), w1 = *(const u32x4*)(row + bs1);
         const u32x4 b1 = {__builtin_amdgcn_alignbyte(w0[1], w0[0], 2), __builtin_amdgcn_alignbyte(w0[2], w0[1], 2),
                           __builtin_amdgcn_alignbyte(w0[3], w0[2], 2), __builtin_amdgcn_alignbyte(w1[0], w0[3], 2)};
         const u32x4 b2 = {w0[1], w0[2], w0[3], w1[0]};
 #pragma unroll
-        for (int mb = 0; mb < 4; ++mb) {
-          acc[mb][3 * dy] = mfma(av[mb], w0, acc[mb][3 * dy]);
-          acc[mb][3 * dy + 1] = mfma(av[mb], b1, acc[mb][3 * dy + 1]);
-          acc[mb][3 * dy + 2] = mfma(av[mb], b2, acc[mb][3 * dy + 2]);
+        for (int m = 0; m < 2; ++m) {
+          acc[m][3 * dy] = mfma(av[m], w0, acc[m][3 * dy]);
+          acc[m][3 * dy + 1] = mfma(av[m], b1, acc[m][3 * dy + 1]);
+          acc[m][3 * dy + 2] = mfma(av[m], b2, acc[m][3 * dy + 2]);
         }
-        __builtin_amdgcn_sched_barrier(0);
       }
+    }
+    if (more) stage(cur ^ 1);
+    __syncthreads();
+    return more;
+  };
+  if (t_begin < t_end) {
+    load(t_begin);
+    stage(0);
+    __syncthreads();
+    for (int t = t_begin;; t += 2) {
+      if (!step(t, 0)) break;
+      if (!step(t + 1, 1)) break;
     }
   }
   if (ct == 0) {
-    // lanes with equal (lane & 7) hold the same 8 channels: reduce them, then
-    // over the 4 waves through LDS
+    // gz lanes with equal (lane & 7) hold the same 8 channels: reduce them,
+    // then over the 4 gz waves through LDS (free after the loop's last barrier)
 #pragma unroll
     for (int j = 0; j < 8; ++j)
       for (int off = 8; off < 64; off <<= 1) bsum[j] += __shfl_xor(bsum[j], off);
-    __syncthreads();
     float* red = (float*)lds;
-    if (lane < 8)
+    if (gz_role && lane < 8)
 #pragma unroll
       for (int j = 0; j < 8; ++j) red[wv * 64 + s8 + j] = bsum[j];
     __syncthreads();
@@ -680,11 +707,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   // partial block [co 64][tap 9][c 64] of this chunk and channel tile
   float* pb = a.part + ((size_t)chn * tiles + tile) * (64 * 576);
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
+  for (int m = 0; m < 2; ++m)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int tap = 0; tap < 9; ++tap) pb[((16 * mb + 4 * g + j) * 9 + tap) * 64 + cx] = acc[mb][tap][j];
+      for (int tap = 0; tap < 9; ++tap)
+        pb[((16 * (2 * mh + m) + 4 * g + j) * 9 + tap) * 64 + cx] = acc[m][tap][j];
 }
 
 // gw[co][tap][c] += sum over the nch chunks of the partial blocks of
@@ -1202,7 +1230,7 @@ void wgrad(WgradArgs a, hipStream_t s) {
     a.mtiles = w.mtiles;
     a.nch = w.nch;
     a.chunk = w.chunk;
-    hipLaunchKernelGGL(k_wgrad_halo, dim3((unsigned)(w.mtiles * w.ktiles * w.nch)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_wgrad_halo, dim3((unsigned)(w.mtiles * w.ktiles * w.nch)), dim3(512), 0, s, a);
     const int tiles = w.mtiles * w.ktiles;
     hipLaunchKernelGGL(k_wgrad_sum, dim3((unsigned)((size_t)tiles * 64 * 576 / 16)), dim3(256), 0, s, a.part, tiles,
                        w.nch, w.ktiles, a.cout, a.cin_true, a.gw);
