@@ -778,8 +778,8 @@ __device__ bool scatter_tab(Packet<R>& p, const DustDev& D, uint64_t seed) {
   return false;
 }
 
-template <typename R>
-__device__ uint32_t roulette(Packet<R>& p, const TransportArgs& a, uint64_t cn);
+template <bool MESH, typename R>
+__device__ uint32_t roulette(Packet<R>& p, const TransportArgs& a);
 
 // One loop iteration: one cell segment (Sec. 2.2: cell-to-cell traversal,
 // exponential scattering depth, continuous extinction across the segment by
@@ -920,21 +920,24 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
     // leaving through an open face ends the packet; a periodic face brings
     // it back through the opposite one; on a mesh, leaving the leaf block
     // moves it into the leaf beyond
-    const bool per = (a.boundary >> axis) & 1;
     const int nbx = MESH ? a.mesh.block : a.nx, nby = MESH ? a.mesh.block : a.ny;
     const int nbz = MESH ? a.mesh.block : a.nz;
     if (axis == 0) {
       if (dnx > 0.0) { p.ci++; p.fx = 0.0; } else { p.ci--; p.fx = 1.0; }
       out = p.ci < 0 || p.ci >= nbx;
-      if (out && per) { p.ci = p.ci < 0 ? a.nx - 1 : 0; out = false; }
     } else if (axis == 1) {
       if (dny > 0.0) { p.cj++; p.fy = 0.0; } else { p.cj--; p.fy = 1.0; }
       out = p.cj < 0 || p.cj >= nby;
-      if (out && per) { p.cj = p.cj < 0 ? a.ny - 1 : 0; out = false; }
     } else {
       if (dnz > 0.0) { p.ck++; p.fz = 0.0; } else { p.ck--; p.fz = 1.0; }
       out = p.ck < 0 || p.ck >= nbz;
-      if (out && per) { p.ck = p.ck < 0 ? a.nz - 1 : 0; out = false; }
+    }
+    // the boundary mask is the same for every lane: open grids skip the wrap
+    if (!MESH && a.boundary != 0 && out && ((a.boundary >> axis) & 1)) {
+      if (axis == 0) p.ci = p.ci < 0 ? a.nx - 1 : 0;
+      else if (axis == 1) p.cj = p.cj < 0 ? a.ny - 1 : 0;
+      else p.ck = p.ck < 0 ? a.nz - 1 : 0;
+      out = false;
     }
     if (MESH && out) out = mesh_cross(p, a);
     if (out) {
@@ -944,7 +947,7 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
     // the next step's density, in flight while this iteration finishes
     if (!TallyShape<SPHERE>::HAS_B) p.rho = a.rho[cell_index<MESH>(p, a)];
   }
-  return roulette(p, a, cell_index<MESH>(p, a));
+  return roulette<MESH>(p, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -1228,14 +1231,16 @@ __device__ uint32_t scatter_step(Packet<R>& p, const TransportArgs& a) {
   p.events++;
   p.hash = hash_event(p.hash, EV_SCATTER, c);
   p.tau = -log((double)next_uniform(p, a.seed));
-  return roulette(p, a, c);
+  return roulette<MESH>(p, a);
 }
 
-// Russian roulette after a segment or an event in cell cn (reading R8).
-template <typename R>
-__device__ uint32_t roulette(Packet<R>& p, const TransportArgs& a, uint64_t cn) {
+// Russian roulette after a segment or an event in the packet's cell (reading
+// R8); the cell index is formed only when the check draws
+template <bool MESH, typename R>
+__device__ uint32_t roulette(Packet<R>& p, const TransportArgs& a) {
   if (!isfinite(p.I)) return END_NUMERIC;
   if (a.rr_wmin > 0.0 && p.I < (R)a.rr_wmin * p.w0) {
+    const uint64_t cn = cell_index<MESH>(p, a);
     R u = next_uniform(p, a.seed);
     if (u < (R)a.rr_psurv) {
       const R before = p.I, inv = (R)1 / (R)a.rr_psurv;
