@@ -133,7 +133,8 @@ int kpo_transport(const kpo_grid *g, const float *rho, const float *bhat,
  * the Stokes vector scattered toward each camera, attenuated along the line
  * of sight to the grid's edge, is added to the pixel the event projects to,
  * divided by the pixel's area.  peel: [view][4][npy][npx], accumulated.
- * Open boundaries only; S and traces may be NULL. */
+ * Open boundaries only, on a uniform grid or a composite mesh; S may be
+ * NULL. */
 int kpo_transport_peel(const kpo_grid *g, const float *rho, const float *bhat,
                        const kpo_dust *d, int32_t lam, const kpo_source *src,
                        int32_t n_views, const kpo_view *views,
