@@ -69,23 +69,23 @@ def counter_traffic():
 ATOMIC_CAL_LINES = 1 << 24
 
 
-def atomic_calibration(lines: int = ATOMIC_CAL_LINES, reps: int = 3) -> float:
-    """Random 64-byte-line FP64 atomics the device sustains, in lines/s: the
-    tally flush's own access pattern (lane L adds component L % 6 of block
-    L / 6, one wave covering 10 blocks) over uniformly random blocks of a
-    [256^3][8] FP64 array, in libkpcalib.so (csrc/kp_calib.hip); best of
-    `reps` launches, HIP events."""
+def atomic_calibration(lines: int = ATOMIC_CAL_LINES, reps: int = 3, order: int = 0) -> float:
+    """64-byte-line FP64 atomics the device sustains, in lines/s: the tally
+    flush's own access pattern (lane L adds component L % 6 of block L / 6,
+    one wave covering 10 blocks) over the blocks of a [256^3][8] FP64 array
+    in uniformly random (order 0) or consecutive (order 1) order, in
+    libkpcalib.so (csrc/kp_calib.hip); best of `reps` launches, HIP events."""
     import ctypes as C
     path = os.path.join(ROOT, "paper_2512_01283_amd", "libkpcalib.so")
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: run python -m paper_2512_01283_amd.build")
     lib = C.CDLL(path)
-    lib.kpcal_atomic_lines.argtypes = [C.c_int, C.c_int64, C.c_int, C.c_int, C.POINTER(C.c_double)]
-    lib.kpcal_atomic_lines.restype = C.c_int
+    lib.kpcal_atomic_lines_order.argtypes = [C.c_int, C.c_int64, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)]
+    lib.kpcal_atomic_lines_order.restype = C.c_int
     out = C.c_double()
-    st = lib.kpcal_atomic_lines(0, lines, 6, reps, C.byref(out))
+    st = lib.kpcal_atomic_lines_order(0, lines, 6, reps, order, C.byref(out))
     if st != 0:
-        raise RuntimeError(f"kpcal_atomic_lines failed ({st})")
+        raise RuntimeError(f"kpcal_atomic_lines_order failed ({st})")
     return float(out.value)
 
 
@@ -188,7 +188,8 @@ def main():
         return
     if args.atomic_calibration:
         print(json.dumps({"atomic_calibration_lines": ATOMIC_CAL_LINES,
-                          "lines_per_s": atomic_calibration()}))
+                          "consecutive_lines_per_s": atomic_calibration(order=1),
+                          "uniform_random_lines_per_s": atomic_calibration(order=0)}))
         return
 
     import numpy as np
@@ -322,19 +323,24 @@ def main():
             d["train_wgrad_mfma_frac"] = d["train_wgrad_tflops"] / BF16_PEAK_TFLOPS
         out["detail"]["denoiser"] = d
         dn.close()
-    # the transport's binding resource: random tally-line atomics, against
-    # what a plain scatter-add of the same shape sustains on this device
-    cal = atomic_calibration()
+    # the transport's binding resource: tally-line atomics, against what a
+    # plain scatter-add of the same shape sustains on this device with the
+    # most locality (consecutive lines: the bound) and with none (uniformly
+    # random lines)
+    cal_seq = atomic_calibration(order=1)
+    cal = atomic_calibration(order=0)
     lines = float(np.mean(flushes))
+    achieved = lines / (avg_t * 1e-3)
     out["detail"]["atomic_roofline"] = {
-        "bound": "random 64-byte-line FP64 atomics (tally flush)",
-        "achieved_lines_per_s": lines / (avg_t * 1e-3), "calibrated_lines_per_s": cal,
-        "frac": lines / (avg_t * 1e-3) / cal, "lines_per_launch": lines,
+        "bound": "64-byte-line FP64 atomics (tally flush)",
+        "achieved_lines_per_s": achieved, "calibrated_lines_per_s": cal_seq,
+        "frac": achieved / cal_seq, "lines_per_launch": lines,
+        "uniform_random_lines_per_s": cal, "frac_of_uniform_random": achieved / cal,
         "lines_unit": "tally cell blocks flushed per transport launch (kp_stats.tally_flushes), "
                       "one 64-byte block of six FP64 each",
-        "calibration": "2^24 uniformly random 64-byte blocks of a [256^3][8] FP64 array, six FP64 "
-                       "atomics each in the flush's lane pattern, best of 3 (bench.py --atomic-calibration, "
-                       "csrc/kp_calib.hip)"}
+        "calibration": "2^24 64-byte blocks of a [256^3][8] FP64 array, six FP64 atomics each in the "
+                       "flush's lane pattern, consecutive (the bound) and uniformly random, best of 3 each "
+                       "(bench.py --atomic-calibration, csrc/kp_calib.hip)"}
     if not args.no_cpu_baseline:
         print("timing the oracle on a bounded sample ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample, args.cpu_sample_1t)

@@ -339,6 +339,18 @@ kp_status check_ready(kp_ctx* ctx) {
   return KP_OK;
 }
 
+// Tally layout of the loaded grid: slots per wavelength and bricks along x
+// and y (tally_slot); a composite mesh keeps its cell order.
+struct TallyLayout {
+  uint64_t nslot;
+  int tbx, tby;
+};
+TallyLayout tally_layout(const kp_ctx* ctx) {
+  if (ctx->have_mesh) return TallyLayout{ctx->ncell, 0, 0};
+  const kp_grid& g = ctx->grid;
+  return TallyLayout{tally_slots(g.nx, g.ny, g.nz), (g.nx + 3) / 4, (g.ny + 3) / 4};
+}
+
 // Step 2.  With user_source the source is the per-view array d_S (the
 // caller's, or the per-view tally of tabulated grains when from_tally),
 // else the coherency tally d_tally; the dust's thermal term is added for a
@@ -365,6 +377,13 @@ kp_status image_launch(kp_ctx* ctx, bool user_source, const double* d_S, double*
   a.user_S = d_S;
   a.images = d_out;
   a.ncell = ctx->ncell;
+  // the tally and the per-view tally are in the tally layout, a caller's
+  // source array in cell order
+  const TallyLayout tl = tally_layout(ctx);
+  const bool slots = !user_source || from_tally;
+  a.nslot = slots ? tl.nslot : ctx->ncell;
+  a.tbx = slots ? tl.tbx : 0;
+  a.tby = slots ? tl.tby : 0;
   a.em_B = ((!user_source || from_tally) && ctx->src.kind == 2) ? ctx->d_em_B : nullptr;
   a.boundary = ctx->grid.boundary;
   a.mesh = mesh_dev(ctx);
@@ -475,12 +494,14 @@ kp_status transport_launch(kp_ctx* ctx, const kp_opts* o, uint64_t total, const 
   const bool tab = ctx->have_tables;
   const size_t trace_need = (size_t)nl * o->trace_packets;
   const int npx = ctx->views[0].npx, npy = ctx->views[0].npy, nv = (int)ctx->views.size();
+  const TallyLayout tl = tally_layout(ctx);
   if (tab)
-    KP_HIP(launch_fill_zero(b.tally, (size_t)nl * ctx->ncell * nv * 4 * sizeof(double), s), "tally clear");
+    KP_HIP(launch_fill_zero(b.tally, (size_t)nl * tl.nslot * nv * 4 * sizeof(double), s), "tally clear");
   else
     KP_HIP(launch_tally_init(b.tally, ctx->d_rho, ctx->d_bhat,
                              ctx->d_bhat ? ctx->d_bhat + ctx->ncell : nullptr,
-                             ctx->d_bhat ? ctx->d_bhat + 2 * ctx->ncell : nullptr, ctx->ncell, nl, all_sphere, s),
+                             ctx->d_bhat ? ctx->d_bhat + 2 * ctx->ncell : nullptr, ctx->ncell, nl, all_sphere,
+                             tl.nslot, ctx->grid.nx, ctx->grid.ny, tl.tbx, tl.tby, s),
            "tally initialisation");
   KP_HIP(launch_fill_zero(b.stats, sizeof(StatsDev), s), "stats clear");
   KP_HIP(launch_fill_zero(b.counter, sizeof(unsigned long long), s), "counter clear");
@@ -509,6 +530,9 @@ kp_status transport_launch(kp_ctx* ctx, const kp_opts* o, uint64_t total, const 
   a.max_events = (int)o->max_events;
   a.tally = b.tally;
   a.ncell = ctx->ncell;
+  a.nslot = tl.nslot;
+  a.tbx = tl.tbx;
+  a.tby = tl.tby;
   a.counter = b.counter;
   a.stats = b.stats;
   a.traces = b.traces;
@@ -923,8 +947,9 @@ kp_status kp_transport(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, vo
   const int nl = (int)ctx->dust.size();
   const bool all_sphere = all_spheres(ctx);
   const int ts = tally_stride(all_sphere);
-  const size_t tally_need = ctx->have_tables ? (size_t)nl * ctx->ncell * ctx->views.size() * 4
-                                             : (size_t)nl * ctx->ncell * ts;
+  const uint64_t nslot = tally_layout(ctx).nslot;
+  const size_t tally_need = ctx->have_tables ? (size_t)nl * nslot * ctx->views.size() * 4
+                                             : (size_t)nl * nslot * ts;
   const size_t trace_need = (size_t)nl * o->trace_packets;
   const size_t peel_need =
       o->peel_off ? (size_t)nl * ctx->views.size() * 4 * ctx->views[0].npx * ctx->views[0].npy : 0;
@@ -1013,11 +1038,12 @@ kp_status kp_run_static(kp_ctx* ctx, const uint64_t* counts, const kp_opts* o, d
   const bool all_sphere = all_spheres(ctx);
   const size_t cell_bytes = ctx->have_tables ? (size_t)nv * 4 * sizeof(double)
                                              : (size_t)tally_stride(all_sphere) * sizeof(double);
-  const size_t tally_bytes = (size_t)nl * ctx->ncell * cell_bytes;
+  const uint64_t nslot = tally_layout(ctx).nslot;
+  const size_t tally_bytes = (size_t)nl * nslot * cell_bytes;
   if (tally_bytes > KP_STATIC_TALLY)
     return fail(ctx, KP_ERR_ARG, "the tally needs %zu bytes, more than the %zu of the static scratch "
-                "(%d wavelengths x %llu cells x %zu B): use kp_run", tally_bytes, KP_STATIC_TALLY, nl,
-                (unsigned long long)ctx->ncell, cell_bytes);
+                "(%d wavelengths x %llu cell slots x %zu B): use kp_run", tally_bytes, KP_STATIC_TALLY, nl,
+                (unsigned long long)nslot, cell_bytes);
   // head of the scratch: stats at 0, work counter at 256, the dust table at
   // 512, the camera table after it (at most 1024 x 144 B + 4096 x 80 B)
   const size_t dust_off = 512, dust_bytes = (size_t)nl * sizeof(DustDev);
@@ -1100,6 +1126,31 @@ kp_status kp_get_peel_images(kp_ctx* ctx, double* out, size_t n) {
   return KP_OK;
 }
 
+// Copy of the last step 1's tally to the host in cell order: per (wavelength,
+// cell) the first `keep` of the `stride` doubles at its tally slot, into
+// rows of `row` doubles (zero past `keep`).
+kp_status copy_tally_cells(kp_ctx* ctx, double* out, size_t row, size_t stride, size_t keep) {
+  const TallyLayout tl = tally_layout(ctx);
+  const size_t nl = (size_t)ctx->tally_lambda;
+  std::vector<double> h;
+  try {
+    h.resize(nl * tl.nslot * stride);
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, KP_ERR_OOM, "host copy of the tally (%zu doubles)", nl * tl.nslot * stride);
+  }
+  KP_HIP(hipMemcpy(h.data(), ctx->d_tally, h.size() * sizeof(double), hipMemcpyDeviceToHost), "tally copy");
+  const int nx = ctx->grid.nx, ny = ctx->grid.ny;
+  for (size_t l = 0; l < nl; ++l)
+    for (uint64_t c = 0; c < ctx->ncell; ++c) {
+      const uint64_t ck = tl.tbx ? c / ((uint64_t)nx * ny) : 0, r = tl.tbx ? c - ck * (uint64_t)nx * ny : 0;
+      const uint64_t sl = tally_slot(c, (int)(r % nx), (int)(r / nx), (int)ck, tl.tbx, tl.tby);
+      const double* src = h.data() + (l * tl.nslot + sl) * stride;
+      double* dst = out + (l * ctx->ncell + c) * row;
+      for (size_t k = 0; k < row; ++k) dst[k] = k < keep ? src[k] : 0.0;
+    }
+  return KP_OK;
+}
+
 kp_status kp_get_view_tally(kp_ctx* ctx, double* out, size_t n) {
   if (!ctx) return KP_ERR_ARG;
   if (!ctx->have_tally || !ctx->tally_views)
@@ -1108,8 +1159,7 @@ kp_status kp_get_view_tally(kp_ctx* ctx, double* out, size_t n) {
   const size_t need = (size_t)ctx->tally_lambda * ctx->ncell * ctx->tally_nv * 4;
   if (!out || n != need) return fail(ctx, KP_ERR_ARG, "destination must hold %zu doubles", need);
   KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-  KP_HIP(hipMemcpy(out, ctx->d_tally, n * sizeof(double), hipMemcpyDeviceToHost), "tally copy");
-  return KP_OK;
+  return copy_tally_cells(ctx, out, (size_t)ctx->tally_nv * 4, (size_t)ctx->tally_nv * 4, (size_t)ctx->tally_nv * 4);
 }
 
 kp_status kp_get_tally(kp_ctx* ctx, double* out, size_t n) {
@@ -1121,12 +1171,7 @@ kp_status kp_get_tally(kp_ctx* ctx, double* out, size_t n) {
   const size_t need = rows * 9;
   if (!out || n != need) return fail(ctx, KP_ERR_ARG, "destination must hold %zu doubles", need);
   KP_HIP(hipSetDevice(ctx->device), "hipSetDevice");
-  KP_HIP(hipMemcpy2D(out, 9 * sizeof(double), ctx->d_tally, ctx->tally_ts * sizeof(double),
-                     ctx->tally_nc * sizeof(double), rows, hipMemcpyDeviceToHost), "tally copy");
-  if (ctx->tally_nc < 9)
-    for (size_t r = 0; r < rows; ++r)
-      for (int k = ctx->tally_nc; k < 9; ++k) out[r * 9 + k] = 0.0;
-  return KP_OK;
+  return copy_tally_cells(ctx, out, 9, ctx->tally_ts, ctx->tally_nc);
 }
 
 kp_status kp_get_stats(kp_ctx* ctx, kp_stats* out) {

@@ -98,9 +98,12 @@ struct TransportArgs {
   uint64_t seed;
   double rr_wmin, rr_psurv;
   int max_events;
-  double* tally;  // [lambda][ncell][stride] coherency blocks, or for tabulated
-                  // grains the per-view source [lambda][ncell][view][4]
+  double* tally;  // [lambda][nslot][stride] coherency blocks, or for tabulated
+                  // grains the per-view source [lambda][nslot][view][4], cells
+                  // at their tally_slot
   uint64_t ncell;
+  uint64_t nslot;  // tally slots per wavelength (tally_slots; ncell on a mesh)
+  int tbx, tby;    // bricks along x and y of the tally layout (0 on a mesh)
   unsigned long long* counter;
   StatsDev* stats;
   TraceDev* traces;
@@ -133,17 +136,37 @@ struct ImageArgs {
   const DustDev* dust;
   const ViewDev* views;
   int n_views, n_lambda, npx, npy;
-  const double* tally;  // [lambda][ncell][9]   (coherency source)
-  const double* user_S; // [lambda][ncell][view][4] per-view source (or null)
+  const double* tally;  // [lambda][nslot][stride] coherency source (tally layout)
+  const double* user_S; // [lambda][nslot][view][4] per-view source (or null)
   double* images;       // [lambda][view][4][npy][npx]
   uint64_t ncell;
+  uint64_t nslot;       // slots per wavelength of tally / user_S, and their
+  int tbx, tby;         // bricks (tbx = 0: cell order, a caller's S or a mesh)
   const float* em_B;    // [lambda][ncell] source function of the dust's thermal
                         // emission, or null (no thermal source term)
   int boundary;         // bit a: axis a periodic
   MeshDev mesh;         // the kernels instantiated for a composite mesh
 };
 
-// Tally layout [lambda][cell][stride] FP64: 6 reals (stride 8, one 64-B block
+// Tally slot of cell c = (i, j, k) of a uniform grid: the tally and the
+// per-view source are stored in bricks of 4 x 4 x 4 cells (bricks x-fastest
+// over tbx x tby x .., cells x-fastest inside a brick), so that the flushes
+// of a packet's successive cells, neighbours in space, fall in a few DRAM
+// rows instead of rows 1 KB (y) and 256 KB (z) apart; on the 256^3 disk the
+// flush rate rose from 1.61e10 to 1.85e10 lines/s.  tbx == 0 keeps the cell
+// order (a composite mesh, whose leaf blocks are contiguous already, and a
+// caller's source array).
+__host__ __device__ inline uint64_t tally_slot(uint64_t c, int i, int j, int k, int tbx, int tby) {
+  if (tbx == 0) return c;
+  return ((((uint64_t)(k >> 2) * (uint64_t)tby + (uint64_t)(j >> 2)) * (uint64_t)tbx + (uint64_t)(i >> 2)) << 6) |
+         (uint64_t)(((k & 3) << 4) | ((j & 3) << 2) | (i & 3));
+}
+// slots per wavelength of an nx x ny x nz grid in the brick layout
+inline uint64_t tally_slots(int nx, int ny, int nz) {
+  return 64ull * (uint64_t)((nx + 3) / 4) * (uint64_t)((ny + 3) / 4) * (uint64_t)((nz + 3) / 4);
+}
+
+// Tally layout [lambda][slot][stride] FP64: 6 reals (stride 8, one 64-B block
 // per cell) when every wavelength has spherical grains, else 9 (stride 16).
 // With stride 16 the slot after the coherency holds the cell's density and
 // the next four the unit quaternion of its grain frame (read by the
@@ -158,7 +181,8 @@ hipError_t launch_image(const ImageArgs& a, bool aligned, bool sphere, bool user
                         hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_tally_init(double* tally, const float* rho, const float* bx, const float* by,
-                             const float* bz, uint64_t ncell, int n_lambda, bool sphere, hipStream_t s);
+                             const float* bz, uint64_t ncell, int n_lambda, bool sphere, uint64_t nslot, int nx,
+                             int ny, int tbx, int tby, hipStream_t s);
 hipError_t launch_validate(const float* rho, const float* bx, const float* by, const float* bz,
                            uint64_t n, unsigned long long* bad, hipStream_t s);
 int transport_max_blocks_per_cu(bool fp64, bool aligned, bool sphere, bool peel, bool tab, bool mesh,

@@ -809,7 +809,8 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
   if (tz < td) { td = tz; axis = 2; }
   if (!(td < inf)) return END_NUMERIC;
   const DustDev& D = a.dust[p.lam];
-  const double* blk = a.tally + ((uint64_t)p.lam * a.ncell + c) * TallyShape<SPHERE>::TS;
+  const uint64_t sl = tally_slot(c, p.ci, p.cj, p.ck, MESH ? 0 : a.tbx, a.tby);
+  const double* blk = a.tally + ((uint64_t)p.lam * a.nslot + sl) * TallyShape<SPHERE>::TS;
   const double rhod = TallyShape<SPHERE>::HAS_B ? blk[TallyShape<SPHERE>::RHO] : (double)p.rho;
   const double kbd = rhod * p.ks;
   double tld;
@@ -893,7 +894,7 @@ __device__ uint32_t step(Packet<R>& p, const TransportArgs& a, bool& has, int64_
       } else {
         coherency<R, NC>(n, JI, JQ, JU, JV, kb, cc);
       }
-      key = (int64_t)((uint64_t)p.lam * a.ncell + c);
+      key = (int64_t)((uint64_t)p.lam * a.nslot + sl);
       has = true;
     }
   }
@@ -1106,7 +1107,9 @@ __device__ void peel_off(const Packet<R>& p, const TransportArgs& a, const Quat<
 #pragma unroll
           for (int k = 0; k < 4; ++k) st[k] *= E;
         } else {
-          const double* blk = a.tally + ((uint64_t)p.lam * a.ncell + c) * TallyShape<SPHERE>::TS;
+          const double* blk =
+              a.tally + ((uint64_t)p.lam * a.nslot + tally_slot(c, ci[0], ci[1], ci[2], MESH ? 0 : a.tbx, a.tby)) *
+                            TallyShape<SPHERE>::TS;
           Quat<double> qc{1.0, 0.0, 0.0, 0.0};
           if (ALIGNED) qc = cell_quat<ALIGNED, SPHERE>(a, blk, c);
           V3<double> og = Om;
@@ -1178,14 +1181,14 @@ __device__ void wave_drain_views(const TransportArgs& a, double* sv, long long* 
       const int e = it / nv, v = it - e * nv;
       const double* x = sv + e * NV;
       const uint64_t key = (uint64_t)sk[e];
-      const DustDev& D = a.dust[key / a.ncell];
+      const DustDev& D = a.dust[key / a.nslot];
       const ViewDev& vw = a.views[v];
       const double s_in[4] = {x[0], x[1], x[2], x[3]};
       tab_toward(D, V3<double>{x[4], x[5], x[6]}, s_in, V3<double>{vw.ox, vw.oy, vw.oz},
                  V3<double>{vw.tx, vw.ty, vw.tz}, V3<double>{vw.px, vw.py, vw.pz}, st);
       if (MESH) {
         const uint64_t b = (uint64_t)a.mesh.block;
-        iv = ldexp(inv_vol, 3 * a.mesh.leaf_org[4 * ((key % a.ncell) / (b * b * b)) + 3]);
+        iv = ldexp(inv_vol, 3 * a.mesh.leaf_org[4 * ((key % a.nslot) / (b * b * b)) + 3]);
       }
     }
 #pragma unroll
@@ -1218,7 +1221,9 @@ __device__ uint32_t scatter_step(Packet<R>& p, const TransportArgs& a) {
   Quat<R> q{(R)1, (R)0, (R)0, (R)0};
   Quat<double> qd{1.0, 0.0, 0.0, 0.0};
   if (ALIGNED) {
-    const double* blk = a.tally + ((uint64_t)p.lam * a.ncell + c) * TallyShape<SPHERE>::TS;
+    const double* blk =
+        a.tally + ((uint64_t)p.lam * a.nslot + tally_slot(c, p.ci, p.cj, p.ck, MESH ? 0 : a.tbx, a.tby)) *
+                      TallyShape<SPHERE>::TS;
     qd = cell_quat<ALIGNED, SPHERE>(a, blk, c);
     q = quat_cast<R>(qd);
   }
@@ -1592,6 +1597,7 @@ __global__ void __launch_bounds__(256) k_image(ImageArgs a) {
       if (axis < 0) break;
       const uint64_t c = MESH ? (uint64_t)leaf * B * B * B + (uint64_t)ci[0] + B * ((uint64_t)ci[1] + B * ci[2])
                               : (uint64_t)ci[0] + (uint64_t)a.nx * ((uint64_t)ci[1] + (uint64_t)a.ny * ci[2]);
+      const uint64_t sl = tally_slot(c, ci[0], ci[1], ci[2], MESH ? 0 : a.tbx, a.tby);
       const double rho = (double)a.rho[c];
       if (rho > 0.0) {
         const double ke = rho * kext;
@@ -1600,14 +1606,14 @@ __global__ void __launch_bounds__(256) k_image(ImageArgs a) {
         Quat<double> q{1.0, 0.0, 0.0, 0.0};
         if (ALIGNED) q = grain_quat(V3<double>{(double)a.bx[c], (double)a.by[c], (double)a.bz[c]});
         if (USER_S) {
-          const double* Sv = a.user_S + (((uint64_t)lam * a.ncell + c) * a.n_views + v) * 4;
+          const double* Sv = a.user_S + (((uint64_t)lam * a.nslot + sl) * a.n_views + v) * 4;
           S[0] = Sv[0]; S[1] = Sv[1]; S[2] = Sv[2]; S[3] = Sv[3];
         } else {
           // source toward the camera from the incident coherency C of the
           // cell: rho'_ij = h_i^T C conj(h_j), h_i = alpha e_i with the lab
           // polarizability alpha = a_perp 1 + (a_par - a_perp) b b^T.
           constexpr int TS = TallyShape<SPHERE>::TS;
-          const double* T = a.tally + ((uint64_t)lam * a.ncell + c) * TS;
+          const double* T = a.tally + ((uint64_t)lam * a.nslot + sl) * TS;
           double C9[9] = {T[0], T[1], T[2], T[3], T[4], T[5], 0.0, 0.0, 0.0};
           if (TallyShape<SPHERE>::NC == 9) { C9[6] = T[6]; C9[7] = T[7]; C9[8] = T[8]; }
           source_toward<SPHERE>(C9, q, D, e1, e2, D.pfac * inv_vol, S);
@@ -1700,14 +1706,19 @@ __global__ void k_fill_zero(uint64_t* p, uint64_t nwords, unsigned char* tail, i
 // Tally blocks before a transport run: coherency slots zero and, with co_b
 // (non-spherical grains), the density in slot nc and the grain-frame
 // quaternion of the alignment direction (identity without one) in slots
-// nc+1..nc+4, for every (wavelength, cell); the rest of each block zero.
+// nc+1..nc+4, for every (wavelength, cell) at its tally slot; the rest of
+// each block zero (the padding slots of the bricks are never read).
 __global__ void k_tally_init(double* tally, const float* rho, const float* bx, const float* by,
-                             const float* bz, uint64_t ncell, int n_lambda, int ts, int nc, int co_b) {
+                             const float* bz, uint64_t ncell, int n_lambda, int ts, int nc, int co_b,
+                             uint64_t nslot, int nx, int ny, int tbx, int tby) {
   const uint64_t n = (uint64_t)n_lambda * ncell;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const uint64_t c = i % ncell;
-    double* b = tally + i * ts;
+    const uint64_t lam = i / ncell, c = i - lam * ncell;
+    const uint64_t cxy = (uint64_t)nx * (uint64_t)ny;
+    const int ck = tbx ? (int)(c / cxy) : 0, rem = tbx ? (int)(c - (uint64_t)ck * cxy) : 0;
+    const uint64_t sl = tally_slot(c, rem % nx, rem / nx, ck, tbx, tby);
+    double* b = tally + (lam * nslot + sl) * ts;
     for (int k = 0; k < ts; ++k) b[k] = 0.0;
     if (co_b) {
       b[nc] = (double)rho[c];
@@ -1955,14 +1966,15 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
 }
 
 hipError_t launch_tally_init(double* tally, const float* rho, const float* bx, const float* by,
-                             const float* bz, uint64_t ncell, int n_lambda, bool sphere, hipStream_t s) {
+                             const float* bz, uint64_t ncell, int n_lambda, bool sphere, uint64_t nslot, int nx,
+                             int ny, int tbx, int tby, hipStream_t s) {
   const int ts = tally_stride(sphere), nc = tally_components(sphere);
   const int co_b = sphere ? 0 : 1;
   uint64_t blocks = ((uint64_t)n_lambda * ncell + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (blocks == 0) blocks = 1;
   hipLaunchKernelGGL(k_tally_init, dim3((unsigned)blocks), dim3(256), 0, s, tally, rho, bx, by, bz, ncell,
-                     n_lambda, ts, nc, co_b);
+                     n_lambda, ts, nc, co_b, nslot, nx, ny, tbx, tby);
   return hipGetLastError();
 }
 
