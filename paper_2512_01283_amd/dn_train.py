@@ -17,7 +17,7 @@ runs; N_den(eps) by log-log interpolation of the denoised error over the
 input packet counts; the reference's own error is estimated from two
 independent halves and must be at most eps / 3.
 
-    python -m paper_2512_01283_amd.dn_train --out gpurun_out/dn   # full run
+    python -m paper_2512_01283_amd.dn_train --out dn_out/dn   # full run
 """
 from __future__ import annotations
 
@@ -234,7 +234,7 @@ def _ratios(per, plain_counts, den_counts, tta):
 def main(argv=None):
     import torch
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--out", default="gpurun_out/dn")
+    ap.add_argument("--out", default="dn_out/dn")
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--npix", type=int, default=256)
     ap.add_argument("--train-seeds", default="1000:1064")
