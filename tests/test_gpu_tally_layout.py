@@ -1,0 +1,90 @@
+"""The tally's storage order on the GPU (cells in bricks of 4 x 4 x 4, the
+grid padded to multiples of 4) on a grid whose sides are neither equal nor
+multiples of 4 (18 x 13 x 11), against the FP64 oracle through the C ABI:
+every packet's path, the images formed from the tally, the per-view tally
+of tabulated grains returned in cell order, and the coherency tally's
+support (zero exactly where the density is), for spherical and aligned
+grains (64- and 128-byte tally blocks).  Bars as in test_gpu_parity.py."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2512_01283_amd import workloads as W
+from parity_util import compare_traces, gpu_run, say
+
+pytestmark = pytest.mark.gpu
+
+NX, NY, NZ = 18, 13, 11
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle as o
+    o.lib()
+    return o
+
+
+def odd_box(packets=6000, grains="sphere"):
+    """An ellipsoid of density 1 (semi-axes 0.9, 0.6, 0.5) inside an
+    18 x 13 x 11 box of cubic cells (dx = 0.1), the source off the lattice
+    at (0.03, -0.02, 0.01), three oblique cameras."""
+    dx = 0.1
+    grid = dict(nx=NX, ny=NY, nz=NZ, x0=-NX * dx / 2, y0=-NY * dx / 2, z0=-NZ * dx / 2, dx=dx)
+    X, Y, Z = np.meshgrid(*(grid[o] + (np.arange(grid[n]) + 0.5) * dx for o, n in
+                            (("x0", "nx"), ("y0", "ny"), ("z0", "nz"))), indexing="ij")
+    inside = (X / 0.9) ** 2 + (Y / 0.6) ** 2 + (Z / 0.5) ** 2 < 1.0
+    rho = np.ascontiguousarray(np.transpose(np.where(inside, 1.0, 0.0), (2, 1, 0)), dtype=np.float32).reshape(-1)
+    views = [W.view(t, p, 20, half_width=1.0) for t, p in ((35.0, 70.0), (123.0, 211.0), (80.0, 10.0))]
+    cfg = dict(name="odd_box", grid=grid, rho=rho, bhat=None, dust=[W.sphere_dust(1.5, 0.8)],
+               source=dict(kind=0, pos=(0.03, -0.02, 0.01), dir=(0.0, 0.0, 1.0), lum=1.0),
+               views=views, packets=[int(packets)], opts=W.default_opts(5), precision="f64")
+    if grains == "aligned":
+        b = np.array([math.sin(30 * W.DEG), 0.2, math.cos(30 * W.DEG)])
+        b /= np.linalg.norm(b)
+        cfg["bhat"] = np.repeat(b[:, None], NX * NY * NZ, axis=1).astype(np.float32)
+        cfg["dust"] = [W.oblate_dust(1.5, 0.6)]
+    elif grains == "table":
+        cfg["dust"] = [W.table_dust(1.5, 0.8, W.hg_table(0.5, n_theta=181))]
+    return cfg
+
+
+@pytest.mark.parametrize("grains,tol", [("sphere", 1e-12), ("aligned", 1e-10)])
+def test_odd_grid_paths_images_and_tally_support(O, grains, tol):
+    cfg = odd_box(grains=grains)
+    say(f"case: {NX}x{NY}x{NZ} box, {grains} grains, fp64 6000 packets")
+    ctx = gpu_run(cfg, trace_packets=6000, transport_fp64=1)
+    try:
+        img_o, _, tr_o, st_o = O.run(cfg, traces=True)
+        compare_traces(ctx.traces(), tr_o, tol, 1.0, f"odd box {grains}")
+        st = ctx.stats()
+        for k in ("cell_steps", "scatterings", "escaped", "rr_kills"):
+            assert st[k] == st_o[k], k
+        img = ctx.images()[0]
+        d = np.abs(img - img_o).max() / np.abs(img_o[:, 0]).max()
+        say(f"[odd box {grains}] image max |d|/I_max = {d:.3e}")
+        assert d < 1e-10
+        C = ctx.tally()[0]  # [cell][9] in cell order
+        empty = np.asarray(cfg["rho"]) == 0
+        assert np.all(C[empty] == 0.0)
+        assert np.count_nonzero(C[~empty, 0]) > 0.9 * np.count_nonzero(~empty)
+    finally:
+        ctx.close()
+
+
+def test_odd_grid_view_tally_in_cell_order(O):
+    """Tabulated grains: the per-view source returned by kp_get_view_tally
+    (stored in bricks on the device) equals the oracle's, cell by cell."""
+    cfg = odd_box(packets=8000, grains="table")
+    say(f"case: {NX}x{NY}x{NZ} box, table grains, fp64 8000 packets")
+    ctx = gpu_run(cfg, trace_packets=8000, transport_fp64=1)
+    try:
+        img_o, S_o, tr_o, _ = O.run(cfg, traces=True)
+        compare_traces(ctx.traces(), tr_o, 1e-12, 1.0, "odd box tables")
+        S = ctx.view_tally()[0]
+        dS = np.abs(S - S_o).max() / np.abs(S_o).max()
+        d = np.abs(ctx.images()[0] - img_o).max() / np.abs(img_o[:, 0]).max()
+        say(f"[odd box tables] view tally max |d|/max = {dS:.3e}; image max |d|/I_max = {d:.3e}")
+        assert dS < 1e-10 and d < 1e-10
+    finally:
+        ctx.close()
