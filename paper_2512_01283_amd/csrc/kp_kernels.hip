@@ -1304,12 +1304,14 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
   constexpr int NC = TallyShape<SPHERE>::NC, TS = TallyShape<SPHERE>::TS;
   __shared__ unsigned long long sc[SC_N];
   __shared__ double se[SE_N];
-  // flush staging, one area of FLUSH_CAP entries per wavefront (56 KB per
+  // flush staging, one area of FLUSH_CAP entries per wavefront (43 KB per
   // block for spheres, 61 KB for aligned grains: two blocks per CU; 32 KB
   // for tabulated grains, whose entries are the segment's Stokes integral and
-  // direction, 7 values)
+  // direction, 7 values).  With the tally in bricks, drains of up to 128
+  // entries (a cap of 192) beat 192 (cap 256) on the 256^3 disk: 726.8 vs
+  // 737.9 ms (a cap of 128: 729.2 ms).
   constexpr int NSV = TAB ? 7 : NC;
-  constexpr int FLUSH_CAP = TAB ? 128 : (NC <= 6 ? 256 : 192);
+  constexpr int FLUSH_CAP = TAB ? 128 : 192;
   __shared__ double s_val[4 * FLUSH_CAP * NSV];
   // tabulated grains: per wavefront the projections of one drain round
   __shared__ double s_proj[TAB ? 4 * 256 : 1];
