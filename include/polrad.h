@@ -368,12 +368,15 @@ kp_status kp_get_peel_images(kp_ctx *ctx, double *host_out, size_t n);
 /* Incident-coherency tally [n_lambda][ncell][9] FP64 of the last step 1
  * (the scattering source of Sec. 2.3, eq. scat-disc-sum, before the camera
  * projection: components xx yy zz xy xz yz and the imaginary yz zx xy
- * parts), per unit cell volume times dx^3; n must equal that size. */
+ * parts), per unit cell volume times dx^3, cells in the order of the
+ * density array whatever layout the device keeps them in; n must equal
+ * that size. */
 kp_status kp_get_tally(kp_ctx *ctx, double *host_out, size_t n);
 /* Per-view scattering source of the last step 1 with tabulated grains (Sec.
  * 2.3, eq. scat-disc-sum: the emissivity toward each camera per unit volume
  * and solid angle, in that camera's basis), [n_lambda][ncell][n_views][4]
- * FP64, copied to host memory; n must equal that size (KP_ERR_ARG), and
+ * FP64, cells in the order of the density array, copied to host memory;
+ * n must equal that size (KP_ERR_ARG), and
  * KP_ERR_STATE when the last step 1 tallied coherencies (dipole grains,
  * kp_get_tally) or formed none. */
 kp_status kp_get_view_tally(kp_ctx *ctx, double *host_out, size_t n);
