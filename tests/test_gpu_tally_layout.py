@@ -88,3 +88,36 @@ def test_odd_grid_view_tally_in_cell_order(O):
         assert dS < 1e-10 and d < 1e-10
     finally:
         ctx.close()
+
+
+@pytest.mark.parametrize("grains,tol", [("sphere", 1e-12), ("aligned", 1e-10)])
+def test_odd_grid_periodic_thermal(O, grains, tol):
+    """x and y periodic (packets wrap into cells whose tally slots lie in
+    the padded bricks' neighbours) and the dust's own thermal emission as
+    the source (step 2 reads the source function in cell order beside the
+    tally at its slot): paths, counters and images equal the oracle's, and
+    the allocation-free entry point gives the same images."""
+    import torch
+    from paper_2512_01283_amd import polrad as P
+    cfg = odd_box(packets=6000, grains=grains)
+    cfg["grid"] = dict(cfg["grid"], boundary=3)
+    cfg["source"] = dict(W.THERMAL_SOURCE)
+    cfg["emission"] = np.full((1, NX * NY * NZ), 1.0, dtype=np.float32)
+    say(f"case: {NX}x{NY}x{NZ} box, x/y periodic, thermal, {grains} grains, fp64 6000 packets")
+    ctx = gpu_run(cfg, trace_packets=6000, transport_fp64=1)
+    try:
+        img_o, _, tr_o, st_o = O.run(cfg, traces=True)
+        compare_traces(ctx.traces(), tr_o, tol, 1.0, f"odd box periodic thermal {grains}")
+        st = ctx.stats()
+        for k in ("cell_steps", "scatterings", "escaped", "rr_kills"):
+            assert st[k] == st_o[k], k
+        img = ctx.images()
+        d = np.abs(img[0] - img_o).max() / np.abs(img_o[:, 0]).max()
+        say(f"[odd box periodic thermal {grains}] image max |d|/I_max = {d:.3e}")
+        assert d < 1e-10
+        out = torch.zeros(img.shape, dtype=torch.float64, device="cuda")
+        P.kp_run_static(ctx.h, cfg["packets"], ctx.opts(transport_fp64=1), out)
+        ds = np.abs(out.cpu().numpy() - img).max() / np.abs(img[:, :, 0]).max()
+        assert ds <= 1e-12, ds
+    finally:
+        ctx.close()
