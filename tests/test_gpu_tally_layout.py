@@ -121,3 +121,23 @@ def test_odd_grid_periodic_thermal(O, grains, tol):
         assert ds <= 1e-12, ds
     finally:
         ctx.close()
+
+
+def test_odd_grid_fp32_sphere(O):
+    """The benchmark's kernel (FP32 polarisation, spherical grains, 64-byte
+    tally blocks) on the padded bricks: every packet follows the oracle's
+    events with its Stokes vector to 1e-5; the images, positive-weight sums
+    of per-segment terms each within that bar of its own intensity, agree to
+    1e-5 of the peak intensity."""
+    cfg = odd_box(packets=6000, grains="sphere")
+    say(f"case: {NX}x{NY}x{NZ} box, sphere grains, fp32 6000 packets")
+    ctx = gpu_run(cfg, trace_packets=6000, transport_fp64=0)
+    try:
+        img_o, _, tr_o, st_o = O.run(cfg, traces=True)
+        compare_traces(ctx.traces(), tr_o, 1e-5, 1.0, "odd box fp32")
+        assert ctx.stats()["cell_steps"] == st_o["cell_steps"]
+        d = np.abs(ctx.images()[0] - img_o).max() / np.abs(img_o[:, 0]).max()
+        say(f"[odd box fp32] image max |d|/I_max = {d:.3e}")
+        assert d < 1e-5
+    finally:
+        ctx.close()
