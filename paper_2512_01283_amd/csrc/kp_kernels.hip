@@ -1307,9 +1307,11 @@ __device__ __forceinline__ void transport_body(const TransportArgs& a) {
   // flush staging, one area of FLUSH_CAP entries per wavefront (43 KB per
   // block for spheres, 61 KB for aligned grains: two blocks per CU; 32 KB
   // for tabulated grains, whose entries are the segment's Stokes integral and
-  // direction, 7 values).  With the tally in bricks, drains of up to 128
-  // entries (a cap of 192) beat 192 (cap 256) on the 256^3 disk: 726.8 vs
-  // 737.9 ms (a cap of 128: 729.2 ms).
+  // direction, 7 values).  A wavefront drains its area once it holds more
+  // than FLUSH_CAP - 64 entries (a stage adds at most 64), so a drain covers
+  // FLUSH_CAP - 63 .. FLUSH_CAP entries.  With the tally in bricks a cap of
+  // 192 beat 256 on the 256^3 disk: 726.8 vs 737.9 ms (a cap of 128:
+  // 729.2 ms).
   constexpr int NSV = TAB ? 7 : NC;
   constexpr int FLUSH_CAP = TAB ? 128 : 192;
   __shared__ double s_val[4 * FLUSH_CAP * NSV];
