@@ -322,8 +322,11 @@ kp_status kp_run(kp_ctx *ctx, const uint64_t *packets_per_lambda, const kp_opts 
  * device, held until the process ends) instead of context buffers; the
  * images go straight to d_images (device, borrowed, [n_lambda][n_views][4]
  * [npy][npx] FP64, n its element count).  Limits: the tally, n_lambda x
- * ncell x 64 B for spherical grains (x 128 B otherwise), must fit 256 MiB
- * (KP_ERR_ARG otherwise, before any launch: use kp_run), and no traces are
+ * nslot x 64 B for spherical grains (x 128 B for aligned grains, x 32 B x
+ * n_views for tabulated ones), with nslot = ncell on a composite mesh and
+ * 64 ceil(nx/4) ceil(ny/4) ceil(nz/4) on a uniform grid (whose tally keeps
+ * its cells in bricks of 4 x 4 x 4), must fit 256 MiB (KP_ERR_ARG
+ * otherwise, before any launch: use kp_run), and no traces are
  * recorded (trace_packets must be 0) and no peel-off images formed
  * (peel_off must be 0).  kp_get_stats then reports this call;
  * kp_image, kp_get_images and kp_get_tally keep referring to the last
