@@ -1711,28 +1711,46 @@ __global__ void k_fill_zero(uint64_t* p, uint64_t nwords, unsigned char* tail, i
 // (non-spherical grains), the density in slot nc and the grain-frame
 // quaternion of the alignment direction (identity without one) in slots
 // nc+1..nc+4, for every (wavelength, cell) at its tally slot; the rest of
-// each block zero (the padding slots of the bricks are never read).
+// each block, and the padding slots of the bricks (never read), zero.  One
+// thread per double of a wavelength's tally (ts = 2^lts doubles per slot),
+// written for every wavelength: consecutive lanes write consecutive doubles.
 __global__ void k_tally_init(double* tally, const float* rho, const float* bx, const float* by,
-                             const float* bz, uint64_t ncell, int n_lambda, int ts, int nc, int co_b,
+                             const float* bz, uint64_t ncell, int n_lambda, int lts, int nc, int co_b,
                              uint64_t nslot, int nx, int ny, int tbx, int tby) {
-  const uint64_t n = (uint64_t)n_lambda * ncell;
+  const int ts = 1 << lts;
+  const uint64_t per = nslot << lts;  // doubles per wavelength
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const uint64_t lam = i / ncell, c = i - lam * ncell;
-    const uint64_t cxy = (uint64_t)nx * (uint64_t)ny;
-    const int ck = tbx ? (int)(c / cxy) : 0, rem = tbx ? (int)(c - (uint64_t)ck * cxy) : 0;
-    const uint64_t sl = tally_slot(c, rem % nx, rem / nx, ck, tbx, tby);
-    double* b = tally + (lam * nslot + sl) * ts;
-    for (int k = 0; k < ts; ++k) b[k] = 0.0;
-    if (co_b) {
-      b[nc] = (double)rho[c];
-      Quat<double> q{1.0, 0.0, 0.0, 0.0};
-      if (bx) q = grain_quat(V3<double>{(double)bx[c], (double)by[c], (double)bz[c]});
-      b[nc + 1] = q.w;
-      b[nc + 2] = q.x;
-      b[nc + 3] = q.y;
-      b[nc + 4] = q.z;
+  const uint64_t cxy = (uint64_t)nx * (uint64_t)ny;
+  const uint64_t nz = tbx ? ncell / cxy : 0;
+  for (uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; o < per; o += stride) {
+    const uint64_t sl = o >> lts;
+    const int k = (int)(o & (uint64_t)(ts - 1));
+    double v = 0.0;
+    if (co_b && k >= nc && k <= nc + 4) {
+      // the cell of slot sl (the inverse of tally_slot), if it is one
+      uint64_t c = sl;
+      bool valid = sl < ncell;
+      if (tbx) {
+        const uint64_t brick = sl >> 6, t = brick / (uint64_t)tbx;
+        const int w = (int)(sl & 63);
+        const uint64_t i = (brick - t * (uint64_t)tbx) * 4 + (uint64_t)(w & 3);
+        const uint64_t j = (t % (uint64_t)tby) * 4 + (uint64_t)((w >> 2) & 3);
+        const uint64_t kz = (t / (uint64_t)tby) * 4 + (uint64_t)(w >> 4);
+        valid = i < (uint64_t)nx && j < (uint64_t)ny && kz < nz;
+        c = i + (uint64_t)nx * j + cxy * kz;
+      }
+      if (valid) {
+        if (k == nc) {
+          v = (double)rho[c];
+        } else {
+          Quat<double> q{1.0, 0.0, 0.0, 0.0};
+          if (bx) q = grain_quat(V3<double>{(double)bx[c], (double)by[c], (double)bz[c]});
+          const int m = k - nc - 1;
+          v = m == 0 ? q.w : (m == 1 ? q.x : (m == 2 ? q.y : q.z));
+        }
+      }
     }
+    for (int lam = 0; lam < n_lambda; ++lam) tally[(uint64_t)lam * per + o] = v;
   }
 }
 
@@ -1974,11 +1992,14 @@ hipError_t launch_tally_init(double* tally, const float* rho, const float* bx, c
                              int ny, int tbx, int tby, hipStream_t s) {
   const int ts = tally_stride(sphere), nc = tally_components(sphere);
   const int co_b = sphere ? 0 : 1;
-  uint64_t blocks = ((uint64_t)n_lambda * ncell + 255) / 256;
+  int lts = 0;
+  while ((1 << lts) < ts) ++lts;
+  if ((1 << lts) != ts || (co_b && nc + 5 > ts)) return hipErrorInvalidValue;
+  uint64_t blocks = ((nslot << lts) + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (blocks == 0) blocks = 1;
   hipLaunchKernelGGL(k_tally_init, dim3((unsigned)blocks), dim3(256), 0, s, tally, rho, bx, by, bz, ncell,
-                     n_lambda, ts, nc, co_b, nslot, nx, ny, tbx, tby);
+                     n_lambda, lts, nc, co_b, nslot, nx, ny, tbx, tby);
   return hipGetLastError();
 }
 
